@@ -1,0 +1,589 @@
+/*
+ * mpcg_oracle.c -- plain, slow CPU oracle for the restarted mixed-precision
+ * CG method (Prolubnikov, "Parameter Optimization for Restarted
+ * Mixed-Precision Iterative Sparse Solver", arXiv 2412.08059).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the bench do.  It shares no code, header or table with the HIP library.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction: every
+ * fused multiply-add below is an explicit fma()/fmaf() call).
+ *
+ * What each function follows:
+ *   or_spmv64 / or_spmv32  -- the sparse product A d of the CG iteration
+ *                             (section "Conjugate Gradient Method"); each row
+ *                             is one multiply-add per stored entry (eq. 16),
+ *                             here as an fma chain in CSR order from 0.
+ *   or_bfs / or_pseudo_diameter -- the 2BFS procedure (section "Computing
+ *                             Pseudo-Diameter of the Graph Matrix") and its
+ *                             per-component maximum for disconnected graphs.
+ *   or_knn_select          -- weighted kNN (section "Finding the Optimal
+ *                             Tolerance ... via a Classification Approach":
+ *                             min-max normalisation, squared Euclidean search,
+ *                             1/rho weights of eq. (23)).
+ *   or_solve               -- Algorithm I (explicit eps1), Algorithm II
+ *                             (eps1 = AUTO: k0 FP32 iterations, v of eq. (13),
+ *                             kNN, continue), and FP64-only CG (eps1 = NONE).
+ *
+ * Readings where the paper is silent (all documented in the design notes):
+ *   - tolerance is relative to ||b||_2 unless tol_mode = 1 (absolute);
+ *   - the loop test uses the recursive residual sqrt(gamma); the true
+ *     residual b - Ax is formed at the restart and at the final check;
+ *   - FP32-phase dot products accumulate in FP64 (each FP32 x FP32 product is
+ *     exact in FP64); alpha and beta are rounded to FP32;
+ *   - 2BFS starts at the smallest vertex of each component; farthest-vertex
+ *     ties go to the smallest index; self-loops are ignored;
+ *   - kNN: loop from sample k+1 with strict '<'; the evicted member is the
+ *     farthest one (ties: largest sample index); zero-distance neighbours
+ *     vote by count; class-score ties go to the larger eps1 (smaller t).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ENOTSPD (-2)
+#define OR_ENOCONV (-3)
+#define OR_ENOMEM (-4)
+#define OR_ENONFINITE (-6)
+#define OR_ENOMODEL (-9)
+
+#define OR_FLAG_FP32_BREAKDOWN 1
+#define OR_FLAG_FP32_MAXIT 2
+#define OR_FLAG_FINAL_RESTARTED 4
+#define OR_FLAG_KNN_EXACT 8
+
+typedef struct {
+    int32_t k0;           /* FP32 iterations used for v (Algorithm II) */
+    int32_t tol_mode;     /* 0: relative to ||b||, 1: absolute */
+    int32_t max_restarts; /* extra FP64 restarts after a failed final check */
+    int32_t knn_k;        /* 0: take k from the model */
+    int64_t maxit1;       /* FP32 iteration cap, <=0: n */
+    int64_t maxit2;       /* FP64 iteration cap, <=0: max(10n, 1000) */
+} or_opts;
+
+typedef struct {
+    int64_t ns;            /* training samples */
+    const double *feat;    /* ns x 4 raw features (n, m, ell, v) */
+    const int32_t *label;  /* class t in 2..7 */
+    const double *fmin;    /* 4 */
+    const double *fmax;    /* 4 */
+    int32_t k;
+    int32_t mask;          /* bit j set: feature j used */
+} or_model;
+
+typedef struct {
+    int32_t status, n1, n2, restarts, flags, k0_used, eps1_class, pad;
+    double eps1_used, v, beta_b, relres_sp, relres_restart_true, relres_final_true;
+    int64_t ell, bfs_t, bfs_u, ncomp;
+} or_stats;
+
+/* ---------------------------------------------------------------- SpMV -- */
+
+void or_spmv64(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
+               const double *x, double *y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+            acc = fma(val[k], x[col[k]], acc);
+        y[i] = acc;
+    }
+}
+
+void or_spmv32(int64_t n, const int64_t *rp, const int32_t *col, const float *val,
+               const float *x, float *y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        float acc = 0.0f;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+            acc = fmaf(val[k], x[col[k]], acc);
+        y[i] = acc;
+    }
+}
+
+/* ----------------------------------------------------------------- BFS -- */
+
+/* Breadth-first search from src over the stored pattern (self-loops ignored).
+ * dist[] must be n long; unreached vertices get -1.  Returns the eccentricity
+ * of src (largest finite distance). */
+int32_t or_bfs(int64_t n, const int64_t *rp, const int32_t *col, int64_t src, int32_t *dist)
+{
+    for (int64_t i = 0; i < n; ++i) dist[i] = -1;
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t head = 0, tail = 0;
+    int32_t ecc = 0;
+    dist[src] = 0;
+    queue[tail++] = src;
+    while (head < tail) {
+        int64_t u = queue[head++];
+        for (int64_t k = rp[u]; k < rp[u + 1]; ++k) {
+            int64_t v = col[k];
+            if (v == u || dist[v] >= 0) continue;
+            dist[v] = dist[u] + 1;
+            if (dist[v] > ecc) ecc = dist[v];
+            queue[tail++] = v;
+        }
+    }
+    free(queue);
+    return ecc;
+}
+
+/* BFS restricted to the vertices reachable from src, using caller scratch.
+ * Returns the number of reached vertices; *far gets the farthest vertex
+ * (ties: smallest index) and *ecc its distance.  dist entries of reached
+ * vertices are reset to -1 before returning. */
+static int64_t bfs_component(const int64_t *rp, const int32_t *col, int64_t src,
+                             int32_t *dist, int64_t *queue, unsigned char *visited,
+                             int64_t *far, int32_t *ecc)
+{
+    int64_t head = 0, tail = 0;
+    dist[src] = 0;
+    queue[tail++] = src;
+    if (visited) visited[src] = 1;
+    while (head < tail) {
+        int64_t u = queue[head++];
+        for (int64_t k = rp[u]; k < rp[u + 1]; ++k) {
+            int64_t v = col[k];
+            if (v == u || dist[v] >= 0) continue;
+            dist[v] = dist[u] + 1;
+            queue[tail++] = v;
+            if (visited) visited[v] = 1;
+        }
+    }
+    int64_t best = src;
+    int32_t bd = 0;
+    for (int64_t q = 0; q < tail; ++q) {
+        int64_t v = queue[q];
+        if (dist[v] > bd || (dist[v] == bd && v < best)) { bd = dist[v]; best = v; }
+    }
+    for (int64_t q = 0; q < tail; ++q) dist[queue[q]] = -1;
+    *far = best;
+    *ecc = bd;
+    return tail;
+}
+
+/* 2BFS pseudo-diameter, taken per connected component and maximised.
+ * out[0] = ell, out[1] = t, out[2] = u of the first component (in order of
+ * its smallest vertex) attaining the maximum, out[3] = number of components. */
+int or_pseudo_diameter(int64_t n, const int64_t *rp, const int32_t *col, int64_t *out)
+{
+    if (n <= 0) return OR_EINVAL;
+    int32_t *dist = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    unsigned char *visited = (unsigned char *)calloc((size_t)n, 1);
+    if (!dist || !queue || !visited) { free(dist); free(queue); free(visited); return OR_ENOMEM; }
+    for (int64_t i = 0; i < n; ++i) dist[i] = -1;
+    int64_t ell = -1, bt = 0, bu = 0, ncomp = 0;
+    for (int64_t s = 0; s < n; ++s) {
+        if (visited[s]) continue;
+        ++ncomp;
+        int64_t t, u;
+        int32_t e1, e2;
+        bfs_component(rp, col, s, dist, queue, visited, &t, &e1);
+        bfs_component(rp, col, t, dist, queue, NULL, &u, &e2);
+        if (e2 > ell) { ell = e2; bt = t; bu = u; }
+    }
+    out[0] = ell; out[1] = bt; out[2] = bu; out[3] = ncomp;
+    free(dist); free(queue); free(visited);
+    return OR_OK;
+}
+
+/* ----------------------------------------------------------------- kNN -- */
+
+static double knn_norm(double x, double lo, double hi)
+{
+    if (hi == lo) return 0.0;
+    return (x - lo) / (hi - lo);
+}
+
+/* Weighted kNN over raw training features.  scores[t-2] receives the class
+ * scores for t = 2..7.  Returns the class t (2..7) or a negative status. */
+int or_knn_select(const or_model *m, const double *query, int32_t k_override,
+                  double *scores, int32_t *exact)
+{
+    if (!m || m->ns <= 0) return OR_ENOMODEL;
+    int64_t ns = m->ns;
+    int32_t k = k_override > 0 ? k_override : m->k;
+    if (k <= 0) return OR_EINVAL;
+    if (k > ns) k = (int32_t)ns;
+    double q[4];
+    for (int j = 0; j < 4; ++j) q[j] = knn_norm(query[j], m->fmin[j], m->fmax[j]);
+    double *d2 = (double *)malloc(sizeof(double) * (size_t)ns);
+    int64_t *set = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+    for (int64_t i = 0; i < ns; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j < 4; ++j) {
+            if (!(m->mask & (1 << j))) continue;
+            double s = knn_norm(m->feat[i * 4 + j], m->fmin[j], m->fmax[j]);
+            double diff = q[j] - s;
+            double sq = diff * diff;
+            acc = acc + sq;
+        }
+        d2[i] = acc;
+    }
+    for (int32_t a = 0; a < k; ++a) set[a] = a;
+    for (int64_t i = k; i < ns; ++i) {
+        int32_t far = 0;
+        for (int32_t a = 1; a < k; ++a) {
+            int64_t ca = set[a], cf = set[far];
+            if (d2[ca] > d2[cf] || (d2[ca] == d2[cf] && ca > cf)) far = a;
+        }
+        if (d2[i] < d2[set[far]]) set[far] = i;
+    }
+    /* ascending sample order for the weighted sums */
+    for (int32_t a = 1; a < k; ++a) {
+        int64_t key = set[a];
+        int32_t b = a - 1;
+        while (b >= 0 && set[b] > key) { set[b + 1] = set[b]; --b; }
+        set[b + 1] = key;
+    }
+    double sc[6] = {0, 0, 0, 0, 0, 0};
+    int zero = 0;
+    for (int32_t a = 0; a < k; ++a) if (d2[set[a]] == 0.0) zero = 1;
+    for (int32_t a = 0; a < k; ++a) {
+        int64_t i = set[a];
+        int32_t t = m->label[i];
+        if (t < 2 || t > 7) { free(d2); free(set); return OR_EINVAL; }
+        if (zero) {
+            if (d2[i] == 0.0) sc[t - 2] = sc[t - 2] + 1.0;
+        } else {
+            sc[t - 2] = sc[t - 2] + 1.0 / sqrt(d2[i]);
+        }
+    }
+    int32_t best = 2;
+    for (int32_t t = 3; t <= 7; ++t)
+        if (sc[t - 2] > sc[best - 2]) best = t;
+    if (scores) for (int j = 0; j < 6; ++j) scores[j] = sc[j];
+    if (exact) *exact = zero;
+    free(d2); free(set);
+    return best;
+}
+
+/* ------------------------------------------------------------------ CG -- */
+
+static double dot64(int64_t n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s = fma(a[i], b[i], s);
+    return s;
+}
+
+/* FP64 accumulation of FP32 products; each product is exact in FP64. */
+static double dot32(int64_t n, const float *a, const float *b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s = fma((double)a[i], (double)b[i], s);
+    return s;
+}
+
+/* r = b - A x (FP64), returns ||r||^2 */
+static double true_residual(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
+                            const double *b, const double *x, double *r)
+{
+    or_spmv64(n, rp, col, val, x, r);
+    for (int64_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
+    return dot64(n, r, r);
+}
+
+static int all_finite(int64_t n, const double *a)
+{
+    for (int64_t i = 0; i < n; ++i) if (!isfinite(a[i])) return 0;
+    return 1;
+}
+
+static const double k_eps_class[8] = {0, 0, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7};
+
+typedef struct {
+    int64_t n;
+    const int64_t *rp; const int32_t *col;
+    const float *val;
+    float *x, *r, *d, *q;
+    double gamma;
+} cg32_state;
+
+/* One FP32 CG iteration.  Returns 0 on success, 1 on breakdown (delta not
+ * positive or not finite; the iterate is left unchanged). */
+static int cg32_step(cg32_state *s)
+{
+    int64_t n = s->n;
+    or_spmv32(n, s->rp, s->col, s->val, s->d, s->q);
+    double delta = dot32(n, s->d, s->q);
+    if (!isfinite(delta) || !(delta > 0.0)) return 1;
+    float alpha = (float)(s->gamma / delta);
+    for (int64_t i = 0; i < n; ++i) {
+        s->x[i] = fmaf(alpha, s->d[i], s->x[i]);
+        s->r[i] = fmaf(-alpha, s->q[i], s->r[i]);
+    }
+    double gnew = dot32(n, s->r, s->r);
+    float beta = (float)(gnew / s->gamma);
+    for (int64_t i = 0; i < n; ++i) s->d[i] = fmaf(beta, s->d[i], s->r[i]);
+    s->gamma = gnew;
+    return 0;
+}
+
+int or_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
+             const double *b, double *x, double eps1, double eps2,
+             const or_opts *opt_in, const or_model *model, or_stats *st)
+{
+    or_opts opt = {20, 0, 5, 0, 0, 0};
+    if (opt_in) opt = *opt_in;
+    or_stats S;
+    memset(&S, 0, sizeof(S));
+    S.eps1_class = -1;
+    S.ell = -1;
+    int status = OR_OK;
+    if (n <= 0 || !rp || !b || !x || !(eps2 > 0.0) || !isfinite(eps2) ||
+        !(eps1 == 0.0 || eps1 == -1.0 || (eps1 > 0.0 && isfinite(eps1)))) {
+        if (st) { S.status = OR_EINVAL; *st = S; }
+        return OR_EINVAL;
+    }
+    int64_t nnz = rp[n];
+    if (rp[0] != 0) status = OR_EINVAL;
+    for (int64_t i = 0; i < n && status == OR_OK; ++i) {
+        if (rp[i + 1] < rp[i]) { status = OR_EINVAL; break; }
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            if (col[k] < 0 || col[k] >= n) { status = OR_EINVAL; break; }
+            if (k > rp[i] && col[k] <= col[k - 1]) { status = OR_EINVAL; break; }
+        }
+    }
+    if (status != OR_OK) { if (st) { S.status = status; *st = S; } return status; }
+    if (!all_finite(nnz, val) || !all_finite(n, b)) {
+        if (st) { S.status = OR_ENONFINITE; *st = S; }
+        return OR_ENONFINITE;
+    }
+    if (eps1 == 0.0 && (!model || model->ns <= 0)) {
+        if (st) { S.status = OR_ENOMODEL; *st = S; }
+        return OR_ENOMODEL;
+    }
+    int64_t maxit1 = opt.maxit1 > 0 ? opt.maxit1 : n;
+    int64_t maxit2 = opt.maxit2 > 0 ? opt.maxit2 : (10 * n > 1000 ? 10 * n : 1000);
+
+    double beta_b = sqrt(dot64(n, b, b));
+    S.beta_b = beta_b;
+    if (beta_b == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        if (st) { S.status = OR_OK; *st = S; }
+        return OR_OK;
+    }
+    double scale = opt.tol_mode == 1 ? 1.0 : beta_b;
+
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    double *d = (double *)malloc(sizeof(double) * (size_t)n);
+    double *q = (double *)malloc(sizeof(double) * (size_t)n);
+
+    if (eps1 != -1.0) {
+        /* ---- first stage: FP32 copy of A and b, x~ = 0 ---- */
+        float *val32 = (float *)malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
+        cg32_state s;
+        s.n = n; s.rp = rp; s.col = col; s.val = val32;
+        s.x = (float *)malloc(sizeof(float) * (size_t)n);
+        s.r = (float *)malloc(sizeof(float) * (size_t)n);
+        s.d = (float *)malloc(sizeof(float) * (size_t)n);
+        s.q = (float *)malloc(sizeof(float) * (size_t)n);
+        for (int64_t k = 0; k < nnz; ++k) val32[k] = (float)val[k];
+        for (int64_t i = 0; i < n; ++i) {
+            s.x[i] = 0.0f;
+            s.r[i] = (float)b[i];      /* r~ = b~ - A~ * 0 */
+            s.d[i] = s.r[i];
+        }
+        s.gamma = dot32(n, s.r, s.r);
+        int64_t n1 = 0;
+        int broke = 0;
+        double e1 = eps1;
+        if (eps1 == 0.0) {
+            /* Algorithm II: k0 iterations, v = mean ||r_i|| / ||r_{i-1}|| */
+            double sum = 0.0;
+            int32_t used = 0;
+            while (used < opt.k0 && s.gamma > 0.0) {
+                double gprev = s.gamma;
+                if (cg32_step(&s)) { broke = 1; break; }
+                ++n1;
+                double ratio = sqrt(s.gamma) / sqrt(gprev);
+                sum = sum + ratio;
+                ++used;
+            }
+            S.k0_used = used;
+            S.v = used > 0 ? sum / (double)used : 0.0;
+            int64_t pd[4];
+            or_pseudo_diameter(n, rp, col, pd);
+            S.ell = pd[0]; S.bfs_t = pd[1]; S.bfs_u = pd[2]; S.ncomp = pd[3];
+            double chi[4] = {(double)n, (double)nnz, (double)pd[0], S.v};
+            int32_t ex = 0;
+            int cls = or_knn_select(model, chi, opt.knn_k, NULL, &ex);
+            if (cls < 0) {
+                status = cls;
+                free(val32); free(s.x); free(s.r); free(s.d); free(s.q);
+                goto done;
+            }
+            S.eps1_class = cls;
+            if (ex) S.flags |= OR_FLAG_KNN_EXACT;
+            e1 = k_eps_class[cls];
+        }
+        S.eps1_used = e1;
+        if (broke) {
+            S.flags |= OR_FLAG_FP32_BREAKDOWN;
+        } else {
+            for (;;) {
+                if (sqrt(s.gamma) <= e1 * scale) break;
+                if (n1 >= maxit1) { S.flags |= OR_FLAG_FP32_MAXIT; break; }
+                if (cg32_step(&s)) { S.flags |= OR_FLAG_FP32_BREAKDOWN; break; }
+                ++n1;
+            }
+        }
+        S.n1 = (int32_t)n1;
+        S.relres_sp = sqrt(s.gamma) / beta_b;
+        for (int64_t i = 0; i < n; ++i) x[i] = (double)s.x[i];   /* float64(x~) */
+        free(val32); free(s.x); free(s.r); free(s.d); free(s.q);
+    } else {
+        S.eps1_used = -1.0;
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+    }
+
+    /* ---- second stage: FP64 CG from x0 = float64(x~) with a true residual ---- */
+    {
+        double thr = eps2 * scale;
+        double gamma = true_residual(n, rp, col, val, b, x, r);
+        for (int64_t i = 0; i < n; ++i) d[i] = r[i];
+        S.relres_restart_true = sqrt(gamma) / beta_b;
+        int64_t n2 = 0;
+        int32_t restarts = 0;
+        for (;;) {
+            while (!(sqrt(gamma) <= thr)) {
+                if (n2 >= maxit2) { status = OR_ENOCONV; goto final; }
+                or_spmv64(n, rp, col, val, d, q);
+                double delta = dot64(n, d, q);
+                if (!isfinite(delta)) { status = OR_ENONFINITE; goto final; }
+                if (!(delta > 0.0)) { status = OR_ENOTSPD; goto final; }
+                double alpha = gamma / delta;
+                for (int64_t i = 0; i < n; ++i) {
+                    x[i] = fma(alpha, d[i], x[i]);
+                    r[i] = fma(-alpha, q[i], r[i]);
+                }
+                double gnew = dot64(n, r, r);
+                double beta = gnew / gamma;
+                for (int64_t i = 0; i < n; ++i) d[i] = fma(beta, d[i], r[i]);
+                gamma = gnew;
+                ++n2;
+            }
+            {
+                double rho = sqrt(true_residual(n, rp, col, val, b, x, q));
+                S.relres_final_true = rho / beta_b;
+                if (rho <= thr) break;
+                if (restarts >= opt.max_restarts) { status = OR_ENOCONV; break; }
+                ++restarts;
+                S.flags |= OR_FLAG_FINAL_RESTARTED;
+                gamma = true_residual(n, rp, col, val, b, x, r);
+                for (int64_t i = 0; i < n; ++i) d[i] = r[i];
+            }
+        }
+    final:
+        S.n2 = (int32_t)n2;
+        S.restarts = restarts;
+        if (status != OR_OK && S.relres_final_true == 0.0) {
+            double rho = sqrt(true_residual(n, rp, col, val, b, x, q));
+            S.relres_final_true = rho / beta_b;
+        }
+    }
+done:
+    free(r); free(d); free(q);
+    S.status = status;
+    if (st) *st = S;
+    return status;
+}
+
+/* ------------------------------------------------- diagnostics for pins -- */
+
+/* First nd search directions of FP64 CG from x0 = 0 (row-major nd x n).
+ * Returns the number of directions recorded (fewer if CG stopped exactly). */
+int64_t or_cg64_directions(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
+                           const double *b, int64_t nd, double *dirs)
+{
+    double *x = (double *)calloc((size_t)n, sizeof(double));
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    double *d = (double *)malloc(sizeof(double) * (size_t)n);
+    double *q = (double *)malloc(sizeof(double) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) { r[i] = b[i]; d[i] = b[i]; }
+    double gamma = dot64(n, r, r);
+    int64_t got = 0;
+    for (; got < nd; ++got) {
+        memcpy(dirs + got * n, d, sizeof(double) * (size_t)n);
+        if (gamma == 0.0) { ++got; break; }
+        or_spmv64(n, rp, col, val, d, q);
+        double delta = dot64(n, d, q);
+        if (!(delta > 0.0)) { ++got; break; }
+        double alpha = gamma / delta;
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] = fma(alpha, d[i], x[i]);
+            r[i] = fma(-alpha, q[i], r[i]);
+        }
+        double gnew = dot64(n, r, r);
+        double beta = gnew / gamma;
+        for (int64_t i = 0; i < n; ++i) d[i] = fma(beta, d[i], r[i]);
+        gamma = gnew;
+    }
+    free(x); free(r); free(d); free(q);
+    return got;
+}
+
+/* Plain CG from x0 = 0 entirely in one precision (prec = 32 or 64) for
+ * `iters` iterations; true_res[i] = ||b - A x_i|| in FP64 for i = 0..iters. */
+void or_cg_true_residuals(int32_t prec, int64_t n, const int64_t *rp, const int32_t *col,
+                          const double *val, const double *b, int64_t iters, double *true_res)
+{
+    int64_t nnz = rp[n];
+    double *xd = (double *)calloc((size_t)n, sizeof(double));
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)n);
+    if (prec == 32) {
+        float *val32 = (float *)malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
+        cg32_state s;
+        s.n = n; s.rp = rp; s.col = col; s.val = val32;
+        s.x = (float *)calloc((size_t)n, sizeof(float));
+        s.r = (float *)malloc(sizeof(float) * (size_t)n);
+        s.d = (float *)malloc(sizeof(float) * (size_t)n);
+        s.q = (float *)malloc(sizeof(float) * (size_t)n);
+        for (int64_t k = 0; k < nnz; ++k) val32[k] = (float)val[k];
+        for (int64_t i = 0; i < n; ++i) { s.r[i] = (float)b[i]; s.d[i] = s.r[i]; }
+        s.gamma = dot32(n, s.r, s.r);
+        for (int64_t it = 0; it <= iters; ++it) {
+            for (int64_t i = 0; i < n; ++i) xd[i] = (double)s.x[i];
+            true_res[it] = sqrt(true_residual(n, rp, col, val, b, xd, tmp));
+            if (it == iters) break;
+            if (s.gamma == 0.0 || cg32_step(&s)) {
+                for (int64_t j = it + 1; j <= iters; ++j) true_res[j] = true_res[it];
+                break;
+            }
+        }
+        free(val32); free(s.x); free(s.r); free(s.d); free(s.q);
+    } else {
+        double *r = (double *)malloc(sizeof(double) * (size_t)n);
+        double *d = (double *)malloc(sizeof(double) * (size_t)n);
+        double *q = (double *)malloc(sizeof(double) * (size_t)n);
+        for (int64_t i = 0; i < n; ++i) { r[i] = b[i]; d[i] = b[i]; }
+        double gamma = dot64(n, r, r);
+        for (int64_t it = 0; it <= iters; ++it) {
+            true_res[it] = sqrt(true_residual(n, rp, col, val, b, xd, tmp));
+            if (it == iters) break;
+            or_spmv64(n, rp, col, val, d, q);
+            double delta = dot64(n, d, q);
+            if (gamma == 0.0 || !(delta > 0.0)) {
+                for (int64_t j = it + 1; j <= iters; ++j) true_res[j] = true_res[it];
+                break;
+            }
+            double alpha = gamma / delta;
+            for (int64_t i = 0; i < n; ++i) {
+                xd[i] = fma(alpha, d[i], xd[i]);
+                r[i] = fma(-alpha, q[i], r[i]);
+            }
+            double gnew = dot64(n, r, r);
+            double beta = gnew / gamma;
+            for (int64_t i = 0; i < n; ++i) d[i] = fma(beta, d[i], r[i]);
+            gamma = gnew;
+        }
+        free(r); free(d); free(q);
+    }
+    free(xd); free(tmp);
+}
