@@ -1,0 +1,189 @@
+/*
+ * mpcg.h -- C ABI of the MI355X (gfx950) restarted mixed-precision CG library.
+ *
+ * The method (Prolubnikov, "Parameter Optimization for Restarted
+ * Mixed-Precision Iterative Sparse Solver", arXiv 2412.08059):
+ *   Algorithm I  -- CG on float32(A), float32(b) from x~0 = 0 down to the
+ *                   tolerance eps1, then float64(x~) as the start of FP64 CG on
+ *                   A x = b down to eps2 (sections "Two-Stage Algorithm ..."
+ *                   and "Conjugate Gradient Method").
+ *   Algorithm II -- the same, with eps1 picked per matrix: k0 FP32 iterations
+ *                   give v, the mean of ||r_i|| / ||r_{i-1}|| (eq. 13); the
+ *                   feature vector chi = (n, m, pseudo-diameter, v) is
+ *                   classified by weighted kNN into eps1 = 10^-t, t = 2..7
+ *                   (eq. 23), and the FP32 recurrence continues from iterate
+ *                   k0 (Remark 3).
+ *   2BFS         -- pseudo-diameter of the matrix graph by two breadth-first
+ *                   sweeps, maximised over connected components (section
+ *                   "Computing Pseudo-Diameter of the Graph Matrix").
+ *
+ * Conventions for every entry point:
+ *   - Every call returns an mpcg_status; 0 is success, negatives are errors.
+ *     No C++ exception crosses the ABI.
+ *   - Matrix, vector and output pointers are DEVICE pointers (hipMalloc or
+ *     torch tensors on the same GPU) unless stated otherwise; struct
+ *     arguments (mpcg_csr, mpcg_stats, mpcg_features_t, mpcg_options) are
+ *     HOST memory.
+ *   - The caller owns every buffer.  The library allocates no device memory:
+ *     all scratch lives in the arena handed over by mpcg_set_workspace.  It
+ *     allocates a few KB of pinned host memory per context for the readbacks.
+ *   - All work is enqueued on the context's stream; a call returns after its
+ *     results are complete (it synchronises that stream).  One context per
+ *     host thread and stream; calls on one context must not overlap.
+ *   - Tolerances are relative to ||b||_2 (tol_mode 0) or absolute (tol_mode 1).
+ */
+#ifndef MPCG_H
+#define MPCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MPCG_OK = 0,
+    MPCG_EINVAL = -1,     /* bad argument or malformed CSR; nothing was written */
+    MPCG_ENOTSPD = -2,    /* d^T A d <= 0 in the FP64 phase */
+    MPCG_ENOCONV = -3,    /* FP64 iteration cap or restart cap reached; x holds the last iterate */
+    MPCG_ENOMEM = -4,     /* workspace missing or smaller than mpcg_workspace_size */
+    MPCG_EDEVICE = -5,    /* a HIP runtime call failed or a device-side guard tripped */
+    MPCG_ENONFINITE = -6, /* NaN/Inf in A or b, or a non-finite d^T A d in the FP64 phase */
+    MPCG_EBUSY = -7,      /* batch engine full */
+    MPCG_ECANCELED = -8,  /* batch request cancelled */
+    MPCG_ENOMODEL = -9    /* eps1 = MPCG_EPS1_AUTO without a loaded kNN model */
+} mpcg_status;
+
+/* CSR matrix A (n x n), 0-based, DEVICE arrays.
+ *   row_ptr  n+1 entries, int32 (row_ptr_is_i64 = 0) or int64 (= 1);
+ *            row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz < 2^31.
+ *   col_idx  nnz int32 column indices, strictly increasing within a row.
+ *   val      nnz float64 values, finite, no stored zeros.
+ * The pattern is expected to be symmetric (A is SPD); it is not checked. */
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    const void *row_ptr;
+    int32_t row_ptr_is_i64;
+    int32_t pad_;
+    const int32_t *col_idx;
+    const double *val;
+} mpcg_csr;
+
+/* chi(A) = (n, m, pseudo-diameter, v) and the 2BFS by-products. */
+typedef struct {
+    int64_t n;            /* rows */
+    int64_t m;            /* stored entries (nnz, diagonal included) */
+    int64_t pdiam;        /* 2BFS pseudo-diameter, max over components */
+    int64_t bfs_t;        /* farthest vertex of the first sweep (component attaining pdiam) */
+    int64_t bfs_u;        /* farthest vertex of the second sweep */
+    int32_t n_components; /* connected components of the matrix graph */
+    int32_t k0_used;      /* FP32 iterations that entered v (< k0 only if CG ended early) */
+    double v;             /* eq. (13) */
+} mpcg_features_t;
+
+#define MPCG_FLAG_FP32_BREAKDOWN 1   /* FP32 d^T A d <= 0 or non-finite: switched to FP64 early */
+#define MPCG_FLAG_FP32_MAXIT 2       /* FP32 phase hit maxit1: switched to FP64 */
+#define MPCG_FLAG_FINAL_RESTARTED 4  /* final true residual above eps2: FP64 restarted from b - Ax */
+#define MPCG_FLAG_KNN_EXACT 8        /* a training sample had zero distance to chi */
+
+typedef struct {
+    int32_t n1;           /* FP32 iterations (the k0 prefix included) */
+    int32_t n2;           /* FP64 iterations */
+    int32_t restarts;     /* FP64 restarts after the final check */
+    int32_t flags;        /* MPCG_FLAG_* */
+    int32_t eps1_class;   /* t of eps1 = 10^-t chosen by kNN, -1 otherwise */
+    int32_t status;       /* same as the return value */
+    double eps1_used;     /* eps1 of the FP32 phase (-1 for FP64-only) */
+    double relres_sp;     /* recursive ||r~|| / ||b|| when the FP32 phase stopped */
+    double relres_restart_true; /* ||b - A float64(x~)|| / ||b|| at the restart */
+    double relres_final_true;   /* ||b - A x|| / ||b|| of the returned x */
+    double omega_measured;      /* (t_sp / n1) / (t_dp / n2), 0 if undefined */
+    double I_third;             /* n1 / 3 + n2, eq. (4) with omega = 1/3 */
+    double I_meas;              /* omega_measured * n1 + n2 */
+    double t_feat_ms;           /* 2BFS (Algorithm II only) */
+    double t_sp_ms;             /* ingest + FP32 phase (k0 prefix and kNN included) */
+    double t_dp_ms;             /* restart + FP64 phase + final check(s) */
+    double t_total_ms;
+    mpcg_features_t feat;       /* filled for eps1 = MPCG_EPS1_AUTO */
+} mpcg_stats;
+
+typedef struct {
+    int32_t k0;           /* FP32 iterations for v (Algorithm II); default 20, at most 64 */
+    int32_t knn_k;        /* neighbours; 0 = the model's k */
+    int32_t tol_mode;     /* 0 relative to ||b|| (default), 1 absolute */
+    int32_t max_restarts; /* FP64 restarts after a failed final check; default 5 */
+    int32_t graph_iters;  /* CG iterations enqueued between host polls; 0 = default (8) */
+    int32_t pad_;
+    int64_t maxit1;       /* FP32 cap; <= 0: n */
+    int64_t maxit2;       /* FP64 cap; <= 0: max(10 n, 1000) */
+} mpcg_options;
+
+typedef struct mpcg_ctx mpcg_ctx;
+
+#define MPCG_EPS1_AUTO 0.0     /* Algorithm II: features + kNN choose eps1 */
+#define MPCG_EPS1_NONE (-1.0)  /* FP64-only CG from x0 = 0 (the comparator) */
+
+/* Create a context bound to the current HIP device and to hip_stream
+ * (a hipStream_t; NULL = the default stream).  opt may be NULL (defaults).
+ * Errors: EINVAL (ctx NULL or options out of range), EDEVICE. */
+mpcg_status mpcg_create(mpcg_ctx **ctx, const mpcg_options *opt, void *hip_stream);
+
+/* Release the context and its pinned host buffers (not the workspace). */
+mpcg_status mpcg_destroy(mpcg_ctx *ctx);
+
+/* Bytes of device workspace needed for systems up to n rows and nnz entries. */
+mpcg_status mpcg_workspace_size(const mpcg_ctx *ctx, int64_t n, int64_t nnz, size_t *bytes);
+
+/* Hand the library a device arena (>= mpcg_workspace_size, 256-byte aligned).
+ * The caller keeps ownership and must keep it alive while the context uses it. */
+mpcg_status mpcg_set_workspace(mpcg_ctx *ctx, void *dev_arena, size_t bytes);
+
+/* Load the kNN model file (host path).  Text format: header lines
+ * "mpcg-knn-model 1", "k K", "mask M", "omega W", "ns N", "fmin f0..f3",
+ * "fmax f0..f3", then N lines "n m ell v t".  EINVAL on a malformed file. */
+mpcg_status mpcg_load_model(mpcg_ctx *ctx, const char *path);
+
+/* Algorithm II features of A: n, m, 2BFS pseudo-diameter (per component,
+ * maximised) and v over the first k0 FP32 CG iterations on float32(A) x =
+ * float32(b) from 0.  b is a device float64[n]. */
+mpcg_status mpcg_features(mpcg_ctx *ctx, const mpcg_csr *A, const double *b, int32_t k0,
+                          mpcg_features_t *out);
+
+/* Weighted kNN on host features: min-max normalisation from the model,
+ * squared Euclidean search, 1/rho weights (eq. 23); ties to the larger eps1.
+ * Writes eps1 = 10^-t and t.  ENOMODEL without a model. */
+mpcg_status mpcg_select_eps1(const mpcg_ctx *ctx, const mpcg_features_t *f, double *eps1,
+                             int32_t *cls);
+
+/* Solve A x = b.  x is a device float64[n] output (its input value is ignored;
+ * x0 = 0).  eps1 > 0: Algorithm I with that eps1; MPCG_EPS1_AUTO: Algorithm II;
+ * MPCG_EPS1_NONE: FP64-only CG.  eps2 > 0 is the final tolerance, checked on
+ * the true residual b - A x.  stats may be NULL.
+ * ||b|| = 0 returns x = 0 and MPCG_OK. */
+mpcg_status mpcg_solve(mpcg_ctx *ctx, const mpcg_csr *A, const double *b, double *x, double eps1,
+                       double eps2, mpcg_stats *stats);
+
+/* y = A x with the solver's SpMV kernel (one fma chain per row in CSR order).
+ * precision 64: x, y float64; precision 32: x, y float32 and A rounded to
+ * float32 (round to nearest even).  For parity tests and bandwidth timing. */
+mpcg_status mpcg_spmv(mpcg_ctx *ctx, const mpcg_csr *A, int32_t precision, const void *x, void *y);
+
+/* Breadth-first search from vertex src over the stored pattern (self-loops
+ * ignored).  dist: device int32[n], -1 for unreached vertices.  *ecc (host)
+ * gets the largest distance, *far (host) the smallest vertex at that distance. */
+mpcg_status mpcg_bfs(mpcg_ctx *ctx, const mpcg_csr *A, int64_t src, int32_t *dist, int64_t *ecc,
+                     int64_t *far);
+
+/* Time of the most recent mpcg_spmv kernel launch in milliseconds (HIP events
+ * on the context stream), 0 if none. */
+mpcg_status mpcg_last_kernel_ms(const mpcg_ctx *ctx, double *ms);
+
+const char *mpcg_strerror(mpcg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPCG_H */

@@ -1,0 +1,101 @@
+"""MI355X (gfx950) restarted mixed-precision CG (arXiv 2412.08059).
+
+The work runs in ``libmpcg.so`` (hand-written HIP kernels behind the C ABI in
+include/mpcg.h).  This package adds a ctypes binding (``capi``) and a small
+torch-facing wrapper: torch supplies device memory and the stream, nothing
+else.
+"""
+
+from __future__ import annotations
+
+import os
+
+from . import capi  # noqa: F401  (raises ImportError when the library is not built)
+from .capi import (  # noqa: F401
+    MPCG_EPS1_AUTO,
+    MPCG_EPS1_NONE,
+    MPCG_OK,
+    MpcgError,
+    mpcg_csr,
+    mpcg_options,
+)
+
+DEFAULT_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "knn_model.txt")
+
+
+class DeviceCSR:
+    """CSR matrix resident on the GPU (torch tensors) plus its C descriptor."""
+
+    def __init__(self, row_ptr, col, val, n: int, row_ptr_i64: bool = False):
+        self.row_ptr, self.col, self.val, self.n = row_ptr, col, val, int(n)
+        self.nnz = int(col.numel())
+        self.desc = mpcg_csr(self.n, self.nnz, row_ptr.data_ptr(), 1 if row_ptr_i64 else 0, 0,
+                             col.data_ptr() if self.nnz else 0, val.data_ptr() if self.nnz else 0)
+
+    @staticmethod
+    def from_host(a, device="cuda", row_ptr_i64: bool = False) -> "DeviceCSR":
+        import numpy as np
+        import torch
+        rp_dtype = np.int64 if row_ptr_i64 else np.int32
+        rp = torch.from_numpy(np.ascontiguousarray(a.row_ptr, dtype=rp_dtype)).to(device)
+        col = torch.from_numpy(np.ascontiguousarray(a.col, dtype=np.int32)).to(device)
+        val = torch.from_numpy(np.ascontiguousarray(a.val, dtype=np.float64)).to(device)
+        return DeviceCSR(rp, col, val, a.n, row_ptr_i64)
+
+
+class Solver:
+    """One library context bound to the current torch stream, with its own
+    workspace tensor sized for systems up to (n_max, nnz_max)."""
+
+    def __init__(self, n_max: int, nnz_max: int, *, k0: int = 20, knn_k: int = 0, tol_mode: int = 0,
+                 max_restarts: int = 5, graph_iters: int = 0, maxit1: int = 0, maxit2: int = 0,
+                 model: str | None = None, device="cuda"):
+        import torch
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        opt = mpcg_options(k0, knn_k, tol_mode, max_restarts, graph_iters, 0, maxit1, maxit2)
+        self.ctx = capi.mpcg_create(opt, self.stream.cuda_stream)
+        nbytes = capi.mpcg_workspace_size(self.ctx, max(1, n_max), max(0, nnz_max))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        st = capi.mpcg_set_workspace(self.ctx, self.workspace.data_ptr(), nbytes)
+        if st != MPCG_OK:
+            raise MpcgError(st, "mpcg_set_workspace")
+        if model:
+            st = capi.mpcg_load_model(self.ctx, model)
+            if st != MPCG_OK:
+                raise MpcgError(st, f"mpcg_load_model({model})")
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            capi.mpcg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, A: DeviceCSR, b, eps1: float, eps2: float = 1e-10, x=None):
+        """Returns (status, x, stats); x is a float64 device tensor."""
+        import torch
+        if x is None:
+            x = torch.empty(A.n, dtype=torch.float64, device=self.device)
+        st, stats = capi.mpcg_solve(self.ctx, A.desc, b.data_ptr(), x.data_ptr(), eps1, eps2)
+        return st, x, stats
+
+    def features(self, A: DeviceCSR, b, k0: int = 20):
+        return capi.mpcg_features(self.ctx, A.desc, b.data_ptr(), k0)
+
+    def spmv(self, A: DeviceCSR, x, precision: int = 64):
+        import torch
+        dt = torch.float64 if precision == 64 else torch.float32
+        y = torch.empty(A.n, dtype=dt, device=self.device)
+        st = capi.mpcg_spmv(self.ctx, A.desc, precision, x.data_ptr(), y.data_ptr())
+        return st, y
+
+    def bfs(self, A: DeviceCSR, src: int):
+        import torch
+        dist = torch.empty(A.n, dtype=torch.int32, device=self.device)
+        st, ecc, far = capi.mpcg_bfs(self.ctx, A.desc, src, dist.data_ptr())
+        return st, dist, ecc, far

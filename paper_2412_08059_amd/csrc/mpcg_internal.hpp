@@ -1,0 +1,129 @@
+// Internal declarations shared by the HIP kernels and the host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "knn.hpp"
+#include "mpcg.h"
+
+namespace mpcg {
+
+constexpr int kBlock = 256;           // threads per block of every multi-block kernel
+constexpr int kVecPerThread = 4;      // elements per thread in the vector kernels
+constexpr int kVecTile = kBlock * kVecPerThread;
+constexpr int kK0Max = 64;            // longest FP32 prefix recorded for v
+constexpr int kLdsBytes = 32768;      // LDS staging per SpMV block (val + gathered x)
+constexpr int kBfsSmallCap = 4096;    // frontier size handled by the one-workgroup BFS kernel
+constexpr int kBfsSmallThreads = 1024;
+constexpr int kBfsLevelBlocks = 1024; // grid of the multi-block BFS level kernel
+constexpr int kNumXcd = 8;            // MI355X: blocks are dispatched round-robin over 8 XCDs
+
+enum StopReason : int32_t { kRunning = 0, kConverged = 1, kMaxit = 2, kNotSpd = 3, kNonFinite = 4 };
+
+enum IngestError : int32_t {
+    kErrRowPtr = 1, kErrCol = 2, kErrUnsorted = 4, kErrNonFiniteA = 8, kErrNonFiniteB = 16
+};
+
+// Device-resident solver state: every scalar of the CG recurrence lives here,
+// so kernels can be enqueued ahead of the host and stop by themselves.
+struct alignas(256) DevState {
+    // CG recurrence (FP64 storage; alpha/beta hold the working-precision value)
+    double gamma;     // r.r of the current residual
+    double delta;     // d.(A d) of the last iteration
+    double alpha;
+    double beta;
+    double thr;       // stop when sqrt(gamma) <= thr
+    double bnorm2;    // ||b||^2 (FP64)
+    double resid2;    // ||b - A x||^2 from the residual kernel
+    double spare0;
+    int32_t iter;     // iterations done in this precision
+    int32_t maxit;
+    int32_t live;     // 1 while iterations must continue
+    int32_t reason;   // StopReason
+    int32_t k0rec;    // ratios[i] = ||r_{i+1}|| / ||r_i|| is recorded while i < k0rec
+    int32_t guard;    // device-side guard tripped (bounded loop exhausted)
+    int32_t ing_err;  // IngestError bits
+    int32_t max_row;  // longest row seen by the ingest kernel
+    uint32_t tk_spmv, tk_upd, tk_init, tk_misc;  // tickets of the single-pass reductions
+    double ratios[kK0Max];
+    // BFS
+    int32_t bfs_level;    // distance of the current frontier
+    int32_t bfs_cur;      // current frontier size
+    int32_t bfs_next;     // next frontier size (atomic counter)
+    int32_t bfs_parity;   // queue buffer holding the current frontier
+    int32_t bfs_done;
+    int32_t bfs_cur_min;  // smallest vertex of the current frontier
+    int32_t bfs_next_min;
+    int32_t bfs_far;      // smallest vertex of the last non-empty frontier (when done)
+    int64_t bfs_visited;
+    uint32_t tk_bfs;
+    int32_t ncomp;
+    uint64_t comp_best;   // (ecc << 32) | ~component of the best component
+};
+
+// Byte offsets of every region inside the caller's arena.
+struct Layout {
+    size_t state, part, rp32, val32;
+    size_t x32, r32, q32, dA32, dB32;
+    size_t r64, q64, dA64, dB64;
+    size_t dist, q0, q1, label, tarr, best;
+    size_t total;
+    int64_t n, nnz, part_cap;
+};
+
+Layout plan_layout(int64_t n, int64_t nnz);
+
+// Rows per SpMV block so that a block's entries fill one LDS chunk on average.
+int spmv_rows_per_block(int64_t n, int64_t nnz, int value_bytes);
+
+// ----- launch wrappers (kernels_cg.hip) -----
+void launch_ingest(hipStream_t s, const void *rp_in, int rp_is_i64, const int32_t *col,
+                   const double *val, const double *b, int32_t n, int64_t nnz, int32_t *rp32_out,
+                   float *val32_out, DevState *st);
+void launch_fill_f64(hipStream_t s, double *p, int64_t n, double v);
+void launch_fill_i32(hipStream_t s, int32_t *p, int64_t n, int32_t v);
+void launch_init32(hipStream_t s, const double *b, float *x, float *r, float *dA, int32_t n,
+                   double eps, int abs_tol, int32_t maxit, int32_t k0rec, double *part, DevState *st);
+void launch_init64(hipStream_t s, const double *b, double *x, double *r, double *dA, int32_t n,
+                   double eps, int abs_tol, int32_t maxit, double *part, DevState *st);
+void launch_set_phase(hipStream_t s, DevState *st, double thr, int32_t maxit, int32_t k0rec,
+                      int32_t reset_iter);
+template <typename T>
+void launch_cg_spmv(hipStream_t s, const int32_t *rp, const int32_t *col, const T *val, int32_t n,
+                    int R, const T *r, T *dA, T *dB, T *q, double *part, DevState *st);
+template <typename T>
+void launch_cg_update(hipStream_t s, int32_t n, T *x, T *r, const T *q, const T *dA, const T *dB,
+                      double *part, DevState *st);
+// r = b - A x (x from float x32 when x32 != nullptr, else from x64), x64 <- float64(x32),
+// zero the next "old direction" buffer, gamma = r.r, set thr/maxit.
+void launch_restart(hipStream_t s, const int32_t *rp, const int32_t *col, const double *val,
+                    int32_t n, int R, const float *x32, double *x64, const double *b, double *r,
+                    double *dA, double *dB, double eps, int abs_tol, int32_t maxit, double *part,
+                    DevState *st);
+void launch_resid(hipStream_t s, const int32_t *rp, const int32_t *col, const double *val,
+                  int32_t n, int R, const double *x64, const double *b, double *part, DevState *st);
+template <typename T>
+void launch_spmv_plain(hipStream_t s, const int32_t *rp, const int32_t *col, const T *val,
+                       int32_t n, int R, const T *x, T *y);
+
+// ----- BFS (kernels_bfs.hip) -----
+struct BfsBufs {
+    const int32_t *rp, *col;
+    int32_t n;
+    int32_t lanes;          // lanes per frontier vertex in the one-workgroup kernel
+    int32_t *dist, *q0, *q1, *label, *tarr;
+    unsigned long long *best;
+    DevState *st;
+};
+void launch_bfs_seed_single(hipStream_t s, const BfsBufs &b, int32_t src);
+void launch_bfs_round(hipStream_t s, const BfsBufs &b, int levels);
+void launch_cc(hipStream_t s, const BfsBufs &b);
+void launch_bfs_seed_roots(hipStream_t s, const BfsBufs &b);
+void launch_comp_argmax(hipStream_t s, const BfsBufs &b, int second_sweep);
+void launch_bfs_seed_far(hipStream_t s, const BfsBufs &b);
+void launch_comp_final(hipStream_t s, const BfsBufs &b);
+
+}  // namespace mpcg
