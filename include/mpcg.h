@@ -180,6 +180,22 @@ mpcg_status mpcg_bfs(mpcg_ctx *ctx, const mpcg_csr *A, int64_t src, int32_t *dis
  * on the context stream), 0 if none. */
 mpcg_status mpcg_last_kernel_ms(const mpcg_ctx *ctx, double *ms);
 
+/* Kernels that mpcg_time_kernel can time (the ones a solve launches). */
+#define MPCG_KERNEL_CG_SPMV_F64 0   /* direction update + q = A d + d.q, FP64 */
+#define MPCG_KERNEL_CG_SPMV_F32 1   /* the same on float32(A), FP32 vectors */
+#define MPCG_KERNEL_UPDATE_F64 2    /* x += alpha d, r -= alpha q, r.r, FP64 */
+#define MPCG_KERNEL_UPDATE_F32 3
+#define MPCG_KERNEL_SPMV_F64 4      /* plain y = A x (mpcg_spmv) */
+#define MPCG_KERNEL_SPMV_F32 5
+
+/* Measurement hook: run `reps` back-to-back launches of one solver kernel on A
+ * with the workspace's scratch vectors (set to finite values, recurrence held
+ * live), bracketed by HIP events on the context stream; *ms gets the mean
+ * milliseconds per launch.  Overwrites the workspace only.  EINVAL for an
+ * unknown kernel id or reps < 1. */
+mpcg_status mpcg_time_kernel(mpcg_ctx *ctx, const mpcg_csr *A, int32_t kernel, int32_t reps,
+                             double *ms);
+
 const char *mpcg_strerror(mpcg_status s);
 
 #ifdef __cplusplus

@@ -1,6 +1,7 @@
 """Build the gfx950 HIP library ``libmpcg.so`` in-tree with hipcc.
 
-    python -m paper_2412_08059_amd.build        # or paper_2412_08059_amd.build.build()
+    python paper_2412_08059_amd/build.py     (run as a script: importing the
+                                             package would load the library)
 
 Device code is compiled for gfx950 only, with packed-FP32 instructions turned
 off.  The host-side kNN file is compiled with -ffp-contract=off so that its

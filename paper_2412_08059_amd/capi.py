@@ -38,8 +38,15 @@ MPCG_FLAG_KNN_EXACT = 8
 EXPORTED = (
     "mpcg_create", "mpcg_destroy", "mpcg_workspace_size", "mpcg_set_workspace", "mpcg_load_model",
     "mpcg_features", "mpcg_select_eps1", "mpcg_solve", "mpcg_spmv", "mpcg_bfs",
-    "mpcg_last_kernel_ms", "mpcg_strerror",
+    "mpcg_last_kernel_ms", "mpcg_time_kernel", "mpcg_strerror",
 )
+
+MPCG_KERNEL_CG_SPMV_F64 = 0
+MPCG_KERNEL_CG_SPMV_F32 = 1
+MPCG_KERNEL_UPDATE_F64 = 2
+MPCG_KERNEL_UPDATE_F32 = 3
+MPCG_KERNEL_SPMV_F64 = 4
+MPCG_KERNEL_SPMV_F32 = 5
 
 
 class mpcg_csr(ctypes.Structure):
@@ -94,6 +101,7 @@ def _load():
         "mpcg_spmv": ([P, ctypes.POINTER(mpcg_csr), I32, P, P], I32),
         "mpcg_bfs": ([P, ctypes.POINTER(mpcg_csr), I64, P, ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
         "mpcg_last_kernel_ms": ([P, ctypes.POINTER(D)], I32),
+        "mpcg_time_kernel": ([P, ctypes.POINTER(mpcg_csr), I32, I32, ctypes.POINTER(D)], I32),
         "mpcg_strerror": ([I32], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -186,4 +194,11 @@ def mpcg_bfs(ctx: int, A: mpcg_csr, src: int, dist_ptr: int):
 def mpcg_last_kernel_ms(ctx: int) -> float:
     ms = ctypes.c_double(0.0)
     _check(lib.mpcg_last_kernel_ms(ctypes.c_void_p(ctx), ctypes.byref(ms)), "mpcg_last_kernel_ms")
+    return ms.value
+
+
+def mpcg_time_kernel(ctx: int, A: mpcg_csr, kernel: int, reps: int) -> float:
+    ms = ctypes.c_double(0.0)
+    _check(lib.mpcg_time_kernel(ctypes.c_void_p(ctx), ctypes.byref(A), kernel, reps, ctypes.byref(ms)),
+           "mpcg_time_kernel")
     return ms.value

@@ -496,8 +496,12 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
                        abs_tol, maxit2, p.part, p.st);
         HIPCHK(hipGetLastError());
     } else {
+        // FP64-only CG from x0 = 0 through the restart kernel: r = b - A*0 = b
+        // exactly, with the same reductions as the mixed path's restart.
         HIPCHK(hipEventRecord(c->tm[3], c->stream));
-        launch_init64(c->stream, b, x, r64, dA64, p.n, eps2, abs_tol, maxit2, p.part, p.st);
+        launch_fill_f64(c->stream, x, n, 0.0);
+        launch_restart(c->stream, p.rp, p.col, p.val, p.n, p.R64, nullptr, x, b, r64, dA64, dB64, eps2,
+                       abs_tol, maxit2, p.part, p.st);
         HIPCHK(hipGetLastError());
     }
     rc = read_state(c, p, &s);
@@ -610,6 +614,70 @@ mpcg_status mpcg_last_kernel_ms(const mpcg_ctx *c, double *ms)
 {
     if (!c || !ms) return MPCG_EINVAL;
     *ms = c->last_kernel_ms;
+    return MPCG_OK;
+}
+
+mpcg_status mpcg_time_kernel(mpcg_ctx *c, const mpcg_csr *A, int32_t kernel, int32_t reps, double *ms)
+{
+    if (!c || !A || !ms || reps < 1 || kernel < 0 || kernel > 5) return MPCG_EINVAL;
+    const bool f32 = (kernel & 1) != 0;
+    Plan p;
+    mpcg_status rc = ingest(c, A, nullptr, f32, &p);
+    if (rc != MPCG_OK) return rc;
+    float *x32 = p.at<float>(p.L.x32), *r32 = p.at<float>(p.L.r32), *q32 = p.at<float>(p.L.q32);
+    float *dA32 = p.at<float>(p.L.dA32), *dB32 = p.at<float>(p.L.dB32);
+    double *r64 = p.at<double>(p.L.r64), *q64 = p.at<double>(p.L.q64);
+    double *dA64 = p.at<double>(p.L.dA64), *dB64 = p.at<double>(p.L.dB64);
+    double *x64 = p.at<double>(p.L.best);   // the BFS key array doubles as x here
+    if (f32) {
+        launch_fill_f32(c->stream, x32, p.n, 0.0f);
+        launch_fill_f32(c->stream, r32, p.n, 1.0f);
+        launch_fill_f32(c->stream, q32, p.n, 0.5f);
+        launch_fill_f32(c->stream, dA32, p.n, 0.25f);
+        launch_fill_f32(c->stream, dB32, p.n, 0.25f);
+    } else {
+        launch_fill_f64(c->stream, x64, p.n, 0.0);
+        launch_fill_f64(c->stream, r64, p.n, 1.0);
+        launch_fill_f64(c->stream, q64, p.n, 0.5);
+        launch_fill_f64(c->stream, dA64, p.n, 0.25);
+        launch_fill_f64(c->stream, dB64, p.n, 0.25);
+    }
+    launch_timing_state(c->stream, p.st);
+    HIPCHK(hipGetLastError());
+    auto one = [&]() {
+        switch (kernel) {
+        case MPCG_KERNEL_CG_SPMV_F64:
+            launch_cg_spmv<double>(c->stream, p.rp, p.col, p.val, p.n, p.R64, r64, dA64, dB64, q64, p.part, p.st);
+            break;
+        case MPCG_KERNEL_CG_SPMV_F32:
+            launch_cg_spmv<float>(c->stream, p.rp, p.col, p.at<float>(p.L.val32), p.n, p.R32, r32, dA32, dB32,
+                                  q32, p.part, p.st);
+            break;
+        case MPCG_KERNEL_UPDATE_F64:
+            launch_cg_update<double>(c->stream, p.n, x64, r64, q64, dA64, dB64, p.part, p.st);
+            break;
+        case MPCG_KERNEL_UPDATE_F32:
+            launch_cg_update<float>(c->stream, p.n, x32, r32, q32, dA32, dB32, p.part, p.st);
+            break;
+        case MPCG_KERNEL_SPMV_F64:
+            launch_spmv_plain<double>(c->stream, p.rp, p.col, p.val, p.n, p.R64, r64, q64);
+            break;
+        default:
+            launch_spmv_plain<float>(c->stream, p.rp, p.col, p.at<float>(p.L.val32), p.n, p.R32, r32, q32);
+            break;
+        }
+    };
+    one();   // warm caches and code
+    HIPCHK(hipEventRecord(c->tm[5], c->stream));
+    for (int i = 0; i < reps; ++i) one();
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(c->tm[6], c->stream));
+    HIPCHK(hipEventSynchronize(c->tm[6]));
+    DevState s;
+    rc = read_state(c, p, &s);
+    if (rc != MPCG_OK) return rc;
+    if (!s.live) return MPCG_EDEVICE;   // a launch exited early: the timing would be wrong
+    *ms = elapsed(c->tm[5], c->tm[6]) / reps;
     return MPCG_OK;
 }
 

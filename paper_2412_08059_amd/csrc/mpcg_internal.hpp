@@ -84,13 +84,13 @@ void launch_ingest(hipStream_t s, const void *rp_in, int rp_is_i64, const int32_
                    const double *val, const double *b, int32_t n, int64_t nnz, int32_t *rp32_out,
                    float *val32_out, DevState *st);
 void launch_fill_f64(hipStream_t s, double *p, int64_t n, double v);
+void launch_fill_f32(hipStream_t s, float *p, int64_t n, float v);
 void launch_fill_i32(hipStream_t s, int32_t *p, int64_t n, int32_t v);
 void launch_init32(hipStream_t s, const double *b, float *x, float *r, float *dA, int32_t n,
                    double eps, int abs_tol, int32_t maxit, int32_t k0rec, double *part, DevState *st);
-void launch_init64(hipStream_t s, const double *b, double *x, double *r, double *dA, int32_t n,
-                   double eps, int abs_tol, int32_t maxit, double *part, DevState *st);
 void launch_set_phase(hipStream_t s, DevState *st, double thr, int32_t maxit, int32_t k0rec,
                       int32_t reset_iter);
+void launch_timing_state(hipStream_t s, DevState *st);
 template <typename T>
 void launch_cg_spmv(hipStream_t s, const int32_t *rp, const int32_t *col, const T *val, int32_t n,
                     int R, const T *r, T *dA, T *dB, T *q, double *part, DevState *st);
@@ -98,7 +98,7 @@ template <typename T>
 void launch_cg_update(hipStream_t s, int32_t n, T *x, T *r, const T *q, const T *dA, const T *dB,
                       double *part, DevState *st);
 // r = b - A x (x from float x32 when x32 != nullptr, else from x64), x64 <- float64(x32),
-// zero the next "old direction" buffer, gamma = r.r, set thr/maxit.
+// zero the next "old direction" buffer, gamma = r.r, ||b||^2, set thr/maxit.
 void launch_restart(hipStream_t s, const int32_t *rp, const int32_t *col, const double *val,
                     int32_t n, int R, const float *x32, double *x64, const double *b, double *r,
                     double *dA, double *dB, double eps, int abs_tol, int32_t maxit, double *part,

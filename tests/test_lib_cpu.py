@@ -22,8 +22,8 @@ def _declared():
 @pytest.fixture(scope="module")
 def built():
     if not os.path.exists(LIB):
-        from paper_2412_08059_amd import build
-        build.build()
+        import __graft_entry__
+        __graft_entry__._hip_build_module().build()
     return LIB
 
 
