@@ -14,6 +14,7 @@ using namespace mpcg;
 
 struct mpcg_ctx {
     int device = 0;
+    int num_cu = 256;
     hipStream_t stream = nullptr;
     mpcg_options opt{};
     char *ws = nullptr;
@@ -24,6 +25,7 @@ struct mpcg_ctx {
     KnnModel model;
     bool has_model = false;
     float last_kernel_ms = 0.0f;
+    bool force_csr = false;   // MPCG_FORCE_CSR=1: always use the CSR-stream kernels
 };
 
 #define HIPCHK(x)                                        \
@@ -47,9 +49,8 @@ Layout plan_layout(int64_t n, int64_t nnz)
     const size_t N = (size_t)n, M = (size_t)(nnz > 0 ? nnz : 1);
     L.n = n;
     L.nnz = nnz;
-    L.part_cap = (n + 31) / 32 + 64;   // SpMV blocks hold >= 32 rows; vector blocks 1024
     L.state = take(sizeof(DevState));
-    L.part = take(sizeof(double) * 2 * (size_t)L.part_cap);
+    L.part = take(sizeof(double) * 3 * (size_t)kMaxGrid);   // product partials (2 per block), update partials
     L.rp32 = take(sizeof(int32_t) * (N + 1));
     L.val32 = take(sizeof(float) * M);
     L.x32 = take(sizeof(float) * N);
@@ -67,12 +68,21 @@ Layout plan_layout(int64_t n, int64_t nnz)
     L.label = take(sizeof(int32_t) * N);
     L.tarr = take(sizeof(int32_t) * N);
     L.best = take(sizeof(unsigned long long) * N);
+    // SELL-64 copy: padding up to the same number of entries again is accepted
+    const size_t nsl = (N + 63) / 64;
+    L.sell_cap = 2 * (int64_t)M + 64 * 64;
+    L.sell_wid = take(sizeof(int64_t) * nsl);
+    L.sell_off = take(sizeof(int64_t) * (nsl + 1));
+    L.sell_col = take(sizeof(int32_t) * (size_t)L.sell_cap);
+    L.sell_v64 = take(sizeof(double) * (size_t)L.sell_cap);
+    L.sell_v32 = take(sizeof(float) * (size_t)L.sell_cap);
     L.total = off;
     return L;
 }
 
-int spmv_rows_per_block(int64_t n, int64_t nnz, int value_bytes)
+SpmvShape spmv_shape(int64_t n, int64_t nnz, int value_bytes, int num_cu)
 {
+    // rows per tile so that a tile's entries fill one LDS chunk on average
     const int64_t chunk = kLdsBytes / (2 * value_bytes);
     int64_t avg = n > 0 ? (nnz + n - 1) / n : 1;
     if (avg < 1) avg = 1;
@@ -80,7 +90,15 @@ int spmv_rows_per_block(int64_t n, int64_t nnz, int value_bytes)
     R = (R / 32) * 32;
     if (R < 32) R = 32;
     if (R > kBlock) R = kBlock;
-    return (int)R;
+    SpmvShape sh;
+    sh.n = (int32_t)n;
+    sh.R = (int32_t)R;
+    sh.ntiles = (int32_t)((n + R - 1) / R);
+    int64_t g = (int64_t)kSpmvBlocksPerCu * num_cu;
+    if (g > kMaxGrid) g = kMaxGrid;
+    if (g > sh.ntiles) g = sh.ntiles;
+    sh.grid = (int32_t)(g < 1 ? 1 : g);
+    return sh;
 }
 
 }  // namespace mpcg
@@ -95,8 +113,12 @@ struct Plan {
     const int32_t *col = nullptr;
     const double *val = nullptr;
     DevState *st = nullptr;
-    double *part = nullptr;
-    int R32 = 256, R64 = 256;
+    double *sp = nullptr;   // partials written by the product kernels (2 per block)
+    double *up = nullptr;   // partials written by the update kernel
+    SpmvShape sh32{}, sh64{};
+    SellMat sell{};
+    bool use_sell = false;
+    int nup = 1;
     char *ws = nullptr;
     template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
 };
@@ -124,37 +146,129 @@ mpcg_status ingest(mpcg_ctx *c, const mpcg_csr *A, const double *b, bool need_va
     p->col = A->col_idx;
     p->val = A->val;
     p->st = p->at<DevState>(p->L.state);
-    p->part = p->at<double>(p->L.part);
+    p->sp = p->at<double>(p->L.part);
+    p->up = p->sp + 2 * kMaxGrid;
     int32_t *rp32 = A->row_ptr_is_i64 ? p->at<int32_t>(p->L.rp32) : nullptr;
     p->rp = A->row_ptr_is_i64 ? rp32 : static_cast<const int32_t *>(A->row_ptr);
     HIPCHK(hipMemsetAsync(p->st, 0, sizeof(DevState), c->stream));
     launch_ingest(c->stream, A->row_ptr, A->row_ptr_is_i64 ? 1 : 0, A->col_idx, A->val, b, p->n,
-                  A->nnz, rp32, need_val32 ? p->at<float>(p->L.val32) : nullptr, p->st);
+                  A->nnz, rp32, p->st);
+    // SELL-64 slice widths and offsets (reads only row pointers, so it is safe
+    // to enqueue before the validation verdict is known)
+    int64_t *soff = p->at<int64_t>(p->L.sell_off);
+    launch_sell_plan(c->stream, p->rp, p->n, p->at<int64_t>(p->L.sell_wid), soff);
     HIPCHK(hipGetLastError());
-    DevState s;
-    mpcg_status rc = read_state(c, *p, &s);
-    if (rc != MPCG_OK) return rc;
-    if (s.ing_err & (kErrRowPtr | kErrCol | kErrUnsorted)) return MPCG_EINVAL;
-    if (s.ing_err & (kErrNonFiniteA | kErrNonFiniteB)) return MPCG_ENONFINITE;
-    p->R64 = spmv_rows_per_block(A->n, A->nnz, 8);
-    p->R32 = spmv_rows_per_block(A->n, A->nnz, 4);
+    const int nsl = (p->n + 63) / 64;
+    HIPCHK(hipMemcpyAsync(&c->hst[2].spare_i64, soff + nsl, sizeof(int64_t), hipMemcpyDeviceToHost,
+                          c->stream));
+    int64_t padded = 0;
+    {
+        DevState s;
+        HIPCHK(hipMemcpyAsync(&c->hst[1], p->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        s = c->hst[1];
+        padded = c->hst[2].spare_i64;
+        if (s.ing_err & (kErrRowPtr | kErrCol | kErrUnsorted)) return MPCG_EINVAL;
+        if (s.ing_err & (kErrNonFiniteA | kErrNonFiniteB)) return MPCG_ENONFINITE;
+        p->use_sell = padded >= 0 && padded <= p->L.sell_cap && !c->force_csr;
+        p->sell.idx16 = s.max_band < 32768 ? 1 : 0;
+    }
+    p->sh64 = spmv_shape(A->n, A->nnz, 8, c->num_cu);
+    p->sh32 = spmv_shape(A->n, A->nnz, 4, c->num_cu);
+    p->nup = vec_grid(A->n);
+    if (p->use_sell) {
+        SellMat &m = p->sell;
+        m.rp = p->rp;
+        m.off = soff;
+        m.n = p->n;
+        m.nslices = nsl;
+        int64_t g = ((int64_t)nsl + kBlock / 64 - 1) / (kBlock / 64);
+        if (g > kMaxGrid) g = kMaxGrid;
+        m.grid = (int32_t)(g < 1 ? 1 : g);
+        m.scol = p->ws + p->L.sell_col;
+        m.v64 = p->at<double>(p->L.sell_v64);
+        m.v32 = need_val32 ? p->at<float>(p->L.sell_v32) : nullptr;
+        launch_sell_fill(c->stream, p->rp, A->col_idx, A->val, p->n, soff, p->ws + p->L.sell_col, m.idx16,
+                         p->at<double>(p->L.sell_v64), need_val32 ? p->at<float>(p->L.sell_v32) : nullptr);
+    } else if (need_val32) {
+        launch_cast32(c->stream, A->val, p->at<float>(p->L.val32), A->nnz);
+    }
+    HIPCHK(hipGetLastError());
     return MPCG_OK;
+}
+
+// ---- dispatch: SELL-64 kernels when the padded copy fits, CSR-stream otherwise
+
+int prod_grid(const Plan &p, bool f32) { return p.use_sell ? p.sell.grid : (f32 ? p.sh32.grid : p.sh64.grid); }
+
+template <typename T> const T *csr_vals(const Plan &p);
+template <> const float *csr_vals<float>(const Plan &p) { return p.at<float>(p.L.val32); }
+template <> const double *csr_vals<double>(const Plan &p) { return p.val; }
+template <typename T> const SpmvShape &csr_shape(const Plan &p);
+template <> const SpmvShape &csr_shape<float>(const Plan &p) { return p.sh32; }
+template <> const SpmvShape &csr_shape<double>(const Plan &p) { return p.sh64; }
+
+template <typename T>
+void run_cg_spmv(hipStream_t s, const Plan &p, const T *r, T *dA, T *dB, T *q, int it, int it0)
+{
+    if (p.use_sell)
+        launch_sell_cg_spmv<T>(s, p.sell, r, dA, dB, q, p.up, p.nup, p.sp, it, it0, p.st);
+    else
+        launch_cg_spmv<T>(s, csr_shape<T>(p), p.rp, p.col, csr_vals<T>(p), r, dA, dB, q, p.up, p.nup, p.sp,
+                          it, it0, p.st);
+}
+
+template <typename T>
+void run_cg_update(hipStream_t s, const Plan &p, T *x, T *r, const T *q, const T *dA, const T *dB, int it)
+{
+    launch_cg_update<T>(s, p.n, x, r, q, dA, dB, p.sp, prod_grid(p, sizeof(T) == 4), p.up, it, p.st);
+}
+
+void run_restart(hipStream_t s, const Plan &p, const float *x32, double *x, const double *b, double *r,
+                 double *dA, double *dB, int it0, double eps, int abs_tol, int32_t maxit)
+{
+    if (p.use_sell) {
+        launch_sell_restart(s, p.sell, x32, x, b, r, dA, dB, it0, p.sp, p.st);
+        launch_fin_restart(s, p.sp, p.sell.grid, it0, eps, abs_tol, maxit, p.st);
+    } else {
+        launch_restart(s, p.sh64, p.rp, p.col, p.val, x32, x, b, r, dA, dB, it0, eps, abs_tol, maxit, p.sp,
+                       p.st);
+    }
+}
+
+void run_resid(hipStream_t s, const Plan &p, const double *x, const double *b)
+{
+    if (p.use_sell) {
+        launch_sell_resid(s, p.sell, x, b, p.sp, p.st);
+        launch_fin_resid(s, p.sp, p.sell.grid, p.st);
+    } else {
+        launch_resid(s, p.sh64, p.rp, p.col, p.val, x, b, p.sp, p.st);
+    }
+}
+
+template <typename T>
+void run_plain(hipStream_t s, const Plan &p, const T *x, T *y)
+{
+    if (p.use_sell) launch_sell_plain<T>(s, p.sell, x, y);
+    else launch_spmv_plain<T>(s, csr_shape<T>(p), p.rp, p.col, csr_vals<T>(p), x, y);
 }
 
 int poll_iters(const mpcg_ctx *c) { return c->opt.graph_iters > 0 ? c->opt.graph_iters : 8; }
 
-// Run CG iterations in precision T until the device says stop.  Groups of
-// iterations are enqueued one ahead of the state snapshot being inspected.
+// Run CG iterations in precision T from iteration `it` (phase started at
+// `it0`) until the device says stop.  Groups of iterations are enqueued one
+// ahead of the state snapshot being inspected; iterations enqueued after the
+// stop return at once.
 template <typename T>
-mpcg_status cg_loop(mpcg_ctx *c, const Plan &p, const T *val, int R, T *x, T *r, T *q, T *dA,
-                    T *dB, DevState *out)
+mpcg_status cg_loop(mpcg_ctx *c, const Plan &p, T *x, T *r, T *q, T *dA, T *dB, int it, int it0,
+                    DevState *out)
 {
     const int G = poll_iters(c);
     int64_t k = 0;
     for (;;) {
-        for (int g = 0; g < G; ++g) {
-            launch_cg_spmv<T>(c->stream, p.rp, p.col, val, p.n, R, r, dA, dB, q, p.part, p.st);
-            launch_cg_update<T>(c->stream, p.n, x, r, q, dA, dB, p.part, p.st);
+        for (int g = 0; g < G; ++g, ++it) {
+            run_cg_spmv<T>(c->stream, p, r, dA, dB, q, it, it0);
+            run_cg_update<T>(c->stream, p, x, r, q, dA, dB, it);
         }
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(&c->hst[k & 1], p.st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
@@ -164,6 +278,7 @@ mpcg_status cg_loop(mpcg_ctx *c, const Plan &p, const T *val, int R, T *x, T *r,
             if (!c->hst[(k - 1) & 1].live) break;
         }
         ++k;
+        if (it > 0x7ffffff0 - G) return MPCG_EDEVICE;
     }
     return read_state(c, p, out);
 }
@@ -259,11 +374,11 @@ mpcg_status fp32_prefix(mpcg_ctx *c, const Plan &p, const double *b, int32_t k0,
     float *x = p.at<float>(p.L.x32), *r = p.at<float>(p.L.r32), *q = p.at<float>(p.L.q32);
     float *dA = p.at<float>(p.L.dA32), *dB = p.at<float>(p.L.dB32);
     // thr = 0: only gamma' = 0 or a breakdown ends the prefix before k0
-    launch_init32(c->stream, b, x, r, dA, p.n, 0.0, 1, k0, k0, p.part, p.st);
+    launch_init32(c->stream, b, x, r, dA, p.n, 0.0, 1, k0, k0, p.sp, p.st);
     HIPCHK(hipGetLastError());
     mpcg_status rc = read_state(c, p, s);
     if (rc != MPCG_OK) return rc;
-    if (s->live) rc = cg_loop<float>(c, p, p.at<float>(p.L.val32), p.R32, x, r, q, dA, dB, s);
+    if (s->live) rc = cg_loop<float>(c, p, x, r, q, dA, dB, 0, 0, s);
     return rc;
 }
 
@@ -322,7 +437,12 @@ mpcg_status mpcg_create(mpcg_ctx **out, const mpcg_options *opt, void *hip_strea
     if (!c) return MPCG_EDEVICE;
     c->opt = o;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    {
+        const char *e = std::getenv("MPCG_FORCE_CSR");
+        c->force_csr = e && e[0] == '1';
+    }
     if (hipGetDevice(&c->device) != hipSuccess ||
+        hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
         hipHostMalloc((void **)&c->hst, 3 * sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
         delete c;
         return MPCG_EDEVICE;
@@ -440,7 +560,6 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
     if (!dponly) {
         float *x32 = p.at<float>(p.L.x32), *r32 = p.at<float>(p.L.r32), *q32 = p.at<float>(p.L.q32);
         float *dA32 = p.at<float>(p.L.dA32), *dB32 = p.at<float>(p.L.dB32);
-        const float *val32 = p.at<float>(p.L.val32);
         bool broke = false;
         if (autoe) {
             HIPCHK(hipEventRecord(c->tm[1], c->stream));
@@ -468,20 +587,19 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
             if (exact) S.flags |= MPCG_FLAG_KNN_EXACT;
             if (!broke) {
                 const double thr1 = abs_tol ? e1 : e1 * std::sqrt(s.bnorm2);
-                launch_set_phase(c->stream, p.st, thr1, maxit1, c->opt.k0, 0);
+                // continue the same recurrence from iteration k0 (Remark 3)
+                launch_set_phase(c->stream, p.st, thr1, maxit1, c->opt.k0);
                 HIPCHK(hipGetLastError());
-                rc = read_state(c, p, &s);
-                if (rc != MPCG_OK) return rc;
-                if (s.live) rc = cg_loop<float>(c, p, val32, p.R32, x32, r32, q32, dA32, dB32, &s);
+                rc = cg_loop<float>(c, p, x32, r32, q32, dA32, dB32, s.iter, 0, &s);
                 if (rc != MPCG_OK) return rc;
             }
         } else {
-            launch_init32(c->stream, b, x32, r32, dA32, p.n, eps1, abs_tol, maxit1, 0, p.part, p.st);
+            launch_init32(c->stream, b, x32, r32, dA32, p.n, eps1, abs_tol, maxit1, 0, p.sp, p.st);
             HIPCHK(hipGetLastError());
             rc = read_state(c, p, &s);
             if (rc != MPCG_OK) return rc;
             if (s.bnorm2 == 0.0) goto zero_rhs;
-            if (s.live) rc = cg_loop<float>(c, p, val32, p.R32, x32, r32, q32, dA32, dB32, &s);
+            if (s.live) rc = cg_loop<float>(c, p, x32, r32, q32, dA32, dB32, 0, 0, &s);
             if (rc != MPCG_OK) return rc;
         }
         if (s.reason == kNotSpd || s.reason == kNonFinite) S.flags |= MPCG_FLAG_FP32_BREAKDOWN;
@@ -491,17 +609,14 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
         S.relres_sp = std::sqrt(s.gamma) / bnorm;
         HIPCHK(hipEventRecord(c->tm[3], c->stream));
         // restart in FP64 from float64(x~) with a freshly computed residual
-        launch_set_phase(c->stream, p.st, 0.0, 0, 0, 1);
-        launch_restart(c->stream, p.rp, p.col, p.val, p.n, p.R64, x32, x, b, r64, dA64, dB64, eps2,
-                       abs_tol, maxit2, p.part, p.st);
+        run_restart(c->stream, p, x32, x, b, r64, dA64, dB64, 0, eps2, abs_tol, maxit2);
         HIPCHK(hipGetLastError());
     } else {
         // FP64-only CG from x0 = 0 through the restart kernel: r = b - A*0 = b
         // exactly, with the same reductions as the mixed path's restart.
         HIPCHK(hipEventRecord(c->tm[3], c->stream));
         launch_fill_f64(c->stream, x, n, 0.0);
-        launch_restart(c->stream, p.rp, p.col, p.val, p.n, p.R64, nullptr, x, b, r64, dA64, dB64, eps2,
-                       abs_tol, maxit2, p.part, p.st);
+        run_restart(c->stream, p, nullptr, x, b, r64, dA64, dB64, 0, eps2, abs_tol, maxit2);
         HIPCHK(hipGetLastError());
     }
     rc = read_state(c, p, &s);
@@ -513,13 +628,13 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
         const double thr2 = abs_tol ? eps2 : eps2 * bnorm;
         for (;;) {
             if (s.live) {
-                rc = cg_loop<double>(c, p, p.val, p.R64, x, r64, q64, dA64, dB64, &s);
+                rc = cg_loop<double>(c, p, x, r64, q64, dA64, dB64, s.iter, s.iter, &s);
                 if (rc != MPCG_OK) return rc;
             }
             if (s.reason == kMaxit) { rc = MPCG_ENOCONV; break; }
             if (s.reason == kNotSpd) { rc = MPCG_ENOTSPD; break; }
             if (s.reason == kNonFinite) { rc = MPCG_ENONFINITE; break; }
-            launch_resid(c->stream, p.rp, p.col, p.val, p.n, p.R64, x, b, p.part, p.st);
+            run_resid(c->stream, p, x, b);
             HIPCHK(hipGetLastError());
             rc = read_state(c, p, &s);
             if (rc != MPCG_OK) return rc;
@@ -529,14 +644,13 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
             if (S.restarts >= c->opt.max_restarts) { rc = MPCG_ENOCONV; break; }
             S.restarts++;
             S.flags |= MPCG_FLAG_FINAL_RESTARTED;
-            launch_restart(c->stream, p.rp, p.col, p.val, p.n, p.R64, nullptr, x, b, r64, dA64, dB64,
-                           eps2, abs_tol, maxit2, p.part, p.st);
+            run_restart(c->stream, p, nullptr, x, b, r64, dA64, dB64, s.iter, eps2, abs_tol, maxit2);
             HIPCHK(hipGetLastError());
             rc = read_state(c, p, &s);
             if (rc != MPCG_OK) return rc;
         }
         if (rc != MPCG_OK && S.relres_final_true == 0.0) {
-            launch_resid(c->stream, p.rp, p.col, p.val, p.n, p.R64, x, b, p.part, p.st);
+            run_resid(c->stream, p, x, b);
             DevState s2;
             if (read_state(c, p, &s2) == MPCG_OK) S.relres_final_true = std::sqrt(s2.resid2) / bnorm;
         }
@@ -578,11 +692,9 @@ mpcg_status mpcg_spmv(mpcg_ctx *c, const mpcg_csr *A, int32_t precision, const v
     if (rc != MPCG_OK) return rc;
     HIPCHK(hipEventRecord(c->tm[5], c->stream));
     if (precision == 64)
-        launch_spmv_plain<double>(c->stream, p.rp, p.col, p.val, p.n, p.R64,
-                                  static_cast<const double *>(x), static_cast<double *>(y));
+        run_plain<double>(c->stream, p, static_cast<const double *>(x), static_cast<double *>(y));
     else
-        launch_spmv_plain<float>(c->stream, p.rp, p.col, p.at<float>(p.L.val32), p.n, p.R32,
-                                 static_cast<const float *>(x), static_cast<float *>(y));
+        run_plain<float>(c->stream, p, static_cast<const float *>(x), static_cast<float *>(y));
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(c->tm[6], c->stream));
     HIPCHK(hipEventSynchronize(c->tm[6]));
@@ -642,28 +754,27 @@ mpcg_status mpcg_time_kernel(mpcg_ctx *c, const mpcg_csr *A, int32_t kernel, int
         launch_fill_f64(c->stream, dA64, p.n, 0.25);
         launch_fill_f64(c->stream, dB64, p.n, 0.25);
     }
-    launch_timing_state(c->stream, p.st);
+    launch_timing_state(c->stream, p.st, p.sp, 3 * kMaxGrid);
     HIPCHK(hipGetLastError());
     auto one = [&]() {
         switch (kernel) {
         case MPCG_KERNEL_CG_SPMV_F64:
-            launch_cg_spmv<double>(c->stream, p.rp, p.col, p.val, p.n, p.R64, r64, dA64, dB64, q64, p.part, p.st);
+            run_cg_spmv<double>(c->stream, p, r64, dA64, dB64, q64, 1, 0);
             break;
         case MPCG_KERNEL_CG_SPMV_F32:
-            launch_cg_spmv<float>(c->stream, p.rp, p.col, p.at<float>(p.L.val32), p.n, p.R32, r32, dA32, dB32,
-                                  q32, p.part, p.st);
+            run_cg_spmv<float>(c->stream, p, r32, dA32, dB32, q32, 1, 0);
             break;
         case MPCG_KERNEL_UPDATE_F64:
-            launch_cg_update<double>(c->stream, p.n, x64, r64, q64, dA64, dB64, p.part, p.st);
+            run_cg_update<double>(c->stream, p, x64, r64, q64, dA64, dB64, 1);
             break;
         case MPCG_KERNEL_UPDATE_F32:
-            launch_cg_update<float>(c->stream, p.n, x32, r32, q32, dA32, dB32, p.part, p.st);
+            run_cg_update<float>(c->stream, p, x32, r32, q32, dA32, dB32, 1);
             break;
         case MPCG_KERNEL_SPMV_F64:
-            launch_spmv_plain<double>(c->stream, p.rp, p.col, p.val, p.n, p.R64, r64, q64);
+            run_plain<double>(c->stream, p, r64, q64);
             break;
         default:
-            launch_spmv_plain<float>(c->stream, p.rp, p.col, p.at<float>(p.L.val32), p.n, p.R32, r32, q32);
+            run_plain<float>(c->stream, p, r32, q32);
             break;
         }
     };

@@ -56,7 +56,7 @@ void launch_bfs_seed_single(hipStream_t s, const BfsBufs &b, int32_t src)
 // multi-block kernel can take over when it outgrows LDS.
 __global__ void __launch_bounds__(kBfsSmallThreads)
 k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int32_t *dist,
-            int32_t *q0, int32_t *q1, int32_t lanes, DevState *st)
+            int32_t *q0, int32_t *q1, int32_t n, int32_t lanes, DevState *st)
 {
     __shared__ int32_t sq[2][kBfsSmallCap];
     __shared__ int32_t s_cnt, s_min, s_cur, s_level, s_par, s_go, s_curmin;
@@ -89,6 +89,7 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
         for (int w = tid; w < work; w += kBfsSmallThreads) {
             const int f = w / lanes, l = w - f * lanes;
             const int u = sq[c][f];
+            if ((unsigned)u >= (unsigned)n) continue;
             const int e = rp[u + 1];
             for (int k = rp[u] + l; k < e; k += lanes) {
                 const int v = col[k];
@@ -154,9 +155,9 @@ __device__ inline int wave_min_i(int v)
 // frontier take one atomic per wave.
 __global__ void __launch_bounds__(kBlock)
 k_bfs_level(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int32_t *dist,
-            int32_t *q0, int32_t *q1, DevState *st)
+            int32_t *q0, int32_t *q1, int32_t n, DevState *st)
 {
-    const int cur = st->bfs_cur;
+    const int cur = min(st->bfs_cur, n);
     if (st->bfs_done || cur <= kBfsSmallCap) return;
     const int level = st->bfs_level;
     const int par = st->bfs_parity;
@@ -172,8 +173,10 @@ k_bfs_level(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
         int u = -1, kb = 0, len = 0;
         if (i < cur) {
             u = qc[i];
-            kb = rp[u];
-            len = rp[u + 1] - kb;
+            if ((unsigned)u < (unsigned)n) {
+                kb = rp[u];
+                len = rp[u + 1] - kb;
+            }
         }
         const int wlen = wave_max_i(len);
         for (int j = 0; j < wlen; ++j) {
@@ -198,19 +201,20 @@ k_bfs_level(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
         }
     }
     wmin = wave_min_i(wmin);
-    if (lane == 0 && wmin != kIntMax) atomicMin(&st->bfs_next_min, wmin);
-
-    __shared__ int amlast;
+    // The last block to arrive only needs the two atomic counters, so the
+    // arrival ticket needs no memory fence: every block's counter updates are
+    // returning atomics, complete before its ticket increment is issued.
+    __shared__ int amlast, sink;
+    if (lane == 0 && wmin != kIntMax)
+        sink = __hip_atomic_fetch_min(&st->bfs_next_min, wmin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t t = __hip_atomic_fetch_add(&st->tk_bfs, 1u, __ATOMIC_ACQ_REL,
+        const uint32_t t = __hip_atomic_fetch_add(&st->tk_bfs, 1u, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT);
         amlast = (t == gridDim.x - 1);
     }
     __syncthreads();
     if (amlast && threadIdx.x == 0) {
-        __threadfence();
         const int nxt = atomic_load_i32(&st->bfs_next);
         const int nmin = atomic_load_i32(&st->bfs_next_min);
         if (nxt == 0) {
@@ -233,12 +237,12 @@ k_bfs_level(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
 void launch_bfs_round(hipStream_t s, const BfsBufs &b, int levels)
 {
     hipLaunchKernelGGL(k_bfs_small, dim3(1), dim3(kBfsSmallThreads), 0, s, b.rp, b.col, b.dist, b.q0,
-                       b.q1, b.lanes, b.st);
+                       b.q1, b.n, b.lanes, b.st);
     int grid = (b.n + kBlock - 1) / kBlock;
     if (grid > kBfsLevelBlocks) grid = kBfsLevelBlocks;
     for (int l = 0; l < levels; ++l)
         hipLaunchKernelGGL(k_bfs_level, dim3(grid), dim3(kBlock), 0, s, b.rp, b.col, b.dist, b.q0, b.q1,
-                           b.st);
+                           b.n, b.st);
 }
 
 // ------------------------------------------------ connected components --

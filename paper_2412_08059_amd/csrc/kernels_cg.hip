@@ -2,13 +2,19 @@
 // chains, fused axpy + dot updates, and a single-pass deterministic grid
 // reduction that finalises the CG scalars on the device.
 //
-// One CG iteration is two launches:
-//   k_spmv<CG>   d_i = r_i + beta_i d_{i-1} (own rows written, gathered
-//                columns recomputed on the fly), q = A d_i, delta = d_i.q,
-//                last block: alpha = gamma / delta (rounded to the working
-//                precision), breakdown test.
-//   k_update     x += alpha d_i, r -= alpha q, gamma' = r.r, last block:
-//                beta = gamma'/gamma, decay ratio for v (eq. 13), stop test.
+// One CG iteration i is two launches:
+//   k_cg_spmv    gamma_i = r_i.r_i from the update partials of iteration i-1,
+//                stop test, beta_i = gamma_i / gamma_{i-1}, decay ratio for v
+//                (eq. 13); d_i = r_i + beta_i d_{i-1} (own rows written,
+//                gathered columns recomputed on the fly), q = A d_i, partials
+//                of d_i.q.
+//   k_cg_update  delta_i from those partials, breakdown test,
+//                alpha_i = gamma_i / delta_i (rounded to the working
+//                precision), x += alpha d_i, r -= alpha q, partials of r.r.
+// Every block of a kernel finishes the previous kernel's reduction itself
+// (same partials, same order, same bits), so blocks of one grid never wait
+// for each other and no cross-block memory fence is needed; block 0 records
+// the scalars in the device state for the host.
 // These are the steps of the CG procedure in the paper's "Conjugate Gradient
 // Method" section with the direction update moved to the start of the next
 // product; the arithmetic of each element is unchanged.
@@ -43,42 +49,26 @@ __device__ inline double block_sum(double v, double *sm)
     return s;
 }
 
-__device__ inline void store_agent(double *p, double v)
+// Block sum delivered to every thread of the block.
+__device__ inline double block_sum_all(double v, double *sm)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline double load_agent(const double *p)
-{
-    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double s = block_sum(v, sm);
+    if (threadIdx.x == 0) sm[kBlock / 64] = s;
+    __syncthreads();
+    s = sm[kBlock / 64];
+    __syncthreads();
+    return s;
 }
 
-// Single-pass grid reduction of NV doubles.  Every block calls it exactly
-// once; it returns true in the last block to arrive, where out[] (thread 0)
-// holds the sums taken in block order 0..nblk-1 (same order every run).
-template <int NV>
-__device__ bool grid_reduce(const double (&v)[NV], double *part, uint32_t *ticket, int nblk,
-                            int bid, double (&out)[NV])
+// Sum of component j of cnt partials (stride doubles apart) written by the
+// previous kernel, in a fixed order; every block that calls it gets the same
+// bits.  Reductions are finished by their consumer this way, so no kernel
+// needs blocks of its own grid to communicate.
+__device__ inline double reduce_partials(const double *p, int cnt, int stride, int j, double *sm)
 {
-    __shared__ double sm[kBlock / 64];
-    __shared__ int amlast;
-    double bs[NV];
-    for (int j = 0; j < NV; ++j) bs[j] = block_sum(v[j], sm);
-    if (threadIdx.x == 0) {
-        for (int j = 0; j < NV; ++j) store_agent(part + (size_t)bid * NV + j, bs[j]);
-        __threadfence();
-        uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        amlast = (t == (uint32_t)(nblk - 1));
-    }
-    __syncthreads();
-    if (!amlast) return false;
-    __threadfence();
-    for (int j = 0; j < NV; ++j) {
-        double acc = 0.0;
-        for (int i = threadIdx.x; i < nblk; i += kBlock) acc += load_agent(part + (size_t)i * NV + j);
-        out[j] = block_sum(acc, sm);
-    }
-    if (threadIdx.x == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return true;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < cnt; i += kBlock) acc += p[(size_t)i * stride + j];
+    return block_sum_all(acc, sm);
 }
 
 // Blocks are dispatched round-robin over the XCDs; map them so that each XCD
@@ -99,10 +89,10 @@ template <> __device__ inline double fmaT<double>(double a, double b, double c) 
 __global__ void __launch_bounds__(kBlock)
 k_ingest(const void *rp_in, int rp_is_i64, const int32_t *__restrict__ col,
          const double *__restrict__ val, const double *__restrict__ b, int32_t n, int64_t nnz,
-         int32_t *__restrict__ rp32_out, float *__restrict__ val32_out, DevState *st)
+         int32_t *__restrict__ rp32_out, DevState *st)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    int err = 0, len = 0;
+    int err = 0, len = 0, band = 0;
     if (i < n) {
         int64_t lo, hi;
         if (rp_is_i64) {
@@ -124,9 +114,9 @@ k_ingest(const void *rp_in, int rp_is_i64, const int32_t *__restrict__ col,
                 if (c < 0 || c >= n) err |= kErrCol;
                 if (c <= prev) err |= kErrUnsorted;
                 prev = c;
-                const double v = val[k];
-                if (!isfinite(v)) err |= kErrNonFiniteA;
-                if (val32_out) val32_out[k] = (float)v;
+                const int d = c > (int)i ? c - (int)i : (int)i - c;
+                band = band > d ? band : d;
+                if (!isfinite(val[k])) err |= kErrNonFiniteA;
             }
         }
         if (rp32_out) {
@@ -140,20 +130,37 @@ k_ingest(const void *rp_in, int rp_is_i64, const int32_t *__restrict__ col,
         err |= __shfl_xor(err, off, 64);
         const int o = __shfl_xor(len, off, 64);
         len = len > o ? len : o;
+        const int ob = __shfl_xor(band, off, 64);
+        band = band > ob ? band : ob;
     }
     if ((threadIdx.x & 63) == 0) {
         if (err) atomicOr(&st->ing_err, err);
         atomicMax(&st->max_row, len);
+        atomicMax(&st->max_band, band);
     }
+}
+
+__global__ void k_cast32(const double *__restrict__ val, float *__restrict__ val32, int64_t nnz)
+{
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * kBlock)
+        val32[k] = (float)val[k];
 }
 
 void launch_ingest(hipStream_t s, const void *rp_in, int rp_is_i64, const int32_t *col,
                    const double *val, const double *b, int32_t n, int64_t nnz, int32_t *rp32_out,
-                   float *val32_out, DevState *st)
+                   DevState *st)
 {
     const int grid = (int)((n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_ingest, dim3(grid), dim3(kBlock), 0, s, rp_in, rp_is_i64, col, val, b, n,
-                       nnz, rp32_out, val32_out, st);
+                       nnz, rp32_out, st);
+}
+
+void launch_cast32(hipStream_t s, const double *val, float *val32, int64_t nnz)
+{
+    if (nnz <= 0) return;
+    int64_t g = (nnz + kBlock - 1) / kBlock;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_cast32, dim3((int)g), dim3(kBlock), 0, s, val, val32, nnz);
 }
 
 // ---------------------------------------------------------------- fills --
@@ -172,6 +179,14 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
 {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
         p[i] = v;
+}
+
+int vec_grid(int64_t n)
+{
+    int64_t g = (n + kVecTile - 1) / kVecTile;
+    if (g > kMaxGrid) g = kMaxGrid;
+    if (g < 1) g = 1;
+    return (int)g;
 }
 
 static int fill_grid(int64_t n)
@@ -198,84 +213,104 @@ void launch_fill_i32(hipStream_t s, int32_t *p, int64_t n, int32_t v)
 // ------------------------------------------------------------ phase init --
 
 // Sets the stop test of a phase from the freshly reduced gamma.
-__device__ inline void start_phase(DevState *st, double gamma, double eps, int abs_tol, int32_t maxit)
+__device__ inline void start_phase(DevState *st, double gamma, int32_t iter, double eps, int abs_tol,
+                                   int32_t maxit)
 {
     st->gamma = gamma;
-    st->beta = 0.0;
+    st->gam[iter & 1] = gamma;
+    st->iter = iter;
     st->thr = abs_tol ? eps : eps * sqrt(st->bnorm2);
     st->maxit = maxit;
     if (sqrt(gamma) <= st->thr) {
         st->live = 0; st->reason = kConverged;
-    } else if (st->iter >= maxit) {
+    } else if (iter >= maxit) {
         st->live = 0; st->reason = kMaxit;
     } else {
         st->live = 1; st->reason = kRunning;
     }
 }
 
-// FP32 phase from x~ = 0: r~ = float32(b), old direction = 0,
-// gamma = r~.r~ and ||b||^2, both accumulated in FP64.
+// FP32 phase from x~ = 0: r~ = float32(b), old direction = 0; partials of
+// r~.r~ and b.b (FP64) for k_fin_init32.
 __global__ void __launch_bounds__(kBlock)
 k_init32(const double *__restrict__ b, float *__restrict__ x, float *__restrict__ r,
-         float *__restrict__ dA, int32_t n, double eps, int abs_tol, int32_t maxit, int32_t k0rec,
-         double *part, DevState *st)
+         float *__restrict__ dA, int32_t n, double *part)
 {
-    double s[2] = {0.0, 0.0};
-    const int64_t base = (int64_t)blockIdx.x * kVecTile + threadIdx.x;
+    __shared__ double sm[kBlock / 64 + 1];
+    double s0 = 0.0, s1 = 0.0;
+    const int64_t nchunk = ((int64_t)n + kVecTile - 1) / kVecTile;
+    for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
 #pragma unroll
-    for (int j = 0; j < kVecPerThread; ++j) {
-        const int64_t i = base + j * kBlock;
-        if (i < n) {
-            const double bv = b[i];
-            const float rv = (float)bv;
-            r[i] = rv;
-            x[i] = 0.0f;
-            dA[i] = 0.0f;
-            s[0] = fma((double)rv, (double)rv, s[0]);
-            s[1] = fma(bv, bv, s[1]);
+        for (int j = 0; j < kVecPerThread; ++j) {
+            const int64_t i = c * kVecTile + j * kBlock + threadIdx.x;
+            if (i < n) {
+                const double bv = b[i];
+                const float rv = (float)bv;
+                r[i] = rv;
+                x[i] = 0.0f;
+                dA[i] = 0.0f;
+                s0 = fma((double)rv, (double)rv, s0);
+                s1 = fma(bv, bv, s1);
+            }
         }
     }
-    double out[2];
-    if (grid_reduce<2>(s, part, &st->tk_init, gridDim.x, blockIdx.x, out) && threadIdx.x == 0) {
-        st->bnorm2 = out[1];
-        st->iter = 0;
+    s0 = block_sum(s0, sm);
+    s1 = block_sum(s1, sm);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s0;
+        part[2 * blockIdx.x + 1] = s1;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_fin_init32(const double *part, int cnt, double eps, int abs_tol, int32_t maxit, int32_t k0rec,
+             DevState *st)
+{
+    __shared__ double sm[kBlock / 64 + 1];
+    const double g = reduce_partials(part, cnt, 2, 0, sm);
+    const double bb = reduce_partials(part, cnt, 2, 1, sm);
+    if (threadIdx.x == 0) {
+        st->bnorm2 = bb;
         st->k0rec = k0rec;
-        start_phase(st, out[0], eps, abs_tol, maxit);
+        start_phase(st, g, 0, eps, abs_tol, maxit);
     }
 }
 
 void launch_init32(hipStream_t s, const double *b, float *x, float *r, float *dA, int32_t n,
                    double eps, int abs_tol, int32_t maxit, int32_t k0rec, double *part, DevState *st)
 {
-    const int grid = (n + kVecTile - 1) / kVecTile;
-    hipLaunchKernelGGL(k_init32, dim3(grid), dim3(kBlock), 0, s, b, x, r, dA, n, eps, abs_tol, maxit,
-                       k0rec, part, st);
+    const int grid = vec_grid(n);
+    hipLaunchKernelGGL(k_init32, dim3(grid), dim3(kBlock), 0, s, b, x, r, dA, n, part);
+    hipLaunchKernelGGL(k_fin_init32, dim3(1), dim3(kBlock), 0, s, part, grid, eps, abs_tol, maxit, k0rec,
+                       st);
 }
-// Continue a phase with a new stop test (Algorithm II after the k0 prefix).
-__global__ void k_set_phase(DevState *st, double thr, int32_t maxit, int32_t k0rec, int32_t reset_iter)
+
+// Continue a phase with a new stop test (Algorithm II after the k0 prefix);
+// the next product re-derives gamma and applies the test.
+__global__ void k_set_phase(DevState *st, double thr, int32_t maxit, int32_t k0rec)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        if (reset_iter) st->iter = 0;
         st->thr = thr;
         st->maxit = maxit;
         st->k0rec = k0rec;
-        if (sqrt(st->gamma) <= thr) {
-            st->live = 0; st->reason = kConverged;
-        } else if (st->iter >= maxit) {
-            st->live = 0; st->reason = kMaxit;
-        } else {
-            st->live = 1; st->reason = kRunning;
-        }
+        st->live = 1;
+        st->reason = kRunning;
     }
 }
 
-// Measurement set-up: a live recurrence that no test can stop.
-__global__ void k_timing_state(DevState *st)
+void launch_set_phase(hipStream_t s, DevState *st, double thr, int32_t maxit, int32_t k0rec)
 {
+    hipLaunchKernelGGL(k_set_phase, dim3(1), dim3(64), 0, s, st, thr, maxit, k0rec);
+}
+
+// Measurement set-up: a live recurrence that no test can stop, finite partials.
+__global__ void k_timing_state(DevState *st, double *part, int cnt)
+{
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) part[i] = 1e-3;
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->gamma = 1.0;
-        st->alpha = 1e-3;
-        st->beta = 0.5;
+        st->gam[0] = 1.0;
+        st->gam[1] = 1.0;
         st->thr = 0.0;
         st->iter = 0;
         st->maxit = 0x7fffffff;
@@ -285,15 +320,9 @@ __global__ void k_timing_state(DevState *st)
     }
 }
 
-void launch_timing_state(hipStream_t s, DevState *st)
+void launch_timing_state(hipStream_t s, DevState *st, double *part, int cnt)
 {
-    hipLaunchKernelGGL(k_timing_state, dim3(1), dim3(64), 0, s, st);
-}
-
-void launch_set_phase(hipStream_t s, DevState *st, double thr, int32_t maxit, int32_t k0rec,
-                      int32_t reset_iter)
-{
-    hipLaunchKernelGGL(k_set_phase, dim3(1), dim3(64), 0, s, st, thr, maxit, k0rec, reset_iter);
+    hipLaunchKernelGGL(k_timing_state, dim3(1), dim3(kBlock), 0, s, st, part, cnt);
 }
 
 // ------------------------------------------------------------- CSR-stream --
@@ -306,10 +335,14 @@ struct SpmvArgs {
     const int32_t *col;
     const T *val;
     int32_t n;
-    int32_t R;        // rows per block
+    int32_t R;         // rows per tile
+    int32_t ntiles;
+    int32_t it, it0;   // CG iteration and the first iteration of the phase
     // CG
     const T *r;
     T *dA, *dB, *q;
+    const double *up;  // update partials of iteration it-1
+    int32_t nup;
     // restart / residual (T = double)
     const float *x32;
     const double *x64in;
@@ -317,239 +350,288 @@ struct SpmvArgs {
     const double *b;
     double *rout;
     double *dzA, *dzB;
-    double eps;
-    int32_t abs_tol, maxit;
     // plain
     const T *xin;
     T *yout;
-    double *part;
+    double *part;      // this kernel's partials
     DevState *st;
 };
 
-// A block owns R consecutive rows.  Phase 1 streams the block's entries
-// [rp[row0], rp[row1]) in LDS-sized chunks with coalesced col/val loads and
-// gathers the vector entry of each column; phase 2 lets thread t run the fma
-// chain of row row0 + t over its entries in CSR order, starting from 0 -- the
-// same rounding sequence as a sequential row loop.
+// A tile is R consecutive rows; a block walks a contiguous range of tiles.
+// Phase 1 streams the tile's entries [rp[row0], rp[row1]) in LDS-sized chunks
+// with coalesced col/val loads and gathers the vector entry of each column;
+// phase 2 lets thread t run the fma chain of row row0 + t over its entries in
+// CSR order, starting from 0 -- the rounding sequence of a sequential row loop.
 template <int MODE, typename T>
 __global__ void __launch_bounds__(kBlock) k_spmv(SpmvArgs<T> a)
 {
     constexpr int CHUNK = kLdsBytes / (2 * (int)sizeof(T));
+    constexpr int NV = (MODE == kModeRestart) ? 2 : 1;
     __shared__ T s_val[CHUNK];
     __shared__ T s_x[CHUNK];
+    __shared__ double sm[kBlock / 64 + 1];
     DevState *st = a.st;
-    if (MODE == kModeCg) {
-        if (!st->live) return;
-    }
-    const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x;
-    const int row0 = bid * a.R;
-    const int row1 = min(row0 + a.R, a.n);
 
     T beta = T(0);
     const T *dold = nullptr;
     T *dnew = nullptr;
     if (MODE == kModeCg) {
-        const int it = st->iter;
-        beta = (T)st->beta;
+        // block 0 may clear st->live during this kernel: take one block-wide reading
+        __shared__ int s_live;
+        if (tid == 0) s_live = st->live;
+        __syncthreads();
+        if (!s_live) return;
+        const int it = a.it;
+        if (it != a.it0) {
+            const double g = reduce_partials(a.up, a.nup, 1, 0, sm);
+            const double gp = st->gam[(it - 1) & 1];
+            const bool conv = sqrt(g) <= st->thr;
+            const bool cap = !conv && it >= st->maxit;
+            if (blockIdx.x == 0 && tid == 0) {
+                st->gam[it & 1] = g;
+                const int k = it - 1;
+                if (k < st->k0rec && k < kK0Max) st->ratios[k] = sqrt(g) / sqrt(gp);
+                if (conv || cap) {
+                    st->gamma = g;
+                    st->iter = it;
+                    st->reason = conv ? kConverged : kMaxit;
+                    st->live = 0;
+                }
+            }
+            if (conv || cap) return;
+            beta = (T)(g / gp);
+        }
         dold = (it & 1) ? a.dB : a.dA;
         dnew = (it & 1) ? a.dA : a.dB;
     }
 
-    const int my_row = row0 + tid;
-    const bool has = (tid < a.R) && (my_row < row1);
-    int my_lo = 0, my_hi = 0;
-    if (has) {
-        my_lo = a.rp[my_row];
-        my_hi = a.rp[my_row + 1];
-    }
-    const int lo = a.rp[row0];
-    const int hi = a.rp[row1];
-
-    T acc = T(0);
-    for (int c0 = lo; c0 < hi; c0 += CHUNK) {
-        const int cn = min(CHUNK, hi - c0);
-        for (int j = tid; j < cn; j += kBlock) {
-            const int k = c0 + j;
-            const int c = a.col[k];
-            s_val[j] = a.val[k];
-            T g;
-            if (MODE == kModeCg) {
-                g = fmaT<T>(beta, dold[c], a.r[c]);
-            } else if (MODE == kModeRestart || MODE == kModeResid) {
-                g = a.x32 ? (T)a.x32[c] : (T)a.x64in[c];
-            } else {
-                g = a.xin[c];
-            }
-            s_x[j] = g;
-        }
-        __syncthreads();
-        if (has) {
-            const int kb = max(my_lo, c0), ke = min(my_hi, c0 + cn);
-            for (int k = kb; k < ke; ++k) acc = fmaT<T>(s_val[k - c0], s_x[k - c0], acc);
-        }
-        __syncthreads();
-    }
-
-    if (MODE == kModePlain) {
-        if (has) a.yout[my_row] = acc;
-        return;
-    }
-
-    // restart also reduces ||b||^2, so that FP64-only runs (x = 0) and mixed
-    // runs share one reduction layout for gamma and for the stop threshold
-    constexpr int NV = (MODE == kModeRestart) ? 2 : 1;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int t0 = (int)((int64_t)lb * a.ntiles / gridDim.x);
+    const int t1 = (int)((int64_t)(lb + 1) * a.ntiles / gridDim.x);
     double s[NV];
     for (int j = 0; j < NV; ++j) s[j] = 0.0;
-    if (has) {
-        if (MODE == kModeCg) {
-            const T dn = fmaT<T>(beta, dold[my_row], a.r[my_row]);
-            dnew[my_row] = dn;
-            a.q[my_row] = acc;
-            s[0] = fma((double)dn, (double)acc, 0.0);
-        } else {
-            const double bv = a.b[my_row];
-            const double res = bv - (double)acc;
-            if (MODE == kModeRestart) {
-                if (a.x32) a.x64out[my_row] = (double)a.x32[my_row];
-                a.rout[my_row] = res;
-                const int it = st->iter;
-                double *dz = (it & 1) ? a.dzB : a.dzA;
-                dz[my_row] = 0.0;
-                s[NV - 1] = fma(bv, bv, 0.0);
-            }
-            s[0] = fma(res, res, 0.0);
+
+    for (int t = t0; t < t1; ++t) {
+        const int row0 = t * a.R;
+        const int row1 = min(row0 + a.R, a.n);
+        const int my_row = row0 + tid;
+        const bool has = (tid < a.R) && (my_row < row1);
+        int my_lo = 0, my_hi = 0;
+        if (has) {
+            my_lo = a.rp[my_row];
+            my_hi = a.rp[my_row + 1];
         }
-    }
-    double out[NV];
-    uint32_t *tk = (MODE == kModeCg) ? &st->tk_spmv : &st->tk_misc;
-    if (grid_reduce<NV>(s, a.part, tk, gridDim.x, bid, out) && threadIdx.x == 0) {
-        const double sum = out[0];
-        if (MODE == kModeCg) {
-            st->delta = sum;
-            if (!isfinite(sum)) {
-                st->live = 0; st->reason = kNonFinite;
-            } else if (!(sum > 0.0)) {
-                st->live = 0; st->reason = kNotSpd;
+        const int lo = a.rp[row0];
+        const int hi = a.rp[row1];
+        T acc = T(0);
+        for (int c0 = lo; c0 < hi; c0 += CHUNK) {
+            const int cn = min(CHUNK, hi - c0);
+            for (int j = tid; j < cn; j += kBlock) {
+                const int k = c0 + j;
+                const int c = a.col[k];
+                s_val[j] = a.val[k];
+                T g;
+                if (MODE == kModeCg) {
+                    g = fmaT<T>(beta, dold[c], a.r[c]);
+                } else if (MODE == kModeRestart || MODE == kModeResid) {
+                    g = a.x32 ? (T)a.x32[c] : (T)a.x64in[c];
+                } else {
+                    g = a.xin[c];
+                }
+                s_x[j] = g;
+            }
+            __syncthreads();
+            if (has) {
+                const int kb = max(my_lo, c0), ke = min(my_hi, c0 + cn);
+                for (int k = kb; k < ke; ++k) acc = fmaT<T>(s_val[k - c0], s_x[k - c0], acc);
+            }
+            __syncthreads();
+        }
+        if (has) {
+            if (MODE == kModePlain) {
+                a.yout[my_row] = acc;
+            } else if (MODE == kModeCg) {
+                const T dn = fmaT<T>(beta, dold[my_row], a.r[my_row]);
+                dnew[my_row] = dn;
+                a.q[my_row] = acc;
+                s[0] = fma((double)dn, (double)acc, s[0]);
             } else {
-                st->alpha = (double)(T)(st->gamma / sum);
+                const double bv = a.b[my_row];
+                const double res = bv - (double)acc;
+                if (MODE == kModeRestart) {
+                    if (a.x32) a.x64out[my_row] = (double)a.x32[my_row];
+                    a.rout[my_row] = res;
+                    double *dz = (a.it0 & 1) ? a.dzB : a.dzA;
+                    dz[my_row] = 0.0;
+                    s[NV - 1] = fma(bv, bv, s[NV - 1]);
+                }
+                s[0] = fma(res, res, s[0]);
             }
-        } else if (MODE == kModeRestart) {
-            st->bnorm2 = out[NV - 1];
-            start_phase(st, sum, a.eps, a.abs_tol, a.maxit);
-        } else {
-            st->resid2 = sum;
         }
+    }
+    if (MODE == kModePlain) return;
+    for (int j = 0; j < NV; ++j) {
+        const double bs = block_sum(s[j], sm);
+        if (tid == 0) a.part[(size_t)lb * NV + j] = bs;
     }
 }
 
-template <typename T>
-static int spmv_grid(int32_t n, int R)
+// Finish the restart: ||b||^2, gamma of the fresh residual, stop test.
+__global__ void __launch_bounds__(kBlock)
+k_fin_restart(const double *part, int cnt, int32_t it0, double eps, int abs_tol, int32_t maxit,
+              DevState *st)
 {
-    return (n + R - 1) / R;
+    __shared__ double sm[kBlock / 64 + 1];
+    const double g = reduce_partials(part, cnt, 2, 0, sm);
+    const double bb = reduce_partials(part, cnt, 2, 1, sm);
+    if (threadIdx.x == 0) {
+        st->bnorm2 = bb;
+        st->k0rec = 0;
+        start_phase(st, g, it0, eps, abs_tol, maxit);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_fin_resid(const double *part, int cnt, DevState *st)
+{
+    __shared__ double sm[kBlock / 64 + 1];
+    const double r2 = reduce_partials(part, cnt, 1, 0, sm);
+    if (threadIdx.x == 0) st->resid2 = r2;
 }
 
 template <typename T>
-void launch_cg_spmv(hipStream_t s, const int32_t *rp, const int32_t *col, const T *val, int32_t n,
-                    int R, const T *r, T *dA, T *dB, T *q, double *part, DevState *st)
+static SpmvArgs<T> spmv_args(const SpmvShape &sh, const int32_t *rp, const int32_t *col, const T *val)
 {
     SpmvArgs<T> a{};
-    a.rp = rp; a.col = col; a.val = val; a.n = n; a.R = R;
-    a.r = r; a.dA = dA; a.dB = dB; a.q = q; a.part = part; a.st = st;
-    hipLaunchKernelGGL((k_spmv<kModeCg, T>), dim3(spmv_grid<T>(n, R)), dim3(kBlock), 0, s, a);
+    a.rp = rp; a.col = col; a.val = val; a.n = sh.n; a.R = sh.R; a.ntiles = sh.ntiles;
+    return a;
 }
 
-void launch_restart(hipStream_t s, const int32_t *rp, const int32_t *col, const double *val,
-                    int32_t n, int R, const float *x32, double *x64, const double *b, double *r,
-                    double *dA, double *dB, double eps, int abs_tol, int32_t maxit, double *part,
-                    DevState *st)
+template <typename T>
+void launch_cg_spmv(hipStream_t s, const SpmvShape &sh, const int32_t *rp, const int32_t *col,
+                    const T *val, const T *r, T *dA, T *dB, T *q, const double *up, int nup,
+                    double *part, int it, int it0, DevState *st)
 {
-    SpmvArgs<double> a{};
-    a.rp = rp; a.col = col; a.val = val; a.n = n; a.R = R;
+    SpmvArgs<T> a = spmv_args<T>(sh, rp, col, val);
+    a.it = it; a.it0 = it0;
+    a.r = r; a.dA = dA; a.dB = dB; a.q = q; a.up = up; a.nup = nup; a.part = part; a.st = st;
+    hipLaunchKernelGGL((k_spmv<kModeCg, T>), dim3(sh.grid), dim3(kBlock), 0, s, a);
+}
+
+void launch_restart(hipStream_t s, const SpmvShape &sh, const int32_t *rp, const int32_t *col,
+                    const double *val, const float *x32, double *x64, const double *b, double *r,
+                    double *dA, double *dB, int it0, double eps, int abs_tol, int32_t maxit,
+                    double *part, DevState *st)
+{
+    SpmvArgs<double> a = spmv_args<double>(sh, rp, col, val);
+    a.it0 = it0;
     a.x32 = x32; a.x64in = x64; a.x64out = x64; a.b = b; a.rout = r; a.dzA = dA; a.dzB = dB;
-    a.eps = eps; a.abs_tol = abs_tol; a.maxit = maxit; a.part = part; a.st = st;
-    hipLaunchKernelGGL((k_spmv<kModeRestart, double>), dim3(spmv_grid<double>(n, R)), dim3(kBlock), 0,
-                       s, a);
+    a.part = part; a.st = st;
+    hipLaunchKernelGGL((k_spmv<kModeRestart, double>), dim3(sh.grid), dim3(kBlock), 0, s, a);
+    launch_fin_restart(s, part, sh.grid, it0, eps, abs_tol, maxit, st);
 }
 
-void launch_resid(hipStream_t s, const int32_t *rp, const int32_t *col, const double *val,
-                  int32_t n, int R, const double *x64, const double *b, double *part, DevState *st)
+void launch_fin_restart(hipStream_t s, const double *part, int cnt, int it0, double eps, int abs_tol,
+                        int32_t maxit, DevState *st)
 {
-    SpmvArgs<double> a{};
-    a.rp = rp; a.col = col; a.val = val; a.n = n; a.R = R;
+    hipLaunchKernelGGL(k_fin_restart, dim3(1), dim3(kBlock), 0, s, part, cnt, it0, eps, abs_tol, maxit, st);
+}
+
+void launch_fin_resid(hipStream_t s, const double *part, int cnt, DevState *st)
+{
+    hipLaunchKernelGGL(k_fin_resid, dim3(1), dim3(kBlock), 0, s, part, cnt, st);
+}
+
+void launch_resid(hipStream_t s, const SpmvShape &sh, const int32_t *rp, const int32_t *col,
+                  const double *val, const double *x64, const double *b, double *part, DevState *st)
+{
+    SpmvArgs<double> a = spmv_args<double>(sh, rp, col, val);
     a.x32 = nullptr; a.x64in = x64; a.b = b; a.part = part; a.st = st;
-    hipLaunchKernelGGL((k_spmv<kModeResid, double>), dim3(spmv_grid<double>(n, R)), dim3(kBlock), 0,
-                       s, a);
+    hipLaunchKernelGGL((k_spmv<kModeResid, double>), dim3(sh.grid), dim3(kBlock), 0, s, a);
+    launch_fin_resid(s, part, sh.grid, st);
 }
 
 template <typename T>
-void launch_spmv_plain(hipStream_t s, const int32_t *rp, const int32_t *col, const T *val,
-                       int32_t n, int R, const T *x, T *y)
+void launch_spmv_plain(hipStream_t s, const SpmvShape &sh, const int32_t *rp, const int32_t *col,
+                       const T *val, const T *x, T *y)
 {
-    SpmvArgs<T> a{};
-    a.rp = rp; a.col = col; a.val = val; a.n = n; a.R = R; a.xin = x; a.yout = y;
-    hipLaunchKernelGGL((k_spmv<kModePlain, T>), dim3(spmv_grid<T>(n, R)), dim3(kBlock), 0, s, a);
+    SpmvArgs<T> a = spmv_args<T>(sh, rp, col, val);
+    a.xin = x; a.yout = y;
+    hipLaunchKernelGGL((k_spmv<kModePlain, T>), dim3(sh.grid), dim3(kBlock), 0, s, a);
 }
 
 // ------------------------------------------------------------- update --
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_update(int32_t n, T *__restrict__ x, T *__restrict__ r, const T *__restrict__ q,
-         const T *__restrict__ dA, const T *__restrict__ dB, double *part, DevState *st)
+k_cg_update(int32_t n, T *__restrict__ x, T *__restrict__ r, const T *__restrict__ q,
+            const T *__restrict__ dA, const T *__restrict__ dB, const double *sp, int nsp,
+            double *up, int it, DevState *st)
 {
-    if (!st->live) return;
-    const int it = st->iter;
-    const T alpha = (T)st->alpha;
+    __shared__ double sm[kBlock / 64 + 1];
+    __shared__ int s_live;
+    if (threadIdx.x == 0) s_live = st->live;
+    __syncthreads();
+    if (!s_live) return;
+    const double delta = reduce_partials(sp, nsp, 1, 0, sm);
+    const double g = st->gam[it & 1];
+    if (!isfinite(delta) || !(delta > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->delta = delta;
+            st->gamma = g;
+            st->iter = it;
+            st->reason = isfinite(delta) ? kNotSpd : kNonFinite;
+            st->live = 0;
+        }
+        return;
+    }
+    const T alpha = (T)(g / delta);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->delta = delta;
+        st->alpha = (double)alpha;
+    }
     const T *dn = (it & 1) ? dA : dB;   // written by the product of iteration it
-    double s[1] = {0.0};
-    const int64_t base = (int64_t)blockIdx.x * kVecTile + threadIdx.x;
+    double s = 0.0;
+    const int64_t nchunk = ((int64_t)n + kVecTile - 1) / kVecTile;
+    for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
 #pragma unroll
-    for (int j = 0; j < kVecPerThread; ++j) {
-        const int64_t i = base + j * kBlock;
-        if (i < n) {
-            x[i] = fmaT<T>(alpha, dn[i], x[i]);
-            const T rv = fmaT<T>(-alpha, q[i], r[i]);
-            r[i] = rv;
-            s[0] = fma((double)rv, (double)rv, s[0]);
+        for (int j = 0; j < kVecPerThread; ++j) {
+            const int64_t i = c * kVecTile + j * kBlock + threadIdx.x;
+            if (i < n) {
+                x[i] = fmaT<T>(alpha, dn[i], x[i]);
+                const T rv = fmaT<T>(-alpha, q[i], r[i]);
+                r[i] = rv;
+                s = fma((double)rv, (double)rv, s);
+            }
         }
     }
-    double out[1];
-    if (grid_reduce<1>(s, part, &st->tk_upd, gridDim.x, blockIdx.x, out) && threadIdx.x == 0) {
-        const double gnew = out[0], gold = st->gamma;
-        if (it < st->k0rec && it < kK0Max) st->ratios[it] = sqrt(gnew) / sqrt(gold);
-        st->beta = (double)(T)(gnew / gold);
-        st->gamma = gnew;
-        st->iter = it + 1;
-        if (sqrt(gnew) <= st->thr) {
-            st->live = 0; st->reason = kConverged;
-        } else if (it + 1 >= st->maxit) {
-            st->live = 0; st->reason = kMaxit;
-        }
-    }
+    s = block_sum(s, sm);
+    if (threadIdx.x == 0) up[blockIdx.x] = s;
 }
 
 template <typename T>
 void launch_cg_update(hipStream_t s, int32_t n, T *x, T *r, const T *q, const T *dA, const T *dB,
-                      double *part, DevState *st)
+                      const double *sp, int nsp, double *up, int it, DevState *st)
 {
-    const int grid = (n + kVecTile - 1) / kVecTile;
-    hipLaunchKernelGGL(k_update<T>, dim3(grid), dim3(kBlock), 0, s, n, x, r, q, dA, dB, part, st);
+    hipLaunchKernelGGL(k_cg_update<T>, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, x, r, q, dA, dB, sp,
+                       nsp, up, it, st);
 }
 
-template void launch_cg_spmv<float>(hipStream_t, const int32_t *, const int32_t *, const float *,
-                                    int32_t, int, const float *, float *, float *, float *, double *,
-                                    DevState *);
-template void launch_cg_spmv<double>(hipStream_t, const int32_t *, const int32_t *, const double *,
-                                     int32_t, int, const double *, double *, double *, double *,
-                                     double *, DevState *);
+template void launch_cg_spmv<float>(hipStream_t, const SpmvShape &, const int32_t *, const int32_t *,
+                                    const float *, const float *, float *, float *, float *,
+                                    const double *, int, double *, int, int, DevState *);
+template void launch_cg_spmv<double>(hipStream_t, const SpmvShape &, const int32_t *, const int32_t *,
+                                     const double *, const double *, double *, double *, double *,
+                                     const double *, int, double *, int, int, DevState *);
 template void launch_cg_update<float>(hipStream_t, int32_t, float *, float *, const float *,
-                                      const float *, const float *, double *, DevState *);
+                                      const float *, const float *, const double *, int, double *, int,
+                                      DevState *);
 template void launch_cg_update<double>(hipStream_t, int32_t, double *, double *, const double *,
-                                       const double *, const double *, double *, DevState *);
-template void launch_spmv_plain<float>(hipStream_t, const int32_t *, const int32_t *, const float *,
-                                       int32_t, int, const float *, float *);
-template void launch_spmv_plain<double>(hipStream_t, const int32_t *, const int32_t *,
-                                        const double *, int32_t, int, const double *, double *);
+                                       const double *, const double *, const double *, int, double *,
+                                       int, DevState *);
+template void launch_spmv_plain<float>(hipStream_t, const SpmvShape &, const int32_t *, const int32_t *,
+                                       const float *, const float *, float *);
+template void launch_spmv_plain<double>(hipStream_t, const SpmvShape &, const int32_t *,
+                                        const int32_t *, const double *, const double *, double *);
 
 }  // namespace mpcg

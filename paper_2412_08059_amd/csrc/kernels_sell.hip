@@ -1,0 +1,354 @@
+// SELL-64 storage and kernels for the CG products (gfx950, wave64).
+//
+// At ingest the CSR matrix is copied into slices of 64 consecutive rows, one
+// row per lane of a wavefront; the k-th entries of the 64 rows are stored
+// next to each other (column-major inside the slice), so every load of a
+// value or column index is one coalesced 64-wide access.  Each lane still
+// walks its own row in CSR order with one fma chain starting from 0 -- the
+// same rounding sequence as the sequential row loop -- and the padding past a
+// row's length is never touched (per-lane predicate, no dummy fma).
+//
+// When the matrix bandwidth max|i - j| is below 32768 the column is stored as
+// a 16-bit offset from the row (2 bytes instead of 4 per entry).  A CG
+// product then moves 10 bytes per entry in FP64 and 6 bytes in FP32.
+//
+// A wave needs no LDS and no block barrier, so many waves per SIMD hide the
+// gather latency.  Blocks walk contiguous, XCD-local ranges of slices.
+
+#include "mpcg_internal.hpp"
+
+#include <cmath>
+
+namespace mpcg {
+
+template <typename T> __device__ inline T fma_t(T a, T b, T c);
+template <> __device__ inline float fma_t<float>(float a, float b, float c) { return fmaf(a, b, c); }
+template <> __device__ inline double fma_t<double>(double a, double b, double c) { return fma(a, b, c); }
+
+__device__ inline double sell_wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline double sell_block_sum(double v, double *sm)
+{
+    v = sell_wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sm[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kBlock / 64; ++i) s += sm[i];
+    __syncthreads();
+    return s;
+}
+
+__device__ inline double sell_reduce_partials(const double *p, int cnt, double *sm)
+{
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < cnt; i += kBlock) acc += p[i];
+    double s = sell_block_sum(acc, sm);
+    if (threadIdx.x == 0) sm[kBlock / 64] = s;
+    __syncthreads();
+    s = sm[kBlock / 64];
+    __syncthreads();
+    return s;
+}
+
+__device__ inline int sell_xcd_remap(int b, int nb)
+{
+    const int q = nb / kNumXcd, rem = nb % kNumXcd;
+    const int x = b % kNumXcd, i = b / kNumXcd;
+    return x * q + (x < rem ? x : rem) + i;
+}
+
+// ---------------------------------------------------------------- build --
+
+// slice width (longest row of the slice) times 64, per slice
+__global__ void k_sell_width(const int32_t *__restrict__ rp, int32_t n, int32_t nslices, int64_t *wid)
+{
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= nslices) return;
+    const int r0 = s * 64, r1 = min(r0 + 64, n);
+    int w = 0;
+    int prev = rp[r0];
+    for (int r = r0; r < r1; ++r) {
+        const int nx = rp[r + 1];
+        w = max(w, nx - prev);
+        prev = nx;
+    }
+    wid[s] = (int64_t)w * 64;
+}
+
+// exclusive scan of the padded slice sizes (one block), off[nslices] = total
+__global__ void __launch_bounds__(1024) k_sell_scan(const int64_t *wid, int32_t nslices, int64_t *off)
+{
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int per = (nslices + 1023) / 1024;
+    const int a = min(t * per, nslices), b = min(a + per, nslices);
+    int64_t sum = 0;
+    for (int i = a; i < b; ++i) sum += wid[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int64_t v = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = part[t] - sum;
+    for (int i = a; i < b; ++i) {
+        off[i] = run;
+        run += wid[i];
+    }
+    if (t == 1023) off[nslices] = part[1023];
+}
+
+template <typename IDX>
+__global__ void __launch_bounds__(kBlock)
+k_sell_fill(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+            const double *__restrict__ val, int32_t n, const int64_t *__restrict__ off,
+            IDX *__restrict__ scol, double *__restrict__ sv64, float *__restrict__ sv32)
+{
+    const int row = blockIdx.x * kBlock + threadIdx.x;
+    if (row >= n) return;
+    const int s = row >> 6, lane = row & 63;
+    const int64_t base = off[s] + lane;
+    const int lo = rp[row], hi = rp[row + 1];
+    for (int k = lo; k < hi; ++k) {
+        const int64_t dst = base + (int64_t)(k - lo) * 64;
+        const int c = col[k];
+        if (sizeof(IDX) == 2) scol[dst] = (IDX)(c - row);
+        else scol[dst] = (IDX)c;
+        const double v = val[k];
+        if (sv64) sv64[dst] = v;
+        if (sv32) sv32[dst] = (float)v;
+    }
+}
+
+void launch_sell_plan(hipStream_t s, const int32_t *rp, int32_t n, int64_t *wid, int64_t *off)
+{
+    const int nslices = (n + 63) / 64;
+    hipLaunchKernelGGL(k_sell_width, dim3((nslices + kBlock - 1) / kBlock), dim3(kBlock), 0, s, rp, n,
+                       nslices, wid);
+    hipLaunchKernelGGL(k_sell_scan, dim3(1), dim3(1024), 0, s, wid, nslices, off);
+}
+
+void launch_sell_fill(hipStream_t s, const int32_t *rp, const int32_t *col, const double *val,
+                      int32_t n, const int64_t *off, void *scol, int idx16, double *sv64, float *sv32)
+{
+    const int grid = (n + kBlock - 1) / kBlock;
+    if (idx16)
+        hipLaunchKernelGGL(k_sell_fill<int16_t>, dim3(grid), dim3(kBlock), 0, s, rp, col, val, n, off,
+                           static_cast<int16_t *>(scol), sv64, sv32);
+    else
+        hipLaunchKernelGGL(k_sell_fill<int32_t>, dim3(grid), dim3(kBlock), 0, s, rp, col, val, n, off,
+                           static_cast<int32_t *>(scol), sv64, sv32);
+}
+
+// -------------------------------------------------------------- kernels --
+
+enum SellMode { kSellCg = 0, kSellRestart = 1, kSellResid = 2, kSellPlain = 3 };
+
+template <typename T>
+struct SellArgs {
+    const int32_t *rp;
+    const void *scol;
+    const T *sval;
+    const int64_t *off;
+    int32_t n, nslices;
+    int32_t it, it0;
+    const T *r;
+    T *dA, *dB, *q;
+    const double *up;
+    int32_t nup;
+    const float *x32;
+    const double *x64in;
+    double *x64out;
+    const double *b;
+    double *rout;
+    double *dzA, *dzB;
+    const T *xin;
+    T *yout;
+    double *part;
+    DevState *st;
+};
+
+constexpr int kSellBatch = 4;   // entries whose loads are issued together
+
+template <int MODE, typename T, typename IDX>
+__global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
+{
+    constexpr int NV = (MODE == kSellRestart) ? 2 : 1;
+    __shared__ double sm[kBlock / 64 + 1];
+    DevState *st = a.st;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+
+    T beta = T(0);
+    const T *dold = nullptr;
+    T *dnew = nullptr;
+    if (MODE == kSellCg) {
+        __shared__ int s_live;
+        if (tid == 0) s_live = st->live;
+        __syncthreads();
+        if (!s_live) return;
+        const int it = a.it;
+        if (it != a.it0) {
+            const double g = sell_reduce_partials(a.up, a.nup, sm);
+            const double gp = st->gam[(it - 1) & 1];
+            const bool conv = sqrt(g) <= st->thr;
+            const bool cap = !conv && it >= st->maxit;
+            if (blockIdx.x == 0 && tid == 0) {
+                st->gam[it & 1] = g;
+                const int k = it - 1;
+                if (k < st->k0rec && k < kK0Max) st->ratios[k] = sqrt(g) / sqrt(gp);
+                if (conv || cap) {
+                    st->gamma = g;
+                    st->iter = it;
+                    st->reason = conv ? kConverged : kMaxit;
+                    st->live = 0;
+                }
+            }
+            if (conv || cap) return;
+            beta = (T)(g / gp);
+        }
+        dold = (it & 1) ? a.dB : a.dA;
+        dnew = (it & 1) ? a.dA : a.dB;
+    }
+
+    const IDX *scol = static_cast<const IDX *>(a.scol);
+    const int lb = sell_xcd_remap(blockIdx.x, gridDim.x);
+    const int s0 = (int)((int64_t)lb * a.nslices / gridDim.x);
+    const int s1 = (int)((int64_t)(lb + 1) * a.nslices / gridDim.x);
+    double s[NV];
+    for (int j = 0; j < NV; ++j) s[j] = 0.0;
+
+    for (int sl = s0 + wv; sl < s1; sl += kBlock / 64) {
+        const int row = sl * 64 + lane;
+        const bool has = row < a.n;
+        const int len = has ? a.rp[row + 1] - a.rp[row] : 0;
+        const int64_t base = a.off[sl];
+        const int W = (int)((a.off[sl + 1] - base) >> 6);
+        const IDX *cp = scol + base + lane;
+        const T *vp = a.sval + base + lane;
+        T acc = T(0);
+        for (int k0 = 0; k0 < W; k0 += kSellBatch) {
+            int c[kSellBatch];
+            T v[kSellBatch], g[kSellBatch];
+#pragma unroll
+            for (int j = 0; j < kSellBatch; ++j) {
+                if (k0 + j < len) {
+                    const IDX ci = cp[(int64_t)(k0 + j) * 64];
+                    c[j] = (sizeof(IDX) == 2) ? row + (int)ci : (int)ci;
+                    v[j] = vp[(int64_t)(k0 + j) * 64];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kSellBatch; ++j) {
+                if (k0 + j < len) {
+                    if (MODE == kSellCg) g[j] = fma_t<T>(beta, dold[c[j]], a.r[c[j]]);
+                    else if (MODE == kSellPlain) g[j] = a.xin[c[j]];
+                    else g[j] = a.x32 ? (T)a.x32[c[j]] : (T)a.x64in[c[j]];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kSellBatch; ++j)
+                if (k0 + j < len) acc = fma_t<T>(v[j], g[j], acc);
+        }
+        if (has) {
+            if (MODE == kSellPlain) {
+                a.yout[row] = acc;
+            } else if (MODE == kSellCg) {
+                const T dn = fma_t<T>(beta, dold[row], a.r[row]);
+                dnew[row] = dn;
+                a.q[row] = acc;
+                s[0] = fma((double)dn, (double)acc, s[0]);
+            } else {
+                const double bv = a.b[row];
+                const double res = bv - (double)acc;
+                if (MODE == kSellRestart) {
+                    if (a.x32) a.x64out[row] = (double)a.x32[row];
+                    a.rout[row] = res;
+                    double *dz = (a.it0 & 1) ? a.dzB : a.dzA;
+                    dz[row] = 0.0;
+                    s[NV - 1] = fma(bv, bv, s[NV - 1]);
+                }
+                s[0] = fma(res, res, s[0]);
+            }
+        }
+    }
+    if (MODE == kSellPlain) return;
+    for (int j = 0; j < NV; ++j) {
+        const double bs = sell_block_sum(s[j], sm);
+        if (tid == 0) a.part[(size_t)lb * NV + j] = bs;
+    }
+}
+
+template <int MODE, typename T>
+static void sell_launch(hipStream_t s, const SellMat &m, const SellArgs<T> &a)
+{
+    if (m.idx16)
+        hipLaunchKernelGGL((k_sell<MODE, T, int16_t>), dim3(m.grid), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_sell<MODE, T, int32_t>), dim3(m.grid), dim3(kBlock), 0, s, a);
+}
+
+template <typename T>
+static SellArgs<T> sell_args(const SellMat &m, const T *sval)
+{
+    SellArgs<T> a{};
+    a.rp = m.rp; a.scol = m.scol; a.sval = sval; a.off = m.off; a.n = m.n; a.nslices = m.nslices;
+    return a;
+}
+
+template <typename T> static const T *sell_vals(const SellMat &m);
+template <> const float *sell_vals<float>(const SellMat &m) { return m.v32; }
+template <> const double *sell_vals<double>(const SellMat &m) { return m.v64; }
+
+template <typename T>
+void launch_sell_cg_spmv(hipStream_t s, const SellMat &m, const T *r, T *dA, T *dB, T *q,
+                         const double *up, int nup, double *part, int it, int it0, DevState *st)
+{
+    SellArgs<T> a = sell_args<T>(m, sell_vals<T>(m));
+    a.it = it; a.it0 = it0; a.r = r; a.dA = dA; a.dB = dB; a.q = q; a.up = up; a.nup = nup;
+    a.part = part; a.st = st;
+    sell_launch<kSellCg, T>(s, m, a);
+}
+
+void launch_sell_restart(hipStream_t s, const SellMat &m, const float *x32, double *x64,
+                         const double *b, double *r, double *dA, double *dB, int it0, double *part,
+                         DevState *st)
+{
+    SellArgs<double> a = sell_args<double>(m, m.v64);
+    a.it0 = it0; a.x32 = x32; a.x64in = x64; a.x64out = x64; a.b = b; a.rout = r; a.dzA = dA; a.dzB = dB;
+    a.part = part; a.st = st;
+    sell_launch<kSellRestart, double>(s, m, a);
+}
+
+void launch_sell_resid(hipStream_t s, const SellMat &m, const double *x64, const double *b,
+                       double *part, DevState *st)
+{
+    SellArgs<double> a = sell_args<double>(m, m.v64);
+    a.x64in = x64; a.b = b; a.part = part; a.st = st;
+    sell_launch<kSellResid, double>(s, m, a);
+}
+
+template <typename T>
+void launch_sell_plain(hipStream_t s, const SellMat &m, const T *x, T *y)
+{
+    SellArgs<T> a = sell_args<T>(m, sell_vals<T>(m));
+    a.xin = x; a.yout = y;
+    sell_launch<kSellPlain, T>(s, m, a);
+}
+
+template void launch_sell_cg_spmv<float>(hipStream_t, const SellMat &, const float *, float *, float *,
+                                         float *, const double *, int, double *, int, int, DevState *);
+template void launch_sell_cg_spmv<double>(hipStream_t, const SellMat &, const double *, double *,
+                                          double *, double *, const double *, int, double *, int, int,
+                                          DevState *);
+template void launch_sell_plain<float>(hipStream_t, const SellMat &, const float *, float *);
+template void launch_sell_plain<double>(hipStream_t, const SellMat &, const double *, double *);
+
+}  // namespace mpcg

@@ -20,6 +20,8 @@ constexpr int kBfsSmallCap = 4096;    // frontier size handled by the one-workgr
 constexpr int kBfsSmallThreads = 1024;
 constexpr int kBfsLevelBlocks = 1024; // grid of the multi-block BFS level kernel
 constexpr int kNumXcd = 8;            // MI355X: blocks are dispatched round-robin over 8 XCDs
+constexpr int kMaxGrid = 2048;        // largest grid of a kernel that writes reduction partials
+constexpr int kSpmvBlocksPerCu = 5;   // 32 KB of LDS per block, 160 KB per CU
 
 enum StopReason : int32_t { kRunning = 0, kConverged = 1, kMaxit = 2, kNotSpd = 3, kNonFinite = 4 };
 
@@ -38,8 +40,8 @@ struct alignas(256) DevState {
     double thr;       // stop when sqrt(gamma) <= thr
     double bnorm2;    // ||b||^2 (FP64)
     double resid2;    // ||b - A x||^2 from the residual kernel
-    double spare0;
-    int32_t iter;     // iterations done in this precision
+    double gam[2];    // gamma_i by parity of i (the product of iteration i writes slot i & 1)
+    int32_t iter;     // iteration at which the phase started or stopped
     int32_t maxit;
     int32_t live;     // 1 while iterations must continue
     int32_t reason;   // StopReason
@@ -47,7 +49,8 @@ struct alignas(256) DevState {
     int32_t guard;    // device-side guard tripped (bounded loop exhausted)
     int32_t ing_err;  // IngestError bits
     int32_t max_row;  // longest row seen by the ingest kernel
-    uint32_t tk_spmv, tk_upd, tk_init, tk_misc;  // tickets of the single-pass reductions
+    int32_t max_band; // largest |i - j| over the stored entries
+    int32_t pad_band;
     double ratios[kK0Max];
     // BFS
     int32_t bfs_level;    // distance of the current frontier
@@ -62,6 +65,7 @@ struct alignas(256) DevState {
     uint32_t tk_bfs;
     int32_t ncomp;
     uint64_t comp_best;   // (ecc << 32) | ~component of the best component
+    int64_t spare_i64;    // host-side scratch in the pinned mirror
 };
 
 // Byte offsets of every region inside the caller's arena.
@@ -70,44 +74,85 @@ struct Layout {
     size_t x32, r32, q32, dA32, dB32;
     size_t r64, q64, dA64, dB64;
     size_t dist, q0, q1, label, tarr, best;
+    size_t sell_wid, sell_off, sell_col, sell_v64, sell_v32;
+    int64_t sell_cap;   // padded entries the SELL arrays can hold
     size_t total;
-    int64_t n, nnz, part_cap;
+    int64_t n, nnz;
+};
+
+// Launch shape of the CSR-stream kernels: tiles of R rows, `grid` blocks each
+// walking a contiguous range of tiles.
+struct SpmvShape {
+    int32_t n, R, ntiles, grid;
+};
+SpmvShape spmv_shape(int64_t n, int64_t nnz, int value_bytes, int num_cu);
+int vec_grid(int64_t n);
+
+// SELL-64 copy of A (kernels_sell.hip): slices of 64 rows, entries of a slice
+// stored column-major, 16-bit column offsets when the bandwidth allows.
+struct SellMat {
+    const int32_t *rp;
+    const void *scol;
+    const double *v64;
+    const float *v32;
+    const int64_t *off;
+    int32_t n, nslices, grid, idx16;
 };
 
 Layout plan_layout(int64_t n, int64_t nnz);
 
-// Rows per SpMV block so that a block's entries fill one LDS chunk on average.
-int spmv_rows_per_block(int64_t n, int64_t nnz, int value_bytes);
 
 // ----- launch wrappers (kernels_cg.hip) -----
 void launch_ingest(hipStream_t s, const void *rp_in, int rp_is_i64, const int32_t *col,
                    const double *val, const double *b, int32_t n, int64_t nnz, int32_t *rp32_out,
-                   float *val32_out, DevState *st);
+                   DevState *st);
+void launch_cast32(hipStream_t s, const double *val, float *val32, int64_t nnz);
 void launch_fill_f64(hipStream_t s, double *p, int64_t n, double v);
 void launch_fill_f32(hipStream_t s, float *p, int64_t n, float v);
 void launch_fill_i32(hipStream_t s, int32_t *p, int64_t n, int32_t v);
 void launch_init32(hipStream_t s, const double *b, float *x, float *r, float *dA, int32_t n,
                    double eps, int abs_tol, int32_t maxit, int32_t k0rec, double *part, DevState *st);
-void launch_set_phase(hipStream_t s, DevState *st, double thr, int32_t maxit, int32_t k0rec,
-                      int32_t reset_iter);
-void launch_timing_state(hipStream_t s, DevState *st);
+void launch_set_phase(hipStream_t s, DevState *st, double thr, int32_t maxit, int32_t k0rec);
+void launch_timing_state(hipStream_t s, DevState *st, double *part, int cnt);
+// CG iteration `it` of a phase that started at `it0`: product kernel (reads the
+// update partials `up`, writes its own to `part`) and update kernel (reads
+// `sp`, writes `up`).
 template <typename T>
-void launch_cg_spmv(hipStream_t s, const int32_t *rp, const int32_t *col, const T *val, int32_t n,
-                    int R, const T *r, T *dA, T *dB, T *q, double *part, DevState *st);
+void launch_cg_spmv(hipStream_t s, const SpmvShape &sh, const int32_t *rp, const int32_t *col,
+                    const T *val, const T *r, T *dA, T *dB, T *q, const double *up, int nup,
+                    double *part, int it, int it0, DevState *st);
 template <typename T>
 void launch_cg_update(hipStream_t s, int32_t n, T *x, T *r, const T *q, const T *dA, const T *dB,
-                      double *part, DevState *st);
+                      const double *sp, int nsp, double *up, int it, DevState *st);
 // r = b - A x (x from float x32 when x32 != nullptr, else from x64), x64 <- float64(x32),
-// zero the next "old direction" buffer, gamma = r.r, ||b||^2, set thr/maxit.
-void launch_restart(hipStream_t s, const int32_t *rp, const int32_t *col, const double *val,
-                    int32_t n, int R, const float *x32, double *x64, const double *b, double *r,
-                    double *dA, double *dB, double eps, int abs_tol, int32_t maxit, double *part,
-                    DevState *st);
-void launch_resid(hipStream_t s, const int32_t *rp, const int32_t *col, const double *val,
-                  int32_t n, int R, const double *x64, const double *b, double *part, DevState *st);
+// zero the old-direction buffer of iteration it0, gamma = r.r, ||b||^2, stop test.
+void launch_restart(hipStream_t s, const SpmvShape &sh, const int32_t *rp, const int32_t *col,
+                    const double *val, const float *x32, double *x64, const double *b, double *r,
+                    double *dA, double *dB, int it0, double eps, int abs_tol, int32_t maxit,
+                    double *part, DevState *st);
+void launch_resid(hipStream_t s, const SpmvShape &sh, const int32_t *rp, const int32_t *col,
+                  const double *val, const double *x64, const double *b, double *part, DevState *st);
+void launch_fin_restart(hipStream_t s, const double *part, int cnt, int it0, double eps, int abs_tol,
+                        int32_t maxit, DevState *st);
+void launch_fin_resid(hipStream_t s, const double *part, int cnt, DevState *st);
 template <typename T>
-void launch_spmv_plain(hipStream_t s, const int32_t *rp, const int32_t *col, const T *val,
-                       int32_t n, int R, const T *x, T *y);
+void launch_spmv_plain(hipStream_t s, const SpmvShape &sh, const int32_t *rp, const int32_t *col,
+                       const T *val, const T *x, T *y);
+
+// ----- SELL-64 (kernels_sell.hip) -----
+void launch_sell_plan(hipStream_t s, const int32_t *rp, int32_t n, int64_t *wid, int64_t *off);
+void launch_sell_fill(hipStream_t s, const int32_t *rp, const int32_t *col, const double *val,
+                      int32_t n, const int64_t *off, void *scol, int idx16, double *sv64, float *sv32);
+template <typename T>
+void launch_sell_cg_spmv(hipStream_t s, const SellMat &m, const T *r, T *dA, T *dB, T *q,
+                         const double *up, int nup, double *part, int it, int it0, DevState *st);
+void launch_sell_restart(hipStream_t s, const SellMat &m, const float *x32, double *x64,
+                         const double *b, double *r, double *dA, double *dB, int it0, double *part,
+                         DevState *st);
+void launch_sell_resid(hipStream_t s, const SellMat &m, const double *x64, const double *b,
+                       double *part, DevState *st);
+template <typename T>
+void launch_sell_plain(hipStream_t s, const SellMat &m, const T *x, T *y);
 
 // ----- BFS (kernels_bfs.hip) -----
 struct BfsBufs {

@@ -41,6 +41,25 @@ def solver(torch_mod):
     s.close()
 
 
+@pytest.fixture(scope="module")
+def solver_csr(torch_mod):
+    """A context that always takes the CSR-stream kernels (the fallback used
+    when the SELL-64 copy would need too much padding)."""
+    from paper_2412_08059_amd import Solver
+    os.environ["MPCG_FORCE_CSR"] = "1"
+    try:
+        s = Solver(200_000, 4_000_000, model=TEST_MODEL)
+    finally:
+        del os.environ["MPCG_FORCE_CSR"]
+    yield s
+    s.close()
+
+
+@pytest.fixture(params=["sell", "csr"])
+def any_solver(request, solver, solver_csr):
+    return solver if request.param == "sell" else solver_csr
+
+
 def dev(a, **kw):
     from paper_2412_08059_amd import DeviceCSR
     return DeviceCSR.from_host(a, **kw)
@@ -80,7 +99,8 @@ SPMV_CASES = {
 
 @pytest.mark.parametrize("name", list(SPMV_CASES))
 @pytest.mark.parametrize("prec", [64, 32])
-def test_spmv_bitwise(solver, torch_mod, name, prec):
+def test_spmv_bitwise(any_solver, torch_mod, name, prec):
+    solver = any_solver
     a = SPMV_CASES[name]()
     rng = np.random.default_rng(11)
     x = rng.uniform(-1, 1, size=a.n)
@@ -168,7 +188,8 @@ SOLVE_CASES = {
 
 
 @pytest.mark.parametrize("name", list(SOLVE_CASES))
-def test_solve_parity(solver, torch_mod, name):
+def test_solve_parity(any_solver, torch_mod, name):
+    solver = any_solver
     gen, eps_list = SOLVE_CASES[name]
     a = gen()
     xs, b = W.rhs(a, seed=0)
