@@ -151,28 +151,23 @@ mpcg_status ingest(mpcg_ctx *c, const mpcg_csr *A, const double *b, bool need_va
     int32_t *rp32 = A->row_ptr_is_i64 ? p->at<int32_t>(p->L.rp32) : nullptr;
     p->rp = A->row_ptr_is_i64 ? rp32 : static_cast<const int32_t *>(A->row_ptr);
     HIPCHK(hipMemsetAsync(p->st, 0, sizeof(DevState), c->stream));
-    launch_ingest(c->stream, A->row_ptr, A->row_ptr_is_i64 ? 1 : 0, A->col_idx, A->val, b, p->n,
-                  A->nnz, rp32, p->st);
-    // SELL-64 slice widths and offsets (reads only row pointers, so it is safe
-    // to enqueue before the validation verdict is known)
     int64_t *soff = p->at<int64_t>(p->L.sell_off);
-    launch_sell_plan(c->stream, p->rp, p->n, p->at<int64_t>(p->L.sell_wid), soff);
-    HIPCHK(hipGetLastError());
     const int nsl = (p->n + 63) / 64;
+    launch_ingest_sell(c->stream, A->row_ptr, A->row_ptr_is_i64 ? 1 : 0, p->rp, rp32, A->col_idx, A->val, b,
+                       p->n, A->nnz, p->at<int64_t>(p->L.sell_wid), soff, p->L.sell_cap, c->force_csr ? 0 : 1,
+                       p->ws + p->L.sell_col, p->at<double>(p->L.sell_v64),
+                       need_val32 ? p->at<float>(p->L.sell_v32) : nullptr, p->st);
+    HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(&c->hst[2].spare_i64, soff + nsl, sizeof(int64_t), hipMemcpyDeviceToHost,
                           c->stream));
-    int64_t padded = 0;
-    {
-        DevState s;
-        HIPCHK(hipMemcpyAsync(&c->hst[1], p->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        s = c->hst[1];
-        padded = c->hst[2].spare_i64;
-        if (s.ing_err & (kErrRowPtr | kErrCol | kErrUnsorted)) return MPCG_EINVAL;
-        if (s.ing_err & (kErrNonFiniteA | kErrNonFiniteB)) return MPCG_ENONFINITE;
-        p->use_sell = padded >= 0 && padded <= p->L.sell_cap && !c->force_csr;
-        p->sell.idx16 = s.max_band < 32768 ? 1 : 0;
-    }
+    HIPCHK(hipMemcpyAsync(&c->hst[1], p->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const DevState s = c->hst[1];
+    const int64_t padded = c->hst[2].spare_i64;
+    if (s.ing_err & (kErrRowPtr | kErrCol | kErrUnsorted)) return MPCG_EINVAL;
+    if (s.ing_err & (kErrNonFiniteA | kErrNonFiniteB)) return MPCG_ENONFINITE;
+    // the entry kernel filled the SELL copy under exactly this condition
+    p->use_sell = !c->force_csr && padded <= p->L.sell_cap;
     p->sh64 = spmv_shape(A->n, A->nnz, 8, c->num_cu);
     p->sh32 = spmv_shape(A->n, A->nnz, 4, c->num_cu);
     p->nup = vec_grid(A->n);
@@ -182,14 +177,13 @@ mpcg_status ingest(mpcg_ctx *c, const mpcg_csr *A, const double *b, bool need_va
         m.off = soff;
         m.n = p->n;
         m.nslices = nsl;
+        m.idx16 = s.max_band < 32768 ? 1 : 0;
         int64_t g = ((int64_t)nsl + kBlock / 64 - 1) / (kBlock / 64);
         if (g > kMaxGrid) g = kMaxGrid;
         m.grid = (int32_t)(g < 1 ? 1 : g);
         m.scol = p->ws + p->L.sell_col;
         m.v64 = p->at<double>(p->L.sell_v64);
         m.v32 = need_val32 ? p->at<float>(p->L.sell_v32) : nullptr;
-        launch_sell_fill(c->stream, p->rp, A->col_idx, A->val, p->n, soff, p->ws + p->L.sell_col, m.idx16,
-                         p->at<double>(p->L.sell_v64), need_val32 ? p->at<float>(p->L.sell_v32) : nullptr);
     } else if (need_val32) {
         launch_cast32(c->stream, A->val, p->at<float>(p->L.val32), A->nnz);
     }
@@ -293,6 +287,9 @@ BfsBufs bfs_bufs(const Plan &p)
     int lanes = 1;
     while (lanes < avg && lanes < 32) lanes <<= 1;
     b.lanes = lanes;
+    b.small_max = kBfsSmallWork / lanes;
+    if (b.small_max < 64) b.small_max = 64;
+    if (b.small_max > kBfsSmallCap) b.small_max = kBfsSmallCap;
     b.dist = p.at<int32_t>(p.L.dist);
     b.q0 = p.at<int32_t>(p.L.q0);
     b.q1 = p.at<int32_t>(p.L.q1);

@@ -51,12 +51,13 @@ void launch_bfs_seed_single(hipStream_t s, const BfsBufs &b, int32_t src)
 
 // ------------------------------------------------- one-workgroup rounds --
 
-// Runs levels while 0 < frontier <= kBfsSmallCap.  The frontier lives in LDS;
+// Runs levels while 0 < frontier <= small_max (<= kBfsSmallCap, chosen so
+// that one pass of the 1024 threads covers the level).  The frontier lives in LDS;
 // the next frontier is also written to the global queue so that the
 // multi-block kernel can take over when it outgrows LDS.
 __global__ void __launch_bounds__(kBfsSmallThreads)
 k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int32_t *dist,
-            int32_t *q0, int32_t *q1, int32_t n, int32_t lanes, DevState *st)
+            int32_t *q0, int32_t *q1, int32_t n, int32_t lanes, int32_t small_max, DevState *st)
 {
     __shared__ int32_t sq[2][kBfsSmallCap];
     __shared__ int32_t s_cnt, s_min, s_cur, s_level, s_par, s_go, s_curmin;
@@ -64,7 +65,7 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
     const int tid = threadIdx.x;
     if (tid == 0) {
         const int cur = st->bfs_cur;
-        s_go = (!st->bfs_done && cur > 0 && cur <= kBfsSmallCap) ? 1 : 0;
+        s_go = (!st->bfs_done && cur > 0 && cur <= small_max) ? 1 : 0;
         s_cur = cur;
         s_level = st->bfs_level;
         s_par = st->bfs_parity;
@@ -114,7 +115,7 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
         }
         c ^= 1;
         __syncthreads();
-        if (nxt > kBfsSmallCap) break;
+        if (nxt > small_max) break;
     }
     if (tid == 0) {
         st->bfs_level = s_level;
@@ -150,40 +151,42 @@ __device__ inline int wave_min_i(int v)
     return v;
 }
 
-// One level, top-down, one thread per frontier vertex; all lanes of a wave
-// walk their neighbour lists in lockstep so that appends to the next
-// frontier take one atomic per wave.
+// One level, top-down.  `lanes` consecutive lanes share a frontier vertex
+// and take its neighbours in parallel (lane l: entries l, l + lanes, ...);
+// every wave runs a wave-uniform loop so that appends to the next frontier
+// take one atomic per wave and step.
 __global__ void __launch_bounds__(kBlock)
 k_bfs_level(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int32_t *dist,
-            int32_t *q0, int32_t *q1, int32_t n, DevState *st)
+            int32_t *q0, int32_t *q1, int32_t n, int32_t lanes, int32_t small_max, DevState *st)
 {
     const int cur = min(st->bfs_cur, n);
-    if (st->bfs_done || cur <= kBfsSmallCap) return;
+    if (st->bfs_done || cur <= small_max) return;
     const int level = st->bfs_level;
     const int par = st->bfs_parity;
     const int32_t *qc = par ? q1 : q0;
     int32_t *qn = par ? q0 : q1;
     const int lane = threadIdx.x & 63;
     int wmin = kIntMax;
-    const int stride = gridDim.x * kBlock;
-    const int first = blockIdx.x * kBlock + (threadIdx.x & ~63);
-    // wave-uniform loop bound so that ballots see every lane
-    for (int wbase = first; wbase < cur; wbase += stride) {
-        const int i = wbase + lane;
-        int u = -1, kb = 0, len = 0;
-        if (i < cur) {
-            u = qc[i];
+    const int64_t items = (int64_t)cur * lanes;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t wbase = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); wbase < items; wbase += stride) {
+        const int64_t w = wbase + lane;
+        int u = -1, k = 0, e = 0;
+        if (w < items) {
+            const int f = (int)(w / lanes), l = (int)(w - (int64_t)f * lanes);
+            u = qc[f];
             if ((unsigned)u < (unsigned)n) {
-                kb = rp[u];
-                len = rp[u + 1] - kb;
+                k = rp[u] + l;
+                e = rp[u + 1];
             }
         }
-        const int wlen = wave_max_i(len);
-        for (int j = 0; j < wlen; ++j) {
+        int steps = k < e ? (e - k + lanes - 1) / lanes : 0;
+        steps = wave_max_i(steps);
+        for (int j = 0; j < steps; ++j, k += lanes) {
             int v = -1;
             bool found = false;
-            if (j < len) {
-                v = col[kb + j];
+            if (k < e) {
+                v = col[k];
                 if (v != u && dist[v] < 0) found = (atomicCAS(&dist[v], -1, level + 1) == -1);
             }
             const unsigned long long m = __ballot(found);
@@ -237,12 +240,12 @@ k_bfs_level(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
 void launch_bfs_round(hipStream_t s, const BfsBufs &b, int levels)
 {
     hipLaunchKernelGGL(k_bfs_small, dim3(1), dim3(kBfsSmallThreads), 0, s, b.rp, b.col, b.dist, b.q0,
-                       b.q1, b.n, b.lanes, b.st);
+                       b.q1, b.n, b.lanes, b.small_max, b.st);
     int grid = (b.n + kBlock - 1) / kBlock;
     if (grid > kBfsLevelBlocks) grid = kBfsLevelBlocks;
     for (int l = 0; l < levels; ++l)
         hipLaunchKernelGGL(k_bfs_level, dim3(grid), dim3(kBlock), 0, s, b.rp, b.col, b.dist, b.q0, b.q1,
-                           b.n, b.st);
+                           b.n, b.lanes, b.small_max, b.st);
 }
 
 // ------------------------------------------------ connected components --

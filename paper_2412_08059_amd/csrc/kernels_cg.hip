@@ -84,75 +84,10 @@ template <typename T> __device__ inline T fmaT(T a, T b, T c);
 template <> __device__ inline float fmaT<float>(float a, float b, float c) { return fmaf(a, b, c); }
 template <> __device__ inline double fmaT<double>(double a, double b, double c) { return fma(a, b, c); }
 
-// --------------------------------------------------------------- ingest --
-
-__global__ void __launch_bounds__(kBlock)
-k_ingest(const void *rp_in, int rp_is_i64, const int32_t *__restrict__ col,
-         const double *__restrict__ val, const double *__restrict__ b, int32_t n, int64_t nnz,
-         int32_t *__restrict__ rp32_out, DevState *st)
-{
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    int err = 0, len = 0, band = 0;
-    if (i < n) {
-        int64_t lo, hi;
-        if (rp_is_i64) {
-            lo = ((const int64_t *)rp_in)[i];
-            hi = ((const int64_t *)rp_in)[i + 1];
-        } else {
-            lo = ((const int32_t *)rp_in)[i];
-            hi = ((const int32_t *)rp_in)[i + 1];
-        }
-        if (i == 0 && lo != 0) err |= kErrRowPtr;
-        if (i == n - 1 && hi != nnz) err |= kErrRowPtr;
-        if (lo < 0 || hi < lo || hi > nnz) {
-            err |= kErrRowPtr;
-        } else {
-            len = (int)(hi - lo);
-            int prev = -1;
-            for (int64_t k = lo; k < hi; ++k) {
-                const int c = col[k];
-                if (c < 0 || c >= n) err |= kErrCol;
-                if (c <= prev) err |= kErrUnsorted;
-                prev = c;
-                const int d = c > (int)i ? c - (int)i : (int)i - c;
-                band = band > d ? band : d;
-                if (!isfinite(val[k])) err |= kErrNonFiniteA;
-            }
-        }
-        if (rp32_out) {
-            rp32_out[i] = (int32_t)lo;
-            if (i == n - 1) rp32_out[n] = (int32_t)hi;
-        }
-        if (b && !isfinite(b[i])) err |= kErrNonFiniteB;
-    }
-    // one atomic per wave
-    for (int off = 32; off > 0; off >>= 1) {
-        err |= __shfl_xor(err, off, 64);
-        const int o = __shfl_xor(len, off, 64);
-        len = len > o ? len : o;
-        const int ob = __shfl_xor(band, off, 64);
-        band = band > ob ? band : ob;
-    }
-    if ((threadIdx.x & 63) == 0) {
-        if (err) atomicOr(&st->ing_err, err);
-        atomicMax(&st->max_row, len);
-        atomicMax(&st->max_band, band);
-    }
-}
-
 __global__ void k_cast32(const double *__restrict__ val, float *__restrict__ val32, int64_t nnz)
 {
     for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * kBlock)
         val32[k] = (float)val[k];
-}
-
-void launch_ingest(hipStream_t s, const void *rp_in, int rp_is_i64, const int32_t *col,
-                   const double *val, const double *b, int32_t n, int64_t nnz, int32_t *rp32_out,
-                   DevState *st)
-{
-    const int grid = (int)((n + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_ingest, dim3(grid), dim3(kBlock), 0, s, rp_in, rp_is_i64, col, val, b, n,
-                       nnz, rp32_out, st);
 }
 
 void launch_cast32(hipStream_t s, const double *val, float *val32, int64_t nnz)

@@ -63,22 +63,66 @@ __device__ inline int sell_xcd_remap(int b, int nb)
     return x * q + (x < rem ? x : rem) + i;
 }
 
-// ---------------------------------------------------------------- build --
+// ------------------------------------------------------------- ingest --
+//
+// Ingest is three launches and one host read-back:
+//   k_ingest_rows     thread per row: row-pointer checks (and int64 -> int32
+//                     conversion), b finite, row length, bandwidth from the
+//                     first and last column of the row, slice width;
+//   k_sell_scan       padded slice offsets;
+//   k_ingest_entries  wave per slice, entries read in coalesced 64-wide
+//                     strides: column range, strictly increasing columns,
+//                     finite values, and the SELL-64 copy when it fits.
 
-// slice width (longest row of the slice) times 64, per slice
-__global__ void k_sell_width(const int32_t *__restrict__ rp, int32_t n, int32_t nslices, int64_t *wid)
+__global__ void __launch_bounds__(kBlock)
+k_ingest_rows(const void *rp_in, int rp_is_i64, const int32_t *__restrict__ col,
+              const double *__restrict__ b, int32_t n, int64_t nnz, int32_t nslices,
+              int32_t *__restrict__ rp32_out, int64_t *__restrict__ wid, DevState *st)
 {
-    const int s = blockIdx.x * kBlock + threadIdx.x;
-    if (s >= nslices) return;
-    const int r0 = s * 64, r1 = min(r0 + 64, n);
-    int w = 0;
-    int prev = rp[r0];
-    for (int r = r0; r < r1; ++r) {
-        const int nx = rp[r + 1];
-        w = max(w, nx - prev);
-        prev = nx;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int err = 0, len = 0, band = 0;
+    if (i < n) {
+        int64_t lo, hi;
+        if (rp_is_i64) {
+            lo = ((const int64_t *)rp_in)[i];
+            hi = ((const int64_t *)rp_in)[i + 1];
+        } else {
+            lo = ((const int32_t *)rp_in)[i];
+            hi = ((const int32_t *)rp_in)[i + 1];
+        }
+        if (i == 0 && lo != 0) err |= kErrRowPtr;
+        if (i == n - 1 && hi != nnz) err |= kErrRowPtr;
+        if (lo < 0 || hi < lo || hi > nnz) {
+            err |= kErrRowPtr;
+        } else if (hi > lo) {
+            len = (int)(hi - lo);
+            const int c0 = col[lo], c1 = col[hi - 1];
+            if (c0 < 0 || c1 >= n) err |= kErrCol;
+            const int64_t d0 = i - (int64_t)c0, d1 = (int64_t)c1 - i;
+            int64_t d = d0 > d1 ? d0 : d1;
+            if (d < 0) d = -d;
+            band = d > 0x3fffffff ? 0x3fffffff : (int)d;
+        }
+        if (rp32_out) {
+            rp32_out[i] = (int32_t)lo;
+            if (i == n - 1) rp32_out[n] = (int32_t)hi;
+        }
+        if (b && !isfinite(b[i])) err |= kErrNonFiniteB;
     }
-    wid[s] = (int64_t)w * 64;
+    for (int off = 32; off > 0; off >>= 1) {
+        err |= __shfl_xor(err, off, 64);
+        const int ol = __shfl_xor(len, off, 64);
+        len = len > ol ? len : ol;
+        const int ob = __shfl_xor(band, off, 64);
+        band = band > ob ? band : ob;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        const int64_t s = i >> 6;
+        if (s < nslices) wid[s] = (int64_t)len * 64;
+        if (err) atomicOr(&st->ing_err, err);
+        atomicMax(&st->max_row, len);
+        atomicMax(&st->max_band, band);
+    }
 }
 
 // exclusive scan of the padded slice sizes (one block), off[nslices] = total
@@ -106,46 +150,72 @@ __global__ void __launch_bounds__(1024) k_sell_scan(const int64_t *wid, int32_t 
     if (t == 1023) off[nslices] = part[1023];
 }
 
-template <typename IDX>
 __global__ void __launch_bounds__(kBlock)
-k_sell_fill(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-            const double *__restrict__ val, int32_t n, const int64_t *__restrict__ off,
-            IDX *__restrict__ scol, double *__restrict__ sv64, float *__restrict__ sv32)
+k_ingest_entries(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                 const double *__restrict__ val, int32_t n, int32_t nslices,
+                 const int64_t *__restrict__ off, int64_t cap, int allow_fill, void *scol,
+                 double *__restrict__ sv64, float *__restrict__ sv32, DevState *st)
 {
-    const int row = blockIdx.x * kBlock + threadIdx.x;
-    if (row >= n) return;
-    const int s = row >> 6, lane = row & 63;
-    const int64_t base = off[s] + lane;
-    const int lo = rp[row], hi = rp[row + 1];
-    for (int k = lo; k < hi; ++k) {
-        const int64_t dst = base + (int64_t)(k - lo) * 64;
-        const int c = col[k];
-        if (sizeof(IDX) == 2) scol[dst] = (IDX)(c - row);
-        else scol[dst] = (IDX)c;
-        const double v = val[k];
-        if (sv64) sv64[dst] = v;
-        if (sv32) sv32[dst] = (float)v;
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) s_ok = !(st->ing_err & kErrRowPtr);
+    __syncthreads();
+    if (!s_ok) return;   // row pointers are not usable
+    const bool fill = allow_fill && off[nslices] <= cap;
+    const bool idx16 = st->max_band < 32768;
+    const int lane = threadIdx.x & 63;
+    int err = 0;
+    for (int s = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); s < nslices; s += gridDim.x * (kBlock / 64)) {
+        const int r0 = s * 64;
+        const int nrows = min(64, n - r0);
+        const int rpl = rp[r0 + min(lane, nrows)];      // start of row r0 + lane
+        const int lo = __shfl(rpl, 0, 64);
+        const int hi = rp[r0 + nrows];
+        const int64_t base_off = fill ? off[s] : 0;
+        for (int kb = lo; kb < hi; kb += 64) {          // wave-uniform trip count
+            const int k = kb + lane;
+            // row of entry k: largest m < nrows with rp[r0 + m] <= k
+            int m = 0;
+            for (int step = 32; step > 0; step >>= 1) {
+                const int cand = m + step;
+                const int v = __shfl(rpl, cand < 64 ? cand : 63, 64);
+                if (cand < nrows && v <= k) m = cand;
+            }
+            const int rstart = __shfl(rpl, m, 64);
+            if (k < hi) {
+                const int row = r0 + m;
+                const int pos = k - rstart;
+                const int c = col[k];
+                if (c < 0 || c >= n) err |= kErrCol;
+                if (pos > 0 && c <= col[k - 1]) err |= kErrUnsorted;
+                const double v = val[k];
+                if (!isfinite(v)) err |= kErrNonFiniteA;
+                if (fill) {
+                    const int64_t dst = base_off + (int64_t)pos * 64 + m;
+                    if (idx16) static_cast<int16_t *>(scol)[dst] = (int16_t)(c - row);
+                    else static_cast<int32_t *>(scol)[dst] = c;
+                    sv64[dst] = v;
+                    if (sv32) sv32[dst] = (float)v;
+                }
+            }
+        }
     }
+    for (int o = 32; o > 0; o >>= 1) err |= __shfl_xor(err, o, 64);
+    if (lane == 0 && err) atomicOr(&st->ing_err, err);
 }
 
-void launch_sell_plan(hipStream_t s, const int32_t *rp, int32_t n, int64_t *wid, int64_t *off)
+void launch_ingest_sell(hipStream_t s, const void *rp_in, int rp_is_i64, const int32_t *rp32,
+                        int32_t *rp32_out, const int32_t *col, const double *val, const double *b,
+                        int32_t n, int64_t nnz, int64_t *wid, int64_t *off, int64_t cap, int allow_fill,
+                        void *scol, double *sv64, float *sv32, DevState *st)
 {
     const int nslices = (n + 63) / 64;
-    hipLaunchKernelGGL(k_sell_width, dim3((nslices + kBlock - 1) / kBlock), dim3(kBlock), 0, s, rp, n,
-                       nslices, wid);
+    hipLaunchKernelGGL(k_ingest_rows, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, rp_in, rp_is_i64,
+                       col, b, n, nnz, nslices, rp32_out, wid, st);
     hipLaunchKernelGGL(k_sell_scan, dim3(1), dim3(1024), 0, s, wid, nslices, off);
-}
-
-void launch_sell_fill(hipStream_t s, const int32_t *rp, const int32_t *col, const double *val,
-                      int32_t n, const int64_t *off, void *scol, int idx16, double *sv64, float *sv32)
-{
-    const int grid = (n + kBlock - 1) / kBlock;
-    if (idx16)
-        hipLaunchKernelGGL(k_sell_fill<int16_t>, dim3(grid), dim3(kBlock), 0, s, rp, col, val, n, off,
-                           static_cast<int16_t *>(scol), sv64, sv32);
-    else
-        hipLaunchKernelGGL(k_sell_fill<int32_t>, dim3(grid), dim3(kBlock), 0, s, rp, col, val, n, off,
-                           static_cast<int32_t *>(scol), sv64, sv32);
+    int g = (nslices + 3) / 4;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_ingest_entries, dim3(g), dim3(kBlock), 0, s, rp32, col, val, n, nslices, off, cap,
+                       allow_fill, scol, sv64, sv32, st);
 }
 
 // -------------------------------------------------------------- kernels --

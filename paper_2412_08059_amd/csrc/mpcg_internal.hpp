@@ -18,7 +18,8 @@ constexpr int kK0Max = 64;            // longest FP32 prefix recorded for v
 constexpr int kLdsBytes = 32768;      // LDS staging per SpMV block (val + gathered x)
 constexpr int kBfsSmallCap = 4096;    // frontier size handled by the one-workgroup BFS kernel
 constexpr int kBfsSmallThreads = 1024;
-constexpr int kBfsLevelBlocks = 1024; // grid of the multi-block BFS level kernel
+constexpr int kBfsSmallWork = 2048;   // (vertex, lane) items per level in the one-workgroup kernel
+constexpr int kBfsLevelBlocks = 256;  // grid of the multi-block BFS level kernel (arrival ticket per block)
 constexpr int kNumXcd = 8;            // MI355X: blocks are dispatched round-robin over 8 XCDs
 constexpr int kMaxGrid = 2048;        // largest grid of a kernel that writes reduction partials
 constexpr int kSpmvBlocksPerCu = 5;   // 32 KB of LDS per block, 160 KB per CU
@@ -103,9 +104,12 @@ Layout plan_layout(int64_t n, int64_t nnz);
 
 
 // ----- launch wrappers (kernels_cg.hip) -----
-void launch_ingest(hipStream_t s, const void *rp_in, int rp_is_i64, const int32_t *col,
-                   const double *val, const double *b, int32_t n, int64_t nnz, int32_t *rp32_out,
-                   DevState *st);
+// Validate A (and b), convert int64 row pointers, and build the SELL-64 copy
+// when its padded size fits in `cap` entries (see kernels_sell.hip).
+void launch_ingest_sell(hipStream_t s, const void *rp_in, int rp_is_i64, const int32_t *rp32,
+                        int32_t *rp32_out, const int32_t *col, const double *val, const double *b,
+                        int32_t n, int64_t nnz, int64_t *wid, int64_t *off, int64_t cap, int allow_fill,
+                        void *scol, double *sv64, float *sv32, DevState *st);
 void launch_cast32(hipStream_t s, const double *val, float *val32, int64_t nnz);
 void launch_fill_f64(hipStream_t s, double *p, int64_t n, double v);
 void launch_fill_f32(hipStream_t s, float *p, int64_t n, float v);
@@ -140,9 +144,6 @@ void launch_spmv_plain(hipStream_t s, const SpmvShape &sh, const int32_t *rp, co
                        const T *val, const T *x, T *y);
 
 // ----- SELL-64 (kernels_sell.hip) -----
-void launch_sell_plan(hipStream_t s, const int32_t *rp, int32_t n, int64_t *wid, int64_t *off);
-void launch_sell_fill(hipStream_t s, const int32_t *rp, const int32_t *col, const double *val,
-                      int32_t n, const int64_t *off, void *scol, int idx16, double *sv64, float *sv32);
 template <typename T>
 void launch_sell_cg_spmv(hipStream_t s, const SellMat &m, const T *r, T *dA, T *dB, T *q,
                          const double *up, int nup, double *part, int it, int it0, DevState *st);
@@ -159,6 +160,7 @@ struct BfsBufs {
     const int32_t *rp, *col;
     int32_t n;
     int32_t lanes;          // lanes per frontier vertex in the one-workgroup kernel
+    int32_t small_max;      // largest frontier left to the one-workgroup kernel
     int32_t *dist, *q0, *q1, *label, *tarr;
     unsigned long long *best;
     DevState *st;
