@@ -102,8 +102,8 @@ typedef struct {
     double omega_measured;      /* (t_sp / n1) / (t_dp / n2), 0 if undefined */
     double I_third;             /* n1 / 3 + n2, eq. (4) with omega = 1/3 */
     double I_meas;              /* omega_measured * n1 + n2 */
-    double t_feat_ms;           /* 2BFS (Algorithm II only) */
-    double t_sp_ms;             /* ingest + FP32 phase (k0 prefix and kNN included) */
+    double t_feat_ms;           /* 2BFS (Algorithm II only; runs beside the FP32 phase) */
+    double t_sp_ms;             /* call start to the FP64 restart: ingest, FP32 phase, kNN */
     double t_dp_ms;             /* restart + FP64 phase + final check(s) */
     double t_total_ms;
     mpcg_features_t feat;       /* filled for eps1 = MPCG_EPS1_AUTO */

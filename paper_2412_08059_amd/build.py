@@ -43,7 +43,7 @@ def build(verbose: bool = False) -> str:
     """Compile every source and link libmpcg.so (always rebuilds)."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     hipcc = _hipcc()
-    common = ["-O3", "-fPIC", "-std=c++17", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall"]
+    common = ["-O3", "-fPIC", "-std=c++17", "-pthread", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall"]
     dev = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
     objs = []
     for src in HIP_SOURCES:
@@ -57,7 +57,7 @@ def build(verbose: bool = False) -> str:
               os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
+    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs])
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")

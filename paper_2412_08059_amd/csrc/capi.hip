@@ -5,21 +5,34 @@
 
 #include "mpcg_internal.hpp"
 
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <thread>
 
 using namespace mpcg;
+
+// A stream plus the pinned snapshots and events used to poll the device state
+// from it.
+struct Chan {
+    hipStream_t s = nullptr;
+    DevState *poll[2] = {nullptr, nullptr};
+    DevState *sync = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
 
 struct mpcg_ctx {
     int device = 0;
     int num_cu = 256;
     hipStream_t stream = nullptr;
+    hipStream_t side_stream = nullptr;   // owned: the 2BFS of Algorithm II runs here
+    Chan main, side;
     mpcg_options opt{};
     char *ws = nullptr;
     size_t ws_bytes = 0;
-    DevState *hst = nullptr;   // pinned: [0],[1] poll snapshots, [2] synchronous reads
+    DevState *hst = nullptr;   // pinned: [0],[1],[2] main channel, [3],[4],[5] side channel
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t tm[8] = {};
     KnnModel model;
@@ -76,6 +89,8 @@ Layout plan_layout(int64_t n, int64_t nnz)
     L.sell_col = take(sizeof(int32_t) * (size_t)L.sell_cap);
     L.sell_v64 = take(sizeof(double) * (size_t)L.sell_cap);
     L.sell_v32 = take(sizeof(float) * (size_t)L.sell_cap);
+    L.ingest_blk = take(sizeof(int32_t) * 3 * ((N + kBlock - 1) / kBlock + 1));
+    L.snap32 = take(sizeof(float) * kNumEps * N);
     L.total = off;
     return L;
 }
@@ -123,13 +138,15 @@ struct Plan {
     template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
 };
 
-mpcg_status read_state(mpcg_ctx *c, const Plan &p, DevState *out)
+mpcg_status read_state(const Chan &ch, const Plan &p, DevState *out)
 {
-    HIPCHK(hipMemcpyAsync(&c->hst[2], p.st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    *out = c->hst[2];
+    HIPCHK(hipMemcpyAsync(ch.sync, p.st, sizeof(DevState), hipMemcpyDeviceToHost, ch.s));
+    HIPCHK(hipStreamSynchronize(ch.s));
+    *out = *ch.sync;
     return MPCG_OK;
 }
+
+mpcg_status read_state(mpcg_ctx *c, const Plan &p, DevState *out) { return read_state(c->main, p, out); }
 
 // Validate A (and b) on the device, convert row pointers / cast values when
 // asked, and read back the verdict before any result buffer is touched.
@@ -154,7 +171,8 @@ mpcg_status ingest(mpcg_ctx *c, const mpcg_csr *A, const double *b, bool need_va
     int64_t *soff = p->at<int64_t>(p->L.sell_off);
     const int nsl = (p->n + 63) / 64;
     launch_ingest_sell(c->stream, A->row_ptr, A->row_ptr_is_i64 ? 1 : 0, p->rp, rp32, A->col_idx, A->val, b,
-                       p->n, A->nnz, p->at<int64_t>(p->L.sell_wid), soff, p->L.sell_cap, c->force_csr ? 0 : 1,
+                       p->n, A->nnz, p->at<int64_t>(p->L.sell_wid), soff, p->at<int32_t>(p->L.ingest_blk),
+                       p->L.sell_cap, c->force_csr ? 0 : 1,
                        p->ws + p->L.sell_col, p->at<double>(p->L.sell_v64),
                        need_val32 ? p->at<float>(p->L.sell_v32) : nullptr, p->st);
     HIPCHK(hipGetLastError());
@@ -202,14 +220,20 @@ template <typename T> const SpmvShape &csr_shape(const Plan &p);
 template <> const SpmvShape &csr_shape<float>(const Plan &p) { return p.sh32; }
 template <> const SpmvShape &csr_shape<double>(const Plan &p) { return p.sh64; }
 
+template <typename T> T *snap_buf(const Plan &p);
+template <> float *snap_buf<float>(const Plan &p) { return p.at<float>(p.L.snap32); }
+template <> double *snap_buf<double>(const Plan &) { return nullptr; }
+
+// x and snap are used only by the Algorithm II run-ahead (FP32)
 template <typename T>
-void run_cg_spmv(hipStream_t s, const Plan &p, const T *r, T *dA, T *dB, T *q, int it, int it0)
+void run_cg_spmv(hipStream_t s, const Plan &p, const T *r, T *dA, T *dB, T *q, int it, int it0,
+                 const T *x = nullptr, T *snap = nullptr)
 {
     if (p.use_sell)
-        launch_sell_cg_spmv<T>(s, p.sell, r, dA, dB, q, p.up, p.nup, p.sp, it, it0, p.st);
+        launch_sell_cg_spmv<T>(s, p.sell, r, dA, dB, q, p.up, p.nup, p.sp, it, it0, x, snap, p.st);
     else
         launch_cg_spmv<T>(s, csr_shape<T>(p), p.rp, p.col, csr_vals<T>(p), r, dA, dB, q, p.up, p.nup, p.sp,
-                          it, it0, p.st);
+                          it, it0, x, snap, p.st);
 }
 
 template <typename T>
@@ -250,31 +274,36 @@ void run_plain(hipStream_t s, const Plan &p, const T *x, T *y)
 int poll_iters(const mpcg_ctx *c) { return c->opt.graph_iters > 0 ? c->opt.graph_iters : 8; }
 
 // Run CG iterations in precision T from iteration `it` (phase started at
-// `it0`) until the device says stop.  Groups of iterations are enqueued one
-// ahead of the state snapshot being inspected; iterations enqueued after the
-// stop return at once.
+// `it0`) until the device says stop, or until *stop_flag is set (Algorithm II
+// run-ahead).  Groups of iterations are enqueued one ahead of the state
+// snapshot being inspected; iterations enqueued after a device stop return at
+// once.  *it_next gets the index of the next iteration that was not enqueued.
 template <typename T>
 mpcg_status cg_loop(mpcg_ctx *c, const Plan &p, T *x, T *r, T *q, T *dA, T *dB, int it, int it0,
-                    DevState *out)
+                    DevState *out, const std::atomic<int> *stop_flag = nullptr, int *it_next = nullptr)
 {
     const int G = poll_iters(c);
+    const Chan &ch = c->main;
+    T *snap = stop_flag ? snap_buf<T>(p) : nullptr;
     int64_t k = 0;
     for (;;) {
         for (int g = 0; g < G; ++g, ++it) {
-            run_cg_spmv<T>(c->stream, p, r, dA, dB, q, it, it0);
-            run_cg_update<T>(c->stream, p, x, r, q, dA, dB, it);
+            run_cg_spmv<T>(ch.s, p, r, dA, dB, q, it, it0, x, snap);
+            run_cg_update<T>(ch.s, p, x, r, q, dA, dB, it);
         }
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(&c->hst[k & 1], p.st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipEventRecord(c->ev[k & 1], c->stream));
+        HIPCHK(hipMemcpyAsync(ch.poll[k & 1], p.st, sizeof(DevState), hipMemcpyDeviceToHost, ch.s));
+        HIPCHK(hipEventRecord(ch.ev[k & 1], ch.s));
         if (k > 0) {
-            HIPCHK(hipEventSynchronize(c->ev[(k - 1) & 1]));
-            if (!c->hst[(k - 1) & 1].live) break;
+            HIPCHK(hipEventSynchronize(ch.ev[(k - 1) & 1]));
+            if (!ch.poll[(k - 1) & 1]->live) break;
         }
+        if (stop_flag && stop_flag->load()) break;
         ++k;
         if (it > 0x7ffffff0 - G) return MPCG_EDEVICE;
     }
-    return read_state(c, p, out);
+    if (it_next) *it_next = it;
+    return read_state(ch, p, out);
 }
 
 BfsBufs bfs_bufs(const Plan &p)
@@ -300,36 +329,40 @@ BfsBufs bfs_bufs(const Plan &p)
     return b;
 }
 
-mpcg_status bfs_run(mpcg_ctx *c, const Plan &p, const BfsBufs &bb, DevState *out)
+mpcg_status bfs_run(const Chan &ch, const Plan &p, const BfsBufs &bb, DevState *out)
 {
     const int levels = 16;
     for (int64_t round = 0;; ++round) {
-        launch_bfs_round(c->stream, bb, levels);
+        launch_bfs_round(ch.s, bb, levels);
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(&c->hst[round & 1], p.st, sizeof(DevState), hipMemcpyDeviceToHost,
-                              c->stream));
-        HIPCHK(hipEventRecord(c->ev[round & 1], c->stream));
+        HIPCHK(hipMemcpyAsync(ch.poll[round & 1], p.st, sizeof(DevState), hipMemcpyDeviceToHost, ch.s));
+        HIPCHK(hipEventRecord(ch.ev[round & 1], ch.s));
         if (round > 0) {
-            HIPCHK(hipEventSynchronize(c->ev[(round - 1) & 1]));
-            if (c->hst[(round - 1) & 1].bfs_done) break;
+            HIPCHK(hipEventSynchronize(ch.ev[(round - 1) & 1]));
+            if (ch.poll[(round - 1) & 1]->bfs_done) break;
+            if (ch.poll[(round - 1) & 1]->guard) {
+                (void)hipStreamSynchronize(ch.s);
+                return MPCG_EDEVICE;
+            }
         }
         if (round > (int64_t)p.n + 4) return MPCG_EDEVICE;   // every round expands >= 1 level
     }
-    return read_state(c, p, out);
+    return read_state(ch, p, out);
 }
 
 // 2BFS per component; fills pdiam, bfs_t, bfs_u, n_components.
-mpcg_status pseudo_diameter(mpcg_ctx *c, const Plan &p, mpcg_features_t *f)
+mpcg_status pseudo_diameter(const Chan &ch, const Plan &p, mpcg_features_t *f)
 {
     BfsBufs bb = bfs_bufs(p);
     DevState s;
-    launch_bfs_seed_single(c->stream, bb, 0);
-    mpcg_status rc = bfs_run(c, p, bb, &s);
+    launch_bfs_seed_single(ch.s, bb, 0);
+    mpcg_status rc = bfs_run(ch, p, bb, &s);
     if (rc != MPCG_OK) return rc;
+    if (s.guard) return MPCG_EDEVICE;
     if (s.bfs_visited == p.n) {
         const int32_t t = s.bfs_far;
-        launch_bfs_seed_single(c->stream, bb, t);
-        rc = bfs_run(c, p, bb, &s);
+        launch_bfs_seed_single(ch.s, bb, t);
+        rc = bfs_run(ch, p, bb, &s);
         if (rc != MPCG_OK) return rc;
         f->pdiam = s.bfs_level;
         f->bfs_t = t;
@@ -337,27 +370,27 @@ mpcg_status pseudo_diameter(mpcg_ctx *c, const Plan &p, mpcg_features_t *f)
         f->n_components = 1;
         return MPCG_OK;
     }
-    launch_cc(c->stream, bb);
-    launch_bfs_seed_roots(c->stream, bb);
-    rc = bfs_run(c, p, bb, &s);
+    launch_cc(ch.s, bb);
+    launch_bfs_seed_roots(ch.s, bb);
+    rc = bfs_run(ch, p, bb, &s);
     if (rc != MPCG_OK) return rc;
-    launch_comp_argmax(c->stream, bb, 0);
-    launch_bfs_seed_far(c->stream, bb);
-    rc = bfs_run(c, p, bb, &s);
+    launch_comp_argmax(ch.s, bb, 0);
+    launch_bfs_seed_far(ch.s, bb);
+    rc = bfs_run(ch, p, bb, &s);
     if (rc != MPCG_OK) return rc;
-    launch_comp_argmax(c->stream, bb, 1);
-    launch_comp_final(c->stream, bb);
+    launch_comp_argmax(ch.s, bb, 1);
+    launch_comp_final(ch.s, bb);
     HIPCHK(hipGetLastError());
-    rc = read_state(c, p, &s);
+    rc = read_state(ch, p, &s);
     if (rc != MPCG_OK) return rc;
     if (s.guard) return MPCG_EDEVICE;
     const uint64_t key = s.comp_best;
     const int32_t comp = (int32_t)(0xffffffffu - (uint32_t)(key & 0xffffffffull));
     int32_t t = 0;
     unsigned long long bu = 0;
-    HIPCHK(hipMemcpyAsync(&t, bb.tarr + comp, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(&bu, bb.best + comp, sizeof(bu), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpyAsync(&t, bb.tarr + comp, sizeof(int32_t), hipMemcpyDeviceToHost, ch.s));
+    HIPCHK(hipMemcpyAsync(&bu, bb.best + comp, sizeof(bu), hipMemcpyDeviceToHost, ch.s));
+    HIPCHK(hipStreamSynchronize(ch.s));
     f->pdiam = (int64_t)(key >> 32);
     f->bfs_t = t;
     f->bfs_u = (int64_t)(0xffffffffu - (uint32_t)(bu & 0xffffffffull));
@@ -440,14 +473,27 @@ mpcg_status mpcg_create(mpcg_ctx **out, const mpcg_options *opt, void *hip_strea
     }
     if (hipGetDevice(&c->device) != hipSuccess ||
         hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
-        hipHostMalloc((void **)&c->hst, 3 * sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
-        delete c;
+        hipHostMalloc((void **)&c->hst, 6 * sizeof(DevState), hipHostMallocDefault) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking) != hipSuccess) {
+        mpcg_destroy(c);
         return MPCG_EDEVICE;
     }
     for (auto &e : c->ev)
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return MPCG_EDEVICE;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) { mpcg_destroy(c); return MPCG_EDEVICE; }
     for (auto &e : c->tm)
-        if (hipEventCreate(&e) != hipSuccess) return MPCG_EDEVICE;
+        if (hipEventCreate(&e) != hipSuccess) { mpcg_destroy(c); return MPCG_EDEVICE; }
+    c->main.s = c->stream;
+    c->main.poll[0] = &c->hst[0];
+    c->main.poll[1] = &c->hst[1];
+    c->main.sync = &c->hst[2];
+    c->main.ev[0] = c->ev[0];
+    c->main.ev[1] = c->ev[1];
+    c->side.s = c->side_stream;
+    c->side.poll[0] = &c->hst[3];
+    c->side.poll[1] = &c->hst[4];
+    c->side.sync = &c->hst[5];
+    for (auto &e : c->side.ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) { mpcg_destroy(c); return MPCG_EDEVICE; }
     *out = c;
     return MPCG_OK;
 }
@@ -455,8 +501,13 @@ mpcg_status mpcg_create(mpcg_ctx **out, const mpcg_options *opt, void *hip_strea
 mpcg_status mpcg_destroy(mpcg_ctx *c)
 {
     if (!c) return MPCG_EINVAL;
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    if (c->side_stream) {
+        (void)hipStreamSynchronize(c->side_stream);
+        (void)hipStreamDestroy(c->side_stream);
+    }
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
+    for (auto &e : c->side.ev) if (e) (void)hipEventDestroy(e);
     for (auto &e : c->tm) if (e) (void)hipEventDestroy(e);
     if (c->hst) (void)hipHostFree(c->hst);
     knn_free(&c->model);
@@ -513,7 +564,7 @@ mpcg_status mpcg_features(mpcg_ctx *c, const mpcg_csr *A, const double *b, int32
     mpcg_features_t f{};
     f.n = A->n;
     f.m = A->nnz;
-    rc = pseudo_diameter(c, p, &f);
+    rc = pseudo_diameter(c->main, p, &f);
     if (rc != MPCG_OK) return rc;
     DevState s;
     rc = fp32_prefix(c, p, b, k0, &s);
@@ -557,23 +608,45 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
     if (!dponly) {
         float *x32 = p.at<float>(p.L.x32), *r32 = p.at<float>(p.L.r32), *q32 = p.at<float>(p.L.q32);
         float *dA32 = p.at<float>(p.L.dA32), *dB32 = p.at<float>(p.L.dB32);
+        const float *x32_src = x32;   // x~ handed to the FP64 restart
         bool broke = false;
         if (autoe) {
-            HIPCHK(hipEventRecord(c->tm[1], c->stream));
+            // Algorithm II.  The 2BFS runs on the side stream from a host
+            // thread.  Meanwhile the main stream does the k0-iteration prefix
+            // (v) and then keeps iterating the same FP32 recurrence, copying x~
+            // the first time sqrt(gamma) drops below each candidate eps1 * ||b||.
+            // Once kNN has chosen eps1 the state at that first crossing -- the
+            // state Algorithm II stops in -- is taken from its copy.
             mpcg_features_t f{};
             f.n = n;
             f.m = A->nnz;
-            rc = pseudo_diameter(c, p, &f);
+            mpcg_status rc_bfs = MPCG_OK;
+            std::atomic<int> bfs_done{0};
+            std::thread bfs_thread([&]() {
+                (void)hipSetDevice(c->device);
+                (void)hipEventRecord(c->tm[1], c->side.s);
+                rc_bfs = pseudo_diameter(c->side, p, &f);
+                (void)hipEventRecord(c->tm[2], c->side.s);
+                (void)hipEventSynchronize(c->tm[2]);
+                bfs_done.store(1);
+            });
+            DevState sp0;
+            rc = fp32_prefix(c, p, b, c->opt.k0, &sp0);
+            s = sp0;
+            int it_next = sp0.iter;
+            broke = (sp0.reason == kNotSpd || sp0.reason == kNonFinite);
+            if (rc == MPCG_OK && sp0.bnorm2 > 0.0 && !broke) {
+                launch_set_spec(c->stream, p.st, abs_tol ? 1.0 : std::sqrt(sp0.bnorm2), sp0.iter, maxit1);
+                rc = cg_loop<float>(c, p, x32, r32, q32, dA32, dB32, sp0.iter, 0, &s, &bfs_done, &it_next);
+            }
+            bfs_thread.join();
+            if (rc == MPCG_OK) rc = rc_bfs;
             if (rc != MPCG_OK) { S.status = rc; if (stats) *stats = S; return rc; }
-            HIPCHK(hipEventRecord(c->tm[2], c->stream));
             feat_timed = true;
-            rc = fp32_prefix(c, p, b, c->opt.k0, &s);
-            if (rc != MPCG_OK) { S.status = rc; if (stats) *stats = S; return rc; }
-            if (s.bnorm2 == 0.0) goto zero_rhs;
-            f.k0_used = s.iter;
-            f.v = v_from_ratios(s, s.iter);
+            if (sp0.bnorm2 == 0.0) goto zero_rhs;
+            f.k0_used = sp0.iter;
+            f.v = v_from_ratios(sp0, sp0.iter);
             S.feat = f;
-            broke = (s.reason == kNotSpd || s.reason == kNonFinite);
             const double chi[4] = {(double)f.n, (double)f.m, (double)f.pdiam, f.v};
             int32_t exact = 0;
             const int cls = knn_select(c->model, chi, c->opt.knn_k, &exact);
@@ -583,12 +656,23 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
             S.eps1_used = e1;
             if (exact) S.flags |= MPCG_FLAG_KNN_EXACT;
             if (!broke) {
-                const double thr1 = abs_tol ? e1 : e1 * std::sqrt(s.bnorm2);
-                // continue the same recurrence from iteration k0 (Remark 3)
-                launch_set_phase(c->stream, p.st, thr1, maxit1, c->opt.k0);
-                HIPCHK(hipGetLastError());
-                rc = cg_loop<float>(c, p, x32, r32, q32, dA32, dB32, s.iter, 0, &s);
-                if (rc != MPCG_OK) return rc;
+                const int ci = cls - 2;
+                if (s.cross_iter[ci] >= 0) {
+                    // crossed during the run-ahead: restart from the copy
+                    x32_src = p.at<float>(p.L.snap32) + (size_t)ci * p.n;
+                    s.iter = s.cross_iter[ci];
+                    s.gamma = s.cross_gamma[ci];
+                    s.reason = kConverged;
+                } else if (s.live) {
+                    // not there yet: continue with the chosen tolerance (Remark 3)
+                    const double thr1 = abs_tol ? e1 : e1 * std::sqrt(sp0.bnorm2);
+                    launch_set_phase(c->stream, p.st, thr1, maxit1, c->opt.k0);
+                    HIPCHK(hipGetLastError());
+                    rc = cg_loop<float>(c, p, x32, r32, q32, dA32, dB32, it_next, 0, &s);
+                    if (rc != MPCG_OK) return rc;
+                }
+                // otherwise the run-ahead stopped (breakdown or maxit1) before
+                // reaching eps1: s already holds that stop
             }
         } else {
             launch_init32(c->stream, b, x32, r32, dA32, p.n, eps1, abs_tol, maxit1, 0, p.sp, p.st);
@@ -606,7 +690,7 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
         S.relres_sp = std::sqrt(s.gamma) / bnorm;
         HIPCHK(hipEventRecord(c->tm[3], c->stream));
         // restart in FP64 from float64(x~) with a freshly computed residual
-        run_restart(c->stream, p, x32, x, b, r64, dA64, dB64, 0, eps2, abs_tol, maxit2);
+        run_restart(c->stream, p, x32_src, x, b, r64, dA64, dB64, 0, eps2, abs_tol, maxit2);
         HIPCHK(hipGetLastError());
     } else {
         // FP64-only CG from x0 = 0 through the restart kernel: r = b - A*0 = b
@@ -658,10 +742,9 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
     S.t_total_ms = elapsed(c->tm[0], c->tm[4]);
     S.t_dp_ms = elapsed(c->tm[3], c->tm[4]);
     S.t_sp_ms = dponly ? 0.0 : elapsed(c->tm[0], c->tm[3]);
-    if (feat_timed) {
-        S.t_feat_ms = elapsed(c->tm[1], c->tm[2]);
-        S.t_sp_ms -= S.t_feat_ms;
-    }
+    // the 2BFS overlaps the FP32 phase (side stream), so t_sp_ms is the main
+    // stream's time from the start of the call to the restart
+    if (feat_timed) S.t_feat_ms = elapsed(c->tm[1], c->tm[2]);
     if (S.n1 > 0 && S.n2 > 0 && S.t_dp_ms > 0.0)
         S.omega_measured = (S.t_sp_ms / S.n1) / (S.t_dp_ms / S.n2);
     S.I_third = S.n1 / 3.0 + S.n2;
@@ -709,7 +792,7 @@ mpcg_status mpcg_bfs(mpcg_ctx *c, const mpcg_csr *A, int64_t src, int32_t *dist,
     BfsBufs bb = bfs_bufs(p);
     launch_bfs_seed_single(c->stream, bb, (int32_t)src);
     DevState s;
-    rc = bfs_run(c, p, bb, &s);
+    rc = bfs_run(c->main, p, bb, &s);
     if (rc != MPCG_OK) return rc;
     HIPCHK(hipMemcpyAsync(dist, bb.dist, sizeof(int32_t) * (size_t)p.n, hipMemcpyDeviceToDevice,
                           c->stream));

@@ -228,6 +228,7 @@ __global__ void k_set_phase(DevState *st, double thr, int32_t maxit, int32_t k0r
         st->thr = thr;
         st->maxit = maxit;
         st->k0rec = k0rec;
+        st->spec_on = 0;
         st->live = 1;
         st->reason = kRunning;
     }
@@ -236,6 +237,29 @@ __global__ void k_set_phase(DevState *st, double thr, int32_t maxit, int32_t k0r
 void launch_set_phase(hipStream_t s, DevState *st, double thr, int32_t maxit, int32_t k0rec)
 {
     hipLaunchKernelGGL(k_set_phase, dim3(1), dim3(64), 0, s, st, thr, maxit, k0rec);
+}
+
+__global__ void k_set_spec(DevState *st, double scale, int32_t k0, int32_t maxit)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double eps[kNumEps] = {1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7};
+        for (int t = 0; t < kNumEps; ++t) {
+            st->spec_thr[t] = eps[t] * scale;
+            st->cross_iter[t] = -1;
+            st->cross_gamma[t] = 0.0;
+        }
+        st->spec_k0 = k0;
+        st->spec_on = 1;
+        st->thr = st->spec_thr[kNumEps - 1];   // no candidate is tighter: stop there at the latest
+        st->maxit = maxit;
+        st->live = 1;
+        st->reason = kRunning;
+    }
+}
+
+void launch_set_spec(hipStream_t s, DevState *st, double scale, int32_t k0, int32_t maxit)
+{
+    hipLaunchKernelGGL(k_set_spec, dim3(1), dim3(64), 0, s, st, scale, k0, maxit);
 }
 
 // Measurement set-up: a live recurrence that no test can stop, finite partials.
@@ -288,6 +312,8 @@ struct SpmvArgs {
     // plain
     const T *xin;
     T *yout;
+    const T *xs;       // x~ and the snapshot copies (run-ahead, FP32 only)
+    T *snap;
     double *part;      // this kernel's partials
     DevState *st;
 };
@@ -332,6 +358,21 @@ __global__ void __launch_bounds__(kBlock) k_spmv(SpmvArgs<T> a)
                     st->iter = it;
                     st->reason = conv ? kConverged : kMaxit;
                     st->live = 0;
+                }
+            }
+            const unsigned cross = a.snap ? spec_crossings(st, it, g) : 0u;
+            if (cross) {
+                const int lb0 = xcd_remap(blockIdx.x, gridDim.x);
+                const int r0 = (int)((int64_t)lb0 * a.ntiles / gridDim.x) * a.R;
+                const int r1 = min((int)((int64_t)(lb0 + 1) * a.ntiles / gridDim.x) * a.R, a.n);
+                for (int t = 0; t < kNumEps; ++t) {
+                    if (!(cross & (1u << t))) continue;
+                    T *dst = a.snap + (size_t)t * a.n;
+                    for (int i = r0 + tid; i < r1; i += kBlock) dst[i] = a.xs[i];
+                    if (blockIdx.x == 0 && tid == 0) {
+                        st->cross_iter[t] = it;
+                        st->cross_gamma[t] = g;
+                    }
                 }
             }
             if (conv || cap) return;
@@ -445,10 +486,10 @@ static SpmvArgs<T> spmv_args(const SpmvShape &sh, const int32_t *rp, const int32
 template <typename T>
 void launch_cg_spmv(hipStream_t s, const SpmvShape &sh, const int32_t *rp, const int32_t *col,
                     const T *val, const T *r, T *dA, T *dB, T *q, const double *up, int nup,
-                    double *part, int it, int it0, DevState *st)
+                    double *part, int it, int it0, const T *x, T *snap, DevState *st)
 {
     SpmvArgs<T> a = spmv_args<T>(sh, rp, col, val);
-    a.it = it; a.it0 = it0;
+    a.it = it; a.it0 = it0; a.xs = x; a.snap = snap;
     a.r = r; a.dA = dA; a.dB = dB; a.q = q; a.up = up; a.nup = nup; a.part = part; a.st = st;
     hipLaunchKernelGGL((k_spmv<kModeCg, T>), dim3(sh.grid), dim3(kBlock), 0, s, a);
 }
@@ -554,10 +595,12 @@ void launch_cg_update(hipStream_t s, int32_t n, T *x, T *r, const T *q, const T 
 
 template void launch_cg_spmv<float>(hipStream_t, const SpmvShape &, const int32_t *, const int32_t *,
                                     const float *, const float *, float *, float *, float *,
-                                    const double *, int, double *, int, int, DevState *);
+                                    const double *, int, double *, int, int, const float *, float *,
+                                    DevState *);
 template void launch_cg_spmv<double>(hipStream_t, const SpmvShape &, const int32_t *, const int32_t *,
                                      const double *, const double *, double *, double *, double *,
-                                     const double *, int, double *, int, int, DevState *);
+                                     const double *, int, double *, int, int, const double *, double *,
+                                     DevState *);
 template void launch_cg_update<float>(hipStream_t, int32_t, float *, float *, const float *,
                                       const float *, const float *, const double *, int, double *, int,
                                       DevState *);

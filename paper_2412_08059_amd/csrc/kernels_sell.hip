@@ -77,8 +77,9 @@ __device__ inline int sell_xcd_remap(int b, int nb)
 __global__ void __launch_bounds__(kBlock)
 k_ingest_rows(const void *rp_in, int rp_is_i64, const int32_t *__restrict__ col,
               const double *__restrict__ b, int32_t n, int64_t nnz, int32_t nslices,
-              int32_t *__restrict__ rp32_out, int64_t *__restrict__ wid, DevState *st)
+              int32_t *__restrict__ rp32_out, int64_t *__restrict__ wid, int32_t *__restrict__ blk)
 {
+    __shared__ int sm[3][kBlock / 64];
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int err = 0, len = 0, band = 0;
     if (i < n) {
@@ -116,20 +117,63 @@ k_ingest_rows(const void *rp_in, int rp_is_i64, const int32_t *__restrict__ col,
         const int ob = __shfl_xor(band, off, 64);
         band = band > ob ? band : ob;
     }
+    // per-block statistics; the scan kernel folds them (no same-address atomics)
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         const int64_t s = i >> 6;
         if (s < nslices) wid[s] = (int64_t)len * 64;
-        if (err) atomicOr(&st->ing_err, err);
-        atomicMax(&st->max_row, len);
-        atomicMax(&st->max_band, band);
+        sm[0][w] = err;
+        sm[1][w] = len;
+        sm[2][w] = band;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int e = 0, l = 0, bd = 0;
+        for (int j = 0; j < kBlock / 64; ++j) {
+            e |= sm[0][j];
+            l = l > sm[1][j] ? l : sm[1][j];
+            bd = bd > sm[2][j] ? bd : sm[2][j];
+        }
+        blk[3 * blockIdx.x] = e;
+        blk[3 * blockIdx.x + 1] = l;
+        blk[3 * blockIdx.x + 2] = bd;
     }
 }
 
-// exclusive scan of the padded slice sizes (one block), off[nslices] = total
-__global__ void __launch_bounds__(1024) k_sell_scan(const int64_t *wid, int32_t nslices, int64_t *off)
+// exclusive scan of the padded slice sizes (one block), off[nslices] = total;
+// also folds the per-block ingest statistics into the device state
+__global__ void __launch_bounds__(1024)
+k_sell_scan(const int64_t *wid, int32_t nslices, int64_t *off, const int32_t *blk, int32_t nblk,
+            DevState *st)
 {
     __shared__ int64_t part[1024];
+    __shared__ int fold[3][1024];
     const int t = threadIdx.x;
+    {
+        int e = 0, l = 0, bd = 0;
+        for (int i = t; i < nblk; i += 1024) {
+            e |= blk[3 * i];
+            l = l > blk[3 * i + 1] ? l : blk[3 * i + 1];
+            bd = bd > blk[3 * i + 2] ? bd : blk[3 * i + 2];
+        }
+        fold[0][t] = e;
+        fold[1][t] = l;
+        fold[2][t] = bd;
+        __syncthreads();
+        for (int d = 512; d > 0; d >>= 1) {
+            if (t < d) {
+                fold[0][t] |= fold[0][t + d];
+                fold[1][t] = fold[1][t] > fold[1][t + d] ? fold[1][t] : fold[1][t + d];
+                fold[2][t] = fold[2][t] > fold[2][t + d] ? fold[2][t] : fold[2][t + d];
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
+            st->ing_err |= fold[0][0];
+            st->max_row = fold[1][0];
+            st->max_band = fold[2][0];
+        }
+    }
     const int per = (nslices + 1023) / 1024;
     const int a = min(t * per, nslices), b = min(a + per, nslices);
     int64_t sum = 0;
@@ -205,13 +249,14 @@ k_ingest_entries(const int32_t *__restrict__ rp, const int32_t *__restrict__ col
 
 void launch_ingest_sell(hipStream_t s, const void *rp_in, int rp_is_i64, const int32_t *rp32,
                         int32_t *rp32_out, const int32_t *col, const double *val, const double *b,
-                        int32_t n, int64_t nnz, int64_t *wid, int64_t *off, int64_t cap, int allow_fill,
-                        void *scol, double *sv64, float *sv32, DevState *st)
+                        int32_t n, int64_t nnz, int64_t *wid, int64_t *off, int32_t *blk, int64_t cap,
+                        int allow_fill, void *scol, double *sv64, float *sv32, DevState *st)
 {
     const int nslices = (n + 63) / 64;
-    hipLaunchKernelGGL(k_ingest_rows, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, rp_in, rp_is_i64,
-                       col, b, n, nnz, nslices, rp32_out, wid, st);
-    hipLaunchKernelGGL(k_sell_scan, dim3(1), dim3(1024), 0, s, wid, nslices, off);
+    const int nblk = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_ingest_rows, dim3(nblk), dim3(kBlock), 0, s, rp_in, rp_is_i64, col, b, n, nnz,
+                       nslices, rp32_out, wid, blk);
+    hipLaunchKernelGGL(k_sell_scan, dim3(1), dim3(1024), 0, s, wid, nslices, off, blk, nblk, st);
     int g = (nslices + 3) / 4;
     if (g > 8192) g = 8192;
     hipLaunchKernelGGL(k_ingest_entries, dim3(g), dim3(kBlock), 0, s, rp32, col, val, n, nslices, off, cap,
@@ -242,6 +287,8 @@ struct SellArgs {
     double *dzA, *dzB;
     const T *xin;
     T *yout;
+    const T *xs;
+    T *snap;
     double *part;
     DevState *st;
 };
@@ -279,6 +326,21 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
                     st->iter = it;
                     st->reason = conv ? kConverged : kMaxit;
                     st->live = 0;
+                }
+            }
+            const unsigned cross = a.snap ? spec_crossings(st, it, g) : 0u;
+            if (cross) {
+                const int lb0 = sell_xcd_remap(blockIdx.x, gridDim.x);
+                const int r0 = (int)((int64_t)lb0 * a.nslices / gridDim.x) * 64;
+                const int r1 = min((int)((int64_t)(lb0 + 1) * a.nslices / gridDim.x) * 64, a.n);
+                for (int t = 0; t < kNumEps; ++t) {
+                    if (!(cross & (1u << t))) continue;
+                    T *dst = a.snap + (size_t)t * a.n;
+                    for (int i = r0 + tid; i < r1; i += kBlock) dst[i] = a.xs[i];
+                    if (blockIdx.x == 0 && tid == 0) {
+                        st->cross_iter[t] = it;
+                        st->cross_gamma[t] = g;
+                    }
                 }
             }
             if (conv || cap) return;
@@ -379,10 +441,12 @@ template <> const double *sell_vals<double>(const SellMat &m) { return m.v64; }
 
 template <typename T>
 void launch_sell_cg_spmv(hipStream_t s, const SellMat &m, const T *r, T *dA, T *dB, T *q,
-                         const double *up, int nup, double *part, int it, int it0, DevState *st)
+                         const double *up, int nup, double *part, int it, int it0, const T *x, T *snap,
+                         DevState *st)
 {
     SellArgs<T> a = sell_args<T>(m, sell_vals<T>(m));
     a.it = it; a.it0 = it0; a.r = r; a.dA = dA; a.dB = dB; a.q = q; a.up = up; a.nup = nup;
+    a.xs = x; a.snap = snap;
     a.part = part; a.st = st;
     sell_launch<kSellCg, T>(s, m, a);
 }
@@ -414,10 +478,11 @@ void launch_sell_plain(hipStream_t s, const SellMat &m, const T *x, T *y)
 }
 
 template void launch_sell_cg_spmv<float>(hipStream_t, const SellMat &, const float *, float *, float *,
-                                         float *, const double *, int, double *, int, int, DevState *);
+                                         float *, const double *, int, double *, int, int, const float *,
+                                         float *, DevState *);
 template void launch_sell_cg_spmv<double>(hipStream_t, const SellMat &, const double *, double *,
                                           double *, double *, const double *, int, double *, int, int,
-                                          DevState *);
+                                          const double *, double *, DevState *);
 template void launch_sell_plain<float>(hipStream_t, const SellMat &, const float *, float *);
 template void launch_sell_plain<double>(hipStream_t, const SellMat &, const double *, double *);
 

@@ -15,6 +15,7 @@ constexpr int kBlock = 256;           // threads per block of every multi-block 
 constexpr int kVecPerThread = 4;      // elements per thread in the vector kernels
 constexpr int kVecTile = kBlock * kVecPerThread;
 constexpr int kK0Max = 64;            // longest FP32 prefix recorded for v
+constexpr int kNumEps = 6;            // eps1 candidates 1e-2 ... 1e-7
 constexpr int kLdsBytes = 32768;      // LDS staging per SpMV block (val + gathered x)
 constexpr int kBfsSmallCap = 4096;    // frontier size handled by the one-workgroup BFS kernel
 constexpr int kBfsSmallThreads = 1024;
@@ -66,6 +67,13 @@ struct alignas(256) DevState {
     uint32_t tk_bfs;
     int32_t ncomp;
     uint64_t comp_best;   // (ecc << 32) | ~component of the best component
+    // Algorithm II run-ahead: while the features are computed, the FP32
+    // recurrence continues and x~ is copied the first time sqrt(gamma_i) drops
+    // below each candidate threshold spec_thr[t] (t = eps1 class - 2), i >= spec_k0.
+    int32_t spec_on, spec_k0;
+    int32_t cross_iter[6];
+    double spec_thr[6];
+    double cross_gamma[6];
     int64_t spare_i64;    // host-side scratch in the pinned mirror
 };
 
@@ -75,7 +83,8 @@ struct Layout {
     size_t x32, r32, q32, dA32, dB32;
     size_t r64, q64, dA64, dB64;
     size_t dist, q0, q1, label, tarr, best;
-    size_t sell_wid, sell_off, sell_col, sell_v64, sell_v32;
+    size_t sell_wid, sell_off, sell_col, sell_v64, sell_v32, ingest_blk;
+    size_t snap32;      // kNumEps copies of x~ taken at the candidate thresholds
     int64_t sell_cap;   // padded entries the SELL arrays can hold
     size_t total;
     int64_t n, nnz;
@@ -103,13 +112,29 @@ struct SellMat {
 Layout plan_layout(int64_t n, int64_t nnz);
 
 
+// Run-ahead test inside the CG product of iteration `it` (FP32 only): returns
+// the mask of candidate thresholds first crossed at this iteration (the same in
+// every block) and lets block 0 record them; blocks then copy their rows of x~.
+__device__ inline unsigned spec_crossings(DevState *st, int it, double g)
+{
+    if (!st->spec_on || it < st->spec_k0) return 0u;
+    unsigned mask = 0u;
+    const double rg = sqrt(g);
+    for (int t = 0; t < kNumEps; ++t) {
+        const int ci = st->cross_iter[t];   // -1, an earlier iteration, or `it` (block 0, this kernel)
+        const bool before = ci >= 0 && ci < it;
+        if (!before && rg <= st->spec_thr[t]) mask |= 1u << t;
+    }
+    return mask;
+}
+
 // ----- launch wrappers (kernels_cg.hip) -----
 // Validate A (and b), convert int64 row pointers, and build the SELL-64 copy
 // when its padded size fits in `cap` entries (see kernels_sell.hip).
 void launch_ingest_sell(hipStream_t s, const void *rp_in, int rp_is_i64, const int32_t *rp32,
                         int32_t *rp32_out, const int32_t *col, const double *val, const double *b,
-                        int32_t n, int64_t nnz, int64_t *wid, int64_t *off, int64_t cap, int allow_fill,
-                        void *scol, double *sv64, float *sv32, DevState *st);
+                        int32_t n, int64_t nnz, int64_t *wid, int64_t *off, int32_t *blk, int64_t cap,
+                        int allow_fill, void *scol, double *sv64, float *sv32, DevState *st);
 void launch_cast32(hipStream_t s, const double *val, float *val32, int64_t nnz);
 void launch_fill_f64(hipStream_t s, double *p, int64_t n, double v);
 void launch_fill_f32(hipStream_t s, float *p, int64_t n, float v);
@@ -117,6 +142,8 @@ void launch_fill_i32(hipStream_t s, int32_t *p, int64_t n, int32_t v);
 void launch_init32(hipStream_t s, const double *b, float *x, float *r, float *dA, int32_t n,
                    double eps, int abs_tol, int32_t maxit, int32_t k0rec, double *part, DevState *st);
 void launch_set_phase(hipStream_t s, DevState *st, double thr, int32_t maxit, int32_t k0rec);
+// Start the run-ahead: thresholds eps_t * scale, first test at iteration k0.
+void launch_set_spec(hipStream_t s, DevState *st, double scale, int32_t k0, int32_t maxit);
 void launch_timing_state(hipStream_t s, DevState *st, double *part, int cnt);
 // CG iteration `it` of a phase that started at `it0`: product kernel (reads the
 // update partials `up`, writes its own to `part`) and update kernel (reads
@@ -124,7 +151,7 @@ void launch_timing_state(hipStream_t s, DevState *st, double *part, int cnt);
 template <typename T>
 void launch_cg_spmv(hipStream_t s, const SpmvShape &sh, const int32_t *rp, const int32_t *col,
                     const T *val, const T *r, T *dA, T *dB, T *q, const double *up, int nup,
-                    double *part, int it, int it0, DevState *st);
+                    double *part, int it, int it0, const T *x, T *snap, DevState *st);
 template <typename T>
 void launch_cg_update(hipStream_t s, int32_t n, T *x, T *r, const T *q, const T *dA, const T *dB,
                       const double *sp, int nsp, double *up, int it, DevState *st);
@@ -146,7 +173,8 @@ void launch_spmv_plain(hipStream_t s, const SpmvShape &sh, const int32_t *rp, co
 // ----- SELL-64 (kernels_sell.hip) -----
 template <typename T>
 void launch_sell_cg_spmv(hipStream_t s, const SellMat &m, const T *r, T *dA, T *dB, T *q,
-                         const double *up, int nup, double *part, int it, int it0, DevState *st);
+                         const double *up, int nup, double *part, int it, int it0, const T *x, T *snap,
+                         DevState *st);
 void launch_sell_restart(hipStream_t s, const SellMat &m, const float *x32, double *x64,
                          const double *b, double *r, double *dA, double *dB, int it0, double *part,
                          DevState *st);
@@ -167,6 +195,7 @@ struct BfsBufs {
 };
 void launch_bfs_seed_single(hipStream_t s, const BfsBufs &b, int32_t src);
 void launch_bfs_round(hipStream_t s, const BfsBufs &b, int levels);
+
 void launch_cc(hipStream_t s, const BfsBufs &b);
 void launch_bfs_seed_roots(hipStream_t s, const BfsBufs &b);
 void launch_comp_argmax(hipStream_t s, const BfsBufs &b, int second_sweep);
