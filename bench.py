@@ -44,6 +44,27 @@ def kernel_bytes(kind: str, n: int, m: int) -> float:
     return (s + 4) * m + 4 * (n + 1) + 2 * s * n
 
 
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed PMC summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain-copy calibration), or None
+    when the summary is for another workload or the kernel's source file has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic_varcoef3d_128.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        k = rec["kernels"][kernel]
+        if rec.get("workload") != workload:
+            return None
+        with open(os.path.join(ROOT, k["source"]), "rb") as f:
+            if hashlib.sha1(f.read()).hexdigest() != k["source_sha1"]:
+                return None
+        return float(k["bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(a, b, n1, n2, n_dp):
     """The oracle (scalar C, one thread) on a bounded sample of the same
     workload, extrapolated to a time-to-1e-10 with the GPU's iteration counts."""
@@ -89,6 +110,9 @@ def main():
     ap.add_argument("--model", default=None, help="kNN model file (default: the packaged one)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="for PMC runs: a 1 GiB device copy (counter calibration) and 20 launches of "
+                         "each CG kernel on the workload, nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the single-system solve "
@@ -114,6 +138,18 @@ def main():
     solver = Solver(n, m, model=model if have_model else None)
     A = DeviceCSR.from_host(a)
     B = torch.from_numpy(b).cuda()
+    if args.kernel_only:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        for kid in (capi.MPCG_KERNEL_CG_SPMV_F64, capi.MPCG_KERNEL_UPDATE_F64, capi.MPCG_KERNEL_CG_SPMV_F32,
+                    capi.MPCG_KERNEL_UPDATE_F32):
+            capi.mpcg_time_kernel(solver.ctx, A.desc, kid, 20)
+        solver.close()
+        print(json.dumps({"kernel_only": True, "copy_bytes": 1 << 30}))
+        return
     X = torch.empty(n, dtype=torch.float64, device="cuda")
     eps1 = capi.MPCG_EPS1_AUTO if have_model else 1e-4
     torch.cuda.synchronize()
@@ -165,8 +201,10 @@ def main():
              "cg_spmv_f64": sm.n2 * kt["cg_spmv_f64"], "update_f64": sm.n2 * kt["update_f64"]}
     dom = max(share, key=share.get)
     dom_gbs = kernels[dom]["GBs"]
+    traffic = measured_traffic(dom, f"varcoef3d {args.grid}^3 seed {args.seed}")
     roofline = {"bound": "hbm", "kernel": dom, "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(dom_gbs / HBM_PEAK_GBS, 3), "traffic": None,
+                "frac": round(dom_gbs / HBM_PEAK_GBS, 3),
+                "traffic": None if traffic is None else int(traffic),
                 "bytes_per_launch": kernels[dom]["bytes"], "us_per_launch": kernels[dom]["us"]}
 
     sweep = None

@@ -56,11 +56,29 @@ __device__ inline double sell_reduce_partials(const double *p, int cnt, double *
     return s;
 }
 
-__device__ inline int sell_xcd_remap(int b, int nb)
+// Slice groups (kBlock / 64 slices, one per wave) of an XCD's contiguous
+// range are dealt round-robin to that XCD's blocks: at any moment the blocks
+// of one XCD work on a narrow window of consecutive rows, so the rows that a
+// stencil's neighbour planes gather are still in that XCD's L2.
+struct SliceWalk {
+    int g, g_end, step;   // group index, end, stride
+};
+
+__device__ inline SliceWalk slice_walk(int nslices)
 {
-    const int q = nb / kNumXcd, rem = nb % kNumXcd;
-    const int x = b % kNumXcd, i = b / kNumXcd;
-    return x * q + (x < rem ? x : rem) + i;
+    constexpr int per = kBlock / 64;
+    const int ngroups = (nslices + per - 1) / per;
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int nx = nb < kNumXcd ? nb : kNumXcd;           // XCDs that hold blocks
+    const int q = nb / nx, rem = nb % nx;
+    const int x = b % nx, i = b / nx;
+    const int bx = q + (x < rem ? 1 : 0);                 // blocks on this XCD (>= 1)
+    const int64_t before = (int64_t)x * q + (x < rem ? x : rem);
+    SliceWalk w;                                          // groups in proportion to blocks
+    w.g = (int)(before * ngroups / nb) + i;
+    w.g_end = (int)((before + bx) * ngroups / nb);
+    w.step = bx;
+    return w;
 }
 
 // ------------------------------------------------------------- ingest --
@@ -330,13 +348,14 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
             }
             const unsigned cross = a.snap ? spec_crossings(st, it, g) : 0u;
             if (cross) {
-                const int lb0 = sell_xcd_remap(blockIdx.x, gridDim.x);
-                const int r0 = (int)((int64_t)lb0 * a.nslices / gridDim.x) * 64;
-                const int r1 = min((int)((int64_t)(lb0 + 1) * a.nslices / gridDim.x) * 64, a.n);
+                // copy x~ for the rows of this block's slices
                 for (int t = 0; t < kNumEps; ++t) {
                     if (!(cross & (1u << t))) continue;
                     T *dst = a.snap + (size_t)t * a.n;
-                    for (int i = r0 + tid; i < r1; i += kBlock) dst[i] = a.xs[i];
+                    for (SliceWalk w = slice_walk(a.nslices); w.g < w.g_end; w.g += w.step) {
+                        const int r0 = w.g * kBlock, r1 = min(r0 + kBlock, a.n);
+                        if (r0 + tid < r1) dst[r0 + tid] = a.xs[r0 + tid];
+                    }
                     if (blockIdx.x == 0 && tid == 0) {
                         st->cross_iter[t] = it;
                         st->cross_gamma[t] = g;
@@ -351,13 +370,13 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
     }
 
     const IDX *scol = static_cast<const IDX *>(a.scol);
-    const int lb = sell_xcd_remap(blockIdx.x, gridDim.x);
-    const int s0 = (int)((int64_t)lb * a.nslices / gridDim.x);
-    const int s1 = (int)((int64_t)(lb + 1) * a.nslices / gridDim.x);
+    const int lb = blockIdx.x;   // partial slot (fixed per block, so sums keep one order)
     double s[NV];
     for (int j = 0; j < NV; ++j) s[j] = 0.0;
 
-    for (int sl = s0 + wv; sl < s1; sl += kBlock / 64) {
+    for (SliceWalk w = slice_walk(a.nslices); w.g < w.g_end; w.g += w.step) {
+        const int sl = w.g * (kBlock / 64) + wv;
+        if (sl >= a.nslices) continue;
         const int row = sl * 64 + lane;
         const bool has = row < a.n;
         const int len = has ? a.rp[row + 1] - a.rp[row] : 0;

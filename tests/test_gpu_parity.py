@@ -386,3 +386,30 @@ def test_full_size_config3_pseudo_diameter(solver, torch_mod, name):
     assert (f.pdiam, f.bfs_t, f.bfs_u, f.n_components) == ref
     if name == "banded_1M":
         assert ref == (125_000, 999_993, 0, 1)
+
+
+@pytest.mark.parametrize("name", ["config1_poisson2d_64", "varcoef3d_40"])
+@pytest.mark.parametrize("t", [3, 4, 5, 6, 7])
+def test_algorithm2_runahead_equals_algorithm1_bitwise(torch_mod, tmp_path, name, t):
+    """With the class forced to t, Algorithm II (2BFS beside the FP32 phase,
+    x~ copied at the first crossing of each candidate) must land on the state
+    Algorithm I with eps1 = 10^-t stops in, whenever that stop is at or after
+    the k0 = 20 prefix: same N1, N2 and the same x bit for bit."""
+    from paper_2412_08059_amd import Solver
+    a = W.poisson2d(64) if name.startswith("config1") else W.varcoef3d(40, seed=5)
+    _, b = W.rhs(a, seed=11)
+    mpath = tmp_path / f"one_class_{t}.txt"
+    oracle.save_model(oracle.KnnModel.from_samples(np.array([[1.0, 1, 1, 1], [2.0, 2, 2, 2]]), [t, t], k=1),
+                      str(mpath))
+    s = Solver(a.n, a.nnz, model=str(mpath))
+    A, B = dev(a), t64(torch_mod, b)
+    st2, x2, s2 = s.solve(A, B, 0.0, 1e-10)
+    x2 = x2.cpu().numpy()
+    st1, x1, s1 = s.solve(A, B, 10.0 ** -t, 1e-10)
+    s.close()
+    assert st1 == st2 == 0 and s2.eps1_class == t
+    if s1.n1 >= 20:
+        assert (s2.n1, s2.n2) == (s1.n1, s1.n2)
+        assert np.array_equal(x2, x1.cpu().numpy())
+    else:
+        assert s2.n1 == 20   # the prefix already passed eps1; Algorithm II stops after it
