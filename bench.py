@@ -35,11 +35,12 @@ def kernel_bytes(kind: str, n: int, m: int) -> float:
     x-gather counted once per vector, i.e. perfect reuse)."""
     s = 8 if kind.endswith("64") else 4
     if kind.startswith("cg_spmv"):
-        # val + col, row pointers, gather of r and d_old, writes of d_new and q
-        return (s + 4) * m + 4 * (n + 1) + 4 * s * n
+        # val + col, row pointers, gathers of r and d_old, x read and written
+        # (the previous iteration's x += alpha d), writes of d_new and q
+        return (s + 4) * m + 4 * (n + 1) + 6 * s * n
     if kind.startswith("update"):
-        # reads x, r, q, d_new; writes x, r
-        return 6 * s * n
+        # reads r, q; writes r
+        return 3 * s * n
     # plain y = A x
     return (s + 4) * m + 4 * (n + 1) + 2 * s * n
 

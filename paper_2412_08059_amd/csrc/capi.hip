@@ -39,6 +39,9 @@ struct mpcg_ctx {
     bool has_model = false;
     float last_kernel_ms = 0.0f;
     bool force_csr = false;   // MPCG_FORCE_CSR=1: always use the CSR-stream kernels
+    int sell_batch = 4;       // MPCG_SELL_BATCH=4|8: loads in flight per row in the SELL kernels
+    int cg_grid = kMaxGrid;   // MPCG_CG_GRID: most blocks of a CG product launch
+    int up_grid = kUpdateGrid;   // MPCG_UP_GRID: most blocks of a CG update launch
 };
 
 #define HIPCHK(x)                                        \
@@ -189,6 +192,7 @@ mpcg_status ingest(mpcg_ctx *c, const mpcg_csr *A, const double *b, bool need_va
     p->sh64 = spmv_shape(A->n, A->nnz, 8, c->num_cu);
     p->sh32 = spmv_shape(A->n, A->nnz, 4, c->num_cu);
     p->nup = vec_grid(A->n);
+    if (p->nup > c->up_grid) p->nup = c->up_grid;
     if (p->use_sell) {
         SellMat &m = p->sell;
         m.rp = p->rp;
@@ -196,8 +200,9 @@ mpcg_status ingest(mpcg_ctx *c, const mpcg_csr *A, const double *b, bool need_va
         m.n = p->n;
         m.nslices = nsl;
         m.idx16 = s.max_band < 32768 ? 1 : 0;
+        m.batch = c->sell_batch;
         int64_t g = ((int64_t)nsl + kBlock / 64 - 1) / (kBlock / 64);
-        if (g > kMaxGrid) g = kMaxGrid;
+        if (g > c->cg_grid) g = c->cg_grid;
         m.grid = (int32_t)(g < 1 ? 1 : g);
         m.scol = p->ws + p->L.sell_col;
         m.v64 = p->at<double>(p->L.sell_v64);
@@ -224,10 +229,10 @@ template <typename T> T *snap_buf(const Plan &p);
 template <> float *snap_buf<float>(const Plan &p) { return p.at<float>(p.L.snap32); }
 template <> double *snap_buf<double>(const Plan &) { return nullptr; }
 
-// x and snap are used only by the Algorithm II run-ahead (FP32)
+// snap is used only by the Algorithm II run-ahead (FP32)
 template <typename T>
-void run_cg_spmv(hipStream_t s, const Plan &p, const T *r, T *dA, T *dB, T *q, int it, int it0,
-                 const T *x = nullptr, T *snap = nullptr)
+void run_cg_spmv(hipStream_t s, const Plan &p, const T *r, T *dA, T *dB, T *q, int it, int it0, T *x,
+                 T *snap = nullptr)
 {
     if (p.use_sell)
         launch_sell_cg_spmv<T>(s, p.sell, r, dA, dB, q, p.up, p.nup, p.sp, it, it0, x, snap, p.st);
@@ -237,9 +242,9 @@ void run_cg_spmv(hipStream_t s, const Plan &p, const T *r, T *dA, T *dB, T *q, i
 }
 
 template <typename T>
-void run_cg_update(hipStream_t s, const Plan &p, T *x, T *r, const T *q, const T *dA, const T *dB, int it)
+void run_cg_update(hipStream_t s, const Plan &p, T *r, const T *q, int it)
 {
-    launch_cg_update<T>(s, p.n, x, r, q, dA, dB, p.sp, prod_grid(p, sizeof(T) == 4), p.up, it, p.st);
+    launch_cg_update<T>(s, p.n, r, q, p.sp, prod_grid(p, sizeof(T) == 4), p.up, p.nup, it, p.st);
 }
 
 void run_restart(hipStream_t s, const Plan &p, const float *x32, double *x, const double *b, double *r,
@@ -289,7 +294,7 @@ mpcg_status cg_loop(mpcg_ctx *c, const Plan &p, T *x, T *r, T *q, T *dA, T *dB, 
     for (;;) {
         for (int g = 0; g < G; ++g, ++it) {
             run_cg_spmv<T>(ch.s, p, r, dA, dB, q, it, it0, x, snap);
-            run_cg_update<T>(ch.s, p, x, r, q, dA, dB, it);
+            run_cg_update<T>(ch.s, p, r, q, it);
         }
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(ch.poll[k & 1], p.st, sizeof(DevState), hipMemcpyDeviceToHost, ch.s));
@@ -306,9 +311,19 @@ mpcg_status cg_loop(mpcg_ctx *c, const Plan &p, T *x, T *r, T *q, T *dA, T *dB, 
     return read_state(ch, p, out);
 }
 
+int env_int(const char *name, int def)
+{
+    const char *e = std::getenv(name);
+    return (e && e[0]) ? std::atoi(e) : def;
+}
+
 BfsBufs bfs_bufs(const Plan &p)
 {
+    static const int grid = env_int("MPCG_BFS_GRID", kBfsLevelBlocks);
+    static const int precheck = env_int("MPCG_BFS_PRECHECK", 1);
     BfsBufs b{};
+    b.grid = grid > 0 && grid <= 4096 ? grid : kBfsLevelBlocks;
+    b.precheck = precheck ? 1 : 0;
     b.rp = p.rp;
     b.col = p.col;
     b.n = p.n;
@@ -332,8 +347,10 @@ BfsBufs bfs_bufs(const Plan &p)
 mpcg_status bfs_run(const Chan &ch, const Plan &p, const BfsBufs &bb, DevState *out)
 {
     const int levels = 16;
+    int k = 0;
     for (int64_t round = 0;; ++round) {
-        launch_bfs_round(ch.s, bb, levels);
+        k = launch_bfs_round(ch.s, bb, levels, k);
+        if (k > 0x3fffffff) k &= 1;   // k only selects a parity slot: keep its parity
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(ch.poll[round & 1], p.st, sizeof(DevState), hipMemcpyDeviceToHost, ch.s));
         HIPCHK(hipEventRecord(ch.ev[round & 1], ch.s));
@@ -364,7 +381,7 @@ mpcg_status pseudo_diameter(const Chan &ch, const Plan &p, mpcg_features_t *f)
         launch_bfs_seed_single(ch.s, bb, t);
         rc = bfs_run(ch, p, bb, &s);
         if (rc != MPCG_OK) return rc;
-        f->pdiam = s.bfs_level;
+        f->pdiam = s.bfs_ecc;
         f->bfs_t = t;
         f->bfs_u = s.bfs_far;
         f->n_components = 1;
@@ -470,6 +487,12 @@ mpcg_status mpcg_create(mpcg_ctx **out, const mpcg_options *opt, void *hip_strea
     {
         const char *e = std::getenv("MPCG_FORCE_CSR");
         c->force_csr = e && e[0] == '1';
+        const char *bt = std::getenv("MPCG_SELL_BATCH");
+        if (bt && bt[0] == '8') c->sell_batch = 8;
+        const int cgg = env_int("MPCG_CG_GRID", kMaxGrid);
+        c->cg_grid = cgg >= 64 && cgg <= kMaxGrid ? cgg : kMaxGrid;
+        const int upg = env_int("MPCG_UP_GRID", kUpdateGrid);
+        c->up_grid = upg >= 64 && upg <= kMaxGrid ? upg : kUpdateGrid;
     }
     if (hipGetDevice(&c->device) != hipSuccess ||
         hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
@@ -797,7 +820,7 @@ mpcg_status mpcg_bfs(mpcg_ctx *c, const mpcg_csr *A, int64_t src, int32_t *dist,
     HIPCHK(hipMemcpyAsync(dist, bb.dist, sizeof(int32_t) * (size_t)p.n, hipMemcpyDeviceToDevice,
                           c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    if (ecc) *ecc = s.bfs_level;
+    if (ecc) *ecc = s.bfs_ecc;
     if (far) *far = s.bfs_far;
     return MPCG_OK;
 }
@@ -839,16 +862,16 @@ mpcg_status mpcg_time_kernel(mpcg_ctx *c, const mpcg_csr *A, int32_t kernel, int
     auto one = [&]() {
         switch (kernel) {
         case MPCG_KERNEL_CG_SPMV_F64:
-            run_cg_spmv<double>(c->stream, p, r64, dA64, dB64, q64, 1, 0);
+            run_cg_spmv<double>(c->stream, p, r64, dA64, dB64, q64, 1, 0, x64);
             break;
         case MPCG_KERNEL_CG_SPMV_F32:
-            run_cg_spmv<float>(c->stream, p, r32, dA32, dB32, q32, 1, 0);
+            run_cg_spmv<float>(c->stream, p, r32, dA32, dB32, q32, 1, 0, x32);
             break;
         case MPCG_KERNEL_UPDATE_F64:
-            run_cg_update<double>(c->stream, p, x64, r64, q64, dA64, dB64, 1);
+            run_cg_update<double>(c->stream, p, r64, q64, 1);
             break;
         case MPCG_KERNEL_UPDATE_F32:
-            run_cg_update<float>(c->stream, p, x32, r32, q32, dA32, dB32, 1);
+            run_cg_update<float>(c->stream, p, r32, q32, 1);
             break;
         case MPCG_KERNEL_SPMV_F64:
             run_plain<double>(c->stream, p, r64, q64);

@@ -25,21 +25,29 @@ __device__ inline int atomic_load_i32(const int32_t *p)
 
 // ------------------------------------------------------------ seeding --
 
+// Level 0 holds `cnt0` sources (already in queue 0 with distance 0).
+__device__ inline void bfs_start(DevState *st, int cnt0, int min0)
+{
+    st->bfs_lv[0] = 0;
+    st->bfs_lv[1] = 0;
+    st->bfs_cnt[0] = cnt0;
+    st->bfs_min[0] = min0;
+    for (int j = 1; j < 4; ++j) {
+        st->bfs_cnt[j] = 0;
+        st->bfs_min[j] = kIntMax;
+    }
+    st->bfs_done = cnt0 == 0;
+    st->bfs_ecc = 0;
+    st->bfs_far = min0;
+    st->bfs_visited = 0;
+}
+
 __global__ void k_bfs_seed_single(int32_t *dist, int32_t *q0, int32_t src, DevState *st)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         dist[src] = 0;
         q0[0] = src;
-        st->bfs_level = 0;
-        st->bfs_cur = 1;
-        st->bfs_next = 0;
-        st->bfs_parity = 0;
-        st->bfs_done = 0;
-        st->bfs_cur_min = src;
-        st->bfs_next_min = kIntMax;
-        st->bfs_far = src;
-        st->bfs_visited = 1;
-        st->tk_bfs = 0;
+        bfs_start(st, 1, src);
     }
 }
 
@@ -49,33 +57,53 @@ void launch_bfs_seed_single(hipStream_t s, const BfsBufs &b, int32_t src)
     hipLaunchKernelGGL(k_bfs_seed_single, dim3(1), dim3(64), 0, s, b.dist, b.q0, src, b.st);
 }
 
+// Level L was expanded by the previous launch and found nothing: the BFS is
+// done, with the last non-empty level L - 1.
+__device__ inline void bfs_finish(DevState *st, int L)
+{
+    st->bfs_done = 1;
+    st->bfs_ecc = L - 1;
+    st->bfs_far = st->bfs_min[(L - 1) & 3];
+}
+
 // ------------------------------------------------- one-workgroup rounds --
 
 // Runs levels while 0 < frontier <= small_max (<= kBfsSmallCap, chosen so
-// that one pass of the 1024 threads covers the level).  The frontier lives in LDS;
-// the next frontier is also written to the global queue so that the
-// multi-block kernel can take over when it outgrows LDS.
+// that one pass of the 1024 threads covers the level).  The frontier lives in
+// LDS; every level is also written to its global queue so that the
+// multi-block kernel can take over when the frontier outgrows LDS.  A launch
+// that does not run hands its level on unchanged.
 __global__ void __launch_bounds__(kBfsSmallThreads)
 k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int32_t *dist,
-            int32_t *q0, int32_t *q1, int32_t n, int32_t lanes, int32_t small_max, DevState *st)
+            int32_t *q0, int32_t *q1, int32_t n, int32_t lanes, int32_t small_max, int32_t k,
+            DevState *st)
 {
     __shared__ int32_t sq[2][kBfsSmallCap];
-    __shared__ int32_t s_cnt, s_min, s_cur, s_level, s_par, s_go, s_curmin;
+    __shared__ int32_t s_cnt, s_min, s_cur, s_level, s_go, s_curmin;
     __shared__ long long s_vis;
     const int tid = threadIdx.x;
     if (tid == 0) {
-        const int cur = st->bfs_cur;
-        s_go = (!st->bfs_done && cur > 0 && cur <= small_max) ? 1 : 0;
-        s_cur = cur;
-        s_level = st->bfs_level;
-        s_par = st->bfs_parity;
-        s_curmin = st->bfs_cur_min;
-        s_vis = st->bfs_visited;
+        s_go = 0;
+        if (!st->bfs_done) {
+            const int L = st->bfs_lv[k & 1];
+            const int cur = st->bfs_cnt[L & 3];
+            if (cur == 0) {
+                bfs_finish(st, L);
+            } else if (cur > small_max) {
+                st->bfs_lv[(k + 1) & 1] = L;
+            } else {
+                s_go = 1;
+                s_cur = cur;
+                s_level = L;
+                s_curmin = st->bfs_min[L & 3];
+                s_vis = st->bfs_visited;
+            }
+        }
     }
     __syncthreads();
     if (!s_go) return;
     {
-        const int32_t *qc = s_par ? q1 : q0;
+        const int32_t *qc = (s_level & 1) ? q1 : q0;
         for (int i = tid; i < s_cur; i += kBfsSmallThreads) sq[0][i] = qc[i];
     }
     int c = 0;
@@ -85,15 +113,15 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
         if (tid == 0) { s_cnt = 0; s_min = kIntMax; }
         __syncthreads();
         const int cur = s_cur, level = s_level;
-        int32_t *qn = s_par ? q0 : q1;
+        int32_t *qn = (level & 1) ? q0 : q1;
         const int work = cur * lanes;
         for (int w = tid; w < work; w += kBfsSmallThreads) {
             const int f = w / lanes, l = w - f * lanes;
             const int u = sq[c][f];
             if ((unsigned)u >= (unsigned)n) continue;
             const int e = rp[u + 1];
-            for (int k = rp[u] + l; k < e; k += lanes) {
-                const int v = col[k];
+            for (int j = rp[u] + l; j < e; j += lanes) {
+                const int v = col[j];
                 if (v == u || dist[v] >= 0) continue;
                 if (atomicCAS(&dist[v], -1, level + 1) == -1) {
                     const int pos = atomicAdd(&s_cnt, 1);
@@ -105,11 +133,10 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
         }
         __syncthreads();
         const int nxt = s_cnt;
+        if (tid == 0) s_vis += cur;
         if (nxt == 0) { finished = true; break; }
         if (tid == 0) {
-            s_vis += nxt;
             s_level = level + 1;
-            s_par ^= 1;
             s_cur = nxt;
             s_curmin = s_min;
         }
@@ -118,16 +145,18 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
         if (nxt > small_max) break;
     }
     if (tid == 0) {
-        st->bfs_level = s_level;
-        st->bfs_cur = finished ? 0 : s_cur;
-        st->bfs_parity = s_par;
-        st->bfs_cur_min = s_curmin;
+        const int L = s_level;
         st->bfs_visited = s_vis;
-        st->bfs_next = 0;
-        st->bfs_next_min = kIntMax;
         if (finished) {
             st->bfs_done = 1;
+            st->bfs_ecc = L;
             st->bfs_far = s_curmin;
+        } else {
+            st->bfs_cnt[L & 3] = s_cur;
+            st->bfs_min[L & 3] = s_curmin;
+            st->bfs_cnt[(L + 1) & 3] = 0;
+            st->bfs_min[(L + 1) & 3] = kIntMax;
+            st->bfs_lv[(k + 1) & 1] = L;
         }
     }
 }
@@ -152,100 +181,120 @@ __device__ inline int wave_min_i(int v)
 }
 
 // One level, top-down.  `lanes` consecutive lanes share a frontier vertex
-// and take its neighbours in parallel (lane l: entries l, l + lanes, ...);
-// every wave runs a wave-uniform loop so that appends to the next frontier
-// take one atomic per wave and step.
+// and take its neighbours in parallel (lane l: entries l, l + lanes, ...).
+// Each thread takes kBfsItems work items at once and issues their loads
+// together, so a level costs a handful of dependent memory round trips (level
+// and count; frontier vertices; row bounds; columns; claims) whatever its
+// size; the vertices a wave claims in one step are appended with a single
+// atomic.  Block 0 retires the level and clears the counters of the level
+// after next; the next frontier's minimum is folded in with non-returning
+// atomics.
+constexpr int kBfsItems = 4;
+
 __global__ void __launch_bounds__(kBlock)
 k_bfs_level(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int32_t *dist,
-            int32_t *q0, int32_t *q1, int32_t n, int32_t lanes, int32_t small_max, DevState *st)
+            int32_t *q0, int32_t *q1, int32_t n, int32_t lanes, int32_t k, int32_t precheck, DevState *st)
 {
-    const int cur = min(st->bfs_cur, n);
-    if (st->bfs_done || cur <= small_max) return;
-    const int level = st->bfs_level;
-    const int par = st->bfs_parity;
-    const int32_t *qc = par ? q1 : q0;
-    int32_t *qn = par ? q0 : q1;
+    if (st->bfs_done) return;
+    const int L = st->bfs_lv[k & 1];
+    const int cur = min(st->bfs_cnt[L & 3], n);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (cur == 0) {
+            bfs_finish(st, L);
+        } else {
+            st->bfs_visited += cur;
+            st->bfs_lv[(k + 1) & 1] = L + 1;
+            st->bfs_cnt[(L + 2) & 3] = 0;
+            st->bfs_min[(L + 2) & 3] = kIntMax;
+        }
+    }
+    if (cur == 0) return;
+    const int32_t *qc = (L & 1) ? q1 : q0;
+    int32_t *qn = (L & 1) ? q0 : q1;
+    int *cnt_next = &st->bfs_cnt[(L + 1) & 3];
     const int lane = threadIdx.x & 63;
+    const unsigned long long lt = (1ull << lane) - 1ull;
     int wmin = kIntMax;
     const int64_t items = (int64_t)cur * lanes;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t wbase = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); wbase < items; wbase += stride) {
-        const int64_t w = wbase + lane;
-        int u = -1, k = 0, e = 0;
-        if (w < items) {
-            const int f = (int)(w / lanes), l = (int)(w - (int64_t)f * lanes);
-            u = qc[f];
-            if ((unsigned)u < (unsigned)n) {
-                k = rp[u] + l;
-                e = rp[u + 1];
+    const int64_t span = stride * kBfsItems;
+    for (int64_t wbase = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); wbase < items; wbase += span) {
+        int u[kBfsItems], j[kBfsItems], e[kBfsItems];
+#pragma unroll
+        for (int i = 0; i < kBfsItems; ++i) {
+            const int64_t w = wbase + i * stride + lane;
+            u[i] = -1;
+            j[i] = 0;
+            e[i] = 0;
+            if (w < items) u[i] = qc[(int)(w / lanes)];
+        }
+#pragma unroll
+        for (int i = 0; i < kBfsItems; ++i) {
+            if ((unsigned)u[i] < (unsigned)n) {
+                const int64_t w = wbase + i * stride + lane;
+                j[i] = rp[u[i]] + (int)(w % lanes);
+                e[i] = rp[u[i] + 1];
             }
         }
-        int steps = k < e ? (e - k + lanes - 1) / lanes : 0;
+        int steps = 0;
+#pragma unroll
+        for (int i = 0; i < kBfsItems; ++i) {
+            const int si = j[i] < e[i] ? (e[i] - j[i] + lanes - 1) / lanes : 0;
+            steps = steps > si ? steps : si;
+        }
         steps = wave_max_i(steps);
-        for (int j = 0; j < steps; ++j, k += lanes) {
-            int v = -1;
-            bool found = false;
-            if (k < e) {
-                v = col[k];
-                if (v != u && dist[v] < 0) found = (atomicCAS(&dist[v], -1, level + 1) == -1);
+        for (int t = 0; t < steps; ++t) {
+            int v[kBfsItems];
+            bool found[kBfsItems];
+#pragma unroll
+            for (int i = 0; i < kBfsItems; ++i) {
+                v[i] = j[i] < e[i] ? col[j[i]] : -1;
+                j[i] += lanes;
             }
-            const unsigned long long m = __ballot(found);
-            if (m) {
-                const int leader = __ffsll((long long)m) - 1;
-                int base = 0;
-                if (lane == leader) base = atomicAdd(&st->bfs_next, __popcll(m));
-                base = __shfl(base, leader, 64);
-                if (found) {
-                    const int off = __popcll(m & ((1ull << lane) - 1ull));
-                    qn[base + off] = v;
-                    wmin = wmin < v ? wmin : v;
+            if (precheck) {
+#pragma unroll
+                for (int i = 0; i < kBfsItems; ++i)
+                    if (v[i] >= 0 && (v[i] == u[i] || dist[v[i]] >= 0)) v[i] = -1;
+            }
+#pragma unroll
+            for (int i = 0; i < kBfsItems; ++i)
+                found[i] = v[i] >= 0 && v[i] != u[i] && atomicCAS(&dist[v[i]], -1, L + 1) == -1;
+            unsigned long long m[kBfsItems];
+            int total = 0;
+#pragma unroll
+            for (int i = 0; i < kBfsItems; ++i) {
+                m[i] = __ballot(found[i]);
+                total += __popcll(m[i]);
+            }
+            if (total == 0) continue;
+            int base = 0;
+            if (lane == 0) base = atomicAdd(cnt_next, total);
+            base = __shfl(base, 0, 64);
+#pragma unroll
+            for (int i = 0; i < kBfsItems; ++i) {
+                if (found[i]) {
+                    qn[base + __popcll(m[i] & lt)] = v[i];
+                    wmin = wmin < v[i] ? wmin : v[i];
                 }
+                base += __popcll(m[i]);
             }
         }
     }
     wmin = wave_min_i(wmin);
-    // The last block to arrive only needs the two atomic counters, so the
-    // arrival ticket needs no memory fence: every block's counter updates are
-    // returning atomics, complete before its ticket increment is issued.
-    __shared__ int amlast, sink;
-    if (lane == 0 && wmin != kIntMax)
-        sink = __hip_atomic_fetch_min(&st->bfs_next_min, wmin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t t = __hip_atomic_fetch_add(&st->tk_bfs, 1u, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-        amlast = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (amlast && threadIdx.x == 0) {
-        const int nxt = atomic_load_i32(&st->bfs_next);
-        const int nmin = atomic_load_i32(&st->bfs_next_min);
-        if (nxt == 0) {
-            st->bfs_done = 1;
-            st->bfs_cur = 0;
-            st->bfs_far = st->bfs_cur_min;
-        } else {
-            st->bfs_visited += nxt;
-            st->bfs_level = level + 1;
-            st->bfs_cur = nxt;
-            st->bfs_cur_min = nmin;
-            st->bfs_parity = par ^ 1;
-        }
-        st->bfs_next = 0;
-        st->bfs_next_min = kIntMax;
-        __hip_atomic_store(&st->tk_bfs, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (lane == 0 && wmin != kIntMax) atomicMin(&st->bfs_min[(L + 1) & 3], wmin);
 }
 
-void launch_bfs_round(hipStream_t s, const BfsBufs &b, int levels)
+int launch_bfs_round(hipStream_t s, const BfsBufs &b, int levels, int k)
 {
     hipLaunchKernelGGL(k_bfs_small, dim3(1), dim3(kBfsSmallThreads), 0, s, b.rp, b.col, b.dist, b.q0,
-                       b.q1, b.n, b.lanes, b.small_max, b.st);
+                       b.q1, b.n, b.lanes, b.small_max, k, b.st);
+    ++k;
     int grid = (b.n + kBlock - 1) / kBlock;
-    if (grid > kBfsLevelBlocks) grid = kBfsLevelBlocks;
-    for (int l = 0; l < levels; ++l)
+    if (grid > b.grid) grid = b.grid;
+    for (int l = 0; l < levels; ++l, ++k)
         hipLaunchKernelGGL(k_bfs_level, dim3(grid), dim3(kBlock), 0, s, b.rp, b.col, b.dist, b.q0, b.q1,
-                           b.n, b.lanes, b.small_max, b.st);
+                           b.n, b.lanes, k, b.precheck, b.st);
+    return k;
 }
 
 // ------------------------------------------------ connected components --
@@ -318,42 +367,36 @@ __global__ void k_bfs_seed_roots(const int32_t *label, int32_t *dist, int32_t *q
         dist[v] = root ? 0 : -1;
         if (root) {
             best[v] = 0ull;
-            const int pos = atomicAdd(&st->bfs_next, 1);
+            const int pos = atomicAdd(&st->bfs_cnt[0], 1);
             q0[pos] = v;
         }
     }
 }
 
-__global__ void k_bfs_seed_finish(DevState *st, int roots_in_next)
+// The sources were appended to bfs_cnt[0]; their smallest vertex is not
+// needed (components take their own argmax).
+__global__ void k_bfs_seed_finish(DevState *st, int roots)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        const int cnt = st->bfs_next;
-        st->bfs_level = 0;
-        st->bfs_cur = cnt;
-        st->bfs_next = 0;
-        st->bfs_parity = 0;
-        st->bfs_done = cnt == 0;
-        st->bfs_cur_min = 0;
-        st->bfs_next_min = kIntMax;
-        st->bfs_visited = cnt;
-        st->tk_bfs = 0;
-        if (roots_in_next) {
+        const int cnt = st->bfs_cnt[0];
+        bfs_start(st, cnt, 0);
+        if (roots) {
             st->ncomp = cnt;
             st->comp_best = 0ull;
         }
     }
 }
 
-__global__ void k_zero_next(DevState *st)
+__global__ void k_zero_sources(DevState *st)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) st->bfs_next = 0;
+    if (threadIdx.x == 0 && blockIdx.x == 0) st->bfs_cnt[0] = 0;
 }
 
 void launch_bfs_seed_roots(hipStream_t s, const BfsBufs &b)
 {
     int grid = (b.n + kBlock - 1) / kBlock;
     if (grid > 4096) grid = 4096;
-    hipLaunchKernelGGL(k_zero_next, dim3(1), dim3(64), 0, s, b.st);
+    hipLaunchKernelGGL(k_zero_sources, dim3(1), dim3(64), 0, s, b.st);
     hipLaunchKernelGGL(k_bfs_seed_roots, dim3(grid), dim3(kBlock), 0, s, b.label, b.dist, b.q0, b.best,
                        b.n, b.st);
     hipLaunchKernelGGL(k_bfs_seed_finish, dim3(1), dim3(64), 0, s, b.st, 1);
@@ -407,7 +450,7 @@ __global__ void k_bfs_seed_far(const int32_t *label, int32_t *dist, int32_t *q0,
             tarr[v] = t;
             best[v] = 0ull;
             dist[t] = 0;
-            const int pos = atomicAdd(&st->bfs_next, 1);
+            const int pos = atomicAdd(&st->bfs_cnt[0], 1);
             q0[pos] = t;
         }
     }
@@ -418,7 +461,7 @@ void launch_bfs_seed_far(hipStream_t s, const BfsBufs &b)
     int grid = (b.n + kBlock - 1) / kBlock;
     if (grid > 4096) grid = 4096;
     launch_fill_i32(s, b.dist, b.n, -1);
-    hipLaunchKernelGGL(k_zero_next, dim3(1), dim3(64), 0, s, b.st);
+    hipLaunchKernelGGL(k_zero_sources, dim3(1), dim3(64), 0, s, b.st);
     hipLaunchKernelGGL(k_bfs_seed_far, dim3(grid), dim3(kBlock), 0, s, b.label, b.dist, b.q0, b.tarr,
                        b.best, b.n, b.st);
     hipLaunchKernelGGL(k_bfs_seed_finish, dim3(1), dim3(64), 0, s, b.st, 0);

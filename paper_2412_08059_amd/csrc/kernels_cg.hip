@@ -163,6 +163,17 @@ __device__ inline void start_phase(DevState *st, double gamma, int32_t iter, dou
     } else {
         st->live = 1; st->reason = kRunning;
     }
+    st->stop_it = st->live ? kNoStop : iter - 1;   // no product of iteration >= iter runs after a stop
+    st->x_it = iter;
+}
+
+// A phase resumes after a stop in iteration stop_it: x is complete there.
+__device__ inline void resume_phase(DevState *st)
+{
+    st->x_it = st->stop_it != kNoStop ? st->stop_it : -1;
+    st->stop_it = kNoStop;
+    st->live = 1;
+    st->reason = kRunning;
 }
 
 // FP32 phase from x~ = 0: r~ = float32(b), old direction = 0; partials of
@@ -229,8 +240,7 @@ __global__ void k_set_phase(DevState *st, double thr, int32_t maxit, int32_t k0r
         st->maxit = maxit;
         st->k0rec = k0rec;
         st->spec_on = 0;
-        st->live = 1;
-        st->reason = kRunning;
+        resume_phase(st);
     }
 }
 
@@ -252,8 +262,7 @@ __global__ void k_set_spec(DevState *st, double scale, int32_t k0, int32_t maxit
         st->spec_on = 1;
         st->thr = st->spec_thr[kNumEps - 1];   // no candidate is tighter: stop there at the latest
         st->maxit = maxit;
-        st->live = 1;
-        st->reason = kRunning;
+        resume_phase(st);
     }
 }
 
@@ -274,7 +283,11 @@ __global__ void k_timing_state(DevState *st, double *part, int cnt)
         st->iter = 0;
         st->maxit = 0x7fffffff;
         st->k0rec = 0;
+        st->alph[0] = 0.0;
+        st->alph[1] = 0.0;
         st->live = 1;
+        st->stop_it = kNoStop;
+        st->x_it = -1;
         st->reason = kRunning;
     }
 }
@@ -312,8 +325,8 @@ struct SpmvArgs {
     // plain
     const T *xin;
     T *yout;
-    const T *xs;       // x~ and the snapshot copies (run-ahead, FP32 only)
-    T *snap;
+    T *x;              // CG iterate: receives the deferred alpha_{it-1} d_{it-1}
+    T *snap;           // x~ copies at the run-ahead crossings (FP32 only)
     double *part;      // this kernel's partials
     DevState *st;
 };
@@ -334,19 +347,26 @@ __global__ void __launch_bounds__(kBlock) k_spmv(SpmvArgs<T> a)
     DevState *st = a.st;
     const int tid = threadIdx.x;
 
-    T beta = T(0);
+    T beta = T(0), alpha_prev = T(0);
+    bool x_pending = false;   // x += alpha_{it-1} d_{it-1} still to apply in the main loop
     const T *dold = nullptr;
     T *dnew = nullptr;
     if (MODE == kModeCg) {
-        // block 0 may clear st->live during this kernel: take one block-wide reading
-        __shared__ int s_live;
-        if (tid == 0) s_live = st->live;
-        __syncthreads();
-        if (!s_live) return;
         const int it = a.it;
+        __shared__ int s_skip, s_xdone;
+        if (tid == 0) {
+            s_skip = st->stop_it < it;
+            s_xdone = st->x_it == it;
+        }
+        __syncthreads();
+        if (s_skip) return;
+        dold = (it & 1) ? a.dB : a.dA;
+        dnew = (it & 1) ? a.dA : a.dB;
         if (it != a.it0) {
+            const bool xdone = s_xdone;
             const double g = reduce_partials(a.up, a.nup, 1, 0, sm);
             const double gp = st->gam[(it - 1) & 1];
+            alpha_prev = (T)st->alph[(it - 1) & 1];
             const bool conv = sqrt(g) <= st->thr;
             const bool cap = !conv && it >= st->maxit;
             if (blockIdx.x == 0 && tid == 0) {
@@ -357,29 +377,35 @@ __global__ void __launch_bounds__(kBlock) k_spmv(SpmvArgs<T> a)
                     st->gamma = g;
                     st->iter = it;
                     st->reason = conv ? kConverged : kMaxit;
+                    st->stop_it = it;
                     st->live = 0;
                 }
             }
             const unsigned cross = a.snap ? spec_crossings(st, it, g) : 0u;
-            if (cross) {
+            if (conv || cap || cross) {
+                // the iterate x_it of this block's rows, then its run-ahead copies
                 const int lb0 = xcd_remap(blockIdx.x, gridDim.x);
                 const int r0 = (int)((int64_t)lb0 * a.ntiles / gridDim.x) * a.R;
                 const int r1 = min((int)((int64_t)(lb0 + 1) * a.ntiles / gridDim.x) * a.R, a.n);
-                for (int t = 0; t < kNumEps; ++t) {
-                    if (!(cross & (1u << t))) continue;
-                    T *dst = a.snap + (size_t)t * a.n;
-                    for (int i = r0 + tid; i < r1; i += kBlock) dst[i] = a.xs[i];
-                    if (blockIdx.x == 0 && tid == 0) {
+                for (int i = r0 + tid; i < r1; i += kBlock) {
+                    const T xn = xdone ? a.x[i] : fmaT<T>(alpha_prev, dold[i], a.x[i]);
+                    if (!xdone) a.x[i] = xn;
+                    for (int t = 0; t < kNumEps; ++t)
+                        if (cross & (1u << t)) a.snap[(size_t)t * a.n + i] = xn;
+                }
+                if (blockIdx.x == 0 && tid == 0) {
+                    for (int t = 0; t < kNumEps; ++t) {
+                        if (!(cross & (1u << t))) continue;
                         st->cross_iter[t] = it;
                         st->cross_gamma[t] = g;
                     }
                 }
+                if (conv || cap) return;
+            } else {
+                x_pending = !xdone;
             }
-            if (conv || cap) return;
             beta = (T)(g / gp);
         }
-        dold = (it & 1) ? a.dB : a.dA;
-        dnew = (it & 1) ? a.dA : a.dB;
     }
 
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -428,7 +454,9 @@ __global__ void __launch_bounds__(kBlock) k_spmv(SpmvArgs<T> a)
             if (MODE == kModePlain) {
                 a.yout[my_row] = acc;
             } else if (MODE == kModeCg) {
-                const T dn = fmaT<T>(beta, dold[my_row], a.r[my_row]);
+                const T dof = dold[my_row];
+                if (x_pending) a.x[my_row] = fmaT<T>(alpha_prev, dof, a.x[my_row]);
+                const T dn = fmaT<T>(beta, dof, a.r[my_row]);
                 dnew[my_row] = dn;
                 a.q[my_row] = acc;
                 s[0] = fma((double)dn, (double)acc, s[0]);
@@ -486,10 +514,10 @@ static SpmvArgs<T> spmv_args(const SpmvShape &sh, const int32_t *rp, const int32
 template <typename T>
 void launch_cg_spmv(hipStream_t s, const SpmvShape &sh, const int32_t *rp, const int32_t *col,
                     const T *val, const T *r, T *dA, T *dB, T *q, const double *up, int nup,
-                    double *part, int it, int it0, const T *x, T *snap, DevState *st)
+                    double *part, int it, int it0, T *x, T *snap, DevState *st)
 {
     SpmvArgs<T> a = spmv_args<T>(sh, rp, col, val);
-    a.it = it; a.it0 = it0; a.xs = x; a.snap = snap;
+    a.it = it; a.it0 = it0; a.x = x; a.snap = snap;
     a.r = r; a.dA = dA; a.dB = dB; a.q = q; a.up = up; a.nup = nup; a.part = part; a.st = st;
     hipLaunchKernelGGL((k_spmv<kModeCg, T>), dim3(sh.grid), dim3(kBlock), 0, s, a);
 }
@@ -538,17 +566,18 @@ void launch_spmv_plain(hipStream_t s, const SpmvShape &sh, const int32_t *rp, co
 
 // ------------------------------------------------------------- update --
 
+// Update of iteration it: alpha = gamma_it / delta, r -= alpha q, partials of
+// r.r.  x += alpha d is left to the next product, which reads d anyway.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_cg_update(int32_t n, T *__restrict__ x, T *__restrict__ r, const T *__restrict__ q,
-            const T *__restrict__ dA, const T *__restrict__ dB, const double *sp, int nsp,
-            double *up, int it, DevState *st)
+k_cg_update(int32_t n, T *__restrict__ r, const T *__restrict__ q, const double *sp, int nsp, double *up,
+            int it, DevState *st)
 {
     __shared__ double sm[kBlock / 64 + 1];
-    __shared__ int s_live;
-    if (threadIdx.x == 0) s_live = st->live;
+    __shared__ int s_skip;
+    if (threadIdx.x == 0) s_skip = st->stop_it <= it;
     __syncthreads();
-    if (!s_live) return;
+    if (s_skip) return;
     const double delta = reduce_partials(sp, nsp, 1, 0, sm);
     const double g = st->gam[it & 1];
     if (!isfinite(delta) || !(delta > 0.0)) {
@@ -557,6 +586,7 @@ k_cg_update(int32_t n, T *__restrict__ x, T *__restrict__ r, const T *__restrict
             st->gamma = g;
             st->iter = it;
             st->reason = isfinite(delta) ? kNotSpd : kNonFinite;
+            st->stop_it = it;
             st->live = 0;
         }
         return;
@@ -565,8 +595,8 @@ k_cg_update(int32_t n, T *__restrict__ x, T *__restrict__ r, const T *__restrict
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->delta = delta;
         st->alpha = (double)alpha;
+        st->alph[it & 1] = (double)alpha;
     }
-    const T *dn = (it & 1) ? dA : dB;   // written by the product of iteration it
     double s = 0.0;
     const int64_t nchunk = ((int64_t)n + kVecTile - 1) / kVecTile;
     for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
@@ -574,7 +604,6 @@ k_cg_update(int32_t n, T *__restrict__ x, T *__restrict__ r, const T *__restrict
         for (int j = 0; j < kVecPerThread; ++j) {
             const int64_t i = c * kVecTile + j * kBlock + threadIdx.x;
             if (i < n) {
-                x[i] = fmaT<T>(alpha, dn[i], x[i]);
                 const T rv = fmaT<T>(-alpha, q[i], r[i]);
                 r[i] = rv;
                 s = fma((double)rv, (double)rv, s);
@@ -586,27 +615,24 @@ k_cg_update(int32_t n, T *__restrict__ x, T *__restrict__ r, const T *__restrict
 }
 
 template <typename T>
-void launch_cg_update(hipStream_t s, int32_t n, T *x, T *r, const T *q, const T *dA, const T *dB,
-                      const double *sp, int nsp, double *up, int it, DevState *st)
+void launch_cg_update(hipStream_t s, int32_t n, T *r, const T *q, const double *sp, int nsp, double *up,
+                      int nup, int it, DevState *st)
 {
-    hipLaunchKernelGGL(k_cg_update<T>, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, x, r, q, dA, dB, sp,
-                       nsp, up, it, st);
+    hipLaunchKernelGGL(k_cg_update<T>, dim3(nup), dim3(kBlock), 0, s, n, r, q, sp, nsp, up, it, st);
 }
 
 template void launch_cg_spmv<float>(hipStream_t, const SpmvShape &, const int32_t *, const int32_t *,
                                     const float *, const float *, float *, float *, float *,
-                                    const double *, int, double *, int, int, const float *, float *,
+                                    const double *, int, double *, int, int, float *, float *,
                                     DevState *);
 template void launch_cg_spmv<double>(hipStream_t, const SpmvShape &, const int32_t *, const int32_t *,
                                      const double *, const double *, double *, double *, double *,
-                                     const double *, int, double *, int, int, const double *, double *,
+                                     const double *, int, double *, int, int, double *, double *,
                                      DevState *);
-template void launch_cg_update<float>(hipStream_t, int32_t, float *, float *, const float *,
-                                      const float *, const float *, const double *, int, double *, int,
-                                      DevState *);
-template void launch_cg_update<double>(hipStream_t, int32_t, double *, double *, const double *,
-                                       const double *, const double *, const double *, int, double *,
-                                       int, DevState *);
+template void launch_cg_update<float>(hipStream_t, int32_t, float *, const float *, const double *, int,
+                                      double *, int, int, DevState *);
+template void launch_cg_update<double>(hipStream_t, int32_t, double *, const double *, const double *,
+                                       int, double *, int, int, DevState *);
 template void launch_spmv_plain<float>(hipStream_t, const SpmvShape &, const int32_t *, const int32_t *,
                                        const float *, const float *, float *);
 template void launch_spmv_plain<double>(hipStream_t, const SpmvShape &, const int32_t *,

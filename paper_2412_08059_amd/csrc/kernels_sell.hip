@@ -305,15 +305,14 @@ struct SellArgs {
     double *dzA, *dzB;
     const T *xin;
     T *yout;
-    const T *xs;
-    T *snap;
+    T *x;        // CG iterate: receives the deferred alpha_{it-1} d_{it-1}
+    T *snap;     // x~ copies at the run-ahead crossings (FP32 only)
     double *part;
     DevState *st;
 };
 
-constexpr int kSellBatch = 4;   // entries whose loads are issued together
-
-template <int MODE, typename T, typename IDX>
+// B = entries of a row whose loads are issued together (4 or 8)
+template <int MODE, typename T, typename IDX, int B>
 __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
 {
     constexpr int NV = (MODE == kSellRestart) ? 2 : 1;
@@ -321,18 +320,26 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
     DevState *st = a.st;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 
-    T beta = T(0);
+    T beta = T(0), alpha_prev = T(0);
+    bool x_pending = false;   // x += alpha_{it-1} d_{it-1} still to apply in the main loop
     const T *dold = nullptr;
     T *dnew = nullptr;
     if (MODE == kSellCg) {
-        __shared__ int s_live;
-        if (tid == 0) s_live = st->live;
-        __syncthreads();
-        if (!s_live) return;
         const int it = a.it;
+        __shared__ int s_skip, s_xdone;
+        if (tid == 0) {
+            s_skip = st->stop_it < it;
+            s_xdone = st->x_it == it;
+        }
+        __syncthreads();
+        if (s_skip) return;
+        dold = (it & 1) ? a.dB : a.dA;
+        dnew = (it & 1) ? a.dA : a.dB;
         if (it != a.it0) {
+            const bool xdone = s_xdone;
             const double g = sell_reduce_partials(a.up, a.nup, sm);
             const double gp = st->gam[(it - 1) & 1];
+            alpha_prev = (T)st->alph[(it - 1) & 1];
             const bool conv = sqrt(g) <= st->thr;
             const bool cap = !conv && it >= st->maxit;
             if (blockIdx.x == 0 && tid == 0) {
@@ -343,30 +350,34 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
                     st->gamma = g;
                     st->iter = it;
                     st->reason = conv ? kConverged : kMaxit;
+                    st->stop_it = it;
                     st->live = 0;
                 }
             }
             const unsigned cross = a.snap ? spec_crossings(st, it, g) : 0u;
-            if (cross) {
-                // copy x~ for the rows of this block's slices
-                for (int t = 0; t < kNumEps; ++t) {
-                    if (!(cross & (1u << t))) continue;
-                    T *dst = a.snap + (size_t)t * a.n;
-                    for (SliceWalk w = slice_walk(a.nslices); w.g < w.g_end; w.g += w.step) {
-                        const int r0 = w.g * kBlock, r1 = min(r0 + kBlock, a.n);
-                        if (r0 + tid < r1) dst[r0 + tid] = a.xs[r0 + tid];
-                    }
-                    if (blockIdx.x == 0 && tid == 0) {
+            if (conv || cap || cross) {
+                // the iterate x_it of this block's rows, then its run-ahead copies
+                for (SliceWalk w = slice_walk(a.nslices); w.g < w.g_end; w.g += w.step) {
+                    const int i = w.g * kBlock + tid;
+                    if (i >= a.n) continue;
+                    const T xn = xdone ? a.x[i] : fma_t<T>(alpha_prev, dold[i], a.x[i]);
+                    if (!xdone) a.x[i] = xn;
+                    for (int t = 0; t < kNumEps; ++t)
+                        if (cross & (1u << t)) a.snap[(size_t)t * a.n + i] = xn;
+                }
+                if (blockIdx.x == 0 && tid == 0) {
+                    for (int t = 0; t < kNumEps; ++t) {
+                        if (!(cross & (1u << t))) continue;
                         st->cross_iter[t] = it;
                         st->cross_gamma[t] = g;
                     }
                 }
+                if (conv || cap) return;
+            } else {
+                x_pending = !xdone;
             }
-            if (conv || cap) return;
             beta = (T)(g / gp);
         }
-        dold = (it & 1) ? a.dB : a.dA;
-        dnew = (it & 1) ? a.dA : a.dB;
     }
 
     const IDX *scol = static_cast<const IDX *>(a.scol);
@@ -385,11 +396,11 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
         const IDX *cp = scol + base + lane;
         const T *vp = a.sval + base + lane;
         T acc = T(0);
-        for (int k0 = 0; k0 < W; k0 += kSellBatch) {
-            int c[kSellBatch];
-            T v[kSellBatch], g[kSellBatch];
+        for (int k0 = 0; k0 < W; k0 += B) {
+            int c[B];
+            T v[B], g[B];
 #pragma unroll
-            for (int j = 0; j < kSellBatch; ++j) {
+            for (int j = 0; j < B; ++j) {
                 if (k0 + j < len) {
                     const IDX ci = cp[(int64_t)(k0 + j) * 64];
                     c[j] = (sizeof(IDX) == 2) ? row + (int)ci : (int)ci;
@@ -397,7 +408,7 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
                 }
             }
 #pragma unroll
-            for (int j = 0; j < kSellBatch; ++j) {
+            for (int j = 0; j < B; ++j) {
                 if (k0 + j < len) {
                     if (MODE == kSellCg) g[j] = fma_t<T>(beta, dold[c[j]], a.r[c[j]]);
                     else if (MODE == kSellPlain) g[j] = a.xin[c[j]];
@@ -405,14 +416,16 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
                 }
             }
 #pragma unroll
-            for (int j = 0; j < kSellBatch; ++j)
+            for (int j = 0; j < B; ++j)
                 if (k0 + j < len) acc = fma_t<T>(v[j], g[j], acc);
         }
         if (has) {
             if (MODE == kSellPlain) {
                 a.yout[row] = acc;
             } else if (MODE == kSellCg) {
-                const T dn = fma_t<T>(beta, dold[row], a.r[row]);
+                const T dof = dold[row];
+                if (x_pending) a.x[row] = fma_t<T>(alpha_prev, dof, a.x[row]);
+                const T dn = fma_t<T>(beta, dof, a.r[row]);
                 dnew[row] = dn;
                 a.q[row] = acc;
                 s[0] = fma((double)dn, (double)acc, s[0]);
@@ -440,10 +453,17 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
 template <int MODE, typename T>
 static void sell_launch(hipStream_t s, const SellMat &m, const SellArgs<T> &a)
 {
-    if (m.idx16)
-        hipLaunchKernelGGL((k_sell<MODE, T, int16_t>), dim3(m.grid), dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_sell<MODE, T, int32_t>), dim3(m.grid), dim3(kBlock), 0, s, a);
+    if (m.batch == 8) {
+        if (m.idx16)
+            hipLaunchKernelGGL((k_sell<MODE, T, int16_t, 8>), dim3(m.grid), dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_sell<MODE, T, int32_t, 8>), dim3(m.grid), dim3(kBlock), 0, s, a);
+    } else {
+        if (m.idx16)
+            hipLaunchKernelGGL((k_sell<MODE, T, int16_t, 4>), dim3(m.grid), dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_sell<MODE, T, int32_t, 4>), dim3(m.grid), dim3(kBlock), 0, s, a);
+    }
 }
 
 template <typename T>
@@ -460,12 +480,12 @@ template <> const double *sell_vals<double>(const SellMat &m) { return m.v64; }
 
 template <typename T>
 void launch_sell_cg_spmv(hipStream_t s, const SellMat &m, const T *r, T *dA, T *dB, T *q,
-                         const double *up, int nup, double *part, int it, int it0, const T *x, T *snap,
+                         const double *up, int nup, double *part, int it, int it0, T *x, T *snap,
                          DevState *st)
 {
     SellArgs<T> a = sell_args<T>(m, sell_vals<T>(m));
     a.it = it; a.it0 = it0; a.r = r; a.dA = dA; a.dB = dB; a.q = q; a.up = up; a.nup = nup;
-    a.xs = x; a.snap = snap;
+    a.x = x; a.snap = snap;
     a.part = part; a.st = st;
     sell_launch<kSellCg, T>(s, m, a);
 }
@@ -497,11 +517,11 @@ void launch_sell_plain(hipStream_t s, const SellMat &m, const T *x, T *y)
 }
 
 template void launch_sell_cg_spmv<float>(hipStream_t, const SellMat &, const float *, float *, float *,
-                                         float *, const double *, int, double *, int, int, const float *,
+                                         float *, const double *, int, double *, int, int, float *,
                                          float *, DevState *);
 template void launch_sell_cg_spmv<double>(hipStream_t, const SellMat &, const double *, double *,
                                           double *, double *, const double *, int, double *, int, int,
-                                          const double *, double *, DevState *);
+                                          double *, double *, DevState *);
 template void launch_sell_plain<float>(hipStream_t, const SellMat &, const float *, float *);
 template void launch_sell_plain<double>(hipStream_t, const SellMat &, const double *, double *);
 

@@ -20,12 +20,14 @@ constexpr int kLdsBytes = 32768;      // LDS staging per SpMV block (val + gathe
 constexpr int kBfsSmallCap = 4096;    // frontier size handled by the one-workgroup BFS kernel
 constexpr int kBfsSmallThreads = 1024;
 constexpr int kBfsSmallWork = 2048;   // (vertex, lane) items per level in the one-workgroup kernel
-constexpr int kBfsLevelBlocks = 256;  // grid of the multi-block BFS level kernel (arrival ticket per block)
+constexpr int kBfsLevelBlocks = 64;   // level-kernel blocks: few, so a level costs few dispatches
 constexpr int kNumXcd = 8;            // MI355X: blocks are dispatched round-robin over 8 XCDs
 constexpr int kMaxGrid = 2048;        // largest grid of a kernel that writes reduction partials
+constexpr int kUpdateGrid = 1024;     // blocks of a CG update launch: fewer partials for the next product
 constexpr int kSpmvBlocksPerCu = 5;   // 32 KB of LDS per block, 160 KB per CU
 
 enum StopReason : int32_t { kRunning = 0, kConverged = 1, kMaxit = 2, kNotSpd = 3, kNonFinite = 4 };
+constexpr int32_t kNoStop = 0x7fffffff;   // DevState::stop_it while the recurrence runs
 
 enum IngestError : int32_t {
     kErrRowPtr = 1, kErrCol = 2, kErrUnsorted = 4, kErrNonFiniteA = 8, kErrNonFiniteB = 16
@@ -43,9 +45,14 @@ struct alignas(256) DevState {
     double bnorm2;    // ||b||^2 (FP64)
     double resid2;    // ||b - A x||^2 from the residual kernel
     double gam[2];    // gamma_i by parity of i (the product of iteration i writes slot i & 1)
+    double alph[2];   // alpha_i by parity of i (the update of iteration i writes slot i & 1)
     int32_t iter;     // iteration at which the phase started or stopped
     int32_t maxit;
-    int32_t live;     // 1 while iterations must continue
+    int32_t live;     // 1 while iterations must continue (read by the host)
+    int32_t stop_it;  // the recurrence stopped in iteration stop_it (INT32_MAX while running):
+                      // products of later iterations and updates of it and later do nothing
+    int32_t x_it;     // x already holds x_{x_it} (set between launches, when a phase starts or
+                      // resumes): the product of iteration x_it then has no update to apply
     int32_t reason;   // StopReason
     int32_t k0rec;    // ratios[i] = ||r_{i+1}|| / ||r_i|| is recorded while i < k0rec
     int32_t guard;    // device-side guard tripped (bounded loop exhausted)
@@ -54,17 +61,18 @@ struct alignas(256) DevState {
     int32_t max_band; // largest |i - j| over the stored entries
     int32_t pad_band;
     double ratios[kK0Max];
-    // BFS
-    int32_t bfs_level;    // distance of the current frontier
-    int32_t bfs_cur;      // current frontier size
-    int32_t bfs_next;     // next frontier size (atomic counter)
-    int32_t bfs_parity;   // queue buffer holding the current frontier
+    // BFS.  Launch k of a run expands level bfs_lv[k & 1] (the frontier of
+    // level L is queue L & 1, bfs_cnt[L & 3] vertices, smallest bfs_min[L & 3])
+    // and hands the next level to launch k + 1 in bfs_lv[(k + 1) & 1]; a level
+    // is finished when its launch ends, so no launch needs an arrival count.
+    int32_t bfs_lv[2];
+    int32_t bfs_cnt[4];
+    int32_t bfs_min[4];
     int32_t bfs_done;
-    int32_t bfs_cur_min;  // smallest vertex of the current frontier
-    int32_t bfs_next_min;
-    int32_t bfs_far;      // smallest vertex of the last non-empty frontier (when done)
+    int32_t bfs_ecc;      // largest distance (when done)
+    int32_t bfs_far;      // smallest vertex at distance bfs_ecc (when done)
+    int32_t bfs_pad;
     int64_t bfs_visited;
-    uint32_t tk_bfs;
     int32_t ncomp;
     uint64_t comp_best;   // (ecc << 32) | ~component of the best component
     // Algorithm II run-ahead: while the features are computed, the FP32
@@ -107,6 +115,7 @@ struct SellMat {
     const float *v32;
     const int64_t *off;
     int32_t n, nslices, grid, idx16;
+    int32_t batch;   // row entries whose loads are issued together: 4 or 8
 };
 
 Layout plan_layout(int64_t n, int64_t nnz);
@@ -148,13 +157,17 @@ void launch_timing_state(hipStream_t s, DevState *st, double *part, int cnt);
 // CG iteration `it` of a phase that started at `it0`: product kernel (reads the
 // update partials `up`, writes its own to `part`) and update kernel (reads
 // `sp`, writes `up`).
+// The product of iteration it > it0 also applies the previous iteration's
+// x += alpha_{it-1} d_{it-1} (deferred from the update, which then needs
+// neither x nor d), and copies the updated x~ into `snap` at a run-ahead
+// crossing (FP32 only).
 template <typename T>
 void launch_cg_spmv(hipStream_t s, const SpmvShape &sh, const int32_t *rp, const int32_t *col,
                     const T *val, const T *r, T *dA, T *dB, T *q, const double *up, int nup,
-                    double *part, int it, int it0, const T *x, T *snap, DevState *st);
+                    double *part, int it, int it0, T *x, T *snap, DevState *st);
 template <typename T>
-void launch_cg_update(hipStream_t s, int32_t n, T *x, T *r, const T *q, const T *dA, const T *dB,
-                      const double *sp, int nsp, double *up, int it, DevState *st);
+void launch_cg_update(hipStream_t s, int32_t n, T *r, const T *q, const double *sp, int nsp, double *up,
+                      int nup, int it, DevState *st);
 // r = b - A x (x from float x32 when x32 != nullptr, else from x64), x64 <- float64(x32),
 // zero the old-direction buffer of iteration it0, gamma = r.r, ||b||^2, stop test.
 void launch_restart(hipStream_t s, const SpmvShape &sh, const int32_t *rp, const int32_t *col,
@@ -173,7 +186,7 @@ void launch_spmv_plain(hipStream_t s, const SpmvShape &sh, const int32_t *rp, co
 // ----- SELL-64 (kernels_sell.hip) -----
 template <typename T>
 void launch_sell_cg_spmv(hipStream_t s, const SellMat &m, const T *r, T *dA, T *dB, T *q,
-                         const double *up, int nup, double *part, int it, int it0, const T *x, T *snap,
+                         const double *up, int nup, double *part, int it, int it0, T *x, T *snap,
                          DevState *st);
 void launch_sell_restart(hipStream_t s, const SellMat &m, const float *x32, double *x64,
                          const double *b, double *r, double *dA, double *dB, int it0, double *part,
@@ -192,9 +205,13 @@ struct BfsBufs {
     int32_t *dist, *q0, *q1, *label, *tarr;
     unsigned long long *best;
     DevState *st;
+    int32_t grid;       // blocks of the level kernel
+    int32_t precheck;   // read the distance before claiming a vertex
 };
 void launch_bfs_seed_single(hipStream_t s, const BfsBufs &b, int32_t src);
-void launch_bfs_round(hipStream_t s, const BfsBufs &b, int levels);
+// Enqueues one round (the one-workgroup kernel, then `levels` level kernels)
+// with launch indices k, k + 1, ...; returns the next launch index.
+int launch_bfs_round(hipStream_t s, const BfsBufs &b, int levels, int k);
 
 void launch_cc(hipStream_t s, const BfsBufs &b);
 void launch_bfs_seed_roots(hipStream_t s, const BfsBufs &b);
