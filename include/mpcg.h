@@ -198,6 +198,65 @@ mpcg_status mpcg_time_kernel(mpcg_ctx *ctx, const mpcg_csr *A, int32_t kernel, i
 
 const char *mpcg_strerror(mpcg_status s);
 
+/* ------------------------------------------------------------------------
+ * Batched and continuously admitted solves.
+ *
+ * Many independent systems are solved together: each admitted system gets a
+ * range of 64-row slices and SELL-64 entries in the batch arena, and every
+ * "step" advances all of them at once (CG product, scalar decisions, update,
+ * 2BFS levels) with per-system reductions and per-system convergence, so a
+ * system's result does not depend on the other systems it shares the GPU
+ * with.  Each system follows Algorithm I (fixed eps1), Algorithm II
+ * (MPCG_EPS1_AUTO: 2BFS per connected component and the k0 prefix run side by
+ * side, then kNN) or FP64-only CG (MPCG_EPS1_NONE), with the restart and final
+ * check of mpcg_solve.  Requests that arrive while others run are admitted as
+ * slots, slices and entries free up (first fit), and their work joins the
+ * next step.  A host thread owned by the context drives the steps on a
+ * stream of its own; mpcg_batch_poll returns finished solves without blocking.
+ * -------------------------------------------------------------------------*/
+
+/* One solve.  A, b and x are DEVICE memory owned by the caller and borrowed
+ * until mpcg_batch_poll has reported the request: A and b must stay
+ * unchanged and complete (the caller's stream synchronised) at submission; x
+ * (n doubles) receives the solution. */
+typedef struct {
+    mpcg_csr A;
+    const double *b;
+    double *x;
+    double eps1;       /* MPCG_EPS1_AUTO, MPCG_EPS1_NONE or a finite value > 0 */
+    double eps2;       /* > 0 */
+    void *user;        /* not used by the library */
+} mpcg_request;
+
+/* Arena bytes for a batch engine holding at most max_systems systems,
+ * max_rows rows in total (each system is padded to a multiple of 64 rows) and
+ * max_entries SELL-64 entries in total (nnz plus padding to the longest row
+ * of each 64-row slice).  EINVAL for non-positive sizes. */
+mpcg_status mpcg_batch_workspace_size(const mpcg_ctx *ctx, int64_t max_rows, int64_t max_entries,
+                                      int32_t max_systems, size_t *bytes);
+/* Hands a device arena (>= the size above, 256-byte aligned, owned by the
+ * caller until mpcg_destroy) to the batch engine of this context and starts
+ * its host thread.  Once per context; EBUSY if the engine already runs. */
+mpcg_status mpcg_batch_set_workspace(mpcg_ctx *ctx, void *dev_arena, size_t bytes, int64_t max_rows,
+                                     int64_t max_entries, int32_t max_systems);
+/* Queues `count` requests; ids[i] (HOST array) receives the id of reqs[i].
+ * Validated before anything is queued: EINVAL (bad sizes, pointers or
+ * tolerances), ENOMODEL (AUTO without a model), ENOMEM (a system larger than
+ * the whole arena), EDEVICE (no engine).  Malformed CSR contents are
+ * reported per request by mpcg_batch_poll (EINVAL / ENONFINITE). */
+mpcg_status mpcg_batch_submit(mpcg_ctx *ctx, const mpcg_request *reqs, int32_t count, uint64_t *ids);
+/* Non-blocking: moves up to `cap` finished requests out of the engine;
+ * done_ids[i] and done_stats[i] (HOST arrays) describe one of them, with its
+ * own status in done_stats[i].status; *n_done gets the count.  Before a
+ * request is reported its x is complete in device memory. */
+mpcg_status mpcg_batch_poll(mpcg_ctx *ctx, uint64_t *done_ids, mpcg_stats *done_stats, int32_t cap,
+                            int32_t *n_done);
+/* Cancels a queued or running request; it is reported by mpcg_batch_poll
+ * with status ECANCELED (x undefined).  EINVAL for an unknown or finished id. */
+mpcg_status mpcg_batch_cancel(mpcg_ctx *ctx, uint64_t id);
+/* Requests waiting for admission and systems on the GPU (HOST outputs). */
+mpcg_status mpcg_batch_load(mpcg_ctx *ctx, int32_t *queued, int32_t *active);
+
 #ifdef __cplusplus
 }
 #endif

@@ -99,3 +99,89 @@ class Solver:
         dist = torch.empty(A.n, dtype=torch.int32, device=self.device)
         st, ecc, far = capi.mpcg_bfs(self.ctx, A.desc, src, dist.data_ptr())
         return st, dist, ecc, far
+
+
+class BatchSolver:
+    """Batched / continuously admitted solves (the mpcg_batch_* entry points).
+
+    Owns a library context whose engine thread runs on a stream of its own,
+    and the batch arena (one uint8 tensor).  Submitted systems keep their
+    tensors referenced here until their result has been polled."""
+
+    def __init__(self, max_rows: int, max_entries: int, max_systems: int, *, k0: int = 20, knn_k: int = 0,
+                 tol_mode: int = 0, max_restarts: int = 5, maxit1: int = 0, maxit2: int = 0,
+                 model: str | None = DEFAULT_MODEL, device="cuda"):
+        import torch
+        self.device = torch.device(device)
+        opt = mpcg_options(k0, knn_k, tol_mode, max_restarts, 0, 0, maxit1, maxit2)
+        self.ctx = capi.mpcg_create(opt, torch.cuda.current_stream(self.device).cuda_stream)
+        if model:
+            st = capi.mpcg_load_model(self.ctx, model)
+            if st != MPCG_OK:
+                raise MpcgError(st, f"mpcg_load_model({model})")
+        nbytes = capi.mpcg_batch_workspace_size(self.ctx, max_rows, max_entries, max_systems)
+        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        st = capi.mpcg_batch_set_workspace(self.ctx, self.arena.data_ptr(), nbytes, max_rows, max_entries,
+                                           max_systems)
+        if st != MPCG_OK:
+            raise MpcgError(st, "mpcg_batch_set_workspace")
+        self.live = {}
+
+    def submit(self, systems):
+        """systems: iterable of (DeviceCSR, b, x, eps1, eps2); returns the ids."""
+        import torch
+        systems = list(systems)
+        torch.cuda.current_stream(self.device).synchronize()   # inputs complete before the engine reads them
+        reqs = [capi.mpcg_request(A.desc, b.data_ptr(), x.data_ptr(), float(e1), float(e2), None)
+                for (A, b, x, e1, e2) in systems]
+        st, ids = capi.mpcg_batch_submit(self.ctx, reqs)
+        if st != MPCG_OK:
+            raise MpcgError(st, "mpcg_batch_submit")
+        for rid, sysd in zip(ids, systems):
+            self.live[rid] = sysd
+        return ids
+
+    def poll(self, cap: int = 256):
+        """Finished requests as (id, stats, x); non-blocking."""
+        st, done = capi.mpcg_batch_poll(self.ctx, cap)
+        if st != MPCG_OK:
+            raise MpcgError(st, "mpcg_batch_poll")
+        out = []
+        for rid, stats in done:
+            sysd = self.live.pop(rid, None)
+            out.append((rid, stats, sysd[2] if sysd else None))
+        return out
+
+    def wait_all(self, ids, timeout_s: float = 600.0, sleep_s: float = 0.0005):
+        """Polls until every id in `ids` is reported; returns {id: (stats, x)}."""
+        import time
+        want, got = set(ids), {}
+        t0 = time.perf_counter()
+        while want:
+            for rid, stats, x in self.poll():
+                if rid in want:
+                    want.discard(rid)
+                    got[rid] = (stats, x)
+            if want:
+                if time.perf_counter() - t0 > timeout_s:
+                    raise TimeoutError(f"{len(want)} batch requests not finished after {timeout_s} s")
+                time.sleep(sleep_s)
+        return got
+
+    def cancel(self, rid: int) -> int:
+        return capi.mpcg_batch_cancel(self.ctx, rid)
+
+    def load(self):
+        st, q, a = capi.mpcg_batch_load(self.ctx)
+        return q, a
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            capi.mpcg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

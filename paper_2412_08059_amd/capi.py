@@ -39,6 +39,8 @@ EXPORTED = (
     "mpcg_create", "mpcg_destroy", "mpcg_workspace_size", "mpcg_set_workspace", "mpcg_load_model",
     "mpcg_features", "mpcg_select_eps1", "mpcg_solve", "mpcg_spmv", "mpcg_bfs",
     "mpcg_last_kernel_ms", "mpcg_time_kernel", "mpcg_strerror",
+    "mpcg_batch_workspace_size", "mpcg_batch_set_workspace", "mpcg_batch_submit", "mpcg_batch_poll",
+    "mpcg_batch_cancel", "mpcg_batch_load",
 )
 
 MPCG_KERNEL_CG_SPMV_F64 = 0
@@ -78,6 +80,11 @@ class mpcg_options(ctypes.Structure):
                 ("maxit1", ctypes.c_int64), ("maxit2", ctypes.c_int64)]
 
 
+class mpcg_request(ctypes.Structure):
+    _fields_ = [("A", mpcg_csr), ("b", ctypes.c_void_p), ("x", ctypes.c_void_p), ("eps1", ctypes.c_double),
+                ("eps2", ctypes.c_double), ("user", ctypes.c_void_p)]
+
+
 def _load():
     # torch ships its own libamdhip64.so.7; loading torch first makes the
     # library bind to that same HIP runtime instance (one runtime per process,
@@ -103,6 +110,13 @@ def _load():
         "mpcg_last_kernel_ms": ([P, ctypes.POINTER(D)], I32),
         "mpcg_time_kernel": ([P, ctypes.POINTER(mpcg_csr), I32, I32, ctypes.POINTER(D)], I32),
         "mpcg_strerror": ([I32], ctypes.c_char_p),
+        "mpcg_batch_workspace_size": ([P, I64, I64, I32, ctypes.POINTER(ctypes.c_size_t)], I32),
+        "mpcg_batch_set_workspace": ([P, P, ctypes.c_size_t, I64, I64, I32], I32),
+        "mpcg_batch_submit": ([P, ctypes.POINTER(mpcg_request), I32, ctypes.POINTER(ctypes.c_uint64)], I32),
+        "mpcg_batch_poll": ([P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(mpcg_stats), I32,
+                             ctypes.POINTER(I32)], I32),
+        "mpcg_batch_cancel": ([P, ctypes.c_uint64], I32),
+        "mpcg_batch_load": ([P, ctypes.POINTER(I32), ctypes.POINTER(I32)], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -202,3 +216,43 @@ def mpcg_time_kernel(ctx: int, A: mpcg_csr, kernel: int, reps: int) -> float:
     _check(lib.mpcg_time_kernel(ctypes.c_void_p(ctx), ctypes.byref(A), kernel, reps, ctypes.byref(ms)),
            "mpcg_time_kernel")
     return ms.value
+
+
+def mpcg_batch_workspace_size(ctx: int, max_rows: int, max_entries: int, max_systems: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib.mpcg_batch_workspace_size(ctypes.c_void_p(ctx), max_rows, max_entries, max_systems,
+                                         ctypes.byref(b)), "mpcg_batch_workspace_size")
+    return b.value
+
+
+def mpcg_batch_set_workspace(ctx: int, ptr: int, nbytes: int, max_rows: int, max_entries: int,
+                             max_systems: int) -> int:
+    return lib.mpcg_batch_set_workspace(ctypes.c_void_p(ctx), ctypes.c_void_p(ptr), nbytes, max_rows,
+                                        max_entries, max_systems)
+
+
+def mpcg_batch_submit(ctx: int, reqs) -> tuple[int, list[int]]:
+    n = len(reqs)
+    arr = (mpcg_request * max(n, 1))(*reqs)
+    ids = (ctypes.c_uint64 * max(n, 1))()
+    st = lib.mpcg_batch_submit(ctypes.c_void_p(ctx), arr, n, ids)
+    return st, [int(ids[i]) for i in range(n)] if st == MPCG_OK else []
+
+
+def mpcg_batch_poll(ctx: int, cap: int = 256):
+    ids = (ctypes.c_uint64 * cap)()
+    stats = (mpcg_stats * cap)()
+    nd = ctypes.c_int32(0)
+    st = lib.mpcg_batch_poll(ctypes.c_void_p(ctx), ids, stats, cap, ctypes.byref(nd))
+    return st, [(int(ids[i]), stats[i]) for i in range(nd.value)]
+
+
+def mpcg_batch_cancel(ctx: int, rid: int) -> int:
+    return lib.mpcg_batch_cancel(ctypes.c_void_p(ctx), rid)
+
+
+def mpcg_batch_load(ctx: int):
+    q = ctypes.c_int32(0)
+    a = ctypes.c_int32(0)
+    st = lib.mpcg_batch_load(ctypes.c_void_p(ctx), ctypes.byref(q), ctypes.byref(a))
+    return st, q.value, a.value

@@ -1,0 +1,599 @@
+// Host side of the batched engine: admission by footprint, the step loop,
+// the per-system 2BFS transitions and kNN choice, and retirement.
+//
+// One host thread per engine owns a non-blocking stream.  It enqueues groups
+// of steps and, after each group, an asynchronous copy of the per-system
+// state into pinned memory; it inspects the copy of group g - 1 while group g
+// runs, so the GPU never waits for the host.  Everything the thread decides
+// from a copy is enqueued behind the running group; a slot's later copies are
+// ignored until they reflect that action (the slot's `guard`).
+
+#include "batch_internal.hpp"
+#include "knn.hpp"
+
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+namespace mpcg {
+namespace batch {
+
+namespace {
+
+constexpr int kGroupSteps = 8;
+constexpr double kEpsClass[8] = {0, 0, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7};
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// First-fit allocator over [0, cap).
+struct RangeAlloc {
+    std::map<int64_t, int64_t> free_;   // start -> length
+    void init(int64_t cap)
+    {
+        free_.clear();
+        if (cap > 0) free_[0] = cap;
+    }
+    int64_t alloc(int64_t len)
+    {
+        if (len <= 0) len = 1;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < len) continue;
+            const int64_t s = it->first, rem = it->second - len;
+            free_.erase(it);
+            if (rem) free_[s + len] = rem;
+            return s;
+        }
+        return -1;
+    }
+    void release(int64_t s, int64_t len)
+    {
+        if (len <= 0) len = 1;
+        auto nx = free_.lower_bound(s);
+        if (nx != free_.end() && nx->first == s + len) {
+            len += nx->second;
+            nx = free_.erase(nx);
+        }
+        if (nx != free_.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == s) {
+                pv->second += len;
+                return;
+            }
+        }
+        free_[s] = len;
+    }
+};
+
+struct Pending {
+    uint64_t id;
+    mpcg_request req;
+    double t_submit;
+};
+
+struct Slot {
+    bool used = false;
+    uint64_t id = 0;
+    mpcg_request req{};
+    double t_submit = 0, t_admit = 0, t_feat = 0;
+    int32_t slice0 = 0, nslices = 0;
+    int64_t entry0 = -1, padded = 0;
+    int adm = 0;            // 1: rows and scan enqueued, 2: live
+    bool autoe = false;
+    int feat = 0;           // 0 not started, 1 sweep 1, 2 sweep 2, 3 finishing, 4 done (or none)
+    int64_t guard = 0;      // ignore state copies of groups before this one
+    bool retiring = false;
+    int64_t retire_group = 0;
+    bool cancel = false;
+    int cls = -1;
+    int32_t exact = 0;
+    double eps1 = 0;
+    mpcg_features_t f{};
+};
+
+}  // namespace
+
+struct Engine {
+    int device = 0;
+    mpcg_options opt{};
+    const KnnModel *model = nullptr;
+    BArena a{};
+    hipStream_t s = nullptr;
+    BSys *mirror[2] = {nullptr, nullptr};
+    int32_t mirror_n[2] = {0, 0};
+    int64_t mirror_group[2] = {-1, -1};
+    BSys *stage = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    std::vector<Slot> slots;
+    std::vector<BSys> finals;           // state copy of a slot at completion
+    RangeAlloc slices, entries;
+    int32_t hi_sys = 0, hi_slice = 0;
+    int64_t group = 0;
+
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Pending> pending;        // guarded by mu
+    std::deque<std::pair<uint64_t, mpcg_stats>> done;   // guarded by mu
+    std::vector<uint64_t> cancels;      // guarded by mu
+    int32_t n_queued = 0, n_active = 0; // guarded by mu
+    bool stop = false;                  // guarded by mu
+    std::atomic<bool> failed{false};
+    uint64_t next_id = 1;               // guarded by mu
+    std::thread th;
+
+    std::deque<Pending> local;          // taken from `pending` by the thread
+
+    void run();
+    bool step_once();
+    void finish(Slot &sl, const BSys *M, int status_override);
+    void recompute_hi();
+    void admit();
+    void process(const BSys *m, int32_t cnt, int64_t gi);
+    void fail_all(int status);
+};
+
+void Engine::recompute_hi()
+{
+    int32_t hs = 0, hl = 0;
+    for (int32_t i = 0; i < (int32_t)slots.size(); ++i) {
+        if (!slots[i].used) continue;
+        hs = i + 1;
+        if (slots[i].slice0 + slots[i].nslices > hl) hl = slots[i].slice0 + slots[i].nslices;
+    }
+    hi_sys = hs;
+    hi_slice = hl;
+}
+
+void Engine::finish(Slot &sl, const BSys *M, int status_override)
+{
+    mpcg_stats st{};
+    st.eps1_class = sl.cls;
+    st.eps1_used = sl.req.eps1 == MPCG_EPS1_NONE ? -1.0 : (sl.autoe ? sl.eps1 : sl.req.eps1);
+    if (M) {
+        st.n1 = M->n1;
+        st.n2 = M->n2;
+        st.restarts = M->restarts;
+        st.flags = M->flags | (sl.exact ? MPCG_FLAG_KNN_EXACT : 0);
+        st.status = M->status;
+        st.relres_sp = M->relres_sp;
+        st.relres_restart_true = M->relres_restart;
+        st.relres_final_true = M->relres_final;
+    }
+    if (status_override) st.status = status_override;
+    st.I_third = st.n1 / 3.0 + st.n2;
+    st.t_total_ms = now_ms() - sl.t_submit;
+    st.t_feat_ms = sl.t_feat > 0 ? sl.t_feat - sl.t_admit : 0.0;
+    st.feat = sl.f;
+    std::lock_guard<std::mutex> lk(mu);
+    done.emplace_back(sl.id, st);
+    n_active -= 1;
+}
+
+void Engine::fail_all(int status)
+{
+    failed = true;
+    for (auto &sl : slots) {
+        if (!sl.used) continue;
+        finish(sl, nullptr, status);
+        sl.used = false;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto &p : local) {
+        mpcg_stats st{};
+        st.status = status;
+        done.emplace_back(p.id, st);
+    }
+    for (auto &p : pending) {
+        mpcg_stats st{};
+        st.status = status;
+        done.emplace_back(p.id, st);
+    }
+    n_queued = 0;
+    local.clear();
+    pending.clear();
+}
+
+// Admission, stage 1: a free slot and slice range; rows and the padded-entry
+// scan are enqueued (stage 2 runs once a state copy shows the scan's total).
+void Engine::admit()
+{
+    while (!local.empty()) {
+        int32_t slot = -1;
+        for (int32_t i = 0; i < (int32_t)slots.size(); ++i)
+            if (!slots[i].used) { slot = i; break; }
+        if (slot < 0) return;
+        Pending p = local.front();
+        const mpcg_request &r = p.req;
+        const int32_t n = (int32_t)r.A.n;
+        const int32_t nsl = (n + 63) / 64;
+        const int64_t s0 = slices.alloc(nsl);
+        if (s0 < 0) return;   // wait for space
+        local.pop_front();
+        Slot &sl = slots[slot];
+        sl = Slot{};
+        sl.used = true;
+        sl.id = p.id;
+        sl.req = r;
+        sl.t_submit = p.t_submit;
+        sl.t_admit = now_ms();
+        sl.slice0 = (int32_t)s0;
+        sl.nslices = nsl;
+        sl.adm = 1;
+        sl.autoe = r.eps1 == MPCG_EPS1_AUTO;
+        sl.guard = group;   // the copy after the group enqueued next holds the scan
+        sl.f.n = r.A.n;
+        sl.f.m = r.A.nnz;
+        BSys &S = stage[slot];
+        std::memset(&S, 0, sizeof(BSys));
+        S.row0 = (int32_t)s0 * 64;
+        S.n = n;
+        S.slice0 = (int32_t)s0;
+        S.nslices = nsl;
+        S.nnz = r.A.nnz;
+        S.auto_eps = sl.autoe ? 1 : 0;
+        S.k0 = opt.k0 > 0 ? opt.k0 : 20;
+        S.tol_abs = opt.tol_mode == 1;
+        S.max_restarts = opt.max_restarts >= 0 ? opt.max_restarts : 5;
+        const int64_t mi1 = opt.maxit1 > 0 ? opt.maxit1 : n;
+        const int64_t mi2 = opt.maxit2 > 0 ? opt.maxit2 : (10 * (int64_t)n > 1000 ? 10 * (int64_t)n : 1000);
+        S.maxit1 = (int32_t)(mi1 < 0x7ffffff0 ? mi1 : 0x7ffffff0);
+        S.maxit2 = (int32_t)(mi2 < 0x7ffffff0 ? mi2 : 0x7ffffff0);
+        const int64_t avg = (r.A.nnz + n - 1) / n;
+        int lanes = 1;
+        while (lanes < avg && lanes < 32) lanes <<= 1;
+        S.lanes = lanes;
+        S.eps2 = r.eps2;
+        S.mode = kFree;
+        if (hipMemcpyAsync(&a.sys[slot], &S, sizeof(BSys), hipMemcpyHostToDevice, s) != hipSuccess) {
+            failed = true;
+            return;
+        }
+        launch_admit_rows(s, a, slot, r.A.row_ptr, r.A.row_ptr_is_i64, r.A.nnz, r.b, S.row0, n, S.slice0, nsl);
+        launch_admit_scan(s, a, slot);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            n_queued -= 1;
+            n_active += 1;
+        }
+        recompute_hi();
+    }
+}
+
+void Engine::process(const BSys *m, int32_t cnt, int64_t gi)
+{
+    for (int32_t i = 0; i < (int32_t)slots.size() && i < cnt; ++i) {
+        Slot &sl = slots[i];
+        if (!sl.used || gi < sl.guard) continue;
+        const BSys &M = m[i];
+        if (sl.adm == 1) {
+            sl.padded = M.padded;
+            const int64_t e0 = entries.alloc(sl.padded);
+            if (e0 < 0) {
+                if (sl.padded > a.max_entries) {
+                    finish(sl, nullptr, MPCG_ENOMEM);
+                } else {   // back to the queue until entries free up
+                    std::lock_guard<std::mutex> lk(mu);
+                    local.push_front(Pending{sl.id, sl.req, sl.t_submit});
+                    n_queued += 1;
+                    n_active -= 1;
+                }
+                launch_release(s, a, i, sl.slice0, sl.nslices);
+                slices.release(sl.slice0, sl.nslices);
+                sl.used = false;
+                recompute_hi();
+                continue;
+            }
+            sl.entry0 = e0;
+            stage[i].entry0 = e0;
+            if (hipMemcpyAsync(&a.sys[i].entry0, &stage[i].entry0, sizeof(int64_t), hipMemcpyHostToDevice, s) !=
+                hipSuccess) {
+                failed = true;
+                return;
+            }
+            launch_admit_entries(s, a, i, sl.nslices, sl.req.A.row_ptr, sl.req.A.row_ptr_is_i64, sl.req.A.col_idx,
+                                 sl.req.A.val);
+            launch_admit_finish(s, a, i, sl.nslices, sl.req.eps1);
+            sl.adm = 2;
+            sl.guard = group + 1;
+            continue;
+        }
+        if (sl.retiring) {
+            if (gi >= sl.retire_group) {
+                finish(sl, &finals[i], 0);
+                launch_release(s, a, i, sl.slice0, sl.nslices);
+                slices.release(sl.slice0, sl.nslices);
+                entries.release(sl.entry0, sl.padded);
+                sl.used = false;
+                recompute_hi();
+            }
+            continue;
+        }
+        if (sl.cancel) {
+            launch_cancel(s, a, i);
+            sl.cancel = false;
+            sl.feat = 4;
+            sl.guard = group + 1;
+            continue;
+        }
+        if (sl.autoe && sl.feat < 4) {
+            if (M.err & kErrGuard) {
+                launch_cancel(s, a, i);
+                sl.feat = 4;
+                sl.guard = group + 1;
+                continue;
+            }
+            if (sl.feat == 0) {
+                if (M.err || M.mode == kDone) {
+                    sl.feat = 4;   // malformed input or nothing to solve: no features
+                } else {
+                    launch_bfs_start(s, a, i);
+                    sl.feat = 1;
+                    sl.guard = group + 1;
+                    continue;
+                }
+            } else if (sl.feat == 1 && M.bfs_mode == kBfsSwept) {
+                launch_bfs_next_sweep(s, a, i);
+                sl.feat = 2;
+                sl.guard = group + 1;
+                continue;
+            } else if (sl.feat == 2 && M.bfs_mode == kBfsSwept) {
+                launch_bfs_finish(s, a, i);
+                sl.feat = 3;
+                sl.guard = group + 1;
+                continue;
+            } else if (sl.feat == 3 && M.bfs_mode == kBfsDone && !(M.mode == kCg32 && M.k0_used == 0)) {
+                sl.f.pdiam = M.pdiam;
+                sl.f.bfs_t = M.bfs_t;
+                sl.f.bfs_u = M.bfs_u;
+                sl.f.n_components = M.ncomp;
+                sl.f.k0_used = M.k0_used;
+                double sum = 0.0;
+                for (int j = 0; j < M.k0_used && j < kK0Max; ++j) sum = sum + M.ratios[j];
+                sl.f.v = M.k0_used > 0 ? sum / (double)M.k0_used : 0.0;
+                const double chi[4] = {(double)sl.f.n, (double)sl.f.m, (double)sl.f.pdiam, sl.f.v};
+                sl.exact = 0;
+                const int cls = knn_select(*model, chi, opt.knn_k, &sl.exact);
+                sl.cls = (cls >= 2 && cls <= 7) ? cls : 4;
+                sl.eps1 = kEpsClass[sl.cls];
+                launch_set_eps(s, a, i, sl.eps1);
+                sl.t_feat = now_ms();
+                sl.feat = 4;
+                sl.guard = group + 1;
+                continue;
+            }
+        }
+        if (M.mode == kDone && (!sl.autoe || sl.feat == 4)) {
+            const int st = M.status;
+            if (st != MPCG_EINVAL && st != MPCG_ECANCELED && sl.req.x) {
+                if (hipMemcpyAsync(sl.req.x, a.x64 + M.row0, sizeof(double) * (size_t)M.n, hipMemcpyDeviceToDevice,
+                                   s) != hipSuccess) {
+                    failed = true;
+                    return;
+                }
+            }
+            // the statistics are final in this copy; x is complete once the state copy of
+            // the next group has been taken (same stream)
+            finals[i] = M;
+            sl.retiring = true;
+            sl.retire_group = group + 1;
+            sl.guard = group + 1;
+        }
+    }
+}
+
+bool Engine::step_once()
+{
+    // new submissions and cancellations
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        while (!pending.empty()) {
+            local.push_back(pending.front());
+            pending.pop_front();
+        }
+        for (uint64_t id : cancels) {
+            bool found = false;
+            for (auto it = local.begin(); it != local.end(); ++it) {
+                if (it->id != id) continue;
+                mpcg_stats st{};
+                st.status = MPCG_ECANCELED;
+                done.emplace_back(id, st);
+                local.erase(it);
+                n_queued -= 1;
+                found = true;
+                break;
+            }
+            if (found) continue;
+            for (auto &sl : slots)
+                if (sl.used && sl.id == id && !sl.retiring) sl.cancel = true;
+        }
+        cancels.clear();
+    }
+    admit();
+    if (failed) return false;
+    bool any_used = false, any_live = false;
+    for (auto &sl : slots) {
+        if (!sl.used) continue;
+        any_used = true;
+        if (sl.adm == 2 && !sl.retiring) any_live = true;
+    }
+    if (!any_used) return true;
+    const int k = (int)(group & 1);
+    if (any_live)
+        for (int g = 0; g < kGroupSteps; ++g) launch_step(s, a, hi_slice, hi_sys);
+    if (hipGetLastError() != hipSuccess) return false;
+    mirror_n[k] = hi_sys;
+    mirror_group[k] = group;
+    if (hi_sys > 0 &&
+        hipMemcpyAsync(mirror[k], a.sys, sizeof(BSys) * (size_t)hi_sys, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return false;
+    if (hipEventRecord(ev[k], s) != hipSuccess) return false;
+    const int kp = k ^ 1;
+    if (mirror_group[kp] >= 0 && mirror_group[kp] == group - 1) {
+        if (hipEventSynchronize(ev[kp]) != hipSuccess) return false;
+        process(mirror[kp], mirror_n[kp], group - 1);
+        if (failed) return false;
+    }
+    group += 1;
+    return true;
+}
+
+void Engine::run()
+{
+    if (hipSetDevice(device) != hipSuccess) {
+        fail_all(MPCG_EDEVICE);
+        return;
+    }
+    for (;;) {
+        bool idle;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            if (stop) break;
+            bool any_used = false;
+            for (auto &sl : slots) any_used = any_used || sl.used;
+            idle = !any_used && local.empty() && pending.empty() && cancels.empty();
+            if (idle) {
+                cv.wait_for(lk, std::chrono::milliseconds(20));
+                continue;
+            }
+        }
+        if (!step_once()) {
+            (void)hipStreamSynchronize(s);
+            fail_all(MPCG_EDEVICE);
+            std::unique_lock<std::mutex> lk(mu);
+            while (!stop) cv.wait_for(lk, std::chrono::milliseconds(20));
+            break;
+        }
+    }
+    (void)hipStreamSynchronize(s);
+}
+
+// ------------------------------------------------------------ interface --
+
+Engine *engine_create(int device, const mpcg_options &opt, const KnnModel *model, void *arena, size_t bytes,
+                      int64_t max_rows, int64_t max_entries, int32_t max_sys, int *status)
+{
+    const int64_t max_slices = (max_rows + 63) / 64;
+    if (max_slices <= 0 || max_slices > (0x7fffffff / 64) || max_entries <= 0 || max_sys <= 0 ||
+        max_sys > (1 << 16) || !arena) {
+        *status = MPCG_EINVAL;
+        return nullptr;
+    }
+    if (bytes < arena_bytes(max_sys, (int32_t)max_slices, max_entries)) {
+        *status = MPCG_ENOMEM;
+        return nullptr;
+    }
+    Engine *e = new (std::nothrow) Engine();
+    if (!e) {
+        *status = MPCG_EDEVICE;
+        return nullptr;
+    }
+    e->device = device;
+    e->opt = opt;
+    e->model = model;
+    e->a = carve(arena, max_sys, (int32_t)max_slices, max_entries);
+    e->slots.resize(max_sys);
+    e->finals.resize(max_sys);
+    e->slices.init(max_slices);
+    e->entries.init(max_entries);
+    bool ok = hipStreamCreateWithFlags(&e->s, hipStreamNonBlocking) == hipSuccess;
+    for (int k = 0; k < 2 && ok; ++k) {
+        ok = hipHostMalloc((void **)&e->mirror[k], sizeof(BSys) * (size_t)max_sys, hipHostMallocDefault) ==
+                 hipSuccess &&
+             hipEventCreateWithFlags(&e->ev[k], hipEventDisableTiming) == hipSuccess;
+    }
+    ok = ok && hipHostMalloc((void **)&e->stage, sizeof(BSys) * (size_t)max_sys, hipHostMallocDefault) == hipSuccess;
+    if (ok) {
+        ok = hipMemsetAsync(e->a.sys, 0, sizeof(BSys) * (size_t)max_sys, e->s) == hipSuccess;
+        launch_fill_slices(e->s, e->a);
+        ok = ok && hipGetLastError() == hipSuccess && hipStreamSynchronize(e->s) == hipSuccess;
+    }
+    if (!ok) {
+        engine_destroy(e);
+        *status = MPCG_EDEVICE;
+        return nullptr;
+    }
+    e->th = std::thread([e]() { e->run(); });
+    *status = MPCG_OK;
+    return e;
+}
+
+void engine_destroy(Engine *e)
+{
+    if (!e) return;
+    {
+        std::lock_guard<std::mutex> lk(e->mu);
+        e->stop = true;
+    }
+    e->cv.notify_all();
+    if (e->th.joinable()) e->th.join();
+    if (e->s) {
+        (void)hipStreamSynchronize(e->s);
+        (void)hipStreamDestroy(e->s);
+    }
+    for (auto &v : e->ev) if (v) (void)hipEventDestroy(v);
+    for (auto &m : e->mirror) if (m) (void)hipHostFree(m);
+    if (e->stage) (void)hipHostFree(e->stage);
+    delete e;
+}
+
+int engine_submit(Engine *e, const mpcg_request *reqs, int32_t count, uint64_t *ids)
+{
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (e->failed) return MPCG_EDEVICE;
+    const double t = now_ms();
+    for (int32_t i = 0; i < count; ++i) {
+        const uint64_t id = e->next_id++;
+        ids[i] = id;
+        e->pending.push_back(Pending{id, reqs[i], t});
+        e->n_queued += 1;
+    }
+    e->cv.notify_one();
+    return MPCG_OK;
+}
+
+int engine_poll(Engine *e, uint64_t *ids, mpcg_stats *stats, int32_t cap, int32_t *n_done)
+{
+    std::lock_guard<std::mutex> lk(e->mu);
+    int32_t k = 0;
+    while (k < cap && !e->done.empty()) {
+        ids[k] = e->done.front().first;
+        if (stats) stats[k] = e->done.front().second;
+        e->done.pop_front();
+        ++k;
+    }
+    *n_done = k;
+    return MPCG_OK;
+}
+
+int engine_cancel(Engine *e, uint64_t id)
+{
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (id == 0 || id >= e->next_id) return MPCG_EINVAL;
+    e->cancels.push_back(id);
+    e->cv.notify_one();
+    return MPCG_OK;
+}
+
+int engine_load(Engine *e, int32_t *queued, int32_t *active)
+{
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (queued) *queued = e->n_queued;
+    if (active) *active = e->n_active;
+    return MPCG_OK;
+}
+
+int64_t engine_max_slices(const Engine *e) { return e->a.max_slices; }
+int64_t engine_max_entries(const Engine *e) { return e->a.max_entries; }
+
+}  // namespace batch
+}  // namespace mpcg

@@ -1,0 +1,143 @@
+// Batched engine: many independent systems solved together.
+//
+// Every admitted system owns a contiguous range of 64-row slices in one
+// shared row space (its rows padded to a multiple of 64, so a slice never
+// holds rows of two systems) and a contiguous range of SELL-64 entries.  The
+// union of the systems is a block-diagonal matrix; one "step" advances every
+// system by one unit of its own state machine with a fixed set of launches
+// that cover all slices at once:
+//
+//   k_b_product   per slice: the CG product, the restart residual or the
+//                 final-check residual of the slice's system, as its mode says;
+//                 one partial per slice
+//   k_b_scalar1   one block per system: its partials -> delta / alpha, or the
+//                 restart and final-check decisions
+//   k_b_update    per slice: r -= alpha q, x += alpha d, partial of r.r
+//   k_b_scalar2   one block per system: gamma, stop tests, beta, v ratios
+//   k_b_bfs_*     2BFS levels of the systems whose features are pending
+//
+// Per-system sums are taken over that system's slice partials in a fixed
+// order, so a system's arithmetic does not depend on which other systems
+// share the batch: a solve gives the same bits alone and in any mix.
+
+#pragma once
+
+#include "knn.hpp"
+#include "mpcg_internal.hpp"
+
+namespace mpcg {
+namespace batch {
+
+enum Mode : int32_t {
+    kFree = 0,      // slot unused
+    kHold = 1,      // FP32 prefix done, waiting for eps1 (Algorithm II)
+    kCg32 = 2,
+    kRestart = 3,   // next product forms r = b - A x in FP64
+    kCg64 = 4,
+    kResid = 5,     // next product forms ||b - A x||
+    kDone = 6,
+};
+
+enum RestartSrc : int32_t { kSrcX32 = 0, kSrcX64 = 1, kSrcZero = 2 };
+
+enum BfsMode : int32_t {
+    kBfsNone = 0,
+    kBfsRun = 1,    // a sweep is expanding
+    kBfsSwept = 2,  // a sweep ended; the host finishes it (argmax, next seed)
+    kBfsDone = 3,   // pdiam, t, u, ncomp are final
+};
+
+constexpr int kSlicesPerBlock = kBlock / 64;
+constexpr int32_t kErrGuard = 64;     // a bounded device loop ran out (union-find)
+constexpr int kSmallBfsCap = 2048;   // frontier kept in LDS by the one-block-per-system kernel
+constexpr int kSmallBfsLevels = 16;  // levels one launch may expand for one system
+
+struct alignas(256) BSys {
+    // set at admission
+    int32_t row0, n, slice0, nslices;
+    int64_t nnz, entry0;
+    int32_t auto_eps, k0, tol_abs, max_restarts;
+    int32_t maxit1, maxit2, lanes, err;
+    double eps2;
+    // recurrence
+    int32_t mode, ph_it, n1, n2;
+    int32_t restarts, flags, status, src;
+    int32_t upd, k0_used, eps_set, pend;   // pend: status to report after the final residual
+    double gamma, gamma_prev, delta, alpha, beta, bb, thr1, thr2;
+    double relres_sp, relres_restart, relres_final;
+    double ratios[kK0Max];
+    // 2BFS
+    int32_t bfs_mode, bfs_sweep, bfs_level, bfs_cnt;
+    int32_t bfs_nxt, ncomp, pdiam, bfs_t;
+    int32_t bfs_u, small, pad0, pad1;
+    int64_t padded;                        // SELL-64 entries of the system (admission scan)
+    unsigned long long comp_best;
+    int64_t item0;                         // first BFS work item of this system in the current level
+};
+
+// Device pointers of the batch arena.
+struct BArena {
+    BSys *sys;
+    int32_t max_sys, max_slices;
+    int64_t max_entries;
+    // per slice
+    int32_t *slice_w, *sys_of_slice;
+    int64_t *slice_off;                    // local to the system's entry range
+    double *pslice;                        // 2 per slice
+    // per row
+    int32_t *rowlen;
+    double *b64, *x64, *r64, *q64, *dA64, *dB64;
+    float *x32, *r32, *q32, *dA32, *dB32;
+    int32_t *dist, *q0, *q1, *label, *tarr;
+    unsigned long long *best;
+    // per entry
+    int32_t *col;
+    double *v64;
+    float *v32;
+    // BFS work lists
+    int32_t *act_sys;                      // systems expanding a large level this step
+    int64_t *act_pre;                      // their exclusive item prefix
+    int32_t *small_sys;                    // systems expanding small levels this step
+    int32_t *counts;                       // [0] = #act, [1] = #small, [2] = admission error (unused)
+    int64_t *items;                        // total items of the large level
+};
+
+size_t arena_bytes(int32_t max_sys, int32_t max_slices, int64_t max_entries);
+BArena carve(void *base, int32_t max_sys, int32_t max_slices, int64_t max_entries);
+
+// ---- admission (one system) ----
+void launch_admit_rows(hipStream_t s, const BArena &a, int32_t sys, const void *rp, int rp_i64, int64_t nnz,
+                       const double *b, int32_t row0, int32_t n, int32_t slice0, int32_t nslices);
+void launch_admit_scan(hipStream_t s, const BArena &a, int32_t sys);
+void launch_admit_entries(hipStream_t s, const BArena &a, int32_t sys, int32_t nslices, const void *rp,
+                          int rp_i64, const int32_t *col, const double *val);
+// start mode from the options, then the slices become visible to the step
+void launch_admit_finish(hipStream_t s, const BArena &a, int32_t sys, int32_t nslices, double eps1);
+void launch_release(hipStream_t s, const BArena &a, int32_t sys, int32_t slice0, int32_t nslices);
+void launch_cancel(hipStream_t s, const BArena &a, int32_t sys);
+// Algorithm II: eps1 chosen by the host
+void launch_set_eps(hipStream_t s, const BArena &a, int32_t sys, double eps1);
+void launch_fill_slices(hipStream_t s, const BArena &a);   // every slice unowned
+
+// ---- one step over all systems ----
+void launch_step(hipStream_t s, const BArena &a, int32_t hi_slice, int32_t hi_sys);
+
+// ---- 2BFS of one system (host-driven transitions) ----
+void launch_bfs_start(hipStream_t s, const BArena &a, int32_t sys);          // CC + sweep-1 seeds
+void launch_bfs_next_sweep(hipStream_t s, const BArena &a, int32_t sys);     // argmax + sweep-2 seeds
+void launch_bfs_finish(hipStream_t s, const BArena &a, int32_t sys);         // argmax + per-system result
+
+// ---- host engine (batch_engine.hip) ----
+struct Engine;
+Engine *engine_create(int device, const mpcg_options &opt, const KnnModel *model, void *arena, size_t bytes,
+                      int64_t max_rows, int64_t max_entries, int32_t max_sys, int *status);
+void engine_destroy(Engine *e);
+int engine_submit(Engine *e, const mpcg_request *reqs, int32_t count, uint64_t *ids);
+int engine_poll(Engine *e, uint64_t *ids, mpcg_stats *stats, int32_t cap, int32_t *n_done);
+int engine_cancel(Engine *e, uint64_t id);
+int engine_load(Engine *e, int32_t *queued, int32_t *active);
+int64_t engine_max_slices(const Engine *e);
+int64_t engine_max_entries(const Engine *e);
+
+}  // namespace batch
+}  // namespace mpcg

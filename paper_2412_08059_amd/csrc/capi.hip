@@ -3,6 +3,7 @@
 // context stream; the host polls one device-state snapshot per group of
 // iterations while the next group is already queued.
 
+#include "batch_internal.hpp"
 #include "mpcg_internal.hpp"
 
 #include <atomic>
@@ -42,6 +43,7 @@ struct mpcg_ctx {
     int sell_batch = 4;       // MPCG_SELL_BATCH=4|8: loads in flight per row in the SELL kernels
     int cg_grid = kMaxGrid;   // MPCG_CG_GRID: most blocks of a CG product launch
     int up_grid = kUpdateGrid;   // MPCG_UP_GRID: most blocks of a CG update launch
+    mpcg::batch::Engine *eng = nullptr;   // batched engine (own thread and stream), if started
 };
 
 #define HIPCHK(x)                                        \
@@ -524,6 +526,7 @@ mpcg_status mpcg_create(mpcg_ctx **out, const mpcg_options *opt, void *hip_strea
 mpcg_status mpcg_destroy(mpcg_ctx *c)
 {
     if (!c) return MPCG_EINVAL;
+    if (c->eng) mpcg::batch::engine_destroy(c->eng);
     (void)hipStreamSynchronize(c->stream);
     if (c->side_stream) {
         (void)hipStreamSynchronize(c->side_stream);
@@ -893,6 +896,71 @@ mpcg_status mpcg_time_kernel(mpcg_ctx *c, const mpcg_csr *A, int32_t kernel, int
     if (!s.live) return MPCG_EDEVICE;   // a launch exited early: the timing would be wrong
     *ms = elapsed(c->tm[5], c->tm[6]) / reps;
     return MPCG_OK;
+}
+
+// ------------------------------------------------------------- batches --
+
+mpcg_status mpcg_batch_workspace_size(const mpcg_ctx *c, int64_t max_rows, int64_t max_entries,
+                                      int32_t max_systems, size_t *bytes)
+{
+    if (!c || !bytes || max_rows <= 0 || max_entries <= 0 || max_systems <= 0 || max_systems > (1 << 16))
+        return MPCG_EINVAL;
+    const int64_t ms = (max_rows + 63) / 64;
+    if (ms > 0x7fffffff / 64) return MPCG_EINVAL;
+    *bytes = mpcg::batch::arena_bytes(max_systems, (int32_t)ms, max_entries);
+    return MPCG_OK;
+}
+
+mpcg_status mpcg_batch_set_workspace(mpcg_ctx *c, void *arena, size_t bytes, int64_t max_rows,
+                                     int64_t max_entries, int32_t max_systems)
+{
+    if (!c || !arena || ((uintptr_t)arena & 255)) return MPCG_EINVAL;
+    if (c->eng) return MPCG_EBUSY;
+    int st = MPCG_OK;
+    c->eng = mpcg::batch::engine_create(c->device, c->opt, &c->model, arena, bytes, max_rows, max_entries,
+                                        max_systems, &st);
+    return (mpcg_status)st;
+}
+
+mpcg_status mpcg_batch_submit(mpcg_ctx *c, const mpcg_request *reqs, int32_t count, uint64_t *ids)
+{
+    if (!c || count < 0 || (count > 0 && (!reqs || !ids))) return MPCG_EINVAL;
+    if (!c->eng) return MPCG_EDEVICE;
+    for (int32_t i = 0; i < count; ++i) {
+        const mpcg_request &r = reqs[i];
+        if (r.A.n <= 0 || r.A.n > 0x7fffffc0 || r.A.nnz < 0 || !r.A.row_ptr || !r.b || !r.x) return MPCG_EINVAL;
+        if (r.A.nnz > 0 && (!r.A.col_idx || !r.A.val)) return MPCG_EINVAL;
+        if (!(r.eps2 > 0.0) || !std::isfinite(r.eps2)) return MPCG_EINVAL;
+        const bool autoe = r.eps1 == MPCG_EPS1_AUTO, none = r.eps1 == MPCG_EPS1_NONE;
+        if (!autoe && !none && !(r.eps1 > 0.0 && std::isfinite(r.eps1))) return MPCG_EINVAL;
+        if (autoe && (!c->has_model || c->model.ns <= 0)) return MPCG_ENOMODEL;
+        if ((r.A.n + 63) / 64 > mpcg::batch::engine_max_slices(c->eng) ||
+            r.A.nnz > mpcg::batch::engine_max_entries(c->eng))
+            return MPCG_ENOMEM;
+    }
+    return (mpcg_status)mpcg::batch::engine_submit(c->eng, reqs, count, ids);
+}
+
+mpcg_status mpcg_batch_poll(mpcg_ctx *c, uint64_t *done_ids, mpcg_stats *done_stats, int32_t cap,
+                            int32_t *n_done)
+{
+    if (!c || !n_done || cap < 0 || (cap > 0 && !done_ids)) return MPCG_EINVAL;
+    if (!c->eng) return MPCG_EDEVICE;
+    return (mpcg_status)mpcg::batch::engine_poll(c->eng, done_ids, done_stats, cap, n_done);
+}
+
+mpcg_status mpcg_batch_cancel(mpcg_ctx *c, uint64_t id)
+{
+    if (!c) return MPCG_EINVAL;
+    if (!c->eng) return MPCG_EDEVICE;
+    return (mpcg_status)mpcg::batch::engine_cancel(c->eng, id);
+}
+
+mpcg_status mpcg_batch_load(mpcg_ctx *c, int32_t *queued, int32_t *active)
+{
+    if (!c) return MPCG_EINVAL;
+    if (!c->eng) return MPCG_EDEVICE;
+    return (mpcg_status)mpcg::batch::engine_load(c->eng, queued, active);
 }
 
 }  // extern "C"

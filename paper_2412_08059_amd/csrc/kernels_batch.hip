@@ -1,0 +1,1019 @@
+// Kernels of the batched engine (gfx950, wave64).  The layout and the step
+// are described in batch_internal.hpp.  Per system the arithmetic is the one
+// of the single-system path: the CG procedure of the paper's "Conjugate
+// Gradient Method" section in FP32 (dots accumulated in FP64, alpha and beta
+// rounded to FP32), the restart of Algorithm I step 5 (float64(x~), residual
+// b - A x in FP64), the FP64 phase, the final true-residual check, and the
+// 2BFS of the section "Computing Pseudo-Diameter of the Graph Matrix" per
+// connected component.
+
+#include "batch_internal.hpp"
+
+#include <cmath>
+
+namespace mpcg {
+namespace batch {
+
+namespace {
+
+constexpr int kIntMax = 0x7fffffff;
+constexpr int kLoadBatch = 4;
+
+template <typename T> __device__ inline T fma_b(T a, T b, T c);
+template <> __device__ inline float fma_b<float>(float a, float b, float c) { return fmaf(a, b, c); }
+template <> __device__ inline double fma_b<double>(double a, double b, double c) { return fma(a, b, c); }
+
+__device__ inline double wave_sum_d(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline int wave_max_i32(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        const int o = __shfl_xor(v, off, 64);
+        v = v > o ? v : o;
+    }
+    return v;
+}
+
+// Fixed-order block sum (kBlock threads); the result is valid in thread 0.
+__device__ inline double block_sum_d(double v, double *sm)
+{
+    v = wave_sum_d(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sm[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kBlock / 64; ++i) s += sm[i];
+    __syncthreads();
+    return s;
+}
+
+// Sum of component j of the slice partials of system S, fixed order.
+__device__ inline double sys_sum(const BArena &a, const BSys &S, int j, double *sm)
+{
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < S.nslices; i += kBlock) acc += a.pslice[2 * (size_t)(S.slice0 + i) + j];
+    return block_sum_d(acc, sm);
+}
+
+__device__ inline int64_t rp_at(const void *rp, int i64, int64_t i)
+{
+    return i64 ? static_cast<const int64_t *>(rp)[i] : (int64_t) static_cast<const int32_t *>(rp)[i];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- arena --
+
+static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t arena_bytes(int32_t max_sys, int32_t max_slices, int64_t max_entries)
+{
+    const size_t rows = (size_t)max_slices * 64, sl = (size_t)max_slices, e = (size_t)max_entries;
+    size_t t = 0;
+    t += up256(sizeof(BSys) * (size_t)max_sys);
+    t += up256(4 * sl) * 2 + up256(8 * sl) + up256(16 * sl);          // slice_w, sys_of_slice, slice_off, pslice
+    t += up256(4 * rows);                                             // rowlen
+    t += up256(8 * rows) * 6 + up256(4 * rows) * 5;                   // FP64 and FP32 vectors
+    t += up256(4 * rows) * 5 + up256(8 * rows);                       // BFS
+    t += up256(4 * e) + up256(8 * e) + up256(4 * e);                  // col, v64, v32
+    t += up256(4 * (size_t)max_sys) * 2 + up256(8 * (size_t)max_sys) + 256 + 256;
+    return t;
+}
+
+BArena carve(void *base, int32_t max_sys, int32_t max_slices, int64_t max_entries)
+{
+    BArena a{};
+    char *p = static_cast<char *>(base);
+    const size_t rows = (size_t)max_slices * 64, sl = (size_t)max_slices, e = (size_t)max_entries;
+    auto take = [&](size_t bytes) { char *q = p; p += up256(bytes); return q; };
+    a.max_sys = max_sys;
+    a.max_slices = max_slices;
+    a.max_entries = max_entries;
+    a.sys = reinterpret_cast<BSys *>(take(sizeof(BSys) * (size_t)max_sys));
+    a.slice_w = reinterpret_cast<int32_t *>(take(4 * sl));
+    a.sys_of_slice = reinterpret_cast<int32_t *>(take(4 * sl));
+    a.slice_off = reinterpret_cast<int64_t *>(take(8 * sl));
+    a.pslice = reinterpret_cast<double *>(take(16 * sl));
+    a.rowlen = reinterpret_cast<int32_t *>(take(4 * rows));
+    a.b64 = reinterpret_cast<double *>(take(8 * rows));
+    a.x64 = reinterpret_cast<double *>(take(8 * rows));
+    a.r64 = reinterpret_cast<double *>(take(8 * rows));
+    a.q64 = reinterpret_cast<double *>(take(8 * rows));
+    a.dA64 = reinterpret_cast<double *>(take(8 * rows));
+    a.dB64 = reinterpret_cast<double *>(take(8 * rows));
+    a.x32 = reinterpret_cast<float *>(take(4 * rows));
+    a.r32 = reinterpret_cast<float *>(take(4 * rows));
+    a.q32 = reinterpret_cast<float *>(take(4 * rows));
+    a.dA32 = reinterpret_cast<float *>(take(4 * rows));
+    a.dB32 = reinterpret_cast<float *>(take(4 * rows));
+    a.dist = reinterpret_cast<int32_t *>(take(4 * rows));
+    a.q0 = reinterpret_cast<int32_t *>(take(4 * rows));
+    a.q1 = reinterpret_cast<int32_t *>(take(4 * rows));
+    a.label = reinterpret_cast<int32_t *>(take(4 * rows));
+    a.tarr = reinterpret_cast<int32_t *>(take(4 * rows));
+    a.best = reinterpret_cast<unsigned long long *>(take(8 * rows));
+    a.col = reinterpret_cast<int32_t *>(take(4 * e));
+    a.v64 = reinterpret_cast<double *>(take(8 * e));
+    a.v32 = reinterpret_cast<float *>(take(4 * e));
+    a.act_sys = reinterpret_cast<int32_t *>(take(4 * (size_t)max_sys));
+    a.small_sys = reinterpret_cast<int32_t *>(take(4 * (size_t)max_sys));
+    a.act_pre = reinterpret_cast<int64_t *>(take(8 * (size_t)max_sys));
+    a.counts = reinterpret_cast<int32_t *>(take(256));
+    a.items = reinterpret_cast<int64_t *>(take(256));
+    return a;
+}
+
+// ------------------------------------------------------------ admission --
+
+__global__ void k_fill_slice_w(BArena a, int32_t slice0, int32_t nslices)
+{
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j < nslices) a.slice_w[slice0 + j] = 0;
+}
+
+__global__ void k_fill_slices(BArena a)
+{
+    for (int j = blockIdx.x * kBlock + threadIdx.x; j < a.max_slices; j += gridDim.x * kBlock)
+        a.sys_of_slice[j] = -1;
+}
+
+void launch_fill_slices(hipStream_t s, const BArena &a)
+{
+    int g = (a.max_slices + kBlock - 1) / kBlock;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_fill_slices, dim3(g < 1 ? 1 : g), dim3(kBlock), 0, s, a);
+}
+
+// Thread per (padded) row of the system: row length, slice width, b, the FP32
+// start r~ = float32(b), x = 0, and per-slice partials of r~.r~ and b.b.
+__global__ void __launch_bounds__(kBlock)
+k_admit_rows(BArena a, int32_t sys, const void *rp, int rp_i64, const double *b, int32_t row0, int32_t n,
+             int64_t nnz, int32_t slice0, int32_t nslices)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;   // local row
+    if (i >= (int64_t)nslices * 64) return;
+    const int64_t g = row0 + i;
+    int err = 0, len = 0;
+    double bv = 0.0;
+    if (i < n) {
+        const int64_t lo = rp_at(rp, rp_i64, i), hi = rp_at(rp, rp_i64, i + 1);
+        if (i == 0 && lo != 0) err |= kErrRowPtr;
+        if (i == n - 1 && hi != nnz) err |= kErrRowPtr;
+        if (lo < 0 || hi < lo || hi > nnz || hi - lo > 0x7fffffff) err |= kErrRowPtr;
+        else len = (int)(hi - lo);
+        bv = b[i];
+        if (!isfinite(bv)) err |= kErrNonFiniteB;
+    }
+    a.rowlen[g] = len;
+    a.b64[g] = bv;
+    a.x64[g] = 0.0;
+    a.x32[g] = 0.0f;
+    const float rv = (float)bv;
+    a.r32[g] = rv;
+    a.r64[g] = 0.0;
+    a.q64[g] = 0.0;
+    a.q32[g] = 0.0f;
+    a.dA64[g] = 0.0;
+    a.dB64[g] = 0.0;
+    a.dA32[g] = 0.0f;
+    a.dB32[g] = 0.0f;
+    const int sl = slice0 + (int)(i >> 6);
+    if (len > 0) atomicMax(&a.slice_w[sl], len);
+    const double pr = wave_sum_d((double)rv * (double)rv);
+    const double pb = wave_sum_d(bv * bv);
+    for (int o = 32; o > 0; o >>= 1) err |= __shfl_xor(err, o, 64);
+    if ((threadIdx.x & 63) == 0) {
+        a.pslice[2 * (size_t)sl] = pr;
+        a.pslice[2 * (size_t)sl + 1] = pb;
+        a.sys_of_slice[sl] = -1;   // not visible to the step kernels until the system is complete
+        if (err) atomicOr(&a.sys[sys].err, err);
+    }
+}
+
+// Padded entry offsets of the system's slices (local to its entry range).
+__global__ void __launch_bounds__(1024) k_admit_scan(BArena a, int32_t sys)
+{
+    __shared__ int64_t part[1024];
+    BSys &S = a.sys[sys];
+    const int ns = S.nslices, s0 = S.slice0;
+    const int per = (ns + 1023) / 1024;
+    const int b0 = threadIdx.x * per, b1 = min(b0 + per, ns);
+    int64_t acc = 0;
+    for (int j = b0; j < b1; ++j) acc += (int64_t)a.slice_w[s0 + j] * 64;
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int t = 0; t < 1024; ++t) {
+            const int64_t v = part[t];
+            part[t] = run;
+            run += v;
+        }
+        S.padded = run;
+    }
+    __syncthreads();
+    int64_t run = part[threadIdx.x];
+    for (int j = b0; j < b1; ++j) {
+        a.slice_off[s0 + j] = run;
+        run += (int64_t)a.slice_w[s0 + j] * 64;
+    }
+}
+
+// Wave per slice: column range, strictly increasing columns and finite
+// values checked; entries written column-major inside the slice with global
+// column indices.  Lanes past a row's length get a zero entry on their own
+// row, which the products never read (they stop at the row length).
+__global__ void __launch_bounds__(kBlock)
+k_admit_entries(BArena a, int32_t sys, const void *rp, int rp_i64, const int32_t *col, const double *val)
+{
+    const BSys &S = a.sys[sys];
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * kSlicesPerBlock + (threadIdx.x >> 6);
+    if (j >= S.nslices) return;
+    const int sl = S.slice0 + j;
+    const int64_t i = (int64_t)j * 64 + lane;
+    const int64_t g = S.row0 + i;
+    const int W = a.slice_w[sl];
+    const int64_t base = S.entry0 + a.slice_off[sl] + lane;
+    const int len = a.rowlen[g];
+    const int64_t lo = i < S.n ? rp_at(rp, rp_i64, i) : 0;
+    int err = 0, prev = -1;
+    for (int k = 0; k < W; ++k) {
+        int cg = (int)g;
+        double v = 0.0;
+        if (k < len && lo >= 0 && lo + k < S.nnz) {   // rows with bad pointers have len 0 already
+            const int c = col[lo + k];
+            v = val[lo + k];
+            if (c < 0 || c >= S.n) err |= kErrCol;
+            else if (c <= prev) err |= kErrUnsorted;
+            if (!isfinite(v)) err |= kErrNonFiniteA;
+            prev = c;
+            cg = S.row0 + (c >= 0 && c < S.n ? c : 0);
+        }
+        a.col[base + (int64_t)k * 64] = cg;
+        a.v64[base + (int64_t)k * 64] = v;
+        a.v32[base + (int64_t)k * 64] = (float)v;
+    }
+    for (int o = 32; o > 0; o >>= 1) err |= __shfl_xor(err, o, 64);
+    if (lane == 0 && err) atomicOr(&a.sys[sys].err, err);
+}
+
+// Start state.  Host-filled fields (options, ranges) are already in place.
+__global__ void __launch_bounds__(kBlock) k_admit_finish(BArena a, int32_t sys, double eps1)
+{
+    __shared__ double sm[kBlock / 64 + 1];
+    BSys &S = a.sys[sys];
+    const double g0 = sys_sum(a, S, 0, sm);
+    const double bb = sys_sum(a, S, 1, sm);
+    if (threadIdx.x == 0) {
+        S.bb = bb;
+        S.gamma = g0;
+        S.ph_it = 0;
+        S.n1 = S.n2 = 0;
+        S.restarts = 0;
+        S.upd = 0;
+        const double sb = sqrt(bb);
+        S.thr2 = S.tol_abs ? S.eps2 : S.eps2 * sb;
+        if (S.err) {
+            S.status = (S.err & (kErrNonFiniteA | kErrNonFiniteB)) ? MPCG_ENONFINITE : MPCG_EINVAL;
+            S.mode = kDone;
+        } else if (bb == 0.0) {
+            S.status = MPCG_OK;
+            S.mode = kDone;
+        } else if (eps1 == MPCG_EPS1_NONE) {
+            S.src = kSrcZero;
+            S.mode = kRestart;
+        } else {
+            S.eps_set = S.auto_eps ? 0 : 1;
+            S.thr1 = S.auto_eps ? 0.0 : (S.tol_abs ? eps1 : eps1 * sb);
+            if (S.auto_eps) {
+                S.mode = g0 == 0.0 ? kHold : kCg32;
+            } else if (sqrt(g0) <= S.thr1) {
+                S.relres_sp = sqrt(g0) / sb;
+                S.src = kSrcX32;
+                S.mode = kRestart;
+            } else {
+                S.mode = kCg32;
+            }
+        }
+    }
+}
+
+// Marks the system's slices as live (after every admission kernel).
+__global__ void k_admit_publish(BArena a, int32_t sys)
+{
+    const BSys &S = a.sys[sys];
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < S.nslices; j += gridDim.x * blockDim.x)
+        a.sys_of_slice[S.slice0 + j] = sys;
+}
+
+__global__ void k_release(BArena a, int32_t sys, int32_t slice0, int32_t nslices)
+{
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < nslices; j += gridDim.x * blockDim.x)
+        a.sys_of_slice[slice0 + j] = -1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.sys[sys].mode = kFree;
+        a.sys[sys].bfs_mode = kBfsNone;
+    }
+}
+
+__global__ void k_cancel(BArena a, int32_t sys)
+{
+    if (threadIdx.x == 0) {
+        BSys &S = a.sys[sys];
+        S.mode = kDone;
+        S.status = MPCG_ECANCELED;
+        S.upd = 0;
+        if (S.bfs_mode == kBfsRun || S.bfs_mode == kBfsSwept) S.bfs_mode = kBfsNone;
+    }
+}
+
+// Algorithm II: eps1 from the kNN choice.  A system holding after its k0
+// prefix continues with the eps1 test (Remark 3); one still in the prefix
+// picks the test up when the prefix ends.
+__global__ void k_set_eps(BArena a, int32_t sys, double eps1)
+{
+    if (threadIdx.x != 0) return;
+    BSys &S = a.sys[sys];
+    S.thr1 = S.tol_abs ? eps1 : eps1 * sqrt(S.bb);
+    S.eps_set = 1;
+    if (S.mode != kHold) return;
+    if (sqrt(S.gamma) <= S.thr1) {
+        S.relres_sp = sqrt(S.gamma) / sqrt(S.bb);
+        S.src = kSrcX32;
+        S.ph_it = 0;
+        S.mode = kRestart;
+    } else if (S.n1 >= S.maxit1) {
+        S.flags |= MPCG_FLAG_FP32_MAXIT;
+        S.relres_sp = sqrt(S.gamma) / sqrt(S.bb);
+        S.src = kSrcX32;
+        S.ph_it = 0;
+        S.mode = kRestart;
+    } else {
+        S.mode = kCg32;
+    }
+}
+
+// ----------------------------------------------------------------- step --
+
+// Wave per slice.  CG product of iteration j of the phase:
+// d_j = r_j + beta_j d_{j-1} (d_0 = r_0), q = A d_j, partial of d_j.q (FP64).
+template <typename T>
+__device__ inline double cg_product(const BArena &a, const BSys &S, const T *val, const T *r, T *dA, T *dB,
+                                    T *q, int64_t base, int row, int len)
+{
+    const int j = S.ph_it;
+    const bool first = j == 0;
+    const T beta = (T)S.beta;
+    T *dnew = (j & 1) ? dB : dA;
+    const T *dold = (j & 1) ? dA : dB;
+    T acc = T(0);
+    const int W = wave_max_i32(len);
+    for (int k0 = 0; k0 < W; k0 += kLoadBatch) {
+        int c[kLoadBatch];
+        T v[kLoadBatch], g[kLoadBatch];
+#pragma unroll
+        for (int t = 0; t < kLoadBatch; ++t)
+            if (k0 + t < len) {
+                c[t] = a.col[base + (int64_t)(k0 + t) * 64];
+                v[t] = val[base + (int64_t)(k0 + t) * 64];
+            }
+#pragma unroll
+        for (int t = 0; t < kLoadBatch; ++t)
+            if (k0 + t < len) g[t] = first ? r[c[t]] : fma_b<T>(beta, dold[c[t]], r[c[t]]);
+#pragma unroll
+        for (int t = 0; t < kLoadBatch; ++t)
+            if (k0 + t < len) acc = fma_b<T>(v[t], g[t], acc);
+    }
+    const T dn = first ? r[row] : fma_b<T>(beta, dold[row], r[row]);
+    dnew[row] = dn;
+    q[row] = acc;
+    return (double)dn * (double)acc;
+}
+
+// Restart: r = b - A x with x = float64(x~), x, or 0; x takes that value.
+// Final check: partial of ||b - A x||^2.
+__device__ inline double residual(const BArena &a, const BSys &S, bool restart, int64_t base, int row, int len)
+{
+    const int src = restart ? S.src : kSrcX64;
+    double acc = 0.0;
+    const int W = wave_max_i32(len);
+    for (int k0 = 0; k0 < W; k0 += kLoadBatch) {
+        int c[kLoadBatch];
+        double v[kLoadBatch], g[kLoadBatch];
+#pragma unroll
+        for (int t = 0; t < kLoadBatch; ++t)
+            if (k0 + t < len) {
+                c[t] = a.col[base + (int64_t)(k0 + t) * 64];
+                v[t] = a.v64[base + (int64_t)(k0 + t) * 64];
+            }
+#pragma unroll
+        for (int t = 0; t < kLoadBatch; ++t)
+            if (k0 + t < len)
+                g[t] = src == kSrcX32 ? (double)a.x32[c[t]] : (src == kSrcX64 ? a.x64[c[t]] : 0.0);
+#pragma unroll
+        for (int t = 0; t < kLoadBatch; ++t)
+            if (k0 + t < len) acc = fma(v[t], g[t], acc);
+    }
+    const double res = a.b64[row] - acc;
+    if (restart) {
+        if (src == kSrcX32) a.x64[row] = (double)a.x32[row];
+        else if (src == kSrcZero) a.x64[row] = 0.0;
+        a.r64[row] = res;
+    }
+    return res * res;
+}
+
+__global__ void __launch_bounds__(kBlock) k_b_product(BArena a, int32_t hi_slice)
+{
+    const int sl = blockIdx.x * kSlicesPerBlock + (threadIdx.x >> 6);
+    if (sl >= hi_slice) return;
+    const int s = a.sys_of_slice[sl];
+    if (s < 0) return;
+    const BSys &S = a.sys[s];
+    const int mode = S.mode;
+    if (mode != kCg32 && mode != kCg64 && mode != kRestart && mode != kResid) return;
+    const int lane = threadIdx.x & 63;
+    const int row = sl * 64 + lane;
+    const int len = a.rowlen[row];
+    const int64_t base = S.entry0 + a.slice_off[sl] + lane;
+    double p;
+    if (mode == kCg32) p = cg_product<float>(a, S, a.v32, a.r32, a.dA32, a.dB32, a.q32, base, row, len);
+    else if (mode == kCg64) p = cg_product<double>(a, S, a.v64, a.r64, a.dA64, a.dB64, a.q64, base, row, len);
+    else p = residual(a, S, mode == kRestart, base, row, len);
+    p = wave_sum_d(p);
+    if (lane == 0) a.pslice[2 * (size_t)sl] = p;
+}
+
+// Block per system: finish the product's reduction and take its decision.
+__global__ void __launch_bounds__(kBlock) k_b_scalar1(BArena a)
+{
+    __shared__ double sm[kBlock / 64 + 1];
+    BSys &S = a.sys[blockIdx.x];
+    const int mode = S.mode;
+    if (mode != kCg32 && mode != kCg64 && mode != kRestart && mode != kResid) return;
+    const double v = sys_sum(a, S, 0, sm);
+    if (threadIdx.x != 0) return;
+    const double sb = sqrt(S.bb);
+    if (mode == kCg32 || mode == kCg64) {
+        const double delta = v;
+        S.delta = delta;
+        if (!isfinite(delta) || !(delta > 0.0)) {
+            if (mode == kCg32) {
+                S.flags |= MPCG_FLAG_FP32_BREAKDOWN;
+                if (S.auto_eps && !S.eps_set && S.k0_used == 0) S.k0_used = S.n1 < S.k0 ? S.n1 : S.k0;
+                S.relres_sp = sqrt(S.gamma) / sb;
+                S.src = kSrcX32;
+                S.ph_it = 0;
+                S.mode = kRestart;
+            } else {
+                S.pend = isfinite(delta) ? MPCG_ENOTSPD : MPCG_ENONFINITE;
+                S.mode = kResid;
+            }
+            return;
+        }
+        S.alpha = mode == kCg32 ? (double)(float)(S.gamma / delta) : S.gamma / delta;
+        S.upd = 1;
+    } else if (mode == kRestart) {
+        S.gamma = v;
+        S.relres_restart = sqrt(v) / sb;
+        S.ph_it = 0;
+        if (sqrt(v) <= S.thr2) {
+            S.mode = kResid;
+        } else if (S.n2 >= S.maxit2) {
+            S.pend = MPCG_ENOCONV;
+            S.mode = kResid;
+        } else {
+            S.mode = kCg64;
+        }
+    } else {   // final check
+        const double rho = sqrt(v);
+        S.relres_final = rho / sb;
+        if (S.pend) {
+            S.status = S.pend;
+            S.mode = kDone;
+        } else if (rho <= S.thr2) {
+            S.status = MPCG_OK;
+            S.mode = kDone;
+        } else if (S.restarts < S.max_restarts) {
+            S.restarts += 1;
+            S.flags |= MPCG_FLAG_FINAL_RESTARTED;
+            S.src = kSrcX64;
+            S.mode = kRestart;
+        } else {
+            S.status = MPCG_ENOCONV;
+            S.mode = kDone;
+        }
+    }
+}
+
+template <typename T>
+__device__ inline double cg_update(const BSys &S, T *x, T *r, const T *q, const T *dA, const T *dB, int row)
+{
+    const T alpha = (T)S.alpha;
+    const T *d = (S.ph_it & 1) ? dB : dA;
+    x[row] = fma_b<T>(alpha, d[row], x[row]);
+    const T rv = fma_b<T>(-alpha, q[row], r[row]);
+    r[row] = rv;
+    return (double)rv * (double)rv;
+}
+
+__global__ void __launch_bounds__(kBlock) k_b_update(BArena a, int32_t hi_slice)
+{
+    const int sl = blockIdx.x * kSlicesPerBlock + (threadIdx.x >> 6);
+    if (sl >= hi_slice) return;
+    const int s = a.sys_of_slice[sl];
+    if (s < 0) return;
+    const BSys &S = a.sys[s];
+    if (!S.upd) return;
+    const int lane = threadIdx.x & 63;
+    const int row = sl * 64 + lane;
+    double p = S.mode == kCg32 ? cg_update<float>(S, a.x32, a.r32, a.q32, a.dA32, a.dB32, row)
+                               : cg_update<double>(S, a.x64, a.r64, a.q64, a.dA64, a.dB64, row);
+    p = wave_sum_d(p);
+    if (lane == 0) a.pslice[2 * (size_t)sl] = p;
+}
+
+// Block per system: gamma of the new residual, v ratios, stop tests, beta.
+__global__ void __launch_bounds__(kBlock) k_b_scalar2(BArena a)
+{
+    __shared__ double sm[kBlock / 64 + 1];
+    BSys &S = a.sys[blockIdx.x];
+    if (!S.upd) return;
+    const double g = sys_sum(a, S, 0, sm);
+    if (threadIdx.x != 0) return;
+    S.upd = 0;
+    const double gp = S.gamma;
+    S.gamma_prev = gp;
+    S.gamma = g;
+    S.ph_it += 1;
+    const double sb = sqrt(S.bb);
+    if (S.mode == kCg32) {
+        S.n1 += 1;
+        const bool prefix = S.auto_eps && S.k0_used == 0;
+        if (prefix && S.n1 <= S.k0 && S.n1 <= kK0Max) S.ratios[S.n1 - 1] = sqrt(g) / sqrt(gp);
+        S.beta = (double)(float)(g / gp);
+        if (prefix && (S.n1 >= S.k0 || g == 0.0)) S.k0_used = S.n1;
+        if (prefix && S.n1 < S.k0 && g != 0.0) return;   // Algorithm II: k0 iterations first
+        if (S.auto_eps && !S.eps_set) {
+            S.mode = kHold;
+            return;
+        }
+        if (sqrt(g) <= S.thr1 || S.n1 >= S.maxit1) {
+            if (!(sqrt(g) <= S.thr1)) S.flags |= MPCG_FLAG_FP32_MAXIT;
+            S.relres_sp = sqrt(g) / sb;
+            S.src = kSrcX32;
+            S.ph_it = 0;
+            S.mode = kRestart;
+        }
+    } else {
+        S.n2 += 1;
+        S.beta = g / gp;
+        if (sqrt(g) <= S.thr2) {
+            S.mode = kResid;
+        } else if (S.n2 >= S.maxit2) {
+            S.pend = MPCG_ENOCONV;
+            S.mode = kResid;
+        }
+    }
+}
+
+// ----------------------------------------------------------------- 2BFS --
+
+// Single block: retire the level each running system expanded last step
+// (appends -> frontier), detect ended sweeps, and list this step's work:
+// systems with a frontier that fits in LDS go to the one-block-per-system
+// kernel, the others share the multi-block level kernel through an item
+// prefix.
+__global__ void __launch_bounds__(1024) k_bfs_plan(BArena a, int32_t hi_sys)
+{
+    __shared__ int64_t sitems[1024];
+    __shared__ int32_t sbig[1024], ssmall[1024];
+    __shared__ int64_t base_items;
+    __shared__ int32_t base_big, base_small;
+    if (threadIdx.x == 0) {
+        base_items = 0;
+        base_big = 0;
+        base_small = 0;
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < hi_sys; c0 += 1024) {
+        const int s = c0 + threadIdx.x;
+        int64_t items = 0;
+        int big = 0, small = 0;
+        if (s < hi_sys) {
+            BSys &S = a.sys[s];
+            if (S.bfs_mode == kBfsRun) {
+                const int c = S.bfs_nxt;
+                if (S.bfs_level < 0 && S.bfs_sweep == 1) S.ncomp = c;
+                if (c == 0) {
+                    S.bfs_mode = kBfsSwept;
+                } else {
+                    S.bfs_nxt = 0;
+                    S.bfs_level += 1;
+                    S.bfs_cnt = c;
+                    if (c <= kSmallBfsCap) {
+                        small = 1;
+                    } else {
+                        big = 1;
+                        items = (int64_t)c * S.lanes;
+                    }
+                }
+                S.small = small;
+            }
+        }
+        sitems[threadIdx.x] = items;
+        sbig[threadIdx.x] = big;
+        ssmall[threadIdx.x] = small;
+        __syncthreads();
+        if (threadIdx.x == 0) {   // sequential exclusive scans over this chunk (<= 1024 systems)
+            int64_t ri = base_items;
+            int32_t rb = base_big, rs = base_small;
+            for (int t = 0; t < 1024; ++t) {
+                const int64_t it = sitems[t];
+                const int32_t b = sbig[t], sm_ = ssmall[t];
+                sitems[t] = ri;
+                sbig[t] = rb;
+                ssmall[t] = rs;
+                ri += it;
+                rb += b;
+                rs += sm_;
+            }
+            base_items = ri;
+            base_big = rb;
+            base_small = rs;
+        }
+        __syncthreads();
+        if (big) {
+            a.act_sys[sbig[threadIdx.x]] = s;
+            a.act_pre[sbig[threadIdx.x]] = sitems[threadIdx.x];
+            a.sys[s].item0 = sitems[threadIdx.x];
+        }
+        if (small) a.small_sys[ssmall[threadIdx.x]] = s;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        a.counts[0] = base_big;
+        a.counts[1] = base_small;
+        a.items[0] = base_items;
+    }
+}
+
+// One level of every system on the large list.  Item w belongs to the
+// system k with act_pre[k] <= w < act_pre[k + 1]; `lanes` consecutive items
+// share a frontier vertex and split its row.
+__global__ void __launch_bounds__(kBlock) k_bfs_level_batch(BArena a)
+{
+    const int nact = a.counts[0];
+    if (nact == 0) return;
+    const int64_t items = a.items[0];
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t wbase = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); wbase < items; wbase += stride) {
+        const int64_t w = wbase + lane;
+        int s = -1, u = -1, j = 0, e = 0, lanes = 1, level = 0;
+        int64_t base = 0;
+        if (w < items) {
+            int lo = 0, hi = nact - 1;   // last k with act_pre[k] <= w
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (a.act_pre[mid] <= w) lo = mid;
+                else hi = mid - 1;
+            }
+            s = a.act_sys[lo];
+            const BSys &S = a.sys[s];
+            lanes = S.lanes;
+            level = S.bfs_level;
+            const int64_t loc = w - a.act_pre[lo];
+            const int f = (int)(loc / lanes), l = (int)(loc - (int64_t)f * lanes);
+            const int32_t *qc = (level & 1) ? a.q1 : a.q0;
+            u = qc[S.row0 + f];
+            if (u >= S.row0 && u < S.row0 + S.n) {
+                base = S.entry0 + a.slice_off[u >> 6] + (u & 63);
+                j = l;
+                e = a.rowlen[u];
+            }
+        }
+        int steps = j < e ? (e - j + lanes - 1) / lanes : 0;
+        steps = wave_max_i32(steps);
+        for (int t = 0; t < steps; ++t, j += lanes) {
+            if (j < e) {
+                const int v = a.col[base + (int64_t)j * 64];
+                if (v != u && a.dist[v] < 0 && atomicCAS(&a.dist[v], -1, level + 1) == -1) {
+                    BSys &S = a.sys[s];
+                    const int pos = atomicAdd(&S.bfs_nxt, 1);
+                    int32_t *qn = (level & 1) ? a.q0 : a.q1;
+                    qn[S.row0 + pos] = v;
+                }
+            }
+        }
+    }
+}
+
+// One block per system on the small list: up to kSmallBfsLevels levels with
+// the frontier in LDS, each level's result also written to the global queue.
+// Leaves the system as the plan expects: bfs_level = last level expanded,
+// bfs_nxt = the size of the next frontier (queue (bfs_level + 1) & 1).
+__global__ void __launch_bounds__(kBlock) k_bfs_small_batch(BArena a)
+{
+    __shared__ int32_t sq[2][kSmallBfsCap];
+    __shared__ int32_t s_cnt;
+    if ((int)blockIdx.x >= a.counts[1]) return;
+    const int s = a.small_sys[blockIdx.x];
+    BSys &S = a.sys[s];
+    const int lanes = S.lanes, row0 = S.row0;
+    int level = S.bfs_level;
+    int cur = S.bfs_cnt;
+    {
+        const int32_t *qc = (level & 1) ? a.q1 : a.q0;
+        for (int i = threadIdx.x; i < cur; i += kBlock) sq[0][i] = qc[row0 + i];
+    }
+    int c = 0, nxt = 0;
+    for (int rep = 0; rep < kSmallBfsLevels; ++rep) {
+        if (threadIdx.x == 0) s_cnt = 0;
+        __syncthreads();
+        int32_t *qn = (level & 1) ? a.q0 : a.q1;
+        const int work = cur * lanes;
+        for (int w = threadIdx.x; w < work; w += kBlock) {
+            const int f = w / lanes, l = w - f * lanes;
+            const int u = sq[c][f];
+            const int64_t base = S.entry0 + a.slice_off[u >> 6] + (u & 63);
+            const int e = a.rowlen[u];
+            for (int j = l; j < e; j += lanes) {
+                const int v = a.col[base + (int64_t)j * 64];
+                if (v == u || a.dist[v] >= 0) continue;
+                if (atomicCAS(&a.dist[v], -1, level + 1) == -1) {
+                    const int pos = atomicAdd(&s_cnt, 1);
+                    if (pos < kSmallBfsCap) sq[c ^ 1][pos] = v;
+                    qn[row0 + pos] = v;
+                }
+            }
+        }
+        __syncthreads();
+        nxt = s_cnt;
+        __syncthreads();
+        if (nxt == 0 || nxt > kSmallBfsCap || rep + 1 == kSmallBfsLevels) break;
+        level += 1;
+        cur = nxt;
+        c ^= 1;
+    }
+    if (threadIdx.x == 0) {
+        S.bfs_level = level;
+        S.bfs_cnt = cur;
+        S.bfs_nxt = nxt;
+    }
+}
+
+void launch_step(hipStream_t s, const BArena &a, int32_t hi_slice, int32_t hi_sys)
+{
+    if (hi_slice <= 0 || hi_sys <= 0) return;
+    const int gsl = (hi_slice + kSlicesPerBlock - 1) / kSlicesPerBlock;
+    hipLaunchKernelGGL(k_b_product, dim3(gsl), dim3(kBlock), 0, s, a, hi_slice);
+    hipLaunchKernelGGL(k_b_scalar1, dim3(hi_sys), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_b_update, dim3(gsl), dim3(kBlock), 0, s, a, hi_slice);
+    hipLaunchKernelGGL(k_b_scalar2, dim3(hi_sys), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_bfs_plan, dim3(1), dim3(1024), 0, s, a, hi_sys);
+    hipLaunchKernelGGL(k_bfs_level_batch, dim3(256), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_bfs_small_batch, dim3(hi_sys), dim3(kBlock), 0, s, a);
+}
+
+// ------------------------------------------------- 2BFS per system (host) --
+
+__global__ void k_b_cc_init(BArena a, int32_t sys)
+{
+    const BSys &S = a.sys[sys];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < S.n; i += gridDim.x * kBlock) {
+        a.label[S.row0 + i] = S.row0 + i;   // parent pointers during the hooking
+        a.dist[S.row0 + i] = -1;
+    }
+}
+
+__device__ inline int b_find(int32_t *parent, int x, int *guard)
+{
+    int p = __hip_atomic_load(&parent[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int steps = 0;
+    while (p != x && steps < (1 << 24)) {
+        const int pp = __hip_atomic_load(&parent[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (pp != p) __hip_atomic_store(&parent[x], pp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x = p;
+        p = pp;
+        ++steps;
+    }
+    if (steps >= (1 << 24)) *guard = 1;
+    return x;
+}
+
+// Union-find over the system's edges: roots hooked larger-under-smaller, so
+// every component's root is its smallest vertex.
+__global__ void __launch_bounds__(kBlock) k_b_cc_hook(BArena a, int32_t sys)
+{
+    const BSys &S = a.sys[sys];
+    int guard = 0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < S.n; i += gridDim.x * kBlock) {
+        const int v = S.row0 + i;
+        const int64_t base = S.entry0 + a.slice_off[v >> 6] + (v & 63);
+        const int e = a.rowlen[v];
+        for (int j = 0; j < e; ++j) {
+            const int u = a.col[base + (int64_t)j * 64];
+            if (u <= v) continue;
+            int tries = 0;
+            for (;;) {
+                int ru = b_find(a.label, u, &guard), rv = b_find(a.label, v, &guard);
+                if (ru == rv) break;
+                if (ru < rv) { const int t = ru; ru = rv; rv = t; }
+                if (atomicCAS(&a.label[ru], ru, rv) == ru) break;
+                if (++tries > (1 << 20)) { guard = 1; break; }
+            }
+        }
+    }
+    if (guard) atomicOr(&a.sys[sys].err, kErrGuard);
+}
+
+// Labels compressed; roots seed the first sweep at distance 0.
+__global__ void __launch_bounds__(kBlock) k_b_cc_seed(BArena a, int32_t sys)
+{
+    BSys &S = a.sys[sys];
+    int guard = 0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < S.n; i += gridDim.x * kBlock) {
+        const int v = S.row0 + i;
+        const int r = b_find(a.label, v, &guard);
+        a.label[v] = r;   // only v's own entry is rewritten here; finds read roots' entries, which stay put
+        if (r == v) {
+            a.dist[v] = 0;
+            a.best[v] = 0ull;
+            const int pos = atomicAdd(&S.bfs_nxt, 1);
+            a.q0[S.row0 + pos] = v;
+        }
+    }
+    if (guard) atomicOr(&S.err, kErrGuard);
+}
+
+__global__ void k_b_bfs_arm(BArena a, int32_t sys, int32_t sweep)
+{
+    if (threadIdx.x == 0) {
+        BSys &S = a.sys[sys];
+        S.bfs_level = -1;
+        S.bfs_sweep = sweep;
+        S.bfs_mode = kBfsRun;
+        S.comp_best = 0ull;
+    }
+}
+
+__global__ void k_b_zero_nxt(BArena a, int32_t sys)
+{
+    if (threadIdx.x == 0) a.sys[sys].bfs_nxt = 0;
+}
+
+// Per-component farthest vertex of the sweep: key = (dist << 32) | ~v.
+__global__ void __launch_bounds__(kBlock) k_b_argmax(BArena a, int32_t sys)
+{
+    const BSys &S = a.sys[sys];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < S.n; i += gridDim.x * kBlock) {
+        const int v = S.row0 + i;
+        const int d = a.dist[v];
+        if (d < 0) continue;
+        const unsigned long long key =
+            ((unsigned long long)(unsigned)d << 32) | (unsigned long long)(0xffffffffu - (unsigned)v);
+        atomicMax(&a.best[a.label[v]], key);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_b_fill_dist(BArena a, int32_t sys)
+{
+    const BSys &S = a.sys[sys];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < S.n; i += gridDim.x * kBlock) a.dist[S.row0 + i] = -1;
+}
+
+// Second sweep from t_c of every component c.
+__global__ void __launch_bounds__(kBlock) k_b_seed_far(BArena a, int32_t sys)
+{
+    BSys &S = a.sys[sys];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < S.n; i += gridDim.x * kBlock) {
+        const int v = S.row0 + i;
+        if (a.label[v] != v) continue;
+        const int t = (int)(0xffffffffu - (unsigned)(a.best[v] & 0xffffffffull));
+        if (t < S.row0 || t >= S.row0 + S.n) continue;   // cannot happen: the root itself has a key
+        a.tarr[v] = t;
+        a.best[v] = 0ull;
+        a.dist[t] = 0;
+        const int pos = atomicAdd(&S.bfs_nxt, 1);
+        a.q0[S.row0 + pos] = t;
+    }
+}
+
+// Best component: largest eccentricity, first (smallest root) on ties.
+__global__ void __launch_bounds__(kBlock) k_b_comp_best(BArena a, int32_t sys)
+{
+    BSys &S = a.sys[sys];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < S.n; i += gridDim.x * kBlock) {
+        const int c = S.row0 + i;
+        if (a.label[c] != c) continue;
+        const unsigned long long ecc = a.best[c] >> 32;
+        atomicMax(&S.comp_best, (ecc << 32) | (unsigned long long)(0xffffffffu - (unsigned)c));
+    }
+}
+
+__global__ void k_b_feat_final(BArena a, int32_t sys)
+{
+    if (threadIdx.x != 0) return;
+    BSys &S = a.sys[sys];
+    const unsigned long long key = S.comp_best;
+    const int comp = (int)(0xffffffffu - (unsigned)(key & 0xffffffffull));
+    if (key == 0ull || comp < S.row0 || comp >= S.row0 + S.n) {
+        S.err |= kErrGuard;
+        S.bfs_mode = kBfsDone;
+        return;
+    }
+    S.pdiam = (int)(key >> 32);
+    S.bfs_t = a.tarr[comp] - S.row0;
+    S.bfs_u = (int)(0xffffffffu - (unsigned)(a.best[comp] & 0xffffffffull)) - S.row0;
+    S.bfs_mode = kBfsDone;
+}
+
+static int rows_grid(int n)
+{
+    int g = (n + kBlock - 1) / kBlock;
+    if (g > 4096) g = 4096;
+    return g < 1 ? 1 : g;
+}
+
+void launch_bfs_start(hipStream_t s, const BArena &a, int32_t sys)
+{
+    // the system's n is read on the device; the grid covers the largest admissible system
+    const int g = 4096;
+    hipLaunchKernelGGL(k_b_zero_nxt, dim3(1), dim3(64), 0, s, a, sys);
+    hipLaunchKernelGGL(k_b_cc_init, dim3(g), dim3(kBlock), 0, s, a, sys);
+    hipLaunchKernelGGL(k_b_cc_hook, dim3(g), dim3(kBlock), 0, s, a, sys);
+    hipLaunchKernelGGL(k_b_cc_seed, dim3(g), dim3(kBlock), 0, s, a, sys);
+    hipLaunchKernelGGL(k_b_bfs_arm, dim3(1), dim3(64), 0, s, a, sys, 1);
+}
+
+void launch_bfs_next_sweep(hipStream_t s, const BArena &a, int32_t sys)
+{
+    const int g = 4096;
+    hipLaunchKernelGGL(k_b_argmax, dim3(g), dim3(kBlock), 0, s, a, sys);
+    hipLaunchKernelGGL(k_b_fill_dist, dim3(g), dim3(kBlock), 0, s, a, sys);
+    hipLaunchKernelGGL(k_b_zero_nxt, dim3(1), dim3(64), 0, s, a, sys);
+    hipLaunchKernelGGL(k_b_seed_far, dim3(g), dim3(kBlock), 0, s, a, sys);
+    hipLaunchKernelGGL(k_b_bfs_arm, dim3(1), dim3(64), 0, s, a, sys, 2);
+}
+
+void launch_bfs_finish(hipStream_t s, const BArena &a, int32_t sys)
+{
+    const int g = 4096;
+    hipLaunchKernelGGL(k_b_argmax, dim3(g), dim3(kBlock), 0, s, a, sys);
+    hipLaunchKernelGGL(k_b_comp_best, dim3(g), dim3(kBlock), 0, s, a, sys);
+    hipLaunchKernelGGL(k_b_feat_final, dim3(1), dim3(64), 0, s, a, sys);
+}
+
+// ------------------------------------------------------- admission (host) --
+
+void launch_admit_rows(hipStream_t s, const BArena &a, int32_t sys, const void *rp, int rp_i64, int64_t nnz,
+                       const double *b, int32_t row0, int32_t n, int32_t slice0, int32_t nslices)
+{
+    hipLaunchKernelGGL(k_fill_slice_w, dim3((nslices + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a, slice0,
+                       nslices);
+    hipLaunchKernelGGL(k_admit_rows, dim3((nslices * 64 + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a, sys, rp,
+                       rp_i64, b, row0, n, nnz, slice0, nslices);
+}
+
+void launch_admit_scan(hipStream_t s, const BArena &a, int32_t sys)
+{
+    hipLaunchKernelGGL(k_admit_scan, dim3(1), dim3(1024), 0, s, a, sys);
+}
+
+void launch_admit_entries(hipStream_t s, const BArena &a, int32_t sys, int32_t nslices, const void *rp,
+                          int rp_i64, const int32_t *col, const double *val)
+{
+    hipLaunchKernelGGL(k_admit_entries, dim3((nslices + kSlicesPerBlock - 1) / kSlicesPerBlock), dim3(kBlock), 0,
+                       s, a, sys, rp, rp_i64, col, val);
+}
+
+void launch_admit_finish(hipStream_t s, const BArena &a, int32_t sys, int32_t nslices, double eps1)
+{
+    hipLaunchKernelGGL(k_admit_finish, dim3(1), dim3(kBlock), 0, s, a, sys, eps1);
+    hipLaunchKernelGGL(k_admit_publish, dim3(rows_grid(nslices)), dim3(kBlock), 0, s, a, sys);
+}
+
+void launch_release(hipStream_t s, const BArena &a, int32_t sys, int32_t slice0, int32_t nslices)
+{
+    hipLaunchKernelGGL(k_release, dim3(rows_grid(nslices)), dim3(kBlock), 0, s, a, sys, slice0, nslices);
+}
+
+void launch_cancel(hipStream_t s, const BArena &a, int32_t sys)
+{
+    hipLaunchKernelGGL(k_cancel, dim3(1), dim3(64), 0, s, a, sys);
+}
+
+void launch_set_eps(hipStream_t s, const BArena &a, int32_t sys, double eps1)
+{
+    hipLaunchKernelGGL(k_set_eps, dim3(1), dim3(64), 0, s, a, sys, eps1);
+}
+
+}  // namespace batch
+}  // namespace mpcg

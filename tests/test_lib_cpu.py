@@ -55,6 +55,7 @@ int main(void) {{
   printf("%zu %zu %zu %zu\\n", sizeof(mpcg_csr), sizeof(mpcg_features_t), sizeof(mpcg_stats), sizeof(mpcg_options));
   printf("%zu %zu %zu %zu\\n", offsetof(mpcg_csr, col_idx), offsetof(mpcg_stats, feat),
          offsetof(mpcg_stats, t_total_ms), offsetof(mpcg_options, maxit2));
+  printf("%zu %zu %zu\\n", sizeof(mpcg_request), offsetof(mpcg_request, eps1), offsetof(mpcg_request, user));
   return 0;
 }}""")
     exe = tmp_path / "layout"
@@ -64,7 +65,8 @@ int main(void) {{
     exp = [ctypes.sizeof(capi.mpcg_csr), ctypes.sizeof(capi.mpcg_features_t),
            ctypes.sizeof(capi.mpcg_stats), ctypes.sizeof(capi.mpcg_options),
            capi.mpcg_csr.col_idx.offset, capi.mpcg_stats.feat.offset,
-           capi.mpcg_stats.t_total_ms.offset, capi.mpcg_options.maxit2.offset]
+           capi.mpcg_stats.t_total_ms.offset, capi.mpcg_options.maxit2.offset,
+           ctypes.sizeof(capi.mpcg_request), capi.mpcg_request.eps1.offset, capi.mpcg_request.user.offset]
     assert got == exp
 
 
