@@ -101,6 +101,143 @@ def cpu_baseline(a, b, n1, n2, n_dp):
     }
 
 
+def _mixed_systems(count, n_lo, n_hi, seed):
+    """`count` systems, family uniform over the four workload families, n
+    log-uniform in [n_lo, n_hi], x* ~ U[-1,1], b = A x* (seed + i each)."""
+    import numpy as np
+    import workloads as W
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        fam = W.FAMILIES[int(rng.integers(0, len(W.FAMILIES)))]
+        n = int(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
+        a = W.family_matrix(fam, n, seed=seed + i)
+        _, b = W.rhs(a, seed=seed + i)
+        out.append((fam, a, b))
+    return out
+
+
+def _iter_bytes(n, m, n1, n2):
+    """Algorithmic bytes of n1 FP32 and n2 FP64 CG iterations (product + update)."""
+    it = lambda s: kernel_bytes("cg_spmv" + ("64" if s == 8 else "32"), n, m) + kernel_bytes(
+        "update" + ("64" if s == 8 else "32"), n, m)
+    return n1 * it(4) + n2 * it(8)
+
+
+def bench_batch(args):
+    """Many independent systems in one engine: Algorithm II (kNN eps1), a fixed
+    eps1 = 1e-4 control and FP64-only CG, each submitted as one batch."""
+    import numpy as np
+    import torch
+    from paper_2412_08059_amd import DEFAULT_MODEL, BatchSolver, DeviceCSR
+    t = time.perf_counter()
+    systems = _mixed_systems(args.batch_count, args.batch_nmin, args.batch_nmax, args.seed + 1000)
+    rows = sum(((a.n + 63) // 64) * 64 for _, a, _ in systems)
+    nnz = sum(a.nnz for _, a, _ in systems)
+    print(f"# batch: {len(systems)} systems, {rows} padded rows, {nnz} nonzeros "
+          f"(generated in {time.perf_counter() - t:.1f}s)", file=sys.stderr, flush=True)
+    dev = [(DeviceCSR.from_host(a), torch.from_numpy(b).cuda(),
+            torch.empty(a.n, dtype=torch.float64, device="cuda")) for _, a, b in systems]
+    eng = BatchSolver(rows, 2 * nnz + 64 * rows, len(systems), model=DEFAULT_MODEL)
+    res = {}
+    for label, e1 in (("auto", 0.0), ("fixed_1e-4", 1e-4), ("fp64_only", -1.0)):
+        for rep in range(1 + args.warmup):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ids = eng.submit([(A, B, X, e1, 1e-10) for (A, B, X) in dev])
+            got = eng.wait_all(ids, timeout_s=1800)
+            wall = time.perf_counter() - t0
+        st = [got[i][0] for i in ids]
+        bad = [s.status for s in st if s.status != 0 or s.relres_final_true > 1e-10]
+        n1 = [s.n1 for s in st]
+        n2 = [s.n2 for s in st]
+        byt = sum(_iter_bytes(a.n, a.nnz, s.n1, s.n2) for (_, a, _), s in zip(systems, st))
+        res[label] = {"wall_ms": round(wall * 1e3, 1), "solves_per_s": round(len(st) / wall, 1),
+                      "sum_n1": int(np.sum(n1)), "sum_n2": int(np.sum(n2)), "failed": len(bad),
+                      "cg_GBs": round(byt / wall / 1e9, 1),
+                      "latency_ms_p50": round(float(np.percentile([s.t_total_ms for s in st], 50)), 1),
+                      "latency_ms_max": round(float(np.max([s.t_total_ms for s in st])), 1)}
+        print(f"# batch {label}: {res[label]}", file=sys.stderr, flush=True)
+    eng.close()
+    fams = {f: sum(1 for g, _, _ in systems if g == f) for f in ("lap2d", "lap3d", "banded", "er")}
+    out = {"metric": "batched solves/s, 512 SPD systems, time-to-1e-10 each", "value": res["auto"]["solves_per_s"],
+           "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "f32+f64",
+           "config": {"workload": f"{len(systems)} systems, n log-uniform [{args.batch_nmin:g}, {args.batch_nmax:g}], "
+                                  f"families {fams}, x*~U[-1,1], b=Ax*, eps2=1e-10",
+                      "rows": rows, "nnz": nnz},
+           "speedup_vs_fp64_only": round(res["fp64_only"]["wall_ms"] / res["auto"]["wall_ms"], 3),
+           "modes": res}
+    print(json.dumps(out))
+
+
+def bench_serve(args):
+    """Poisson arrivals at ~80% of the measured saturation throughput; each
+    request gets the feature pass and kNN eps1; the same arrival trace is
+    replayed with FP64-only CG.  Latency = completion (seen by polling) minus
+    scheduled arrival."""
+    import numpy as np
+    import torch
+    from paper_2412_08059_amd import DEFAULT_MODEL, BatchSolver, DeviceCSR
+    systems = _mixed_systems(args.serve_count, args.serve_nmin, args.serve_nmax, args.seed + 5000)
+    rows = sum(((a.n + 63) // 64) * 64 for _, a, _ in systems)
+    nnz = sum(a.nnz for _, a, _ in systems)
+    dev = [(DeviceCSR.from_host(a), torch.from_numpy(b).cuda(),
+            torch.empty(a.n, dtype=torch.float64, device="cuda")) for _, a, b in systems]
+    print(f"# serve: {len(systems)} requests, {rows} padded rows in total", file=sys.stderr, flush=True)
+    cap_rows = max(rows // 2, max(((a.n + 63) // 64) * 64 for _, a, _ in systems))
+    cap_nnz = max(2 * nnz // 2 + 64 * cap_rows, 2 * max(a.nnz for _, a, _ in systems) + 64 * cap_rows)
+    eng = BatchSolver(cap_rows, cap_nnz, 256, model=DEFAULT_MODEL)
+    out_modes = {}
+    # saturation throughput: everything submitted at once
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    got = eng.wait_all(eng.submit([(A, B, X, 0.0, 1e-10) for (A, B, X) in dev]), timeout_s=3600)
+    mu = len(dev) / (time.perf_counter() - t0)
+    lam = 0.8 * mu
+    rng = np.random.default_rng(args.seed + 7)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(dev)))
+    print(f"# serve: saturation {mu:.2f} solves/s, arrival rate {lam:.2f}/s", file=sys.stderr, flush=True)
+    for label, e1 in (("auto", 0.0), ("fp64_only", -1.0)):
+        lat, done_t = {}, {}
+        occ = []
+        order = {}
+        t0 = time.perf_counter()
+        nxt = 0
+        while len(done_t) < len(dev):
+            now = time.perf_counter() - t0
+            batch = []
+            while nxt < len(dev) and arrivals[nxt] <= now:
+                batch.append(nxt)
+                nxt += 1
+            if batch:
+                ids = eng.submit([(dev[i][0], dev[i][1], dev[i][2], e1, 1e-10) for i in batch])
+                for rid, i in zip(ids, batch):
+                    order[rid] = i
+            for rid, st, _ in eng.poll():
+                i = order[rid]
+                done_t[i] = time.perf_counter() - t0
+                lat[i] = (done_t[i] - arrivals[i], st.status, st.relres_final_true)
+            q, a = eng.load()
+            occ.append(a)
+            time.sleep(0.0005)
+        L = np.array([v[0] for v in lat.values()]) * 1e3
+        fails = sum(1 for v in lat.values() if v[1] != 0 or v[2] > 1e-10)
+        span = max(done_t.values()) - arrivals[0]
+        out_modes[label] = {"p50_ms": round(float(np.percentile(L, 50)), 1),
+                            "p99_ms": round(float(np.percentile(L, 99)), 1),
+                            "mean_ms": round(float(L.mean()), 1), "solves_per_s": round(len(dev) / span, 2),
+                            "mean_active": round(float(np.mean(occ)), 2), "failed": fails}
+        print(f"# serve {label}: {out_modes[label]}", file=sys.stderr, flush=True)
+    eng.close()
+    out = {"metric": "served solves: p50/p99 latency (arrival -> result) and solves/s", "value": out_modes["auto"]["p99_ms"],
+           "unit": "ms (p99)", "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f32+f64",
+           "config": {"workload": f"{len(dev)} Poisson-arrival requests at 0.8 x saturation ({mu:.2f}/s), n log-uniform "
+                                  f"[{args.serve_nmin:g}, {args.serve_nmax:g}], four families, eps2=1e-10",
+                      "rows": rows, "nnz": nnz, "arrival_rate_per_s": round(lam, 3)},
+           "modes": out_modes}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,11 +251,25 @@ def main():
     ap.add_argument("--kernel-only", action="store_true",
                     help="for PMC runs: a 1 GiB device copy (counter calibration) and 20 launches of "
                          "each CG kernel on the workload, nothing else")
+    ap.add_argument("--workload", choices=("solve", "batch", "serve"), default="solve",
+                    help="solve: the 128^3 single-system benchmark (default); batch: many systems in one "
+                         "engine; serve: Poisson arrivals with continuous admission")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-nmin", type=float, default=1e3)
+    ap.add_argument("--batch-nmax", type=float, default=2e5)
+    ap.add_argument("--serve-count", type=int, default=64)
+    ap.add_argument("--serve-nmin", type=float, default=1e4)
+    ap.add_argument("--serve-nmax", type=float, default=4e6)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the single-system solve "
               "is not sharded across GPUs in this build", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import numpy as np
     import torch

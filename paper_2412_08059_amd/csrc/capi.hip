@@ -323,7 +323,9 @@ BfsBufs bfs_bufs(const Plan &p)
 {
     static const int grid = env_int("MPCG_BFS_GRID", kBfsLevelBlocks);
     static const int precheck = env_int("MPCG_BFS_PRECHECK", 1);
+    static const int persist = env_int("MPCG_BFS_PERSIST", 0);
     BfsBufs b{};
+    b.persist = persist ? 1 : 0;
     b.grid = grid > 0 && grid <= 4096 ? grid : kBfsLevelBlocks;
     b.precheck = precheck ? 1 : 0;
     b.rp = p.rp;
@@ -370,9 +372,8 @@ mpcg_status bfs_run(const Chan &ch, const Plan &p, const BfsBufs &bb, DevState *
 }
 
 // 2BFS per component; fills pdiam, bfs_t, bfs_u, n_components.
-mpcg_status pseudo_diameter(const Chan &ch, const Plan &p, mpcg_features_t *f)
+mpcg_status pseudo_diameter_with(const Chan &ch, const Plan &p, const BfsBufs &bb, mpcg_features_t *f)
 {
-    BfsBufs bb = bfs_bufs(p);
     DevState s;
     launch_bfs_seed_single(ch.s, bb, 0);
     mpcg_status rc = bfs_run(ch, p, bb, &s);
@@ -415,6 +416,22 @@ mpcg_status pseudo_diameter(const Chan &ch, const Plan &p, mpcg_features_t *f)
     f->bfs_u = (int64_t)(0xffffffffu - (uint32_t)(bu & 0xffffffffull));
     f->n_components = s.ncomp;
     return MPCG_OK;
+}
+
+// The persistent level kernel bounds its barrier waits; if one ran out (its
+// blocks could not all be resident), the BFS is repeated with one launch per
+// level, which needs no co-residency.
+mpcg_status pseudo_diameter(const Chan &ch, const Plan &p, mpcg_features_t *f)
+{
+    BfsBufs bb = bfs_bufs(p);
+    mpcg_status rc = pseudo_diameter_with(ch, p, bb, f);
+    if (rc == MPCG_EDEVICE && bb.persist) {
+        HIPCHK(hipStreamSynchronize(ch.s));
+        HIPCHK(hipMemsetAsync(&p.st->guard, 0, sizeof(int32_t), ch.s));
+        bb.persist = 0;
+        rc = pseudo_diameter_with(ch, p, bb, f);
+    }
+    return rc;
 }
 
 // FP32 prefix of Algorithm II: k0 iterations without the eps1 test.
@@ -819,6 +836,13 @@ mpcg_status mpcg_bfs(mpcg_ctx *c, const mpcg_csr *A, int64_t src, int32_t *dist,
     launch_bfs_seed_single(c->stream, bb, (int32_t)src);
     DevState s;
     rc = bfs_run(c->main, p, bb, &s);
+    if (rc == MPCG_EDEVICE && bb.persist) {   // see pseudo_diameter
+        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipMemsetAsync(&p.st->guard, 0, sizeof(int32_t), c->stream));
+        bb.persist = 0;
+        launch_bfs_seed_single(c->stream, bb, (int32_t)src);
+        rc = bfs_run(c->main, p, bb, &s);
+    }
     if (rc != MPCG_OK) return rc;
     HIPCHK(hipMemcpyAsync(dist, bb.dist, sizeof(int32_t) * (size_t)p.n, hipMemcpyDeviceToDevice,
                           c->stream));

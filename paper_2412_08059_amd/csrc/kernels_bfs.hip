@@ -84,6 +84,7 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
     const int tid = threadIdx.x;
     if (tid == 0) {
         s_go = 0;
+        st->bfs_bar = 0u;   // the persistent kernel of this round starts its barrier count at 0
         if (!st->bfs_done) {
             const int L = st->bfs_lv[k & 1];
             const int cur = st->bfs_cnt[L & 3];
@@ -284,8 +285,175 @@ k_bfs_level(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
     if (lane == 0 && wmin != kIntMax) atomicMin(&st->bfs_min[(L + 1) & 3], wmin);
 }
 
+// ------------------------------------------------ persistent large levels --
+//
+// Expands every level whose frontier is larger than small_max in ONE launch:
+// the blocks meet at a grid barrier between levels instead of ending the
+// kernel.  Data other blocks produce within the launch (queue entries, level
+// counters, the barrier count) is written and read only with agent-scope
+// atomics -- coherent across the XCDs' L2 caches without cache write-back or
+// invalidation -- and each wave waits for its memory operations to complete
+// before its block arrives at the barrier.  The read-only CSR pattern and the
+// distance pre-check use plain loads (a stale distance only costs a failing
+// compare-and-swap).  Every wait is bounded; if one runs out the kernel
+// raises st->guard and the host repeats the BFS with one launch per level.
+// The grid is small, so its blocks can all be resident next to other work.
+
+__device__ inline int aload(const int32_t *p)
+{
+    return __hip_atomic_load(const_cast<int32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void astore(int32_t *p, int v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr uint32_t kBarSpinLimit = 1u << 22;
+
+__global__ void __launch_bounds__(kBlock)
+k_bfs_persist(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int32_t *dist, int32_t *q0,
+              int32_t *q1, int32_t n, int32_t lanes, int32_t small_max, int32_t k, DevState *st)
+{
+    __shared__ int s_ok;
+    if (aload(&st->bfs_done)) return;
+    int L = aload(&st->bfs_lv[k & 1]);
+    int cur = aload(&st->bfs_cnt[L & 3]);
+    const bool b0 = blockIdx.x == 0 && threadIdx.x == 0;
+    if (cur <= small_max) {   // nothing large to do: hand the level on
+        if (b0) astore(&st->bfs_lv[(k + 1) & 1], L);
+        return;
+    }
+    const int lane = threadIdx.x & 63;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t span = stride * kBfsItems;
+    long long visited = 0;
+    for (uint32_t round = 1;; ++round) {
+        if (b0) {
+            visited += cur;
+            astore(&st->bfs_cnt[(L + 2) & 3], 0);
+            astore(&st->bfs_min[(L + 2) & 3], kIntMax);
+        }
+        const int32_t *qc = (L & 1) ? q1 : q0;
+        int32_t *qn = (L & 1) ? q0 : q1;
+        int *cnt_next = &st->bfs_cnt[(L + 1) & 3];
+        int wmin = kIntMax;
+        const int64_t items = (int64_t)min(cur, n) * lanes;
+        for (int64_t wbase = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); wbase < items; wbase += span) {
+            int u[kBfsItems], j[kBfsItems], e[kBfsItems];
+#pragma unroll
+            for (int i = 0; i < kBfsItems; ++i) {
+                const int64_t w = wbase + i * stride + lane;
+                u[i] = w < items ? aload(&qc[(int)(w / lanes)]) : -1;
+                j[i] = 0;
+                e[i] = 0;
+            }
+#pragma unroll
+            for (int i = 0; i < kBfsItems; ++i) {
+                if ((unsigned)u[i] < (unsigned)n) {
+                    const int64_t w = wbase + i * stride + lane;
+                    j[i] = rp[u[i]] + (int)(w % lanes);
+                    e[i] = rp[u[i] + 1];
+                }
+            }
+            int steps = 0;
+#pragma unroll
+            for (int i = 0; i < kBfsItems; ++i) {
+                const int si = j[i] < e[i] ? (e[i] - j[i] + lanes - 1) / lanes : 0;
+                steps = steps > si ? steps : si;
+            }
+            steps = wave_max_i(steps);
+            for (int t = 0; t < steps; ++t) {
+                int v[kBfsItems];
+                bool found[kBfsItems];
+#pragma unroll
+                for (int i = 0; i < kBfsItems; ++i) {
+                    v[i] = j[i] < e[i] ? col[j[i]] : -1;
+                    j[i] += lanes;
+                }
+#pragma unroll
+                for (int i = 0; i < kBfsItems; ++i)
+                    found[i] = v[i] >= 0 && v[i] != u[i] && dist[v[i]] < 0 &&
+                               atomicCAS(&dist[v[i]], -1, L + 1) == -1;
+                unsigned long long m[kBfsItems];
+                int total = 0;
+#pragma unroll
+                for (int i = 0; i < kBfsItems; ++i) {
+                    m[i] = __ballot(found[i]);
+                    total += __popcll(m[i]);
+                }
+                if (total == 0) continue;
+                int base = 0;
+                if (lane == 0) base = atomicAdd(cnt_next, total);
+                base = __shfl(base, 0, 64);
+#pragma unroll
+                for (int i = 0; i < kBfsItems; ++i) {
+                    if (found[i]) {
+                        astore(&qn[base + __popcll(m[i] & lt)], v[i]);
+                        wmin = wmin < v[i] ? wmin : v[i];
+                    }
+                    base += __popcll(m[i]);
+                }
+            }
+        }
+        wmin = wave_min_i(wmin);
+        if (lane == 0 && wmin != kIntMax) atomicMin(&st->bfs_min[(L + 1) & 3], wmin);
+        // this wave's queue stores, claims and counters are complete before its block arrives
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_ok = 1;
+            __hip_atomic_fetch_add(&st->bfs_bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t target = round * gridDim.x;
+            uint32_t spins = 0;
+            while (__hip_atomic_load(&st->bfs_bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > kBarSpinLimit) {
+                    s_ok = 0;
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+        if (!s_ok) {
+            if (threadIdx.x == 0) atomicOr(&st->guard, 1);
+            return;
+        }
+        const int nxt = aload(cnt_next);
+        if (nxt == 0) {   // level L was the last non-empty one
+            if (b0) {
+                st->bfs_visited += visited;
+                astore(&st->bfs_ecc, L);
+                astore(&st->bfs_far, aload(&st->bfs_min[L & 3]));
+                astore(&st->bfs_done, 1);
+            }
+            return;
+        }
+        L += 1;
+        cur = nxt;
+        if (cur <= small_max) {
+            if (b0) {
+                st->bfs_visited += visited;
+                astore(&st->bfs_lv[(k + 1) & 1], L);
+            }
+            return;
+        }
+    }
+}
+
 int launch_bfs_round(hipStream_t s, const BfsBufs &b, int levels, int k)
 {
+    if (b.persist) {
+        hipLaunchKernelGGL(k_bfs_small, dim3(1), dim3(kBfsSmallThreads), 0, s, b.rp, b.col, b.dist, b.q0,
+                           b.q1, b.n, b.lanes, b.small_max, k, b.st);
+        ++k;
+        int grid = (b.n + kBlock - 1) / kBlock;
+        if (grid > b.grid) grid = b.grid;
+        hipLaunchKernelGGL(k_bfs_persist, dim3(grid), dim3(kBlock), 0, s, b.rp, b.col, b.dist, b.q0, b.q1, b.n,
+                           b.lanes, b.small_max, k, b.st);
+        return k + 1;
+    }
+
     hipLaunchKernelGGL(k_bfs_small, dim3(1), dim3(kBfsSmallThreads), 0, s, b.rp, b.col, b.dist, b.q0,
                        b.q1, b.n, b.lanes, b.small_max, k, b.st);
     ++k;

@@ -71,7 +71,7 @@ struct alignas(256) DevState {
     int32_t bfs_done;
     int32_t bfs_ecc;      // largest distance (when done)
     int32_t bfs_far;      // smallest vertex at distance bfs_ecc (when done)
-    int32_t bfs_pad;
+    uint32_t bfs_bar;     // arrivals at the persistent level kernel's grid barrier (cleared per round)
     int64_t bfs_visited;
     int32_t ncomp;
     uint64_t comp_best;   // (ecc << 32) | ~component of the best component
@@ -207,6 +207,7 @@ struct BfsBufs {
     DevState *st;
     int32_t grid;       // blocks of the level kernel
     int32_t precheck;   // read the distance before claiming a vertex
+    int32_t persist;    // large levels in one persistent launch (grid barrier) instead of one launch each
 };
 void launch_bfs_seed_single(hipStream_t s, const BfsBufs &b, int32_t src);
 // Enqueues one round (the one-workgroup kernel, then `levels` level kernels)
