@@ -44,6 +44,9 @@ struct mpcg_ctx {
     int cg_grid = kMaxGrid;   // MPCG_CG_GRID: most blocks of a CG product launch
     int up_grid = kUpdateGrid;   // MPCG_UP_GRID: most blocks of a CG update launch
     mpcg::batch::Engine *eng = nullptr;   // batched engine (own thread and stream), if started
+    int bfs_grid = kBfsLevelBlocks;   // MPCG_BFS_GRID: blocks of the BFS level kernel
+    int bfs_precheck = 1;             // MPCG_BFS_PRECHECK=0: claim without reading the distance first
+    int bfs_persist = 0;              // MPCG_BFS_PERSIST=1: large levels in one persistent launch
 };
 
 #define HIPCHK(x)                                        \
@@ -319,15 +322,12 @@ int env_int(const char *name, int def)
     return (e && e[0]) ? std::atoi(e) : def;
 }
 
-BfsBufs bfs_bufs(const Plan &p)
+BfsBufs bfs_bufs(const mpcg_ctx *c, const Plan &p)
 {
-    static const int grid = env_int("MPCG_BFS_GRID", kBfsLevelBlocks);
-    static const int precheck = env_int("MPCG_BFS_PRECHECK", 1);
-    static const int persist = env_int("MPCG_BFS_PERSIST", 0);
     BfsBufs b{};
-    b.persist = persist ? 1 : 0;
-    b.grid = grid > 0 && grid <= 4096 ? grid : kBfsLevelBlocks;
-    b.precheck = precheck ? 1 : 0;
+    b.persist = c->bfs_persist;
+    b.grid = c->bfs_grid;
+    b.precheck = c->bfs_precheck;
     b.rp = p.rp;
     b.col = p.col;
     b.n = p.n;
@@ -421,9 +421,9 @@ mpcg_status pseudo_diameter_with(const Chan &ch, const Plan &p, const BfsBufs &b
 // The persistent level kernel bounds its barrier waits; if one ran out (its
 // blocks could not all be resident), the BFS is repeated with one launch per
 // level, which needs no co-residency.
-mpcg_status pseudo_diameter(const Chan &ch, const Plan &p, mpcg_features_t *f)
+mpcg_status pseudo_diameter(const mpcg_ctx *c, const Chan &ch, const Plan &p, mpcg_features_t *f)
 {
-    BfsBufs bb = bfs_bufs(p);
+    BfsBufs bb = bfs_bufs(c, p);
     mpcg_status rc = pseudo_diameter_with(ch, p, bb, f);
     if (rc == MPCG_EDEVICE && bb.persist) {
         HIPCHK(hipStreamSynchronize(ch.s));
@@ -510,6 +510,10 @@ mpcg_status mpcg_create(mpcg_ctx **out, const mpcg_options *opt, void *hip_strea
         if (bt && bt[0] == '8') c->sell_batch = 8;
         const int cgg = env_int("MPCG_CG_GRID", kMaxGrid);
         c->cg_grid = cgg >= 64 && cgg <= kMaxGrid ? cgg : kMaxGrid;
+        const int bg = env_int("MPCG_BFS_GRID", kBfsLevelBlocks);
+        c->bfs_grid = bg > 0 && bg <= 4096 ? bg : kBfsLevelBlocks;
+        c->bfs_precheck = env_int("MPCG_BFS_PRECHECK", 1) ? 1 : 0;
+        c->bfs_persist = env_int("MPCG_BFS_PERSIST", 0) ? 1 : 0;
         const int upg = env_int("MPCG_UP_GRID", kUpdateGrid);
         c->up_grid = upg >= 64 && upg <= kMaxGrid ? upg : kUpdateGrid;
     }
@@ -607,7 +611,7 @@ mpcg_status mpcg_features(mpcg_ctx *c, const mpcg_csr *A, const double *b, int32
     mpcg_features_t f{};
     f.n = A->n;
     f.m = A->nnz;
-    rc = pseudo_diameter(c->main, p, &f);
+    rc = pseudo_diameter(c, c->main, p, &f);
     if (rc != MPCG_OK) return rc;
     DevState s;
     rc = fp32_prefix(c, p, b, k0, &s);
@@ -668,7 +672,7 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
             std::thread bfs_thread([&]() {
                 (void)hipSetDevice(c->device);
                 (void)hipEventRecord(c->tm[1], c->side.s);
-                rc_bfs = pseudo_diameter(c->side, p, &f);
+                rc_bfs = pseudo_diameter(c, c->side, p, &f);
                 (void)hipEventRecord(c->tm[2], c->side.s);
                 (void)hipEventSynchronize(c->tm[2]);
                 bfs_done.store(1);
@@ -832,7 +836,7 @@ mpcg_status mpcg_bfs(mpcg_ctx *c, const mpcg_csr *A, int64_t src, int32_t *dist,
     Plan p;
     mpcg_status rc = ingest(c, A, nullptr, false, &p);
     if (rc != MPCG_OK) return rc;
-    BfsBufs bb = bfs_bufs(p);
+    BfsBufs bb = bfs_bufs(c, p);
     launch_bfs_seed_single(c->stream, bb, (int32_t)src);
     DevState s;
     rc = bfs_run(c->main, p, bb, &s);

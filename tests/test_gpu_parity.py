@@ -60,6 +60,25 @@ def any_solver(request, solver, solver_csr):
     return solver if request.param == "sell" else solver_csr
 
 
+@pytest.fixture(scope="module")
+def solver_persist(torch_mod):
+    """A context whose 2BFS expands large levels in one persistent launch
+    (grid barrier between levels) instead of one launch per level."""
+    from paper_2412_08059_amd import Solver
+    os.environ["MPCG_BFS_PERSIST"] = "1"
+    try:
+        s = Solver(2_200_000, 17_500_000, model=TEST_MODEL)
+    finally:
+        del os.environ["MPCG_BFS_PERSIST"]
+    yield s
+    s.close()
+
+
+@pytest.fixture(params=["level", "persist"])
+def bfs_solver(request, solver, solver_persist):
+    return solver if request.param == "level" else solver_persist
+
+
 def dev(a, **kw):
     from paper_2412_08059_amd import DeviceCSR
     return DeviceCSR.from_host(a, **kw)
@@ -131,7 +150,8 @@ BFS_CASES = [
 
 
 @pytest.mark.parametrize("name,gen,srcs", BFS_CASES, ids=[c[0] for c in BFS_CASES])
-def test_bfs_distances_bitwise(solver, torch_mod, name, gen, srcs):
+def test_bfs_distances_bitwise(bfs_solver, torch_mod, name, gen, srcs):
+    solver = bfs_solver
     a = gen()
     A = dev(a)
     for s in srcs:
@@ -164,7 +184,8 @@ PD_CASES = {
 
 
 @pytest.mark.parametrize("name", list(PD_CASES))
-def test_features_bitwise(solver, torch_mod, name):
+def test_features_bitwise(bfs_solver, torch_mod, name):
+    solver = bfs_solver
     a = PD_CASES[name]()
     _, b = W.rhs(a, seed=3)
     print(f"features case={name} n={a.n}", flush=True)
