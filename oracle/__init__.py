@@ -54,6 +54,7 @@ def build(force: bool = False) -> str:
 class _Opts(ctypes.Structure):
     _fields_ = [("k0", ctypes.c_int32), ("tol_mode", ctypes.c_int32),
                 ("max_restarts", ctypes.c_int32), ("knn_k", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("maxit1", ctypes.c_int64), ("maxit2", ctypes.c_int64)]
 
 
@@ -196,11 +197,12 @@ class OracleResult:
 
 def solve(a, b, eps1: float, eps2: float = 1e-10, *, k0: int = 20, tol_mode: int = 0,
           max_restarts: int = 5, maxit1: int = 0, maxit2: int = 0, knn_k: int = 0,
-          model: KnnModel | None = None) -> OracleResult:
+          model: KnnModel | None = None, precond: int = 0) -> OracleResult:
+    """precond = 1: every CG stage preconditioned with M = diag(A) (Jacobi)."""
     rp, col, val = _csr_arrays(a)
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.zeros(a.n, dtype=np.float64)
-    opts = _Opts(k0, tol_mode, max_restarts, knn_k, maxit1, maxit2)
+    opts = _Opts(k0, tol_mode, max_restarts, knn_k, precond, 0, maxit1, maxit2)
     st = _Stats()
     keep = None
     mp = None

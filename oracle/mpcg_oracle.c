@@ -24,7 +24,12 @@
  *                             1/rho weights of eq. (23)).
  *   or_solve               -- Algorithm I (explicit eps1), Algorithm II
  *                             (eps1 = AUTO: k0 FP32 iterations, v of eq. (13),
- *                             kNN, continue), and FP64-only CG (eps1 = NONE).
+ *                             kNN, continue), and FP64-only CG (eps1 = NONE);
+ *                             with precond = 1 every CG stage is the "CG with
+ *                             preconditioning" procedure (subsection
+ *                             "Propagation of Rounding Errors When Precondition
+ *                             is Applied") with the Jacobi preconditioner
+ *                             M = diag(A) that the subsection names.
  *
  * Readings where the paper is silent (all documented in the design notes):
  *   - tolerance is relative to ||b||_2 unless tol_mode = 1 (absolute);
@@ -37,6 +42,13 @@
  *   - kNN: loop from sample k+1 with strict '<'; the evicted member is the
  *     farthest one (ties: largest sample index); zero-distance neighbours
  *     vote by count; class-score ties go to the larger eps1 (smaller t).
+ *   - preconditioned CG: the listing's start r_0 <- M^-1 (b - A x_0), d_0 <- r_0
+ *     is read as r_0 = b - A x_0, d_0 = M^-1 r_0 (its loop then is the standard
+ *     recurrence: alpha = r.M^-1 r / d.A d, beta = r'.M^-1 r' / r.M^-1 r,
+ *     d' = M^-1 r' + beta d); z = M^-1 r is r_i / a_ii, one division per
+ *     element in the working precision; the stop test is on ||r|| as in the
+ *     unpreconditioned stages; a missing or non-positive diagonal entry (no
+ *     SPD matrix has one) is reported as not SPD.
  */
 #include <math.h>
 #include <stdint.h>
@@ -61,6 +73,8 @@ typedef struct {
     int32_t tol_mode;     /* 0: relative to ||b||, 1: absolute */
     int32_t max_restarts; /* extra FP64 restarts after a failed final check */
     int32_t knn_k;        /* 0: take k from the model */
+    int32_t precond;      /* 0: none, 1: Jacobi (M = diag(A)) */
+    int32_t pad;
     int64_t maxit1;       /* FP32 iteration cap, <=0: n */
     int64_t maxit2;       /* FP64 iteration cap, <=0: max(10n, 1000) */
 } or_opts;
@@ -301,9 +315,22 @@ typedef struct {
     int64_t n;
     const int64_t *rp; const int32_t *col;
     const float *val;
-    float *x, *r, *d, *q;
-    double gamma;
+    const float *dg;      /* diagonal of A~ (Jacobi), or NULL: no preconditioner */
+    float *x, *r, *d, *q, *z;
+    double gamma;         /* r.r (stop test, v ratios) */
+    double rho;           /* r.M^-1 r (alpha, beta); equals gamma without a preconditioner */
 } cg32_state;
+
+/* z = M^-1 r and rho = r.z for the current residual. */
+static void precond32(cg32_state *s)
+{
+    if (s->dg) {
+        for (int64_t i = 0; i < s->n; ++i) s->z[i] = s->r[i] / s->dg[i];
+        s->rho = dot32(s->n, s->r, s->z);
+    } else {
+        s->rho = s->gamma;
+    }
+}
 
 /* One FP32 CG iteration.  Returns 0 on success, 1 on breakdown (delta not
  * positive or not finite; the iterate is left unchanged). */
@@ -313,23 +340,35 @@ static int cg32_step(cg32_state *s)
     or_spmv32(n, s->rp, s->col, s->val, s->d, s->q);
     double delta = dot32(n, s->d, s->q);
     if (!isfinite(delta) || !(delta > 0.0)) return 1;
-    float alpha = (float)(s->gamma / delta);
+    float alpha = (float)(s->rho / delta);
     for (int64_t i = 0; i < n; ++i) {
         s->x[i] = fmaf(alpha, s->d[i], s->x[i]);
         s->r[i] = fmaf(-alpha, s->q[i], s->r[i]);
     }
-    double gnew = dot32(n, s->r, s->r);
-    float beta = (float)(gnew / s->gamma);
-    for (int64_t i = 0; i < n; ++i) s->d[i] = fmaf(beta, s->d[i], s->r[i]);
-    s->gamma = gnew;
+    double rho_old = s->rho;
+    s->gamma = dot32(n, s->r, s->r);
+    precond32(s);
+    float beta = (float)(s->rho / rho_old);
+    const float *src = s->dg ? s->z : s->r;   /* M^-1 r' */
+    for (int64_t i = 0; i < n; ++i) s->d[i] = fmaf(beta, s->d[i], src[i]);
     return 0;
+}
+
+/* Diagonal of A (the entry with col == row); 0 if a row has none. */
+static void diagonal(int64_t n, const int64_t *rp, const int32_t *col, const double *val, double *dg)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        dg[i] = 0.0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+            if (col[k] == i) dg[i] = val[k];
+    }
 }
 
 int or_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
              const double *b, double *x, double eps1, double eps2,
              const or_opts *opt_in, const or_model *model, or_stats *st)
 {
-    or_opts opt = {20, 0, 5, 0, 0, 0};
+    or_opts opt = {20, 0, 5, 0, 0, 0, 0, 0};
     if (opt_in) opt = *opt_in;
     or_stats S;
     memset(&S, 0, sizeof(S));
@@ -359,6 +398,22 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val
         if (st) { S.status = OR_ENOMODEL; *st = S; }
         return OR_ENOMODEL;
     }
+    if (opt.precond < 0 || opt.precond > 1) {
+        if (st) { S.status = OR_EINVAL; *st = S; }
+        return OR_EINVAL;
+    }
+    double *dg64 = NULL;
+    if (opt.precond == 1) {
+        dg64 = (double *)malloc(sizeof(double) * (size_t)n);
+        diagonal(n, rp, col, val, dg64);
+        for (int64_t i = 0; i < n; ++i) {
+            if (!(dg64[i] > 0.0)) {
+                free(dg64);
+                if (st) { S.status = OR_ENOTSPD; *st = S; }
+                return OR_ENOTSPD;
+            }
+        }
+    }
     int64_t maxit1 = opt.maxit1 > 0 ? opt.maxit1 : n;
     int64_t maxit2 = opt.maxit2 > 0 ? opt.maxit2 : (10 * n > 1000 ? 10 * n : 1000);
 
@@ -366,6 +421,7 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val
     S.beta_b = beta_b;
     if (beta_b == 0.0) {
         for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        free(dg64);
         if (st) { S.status = OR_OK; *st = S; }
         return OR_OK;
     }
@@ -374,23 +430,32 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val
     double *r = (double *)malloc(sizeof(double) * (size_t)n);
     double *d = (double *)malloc(sizeof(double) * (size_t)n);
     double *q = (double *)malloc(sizeof(double) * (size_t)n);
+    double *z = (double *)malloc(sizeof(double) * (size_t)n);
 
     if (eps1 != -1.0) {
         /* ---- first stage: FP32 copy of A and b, x~ = 0 ---- */
         float *val32 = (float *)malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
         cg32_state s;
+        float *dg32 = NULL;
         s.n = n; s.rp = rp; s.col = col; s.val = val32;
         s.x = (float *)malloc(sizeof(float) * (size_t)n);
         s.r = (float *)malloc(sizeof(float) * (size_t)n);
         s.d = (float *)malloc(sizeof(float) * (size_t)n);
         s.q = (float *)malloc(sizeof(float) * (size_t)n);
+        s.z = (float *)malloc(sizeof(float) * (size_t)n);
         for (int64_t k = 0; k < nnz; ++k) val32[k] = (float)val[k];
+        if (dg64) {   /* the diagonal of A~ */
+            dg32 = (float *)malloc(sizeof(float) * (size_t)n);
+            for (int64_t i = 0; i < n; ++i) dg32[i] = (float)dg64[i];
+        }
+        s.dg = dg32;
         for (int64_t i = 0; i < n; ++i) {
             s.x[i] = 0.0f;
             s.r[i] = (float)b[i];      /* r~ = b~ - A~ * 0 */
-            s.d[i] = s.r[i];
         }
         s.gamma = dot32(n, s.r, s.r);
+        precond32(&s);
+        for (int64_t i = 0; i < n; ++i) s.d[i] = dg32 ? s.z[i] : s.r[i];   /* d_0 = M^-1 r_0 */
         int64_t n1 = 0;
         int broke = 0;
         double e1 = eps1;
@@ -416,7 +481,7 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val
             int cls = or_knn_select(model, chi, opt.knn_k, NULL, &ex);
             if (cls < 0) {
                 status = cls;
-                free(val32); free(s.x); free(s.r); free(s.d); free(s.q);
+                free(val32); free(s.x); free(s.r); free(s.d); free(s.q); free(s.z); free(dg32);
                 goto done;
             }
             S.eps1_class = cls;
@@ -437,7 +502,7 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val
         S.n1 = (int32_t)n1;
         S.relres_sp = sqrt(s.gamma) / beta_b;
         for (int64_t i = 0; i < n; ++i) x[i] = (double)s.x[i];   /* float64(x~) */
-        free(val32); free(s.x); free(s.r); free(s.d); free(s.q);
+        free(val32); free(s.x); free(s.r); free(s.d); free(s.q); free(s.z); free(dg32);
     } else {
         S.eps1_used = -1.0;
         for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
@@ -447,7 +512,13 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val
     {
         double thr = eps2 * scale;
         double gamma = true_residual(n, rp, col, val, b, x, r);
-        for (int64_t i = 0; i < n; ++i) d[i] = r[i];
+        /* z = M^-1 r, rho = r.z (rho = gamma without a preconditioner), d = z */
+        double rho = gamma;
+        if (dg64) {
+            for (int64_t i = 0; i < n; ++i) z[i] = r[i] / dg64[i];
+            rho = dot64(n, r, z);
+        }
+        for (int64_t i = 0; i < n; ++i) d[i] = dg64 ? z[i] : r[i];
         S.relres_restart_true = sqrt(gamma) / beta_b;
         int64_t n2 = 0;
         int32_t restarts = 0;
@@ -458,15 +529,20 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val
                 double delta = dot64(n, d, q);
                 if (!isfinite(delta)) { status = OR_ENONFINITE; goto final; }
                 if (!(delta > 0.0)) { status = OR_ENOTSPD; goto final; }
-                double alpha = gamma / delta;
+                double alpha = rho / delta;
                 for (int64_t i = 0; i < n; ++i) {
                     x[i] = fma(alpha, d[i], x[i]);
                     r[i] = fma(-alpha, q[i], r[i]);
                 }
-                double gnew = dot64(n, r, r);
-                double beta = gnew / gamma;
-                for (int64_t i = 0; i < n; ++i) d[i] = fma(beta, d[i], r[i]);
-                gamma = gnew;
+                gamma = dot64(n, r, r);
+                double rho_new = gamma;
+                if (dg64) {
+                    for (int64_t i = 0; i < n; ++i) z[i] = r[i] / dg64[i];
+                    rho_new = dot64(n, r, z);
+                }
+                double beta = rho_new / rho;
+                for (int64_t i = 0; i < n; ++i) d[i] = fma(beta, d[i], dg64 ? z[i] : r[i]);
+                rho = rho_new;
                 ++n2;
             }
             {
@@ -477,7 +553,12 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val
                 ++restarts;
                 S.flags |= OR_FLAG_FINAL_RESTARTED;
                 gamma = true_residual(n, rp, col, val, b, x, r);
-                for (int64_t i = 0; i < n; ++i) d[i] = r[i];
+                rho = gamma;
+                if (dg64) {
+                    for (int64_t i = 0; i < n; ++i) z[i] = r[i] / dg64[i];
+                    rho = dot64(n, r, z);
+                }
+                for (int64_t i = 0; i < n; ++i) d[i] = dg64 ? z[i] : r[i];
             }
         }
     final:
@@ -489,7 +570,7 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val
         }
     }
 done:
-    free(r); free(d); free(q);
+    free(r); free(d); free(q); free(z); free(dg64);
     S.status = status;
     if (st) *st = S;
     return status;
@@ -541,6 +622,8 @@ void or_cg_true_residuals(int32_t prec, int64_t n, const int64_t *rp, const int3
         float *val32 = (float *)malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
         cg32_state s;
         s.n = n; s.rp = rp; s.col = col; s.val = val32;
+        s.dg = NULL;
+        s.z = NULL;
         s.x = (float *)calloc((size_t)n, sizeof(float));
         s.r = (float *)malloc(sizeof(float) * (size_t)n);
         s.d = (float *)malloc(sizeof(float) * (size_t)n);
@@ -548,6 +631,7 @@ void or_cg_true_residuals(int32_t prec, int64_t n, const int64_t *rp, const int3
         for (int64_t k = 0; k < nnz; ++k) val32[k] = (float)val[k];
         for (int64_t i = 0; i < n; ++i) { s.r[i] = (float)b[i]; s.d[i] = s.r[i]; }
         s.gamma = dot32(n, s.r, s.r);
+        s.rho = s.gamma;
         for (int64_t it = 0; it <= iters; ++it) {
             for (int64_t i = 0; i < n; ++i) xd[i] = (double)s.x[i];
             true_res[it] = sqrt(true_residual(n, rp, col, val, b, xd, tmp));
