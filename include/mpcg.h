@@ -115,7 +115,11 @@ typedef struct {
     int32_t tol_mode;     /* 0 relative to ||b|| (default), 1 absolute */
     int32_t max_restarts; /* FP64 restarts after a failed final check; default 5 */
     int32_t graph_iters;  /* CG iterations enqueued between host polls; 0 = default (8) */
-    int32_t pad_;
+    int32_t precond;      /* 0 none (default); 1 Jacobi, M = diag(A), in both stages (the
+                             preconditioned CG procedure of the subsection "Propagation of
+                             Rounding Errors When Precondition is Applied"): a row without a
+                             positive finite diagonal entry makes mpcg_solve return ENOTSPD;
+                             not available to the batch engine */
     int64_t maxit1;       /* FP32 cap; <= 0: n */
     int64_t maxit2;       /* FP64 cap; <= 0: max(10 n, 1000) */
 } mpcg_options;

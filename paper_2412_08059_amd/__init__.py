@@ -49,11 +49,12 @@ class Solver:
 
     def __init__(self, n_max: int, nnz_max: int, *, k0: int = 20, knn_k: int = 0, tol_mode: int = 0,
                  max_restarts: int = 5, graph_iters: int = 0, maxit1: int = 0, maxit2: int = 0,
-                 model: str | None = None, device="cuda"):
+                 model: str | None = None, precond: int = 0, device="cuda"):
+        """precond = 1: Jacobi-preconditioned stages (M = diag(A))."""
         import torch
         self.device = torch.device(device)
         self.stream = torch.cuda.current_stream(self.device)
-        opt = mpcg_options(k0, knn_k, tol_mode, max_restarts, graph_iters, 0, maxit1, maxit2)
+        opt = mpcg_options(k0, knn_k, tol_mode, max_restarts, graph_iters, precond, maxit1, maxit2)
         self.ctx = capi.mpcg_create(opt, self.stream.cuda_stream)
         nbytes = capi.mpcg_workspace_size(self.ctx, max(1, n_max), max(0, nnz_max))
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)

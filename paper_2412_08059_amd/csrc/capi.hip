@@ -71,7 +71,7 @@ Layout plan_layout(int64_t n, int64_t nnz)
     L.n = n;
     L.nnz = nnz;
     L.state = take(sizeof(DevState));
-    L.part = take(sizeof(double) * 3 * (size_t)kMaxGrid);   // product partials (2 per block), update partials
+    L.part = take(sizeof(double) * 5 * (size_t)kMaxGrid);   // product partials (up to 3 per block), update partials (up to 2)
     L.rp32 = take(sizeof(int32_t) * (N + 1));
     L.val32 = take(sizeof(float) * M);
     L.x32 = take(sizeof(float) * N);
@@ -99,6 +99,10 @@ Layout plan_layout(int64_t n, int64_t nnz)
     L.sell_v32 = take(sizeof(float) * (size_t)L.sell_cap);
     L.ingest_blk = take(sizeof(int32_t) * 3 * ((N + kBlock - 1) / kBlock + 1));
     L.snap32 = take(sizeof(float) * kNumEps * N);
+    L.z32 = take(sizeof(float) * N);
+    L.z64 = take(sizeof(double) * N);
+    L.dg32 = take(sizeof(float) * N);
+    L.dg64 = take(sizeof(double) * N);
     L.total = off;
     return L;
 }
@@ -136,8 +140,11 @@ struct Plan {
     const int32_t *col = nullptr;
     const double *val = nullptr;
     DevState *st = nullptr;
-    double *sp = nullptr;   // partials written by the product kernels (2 per block)
-    double *up = nullptr;   // partials written by the update kernel
+    double *sp = nullptr;   // partials written by the product kernels (up to 3 per block)
+    double *up = nullptr;   // partials written by the update kernel (2 per block with Jacobi)
+    int pc = 0;             // Jacobi-preconditioned stages
+    float *z32 = nullptr, *dg32 = nullptr;
+    double *z64 = nullptr, *dg64 = nullptr;
     SpmvShape sh32{}, sh64{};
     SellMat sell{};
     bool use_sell = false;
@@ -158,7 +165,8 @@ mpcg_status read_state(mpcg_ctx *c, const Plan &p, DevState *out) { return read_
 
 // Validate A (and b) on the device, convert row pointers / cast values when
 // asked, and read back the verdict before any result buffer is touched.
-mpcg_status ingest(mpcg_ctx *c, const mpcg_csr *A, const double *b, bool need_val32, Plan *p)
+mpcg_status ingest(mpcg_ctx *c, const mpcg_csr *A, const double *b, bool need_val32, Plan *p,
+                   bool want_diag = false)
 {
     if (!c || !A || A->n <= 0 || A->n >= 0x7fffffff || A->nnz < 0 || A->nnz >= 0x7fffffff ||
         !A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val)))
@@ -172,7 +180,12 @@ mpcg_status ingest(mpcg_ctx *c, const mpcg_csr *A, const double *b, bool need_va
     p->val = A->val;
     p->st = p->at<DevState>(p->L.state);
     p->sp = p->at<double>(p->L.part);
-    p->up = p->sp + 2 * kMaxGrid;
+    p->up = p->sp + 3 * kMaxGrid;
+    p->pc = want_diag ? 1 : 0;
+    p->z32 = p->at<float>(p->L.z32);
+    p->z64 = p->at<double>(p->L.z64);
+    p->dg32 = p->at<float>(p->L.dg32);
+    p->dg64 = p->at<double>(p->L.dg64);
     int32_t *rp32 = A->row_ptr_is_i64 ? p->at<int32_t>(p->L.rp32) : nullptr;
     p->rp = A->row_ptr_is_i64 ? rp32 : static_cast<const int32_t *>(A->row_ptr);
     HIPCHK(hipMemsetAsync(p->st, 0, sizeof(DevState), c->stream));
@@ -183,6 +196,7 @@ mpcg_status ingest(mpcg_ctx *c, const mpcg_csr *A, const double *b, bool need_va
                        p->L.sell_cap, c->force_csr ? 0 : 1,
                        p->ws + p->L.sell_col, p->at<double>(p->L.sell_v64),
                        need_val32 ? p->at<float>(p->L.sell_v32) : nullptr, p->st);
+    if (want_diag) launch_diag(c->stream, p->rp, A->col_idx, A->val, p->n, p->dg64, p->dg32, p->st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(&c->hst[2].spare_i64, soff + nsl, sizeof(int64_t), hipMemcpyDeviceToHost,
                           c->stream));
@@ -192,6 +206,7 @@ mpcg_status ingest(mpcg_ctx *c, const mpcg_csr *A, const double *b, bool need_va
     const int64_t padded = c->hst[2].spare_i64;
     if (s.ing_err & (kErrRowPtr | kErrCol | kErrUnsorted)) return MPCG_EINVAL;
     if (s.ing_err & (kErrNonFiniteA | kErrNonFiniteB)) return MPCG_ENONFINITE;
+    if (s.ing_err & kErrDiag) return MPCG_ENOTSPD;   // Jacobi needs a positive diagonal (any SPD A has one)
     // the entry kernel filled the SELL copy under exactly this condition
     p->use_sell = !c->force_csr && padded <= p->L.sell_cap;
     p->sh64 = spmv_shape(A->n, A->nnz, 8, c->num_cu);
@@ -234,33 +249,45 @@ template <typename T> T *snap_buf(const Plan &p);
 template <> float *snap_buf<float>(const Plan &p) { return p.at<float>(p.L.snap32); }
 template <> double *snap_buf<double>(const Plan &) { return nullptr; }
 
-// snap is used only by the Algorithm II run-ahead (FP32)
+template <typename T> T *zbuf(const Plan &p);
+template <> float *zbuf<float>(const Plan &p) { return p.z32; }
+template <> double *zbuf<double>(const Plan &p) { return p.z64; }
+template <typename T> const T *dgbuf(const Plan &p);
+template <> const float *dgbuf<float>(const Plan &p) { return p.dg32; }
+template <> const double *dgbuf<double>(const Plan &p) { return p.dg64; }
+
+// The direction is built from r, or from z = M^-1 r with Jacobi.  snap is used
+// only by the Algorithm II run-ahead (FP32).
 template <typename T>
 void run_cg_spmv(hipStream_t s, const Plan &p, const T *r, T *dA, T *dB, T *q, int it, int it0, T *x,
                  T *snap = nullptr)
 {
+    const T *src = p.pc ? zbuf<T>(p) : r;
     if (p.use_sell)
-        launch_sell_cg_spmv<T>(s, p.sell, r, dA, dB, q, p.up, p.nup, p.sp, it, it0, x, snap, p.st);
+        launch_sell_cg_spmv<T>(s, p.sell, src, dA, dB, q, p.up, p.nup, p.sp, it, it0, x, snap, p.pc, p.st);
     else
-        launch_cg_spmv<T>(s, csr_shape<T>(p), p.rp, p.col, csr_vals<T>(p), r, dA, dB, q, p.up, p.nup, p.sp,
-                          it, it0, x, snap, p.st);
+        launch_cg_spmv<T>(s, csr_shape<T>(p), p.rp, p.col, csr_vals<T>(p), src, dA, dB, q, p.up, p.nup, p.sp,
+                          it, it0, x, snap, p.pc, p.st);
 }
 
 template <typename T>
 void run_cg_update(hipStream_t s, const Plan &p, T *r, const T *q, int it)
 {
-    launch_cg_update<T>(s, p.n, r, q, p.sp, prod_grid(p, sizeof(T) == 4), p.up, p.nup, it, p.st);
+    launch_cg_update<T>(s, p.n, r, q, p.sp, prod_grid(p, sizeof(T) == 4), p.up, p.nup, it,
+                        p.pc ? dgbuf<T>(p) : nullptr, p.pc ? zbuf<T>(p) : nullptr, p.st);
 }
 
 void run_restart(hipStream_t s, const Plan &p, const float *x32, double *x, const double *b, double *r,
                  double *dA, double *dB, int it0, double eps, int abs_tol, int32_t maxit)
 {
+    const double *dg = p.pc ? p.dg64 : nullptr;
+    double *z = p.pc ? p.z64 : nullptr;
     if (p.use_sell) {
-        launch_sell_restart(s, p.sell, x32, x, b, r, dA, dB, it0, p.sp, p.st);
+        launch_sell_restart(s, p.sell, x32, x, b, r, dA, dB, it0, dg, z, p.sp, p.st);
         launch_fin_restart(s, p.sp, p.sell.grid, it0, eps, abs_tol, maxit, p.st);
     } else {
-        launch_restart(s, p.sh64, p.rp, p.col, p.val, x32, x, b, r, dA, dB, it0, eps, abs_tol, maxit, p.sp,
-                       p.st);
+        launch_restart(s, p.sh64, p.rp, p.col, p.val, x32, x, b, r, dA, dB, it0, eps, abs_tol, maxit, dg, z,
+                       p.sp, p.st);
     }
 }
 
@@ -440,7 +467,7 @@ mpcg_status fp32_prefix(mpcg_ctx *c, const Plan &p, const double *b, int32_t k0,
     float *x = p.at<float>(p.L.x32), *r = p.at<float>(p.L.r32), *q = p.at<float>(p.L.q32);
     float *dA = p.at<float>(p.L.dA32), *dB = p.at<float>(p.L.dB32);
     // thr = 0: only gamma' = 0 or a breakdown ends the prefix before k0
-    launch_init32(c->stream, b, x, r, dA, p.n, 0.0, 1, k0, k0, p.sp, p.st);
+    launch_init32(c->stream, b, x, r, dA, p.n, 0.0, 1, k0, k0, p.pc ? p.dg32 : nullptr, p.z32, p.sp, p.st);
     HIPCHK(hipGetLastError());
     mpcg_status rc = read_state(c, p, s);
     if (rc != MPCG_OK) return rc;
@@ -497,7 +524,8 @@ mpcg_status mpcg_create(mpcg_ctx **out, const mpcg_options *opt, void *hip_strea
         if (o.k0 <= 0) o.k0 = 20;
         if (o.max_restarts < 0) return MPCG_EINVAL;
     }
-    if (o.k0 > kK0Max || o.tol_mode < 0 || o.tol_mode > 1 || o.knn_k < 0 || o.graph_iters < 0)
+    if (o.k0 > kK0Max || o.tol_mode < 0 || o.tol_mode > 1 || o.knn_k < 0 || o.graph_iters < 0 ||
+        o.precond < 0 || o.precond > 1)
         return MPCG_EINVAL;
     mpcg_ctx *c = new (std::nothrow) mpcg_ctx();
     if (!c) return MPCG_EDEVICE;
@@ -606,7 +634,7 @@ mpcg_status mpcg_features(mpcg_ctx *c, const mpcg_csr *A, const double *b, int32
 {
     if (!c || !b || !out || k0 <= 0 || k0 > kK0Max) return MPCG_EINVAL;
     Plan p;
-    mpcg_status rc = ingest(c, A, b, true, &p);
+    mpcg_status rc = ingest(c, A, b, true, &p, c->opt.precond == 1);
     if (rc != MPCG_OK) return rc;
     mpcg_features_t f{};
     f.n = A->n;
@@ -637,7 +665,7 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
     S.eps1_used = dponly ? -1.0 : eps1;
     HIPCHK(hipEventRecord(c->tm[0], c->stream));
     Plan p;
-    mpcg_status rc = ingest(c, A, b, !dponly, &p);
+    mpcg_status rc = ingest(c, A, b, !dponly, &p, c->opt.precond == 1);
     if (rc != MPCG_OK) { S.status = rc; if (stats) *stats = S; return rc; }
     const int abs_tol = c->opt.tol_mode == 1;
     const int64_t n = A->n;
@@ -722,7 +750,8 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
                 // reaching eps1: s already holds that stop
             }
         } else {
-            launch_init32(c->stream, b, x32, r32, dA32, p.n, eps1, abs_tol, maxit1, 0, p.sp, p.st);
+            launch_init32(c->stream, b, x32, r32, dA32, p.n, eps1, abs_tol, maxit1, 0, p.pc ? p.dg32 : nullptr,
+                          p.z32, p.sp, p.st);
             HIPCHK(hipGetLastError());
             rc = read_state(c, p, &s);
             if (rc != MPCG_OK) return rc;
@@ -888,7 +917,7 @@ mpcg_status mpcg_time_kernel(mpcg_ctx *c, const mpcg_csr *A, int32_t kernel, int
         launch_fill_f64(c->stream, dA64, p.n, 0.25);
         launch_fill_f64(c->stream, dB64, p.n, 0.25);
     }
-    launch_timing_state(c->stream, p.st, p.sp, 3 * kMaxGrid);
+    launch_timing_state(c->stream, p.st, p.sp, 5 * kMaxGrid);
     HIPCHK(hipGetLastError());
     auto one = [&]() {
         switch (kernel) {
@@ -943,6 +972,7 @@ mpcg_status mpcg_batch_set_workspace(mpcg_ctx *c, void *arena, size_t bytes, int
                                      int64_t max_entries, int32_t max_systems)
 {
     if (!c || !arena || ((uintptr_t)arena & 255)) return MPCG_EINVAL;
+    if (c->opt.precond != 0) return MPCG_EINVAL;   // the batched engine runs unpreconditioned stages
     if (c->eng) return MPCG_EBUSY;
     int st = MPCG_OK;
     c->eng = mpcg::batch::engine_create(c->device, c->opt, &c->model, arena, bytes, max_rows, max_entries,

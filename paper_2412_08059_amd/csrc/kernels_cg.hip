@@ -148,11 +148,12 @@ void launch_fill_i32(hipStream_t s, int32_t *p, int64_t n, int32_t v)
 // ------------------------------------------------------------ phase init --
 
 // Sets the stop test of a phase from the freshly reduced gamma.
-__device__ inline void start_phase(DevState *st, double gamma, int32_t iter, double eps, int abs_tol,
+__device__ inline void start_phase(DevState *st, double gamma, double rho, int32_t iter, double eps, int abs_tol,
                                    int32_t maxit)
 {
     st->gamma = gamma;
-    st->gam[iter & 1] = gamma;
+    st->gam[iter & 1] = rho;
+    st->gr[iter & 1] = gamma;
     st->iter = iter;
     st->thr = abs_tol ? eps : eps * sqrt(st->bnorm2);
     st->maxit = maxit;
@@ -176,14 +177,15 @@ __device__ inline void resume_phase(DevState *st)
     st->reason = kRunning;
 }
 
-// FP32 phase from x~ = 0: r~ = float32(b), old direction = 0; partials of
-// r~.r~ and b.b (FP64) for k_fin_init32.
+// FP32 phase from x~ = 0: r~ = float32(b), old direction = 0, z = r~ / dg
+// (Jacobi); partials of r~.r~, b.b and r~.z (r~.r~ without a preconditioner)
+// in FP64 for k_fin_init32.
 __global__ void __launch_bounds__(kBlock)
 k_init32(const double *__restrict__ b, float *__restrict__ x, float *__restrict__ r,
-         float *__restrict__ dA, int32_t n, double *part)
+         float *__restrict__ dA, int32_t n, const float *__restrict__ dg, float *__restrict__ z, double *part)
 {
     __shared__ double sm[kBlock / 64 + 1];
-    double s0 = 0.0, s1 = 0.0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     const int64_t nchunk = ((int64_t)n + kVecTile - 1) / kVecTile;
     for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
 #pragma unroll
@@ -197,14 +199,21 @@ k_init32(const double *__restrict__ b, float *__restrict__ x, float *__restrict_
                 dA[i] = 0.0f;
                 s0 = fma((double)rv, (double)rv, s0);
                 s1 = fma(bv, bv, s1);
+                if (dg) {
+                    const float zv = rv / dg[i];
+                    z[i] = zv;
+                    s2 = fma((double)rv, (double)zv, s2);
+                }
             }
         }
     }
     s0 = block_sum(s0, sm);
     s1 = block_sum(s1, sm);
+    s2 = dg ? block_sum(s2, sm) : s0;
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = s0;
-        part[2 * blockIdx.x + 1] = s1;
+        part[3 * blockIdx.x] = s0;
+        part[3 * blockIdx.x + 1] = s1;
+        part[3 * blockIdx.x + 2] = s2;
     }
 }
 
@@ -213,20 +222,22 @@ k_fin_init32(const double *part, int cnt, double eps, int abs_tol, int32_t maxit
              DevState *st)
 {
     __shared__ double sm[kBlock / 64 + 1];
-    const double g = reduce_partials(part, cnt, 2, 0, sm);
-    const double bb = reduce_partials(part, cnt, 2, 1, sm);
+    const double g = reduce_partials(part, cnt, 3, 0, sm);
+    const double bb = reduce_partials(part, cnt, 3, 1, sm);
+    const double rho = reduce_partials(part, cnt, 3, 2, sm);
     if (threadIdx.x == 0) {
         st->bnorm2 = bb;
         st->k0rec = k0rec;
-        start_phase(st, g, 0, eps, abs_tol, maxit);
+        start_phase(st, g, rho, 0, eps, abs_tol, maxit);
     }
 }
 
 void launch_init32(hipStream_t s, const double *b, float *x, float *r, float *dA, int32_t n,
-                   double eps, int abs_tol, int32_t maxit, int32_t k0rec, double *part, DevState *st)
+                   double eps, int abs_tol, int32_t maxit, int32_t k0rec, const float *dg, float *z,
+                   double *part, DevState *st)
 {
     const int grid = vec_grid(n);
-    hipLaunchKernelGGL(k_init32, dim3(grid), dim3(kBlock), 0, s, b, x, r, dA, n, part);
+    hipLaunchKernelGGL(k_init32, dim3(grid), dim3(kBlock), 0, s, b, x, r, dA, n, dg, z, part);
     hipLaunchKernelGGL(k_fin_init32, dim3(1), dim3(kBlock), 0, s, part, grid, eps, abs_tol, maxit, k0rec,
                        st);
 }
@@ -279,6 +290,8 @@ __global__ void k_timing_state(DevState *st, double *part, int cnt)
         st->gamma = 1.0;
         st->gam[0] = 1.0;
         st->gam[1] = 1.0;
+        st->gr[0] = 1.0;
+        st->gr[1] = 1.0;
         st->thr = 0.0;
         st->iter = 0;
         st->maxit = 0x7fffffff;
@@ -310,6 +323,9 @@ struct SpmvArgs {
     int32_t R;         // rows per tile
     int32_t ntiles;
     int32_t it, it0;   // CG iteration and the first iteration of the phase
+    int32_t pc;        // Jacobi: the update partials hold rho (slot b) and r.r (slot nup + b)
+    const double *dg;  // restart with Jacobi: diag(A) and z = r / diag(A)
+    double *z;
     // CG
     const T *r;
     T *dA, *dB, *q;
@@ -340,7 +356,7 @@ template <int MODE, typename T>
 __global__ void __launch_bounds__(kBlock) k_spmv(SpmvArgs<T> a)
 {
     constexpr int CHUNK = kLdsBytes / (2 * (int)sizeof(T));
-    constexpr int NV = (MODE == kModeRestart) ? 2 : 1;
+    constexpr int NV = (MODE == kModeRestart) ? 3 : 1;
     __shared__ T s_val[CHUNK];
     __shared__ T s_x[CHUNK];
     __shared__ double sm[kBlock / 64 + 1];
@@ -364,13 +380,17 @@ __global__ void __launch_bounds__(kBlock) k_spmv(SpmvArgs<T> a)
         dnew = (it & 1) ? a.dA : a.dB;
         if (it != a.it0) {
             const bool xdone = s_xdone;
-            const double g = reduce_partials(a.up, a.nup, 1, 0, sm);
-            const double gp = st->gam[(it - 1) & 1];
+            // rho_it (alpha, beta) and gamma_it = r.r (stop test, v); equal without a preconditioner
+            const double rho = reduce_partials(a.up, a.nup, 1, 0, sm);
+            const double g = a.pc ? reduce_partials(a.up + a.nup, a.nup, 1, 0, sm) : rho;
+            const double gp = st->gr[(it - 1) & 1];
+            const double rhop = st->gam[(it - 1) & 1];
             alpha_prev = (T)st->alph[(it - 1) & 1];
             const bool conv = sqrt(g) <= st->thr;
             const bool cap = !conv && it >= st->maxit;
             if (blockIdx.x == 0 && tid == 0) {
-                st->gam[it & 1] = g;
+                st->gam[it & 1] = rho;
+                st->gr[it & 1] = g;
                 const int k = it - 1;
                 if (k < st->k0rec && k < kK0Max) st->ratios[k] = sqrt(g) / sqrt(gp);
                 if (conv || cap) {
@@ -404,7 +424,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv(SpmvArgs<T> a)
             } else {
                 x_pending = !xdone;
             }
-            beta = (T)(g / gp);
+            beta = (T)(rho / rhop);
         }
     }
 
@@ -468,7 +488,13 @@ __global__ void __launch_bounds__(kBlock) k_spmv(SpmvArgs<T> a)
                     a.rout[my_row] = res;
                     double *dz = (a.it0 & 1) ? a.dzB : a.dzA;
                     dz[my_row] = 0.0;
-                    s[NV - 1] = fma(bv, bv, s[NV - 1]);
+                    s[1] = fma(bv, bv, s[1]);
+                    double zv = res;
+                    if (a.dg) {
+                        zv = res / a.dg[my_row];
+                        a.z[my_row] = zv;
+                    }
+                    s[2] = fma(res, zv, s[2]);
                 }
                 s[0] = fma(res, res, s[0]);
             }
@@ -487,12 +513,13 @@ k_fin_restart(const double *part, int cnt, int32_t it0, double eps, int abs_tol,
               DevState *st)
 {
     __shared__ double sm[kBlock / 64 + 1];
-    const double g = reduce_partials(part, cnt, 2, 0, sm);
-    const double bb = reduce_partials(part, cnt, 2, 1, sm);
+    const double g = reduce_partials(part, cnt, 3, 0, sm);
+    const double bb = reduce_partials(part, cnt, 3, 1, sm);
+    const double rho = reduce_partials(part, cnt, 3, 2, sm);
     if (threadIdx.x == 0) {
         st->bnorm2 = bb;
         st->k0rec = 0;
-        start_phase(st, g, it0, eps, abs_tol, maxit);
+        start_phase(st, g, rho, it0, eps, abs_tol, maxit);
     }
 }
 
@@ -514,10 +541,10 @@ static SpmvArgs<T> spmv_args(const SpmvShape &sh, const int32_t *rp, const int32
 template <typename T>
 void launch_cg_spmv(hipStream_t s, const SpmvShape &sh, const int32_t *rp, const int32_t *col,
                     const T *val, const T *r, T *dA, T *dB, T *q, const double *up, int nup,
-                    double *part, int it, int it0, T *x, T *snap, DevState *st)
+                    double *part, int it, int it0, T *x, T *snap, int pc, DevState *st)
 {
     SpmvArgs<T> a = spmv_args<T>(sh, rp, col, val);
-    a.it = it; a.it0 = it0; a.x = x; a.snap = snap;
+    a.it = it; a.it0 = it0; a.x = x; a.snap = snap; a.pc = pc;
     a.r = r; a.dA = dA; a.dB = dB; a.q = q; a.up = up; a.nup = nup; a.part = part; a.st = st;
     hipLaunchKernelGGL((k_spmv<kModeCg, T>), dim3(sh.grid), dim3(kBlock), 0, s, a);
 }
@@ -525,10 +552,12 @@ void launch_cg_spmv(hipStream_t s, const SpmvShape &sh, const int32_t *rp, const
 void launch_restart(hipStream_t s, const SpmvShape &sh, const int32_t *rp, const int32_t *col,
                     const double *val, const float *x32, double *x64, const double *b, double *r,
                     double *dA, double *dB, int it0, double eps, int abs_tol, int32_t maxit,
-                    double *part, DevState *st)
+                    const double *dg, double *z, double *part, DevState *st)
 {
     SpmvArgs<double> a = spmv_args<double>(sh, rp, col, val);
     a.it0 = it0;
+    a.dg = dg;
+    a.z = z;
     a.x32 = x32; a.x64in = x64; a.x64out = x64; a.b = b; a.rout = r; a.dzA = dA; a.dzB = dB;
     a.part = part; a.st = st;
     hipLaunchKernelGGL((k_spmv<kModeRestart, double>), dim3(sh.grid), dim3(kBlock), 0, s, a);
@@ -566,12 +595,14 @@ void launch_spmv_plain(hipStream_t s, const SpmvShape &sh, const int32_t *rp, co
 
 // ------------------------------------------------------------- update --
 
-// Update of iteration it: alpha = gamma_it / delta, r -= alpha q, partials of
-// r.r.  x += alpha d is left to the next product, which reads d anyway.
-template <typename T>
+// Update of iteration it: alpha = rho_it / delta, r -= alpha q, partials of
+// r.r -- or, with Jacobi (PC), z = r / diag(A) and partials of r.z (slot b)
+// and r.r (slot nup + b).  x += alpha d is left to the next product, which
+// reads d anyway.
+template <typename T, bool PC>
 __global__ void __launch_bounds__(kBlock)
 k_cg_update(int32_t n, T *__restrict__ r, const T *__restrict__ q, const double *sp, int nsp, double *up,
-            int it, DevState *st)
+            int it, const T *__restrict__ dg, T *__restrict__ z, DevState *st)
 {
     __shared__ double sm[kBlock / 64 + 1];
     __shared__ int s_skip;
@@ -583,7 +614,7 @@ k_cg_update(int32_t n, T *__restrict__ r, const T *__restrict__ q, const double 
     if (!isfinite(delta) || !(delta > 0.0)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             st->delta = delta;
-            st->gamma = g;
+            st->gamma = st->gr[it & 1];
             st->iter = it;
             st->reason = isfinite(delta) ? kNotSpd : kNonFinite;
             st->stop_it = it;
@@ -597,7 +628,7 @@ k_cg_update(int32_t n, T *__restrict__ r, const T *__restrict__ q, const double 
         st->alpha = (double)alpha;
         st->alph[it & 1] = (double)alpha;
     }
-    double s = 0.0;
+    double s = 0.0, s2 = 0.0;
     const int64_t nchunk = ((int64_t)n + kVecTile - 1) / kVecTile;
     for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
 #pragma unroll
@@ -606,33 +637,76 @@ k_cg_update(int32_t n, T *__restrict__ r, const T *__restrict__ q, const double 
             if (i < n) {
                 const T rv = fmaT<T>(-alpha, q[i], r[i]);
                 r[i] = rv;
-                s = fma((double)rv, (double)rv, s);
+                s2 = fma((double)rv, (double)rv, s2);
+                if (PC) {
+                    const T zv = rv / dg[i];
+                    z[i] = zv;
+                    s = fma((double)rv, (double)zv, s);
+                }
             }
         }
     }
-    s = block_sum(s, sm);
-    if (threadIdx.x == 0) up[blockIdx.x] = s;
+    if (PC) {
+        s = block_sum(s, sm);
+        s2 = block_sum(s2, sm);
+        if (threadIdx.x == 0) {
+            up[blockIdx.x] = s;
+            up[gridDim.x + blockIdx.x] = s2;
+        }
+    } else {
+        s2 = block_sum(s2, sm);
+        if (threadIdx.x == 0) up[blockIdx.x] = s2;
+    }
 }
 
 template <typename T>
 void launch_cg_update(hipStream_t s, int32_t n, T *r, const T *q, const double *sp, int nsp, double *up,
-                      int nup, int it, DevState *st)
+                      int nup, int it, const T *dg, T *z, DevState *st)
 {
-    hipLaunchKernelGGL(k_cg_update<T>, dim3(nup), dim3(kBlock), 0, s, n, r, q, sp, nsp, up, it, st);
+    if (dg)
+        hipLaunchKernelGGL((k_cg_update<T, true>), dim3(nup), dim3(kBlock), 0, s, n, r, q, sp, nsp, up, it, dg, z,
+                           st);
+    else
+        hipLaunchKernelGGL((k_cg_update<T, false>), dim3(nup), dim3(kBlock), 0, s, n, r, q, sp, nsp, up, it, dg,
+                           z, st);
+}
+
+// Thread per row: the diagonal entry of A (CSR order, columns sorted).
+__global__ void __launch_bounds__(kBlock)
+k_diag(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const double *__restrict__ val,
+       int32_t n, double *dg64, float *dg32, DevState *st)
+{
+    int bad = 0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        double d = 0.0;
+        const int e = rp[i + 1];
+        for (int k = rp[i]; k < e; ++k)
+            if (col[k] == i) d = val[k];
+        dg64[i] = d;
+        dg32[i] = (float)d;
+        if (!(d > 0.0) || !isfinite(d) || !((float)d > 0.0f) || !isfinite((float)d)) bad = 1;
+    }
+    if (bad) atomicOr(&st->ing_err, kErrDiag);
+}
+
+void launch_diag(hipStream_t s, const int32_t *rp, const int32_t *col, const double *val, int32_t n,
+                 double *dg64, float *dg32, DevState *st)
+{
+    hipLaunchKernelGGL(k_diag, dim3(fill_grid(n)), dim3(kBlock), 0, s, rp, col, val, n, dg64, dg32, st);
 }
 
 template void launch_cg_spmv<float>(hipStream_t, const SpmvShape &, const int32_t *, const int32_t *,
                                     const float *, const float *, float *, float *, float *,
-                                    const double *, int, double *, int, int, float *, float *,
+                                    const double *, int, double *, int, int, float *, float *, int,
                                     DevState *);
 template void launch_cg_spmv<double>(hipStream_t, const SpmvShape &, const int32_t *, const int32_t *,
                                      const double *, const double *, double *, double *, double *,
-                                     const double *, int, double *, int, int, double *, double *,
+                                     const double *, int, double *, int, int, double *, double *, int,
                                      DevState *);
 template void launch_cg_update<float>(hipStream_t, int32_t, float *, const float *, const double *, int,
-                                      double *, int, int, DevState *);
+                                      double *, int, int, const float *, float *, DevState *);
 template void launch_cg_update<double>(hipStream_t, int32_t, double *, const double *, const double *,
-                                       int, double *, int, int, DevState *);
+                                       int, double *, int, int, const double *, double *, DevState *);
 template void launch_spmv_plain<float>(hipStream_t, const SpmvShape &, const int32_t *, const int32_t *,
                                        const float *, const float *, float *);
 template void launch_spmv_plain<double>(hipStream_t, const SpmvShape &, const int32_t *,

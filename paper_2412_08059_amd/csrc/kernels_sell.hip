@@ -307,6 +307,9 @@ struct SellArgs {
     T *yout;
     T *x;        // CG iterate: receives the deferred alpha_{it-1} d_{it-1}
     T *snap;     // x~ copies at the run-ahead crossings (FP32 only)
+    int32_t pc;          // Jacobi: the update partials hold rho (slot b) and r.r (slot nup + b)
+    const double *dg;    // restart with Jacobi: diag(A) and z = r / diag(A)
+    double *z;
     double *part;
     DevState *st;
 };
@@ -315,7 +318,7 @@ struct SellArgs {
 template <int MODE, typename T, typename IDX, int B>
 __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
 {
-    constexpr int NV = (MODE == kSellRestart) ? 2 : 1;
+    constexpr int NV = (MODE == kSellRestart) ? 3 : 1;
     __shared__ double sm[kBlock / 64 + 1];
     DevState *st = a.st;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -337,13 +340,17 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
         dnew = (it & 1) ? a.dA : a.dB;
         if (it != a.it0) {
             const bool xdone = s_xdone;
-            const double g = sell_reduce_partials(a.up, a.nup, sm);
-            const double gp = st->gam[(it - 1) & 1];
+            // rho_it (alpha, beta) and gamma_it = r.r (stop test, v); equal without a preconditioner
+            const double rho = sell_reduce_partials(a.up, a.nup, sm);
+            const double g = a.pc ? sell_reduce_partials(a.up + a.nup, a.nup, sm) : rho;
+            const double gp = st->gr[(it - 1) & 1];
+            const double rhop = st->gam[(it - 1) & 1];
             alpha_prev = (T)st->alph[(it - 1) & 1];
             const bool conv = sqrt(g) <= st->thr;
             const bool cap = !conv && it >= st->maxit;
             if (blockIdx.x == 0 && tid == 0) {
-                st->gam[it & 1] = g;
+                st->gam[it & 1] = rho;
+                st->gr[it & 1] = g;
                 const int k = it - 1;
                 if (k < st->k0rec && k < kK0Max) st->ratios[k] = sqrt(g) / sqrt(gp);
                 if (conv || cap) {
@@ -376,7 +383,7 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
             } else {
                 x_pending = !xdone;
             }
-            beta = (T)(g / gp);
+            beta = (T)(rho / rhop);
         }
     }
 
@@ -437,7 +444,13 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
                     a.rout[row] = res;
                     double *dz = (a.it0 & 1) ? a.dzB : a.dzA;
                     dz[row] = 0.0;
-                    s[NV - 1] = fma(bv, bv, s[NV - 1]);
+                    s[1] = fma(bv, bv, s[1]);
+                    double zv = res;
+                    if (a.dg) {
+                        zv = res / a.dg[row];
+                        a.z[row] = zv;
+                    }
+                    s[2] = fma(res, zv, s[2]);
                 }
                 s[0] = fma(res, res, s[0]);
             }
@@ -480,21 +493,23 @@ template <> const double *sell_vals<double>(const SellMat &m) { return m.v64; }
 
 template <typename T>
 void launch_sell_cg_spmv(hipStream_t s, const SellMat &m, const T *r, T *dA, T *dB, T *q,
-                         const double *up, int nup, double *part, int it, int it0, T *x, T *snap,
+                         const double *up, int nup, double *part, int it, int it0, T *x, T *snap, int pc,
                          DevState *st)
 {
     SellArgs<T> a = sell_args<T>(m, sell_vals<T>(m));
     a.it = it; a.it0 = it0; a.r = r; a.dA = dA; a.dB = dB; a.q = q; a.up = up; a.nup = nup;
-    a.x = x; a.snap = snap;
+    a.x = x; a.snap = snap; a.pc = pc;
     a.part = part; a.st = st;
     sell_launch<kSellCg, T>(s, m, a);
 }
 
 void launch_sell_restart(hipStream_t s, const SellMat &m, const float *x32, double *x64,
-                         const double *b, double *r, double *dA, double *dB, int it0, double *part,
-                         DevState *st)
+                         const double *b, double *r, double *dA, double *dB, int it0, const double *dg,
+                         double *z, double *part, DevState *st)
 {
     SellArgs<double> a = sell_args<double>(m, m.v64);
+    a.dg = dg;
+    a.z = z;
     a.it0 = it0; a.x32 = x32; a.x64in = x64; a.x64out = x64; a.b = b; a.rout = r; a.dzA = dA; a.dzB = dB;
     a.part = part; a.st = st;
     sell_launch<kSellRestart, double>(s, m, a);
@@ -518,10 +533,10 @@ void launch_sell_plain(hipStream_t s, const SellMat &m, const T *x, T *y)
 
 template void launch_sell_cg_spmv<float>(hipStream_t, const SellMat &, const float *, float *, float *,
                                          float *, const double *, int, double *, int, int, float *,
-                                         float *, DevState *);
+                                         float *, int, DevState *);
 template void launch_sell_cg_spmv<double>(hipStream_t, const SellMat &, const double *, double *,
                                           double *, double *, const double *, int, double *, int, int,
-                                          double *, double *, DevState *);
+                                          double *, double *, int, DevState *);
 template void launch_sell_plain<float>(hipStream_t, const SellMat &, const float *, float *);
 template void launch_sell_plain<double>(hipStream_t, const SellMat &, const double *, double *);
 

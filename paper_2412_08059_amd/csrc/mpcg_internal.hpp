@@ -30,21 +30,24 @@ enum StopReason : int32_t { kRunning = 0, kConverged = 1, kMaxit = 2, kNotSpd = 
 constexpr int32_t kNoStop = 0x7fffffff;   // DevState::stop_it while the recurrence runs
 
 enum IngestError : int32_t {
-    kErrRowPtr = 1, kErrCol = 2, kErrUnsorted = 4, kErrNonFiniteA = 8, kErrNonFiniteB = 16
+    kErrRowPtr = 1, kErrCol = 2, kErrUnsorted = 4, kErrNonFiniteA = 8, kErrNonFiniteB = 16,
+    kErrDiag = 32   // Jacobi: a row without a positive, finite diagonal entry
 };
 
 // Device-resident solver state: every scalar of the CG recurrence lives here,
 // so kernels can be enqueued ahead of the host and stop by themselves.
 struct alignas(256) DevState {
     // CG recurrence (FP64 storage; alpha/beta hold the working-precision value)
-    double gamma;     // r.r of the current residual
+    double gamma;     // r.r of the current residual (at a stop or a phase start)
     double delta;     // d.(A d) of the last iteration
     double alpha;
     double beta;
     double thr;       // stop when sqrt(gamma) <= thr
     double bnorm2;    // ||b||^2 (FP64)
     double resid2;    // ||b - A x||^2 from the residual kernel
-    double gam[2];    // gamma_i by parity of i (the product of iteration i writes slot i & 1)
+    double gam[2];    // rho_i = r_i.M^-1 r_i by parity of i (= r_i.r_i without a preconditioner);
+                      // the product of iteration i writes slot i & 1
+    double gr[2];     // r_i.r_i by parity of i (stop test, v ratios)
     double alph[2];   // alpha_i by parity of i (the update of iteration i writes slot i & 1)
     int32_t iter;     // iteration at which the phase started or stopped
     int32_t maxit;
@@ -93,6 +96,7 @@ struct Layout {
     size_t dist, q0, q1, label, tarr, best;
     size_t sell_wid, sell_off, sell_col, sell_v64, sell_v32, ingest_blk;
     size_t snap32;      // kNumEps copies of x~ taken at the candidate thresholds
+    size_t z32, z64, dg32, dg64;   // Jacobi: M^-1 r and diag(A) in both precisions
     int64_t sell_cap;   // padded entries the SELL arrays can hold
     size_t total;
     int64_t n, nnz;
@@ -148,8 +152,15 @@ void launch_cast32(hipStream_t s, const double *val, float *val32, int64_t nnz);
 void launch_fill_f64(hipStream_t s, double *p, int64_t n, double v);
 void launch_fill_f32(hipStream_t s, float *p, int64_t n, float v);
 void launch_fill_i32(hipStream_t s, int32_t *p, int64_t n, int32_t v);
+// FP32 phase start.  Jacobi (dg != nullptr): z = r / dg as well, and the
+// phase's rho is r.z; otherwise rho = r.r.
 void launch_init32(hipStream_t s, const double *b, float *x, float *r, float *dA, int32_t n,
-                   double eps, int abs_tol, int32_t maxit, int32_t k0rec, double *part, DevState *st);
+                   double eps, int abs_tol, int32_t maxit, int32_t k0rec, const float *dg, float *z,
+                   double *part, DevState *st);
+// Jacobi: dg64 = diag(A), dg32 = float32(dg64); a row without a positive,
+// finite diagonal entry sets kErrDiag.
+void launch_diag(hipStream_t s, const int32_t *rp, const int32_t *col, const double *val, int32_t n,
+                 double *dg64, float *dg32, DevState *st);
 void launch_set_phase(hipStream_t s, DevState *st, double thr, int32_t maxit, int32_t k0rec);
 // Start the run-ahead: thresholds eps_t * scale, first test at iteration k0.
 void launch_set_spec(hipStream_t s, DevState *st, double scale, int32_t k0, int32_t maxit);
@@ -161,19 +172,25 @@ void launch_timing_state(hipStream_t s, DevState *st, double *part, int cnt);
 // x += alpha_{it-1} d_{it-1} (deferred from the update, which then needs
 // neither x nor d), and copies the updated x~ into `snap` at a run-ahead
 // crossing (FP32 only).
+// `r` is the vector the direction is built from: the residual, or z = M^-1 r
+// with Jacobi (pc = 1, the update partials then hold rho and r.r).
 template <typename T>
 void launch_cg_spmv(hipStream_t s, const SpmvShape &sh, const int32_t *rp, const int32_t *col,
                     const T *val, const T *r, T *dA, T *dB, T *q, const double *up, int nup,
-                    double *part, int it, int it0, T *x, T *snap, DevState *st);
+                    double *part, int it, int it0, T *x, T *snap, int pc, DevState *st);
+// Jacobi (dg != nullptr): also z = r / dg and partials of r.z (slot 0) and r.r
+// (slot nup + block).
 template <typename T>
 void launch_cg_update(hipStream_t s, int32_t n, T *r, const T *q, const double *sp, int nsp, double *up,
-                      int nup, int it, DevState *st);
+                      int nup, int it, const T *dg, T *z, DevState *st);
 // r = b - A x (x from float x32 when x32 != nullptr, else from x64), x64 <- float64(x32),
 // zero the old-direction buffer of iteration it0, gamma = r.r, ||b||^2, stop test.
+// Jacobi (dg != nullptr): z = r / dg; the partials are r.r, b.b and r.z (r.r
+// again without a preconditioner), three per block.
 void launch_restart(hipStream_t s, const SpmvShape &sh, const int32_t *rp, const int32_t *col,
                     const double *val, const float *x32, double *x64, const double *b, double *r,
                     double *dA, double *dB, int it0, double eps, int abs_tol, int32_t maxit,
-                    double *part, DevState *st);
+                    const double *dg, double *z, double *part, DevState *st);
 void launch_resid(hipStream_t s, const SpmvShape &sh, const int32_t *rp, const int32_t *col,
                   const double *val, const double *x64, const double *b, double *part, DevState *st);
 void launch_fin_restart(hipStream_t s, const double *part, int cnt, int it0, double eps, int abs_tol,
@@ -186,11 +203,11 @@ void launch_spmv_plain(hipStream_t s, const SpmvShape &sh, const int32_t *rp, co
 // ----- SELL-64 (kernels_sell.hip) -----
 template <typename T>
 void launch_sell_cg_spmv(hipStream_t s, const SellMat &m, const T *r, T *dA, T *dB, T *q,
-                         const double *up, int nup, double *part, int it, int it0, T *x, T *snap,
+                         const double *up, int nup, double *part, int it, int it0, T *x, T *snap, int pc,
                          DevState *st);
 void launch_sell_restart(hipStream_t s, const SellMat &m, const float *x32, double *x64,
-                         const double *b, double *r, double *dA, double *dB, int it0, double *part,
-                         DevState *st);
+                         const double *b, double *r, double *dA, double *dB, int it0, const double *dg,
+                         double *z, double *part, DevState *st);
 void launch_sell_resid(hipStream_t s, const SellMat &m, const double *x64, const double *b,
                        double *part, DevState *st);
 template <typename T>
