@@ -45,7 +45,7 @@ struct mpcg_ctx {
     int up_grid = kUpdateGrid;   // MPCG_UP_GRID: most blocks of a CG update launch
     mpcg::batch::Engine *eng = nullptr;   // batched engine (own thread and stream), if started
     int bfs_grid = kBfsLevelBlocks;   // MPCG_BFS_GRID: blocks of the BFS level kernel
-    int bfs_precheck = 1;             // MPCG_BFS_PRECHECK=0: claim without reading the distance first
+    int bfs_precheck = 0;             // MPCG_BFS_PRECHECK=1: read the distance before claiming a vertex
     int bfs_persist = 0;              // MPCG_BFS_PERSIST=1: large levels in one persistent launch
 };
 
@@ -84,8 +84,8 @@ Layout plan_layout(int64_t n, int64_t nnz)
     L.dA64 = take(sizeof(double) * N);
     L.dB64 = take(sizeof(double) * N);
     L.dist = take(sizeof(int32_t) * N);
-    L.q0 = take(sizeof(int32_t) * N);
-    L.q1 = take(sizeof(int32_t) * N);
+    L.q0 = take(sizeof(QEnt) * N);
+    L.q1 = take(sizeof(QEnt) * N);
     L.label = take(sizeof(int32_t) * N);
     L.tarr = take(sizeof(int32_t) * N);
     L.best = take(sizeof(unsigned long long) * N);
@@ -366,8 +366,8 @@ BfsBufs bfs_bufs(const mpcg_ctx *c, const Plan &p)
     if (b.small_max < 64) b.small_max = 64;
     if (b.small_max > kBfsSmallCap) b.small_max = kBfsSmallCap;
     b.dist = p.at<int32_t>(p.L.dist);
-    b.q0 = p.at<int32_t>(p.L.q0);
-    b.q1 = p.at<int32_t>(p.L.q1);
+    b.q0 = p.at<QEnt>(p.L.q0);
+    b.q1 = p.at<QEnt>(p.L.q1);
     b.label = p.at<int32_t>(p.L.label);
     b.tarr = p.at<int32_t>(p.L.tarr);
     b.best = p.at<unsigned long long>(p.L.best);
@@ -540,7 +540,7 @@ mpcg_status mpcg_create(mpcg_ctx **out, const mpcg_options *opt, void *hip_strea
         c->cg_grid = cgg >= 64 && cgg <= kMaxGrid ? cgg : kMaxGrid;
         const int bg = env_int("MPCG_BFS_GRID", kBfsLevelBlocks);
         c->bfs_grid = bg > 0 && bg <= 4096 ? bg : kBfsLevelBlocks;
-        c->bfs_precheck = env_int("MPCG_BFS_PRECHECK", 1) ? 1 : 0;
+        c->bfs_precheck = env_int("MPCG_BFS_PRECHECK", 0) ? 1 : 0;
         c->bfs_persist = env_int("MPCG_BFS_PERSIST", 0) ? 1 : 0;
         const int upg = env_int("MPCG_UP_GRID", kUpdateGrid);
         c->up_grid = upg >= 64 && upg <= kMaxGrid ? upg : kUpdateGrid;

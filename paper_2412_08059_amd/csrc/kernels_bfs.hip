@@ -42,11 +42,11 @@ __device__ inline void bfs_start(DevState *st, int cnt0, int min0)
     st->bfs_visited = 0;
 }
 
-__global__ void k_bfs_seed_single(int32_t *dist, int32_t *q0, int32_t src, DevState *st)
+__global__ void k_bfs_seed_single(const int32_t *rp, int32_t *dist, QEnt *q0, int32_t src, DevState *st)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         dist[src] = 0;
-        q0[0] = src;
+        q0[0] = QEnt{rp[src], rp[src + 1]};
         bfs_start(st, 1, src);
     }
 }
@@ -54,7 +54,7 @@ __global__ void k_bfs_seed_single(int32_t *dist, int32_t *q0, int32_t src, DevSt
 void launch_bfs_seed_single(hipStream_t s, const BfsBufs &b, int32_t src)
 {
     launch_fill_i32(s, b.dist, b.n, -1);
-    hipLaunchKernelGGL(k_bfs_seed_single, dim3(1), dim3(64), 0, s, b.dist, b.q0, src, b.st);
+    hipLaunchKernelGGL(k_bfs_seed_single, dim3(1), dim3(64), 0, s, b.rp, b.dist, b.q0, src, b.st);
 }
 
 // Level L was expanded by the previous launch and found nothing: the BFS is
@@ -75,10 +75,10 @@ __device__ inline void bfs_finish(DevState *st, int L)
 // that does not run hands its level on unchanged.
 __global__ void __launch_bounds__(kBfsSmallThreads)
 k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int32_t *dist,
-            int32_t *q0, int32_t *q1, int32_t n, int32_t lanes, int32_t small_max, int32_t k,
+            QEnt *q0, QEnt *q1, int32_t n, int32_t lanes, int32_t small_max, int32_t k,
             DevState *st)
 {
-    __shared__ int32_t sq[2][kBfsSmallCap];
+    __shared__ QEnt sq[2][kBfsSmallCap];
     __shared__ int32_t s_cnt, s_min, s_cur, s_level, s_go, s_curmin;
     __shared__ long long s_vis;
     const int tid = threadIdx.x;
@@ -104,7 +104,7 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
     __syncthreads();
     if (!s_go) return;
     {
-        const int32_t *qc = (s_level & 1) ? q1 : q0;
+        const QEnt *qc = (s_level & 1) ? q1 : q0;
         for (int i = tid; i < s_cur; i += kBfsSmallThreads) sq[0][i] = qc[i];
     }
     int c = 0;
@@ -114,20 +114,19 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
         if (tid == 0) { s_cnt = 0; s_min = kIntMax; }
         __syncthreads();
         const int cur = s_cur, level = s_level;
-        int32_t *qn = (level & 1) ? q0 : q1;
+        QEnt *qn = (level & 1) ? q0 : q1;
         const int work = cur * lanes;
         for (int w = tid; w < work; w += kBfsSmallThreads) {
             const int f = w / lanes, l = w - f * lanes;
-            const int u = sq[c][f];
-            if ((unsigned)u >= (unsigned)n) continue;
-            const int e = rp[u + 1];
-            for (int j = rp[u] + l; j < e; j += lanes) {
+            const QEnt u = sq[c][f];
+            for (int j = u.b + l; j < u.e; j += lanes) {
                 const int v = col[j];
-                if (v == u || dist[v] >= 0) continue;
+                if ((unsigned)v >= (unsigned)n || dist[v] >= 0) continue;   // a self-loop is visited already
+                const QEnt nv{rp[v], rp[v + 1]};
                 if (atomicCAS(&dist[v], -1, level + 1) == -1) {
                     const int pos = atomicAdd(&s_cnt, 1);
-                    if (pos < kBfsSmallCap) sq[c ^ 1][pos] = v;
-                    qn[pos] = v;
+                    if (pos < kBfsSmallCap) sq[c ^ 1][pos] = nv;
+                    qn[pos] = nv;
                     atomicMin(&s_min, v);
                 }
             }
@@ -184,18 +183,37 @@ __device__ inline int wave_min_i(int v)
 // One level, top-down.  `lanes` consecutive lanes share a frontier vertex
 // and take its neighbours in parallel (lane l: entries l, l + lanes, ...).
 // Each thread takes kBfsItems work items at once and issues their loads
-// together, so a level costs a handful of dependent memory round trips (level
-// and count; frontier vertices; row bounds; columns; claims) whatever its
-// size; the vertices a wave claims in one step are appended with a single
-// atomic.  Block 0 retires the level and clears the counters of the level
-// after next; the next frontier's minimum is folded in with non-returning
-// atomics.
+// together.  The queue holds row ranges, and the first batch's queue entries
+// are read from both queues before the level is known, so a level costs four
+// dependent memory round trips: (state, queue entry), column, claim
+// (compare-and-swap on the distance, with the claimed vertex's row range
+// loaded beside it), append.  Appends and the next frontier's minimum are
+// aggregated per block -- one atomic on the shared counter per block and
+// step, not per wave: all blocks append to the same counter, and same-address
+// atomics serialise.  Block 0 retires the level and clears the counters of
+// the level after next.
 constexpr int kBfsItems = 4;
 
 __global__ void __launch_bounds__(kBlock)
 k_bfs_level(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int32_t *dist,
-            int32_t *q0, int32_t *q1, int32_t n, int32_t lanes, int32_t k, int32_t precheck, DevState *st)
+            QEnt *q0, QEnt *q1, int32_t n, int32_t lanes, int32_t k, int32_t precheck, DevState *st)
 {
+    __shared__ int s_cnt[kBlock / 64], s_base, s_steps, s_min;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t span = stride * kBfsItems;
+    const int64_t wbase0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63);
+    QEnt pa[kBfsItems], pb[kBfsItems];   // first batch from queue 0 and queue 1
+#pragma unroll
+    for (int i = 0; i < kBfsItems; ++i) {
+        const int64_t f = (wbase0 + i * stride + lane) / lanes;
+        pa[i] = QEnt{0, 0};
+        pb[i] = QEnt{0, 0};
+        if (f < n) {
+            pa[i] = q0[f];
+            pb[i] = q1[f];
+        }
+    }
     if (st->bfs_done) return;
     const int L = st->bfs_lv[k & 1];
     const int cur = min(st->bfs_cnt[L & 3], n);
@@ -210,32 +228,26 @@ k_bfs_level(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
         }
     }
     if (cur == 0) return;
-    const int32_t *qc = (L & 1) ? q1 : q0;
-    int32_t *qn = (L & 1) ? q0 : q1;
+    const QEnt *qc = (L & 1) ? q1 : q0;
+    QEnt *qn = (L & 1) ? q0 : q1;
     int *cnt_next = &st->bfs_cnt[(L + 1) & 3];
-    const int lane = threadIdx.x & 63;
     const unsigned long long lt = (1ull << lane) - 1ull;
     int wmin = kIntMax;
     const int64_t items = (int64_t)cur * lanes;
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    const int64_t span = stride * kBfsItems;
-    for (int64_t wbase = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); wbase < items; wbase += span) {
-        int u[kBfsItems], j[kBfsItems], e[kBfsItems];
+    if (threadIdx.x == 0) s_min = kIntMax;
+    // the batch loop is uniform over the block (its waves meet at barriers)
+    const int64_t bbase0 = (int64_t)blockIdx.x * kBlock;
+    bool first = true;
+    for (int64_t bbase = bbase0; bbase < items; bbase += span, first = false) {
+        const int64_t wbase = bbase + (threadIdx.x & ~63);
+        int j[kBfsItems], e[kBfsItems];
 #pragma unroll
         for (int i = 0; i < kBfsItems; ++i) {
             const int64_t w = wbase + i * stride + lane;
-            u[i] = -1;
-            j[i] = 0;
-            e[i] = 0;
-            if (w < items) u[i] = qc[(int)(w / lanes)];
-        }
-#pragma unroll
-        for (int i = 0; i < kBfsItems; ++i) {
-            if ((unsigned)u[i] < (unsigned)n) {
-                const int64_t w = wbase + i * stride + lane;
-                j[i] = rp[u[i]] + (int)(w % lanes);
-                e[i] = rp[u[i] + 1];
-            }
+            QEnt u{0, 0};
+            if (w < items) u = first ? ((L & 1) ? pb[i] : pa[i]) : qc[(int)(w / lanes)];
+            j[i] = u.b + (int)(w % lanes);
+            e[i] = w < items ? u.e : 0;
         }
         int steps = 0;
 #pragma unroll
@@ -244,22 +256,35 @@ k_bfs_level(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
             steps = steps > si ? steps : si;
         }
         steps = wave_max_i(steps);
+        if (threadIdx.x == 0) s_steps = 0;
+        __syncthreads();
+        if (lane == 0) atomicMax(&s_steps, steps);
+        __syncthreads();
+        steps = s_steps;
+        __syncthreads();   // everyone has read s_steps before the next batch resets it
         for (int t = 0; t < steps; ++t) {
             int v[kBfsItems];
             bool found[kBfsItems];
+            QEnt nv[kBfsItems];
 #pragma unroll
             for (int i = 0; i < kBfsItems; ++i) {
                 v[i] = j[i] < e[i] ? col[j[i]] : -1;
+                if ((unsigned)v[i] >= (unsigned)n) v[i] = -1;
                 j[i] += lanes;
             }
             if (precheck) {
 #pragma unroll
                 for (int i = 0; i < kBfsItems; ++i)
-                    if (v[i] >= 0 && (v[i] == u[i] || dist[v[i]] >= 0)) v[i] = -1;
+                    if (v[i] >= 0 && dist[v[i]] >= 0) v[i] = -1;
             }
 #pragma unroll
-            for (int i = 0; i < kBfsItems; ++i)
-                found[i] = v[i] >= 0 && v[i] != u[i] && atomicCAS(&dist[v[i]], -1, L + 1) == -1;
+            for (int i = 0; i < kBfsItems; ++i) {
+                nv[i] = QEnt{0, 0};
+                if (v[i] >= 0) nv[i] = QEnt{rp[v[i]], rp[v[i] + 1]};
+            }
+#pragma unroll
+            for (int i = 0; i < kBfsItems; ++i)   // self-loops fail here: the vertex being expanded is visited
+                found[i] = v[i] >= 0 && atomicCAS(&dist[v[i]], -1, L + 1) == -1;
             unsigned long long m[kBfsItems];
             int total = 0;
 #pragma unroll
@@ -267,22 +292,35 @@ k_bfs_level(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
                 m[i] = __ballot(found[i]);
                 total += __popcll(m[i]);
             }
-            if (total == 0) continue;
-            int base = 0;
-            if (lane == 0) base = atomicAdd(cnt_next, total);
-            base = __shfl(base, 0, 64);
+            // block aggregation: one atomic on the shared counter per block and step
+            if (lane == 0) s_cnt[wv] = total;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int sum = 0;
+                for (int w = 0; w < kBlock / 64; ++w) {
+                    const int c = s_cnt[w];
+                    s_cnt[w] = sum;
+                    sum += c;
+                }
+                s_base = sum > 0 ? atomicAdd(cnt_next, sum) : 0;
+            }
+            __syncthreads();
+            int base = s_base + s_cnt[wv];
 #pragma unroll
             for (int i = 0; i < kBfsItems; ++i) {
                 if (found[i]) {
-                    qn[base + __popcll(m[i] & lt)] = v[i];
+                    qn[base + __popcll(m[i] & lt)] = nv[i];
                     wmin = wmin < v[i] ? wmin : v[i];
                 }
                 base += __popcll(m[i]);
             }
+            __syncthreads();   // s_cnt and s_base are reused by the next step
         }
     }
     wmin = wave_min_i(wmin);
-    if (lane == 0 && wmin != kIntMax) atomicMin(&st->bfs_min[(L + 1) & 3], wmin);
+    if (lane == 0 && wmin != kIntMax) atomicMin(&s_min, wmin);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_min != kIntMax) atomicMin(&st->bfs_min[(L + 1) & 3], s_min);
 }
 
 // ------------------------------------------------ persistent large levels --
@@ -307,14 +345,25 @@ __device__ inline void astore(int32_t *p, int v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ inline QEnt aload_q(const QEnt *p)
+{
+    const uint64_t v = __hip_atomic_load(reinterpret_cast<uint64_t *>(const_cast<QEnt *>(p)), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    return QEnt{(int32_t)(uint32_t)(v & 0xffffffffull), (int32_t)(uint32_t)(v >> 32)};
+}
+__device__ inline void astore_q(QEnt *p, QEnt q)
+{
+    const uint64_t v = (uint64_t)(uint32_t)q.b | ((uint64_t)(uint32_t)q.e << 32);
+    __hip_atomic_store(reinterpret_cast<uint64_t *>(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 constexpr uint32_t kBarSpinLimit = 1u << 22;
 
 __global__ void __launch_bounds__(kBlock)
-k_bfs_persist(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int32_t *dist, int32_t *q0,
-              int32_t *q1, int32_t n, int32_t lanes, int32_t small_max, int32_t k, DevState *st)
+k_bfs_persist(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int32_t *dist, QEnt *q0,
+              QEnt *q1, int32_t n, int32_t lanes, int32_t small_max, int32_t k, DevState *st)
 {
-    __shared__ int s_ok;
+    __shared__ int s_ok, s_cnt[kBlock / 64], s_base, s_steps, s_min;
     if (aload(&st->bfs_done)) return;
     int L = aload(&st->bfs_lv[k & 1]);
     int cur = aload(&st->bfs_cnt[L & 3]);
@@ -323,7 +372,7 @@ k_bfs_persist(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, i
         if (b0) astore(&st->bfs_lv[(k + 1) & 1], L);
         return;
     }
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     const int64_t span = stride * kBfsItems;
@@ -334,27 +383,21 @@ k_bfs_persist(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, i
             astore(&st->bfs_cnt[(L + 2) & 3], 0);
             astore(&st->bfs_min[(L + 2) & 3], kIntMax);
         }
-        const int32_t *qc = (L & 1) ? q1 : q0;
-        int32_t *qn = (L & 1) ? q0 : q1;
+        const QEnt *qc = (L & 1) ? q1 : q0;
+        QEnt *qn = (L & 1) ? q0 : q1;
         int *cnt_next = &st->bfs_cnt[(L + 1) & 3];
         int wmin = kIntMax;
         const int64_t items = (int64_t)min(cur, n) * lanes;
-        for (int64_t wbase = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); wbase < items; wbase += span) {
-            int u[kBfsItems], j[kBfsItems], e[kBfsItems];
+        if (threadIdx.x == 0) s_min = kIntMax;
+        for (int64_t bbase = (int64_t)blockIdx.x * kBlock; bbase < items; bbase += span) {   // block-uniform
+            const int64_t wbase = bbase + (threadIdx.x & ~63);
+            int j[kBfsItems], e[kBfsItems];
 #pragma unroll
             for (int i = 0; i < kBfsItems; ++i) {
                 const int64_t w = wbase + i * stride + lane;
-                u[i] = w < items ? aload(&qc[(int)(w / lanes)]) : -1;
-                j[i] = 0;
-                e[i] = 0;
-            }
-#pragma unroll
-            for (int i = 0; i < kBfsItems; ++i) {
-                if ((unsigned)u[i] < (unsigned)n) {
-                    const int64_t w = wbase + i * stride + lane;
-                    j[i] = rp[u[i]] + (int)(w % lanes);
-                    e[i] = rp[u[i] + 1];
-                }
+                const QEnt u = w < items ? aload_q(&qc[(int)(w / lanes)]) : QEnt{0, 0};
+                j[i] = u.b + (int)(w % lanes);
+                e[i] = w < items ? u.e : 0;
             }
             int steps = 0;
 #pragma unroll
@@ -363,18 +406,30 @@ k_bfs_persist(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, i
                 steps = steps > si ? steps : si;
             }
             steps = wave_max_i(steps);
+            if (threadIdx.x == 0) s_steps = 0;
+            __syncthreads();
+            if (lane == 0) atomicMax(&s_steps, steps);
+            __syncthreads();
+            steps = s_steps;
+            __syncthreads();
             for (int t = 0; t < steps; ++t) {
                 int v[kBfsItems];
                 bool found[kBfsItems];
+                QEnt nv[kBfsItems];
 #pragma unroll
                 for (int i = 0; i < kBfsItems; ++i) {
                     v[i] = j[i] < e[i] ? col[j[i]] : -1;
+                    if ((unsigned)v[i] >= (unsigned)n) v[i] = -1;
                     j[i] += lanes;
                 }
 #pragma unroll
+                for (int i = 0; i < kBfsItems; ++i) {
+                    nv[i] = QEnt{0, 0};
+                    if (v[i] >= 0) nv[i] = QEnt{rp[v[i]], rp[v[i] + 1]};
+                }
+#pragma unroll
                 for (int i = 0; i < kBfsItems; ++i)
-                    found[i] = v[i] >= 0 && v[i] != u[i] && dist[v[i]] < 0 &&
-                               atomicCAS(&dist[v[i]], -1, L + 1) == -1;
+                    found[i] = v[i] >= 0 && atomicCAS(&dist[v[i]], -1, L + 1) == -1;
                 unsigned long long m[kBfsItems];
                 int total = 0;
 #pragma unroll
@@ -382,22 +437,34 @@ k_bfs_persist(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, i
                     m[i] = __ballot(found[i]);
                     total += __popcll(m[i]);
                 }
-                if (total == 0) continue;
-                int base = 0;
-                if (lane == 0) base = atomicAdd(cnt_next, total);
-                base = __shfl(base, 0, 64);
+                if (lane == 0) s_cnt[wv] = total;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    int sum = 0;
+                    for (int w = 0; w < kBlock / 64; ++w) {
+                        const int c = s_cnt[w];
+                        s_cnt[w] = sum;
+                        sum += c;
+                    }
+                    s_base = sum > 0 ? atomicAdd(cnt_next, sum) : 0;
+                }
+                __syncthreads();
+                int base = s_base + s_cnt[wv];
 #pragma unroll
                 for (int i = 0; i < kBfsItems; ++i) {
                     if (found[i]) {
-                        astore(&qn[base + __popcll(m[i] & lt)], v[i]);
+                        astore_q(&qn[base + __popcll(m[i] & lt)], nv[i]);
                         wmin = wmin < v[i] ? wmin : v[i];
                     }
                     base += __popcll(m[i]);
                 }
+                __syncthreads();
             }
         }
         wmin = wave_min_i(wmin);
-        if (lane == 0 && wmin != kIntMax) atomicMin(&st->bfs_min[(L + 1) & 3], wmin);
+        if (lane == 0 && wmin != kIntMax) atomicMin(&s_min, wmin);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_min != kIntMax) atomicMin(&st->bfs_min[(L + 1) & 3], s_min);
         // this wave's queue stores, claims and counters are complete before its block arrives
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
@@ -527,7 +594,7 @@ void launch_cc(hipStream_t s, const BfsBufs &b)
 }
 
 // Multi-source start: every component root (label[v] == v) at distance 0.
-__global__ void k_bfs_seed_roots(const int32_t *label, int32_t *dist, int32_t *q0,
+__global__ void k_bfs_seed_roots(const int32_t *rp, const int32_t *label, int32_t *dist, QEnt *q0,
                                  unsigned long long *best, int32_t n, DevState *st)
 {
     for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
@@ -536,7 +603,7 @@ __global__ void k_bfs_seed_roots(const int32_t *label, int32_t *dist, int32_t *q
         if (root) {
             best[v] = 0ull;
             const int pos = atomicAdd(&st->bfs_cnt[0], 1);
-            q0[pos] = v;
+            q0[pos] = QEnt{rp[v], rp[v + 1]};
         }
     }
 }
@@ -565,7 +632,7 @@ void launch_bfs_seed_roots(hipStream_t s, const BfsBufs &b)
     int grid = (b.n + kBlock - 1) / kBlock;
     if (grid > 4096) grid = 4096;
     hipLaunchKernelGGL(k_zero_sources, dim3(1), dim3(64), 0, s, b.st);
-    hipLaunchKernelGGL(k_bfs_seed_roots, dim3(grid), dim3(kBlock), 0, s, b.label, b.dist, b.q0, b.best,
+    hipLaunchKernelGGL(k_bfs_seed_roots, dim3(grid), dim3(kBlock), 0, s, b.rp, b.label, b.dist, b.q0, b.best,
                        b.n, b.st);
     hipLaunchKernelGGL(k_bfs_seed_finish, dim3(1), dim3(64), 0, s, b.st, 1);
 }
@@ -609,7 +676,7 @@ void launch_comp_argmax(hipStream_t s, const BfsBufs &b, int second_sweep)
 
 // Second sweep start: t_c of every component (from best[c]) at distance 0;
 // tarr[c] keeps t_c, best[c] is reset for the second argmax.
-__global__ void k_bfs_seed_far(const int32_t *label, int32_t *dist, int32_t *q0, int32_t *tarr,
+__global__ void k_bfs_seed_far(const int32_t *rp, const int32_t *label, int32_t *dist, QEnt *q0, int32_t *tarr,
                                unsigned long long *best, int32_t n, DevState *st)
 {
     for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
@@ -619,7 +686,7 @@ __global__ void k_bfs_seed_far(const int32_t *label, int32_t *dist, int32_t *q0,
             best[v] = 0ull;
             dist[t] = 0;
             const int pos = atomicAdd(&st->bfs_cnt[0], 1);
-            q0[pos] = t;
+            q0[pos] = QEnt{rp[t], rp[t + 1]};
         }
     }
 }
@@ -630,7 +697,7 @@ void launch_bfs_seed_far(hipStream_t s, const BfsBufs &b)
     if (grid > 4096) grid = 4096;
     launch_fill_i32(s, b.dist, b.n, -1);
     hipLaunchKernelGGL(k_zero_sources, dim3(1), dim3(64), 0, s, b.st);
-    hipLaunchKernelGGL(k_bfs_seed_far, dim3(grid), dim3(kBlock), 0, s, b.label, b.dist, b.q0, b.tarr,
+    hipLaunchKernelGGL(k_bfs_seed_far, dim3(grid), dim3(kBlock), 0, s, b.rp, b.label, b.dist, b.q0, b.tarr,
                        b.best, b.n, b.st);
     hipLaunchKernelGGL(k_bfs_seed_finish, dim3(1), dim3(64), 0, s, b.st, 0);
 }

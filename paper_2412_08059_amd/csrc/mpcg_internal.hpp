@@ -17,10 +17,10 @@ constexpr int kVecTile = kBlock * kVecPerThread;
 constexpr int kK0Max = 64;            // longest FP32 prefix recorded for v
 constexpr int kNumEps = 6;            // eps1 candidates 1e-2 ... 1e-7
 constexpr int kLdsBytes = 32768;      // LDS staging per SpMV block (val + gathered x)
-constexpr int kBfsSmallCap = 4096;    // frontier size handled by the one-workgroup BFS kernel
+constexpr int kBfsSmallCap = 3072;    // frontier size handled by the one-workgroup BFS kernel
 constexpr int kBfsSmallThreads = 1024;
 constexpr int kBfsSmallWork = 2048;   // (vertex, lane) items per level in the one-workgroup kernel
-constexpr int kBfsLevelBlocks = 64;   // level-kernel blocks: few, so a level costs few dispatches
+constexpr int kBfsLevelBlocks = 128;  // level-kernel blocks (measured best on the 128^3 grid)
 constexpr int kNumXcd = 8;            // MI355X: blocks are dispatched round-robin over 8 XCDs
 constexpr int kMaxGrid = 2048;        // largest grid of a kernel that writes reduction partials
 constexpr int kUpdateGrid = 1024;     // blocks of a CG update launch: fewer partials for the next product
@@ -214,12 +214,19 @@ template <typename T>
 void launch_sell_plain(hipStream_t s, const SellMat &m, const T *x, T *y);
 
 // ----- BFS (kernels_bfs.hip) -----
+// A queued BFS vertex is stored as its CSR row range: the level that expands
+// it needs no further load to find its neighbours.
+struct QEnt {
+    int32_t b, e;
+};
+
 struct BfsBufs {
     const int32_t *rp, *col;
     int32_t n;
     int32_t lanes;          // lanes per frontier vertex in the one-workgroup kernel
     int32_t small_max;      // largest frontier left to the one-workgroup kernel
-    int32_t *dist, *q0, *q1, *label, *tarr;
+    int32_t *dist, *label, *tarr;
+    QEnt *q0, *q1;      // frontier queues: the row range of each queued vertex
     unsigned long long *best;
     DevState *st;
     int32_t grid;       // blocks of the level kernel
