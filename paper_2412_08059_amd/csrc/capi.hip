@@ -47,6 +47,13 @@ struct mpcg_ctx {
     int bfs_grid = kBfsLevelBlocks;   // MPCG_BFS_GRID: blocks of the BFS level kernel
     int bfs_precheck = 0;             // MPCG_BFS_PRECHECK=1: read the distance before claiming a vertex
     int bfs_persist = 0;              // MPCG_BFS_PERSIST=1: large levels in one persistent launch
+    // Algorithm II runs the 2BFS beside the FP32 iterations.  A SELL product
+    // grid of 8 blocks per CU fills every wave slot, so each resident BFS
+    // block would push one product block to the end of the launch (the slice
+    // partition is static): while the BFS runs, the FP32 product takes one
+    // block per CU fewer and the BFS a small grid that fits the freed slots.
+    int cg_grid_shared = 0;           // MPCG_CG_GRID_SHARED: 0 = 7 blocks per CU
+    int bfs_grid_shared = 64;         // MPCG_BFS_GRID_SHARED
 };
 
 #define HIPCHK(x)                                        \
@@ -349,11 +356,11 @@ int env_int(const char *name, int def)
     return (e && e[0]) ? std::atoi(e) : def;
 }
 
-BfsBufs bfs_bufs(const mpcg_ctx *c, const Plan &p)
+BfsBufs bfs_bufs(const mpcg_ctx *c, const Plan &p, bool shared = false)
 {
     BfsBufs b{};
     b.persist = c->bfs_persist;
-    b.grid = c->bfs_grid;
+    b.grid = shared ? c->bfs_grid_shared : c->bfs_grid;
     b.precheck = c->bfs_precheck;
     b.rp = p.rp;
     b.col = p.col;
@@ -448,9 +455,10 @@ mpcg_status pseudo_diameter_with(const Chan &ch, const Plan &p, const BfsBufs &b
 // The persistent level kernel bounds its barrier waits; if one ran out (its
 // blocks could not all be resident), the BFS is repeated with one launch per
 // level, which needs no co-residency.
-mpcg_status pseudo_diameter(const mpcg_ctx *c, const Chan &ch, const Plan &p, mpcg_features_t *f)
+mpcg_status pseudo_diameter(const mpcg_ctx *c, const Chan &ch, const Plan &p, mpcg_features_t *f,
+                            bool shared = false)
 {
-    BfsBufs bb = bfs_bufs(c, p);
+    BfsBufs bb = bfs_bufs(c, p, shared);
     mpcg_status rc = pseudo_diameter_with(ch, p, bb, f);
     if (rc == MPCG_EDEVICE && bb.persist) {
         HIPCHK(hipStreamSynchronize(ch.s));
@@ -459,6 +467,21 @@ mpcg_status pseudo_diameter(const mpcg_ctx *c, const Chan &ch, const Plan &p, mp
         rc = pseudo_diameter_with(ch, p, bb, f);
     }
     return rc;
+}
+
+// The plan of the FP32 launches that run beside the 2BFS: when the SELL
+// product grid fills every CU (8 blocks of 256 threads each), one block per CU
+// fewer.  Both kernels of an iteration take their partial counts from the
+// same plan, and the first product after the switch reduces the update's
+// partials, whose grid does not change.
+Plan shared_plan(const mpcg_ctx *c, const Plan &p)
+{
+    Plan q = p;
+    if (p.use_sell && p.sell.grid >= 8 * c->num_cu) {
+        const int g = c->cg_grid_shared > 0 ? c->cg_grid_shared : 7 * c->num_cu;
+        if (g < q.sell.grid) q.sell.grid = g;
+    }
+    return q;
 }
 
 // FP32 prefix of Algorithm II: k0 iterations without the eps1 test.
@@ -542,6 +565,10 @@ mpcg_status mpcg_create(mpcg_ctx **out, const mpcg_options *opt, void *hip_strea
         c->bfs_grid = bg > 0 && bg <= 4096 ? bg : kBfsLevelBlocks;
         c->bfs_precheck = env_int("MPCG_BFS_PRECHECK", 0) ? 1 : 0;
         c->bfs_persist = env_int("MPCG_BFS_PERSIST", 0) ? 1 : 0;
+        const int cgs = env_int("MPCG_CG_GRID_SHARED", 0);
+        c->cg_grid_shared = cgs >= 64 && cgs <= kMaxGrid ? cgs : 0;
+        const int bgs = env_int("MPCG_BFS_GRID_SHARED", 64);
+        c->bfs_grid_shared = bgs > 0 && bgs <= 4096 ? bgs : 64;
         const int upg = env_int("MPCG_UP_GRID", kUpdateGrid);
         c->up_grid = upg >= 64 && upg <= kMaxGrid ? upg : kUpdateGrid;
     }
@@ -700,19 +727,20 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
             std::thread bfs_thread([&]() {
                 (void)hipSetDevice(c->device);
                 (void)hipEventRecord(c->tm[1], c->side.s);
-                rc_bfs = pseudo_diameter(c, c->side, p, &f);
+                rc_bfs = pseudo_diameter(c, c->side, p, &f, true);
                 (void)hipEventRecord(c->tm[2], c->side.s);
                 (void)hipEventSynchronize(c->tm[2]);
                 bfs_done.store(1);
             });
+            const Plan ps = shared_plan(c, p);   // FP32 launches beside the BFS
             DevState sp0;
-            rc = fp32_prefix(c, p, b, c->opt.k0, &sp0);
+            rc = fp32_prefix(c, ps, b, c->opt.k0, &sp0);
             s = sp0;
             int it_next = sp0.iter;
             broke = (sp0.reason == kNotSpd || sp0.reason == kNonFinite);
             if (rc == MPCG_OK && sp0.bnorm2 > 0.0 && !broke) {
                 launch_set_spec(c->stream, p.st, abs_tol ? 1.0 : std::sqrt(sp0.bnorm2), sp0.iter, maxit1);
-                rc = cg_loop<float>(c, p, x32, r32, q32, dA32, dB32, sp0.iter, 0, &s, &bfs_done, &it_next);
+                rc = cg_loop<float>(c, ps, x32, r32, q32, dA32, dB32, sp0.iter, 0, &s, &bfs_done, &it_next);
             }
             bfs_thread.join();
             if (rc == MPCG_OK) rc = rc_bfs;
