@@ -150,6 +150,7 @@ struct Plan {
     double *sp = nullptr;   // partials written by the product kernels (up to 3 per block)
     double *up = nullptr;   // partials written by the update kernel (2 per block with Jacobi)
     int pc = 0;             // Jacobi-preconditioned stages
+    int32_t band = 0;       // largest |i - j| over the stored entries
     float *z32 = nullptr, *dg32 = nullptr;
     double *z64 = nullptr, *dg64 = nullptr;
     SpmvShape sh32{}, sh64{};
@@ -211,6 +212,7 @@ mpcg_status ingest(mpcg_ctx *c, const mpcg_csr *A, const double *b, bool need_va
     HIPCHK(hipStreamSynchronize(c->stream));
     const DevState s = c->hst[1];
     const int64_t padded = c->hst[2].spare_i64;
+    p->band = s.max_band;
     if (s.ing_err & (kErrRowPtr | kErrCol | kErrUnsorted)) return MPCG_EINVAL;
     if (s.ing_err & (kErrNonFiniteA | kErrNonFiniteB)) return MPCG_ENONFINITE;
     if (s.ing_err & kErrDiag) return MPCG_ENOTSPD;   // Jacobi needs a positive diagonal (any SPD A has one)
@@ -369,6 +371,7 @@ BfsBufs bfs_bufs(const mpcg_ctx *c, const Plan &p, bool shared = false)
     int lanes = 1;
     while (lanes < avg && lanes < 32) lanes <<= 1;
     b.lanes = lanes;
+    b.band = p.band;
     b.small_max = kBfsSmallWork / lanes;
     if (b.small_max < 64) b.small_max = 64;
     if (b.small_max > kBfsSmallCap) b.small_max = kBfsSmallCap;

@@ -70,20 +70,93 @@ __device__ inline void bfs_finish(DevState *st, int L)
 
 // Runs levels while 0 < frontier <= small_max (<= kBfsSmallCap, chosen so
 // that one pass of the 1024 threads covers the level).  The frontier lives in
-// LDS; every level is also written to its global queue so that the
-// multi-block kernel can take over when the frontier outgrows LDS.  A launch
-// that does not run hands its level on unchanged.
+// LDS (entries beyond its size go to the global queue); when it outgrows
+// small_max the LDS part is written to the global queue and the multi-block
+// kernel takes over.  A launch that does not run hands its level on unchanged.
+//
+// Window cache.  On a long thin graph in its natural ordering (a band, a
+// path) the frontier and its neighbours stay inside a narrow range of
+// indices, and a level is a handful of vertices: its cost is the chain of
+// dependent global loads (columns, distance claim, row pointers).  The kernel
+// therefore keeps a window of consecutive rows in LDS -- their row pointers,
+// column indices and distances -- and claims and expands vertices inside it
+// without touching global memory.  The window is only a cache: a vertex
+// outside it takes the global path, and its distances are written back
+// (agent-scope atomic stores, read back with agent-scope atomic loads) before
+// it moves and before the launch ends.  It moves when the next frontier,
+// widened by the largest |i - j| of the matrix, is no longer inside it and
+// that widened range is at most a quarter of the window; it is placed ahead
+// of the frontier in the direction the frontier moves.
+constexpr int kWinRows = 1024;
+constexpr int kWinEntries = 5632;
+
+__device__ inline void astore_i32(int32_t *p, int v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline int wave_max_i(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        const int o = __shfl_xor(v, off, 64);
+        v = v > o ? v : o;
+    }
+    return v;
+}
+__device__ inline int wave_min_i(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        const int o = __shfl_xor(v, off, 64);
+        v = v < o ? v : o;
+    }
+    return v;
+}
+
+// Where the window goes for a frontier with vertices in [fmin, fmax]
+// (pmax: the previous frontier's largest vertex, -1 if unknown).  mode 0:
+// stays; 1: rows [base, base + rows) are read and the window is their longest
+// prefix whose entries fit; 2: the same with the longest suffix (the frontier
+// moves down).
+struct WinPlan {
+    int mode, base, rows;
+};
+__device__ inline WinPlan plan_window(int fmin, int fmax, int pmax, int band, int n, int w0, int nw)
+{
+    WinPlan p{0, 0, 0};
+    const long long lo = (long long)fmin - band, hi = (long long)fmax + band;
+    if (nw > 0 && lo >= w0 && hi < (long long)w0 + nw) return p;   // covered
+    if ((hi - lo + 1) * 4 > kWinRows) return p;                      // too wide to be worth it
+    const long long l0 = lo < 0 ? 0 : lo, h1 = hi >= n ? (long long)n : hi + 1;
+    if (pmax >= 0 && fmax < pmax) {
+        const long long b0 = h1 - kWinRows < 0 ? 0 : h1 - kWinRows;
+        p = WinPlan{2, (int)b0, (int)(h1 - b0)};
+    } else {
+        const long long b0 = l0 > (long long)n - 1 ? (long long)n - 1 : l0;
+        const long long r = (long long)n - b0 < kWinRows ? (long long)n - b0 : kWinRows;
+        p = WinPlan{1, (int)b0, (int)r};
+    }
+    return p;
+}
+
 __global__ void __launch_bounds__(kBfsSmallThreads)
 k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int32_t *dist,
-            QEnt *q0, QEnt *q1, int32_t n, int32_t lanes, int32_t small_max, int32_t k,
+            QEnt *q0, QEnt *q1, int32_t n, int32_t lanes, int32_t small_max, int32_t band, int32_t k,
             DevState *st)
 {
     __shared__ QEnt sq[2][kBfsSmallCap];
-    __shared__ int32_t s_cnt, s_min, s_cur, s_level, s_go, s_curmin;
+    __shared__ int32_t w_rp[kWinRows + 1], w_dist[kWinRows], w_col[kWinEntries];
+    __shared__ int32_t s_cnt, s_min, s_max, s_cur, s_level, s_go, s_curmin, s_fin;
+    __shared__ int32_t s_w0, s_nw, s_new0, s_rows, s_slide, s_pmin, s_pmax, s_fit, s_a;
     __shared__ long long s_vis;
     const int tid = threadIdx.x;
     if (tid == 0) {
         s_go = 0;
+        s_nw = 0;   // empty window: everything takes the global path
+        s_w0 = 0;
+        s_pmin = -1;
+        s_pmax = -1;
+        s_fin = 0;
+        s_slide = 0;
         st->bfs_bar = 0u;   // the persistent kernel of this round starts its barrier count at 0
         if (!st->bfs_done) {
             const int L = st->bfs_lv[k & 1];
@@ -111,39 +184,128 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
     bool finished = false;
     // every iteration expands one level; at most n levels exist
     for (;;) {
-        if (tid == 0) { s_cnt = 0; s_min = kIntMax; }
         __syncthreads();
-        const int cur = s_cur, level = s_level;
-        QEnt *qn = (level & 1) ? q0 : q1;
-        const int work = cur * lanes;
-        for (int w = tid; w < work; w += kBfsSmallThreads) {
-            const int f = w / lanes, l = w - f * lanes;
-            const QEnt u = sq[c][f];
-            for (int j = u.b + l; j < u.e; j += lanes) {
-                const int v = col[j];
-                if ((unsigned)v >= (unsigned)n || dist[v] >= 0) continue;   // a self-loop is visited already
-                const QEnt nv{rp[v], rp[v + 1]};
-                if (atomicCAS(&dist[v], -1, level + 1) == -1) {
+        {
+            // ---- one level with the whole block
+            if (tid == 0) { s_cnt = 0; s_min = kIntMax; s_max = -1; }
+            __syncthreads();
+            const int cur = s_cur, level = s_level;
+            const int w0 = s_w0, nw = s_nw;
+            const int e0 = nw > 0 ? w_rp[0] : 0, e1 = nw > 0 ? w_rp[nw] : 0;
+            QEnt *qn = (level & 1) ? q0 : q1;
+            const int work = cur * lanes;
+            // claims v for the next level; the window part touches LDS only, and
+            // the next frontier is kept in LDS (global queue only past its size)
+            auto visit = [&](int v) {
+                if ((unsigned)v >= (unsigned)n) return;
+                const int wv = v - w0;
+                bool got;
+                QEnt nv;
+                if ((unsigned)wv < (unsigned)nw) {
+                    if (w_dist[wv] >= 0) return;   // a self-loop is visited already
+                    got = atomicCAS(&w_dist[wv], -1, level + 1) == -1;
+                    nv = QEnt{w_rp[wv], w_rp[wv + 1]};
+                } else {
+                    if (dist[v] >= 0) return;
+                    nv = QEnt{rp[v], rp[v + 1]};
+                    got = atomicCAS(&dist[v], -1, level + 1) == -1;
+                }
+                if (got) {
                     const int pos = atomicAdd(&s_cnt, 1);
                     if (pos < kBfsSmallCap) sq[c ^ 1][pos] = nv;
-                    qn[pos] = nv;
+                    else qn[pos] = nv;
                     atomicMin(&s_min, v);
+                    atomicMax(&s_max, v);
+                }
+            };
+            for (int w = tid; w < work; w += kBfsSmallThreads) {
+                const int f = w / lanes, l = w - f * lanes;
+                const QEnt u = sq[c][f];
+                if (u.b >= e0 && u.e <= e1) {   // the row's columns are in the window
+                    for (int j = u.b + l; j < u.e; j += lanes) visit(w_col[j - e0]);
+                } else {
+                    for (int j = u.b + l; j < u.e; j += lanes) visit(col[j]);
                 }
             }
+            __syncthreads();
+            const int nxt = s_cnt;
+            if (tid == 0) {
+                s_vis += cur;
+                if (nxt == 0) {
+                    s_fin = 1;
+                } else {
+                    s_level = level + 1;
+                    s_cur = nxt;
+                    s_curmin = s_min;
+                    const WinPlan wp = nxt <= small_max ? plan_window(s_min, s_max, s_pmax, band, n, s_w0, s_nw)
+                                                        : WinPlan{0, 0, 0};
+                    s_slide = wp.mode;
+                    s_new0 = wp.base;
+                    s_rows = wp.rows;
+                    s_fit = 0;
+                    s_a = wp.rows;
+                    s_pmin = s_min;
+                    s_pmax = s_max;
+                }
+            }
+            __syncthreads();
+            if (s_fin) {
+                finished = true;
+                break;
+            }
+            c ^= 1;
         }
-        __syncthreads();
-        const int nxt = s_cnt;
-        if (tid == 0) s_vis += cur;
-        if (nxt == 0) { finished = true; break; }
-        if (tid == 0) {
-            s_level = level + 1;
-            s_cur = nxt;
-            s_curmin = s_min;
+        if (s_cur > small_max) {   // hand over: the multi-block kernel reads the global queue
+            QEnt *qc = (s_level & 1) ? q1 : q0;
+            for (int i = tid; i < s_cur && i < kBfsSmallCap; i += kBfsSmallThreads) qc[i] = sq[c][i];
+            break;
         }
-        c ^= 1;
-        __syncthreads();
-        if (nxt > small_max) break;
+        if (s_slide) {
+            // write the old window back, then fill the new one
+            const int w0 = s_w0, nw = s_nw;
+            for (int i = tid; i < nw; i += kBfsSmallThreads)
+                if (w_dist[i] >= 0) astore_i32(&dist[w0 + i], w_dist[i]);
+            const int mode = s_slide, nb0 = s_new0, rows = s_rows;
+            __syncthreads();
+            for (int i = tid; i <= rows; i += kBfsSmallThreads) w_rp[i] = rp[nb0 + i];
+            __syncthreads();
+            // w_rp is non-decreasing: the fitting rows are a prefix (mode 1)
+            // or a suffix (mode 2) of the rows read
+            if (mode == 1) {
+                for (int i = tid; i <= rows; i += kBfsSmallThreads)
+                    if (w_rp[i] - w_rp[0] <= kWinEntries) atomicMax(&s_fit, i);
+            } else {
+                for (int i = tid; i <= rows; i += kBfsSmallThreads)
+                    if (w_rp[rows] - w_rp[i] <= kWinEntries) atomicMin(&s_a, i);
+            }
+            __syncthreads();
+            const int a = mode == 1 ? 0 : s_a;
+            const int fit = mode == 1 ? s_fit : rows - a;
+            if (a > 0) {   // move the kept row pointers to the front
+                int t0 = 0, t1 = 0;
+                const int i1 = tid + kBfsSmallThreads;
+                if (tid <= fit) t0 = w_rp[a + tid];
+                if (i1 <= fit) t1 = w_rp[a + i1];
+                __syncthreads();
+                if (tid <= fit) w_rp[tid] = t0;
+                if (i1 <= fit) w_rp[i1] = t1;
+                __syncthreads();
+            }
+            const int base = nb0 + a;
+            const int b0 = w_rp[0], ne = w_rp[fit] - b0;
+            for (int i = tid; i < ne; i += kBfsSmallThreads) w_col[i] = col[b0 + i];
+            for (int i = tid; i < fit; i += kBfsSmallThreads) w_dist[i] = atomic_load_i32(&dist[base + i]);
+            __syncthreads();
+            if (tid == 0) {
+                s_w0 = base;
+                s_nw = fit;
+                s_slide = 0;
+            }
+        }
     }
+    // the window's distances go back to global memory before anyone reads them
+    for (int i = tid; i < s_nw; i += kBfsSmallThreads)
+        if (w_dist[i] >= 0) astore_i32(&dist[s_w0 + i], w_dist[i]);
     if (tid == 0) {
         const int L = s_level;
         st->bfs_visited = s_vis;
@@ -163,22 +325,6 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
 
 // ----------------------------------------------------- multi-block level --
 
-__device__ inline int wave_max_i(int v)
-{
-    for (int off = 32; off > 0; off >>= 1) {
-        const int o = __shfl_xor(v, off, 64);
-        v = v > o ? v : o;
-    }
-    return v;
-}
-__device__ inline int wave_min_i(int v)
-{
-    for (int off = 32; off > 0; off >>= 1) {
-        const int o = __shfl_xor(v, off, 64);
-        v = v < o ? v : o;
-    }
-    return v;
-}
 
 // One level, top-down.  `lanes` consecutive lanes share a frontier vertex
 // and take its neighbours in parallel (lane l: entries l, l + lanes, ...).
@@ -512,7 +658,7 @@ int launch_bfs_round(hipStream_t s, const BfsBufs &b, int levels, int k)
 {
     if (b.persist) {
         hipLaunchKernelGGL(k_bfs_small, dim3(1), dim3(kBfsSmallThreads), 0, s, b.rp, b.col, b.dist, b.q0,
-                           b.q1, b.n, b.lanes, b.small_max, k, b.st);
+                           b.q1, b.n, b.lanes, b.small_max, b.band, k, b.st);
         ++k;
         int grid = (b.n + kBlock - 1) / kBlock;
         if (grid > b.grid) grid = b.grid;
@@ -522,7 +668,7 @@ int launch_bfs_round(hipStream_t s, const BfsBufs &b, int levels, int k)
     }
 
     hipLaunchKernelGGL(k_bfs_small, dim3(1), dim3(kBfsSmallThreads), 0, s, b.rp, b.col, b.dist, b.q0,
-                       b.q1, b.n, b.lanes, b.small_max, k, b.st);
+                       b.q1, b.n, b.lanes, b.small_max, b.band, k, b.st);
     ++k;
     int grid = (b.n + kBlock - 1) / kBlock;
     if (grid > b.grid) grid = b.grid;

@@ -17,7 +17,7 @@ constexpr int kVecTile = kBlock * kVecPerThread;
 constexpr int kK0Max = 64;            // longest FP32 prefix recorded for v
 constexpr int kNumEps = 6;            // eps1 candidates 1e-2 ... 1e-7
 constexpr int kLdsBytes = 32768;      // LDS staging per SpMV block (val + gathered x)
-constexpr int kBfsSmallCap = 3072;    // frontier size handled by the one-workgroup BFS kernel
+constexpr int kBfsSmallCap = 2048;    // frontier size handled by the one-workgroup BFS kernel (>= small_max)
 constexpr int kBfsSmallThreads = 1024;
 constexpr int kBfsSmallWork = 2048;   // (vertex, lane) items per level in the one-workgroup kernel
 constexpr int kBfsLevelBlocks = 128;  // level-kernel blocks (measured best on the 128^3 grid)
@@ -225,6 +225,7 @@ struct BfsBufs {
     int32_t n;
     int32_t lanes;          // lanes per frontier vertex in the one-workgroup kernel
     int32_t small_max;      // largest frontier left to the one-workgroup kernel
+    int32_t band;           // largest |i - j| over the stored entries (window placement)
     int32_t *dist, *label, *tarr;
     QEnt *q0, *q1;      // frontier queues: the row range of each queued vertex
     unsigned long long *best;
