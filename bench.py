@@ -170,6 +170,54 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
+def bench_family(args):
+    """The paper's kNN experiment on its three matrix families (perturbed
+    extended stars, random tree + floor(c n) edges, random bands of density p;
+    Algorithm III values; mu in {1.1, 3, 10}) at n ~ 1000: GPU labelling of
+    every matrix through the batch engine (features, N1/N2 for each eps1,
+    FP64-only), then Acc, Loc, E and E_opt (eq. 27) over random
+    training/test splits with the library's kNN."""
+    import numpy as np
+    from paper_2412_08059_amd import DEFAULT_MODEL, BatchSolver, Solver, family_eval as FE
+    from workloads import paper_family as PF
+    n = args.family_n
+    sizes = {"star": n + 1, "random": n, "banded": n}
+    eng = BatchSolver(256 * (n + 128), 256 * 200_000, 256, model=DEFAULT_MODEL)
+    solver = None if args.family_no_omega else Solver(n + 8, 200_000)
+    fams = {}
+    for fam in ("star", "random", "banded"):
+        specs = PF.sample_specs(fam, sizes[fam], scale=args.family_scale, seed=args.seed)
+        t = time.perf_counter()
+        mats = [PF.make(sp) for sp in specs]
+        tgen = time.perf_counter() - t
+        print(f"# family {fam} n={sizes[fam]}: {len(mats)} matrices (generated in {tgen:.1f}s)",
+              file=sys.stderr, flush=True)
+        rows, secs = FE.label(mats, lambda a, i: PF.paper_rhs(a, 7919 * i + 1)[1], eng, omega_solver=solver)
+        print(f"# family {fam}: labelled in {secs:.1f}s ({8 * len(rows) / secs:.0f} solves/s)",
+              file=sys.stderr, flush=True)
+        res = FE.evaluate(rows, reps=args.family_reps, seed=args.seed)
+        res["label_s"] = round(secs, 1)
+        res["solves_per_s"] = round(8 * len(rows) / secs, 1)
+        fams[fam] = res
+        print(f"# family {fam}: {json.dumps(res)}", file=sys.stderr, flush=True)
+    eng.close()
+    if solver is not None:
+        solver.close()
+    e5 = [fams[f]["per_k"]["5"]["E_third"][0] for f in fams]
+    out = {"metric": "paper-family kNN experiment: E (eq. 27, omega = 1/3, k = 5) mean over the three families",
+           "value": round(float(np.mean(e5)), 2), "unit": "%", "n_gpus": 1, "higher_is_better": True,
+           "data": "synthetic", "dtype": "f32+f64",
+           "config": {"workload": f"perturbed extended stars n={n + 1}, random tree + cn edges n={n}, random bands "
+                                  f"n={n}; Algorithm III values; mu in {{1.1, 3, 10}}; x~U(1,2), b=Ax; eps2=1e-10; "
+                                  f"sample scale {args.family_scale} of the appendix sizes; "
+                                  f"{args.family_reps} training/test splits",
+                      "features": "(m, pseudo-diameter, v)"},
+           "paper_context": {"Acc_pct_n1000": [70, 71, 74], "E_third_pct_n1000": [22, 22, 17.7],
+                             "E_meas_pct_n1000": [31.0, 30.8, 25.3], "note": "sequential CPU, Colab"},
+           "families": fams}
+    print(json.dumps(out))
+
+
 def bench_serve(args):
     """Poisson arrivals at ~80% of the measured saturation throughput; each
     request gets the feature pass and kNN eps1; the same arrival trace is
@@ -252,9 +300,14 @@ def main():
     ap.add_argument("--kernel-only", action="store_true",
                     help="for PMC runs: a 1 GiB device copy (counter calibration) and 20 launches of "
                          "each CG kernel on the workload, nothing else")
-    ap.add_argument("--workload", choices=("solve", "batch", "serve"), default="solve",
+    ap.add_argument("--workload", choices=("solve", "batch", "serve", "family"), default="solve",
                     help="solve: the 128^3 single-system benchmark (default); batch: many systems in one "
-                         "engine; serve: Poisson arrivals with continuous admission")
+                         "engine; serve: Poisson arrivals with continuous admission; family: the paper's "
+                         "kNN experiment on its three matrix families")
+    ap.add_argument("--family-n", type=int, default=1000)
+    ap.add_argument("--family-scale", type=float, default=0.25, help="fraction of the appendix sample sizes")
+    ap.add_argument("--family-reps", type=int, default=20)
+    ap.add_argument("--family-no-omega", action="store_true", help="skip the per-matrix omega measurement")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-nmin", type=float, default=1e3)
     ap.add_argument("--batch-nmax", type=float, default=2e5)
@@ -271,6 +324,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "family":
+        return bench_family(args)
 
     import numpy as np
     import torch

@@ -1,0 +1,170 @@
+"""Pins of the paper-family generators (appendix sample construction and
+Algorithm III) and of the experiment's metric arithmetic (eq. 26, eq. 27,
+Acc, Loc), against facts that do not come from the code under test."""
+
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.csgraph as csg
+
+import oracle
+from workloads import paper_family as PF
+from paper_2412_08059_amd import family_eval as FE
+
+
+def _offdiag(a):
+    m = a.to_scipy().tocoo()
+    off = m.row != m.col
+    return m.row[off], m.col[off], m.data[off]
+
+
+def test_sample_sizes_match_the_appendix():
+    """General sample sizes |S0| of the appendix: 3000/3600/4800 (stars),
+    4800 (random), 1680/3000/6000 (banded)."""
+    assert [len(PF.sample_specs("star", n)) for n in (301, 501, 1001)] == [3000, 3600, 4800]
+    assert [len(PF.sample_specs("random", n)) for n in (300, 500, 1000)] == [4800] * 3
+    assert [len(PF.sample_specs("banded", n)) for n in (300, 500, 1000)] == [1680, 3000, 6000]
+
+
+@pytest.mark.parametrize("n", [301, 501, 1001])
+def test_star_table_pairs(n):
+    for lc, nc in PF.STAR_LC_NC[n]:
+        assert 1 + lc * nc == n
+
+
+@pytest.mark.parametrize("lc,nc", [(10, 30), (1, 300), (300, 1), (5, 60)])
+def test_perturbed_extended_star(lc, nc):
+    for seed in range(3):
+        a = PF.perturbed_extended_star(lc, nc, 3.0, seed)
+        n = a.n
+        assert n == 1 + lc * nc
+        i, j, v = _offdiag(a)
+        assert np.all(v == 1.0)                                   # binary entries
+        edges = i.size // 2
+        assert n - 1 <= edges < n - 1 + math.ceil(0.1 * n)        # tree plus xi < 0.1 n edges
+        deg = np.bincount(i, minlength=n)
+        assert np.allclose(a.to_scipy().diagonal(), 3.0 * deg)     # a_ii = mu * row sum
+        ncomp, _ = csg.connected_components(a.to_scipy(), directed=False)
+        assert ncomp == 1
+        # the star itself is inside: the centre is adjacent to every ray start
+        row0 = set(a.col[a.row_ptr[0]:a.row_ptr[1]].tolist())
+        assert {1 + r * lc for r in range(nc)} <= row0
+
+
+def test_algorithm3_value_distribution():
+    rng = np.random.default_rng(0)
+    v = PF.algorithm3_values(200_000, rng)
+    mag = np.abs(v)
+    assert np.all(((mag >= 0) & (mag <= 3)) | ((mag >= 7) & (mag <= 10)))
+    small = mag <= 3
+    assert abs(small.mean() - 0.5) < 0.01
+    assert abs((v > 0).mean() - 0.5) < 0.01
+    # each range is filled uniformly: its mean and spread match U(a, b)
+    assert abs(mag[small].mean() - 1.5) < 0.02 and abs(mag[~small].mean() - 8.5) < 0.02
+    assert abs(mag[small].var() - 9 / 12) < 0.02
+
+
+@pytest.mark.parametrize("c", PF.RANDOM_C)
+def test_random_sparse(c):
+    n = 300
+    a = PF.random_sparse(n, c, 1.1, seed=7)
+    i, j, v = _offdiag(a)
+    assert i.size // 2 == n - 1 + math.floor(c * n)                # tree + floor(c n) edges
+    assert np.all(np.abs(a.to_scipy() - a.to_scipy().T).data == 0) if (a.to_scipy() - a.to_scipy().T).nnz else True
+    ncomp, _ = csg.connected_components(a.to_scipy(), directed=False)
+    assert ncomp == 1
+    rs = np.bincount(i, weights=np.abs(v), minlength=n)
+    assert np.allclose(a.to_scipy().diagonal(), 1.1 * rs)
+    # strictly diagonally dominant with positive diagonal -> SPD
+    np.linalg.cholesky(a.to_scipy().toarray())
+
+
+def test_random_tree_is_a_tree():
+    rng = np.random.default_rng(3)
+    p, ch = PF.random_tree_edges(500, rng)
+    assert p.size == 499 and np.all(p < ch)
+    g = sp.coo_matrix((np.ones(p.size), (p, ch)), shape=(500, 500))
+    ncomp, _ = csg.connected_components(g, directed=False)
+    assert ncomp == 1
+
+
+@pytest.mark.parametrize("b,p", [(3, 0.4), (11, 0.6), (29, 0.8)])
+def test_random_banded(b, p):
+    n = 1000
+    a = PF.random_banded(n, b, p, 3.0, seed=11)
+    i, j, v = _offdiag(a)
+    w = (b - 1) // 2
+    assert np.all(np.abs(i - j) <= w)
+    slots = sum(n - d for d in range(1, w + 1))
+    dens = (i.size // 2) / slots
+    assert abs(dens - p) < 4 * math.sqrt(p * (1 - p) / slots)
+    assert a.bandwidth() <= w
+
+
+def test_banded_isolated_vertices_solve():
+    """Sparse bands leave isolated vertices (empty rows, b_i = 0); the oracle
+    still reaches eps2 and the 2BFS reports the components."""
+    a = PF.random_banded(400, 3, 0.4, 1.1, seed=5)
+    _, b = PF.paper_rhs(a, 5)
+    r = oracle.solve(a, b, 1e-4, 1e-10)
+    assert r.status == 0 and r.relres_final_true <= 1e-10
+    ncomp, _ = csg.connected_components(a.to_scipy(), directed=False)
+    assert oracle.pseudo_diameter(a)[3] == ncomp
+
+
+def test_training_size_matches_eq26_golden():
+    """The harness's N_S formula reproduces the training sizes printed for the
+    extended-star samples (n = 301, 501, 1001) from the k_CG values the paper
+    gives for them (30.34, 31.5, 34.46) within 0.5 % + 0.5 (the printed k_CG
+    is rounded: n = 1001, k = 10 gives 328.2 against 329); the k = 15 column
+    is a known misprint and is skipped."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "ns_training_sizes.txt")
+    k_cg = {301: 30.34, 501: 31.5, 1001: 34.46}
+    checked = 0
+    for line in open(path):
+        if not line.strip() or line.startswith("#"):
+            continue
+        parts = line.split()
+        n = int(parts[0])
+        for k, ns in zip((1, 5, 10, 15, 20), (int(v) for v in parts[1:])):
+            if k == 15:
+                continue
+            assert abs(FE.training_size(n, k_cg[n], k) - ns) <= 0.005 * ns + 0.5, (n, k)
+            checked += 1
+    assert checked == 12
+
+
+def test_efficiency_and_classes():
+    n1 = np.array([[10, 20, 30, 40, 50, 60], [5, 5, 5, 5, 5, 5]], dtype=float)
+    n2 = np.array([[90, 60, 45, 40, 38, 37], [20, 20, 20, 20, 20, 20]], dtype=float)
+    I = FE.costs(n1, n2, 1 / 3)
+    # row 0: 93.33, 66.67, 55, 53.33, 54.67, 57 -> class 5; row 1: ties -> class 2
+    assert list(FE.optimal_class(I)) == [5, 2]
+    ndp = np.array([100.0, 30.0])
+    sel = np.array([3, 0])
+    e = FE.efficiency(I[np.arange(2), sel], ndp)
+    assert abs(e - (1 - (160 / 3 + 65 / 3) / 130) * 100) < 1e-12
+    # per-row omega
+    I2 = FE.costs(n1, n2, np.array([1.0, 0.5]))
+    assert I2[0, 0] == 100 and I2[1, 0] == 22.5
+
+
+def test_localization_brute_force():
+    rng = np.random.default_rng(1)
+    ftr = rng.uniform(0, 10, size=(40, 4))
+    ltr = rng.integers(2, 8, size=40)
+    fte = rng.uniform(0, 10, size=(15, 4))
+    lte = rng.integers(2, 8, size=15)
+    k = 5
+    got = FE.localization(ftr, ltr, fte, lte, k, mask=14)
+    lo, hi = ftr.min(0), ftr.max(0)
+    tot = 0.0
+    for q, lq in zip(fte, lte):
+        d = [sum(((q[j] - lo[j]) / (hi[j] - lo[j]) - (s[j] - lo[j]) / (hi[j] - lo[j])) ** 2 for j in (1, 2, 3))
+             for s in ftr]
+        nn = sorted(range(40), key=lambda i: (d[i], i))[:k]
+        tot += sum(ltr[i] == lq for i in nn) / k
+    assert abs(got - tot / 15 * 100) < 1e-9

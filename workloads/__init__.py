@@ -21,3 +21,4 @@ from .generators import (  # noqa: F401
     family_matrix,
     FAMILIES,
 )
+from . import paper_family  # noqa: F401,E402
