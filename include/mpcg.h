@@ -180,14 +180,49 @@ mpcg_status mpcg_spmv(mpcg_ctx *ctx, const mpcg_csr *A, int32_t precision, const
 mpcg_status mpcg_bfs(mpcg_ctx *ctx, const mpcg_csr *A, int64_t src, int32_t *dist, int64_t *ecc,
                      int64_t *far);
 
+/* Multi-start 2BFS and an effective-diameter estimate.  The section on
+ * computing the pseudo-diameter notes that repeating 2BFS from several start
+ * vertices and keeping the largest pseudo-diameter improves the estimate;
+ * Remark 1 relates it to the effective diameter, the distance within which a
+ * fixed share q (typically 0.9) of the vertex pairs lie.
+ *
+ * starts: host int32[count], each 0 <= s < n (count may be 0).
+ * q:      the share, 0 < q <= 1.
+ * out (host):
+ *   pdiam        the standard 2BFS pseudo-diameter (per component,
+ *                maximised), as mpcg_features reports it;
+ *   pdiam_multi  the largest of pdiam and, for each start s, l(t_s, u_s):
+ *                t_s the vertex farthest from s, u_s the vertex farthest from
+ *                t_s (ties: smallest index) -- a 2BFS inside s's component;
+ *   best_start   index into starts of the first start whose 2BFS exceeded
+ *                every value before it, -1 when pdiam_multi == pdiam;
+ *   eff_diam     the smallest d >= 1 such that at least q of the pairs
+ *                (s, v) -- s a start, v reachable from s, v != s -- have
+ *                distance <= d (compared as cum >= q * pairs in double);
+ *                0 when there is no pair;
+ *   pairs        the number of such pairs.
+ * Overwrites the workspace.  EINVAL for a null pointer, a start out of range,
+ * count < 0 or q outside (0, 1]. */
+typedef struct {
+    int64_t pdiam;
+    int64_t pdiam_multi;
+    int64_t eff_diam;
+    int64_t pairs;
+    int32_t best_start;
+    int32_t pad_;
+} mpcg_diam_t;
+
+mpcg_status mpcg_diameter_multi(mpcg_ctx *ctx, const mpcg_csr *A, const int32_t *starts, int32_t count,
+                                double q, mpcg_diam_t *out);
+
 /* Time of the most recent mpcg_spmv kernel launch in milliseconds (HIP events
  * on the context stream), 0 if none. */
 mpcg_status mpcg_last_kernel_ms(const mpcg_ctx *ctx, double *ms);
 
 /* Kernels that mpcg_time_kernel can time (the ones a solve launches). */
-#define MPCG_KERNEL_CG_SPMV_F64 0   /* direction update + q = A d + d.q, FP64 */
+#define MPCG_KERNEL_CG_SPMV_F64 0   /* previous x += alpha d, direction update, q = A d, d.q; FP64 */
 #define MPCG_KERNEL_CG_SPMV_F32 1   /* the same on float32(A), FP32 vectors */
-#define MPCG_KERNEL_UPDATE_F64 2    /* x += alpha d, r -= alpha q, r.r, FP64 */
+#define MPCG_KERNEL_UPDATE_F64 2    /* alpha, r -= alpha q, r.r; FP64 */
 #define MPCG_KERNEL_UPDATE_F32 3
 #define MPCG_KERNEL_SPMV_F64 4      /* plain y = A x (mpcg_spmv) */
 #define MPCG_KERNEL_SPMV_F32 5

@@ -91,6 +91,8 @@ def _L():
         lib.or_bfs.restype = ctypes.c_int32
         lib.or_pseudo_diameter.argtypes = [I64, P, P, P]
         lib.or_pseudo_diameter.restype = ctypes.c_int
+        lib.or_diameter_multi.argtypes = [I64, P, P, P, ctypes.c_int32, ctypes.c_double, P]
+        lib.or_diameter_multi.restype = ctypes.c_int
         lib.or_knn_select.argtypes = [ctypes.POINTER(_Model), P, ctypes.c_int32, P, P]
         lib.or_knn_select.restype = ctypes.c_int
         lib.or_solve.argtypes = [I64, P, P, P, P, P, ctypes.c_double, ctypes.c_double,
@@ -148,6 +150,23 @@ def pseudo_diameter(a):
     if st != OK:
         raise ValueError(f"or_pseudo_diameter status {st}")
     return int(out[0]), int(out[1]), int(out[2]), int(out[3])
+
+
+def diameter_multi(a, starts, q: float = 0.9):
+    """(pdiam, pdiam_multi, eff_diam, pairs, best_start): 2BFS repeated from
+    `starts` and the effective diameter over the starts' distances."""
+    rp, col, _ = _csr_arrays(a)
+    s = np.ascontiguousarray(np.asarray(starts, dtype=np.int32))
+    if s.size == 0:
+        s = np.zeros(1, dtype=np.int32)
+        cnt = 0
+    else:
+        cnt = int(s.size)
+    out = np.zeros(5, dtype=np.int64)
+    st = _L().or_diameter_multi(a.n, _p(rp), _p(col), _p(s), cnt, float(q), _p(out))
+    if st != OK:
+        raise ValueError(f"or_diameter_multi status {st}")
+    return tuple(int(v) for v in out)
 
 
 def _model_struct(m: KnnModel):

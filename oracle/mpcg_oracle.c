@@ -18,6 +18,9 @@
  *   or_bfs / or_pseudo_diameter -- the 2BFS procedure (section "Computing
  *                             Pseudo-Diameter of the Graph Matrix") and its
  *                             per-component maximum for disconnected graphs.
+ *   or_diameter_multi      -- 2BFS repeated from several starts (the remark
+ *                             after the procedure) and the effective diameter
+ *                             of Remark 1 from the starts' distances.
  *   or_knn_select          -- weighted kNN (section "Finding the Optimal
  *                             Tolerance ... via a Classification Approach":
  *                             min-max normalisation, squared Euclidean search,
@@ -203,6 +206,53 @@ int or_pseudo_diameter(int64_t n, const int64_t *rp, const int32_t *col, int64_t
     }
     out[0] = ell; out[1] = bt; out[2] = bu; out[3] = ncomp;
     free(dist); free(queue); free(visited);
+    return OR_OK;
+}
+
+/* Multi-start 2BFS and an effective-diameter estimate (the remark after the
+ * 2BFS procedure: repeat 2BFS from several start vertices and keep the
+ * largest pseudo-diameter; Remark 1: the effective diameter is the distance
+ * within which a share q of the vertex pairs lie).  For every start s: a BFS
+ * from s gives t_s (farthest, smallest index on ties) and the distances from
+ * s, which are tallied; a BFS from t_s gives l(t_s, u_s).  The effective
+ * diameter is the smallest d >= 1 with (tally of distances 1..d) >= q * (all
+ * tallied pairs), compared in double.
+ * out[0] = standard pseudo-diameter, out[1] = max over it and the starts'
+ * 2BFS values, out[2] = effective diameter (0 without pairs), out[3] =
+ * number of pairs, out[4] = index of the first start that raised the
+ * maximum (-1 if none). */
+int or_diameter_multi(int64_t n, const int64_t *rp, const int32_t *col, const int32_t *starts,
+                      int32_t count, double q, int64_t *out)
+{
+    if (n <= 0 || count < 0 || !(q > 0.0 && q <= 1.0)) return OR_EINVAL;
+    for (int32_t i = 0; i < count; ++i)
+        if (starts[i] < 0 || starts[i] >= n) return OR_EINVAL;
+    int64_t std4[4];
+    int st = or_pseudo_diameter(n, rp, col, std4);
+    if (st != OR_OK) return st;
+    int32_t *dist = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t *tally = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    if (!dist || !tally) { free(dist); free(tally); return OR_ENOMEM; }
+    int64_t best = std4[0], best_i = -1;
+    for (int32_t i = 0; i < count; ++i) {
+        or_bfs(n, rp, col, starts[i], dist);
+        int64_t t = starts[i];
+        int32_t td = 0;
+        for (int64_t v = 0; v < n; ++v) {
+            if (dist[v] >= 1) tally[dist[v]] += 1;
+            if (dist[v] > td || (dist[v] == td && v < t && dist[v] >= 0)) { td = dist[v]; t = v; }
+        }
+        int32_t e2 = or_bfs(n, rp, col, t, dist);
+        if (e2 > best) { best = e2; best_i = i; }
+    }
+    int64_t pairs = 0, eff = 0, cum = 0;
+    for (int64_t d = 1; d < n; ++d) pairs += tally[d];
+    for (int64_t d = 1; d < n && pairs > 0; ++d) {
+        cum += tally[d];
+        if ((double)cum >= q * (double)pairs) { eff = d; break; }
+    }
+    out[0] = std4[0]; out[1] = best; out[2] = eff; out[3] = pairs; out[4] = best_i;
+    free(dist); free(tally);
     return OR_OK;
 }
 

@@ -101,6 +101,10 @@ class Solver:
         st, ecc, far = capi.mpcg_bfs(self.ctx, A.desc, src, dist.data_ptr())
         return st, dist, ecc, far
 
+    def diameter_multi(self, A: DeviceCSR, starts, q: float = 0.9):
+        """Multi-start 2BFS and the effective-diameter estimate (mpcg_diameter_multi)."""
+        return capi.mpcg_diameter_multi(self.ctx, A.desc, list(starts), q)
+
 
 class BatchSolver:
     """Batched / continuously admitted solves (the mpcg_batch_* entry points).

@@ -37,7 +37,7 @@ MPCG_FLAG_KNN_EXACT = 8
 
 EXPORTED = (
     "mpcg_create", "mpcg_destroy", "mpcg_workspace_size", "mpcg_set_workspace", "mpcg_load_model",
-    "mpcg_features", "mpcg_select_eps1", "mpcg_solve", "mpcg_spmv", "mpcg_bfs",
+    "mpcg_features", "mpcg_select_eps1", "mpcg_solve", "mpcg_spmv", "mpcg_bfs", "mpcg_diameter_multi",
     "mpcg_last_kernel_ms", "mpcg_time_kernel", "mpcg_strerror",
     "mpcg_batch_workspace_size", "mpcg_batch_set_workspace", "mpcg_batch_submit", "mpcg_batch_poll",
     "mpcg_batch_cancel", "mpcg_batch_load",
@@ -61,6 +61,11 @@ class mpcg_features_t(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("pdiam", ctypes.c_int64),
                 ("bfs_t", ctypes.c_int64), ("bfs_u", ctypes.c_int64),
                 ("n_components", ctypes.c_int32), ("k0_used", ctypes.c_int32), ("v", ctypes.c_double)]
+
+
+class mpcg_diam_t(ctypes.Structure):
+    _fields_ = [("pdiam", ctypes.c_int64), ("pdiam_multi", ctypes.c_int64), ("eff_diam", ctypes.c_int64),
+                ("pairs", ctypes.c_int64), ("best_start", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class mpcg_stats(ctypes.Structure):
@@ -107,6 +112,8 @@ def _load():
         "mpcg_solve": ([P, ctypes.POINTER(mpcg_csr), P, P, D, D, ctypes.POINTER(mpcg_stats)], I32),
         "mpcg_spmv": ([P, ctypes.POINTER(mpcg_csr), I32, P, P], I32),
         "mpcg_bfs": ([P, ctypes.POINTER(mpcg_csr), I64, P, ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
+        "mpcg_diameter_multi": ([P, ctypes.POINTER(mpcg_csr), ctypes.POINTER(I32), I32, D,
+                                 ctypes.POINTER(mpcg_diam_t)], I32),
         "mpcg_last_kernel_ms": ([P, ctypes.POINTER(D)], I32),
         "mpcg_time_kernel": ([P, ctypes.POINTER(mpcg_csr), I32, I32, ctypes.POINTER(D)], I32),
         "mpcg_strerror": ([I32], ctypes.c_char_p),
@@ -203,6 +210,14 @@ def mpcg_bfs(ctx: int, A: mpcg_csr, src: int, dist_ptr: int):
     st = lib.mpcg_bfs(ctypes.c_void_p(ctx), ctypes.byref(A), src, ctypes.c_void_p(dist_ptr),
                       ctypes.byref(ecc), ctypes.byref(far))
     return st, ecc.value, far.value
+
+
+def mpcg_diameter_multi(ctx: int, A: mpcg_csr, starts, q: float = 0.9):
+    arr = (ctypes.c_int32 * max(1, len(starts)))(*[int(v) for v in starts])
+    out = mpcg_diam_t()
+    st = lib.mpcg_diameter_multi(ctypes.c_void_p(ctx), ctypes.byref(A), arr, len(starts), float(q),
+                                 ctypes.byref(out))
+    return st, out
 
 
 def mpcg_last_kernel_ms(ctx: int) -> float:

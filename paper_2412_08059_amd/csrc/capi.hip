@@ -12,6 +12,7 @@
 #include <cstring>
 #include <new>
 #include <thread>
+#include <vector>
 
 using namespace mpcg;
 
@@ -913,6 +914,64 @@ mpcg_status mpcg_bfs(mpcg_ctx *c, const mpcg_csr *A, int64_t src, int32_t *dist,
     HIPCHK(hipStreamSynchronize(c->stream));
     if (ecc) *ecc = s.bfs_ecc;
     if (far) *far = s.bfs_far;
+    return MPCG_OK;
+}
+
+mpcg_status mpcg_diameter_multi(mpcg_ctx *c, const mpcg_csr *A, const int32_t *starts, int32_t count, double q,
+                                mpcg_diam_t *out)
+{
+    if (!c || !A || !out || count < 0 || (count > 0 && !starts) || !(q > 0.0 && q <= 1.0)) return MPCG_EINVAL;
+    for (int32_t i = 0; i < count; ++i)
+        if (starts[i] < 0 || (int64_t)starts[i] >= A->n) return MPCG_EINVAL;
+    Plan p;
+    mpcg_status rc = ingest(c, A, nullptr, false, &p);
+    if (rc != MPCG_OK) return rc;
+    mpcg_features_t f{};
+    rc = pseudo_diameter(c, c->main, p, &f);
+    if (rc != MPCG_OK) return rc;
+    mpcg_diam_t d{};
+    d.pdiam = f.pdiam;
+    d.pdiam_multi = f.pdiam;
+    d.best_start = -1;
+    BfsBufs bb = bfs_bufs(c, p);
+    bb.persist = 0;   // one launch per level: needs no co-residency
+    // the per-component key array is not used by single-source sweeps
+    unsigned long long *hist = bb.best;
+    launch_fill_f64(c->stream, reinterpret_cast<double *>(hist), p.n, 0.0);
+    int64_t max_ecc = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        DevState s1, s2;
+        launch_bfs_seed_single(c->stream, bb, starts[i]);
+        rc = bfs_run(c->main, p, bb, &s1);
+        if (rc != MPCG_OK) return rc;
+        launch_dist_hist(c->stream, bb.dist, p.n, hist);
+        if (s1.bfs_ecc > max_ecc) max_ecc = s1.bfs_ecc;
+        launch_bfs_seed_single(c->stream, bb, s1.bfs_far);
+        rc = bfs_run(c->main, p, bb, &s2);
+        if (rc != MPCG_OK) return rc;
+        if (s2.bfs_ecc > d.pdiam_multi) {
+            d.pdiam_multi = s2.bfs_ecc;
+            d.best_start = i;
+        }
+    }
+    if (count > 0 && max_ecc > 0) {
+        std::vector<unsigned long long> h((size_t)max_ecc + 1);
+        HIPCHK(hipMemcpyAsync(h.data(), hist, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost,
+                              c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        unsigned long long total = 0, cum = 0;
+        for (size_t k = 1; k < h.size(); ++k) total += h[k];
+        d.pairs = (int64_t)total;
+        for (size_t k = 1; k < h.size(); ++k) {
+            cum += h[k];
+            if ((double)cum >= q * (double)total) {
+                d.eff_diam = (int64_t)k;
+                break;
+            }
+        }
+    }
+    HIPCHK(hipGetLastError());
+    *out = d;
     return MPCG_OK;
 }
 

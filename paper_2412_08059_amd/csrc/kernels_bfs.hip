@@ -678,6 +678,37 @@ int launch_bfs_round(hipStream_t s, const BfsBufs &b, int levels, int k)
     return k;
 }
 
+// ------------------------------------------------ distance histogram --
+
+// hist[d] += #{v : dist[v] = d}, d >= 1 (unreached vertices and the source are
+// skipped).  Distances below kHistLds are counted in LDS first.
+constexpr int kHistLds = 2048;
+
+__global__ void __launch_bounds__(kBlock)
+k_dist_hist(const int32_t *__restrict__ dist, int32_t n, unsigned long long *hist)
+{
+    __shared__ unsigned int lh[kHistLds];
+    for (int i = threadIdx.x; i < kHistLds; i += kBlock) lh[i] = 0u;
+    __syncthreads();
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+        const int d = dist[v];
+        if (d < 1) continue;
+        if (d < kHistLds) atomicAdd(&lh[d], 1u);
+        else atomicAdd(&hist[d], 1ull);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kHistLds; i += kBlock)
+        if (lh[i]) atomicAdd(&hist[i], (unsigned long long)lh[i]);
+}
+
+void launch_dist_hist(hipStream_t s, const int32_t *dist, int32_t n, unsigned long long *hist)
+{
+    int grid = (n + kBlock - 1) / kBlock;
+    if (grid > 1024) grid = 1024;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_dist_hist, dim3(grid), dim3(kBlock), 0, s, dist, n, hist);
+}
+
 // ------------------------------------------------ connected components --
 
 // Lock-free union-find: roots are hooked larger-under-smaller, so the final

@@ -240,6 +240,8 @@ void launch_bfs_seed_single(hipStream_t s, const BfsBufs &b, int32_t src);
 int launch_bfs_round(hipStream_t s, const BfsBufs &b, int levels, int k);
 
 void launch_cc(hipStream_t s, const BfsBufs &b);
+// hist[d] += number of vertices at distance d >= 1 (hist must hold the largest distance + 1)
+void launch_dist_hist(hipStream_t s, const int32_t *dist, int32_t n, unsigned long long *hist);
 void launch_bfs_seed_roots(hipStream_t s, const BfsBufs &b);
 void launch_comp_argmax(hipStream_t s, const BfsBufs &b, int second_sweep);
 void launch_bfs_seed_far(hipStream_t s, const BfsBufs &b);

@@ -56,6 +56,7 @@ int main(void) {{
   printf("%zu %zu %zu %zu\\n", offsetof(mpcg_csr, col_idx), offsetof(mpcg_stats, feat),
          offsetof(mpcg_stats, t_total_ms), offsetof(mpcg_options, maxit2));
   printf("%zu %zu %zu\\n", sizeof(mpcg_request), offsetof(mpcg_request, eps1), offsetof(mpcg_request, user));
+  printf("%zu %zu\\n", sizeof(mpcg_diam_t), offsetof(mpcg_diam_t, best_start));
   return 0;
 }}""")
     exe = tmp_path / "layout"
@@ -66,7 +67,8 @@ int main(void) {{
            ctypes.sizeof(capi.mpcg_stats), ctypes.sizeof(capi.mpcg_options),
            capi.mpcg_csr.col_idx.offset, capi.mpcg_stats.feat.offset,
            capi.mpcg_stats.t_total_ms.offset, capi.mpcg_options.maxit2.offset,
-           ctypes.sizeof(capi.mpcg_request), capi.mpcg_request.eps1.offset, capi.mpcg_request.user.offset]
+           ctypes.sizeof(capi.mpcg_request), capi.mpcg_request.eps1.offset, capi.mpcg_request.user.offset,
+           ctypes.sizeof(capi.mpcg_diam_t), capi.mpcg_diam_t.best_start.offset]
     assert got == exp
 
 
