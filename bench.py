@@ -218,6 +218,71 @@ def bench_family(args):
     print(json.dumps(out))
 
 
+def bench_jacobi_iter(args):
+    """Algorithm I with the Jacobi method (two-stage Jacobi) against FP64-only
+    Jacobi on a paper-family banded matrix (full bandwidth 17, density 0.8 --
+    dense enough that no vertex is isolated, which Jacobi could not divide by
+    -- Algorithm III values, mu = 3, so the Jacobi contraction factor is at
+    most 1/3), n = 2^21."""
+    import numpy as np
+    import torch
+    from paper_2412_08059_amd import DeviceCSR, Solver
+    from workloads import paper_family as PF
+    n = args.jac_n
+    t = time.perf_counter()
+    a = PF.random_banded(n, 17, 0.8, 3.0, seed=args.seed)
+    _, b = PF.paper_rhs(a, args.seed)
+    print(f"# jacobi_iter: n={a.n} nnz={a.nnz} (generated in {time.perf_counter() - t:.1f}s)", file=sys.stderr,
+          flush=True)
+    sv = Solver(a.n, a.nnz)
+    A = DeviceCSR.from_host(a)
+    B = torch.from_numpy(b).cuda()
+    X = torch.empty(a.n, dtype=torch.float64, device="cuda")
+    runs = {}
+    for label, e1 in [("fp64_only", -1.0)] + [(f"eps1_{e:g}", e) for e in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6)]:
+        ms = []
+        for rep in range(1 + args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, _, S = sv.solve_jacobi(A, B, e1, 1e-10, x=X)
+            torch.cuda.synchronize()
+            if rep > args.warmup:
+                ms.append((time.perf_counter() - t0) * 1e3)
+        runs[label] = {"ms": round(float(np.mean(ms)), 3), "n1": S.n1, "n2": S.n2, "status": st,
+                       "relres_final_true": S.relres_final_true, "t_sp_ms": round(S.t_sp_ms, 3),
+                       "t_dp_ms": round(S.t_dp_ms, 3)}
+        print(f"# jacobi_iter {label}: {runs[label]}", file=sys.stderr, flush=True)
+    from paper_2412_08059_amd import capi
+    kus = {}
+    for kname, kid in (("jacobi_f64", capi.MPCG_KERNEL_JACOBI_F64), ("jacobi_f32", capi.MPCG_KERNEL_JACOBI_F32)):
+        kus[kname] = capi.mpcg_time_kernel(sv.ctx, A.desc, kid, 30) * 1e3
+    sv.close()
+    bad = {k: v["status"] for k, v in runs.items() if v["status"] != 0}
+    if bad:
+        print(json.dumps({"metric": "two-stage Jacobi", "error": f"solve status {bad}"}))
+        sys.exit(1)
+    best = min((k for k in runs if k != "fp64_only"), key=lambda k: runs[k]["ms"])
+    dp = runs["fp64_only"]
+    # algorithmic bytes of one iteration: values + columns, row pointers, and
+    # x gathered once, b, diag(A) and x_{k+1}
+    m = a.nnz
+    byt64 = (8 + 4) * m + 4 * (n + 1) + 4 * 8 * n
+    byt32 = (4 + 4) * m + 4 * (n + 1) + 4 * 4 * n
+    it64_us, it32_us = kus["jacobi_f64"], kus["jacobi_f32"]
+    out = {"metric": "two-stage Jacobi (Algorithm I with the Jacobi method): time to 1e-10, mixed vs FP64-only",
+           "value": runs[best]["ms"], "unit": "ms", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+           "dtype": "f32+f64",
+           "config": {"workload": f"random banded n={n}, full bandwidth 17, density 0.8, Algorithm III values, mu=3, "
+                                  "x~U(1,2), b=Ax, eps2=1e-10", "n": a.n, "m": a.nnz},
+           "best_eps1": best, "fp64_only_ms": dp["ms"], "speedup_vs_fp64_only": round(dp["ms"] / runs[best]["ms"], 3),
+           "iteration_f64": {"us": round(it64_us, 2), "bytes": byt64, "GBs": round(byt64 / it64_us / 1e3, 1),
+                             "frac_hbm": round(byt64 / it64_us / 1e3 / 8000.0, 3)},
+           "iteration_f32": {"us": round(it32_us, 2), "bytes": byt32, "GBs": round(byt32 / it32_us / 1e3, 1),
+                             "frac_hbm": round(byt32 / it32_us / 1e3 / 8000.0, 3)},
+           "runs": runs}
+    print(json.dumps(out))
+
+
 def bench_serve(args):
     """Poisson arrivals at ~80% of the measured saturation throughput; each
     request gets the feature pass and kNN eps1; the same arrival trace is
@@ -300,10 +365,12 @@ def main():
     ap.add_argument("--kernel-only", action="store_true",
                     help="for PMC runs: a 1 GiB device copy (counter calibration) and 20 launches of "
                          "each CG kernel on the workload, nothing else")
-    ap.add_argument("--workload", choices=("solve", "batch", "serve", "family"), default="solve",
+    ap.add_argument("--workload", choices=("solve", "batch", "serve", "family", "jacobi_iter"), default="solve",
                     help="solve: the 128^3 single-system benchmark (default); batch: many systems in one "
                          "engine; serve: Poisson arrivals with continuous admission; family: the paper's "
-                         "kNN experiment on its three matrix families")
+                         "kNN experiment on its three matrix families; jacobi_iter: Algorithm I with the Jacobi "
+                         "method")
+    ap.add_argument("--jac-n", type=int, default=1 << 21)
     ap.add_argument("--family-n", type=int, default=1000)
     ap.add_argument("--family-scale", type=float, default=0.25, help="fraction of the appendix sample sizes")
     ap.add_argument("--family-reps", type=int, default=20)
@@ -326,6 +393,8 @@ def main():
         return bench_serve(args)
     if args.workload == "family":
         return bench_family(args)
+    if args.workload == "jacobi_iter":
+        return bench_jacobi_iter(args)
 
     import numpy as np
     import torch

@@ -180,6 +180,26 @@ mpcg_status mpcg_spmv(mpcg_ctx *ctx, const mpcg_csr *A, int32_t precision, const
 mpcg_status mpcg_bfs(mpcg_ctx *ctx, const mpcg_csr *A, int64_t src, int32_t *dist, int64_t *ecc,
                      int64_t *far);
 
+/* Algorithm I with the Jacobi method in place of CG (the section on the
+ * matrix graph diameter and rounding-error growth in other iterative
+ * methods): x_{k+1} = D^{-1}(b - (L + U) x_k) with A = L + D + U, first in
+ * FP32 on the FP32 copy of A and b from x0 = 0 until the FP32 residual
+ * ||b - A x_k|| <= eps1 ||b|| (or maxit1 updates: MPCG_FLAG_FP32_MAXIT, the
+ * "cannot be achieved" entries of the paper's Jacobi table), then in FP64 from
+ * float64(x~) until ||b - A x_k|| <= eps2 ||b||.  Each iteration forms
+ * s = sum_{j != i} a_ij x_j (row order, one fma chain), t = b_i - s, the
+ * residual t - a_ii x_i of the iterate and x_{k+1,i} = t / a_ii.
+ *
+ * A, b, x as for mpcg_solve; eps1 > 0 or MPCG_EPS1_NONE (FP64 only; kNN eps1
+ * is not offered); eps2 > 0.  stats: n1, n2 = updates per stage, relres_sp =
+ * the FP32 stage's last residual / ||b||, relres_final_true = the FP64
+ * residual of the returned x / ||b||, flags, status.  A missing or
+ * non-positive diagonal entry is ENOTSPD (Jacobi divides by a_ii).  Returns
+ * OK, ENOCONV (maxit2 reached; x holds the last iterate), ENONFINITE or an
+ * input error as mpcg_solve. */
+mpcg_status mpcg_solve_jacobi(mpcg_ctx *ctx, const mpcg_csr *A, const double *b, double *x, double eps1,
+                              double eps2, mpcg_stats *stats);
+
 /* Multi-start 2BFS and an effective-diameter estimate.  The section on
  * computing the pseudo-diameter notes that repeating 2BFS from several start
  * vertices and keeping the largest pseudo-diameter improves the estimate;
@@ -226,6 +246,8 @@ mpcg_status mpcg_last_kernel_ms(const mpcg_ctx *ctx, double *ms);
 #define MPCG_KERNEL_UPDATE_F32 3
 #define MPCG_KERNEL_SPMV_F64 4      /* plain y = A x (mpcg_spmv) */
 #define MPCG_KERNEL_SPMV_F32 5
+#define MPCG_KERNEL_JACOBI_F64 6    /* one Jacobi iteration of mpcg_solve_jacobi (residual + update), FP64 */
+#define MPCG_KERNEL_JACOBI_F32 7
 
 /* Measurement hook: run `reps` back-to-back launches of one solver kernel on A
  * with the workspace's scratch vectors (set to finite values, recurrence held

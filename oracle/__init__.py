@@ -91,6 +91,9 @@ def _L():
         lib.or_bfs.restype = ctypes.c_int32
         lib.or_pseudo_diameter.argtypes = [I64, P, P, P]
         lib.or_pseudo_diameter.restype = ctypes.c_int
+        lib.or_jacobi_solve.argtypes = [I64, P, P, P, P, P, ctypes.c_double, ctypes.c_double,
+                                        ctypes.POINTER(_Opts), ctypes.POINTER(_Stats)]
+        lib.or_jacobi_solve.restype = ctypes.c_int
         lib.or_diameter_multi.argtypes = [I64, P, P, P, ctypes.c_int32, ctypes.c_double, P]
         lib.or_diameter_multi.restype = ctypes.c_int
         lib.or_knn_select.argtypes = [ctypes.POINTER(_Model), P, ctypes.c_int32, P, P]
@@ -150,6 +153,23 @@ def pseudo_diameter(a):
     if st != OK:
         raise ValueError(f"or_pseudo_diameter status {st}")
     return int(out[0]), int(out[1]), int(out[2]), int(out[3])
+
+
+def solve_jacobi(a, b, eps1: float, eps2: float = 1e-10, *, tol_mode: int = 0, maxit1: int = 0,
+                 maxit2: int = 0) -> OracleResult:
+    """Algorithm I with the Jacobi method: FP32 stage to eps1 (eps1 = -1:
+    none), then FP64 from float64(x~) to eps2."""
+    rp, col, val = _csr_arrays(a)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(a.n, dtype=np.float64)
+    opts = _Opts(20, tol_mode, 0, 0, 0, 0, maxit1, maxit2)
+    st = _Stats()
+    status = _L().or_jacobi_solve(a.n, _p(rp), _p(col), _p(val), _p(b), _p(x), float(eps1), float(eps2),
+                                  ctypes.byref(opts), ctypes.byref(st))
+    return OracleResult(status=status, x=x, n1=st.n1, n2=st.n2, restarts=0, flags=st.flags, k0_used=0,
+                        eps1_class=-1, eps1_used=st.eps1_used, v=0.0, beta_b=0.0, relres_sp=st.relres_sp,
+                        relres_restart_true=0.0, relres_final_true=st.relres_final_true, ell=0, bfs_t=0,
+                        bfs_u=0, ncomp=0)
 
 
 def diameter_multi(a, starts, q: float = 0.9):

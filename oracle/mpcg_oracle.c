@@ -18,6 +18,9 @@
  *   or_bfs / or_pseudo_diameter -- the 2BFS procedure (section "Computing
  *                             Pseudo-Diameter of the Graph Matrix") and its
  *                             per-component maximum for disconnected graphs.
+ *   or_jacobi_solve        -- Algorithm I with the Jacobi method in place
+ *                             of CG (section on rounding-error growth in other
+ *                             iterative methods; the paper's Jacobi table).
  *   or_diameter_multi      -- 2BFS repeated from several starts (the remark
  *                             after the procedure) and the effective diameter
  *                             of Remark 1 from the starts' distances.
@@ -207,6 +210,134 @@ int or_pseudo_diameter(int64_t n, const int64_t *rp, const int32_t *col, int64_t
     out[0] = ell; out[1] = bt; out[2] = bu; out[3] = ncomp;
     free(dist); free(queue); free(visited);
     return OR_OK;
+}
+
+/* ------------------------------------------------------ Jacobi method -- */
+
+/* Algorithm I with the Jacobi method in place of CG (the section on the
+ * matrix graph diameter and rounding-error growth in other iterative
+ * methods): x_{k+1} = D^{-1}(b - (L + U) x_k), A = L + D + U.  One iteration
+ * in the working precision: s_i = sum over the stored off-diagonal entries of
+ * row i of a_ij x_j (fma chain in CSR order from 0), t_i = b_i - s_i, the
+ * residual of the iterate r_i = t_i - a_ii x_i (one fma) and
+ * x_{k+1,i} = t_i / a_ii.  ||r_k||^2 is summed in FP64 in row order; the
+ * stage stops with x_k when ||r_k|| <= thr, when it is not finite, or when k
+ * reaches the stage's iteration cap.  Returns the stop reason (1 converged,
+ * 2 cap, 4 non-finite) and the number of updates in *iters. */
+static int jac32_stage(int64_t n, const int64_t *rp, const int32_t *col, const float *v32, const float *d32,
+                       const float *b32, float *x, float *xn, double thr, int64_t maxit, int64_t *iters,
+                       double *g_out, float **ans)
+{
+    float *cur = x, *nxt = xn;
+    for (int64_t k = 0;; ++k) {
+        double g = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            float s = 0.0f;
+            for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+                if (col[e] != i) s = fmaf(v32[e], cur[col[e]], s);
+            const float t = b32[i] - s;
+            const float r = fmaf(-d32[i], cur[i], t);
+            nxt[i] = t / d32[i];
+            g = fma((double)r, (double)r, g);
+        }
+        *g_out = g;
+        *iters = k;
+        *ans = cur;
+        if (!isfinite(g)) return 4;
+        if (sqrt(g) <= thr) return 1;
+        if (k >= maxit) return 2;
+        float *tmp = cur; cur = nxt; nxt = tmp;
+    }
+}
+
+static int jac64_stage(int64_t n, const int64_t *rp, const int32_t *col, const double *val, const double *d,
+                       const double *b, double *x, double *xn, double thr, int64_t maxit, int64_t *iters,
+                       double *g_out, double **ans)
+{
+    double *cur = x, *nxt = xn;
+    for (int64_t k = 0;; ++k) {
+        double g = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+                if (col[e] != i) s = fma(val[e], cur[col[e]], s);
+            const double t = b[i] - s;
+            const double r = fma(-d[i], cur[i], t);
+            nxt[i] = t / d[i];
+            g = fma(r, r, g);
+        }
+        *g_out = g;
+        *iters = k;
+        *ans = cur;
+        if (!isfinite(g)) return 4;
+        if (sqrt(g) <= thr) return 1;
+        if (k >= maxit) return 2;
+        double *tmp = cur; cur = nxt; nxt = tmp;
+    }
+}
+
+/* eps1 = -1: FP64 stage only.  x gets the FP64 stage's answer. */
+int or_jacobi_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val, const double *b,
+                    double *x, double eps1, double eps2, const or_opts *opts, or_stats *st)
+{
+    memset(st, 0, sizeof(*st));
+    st->eps1_class = -1;
+    if (n <= 0 || !(eps2 > 0.0) || (eps1 != -1.0 && !(eps1 > 0.0))) return st->status = OR_EINVAL;
+    for (int64_t i = 0; i < n; ++i)
+        if (!isfinite(b[i])) return st->status = OR_ENONFINITE;
+    for (int64_t e = 0; e < rp[n]; ++e)
+        if (!isfinite(val[e])) return st->status = OR_ENONFINITE;
+    double *d = (double *)malloc(sizeof(double) * (size_t)n);
+    double *xa = (double *)malloc(sizeof(double) * (size_t)n);
+    double *xb = (double *)malloc(sizeof(double) * (size_t)n);
+    float *d32 = (float *)malloc(sizeof(float) * (size_t)n);
+    float *b32 = (float *)malloc(sizeof(float) * (size_t)n);
+    float *v32 = (float *)malloc(sizeof(float) * (size_t)(rp[n] > 0 ? rp[n] : 1));
+    float *ya = (float *)malloc(sizeof(float) * (size_t)n);
+    float *yb = (float *)malloc(sizeof(float) * (size_t)n);
+    int rc = OR_OK;
+    if (!d || !xa || !xb || !d32 || !b32 || !v32 || !ya || !yb) { rc = OR_ENOMEM; goto done; }
+    for (int64_t i = 0; i < n; ++i) {
+        d[i] = 0.0;
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+            if (col[e] == i) d[i] = val[e];
+        if (!(d[i] > 0.0)) { rc = OR_ENOTSPD; goto done; }
+        d32[i] = (float)d[i];
+        b32[i] = (float)b[i];
+    }
+    for (int64_t e = 0; e < rp[n]; ++e) v32[e] = (float)val[e];
+    double bb = 0.0;
+    for (int64_t i = 0; i < n; ++i) bb = fma(b[i], b[i], bb);
+    const double bn = sqrt(bb);
+    const int abs_tol = opts && opts->tol_mode == 1;
+    const int64_t maxit1 = opts && opts->maxit1 > 0 ? opts->maxit1 : n;
+    const int64_t maxit2 = opts && opts->maxit2 > 0 ? opts->maxit2 : (10 * n > 1000 ? 10 * n : 1000);
+    int64_t it = 0;
+    double g = 0.0;
+    if (eps1 != -1.0) {
+        for (int64_t i = 0; i < n; ++i) ya[i] = 0.0f;
+        float *ans32 = ya;
+        const int why = jac32_stage(n, rp, col, v32, d32, b32, ya, yb, abs_tol ? eps1 : eps1 * bn, maxit1, &it,
+                                    &g, &ans32);
+        st->n1 = (int32_t)it;
+        if (why == 2) st->flags |= OR_FLAG_FP32_MAXIT;
+        if (why == 4) st->flags |= OR_FLAG_FP32_BREAKDOWN;
+        st->relres_sp = bn > 0.0 ? sqrt(g) / bn : 0.0;
+        for (int64_t i = 0; i < n; ++i) xa[i] = (double)ans32[i];
+        st->eps1_used = eps1;
+    } else {
+        for (int64_t i = 0; i < n; ++i) xa[i] = 0.0;
+        st->eps1_used = -1.0;
+    }
+    double *ans = xa;
+    const int why = jac64_stage(n, rp, col, val, d, b, xa, xb, abs_tol ? eps2 : eps2 * bn, maxit2, &it, &g, &ans);
+    st->n2 = (int32_t)it;
+    st->relres_final_true = bn > 0.0 ? sqrt(g) / bn : 0.0;
+    memcpy(x, ans, sizeof(double) * (size_t)n);
+    rc = why == 1 ? OR_OK : (why == 4 ? OR_ENONFINITE : OR_ENOCONV);
+done:
+    free(d); free(xa); free(xb); free(d32); free(b32); free(v32); free(ya); free(yb);
+    return st->status = rc;
 }
 
 /* Multi-start 2BFS and an effective-diameter estimate (the remark after the

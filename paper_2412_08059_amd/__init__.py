@@ -85,6 +85,14 @@ class Solver:
         st, stats = capi.mpcg_solve(self.ctx, A.desc, b.data_ptr(), x.data_ptr(), eps1, eps2)
         return st, x, stats
 
+    def solve_jacobi(self, A: DeviceCSR, b, eps1: float, eps2: float = 1e-10, x=None):
+        """Algorithm I with the Jacobi method (mpcg_solve_jacobi); returns (status, x, stats)."""
+        import torch
+        if x is None:
+            x = torch.empty(A.n, dtype=torch.float64, device=self.device)
+        st, stats = capi.mpcg_solve_jacobi(self.ctx, A.desc, b.data_ptr(), x.data_ptr(), eps1, eps2)
+        return st, x, stats
+
     def features(self, A: DeviceCSR, b, k0: int = 20):
         return capi.mpcg_features(self.ctx, A.desc, b.data_ptr(), k0)
 

@@ -22,8 +22,8 @@ INCLUDE = os.path.join(REPO, "include")
 LIB = os.path.join(HERE, "libmpcg.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["kernels_cg.hip", "kernels_sell.hip", "kernels_bfs.hip", "kernels_batch.hip", "batch_engine.hip",
-               "capi.hip"]
+HIP_SOURCES = ["kernels_cg.hip", "kernels_sell.hip", "kernels_bfs.hip", "kernels_jacobi.hip", "kernels_batch.hip",
+               "batch_engine.hip", "capi.hip"]
 HOST_SOURCES = ["knn.cpp"]
 
 

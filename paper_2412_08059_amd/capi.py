@@ -37,7 +37,8 @@ MPCG_FLAG_KNN_EXACT = 8
 
 EXPORTED = (
     "mpcg_create", "mpcg_destroy", "mpcg_workspace_size", "mpcg_set_workspace", "mpcg_load_model",
-    "mpcg_features", "mpcg_select_eps1", "mpcg_solve", "mpcg_spmv", "mpcg_bfs", "mpcg_diameter_multi",
+    "mpcg_features", "mpcg_select_eps1", "mpcg_solve", "mpcg_solve_jacobi", "mpcg_spmv", "mpcg_bfs",
+    "mpcg_diameter_multi",
     "mpcg_last_kernel_ms", "mpcg_time_kernel", "mpcg_strerror",
     "mpcg_batch_workspace_size", "mpcg_batch_set_workspace", "mpcg_batch_submit", "mpcg_batch_poll",
     "mpcg_batch_cancel", "mpcg_batch_load",
@@ -49,6 +50,8 @@ MPCG_KERNEL_UPDATE_F64 = 2
 MPCG_KERNEL_UPDATE_F32 = 3
 MPCG_KERNEL_SPMV_F64 = 4
 MPCG_KERNEL_SPMV_F32 = 5
+MPCG_KERNEL_JACOBI_F64 = 6
+MPCG_KERNEL_JACOBI_F32 = 7
 
 
 class mpcg_csr(ctypes.Structure):
@@ -110,6 +113,7 @@ def _load():
         "mpcg_select_eps1": ([P, ctypes.POINTER(mpcg_features_t), ctypes.POINTER(D),
                               ctypes.POINTER(I32)], I32),
         "mpcg_solve": ([P, ctypes.POINTER(mpcg_csr), P, P, D, D, ctypes.POINTER(mpcg_stats)], I32),
+        "mpcg_solve_jacobi": ([P, ctypes.POINTER(mpcg_csr), P, P, D, D, ctypes.POINTER(mpcg_stats)], I32),
         "mpcg_spmv": ([P, ctypes.POINTER(mpcg_csr), I32, P, P], I32),
         "mpcg_bfs": ([P, ctypes.POINTER(mpcg_csr), I64, P, ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
         "mpcg_diameter_multi": ([P, ctypes.POINTER(mpcg_csr), ctypes.POINTER(I32), I32, D,
@@ -202,6 +206,13 @@ def mpcg_solve(ctx: int, A: mpcg_csr, b_ptr: int, x_ptr: int, eps1: float, eps2:
 def mpcg_spmv(ctx: int, A: mpcg_csr, precision: int, x_ptr: int, y_ptr: int) -> int:
     return lib.mpcg_spmv(ctypes.c_void_p(ctx), ctypes.byref(A), precision, ctypes.c_void_p(x_ptr),
                          ctypes.c_void_p(y_ptr))
+
+
+def mpcg_solve_jacobi(ctx: int, A: mpcg_csr, b_ptr: int, x_ptr: int, eps1: float, eps2: float):
+    s = mpcg_stats()
+    st = lib.mpcg_solve_jacobi(ctypes.c_void_p(ctx), ctypes.byref(A), ctypes.c_void_p(b_ptr),
+                               ctypes.c_void_p(x_ptr), float(eps1), float(eps2), ctypes.byref(s))
+    return st, s
 
 
 def mpcg_bfs(ctx: int, A: mpcg_csr, src: int, dist_ptr: int):

@@ -353,6 +353,46 @@ mpcg_status cg_loop(mpcg_ctx *c, const Plan &p, T *x, T *r, T *q, T *dA, T *dB, 
     return read_state(ch, p, out);
 }
 
+// ---- two-stage Jacobi iteration
+
+JacMat jac_mat(const Plan &p)
+{
+    JacMat m{};
+    m.rp = p.rp;
+    m.col = p.col;
+    m.n = p.n;
+    m.use_sell = p.use_sell;
+    m.sell = p.sell;
+    return m;
+}
+
+// One stage: Jacobi iterations from x0 until the device stops the stage;
+// *out gets the state (iter = updates applied; the iterate is in x0 when iter
+// is even, else in x1).
+template <typename T>
+mpcg_status jacobi_stage(mpcg_ctx *c, const Plan &p, const T *b, const T *dg, T *x0, T *x1, double eps,
+                         int abs_tol, int32_t maxit, const double *b64, DevState *out)
+{
+    const JacMat m = jac_mat(p);
+    const Chan &ch = c->main;
+    launch_jacobi_begin(ch.s, m, b64, p.sp, p.st);
+    const int G = poll_iters(c);
+    int it = 0;
+    for (int64_t g = 0;; ++g) {
+        for (int j = 0; j < G; ++j, ++it)
+            launch_jacobi_iter<T>(ch.s, m, csr_vals<T>(p), b, dg, x0, x1, it, maxit, eps, abs_tol, p.sp, p.st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(ch.poll[g & 1], p.st, sizeof(DevState), hipMemcpyDeviceToHost, ch.s));
+        HIPCHK(hipEventRecord(ch.ev[g & 1], ch.s));
+        if (g > 0) {
+            HIPCHK(hipEventSynchronize(ch.ev[(g - 1) & 1]));
+            if (!ch.poll[(g - 1) & 1]->live) break;
+        }
+        if (it > 0x7ffffff0 - G) return MPCG_EDEVICE;
+    }
+    return read_state(ch, p, out);
+}
+
 int env_int(const char *name, int def)
 {
     const char *e = std::getenv(name);
@@ -917,6 +957,67 @@ mpcg_status mpcg_bfs(mpcg_ctx *c, const mpcg_csr *A, int64_t src, int32_t *dist,
     return MPCG_OK;
 }
 
+mpcg_status mpcg_solve_jacobi(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *x, double eps1,
+                              double eps2, mpcg_stats *stats)
+{
+    if (!c || !A || !b || !x) return MPCG_EINVAL;
+    if (!(eps2 > 0.0) || !std::isfinite(eps2)) return MPCG_EINVAL;
+    const bool dponly = (eps1 == MPCG_EPS1_NONE);
+    if (!dponly && !(eps1 > 0.0 && std::isfinite(eps1))) return MPCG_EINVAL;
+    mpcg_stats S{};
+    S.eps1_class = -1;
+    S.eps1_used = dponly ? -1.0 : eps1;
+    HIPCHK(hipEventRecord(c->tm[0], c->stream));
+    Plan p;
+    mpcg_status rc = ingest(c, A, b, !dponly, &p, true);
+    if (rc != MPCG_OK) {
+        S.status = rc;
+        if (stats) *stats = S;
+        return rc;
+    }
+    const int abs_tol = c->opt.tol_mode == 1;
+    const int64_t n = A->n;
+    int64_t mi1 = c->opt.maxit1 > 0 ? c->opt.maxit1 : n;
+    int64_t mi2 = c->opt.maxit2 > 0 ? c->opt.maxit2 : (10 * n > 1000 ? 10 * n : 1000);
+    const int32_t maxit1 = (int32_t)(mi1 < 0x7fff0000 ? mi1 : 0x7fff0000);
+    const int32_t maxit2 = (int32_t)(mi2 < 0x7fff0000 ? mi2 : 0x7fff0000);
+    DevState s;
+    if (!dponly) {
+        float *b32 = p.at<float>(p.L.r32);
+        float *xa = p.at<float>(p.L.x32), *xb = p.at<float>(p.L.dA32);
+        launch_cast32(c->stream, b, b32, n);
+        launch_fill_f32(c->stream, xa, n, 0.0f);
+        rc = jacobi_stage<float>(c, p, b32, p.dg32, xa, xb, eps1, abs_tol, maxit1, b, &s);
+        if (rc != MPCG_OK) return rc;
+        S.n1 = s.iter;
+        if (s.reason == kMaxit) S.flags |= MPCG_FLAG_FP32_MAXIT;
+        else if (s.reason == kNonFinite) S.flags |= MPCG_FLAG_FP32_BREAKDOWN;
+        if (s.bnorm2 > 0.0) S.relres_sp = std::sqrt(s.gamma) / std::sqrt(s.bnorm2);
+        launch_jacobi_widen(c->stream, (s.iter & 1) ? xb : xa, x, (int32_t)n);
+    } else {
+        launch_fill_f64(c->stream, x, n, 0.0);
+    }
+    HIPCHK(hipEventRecord(c->tm[3], c->stream));
+    double *q64 = p.at<double>(p.L.q64);
+    rc = jacobi_stage<double>(c, p, b, p.dg64, x, q64, eps2, abs_tol, maxit2, b, &s);
+    if (rc != MPCG_OK) return rc;
+    S.n2 = s.iter;
+    if (s.iter & 1) HIPCHK(hipMemcpyAsync(x, q64, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipEventRecord(c->tm[4], c->stream));
+    HIPCHK(hipEventSynchronize(c->tm[4]));
+    S.relres_final_true = s.bnorm2 > 0.0 ? std::sqrt(s.gamma) / std::sqrt(s.bnorm2) : 0.0;
+    const mpcg_status fin = s.reason == kConverged ? MPCG_OK : (s.reason == kNonFinite ? MPCG_ENONFINITE : MPCG_ENOCONV);
+    S.status = fin;
+    float t_sp = 0.f, t_dp = 0.f;
+    (void)hipEventElapsedTime(&t_sp, c->tm[0], c->tm[3]);
+    (void)hipEventElapsedTime(&t_dp, c->tm[3], c->tm[4]);
+    S.t_sp_ms = t_sp;
+    S.t_dp_ms = t_dp;
+    S.t_total_ms = (double)t_sp + (double)t_dp;
+    if (stats) *stats = S;
+    return fin;
+}
+
 mpcg_status mpcg_diameter_multi(mpcg_ctx *c, const mpcg_csr *A, const int32_t *starts, int32_t count, double q,
                                 mpcg_diam_t *out)
 {
@@ -984,10 +1085,11 @@ mpcg_status mpcg_last_kernel_ms(const mpcg_ctx *c, double *ms)
 
 mpcg_status mpcg_time_kernel(mpcg_ctx *c, const mpcg_csr *A, int32_t kernel, int32_t reps, double *ms)
 {
-    if (!c || !A || !ms || reps < 1 || kernel < 0 || kernel > 5) return MPCG_EINVAL;
+    if (!c || !A || !ms || reps < 1 || kernel < 0 || kernel > 7) return MPCG_EINVAL;
     const bool f32 = (kernel & 1) != 0;
+    const bool jac = kernel >= MPCG_KERNEL_JACOBI_F64;
     Plan p;
-    mpcg_status rc = ingest(c, A, nullptr, f32, &p);
+    mpcg_status rc = ingest(c, A, nullptr, f32, &p, jac);
     if (rc != MPCG_OK) return rc;
     float *x32 = p.at<float>(p.L.x32), *r32 = p.at<float>(p.L.r32), *q32 = p.at<float>(p.L.q32);
     float *dA32 = p.at<float>(p.L.dA32), *dB32 = p.at<float>(p.L.dB32);
@@ -1025,6 +1127,14 @@ mpcg_status mpcg_time_kernel(mpcg_ctx *c, const mpcg_csr *A, int32_t kernel, int
             break;
         case MPCG_KERNEL_SPMV_F64:
             run_plain<double>(c->stream, p, r64, q64);
+            break;
+        case MPCG_KERNEL_JACOBI_F64:   // threshold 0 and no cap: every launch runs
+            launch_jacobi_iter<double>(c->stream, jac_mat(p), csr_vals<double>(p), r64, p.dg64, x64, dA64, 1,
+                                       0x7fff0000, 0.0, 1, p.sp, p.st);
+            break;
+        case MPCG_KERNEL_JACOBI_F32:
+            launch_jacobi_iter<float>(c->stream, jac_mat(p), csr_vals<float>(p), r32, p.dg32, x32, dA32, 1,
+                                      0x7fff0000, 0.0, 1, p.sp, p.st);
             break;
         default:
             run_plain<float>(c->stream, p, r32, q32);

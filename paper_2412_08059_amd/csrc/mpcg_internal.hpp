@@ -124,6 +124,24 @@ struct SellMat {
 
 Layout plan_layout(int64_t n, int64_t nnz);
 
+// The matrix as the Jacobi-iteration kernels see it: the SELL-64 copy when the
+// solve uses it, else the CSR input (FP32 values from the val32 copy).
+struct JacMat {
+    const int32_t *rp;
+    const int32_t *col;
+    int32_t n;
+    bool use_sell;
+    SellMat sell;
+};
+int jacobi_grid(const JacMat &m);   // blocks (= partial slots) of one iteration launch
+// partials of ||b||^2 into part[np ..], stop markers reset
+void launch_jacobi_begin(hipStream_t s, const JacMat &m, const double *b, double *part, DevState *st);
+// launch k of a Jacobi stage: x_k in (k & 1 ? x1 : x0) -> x_{k+1}, partials of ||r_k||^2
+template <typename T>
+void launch_jacobi_iter(hipStream_t s, const JacMat &m, const T *val_csr, const T *b, const T *dg, T *x0, T *x1,
+                        int k, int maxit, double eps, int abs_tol, double *part, DevState *st);
+void launch_jacobi_widen(hipStream_t s, const float *x32, double *x64, int32_t n);
+
 
 // Run-ahead test inside the CG product of iteration `it` (FP32 only): returns
 // the mask of candidate thresholds first crossed at this iteration (the same in
