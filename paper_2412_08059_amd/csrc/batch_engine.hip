@@ -15,6 +15,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -119,6 +120,7 @@ struct Engine {
     RangeAlloc slices, entries;
     int32_t hi_sys = 0, hi_slice = 0;
     int64_t group = 0;
+    int small_levels = kSmallBfsLevels;   // MPCG_BATCH_SMALL_LEVELS
 
     std::mutex mu;
     std::condition_variable cv;
@@ -420,16 +422,17 @@ bool Engine::step_once()
     }
     admit();
     if (failed) return false;
-    bool any_used = false, any_live = false;
+    bool any_used = false, any_live = false, any_bfs = false;
     for (auto &sl : slots) {
         if (!sl.used) continue;
         any_used = true;
         if (sl.adm == 2 && !sl.retiring) any_live = true;
+        if (sl.autoe && (sl.feat == 1 || sl.feat == 2)) any_bfs = true;   // sweeps armed, not finished
     }
     if (!any_used) return true;
     const int k = (int)(group & 1);
     if (any_live)
-        for (int g = 0; g < kGroupSteps; ++g) launch_step(s, a, hi_slice, hi_sys);
+        for (int g = 0; g < kGroupSteps; ++g) launch_step(s, a, hi_slice, hi_sys, any_bfs, small_levels);
     if (hipGetLastError() != hipSuccess) return false;
     mirror_n[k] = hi_sys;
     mirror_group[k] = group;
@@ -499,6 +502,11 @@ Engine *engine_create(int device, const mpcg_options &opt, const KnnModel *model
     }
     e->device = device;
     e->opt = opt;
+    {
+        const char *r = std::getenv("MPCG_BATCH_SMALL_LEVELS");
+        const int v = (r && r[0]) ? std::atoi(r) : 0;
+        if (v >= 1 && v <= 4096) e->small_levels = v;
+    }
     e->model = model;
     e->a = carve(arena, max_sys, (int32_t)max_slices, max_entries);
     e->slots.resize(max_sys);

@@ -50,7 +50,7 @@ enum BfsMode : int32_t {
 constexpr int kSlicesPerBlock = kBlock / 64;
 constexpr int32_t kErrGuard = 64;     // a bounded device loop ran out (union-find)
 constexpr int kSmallBfsCap = 2048;   // frontier kept in LDS by the one-block-per-system kernel
-constexpr int kSmallBfsLevels = 16;  // levels one launch may expand for one system
+constexpr int kSmallBfsLevels = 64;  // default of the levels one launch may expand for one system
 
 struct alignas(256) BSys {
     // set at admission
@@ -120,7 +120,10 @@ void launch_set_eps(hipStream_t s, const BArena &a, int32_t sys, double eps1);
 void launch_fill_slices(hipStream_t s, const BArena &a);   // every slice unowned
 
 // ---- one step over all systems ----
-void launch_step(hipStream_t s, const BArena &a, int32_t hi_slice, int32_t hi_sys);
+// bfs: also advance the 2BFS of the systems whose sweeps are running (the host
+// passes false when no system is between its BFS start and finish)
+// small_levels: most levels the one-block-per-system kernel expands per step
+void launch_step(hipStream_t s, const BArena &a, int32_t hi_slice, int32_t hi_sys, bool bfs, int small_levels);
 
 // ---- 2BFS of one system (host-driven transitions) ----
 void launch_bfs_start(hipStream_t s, const BArena &a, int32_t sys);          // CC + sweep-1 seeds

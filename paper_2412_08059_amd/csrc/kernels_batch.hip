@@ -715,11 +715,11 @@ __global__ void __launch_bounds__(kBlock) k_bfs_level_batch(BArena a)
     }
 }
 
-// One block per system on the small list: up to kSmallBfsLevels levels with
+// One block per system on the small list: up to max_levels levels with
 // the frontier in LDS, each level's result also written to the global queue.
 // Leaves the system as the plan expects: bfs_level = last level expanded,
 // bfs_nxt = the size of the next frontier (queue (bfs_level + 1) & 1).
-__global__ void __launch_bounds__(kBlock) k_bfs_small_batch(BArena a)
+__global__ void __launch_bounds__(kBlock) k_bfs_small_batch(BArena a, int32_t max_levels)
 {
     __shared__ int32_t sq[2][kSmallBfsCap];
     __shared__ int32_t s_cnt;
@@ -734,7 +734,7 @@ __global__ void __launch_bounds__(kBlock) k_bfs_small_batch(BArena a)
         for (int i = threadIdx.x; i < cur; i += kBlock) sq[0][i] = qc[row0 + i];
     }
     int c = 0, nxt = 0;
-    for (int rep = 0; rep < kSmallBfsLevels; ++rep) {
+    for (int rep = 0; rep < max_levels; ++rep) {
         if (threadIdx.x == 0) s_cnt = 0;
         __syncthreads();
         int32_t *qn = (level & 1) ? a.q0 : a.q1;
@@ -757,7 +757,7 @@ __global__ void __launch_bounds__(kBlock) k_bfs_small_batch(BArena a)
         __syncthreads();
         nxt = s_cnt;
         __syncthreads();
-        if (nxt == 0 || nxt > kSmallBfsCap || rep + 1 == kSmallBfsLevels) break;
+        if (nxt == 0 || nxt > kSmallBfsCap || rep + 1 == max_levels) break;
         level += 1;
         cur = nxt;
         c ^= 1;
@@ -769,7 +769,7 @@ __global__ void __launch_bounds__(kBlock) k_bfs_small_batch(BArena a)
     }
 }
 
-void launch_step(hipStream_t s, const BArena &a, int32_t hi_slice, int32_t hi_sys)
+void launch_step(hipStream_t s, const BArena &a, int32_t hi_slice, int32_t hi_sys, bool bfs, int small_levels)
 {
     if (hi_slice <= 0 || hi_sys <= 0) return;
     const int gsl = (hi_slice + kSlicesPerBlock - 1) / kSlicesPerBlock;
@@ -777,9 +777,10 @@ void launch_step(hipStream_t s, const BArena &a, int32_t hi_slice, int32_t hi_sy
     hipLaunchKernelGGL(k_b_scalar1, dim3(hi_sys), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_b_update, dim3(gsl), dim3(kBlock), 0, s, a, hi_slice);
     hipLaunchKernelGGL(k_b_scalar2, dim3(hi_sys), dim3(kBlock), 0, s, a);
+    if (!bfs) return;
     hipLaunchKernelGGL(k_bfs_plan, dim3(1), dim3(1024), 0, s, a, hi_sys);
     hipLaunchKernelGGL(k_bfs_level_batch, dim3(256), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_bfs_small_batch, dim3(hi_sys), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_bfs_small_batch, dim3(hi_sys), dim3(kBlock), 0, s, a, small_levels);
 }
 
 // ------------------------------------------------- 2BFS per system (host) --
@@ -869,17 +870,41 @@ __global__ void k_b_zero_nxt(BArena a, int32_t sys)
     if (threadIdx.x == 0) a.sys[sys].bfs_nxt = 0;
 }
 
-// Per-component farthest vertex of the sweep: key = (dist << 32) | ~v.
+// Per-component farthest vertex of the sweep: key = (dist << 32) | ~v.  A
+// connected system sends every vertex to the same key slot, and same-address
+// atomics serialise: a wave whose reached vertices share one component takes
+// the maximum over its lanes first and issues one atomic.
 __global__ void __launch_bounds__(kBlock) k_b_argmax(BArena a, int32_t sys)
 {
     const BSys &S = a.sys[sys];
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < S.n; i += gridDim.x * kBlock) {
-        const int v = S.row0 + i;
-        const int d = a.dist[v];
-        if (d < 0) continue;
-        const unsigned long long key =
-            ((unsigned long long)(unsigned)d << 32) | (unsigned long long)(0xffffffffu - (unsigned)v);
-        atomicMax(&a.best[a.label[v]], key);
+    const int lane = threadIdx.x & 63;
+    // wave-uniform loop: every lane of a wave walks the same bases
+    for (int base = blockIdx.x * kBlock + (threadIdx.x & ~63); base < S.n; base += gridDim.x * kBlock) {
+        const int i = base + lane;
+        int lab = -1;
+        unsigned long long key = 0ull;
+        if (i < S.n) {
+            const int v = S.row0 + i;
+            const int d = a.dist[v];
+            if (d >= 0) {
+                key = ((unsigned long long)(unsigned)d << 32) | (unsigned long long)(0xffffffffu - (unsigned)v);
+                lab = a.label[v];
+            }
+        }
+        const unsigned long long m = __ballot(lab >= 0);
+        if (m == 0ull) continue;
+        const int l0 = __ffsll((unsigned long long)m) - 1;
+        const int L = __shfl(lab, l0, 64);
+        if (__all(lab < 0 || lab == L)) {
+            unsigned long long kmax = key;   // lanes without a vertex hold 0, below every key
+            for (int off = 32; off > 0; off >>= 1) {
+                const unsigned long long o = __shfl_xor(kmax, off, 64);
+                kmax = kmax > o ? kmax : o;
+            }
+            if (lane == l0) atomicMax(&a.best[L], kmax);
+        } else if (lab >= 0) {
+            atomicMax(&a.best[lab], key);
+        }
     }
 }
 
