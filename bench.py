@@ -218,6 +218,76 @@ def bench_family(args):
     print(json.dumps(out))
 
 
+def bench_diameter(args):
+    """Diameter contrast at n = 1M: a band of half-width 8 (pseudo-diameter
+    ~n/8) and an Erdos-Renyi graph Laplacian of mean degree 16 (diameter ~5).
+    For each: the feature pass, the kNN eps1, Algorithm I at every candidate
+    eps1 and FP64-only CG; I = omega N1 + N2 at omega = 1/3 and at the
+    measured omega, and the regret I(chosen) / I(best) - 1."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2412_08059_amd import DEFAULT_MODEL, DeviceCSR, Solver
+    from paper_2412_08059_amd.model_builder import iteration_omega
+    out_cases = {}
+    for name, gen in (("banded_1M", lambda: W.banded(1_000_000, 8, seed=args.seed)),
+                      ("er_1M", lambda: W.er_laplacian(1_000_000, 16, seed=args.seed))):
+        a = gen()
+        _, b = W.rhs(a, seed=args.seed)
+        sv = Solver(a.n, a.nnz, model=DEFAULT_MODEL)
+        A = DeviceCSR.from_host(a)
+        B = torch.from_numpy(b).cuda()
+        X = torch.empty(a.n, dtype=torch.float64, device="cuda")
+        st, f = sv.features(A, B, 20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, f = sv.features(A, B, 20)
+        torch.cuda.synchronize()
+        t_feat = (time.perf_counter() - t0) * 1e3
+        omega = iteration_omega(sv, A)
+
+        def timed(e1):
+            sv.solve(A, B, e1, 1e-10, x=X)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st, _, S = sv.solve(A, B, e1, 1e-10, x=X)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) * 1e3, st, S
+
+        sweep = []
+        for e in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7):
+            ms, st, S = timed(e)
+            sweep.append({"eps1": e, "ms": round(ms, 2), "n1": S.n1, "n2": S.n2, "status": st})
+        ms_dp, st_dp, S_dp = timed(-1.0)
+        ms_auto, st_auto, S_auto = timed(0.0)
+        n1 = np.array([r["n1"] for r in sweep], float)
+        n2 = np.array([r["n2"] for r in sweep], float)
+        chosen = S_auto.eps1_class - 2
+        res = {}
+        for tag, w in (("third", 1.0 / 3.0), ("measured", omega)):
+            I = w * n1 + n2
+            best = int(np.argmin(I))
+            res[tag] = {"omega": round(w, 4), "I_best": round(float(I[best]), 1), "eps1_best": sweep[best]["eps1"],
+                        "I_chosen": round(float(I[chosen]), 1), "regret": round(float(I[chosen] / I[best] - 1.0), 4),
+                        "I_dp": S_dp.n2}
+        out_cases[name] = {"n": a.n, "m": a.nnz, "pdiam": f.pdiam, "v": round(f.v, 6), "n_components": f.n_components,
+                           "t_feat_ms": round(t_feat, 2), "eps1_chosen": S_auto.eps1_used,
+                           "auto_ms": round(ms_auto, 2), "auto_n1": S_auto.n1, "auto_n2": S_auto.n2,
+                           "fp64_only_ms": round(ms_dp, 2), "speedup_vs_fp64_only": round(ms_dp / ms_auto, 3),
+                           "sweep": sweep, "cost": res}
+        print(f"# diameter {name}: {json.dumps(out_cases[name])}", file=sys.stderr, flush=True)
+        sv.close()
+    reg = [out_cases[c]["cost"]["third"]["regret"] for c in out_cases]
+    out = {"metric": "diameter contrast: kNN eps1 regret I(chosen)/I(best) - 1 at omega = 1/3 (mean of the two)",
+           "value": round(float(np.mean(reg)), 4), "unit": "ratio", "n_gpus": 1, "higher_is_better": False,
+           "data": "synthetic", "dtype": "f32+f64",
+           "config": {"workload": "banded n=1M half-width 8 (a_ij ~ U[-1,0), a_ii = row |sum| + 1e-4) and "
+                                  "Erdos-Renyi n=1M mean degree 16 (L = D - Adj + 1e-3 I); x*~U[-1,1], b=Ax*, "
+                                  "eps2=1e-10"},
+           "cases": out_cases}
+    print(json.dumps(out))
+
+
 def bench_jacobi_iter(args):
     """Algorithm I with the Jacobi method (two-stage Jacobi) against FP64-only
     Jacobi on a paper-family banded matrix (full bandwidth 17, density 0.8 --
@@ -365,11 +435,13 @@ def main():
     ap.add_argument("--kernel-only", action="store_true",
                     help="for PMC runs: a 1 GiB device copy (counter calibration) and 20 launches of "
                          "each CG kernel on the workload, nothing else")
-    ap.add_argument("--workload", choices=("solve", "batch", "serve", "family", "jacobi_iter"), default="solve",
+    ap.add_argument("--workload", choices=("solve", "batch", "serve", "family", "jacobi_iter", "diameter"),
+                    default="solve",
                     help="solve: the 128^3 single-system benchmark (default); batch: many systems in one "
                          "engine; serve: Poisson arrivals with continuous admission; family: the paper's "
                          "kNN experiment on its three matrix families; jacobi_iter: Algorithm I with the Jacobi "
-                         "method")
+                         "method; diameter: the banded / random-graph contrast at n = 1M (features, kNN eps1 "
+                         "against the swept optimum)")
     ap.add_argument("--jac-n", type=int, default=1 << 21)
     ap.add_argument("--family-n", type=int, default=1000)
     ap.add_argument("--family-scale", type=float, default=0.25, help="fraction of the appendix sample sizes")
@@ -395,6 +467,8 @@ def main():
         return bench_family(args)
     if args.workload == "jacobi_iter":
         return bench_jacobi_iter(args)
+    if args.workload == "diameter":
+        return bench_diameter(args)
 
     import numpy as np
     import torch

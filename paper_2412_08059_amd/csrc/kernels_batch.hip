@@ -690,7 +690,7 @@ __global__ void __launch_bounds__(kBlock) k_bfs_level_batch(BArena a)
             lanes = S.lanes;
             level = S.bfs_level;
             const int64_t loc = w - a.act_pre[lo];
-            const int f = (int)(loc / lanes), l = (int)(loc - (int64_t)f * lanes);
+            const int f = (int)(loc >> (__ffs(lanes) - 1)), l = (int)(loc & (lanes - 1));   // lanes: power of two
             const int32_t *qc = (level & 1) ? a.q1 : a.q0;
             u = qc[S.row0 + f];
             if (u >= S.row0 && u < S.row0 + S.n) {
@@ -699,7 +699,7 @@ __global__ void __launch_bounds__(kBlock) k_bfs_level_batch(BArena a)
                 e = a.rowlen[u];
             }
         }
-        int steps = j < e ? (e - j + lanes - 1) / lanes : 0;
+        int steps = j < e ? (e - j + lanes - 1) >> (__ffs(lanes) - 1) : 0;
         steps = wave_max_i32(steps);
         for (int t = 0; t < steps; ++t, j += lanes) {
             if (j < e) {
@@ -727,6 +727,7 @@ __global__ void __launch_bounds__(kBlock) k_bfs_small_batch(BArena a, int32_t ma
     const int s = a.small_sys[blockIdx.x];
     BSys &S = a.sys[s];
     const int lanes = S.lanes, row0 = S.row0;
+    const int lsh = __ffs(lanes) - 1;   // lanes is a power of two
     int level = S.bfs_level;
     int cur = S.bfs_cnt;
     {
@@ -740,7 +741,7 @@ __global__ void __launch_bounds__(kBlock) k_bfs_small_batch(BArena a, int32_t ma
         int32_t *qn = (level & 1) ? a.q0 : a.q1;
         const int work = cur * lanes;
         for (int w = threadIdx.x; w < work; w += kBlock) {
-            const int f = w / lanes, l = w - f * lanes;
+            const int f = w >> lsh, l = w & (lanes - 1);
             const int u = sq[c][f];
             const int64_t base = S.entry0 + a.slice_off[u >> 6] + (u & 63);
             const int e = a.rowlen[u];

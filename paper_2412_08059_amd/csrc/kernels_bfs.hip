@@ -149,6 +149,7 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
     __shared__ int32_t s_w0, s_nw, s_new0, s_rows, s_slide, s_pmin, s_pmax, s_fit, s_a;
     __shared__ long long s_vis;
     const int tid = threadIdx.x;
+    const int lsh = __ffs(lanes) - 1;   // lanes is a power of two
     if (tid == 0) {
         s_go = 0;
         s_nw = 0;   // empty window: everything takes the global path
@@ -219,7 +220,7 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
                 }
             };
             for (int w = tid; w < work; w += kBfsSmallThreads) {
-                const int f = w / lanes, l = w - f * lanes;
+                const int f = w >> lsh, l = w & (lanes - 1);
                 const QEnt u = sq[c][f];
                 if (u.b >= e0 && u.e <= e1) {   // the row's columns are in the window
                     for (int j = u.b + l; j < u.e; j += lanes) visit(w_col[j - e0]);
@@ -346,13 +347,14 @@ k_bfs_level(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
 {
     __shared__ int s_cnt[kBlock / 64], s_base, s_steps, s_min;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lsh = __ffs(lanes) - 1;   // lanes is a power of two
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     const int64_t span = stride * kBfsItems;
     const int64_t wbase0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63);
     QEnt pa[kBfsItems], pb[kBfsItems];   // first batch from queue 0 and queue 1
 #pragma unroll
     for (int i = 0; i < kBfsItems; ++i) {
-        const int64_t f = (wbase0 + i * stride + lane) / lanes;
+        const int64_t f = (wbase0 + i * stride + lane) >> lsh;
         pa[i] = QEnt{0, 0};
         pb[i] = QEnt{0, 0};
         if (f < n) {
@@ -391,14 +393,14 @@ k_bfs_level(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
         for (int i = 0; i < kBfsItems; ++i) {
             const int64_t w = wbase + i * stride + lane;
             QEnt u{0, 0};
-            if (w < items) u = first ? ((L & 1) ? pb[i] : pa[i]) : qc[(int)(w / lanes)];
-            j[i] = u.b + (int)(w % lanes);
+            if (w < items) u = first ? ((L & 1) ? pb[i] : pa[i]) : qc[(int)(w >> lsh)];
+            j[i] = u.b + (int)(w & (lanes - 1));
             e[i] = w < items ? u.e : 0;
         }
         int steps = 0;
 #pragma unroll
         for (int i = 0; i < kBfsItems; ++i) {
-            const int si = j[i] < e[i] ? (e[i] - j[i] + lanes - 1) / lanes : 0;
+            const int si = j[i] < e[i] ? (e[i] - j[i] + lanes - 1) >> lsh : 0;
             steps = steps > si ? steps : si;
         }
         steps = wave_max_i(steps);
@@ -519,6 +521,7 @@ k_bfs_persist(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, i
         return;
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lsh = __ffs(lanes) - 1;   // lanes is a power of two
     const unsigned long long lt = (1ull << lane) - 1ull;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     const int64_t span = stride * kBfsItems;
@@ -541,14 +544,14 @@ k_bfs_persist(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, i
 #pragma unroll
             for (int i = 0; i < kBfsItems; ++i) {
                 const int64_t w = wbase + i * stride + lane;
-                const QEnt u = w < items ? aload_q(&qc[(int)(w / lanes)]) : QEnt{0, 0};
-                j[i] = u.b + (int)(w % lanes);
+                const QEnt u = w < items ? aload_q(&qc[(int)(w >> lsh)]) : QEnt{0, 0};
+                j[i] = u.b + (int)(w & (lanes - 1));
                 e[i] = w < items ? u.e : 0;
             }
             int steps = 0;
 #pragma unroll
             for (int i = 0; i < kBfsItems; ++i) {
-                const int si = j[i] < e[i] ? (e[i] - j[i] + lanes - 1) / lanes : 0;
+                const int si = j[i] < e[i] ? (e[i] - j[i] + lanes - 1) >> lsh : 0;
                 steps = steps > si ? steps : si;
             }
             steps = wave_max_i(steps);
