@@ -145,19 +145,21 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
 {
     __shared__ QEnt sq[2][kBfsSmallCap];
     __shared__ int32_t w_rp[kWinRows + 1], w_dist[kWinRows], w_col[kWinEntries];
-    __shared__ int32_t s_cnt, s_min, s_max, s_cur, s_level, s_go, s_curmin, s_fin;
-    __shared__ int32_t s_w0, s_nw, s_new0, s_rows, s_slide, s_pmin, s_pmax, s_fit, s_a;
+    // next-frontier size, smallest and largest vertex, one slot per level
+    // modulo 3: a slot is cleared two levels before it is used again, after
+    // a barrier that every thread passed once it had read the slot
+    __shared__ int32_t s_cnt[3], s_min[3], s_max[3];
+    __shared__ int32_t s_cur, s_level, s_go, s_curmin, s_fit, s_a;
     __shared__ long long s_vis;
     const int tid = threadIdx.x;
     const int lsh = __ffs(lanes) - 1;   // lanes is a power of two
     if (tid == 0) {
         s_go = 0;
-        s_nw = 0;   // empty window: everything takes the global path
-        s_w0 = 0;
-        s_pmin = -1;
-        s_pmax = -1;
-        s_fin = 0;
-        s_slide = 0;
+        for (int i = 0; i < 3; ++i) {
+            s_cnt[i] = 0;
+            s_min[i] = kIntMax;
+            s_max[i] = -1;
+        }
         st->bfs_bar = 0u;   // the persistent kernel of this round starts its barrier count at 0
         if (!st->bfs_done) {
             const int L = st->bfs_lv[k & 1];
@@ -177,96 +179,89 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
     }
     __syncthreads();
     if (!s_go) return;
+    // the level state is block-uniform and kept in registers by every thread
+    int cur = s_cur, level = s_level, curmin = s_curmin;
+    long long vis = s_vis;
     {
-        const QEnt *qc = (s_level & 1) ? q1 : q0;
-        for (int i = tid; i < s_cur; i += kBfsSmallThreads) sq[0][i] = qc[i];
+        const QEnt *qc = (level & 1) ? q1 : q0;
+        for (int i = tid; i < cur; i += kBfsSmallThreads) sq[0][i] = qc[i];
     }
-    int c = 0;
+    int c = 0, p = 0;
+    int w0 = 0, nw = 0, e0 = 0, e1 = 0;   // empty window: everything takes the global path
+    int pmax = -1;
     bool finished = false;
+    __syncthreads();
     // every iteration expands one level; at most n levels exist
     for (;;) {
-        __syncthreads();
-        {
-            // ---- one level with the whole block
-            if (tid == 0) { s_cnt = 0; s_min = kIntMax; s_max = -1; }
-            __syncthreads();
-            const int cur = s_cur, level = s_level;
-            const int w0 = s_w0, nw = s_nw;
-            const int e0 = nw > 0 ? w_rp[0] : 0, e1 = nw > 0 ? w_rp[nw] : 0;
-            QEnt *qn = (level & 1) ? q0 : q1;
-            const int work = cur * lanes;
-            // claims v for the next level; the window part touches LDS only, and
-            // the next frontier is kept in LDS (global queue only past its size)
-            auto visit = [&](int v) {
-                if ((unsigned)v >= (unsigned)n) return;
-                const int wv = v - w0;
-                bool got;
-                QEnt nv;
-                if ((unsigned)wv < (unsigned)nw) {
-                    if (w_dist[wv] >= 0) return;   // a self-loop is visited already
-                    got = atomicCAS(&w_dist[wv], -1, level + 1) == -1;
-                    nv = QEnt{w_rp[wv], w_rp[wv + 1]};
-                } else {
-                    if (dist[v] >= 0) return;
-                    nv = QEnt{rp[v], rp[v + 1]};
-                    got = atomicCAS(&dist[v], -1, level + 1) == -1;
-                }
-                if (got) {
-                    const int pos = atomicAdd(&s_cnt, 1);
-                    if (pos < kBfsSmallCap) sq[c ^ 1][pos] = nv;
-                    else qn[pos] = nv;
-                    atomicMin(&s_min, v);
-                    atomicMax(&s_max, v);
-                }
-            };
-            for (int w = tid; w < work; w += kBfsSmallThreads) {
-                const int f = w >> lsh, l = w & (lanes - 1);
-                const QEnt u = sq[c][f];
-                if (u.b >= e0 && u.e <= e1) {   // the row's columns are in the window
-                    for (int j = u.b + l; j < u.e; j += lanes) visit(w_col[j - e0]);
-                } else {
-                    for (int j = u.b + l; j < u.e; j += lanes) visit(col[j]);
-                }
-            }
-            __syncthreads();
-            const int nxt = s_cnt;
-            if (tid == 0) {
-                s_vis += cur;
-                if (nxt == 0) {
-                    s_fin = 1;
-                } else {
-                    s_level = level + 1;
-                    s_cur = nxt;
-                    s_curmin = s_min;
-                    const WinPlan wp = nxt <= small_max ? plan_window(s_min, s_max, s_pmax, band, n, s_w0, s_nw)
-                                                        : WinPlan{0, 0, 0};
-                    s_slide = wp.mode;
-                    s_new0 = wp.base;
-                    s_rows = wp.rows;
-                    s_fit = 0;
-                    s_a = wp.rows;
-                    s_pmin = s_min;
-                    s_pmax = s_max;
-                }
-            }
-            __syncthreads();
-            if (s_fin) {
-                finished = true;
-                break;
-            }
-            c ^= 1;
+        const int pn = p == 2 ? 0 : p + 1;
+        if (tid == 0) {   // the slot of the next level, last read two levels ago
+            s_cnt[pn] = 0;
+            s_min[pn] = kIntMax;
+            s_max[pn] = -1;
         }
-        if (s_cur > small_max) {   // hand over: the multi-block kernel reads the global queue
-            QEnt *qc = (s_level & 1) ? q1 : q0;
-            for (int i = tid; i < s_cur && i < kBfsSmallCap; i += kBfsSmallThreads) qc[i] = sq[c][i];
+        QEnt *qn = (level & 1) ? q0 : q1;
+        const int work = cur * lanes;
+        // claims v for the next level; the window part touches LDS only, and
+        // the next frontier is kept in LDS (global queue only past its size)
+        auto visit = [&](int v) {
+            if ((unsigned)v >= (unsigned)n) return;
+            const int wv = v - w0;
+            bool got;
+            QEnt nv;
+            if ((unsigned)wv < (unsigned)nw) {
+                if (w_dist[wv] >= 0) return;   // a self-loop is visited already
+                nv = QEnt{w_rp[wv], w_rp[wv + 1]};
+                got = atomicCAS(&w_dist[wv], -1, level + 1) == -1;
+            } else {
+                if (dist[v] >= 0) return;
+                nv = QEnt{rp[v], rp[v + 1]};
+                got = atomicCAS(&dist[v], -1, level + 1) == -1;
+            }
+            if (got) {
+                const int pos = atomicAdd(&s_cnt[p], 1);
+                if (pos < kBfsSmallCap) sq[c ^ 1][pos] = nv;
+                else qn[pos] = nv;
+                atomicMin(&s_min[p], v);
+                atomicMax(&s_max[p], v);
+            }
+        };
+        for (int w = tid; w < work; w += kBfsSmallThreads) {
+            const int f = w >> lsh, l = w & (lanes - 1);
+            const QEnt u = sq[c][f];
+            if (u.b >= e0 && u.e <= e1) {   // the row's columns are in the window
+                for (int j = u.b + l; j < u.e; j += lanes) visit(w_col[j - e0]);
+            } else {
+                for (int j = u.b + l; j < u.e; j += lanes) visit(col[j]);
+            }
+        }
+        __syncthreads();
+        const int nxt = s_cnt[p], mn = s_min[p], mx = s_max[p];
+        vis += cur;
+        if (nxt == 0) {
+            finished = true;
             break;
         }
-        if (s_slide) {
+        ++level;
+        cur = nxt;
+        curmin = mn;
+        c ^= 1;
+        p = pn;
+        if (cur > small_max) {   // hand over: the multi-block kernel reads the global queue
+            QEnt *qc = (level & 1) ? q1 : q0;
+            for (int i = tid; i < cur && i < kBfsSmallCap; i += kBfsSmallThreads) qc[i] = sq[c][i];
+            break;
+        }
+        const WinPlan wp = plan_window(mn, mx, pmax, band, n, w0, nw);
+        pmax = mx;
+        if (wp.mode) {
             // write the old window back, then fill the new one
-            const int w0 = s_w0, nw = s_nw;
             for (int i = tid; i < nw; i += kBfsSmallThreads)
                 if (w_dist[i] >= 0) astore_i32(&dist[w0 + i], w_dist[i]);
-            const int mode = s_slide, nb0 = s_new0, rows = s_rows;
+            if (tid == 0) {
+                s_fit = 0;
+                s_a = wp.rows;
+            }
+            const int mode = wp.mode, nb0 = wp.base, rows = wp.rows;
             __syncthreads();
             for (int i = tid; i <= rows; i += kBfsSmallThreads) w_rp[i] = rp[nb0 + i];
             __syncthreads();
@@ -292,34 +287,30 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
                 if (i1 <= fit) w_rp[i1] = t1;
                 __syncthreads();
             }
-            const int base = nb0 + a;
-            const int b0 = w_rp[0], ne = w_rp[fit] - b0;
-            for (int i = tid; i < ne; i += kBfsSmallThreads) w_col[i] = col[b0 + i];
-            for (int i = tid; i < fit; i += kBfsSmallThreads) w_dist[i] = atomic_load_i32(&dist[base + i]);
+            w0 = nb0 + a;
+            nw = fit;
+            e0 = w_rp[0];
+            e1 = w_rp[fit];
+            for (int i = tid; i < e1 - e0; i += kBfsSmallThreads) w_col[i] = col[e0 + i];
+            for (int i = tid; i < fit; i += kBfsSmallThreads) w_dist[i] = atomic_load_i32(&dist[w0 + i]);
             __syncthreads();
-            if (tid == 0) {
-                s_w0 = base;
-                s_nw = fit;
-                s_slide = 0;
-            }
         }
     }
     // the window's distances go back to global memory before anyone reads them
-    for (int i = tid; i < s_nw; i += kBfsSmallThreads)
-        if (w_dist[i] >= 0) astore_i32(&dist[s_w0 + i], w_dist[i]);
+    for (int i = tid; i < nw; i += kBfsSmallThreads)
+        if (w_dist[i] >= 0) astore_i32(&dist[w0 + i], w_dist[i]);
     if (tid == 0) {
-        const int L = s_level;
-        st->bfs_visited = s_vis;
+        st->bfs_visited = vis;
         if (finished) {
             st->bfs_done = 1;
-            st->bfs_ecc = L;
-            st->bfs_far = s_curmin;
+            st->bfs_ecc = level;
+            st->bfs_far = curmin;
         } else {
-            st->bfs_cnt[L & 3] = s_cur;
-            st->bfs_min[L & 3] = s_curmin;
-            st->bfs_cnt[(L + 1) & 3] = 0;
-            st->bfs_min[(L + 1) & 3] = kIntMax;
-            st->bfs_lv[(k + 1) & 1] = L;
+            st->bfs_cnt[level & 3] = cur;
+            st->bfs_min[level & 3] = curmin;
+            st->bfs_cnt[(level + 1) & 3] = 0;
+            st->bfs_min[(level + 1) & 3] = kIntMax;
+            st->bfs_lv[(k + 1) & 1] = level;
         }
     }
 }
