@@ -599,6 +599,13 @@ void launch_spmv_plain(hipStream_t s, const SpmvShape &sh, const int32_t *rp, co
 // r.r -- or, with Jacobi (PC), z = r / diag(A) and partials of r.z (slot b)
 // and r.r (slot nup + b).  x += alpha d is left to the next product, which
 // reads d anyway.
+// The block's first kUpdPre chunks of r and q (and of diag(A)) depend
+// neither on the stop test nor on delta, so they are loaded before both: the
+// latencies of the stop flag, of the product's partials and of the vectors
+// overlap instead of following each other.  Elements are processed in the
+// same order as without the prefetch.
+constexpr int kUpdPre = 2;
+
 template <typename T, bool PC>
 __global__ void __launch_bounds__(kBlock)
 k_cg_update(int32_t n, T *__restrict__ r, const T *__restrict__ q, const double *sp, int nsp, double *up,
@@ -606,11 +613,41 @@ k_cg_update(int32_t n, T *__restrict__ r, const T *__restrict__ q, const double 
 {
     __shared__ double sm[kBlock / 64 + 1];
     __shared__ int s_skip;
+    const int64_t nchunk = ((int64_t)n + kVecTile - 1) / kVecTile;
+    T rv[kUpdPre][kVecPerThread], qv[kUpdPre][kVecPerThread], dv[kUpdPre][kVecPerThread];
+#pragma unroll
+    for (int p = 0; p < kUpdPre; ++p) {
+#pragma unroll
+        for (int j = 0; j < kVecPerThread; ++j) {
+            const int64_t i = ((int64_t)blockIdx.x + (int64_t)p * gridDim.x) * kVecTile + j * kBlock + threadIdx.x;
+            rv[p][j] = T(0);
+            qv[p][j] = T(0);
+            dv[p][j] = T(1);
+            if (i < n) {
+                rv[p][j] = r[i];
+                qv[p][j] = q[i];
+                if (PC) dv[p][j] = dg[i];
+            }
+        }
+    }
     if (threadIdx.x == 0) s_skip = st->stop_it <= it;
+    const double g = st->gam[it & 1];
+    // delta: the product's partials in a fixed order (the same bits in every block)
+    double acc = 0.0;
+    {
+        int i = threadIdx.x;
+        for (; i + 3 * kBlock < nsp; i += 4 * kBlock) {
+            const double p0 = sp[i], p1 = sp[i + kBlock], p2 = sp[i + 2 * kBlock], p3 = sp[i + 3 * kBlock];
+            acc += p0;
+            acc += p1;
+            acc += p2;
+            acc += p3;
+        }
+        for (; i < nsp; i += kBlock) acc += sp[i];
+    }
     __syncthreads();
     if (s_skip) return;
-    const double delta = reduce_partials(sp, nsp, 1, 0, sm);
-    const double g = st->gam[it & 1];
+    const double delta = block_sum_all(acc, sm);
     if (!isfinite(delta) || !(delta > 0.0)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             st->delta = delta;
@@ -629,21 +666,29 @@ k_cg_update(int32_t n, T *__restrict__ r, const T *__restrict__ q, const double 
         st->alph[it & 1] = (double)alpha;
     }
     double s = 0.0, s2 = 0.0;
-    const int64_t nchunk = ((int64_t)n + kVecTile - 1) / kVecTile;
-    for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
+    auto elem = [&](int64_t i, T r0, T q0, T d0) {
+        const T rn = fmaT<T>(-alpha, q0, r0);
+        r[i] = rn;
+        s2 = fma((double)rn, (double)rn, s2);
+        if (PC) {
+            const T zv = rn / d0;
+            z[i] = zv;
+            s = fma((double)rn, (double)zv, s);
+        }
+    };
+#pragma unroll
+    for (int p = 0; p < kUpdPre; ++p) {
+#pragma unroll
+        for (int j = 0; j < kVecPerThread; ++j) {
+            const int64_t i = ((int64_t)blockIdx.x + (int64_t)p * gridDim.x) * kVecTile + j * kBlock + threadIdx.x;
+            if (i < n) elem(i, rv[p][j], qv[p][j], dv[p][j]);
+        }
+    }
+    for (int64_t c = blockIdx.x + (int64_t)kUpdPre * gridDim.x; c < nchunk; c += gridDim.x) {
 #pragma unroll
         for (int j = 0; j < kVecPerThread; ++j) {
             const int64_t i = c * kVecTile + j * kBlock + threadIdx.x;
-            if (i < n) {
-                const T rv = fmaT<T>(-alpha, q[i], r[i]);
-                r[i] = rv;
-                s2 = fma((double)rv, (double)rv, s2);
-                if (PC) {
-                    const T zv = rv / dg[i];
-                    z[i] = zv;
-                    s = fma((double)rv, (double)zv, s);
-                }
-            }
+            if (i < n) elem(i, r[i], q[i], PC ? dg[i] : T(1));
         }
     }
     if (PC) {

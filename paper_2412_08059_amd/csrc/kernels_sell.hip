@@ -256,7 +256,12 @@ struct SellArgs {
 };
 
 // B = entries of a row whose loads are issued together (4 or 8)
-template <int MODE, typename T, typename IDX, int B>
+// BF: every lane loads all B entries of a batch (no guard per entry), so the
+// batch's index and value loads are issued together and its gathers too; an
+// entry past the row's length is the slice's padding (past W, its last
+// column; both inside the slice), its gather reads the row itself and its
+// product is skipped.  Without BF each entry's loads sit behind its own guard.
+template <int MODE, typename T, typename IDX, int B, bool BF>
 __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
 {
     constexpr int NV = (MODE == kSellRestart) ? 3 : 1;
@@ -343,24 +348,42 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
         const int W = (int)((a.off[sl + 1] - base) >> 6);
         const IDX *cp = scol + base + lane;
         const T *vp = a.sval + base + lane;
+        const int safe = has ? row : a.n - 1;
         T acc = T(0);
         for (int k0 = 0; k0 < W; k0 += B) {
             int c[B];
             T v[B], g[B];
+            if (BF) {
 #pragma unroll
-            for (int j = 0; j < B; ++j) {
-                if (k0 + j < len) {
-                    const IDX ci = cp[(int64_t)(k0 + j) * 64];
-                    c[j] = (sizeof(IDX) == 2) ? row + (int)ci : (int)ci;
-                    v[j] = vp[(int64_t)(k0 + j) * 64];
+                for (int j = 0; j < B; ++j) {
+                    const int kk = k0 + j < W ? k0 + j : W - 1;
+                    const IDX ci = cp[(int64_t)kk * 64];
+                    v[j] = vp[(int64_t)kk * 64];
+                    const int cc = (sizeof(IDX) == 2) ? row + (int)ci : (int)ci;
+                    c[j] = k0 + j < len ? cc : safe;
                 }
-            }
 #pragma unroll
-            for (int j = 0; j < B; ++j) {
-                if (k0 + j < len) {
+                for (int j = 0; j < B; ++j) {
                     if (MODE == kSellCg) g[j] = fma_t<T>(beta, dold[c[j]], a.r[c[j]]);
                     else if (MODE == kSellPlain) g[j] = a.xin[c[j]];
                     else g[j] = a.x32 ? (T)a.x32[c[j]] : (T)a.x64in[c[j]];
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < B; ++j) {
+                    if (k0 + j < len) {
+                        const IDX ci = cp[(int64_t)(k0 + j) * 64];
+                        c[j] = (sizeof(IDX) == 2) ? row + (int)ci : (int)ci;
+                        v[j] = vp[(int64_t)(k0 + j) * 64];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < B; ++j) {
+                    if (k0 + j < len) {
+                        if (MODE == kSellCg) g[j] = fma_t<T>(beta, dold[c[j]], a.r[c[j]]);
+                        else if (MODE == kSellPlain) g[j] = a.xin[c[j]];
+                        else g[j] = a.x32 ? (T)a.x32[c[j]] : (T)a.x64in[c[j]];
+                    }
                 }
             }
 #pragma unroll
@@ -404,20 +427,27 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
     }
 }
 
-template <int MODE, typename T>
-static void sell_launch(hipStream_t s, const SellMat &m, const SellArgs<T> &a)
+template <int MODE, typename T, bool BF>
+static void sell_launch_bf(hipStream_t s, const SellMat &m, const SellArgs<T> &a)
 {
     if (m.batch == 8) {
         if (m.idx16)
-            hipLaunchKernelGGL((k_sell<MODE, T, int16_t, 8>), dim3(m.grid), dim3(kBlock), 0, s, a);
+            hipLaunchKernelGGL((k_sell<MODE, T, int16_t, 8, BF>), dim3(m.grid), dim3(kBlock), 0, s, a);
         else
-            hipLaunchKernelGGL((k_sell<MODE, T, int32_t, 8>), dim3(m.grid), dim3(kBlock), 0, s, a);
+            hipLaunchKernelGGL((k_sell<MODE, T, int32_t, 8, BF>), dim3(m.grid), dim3(kBlock), 0, s, a);
     } else {
         if (m.idx16)
-            hipLaunchKernelGGL((k_sell<MODE, T, int16_t, 4>), dim3(m.grid), dim3(kBlock), 0, s, a);
+            hipLaunchKernelGGL((k_sell<MODE, T, int16_t, 4, BF>), dim3(m.grid), dim3(kBlock), 0, s, a);
         else
-            hipLaunchKernelGGL((k_sell<MODE, T, int32_t, 4>), dim3(m.grid), dim3(kBlock), 0, s, a);
+            hipLaunchKernelGGL((k_sell<MODE, T, int32_t, 4, BF>), dim3(m.grid), dim3(kBlock), 0, s, a);
     }
+}
+
+template <int MODE, typename T>
+static void sell_launch(hipStream_t s, const SellMat &m, const SellArgs<T> &a)
+{
+    if ((m.bf_mask >> (sizeof(T) == 8 ? 1 : 0)) & 1) sell_launch_bf<MODE, T, true>(s, m, a);
+    else sell_launch_bf<MODE, T, false>(s, m, a);
 }
 
 template <typename T>

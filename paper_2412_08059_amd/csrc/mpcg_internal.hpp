@@ -120,6 +120,7 @@ struct SellMat {
     const int64_t *off;
     int32_t n, nslices, grid, idx16;
     int32_t batch;   // row entries whose loads are issued together: 4 or 8
+    int32_t bf_mask; // whole-batch loads without a guard per entry: bit 0 FP32 kernels, bit 1 FP64
 };
 
 Layout plan_layout(int64_t n, int64_t nnz);
