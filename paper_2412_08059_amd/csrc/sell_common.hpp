@@ -35,8 +35,18 @@ __device__ inline double sell_block_sum(double v, double *sm)
 
 __device__ inline double sell_reduce_partials(const double *p, int cnt, double *sm)
 {
+    // four loads in flight per thread, added in index order (the same bits
+    // as one at a time)
     double acc = 0.0;
-    for (int i = threadIdx.x; i < cnt; i += kBlock) acc += p[i];
+    int i = threadIdx.x;
+    for (; i + 3 * kBlock < cnt; i += 4 * kBlock) {
+        const double p0 = p[i], p1 = p[i + kBlock], p2 = p[i + 2 * kBlock], p3 = p[i + 3 * kBlock];
+        acc += p0;
+        acc += p1;
+        acc += p2;
+        acc += p3;
+    }
+    for (; i < cnt; i += kBlock) acc += p[i];
     double s = sell_block_sum(acc, sm);
     if (threadIdx.x == 0) sm[kBlock / 64] = s;
     __syncthreads();
