@@ -377,15 +377,30 @@ __device__ inline double cg_product(const BArena &a, const BSys &S, const T *val
     for (int k0 = 0; k0 < W; k0 += kLoadBatch) {
         int c[kLoadBatch];
         T v[kLoadBatch], g[kLoadBatch];
+        if (sizeof(T) == 4) {
+            // FP32: every lane loads the whole batch (the padding entries are
+            // zero entries on the lane's own row; past W the last column is
+            // read again), so the batch's loads and its gathers are issued
+            // together; only the products past the row's length are skipped
 #pragma unroll
-        for (int t = 0; t < kLoadBatch; ++t)
-            if (k0 + t < len) {
-                c[t] = a.col[base + (int64_t)(k0 + t) * 64];
-                v[t] = val[base + (int64_t)(k0 + t) * 64];
+            for (int t = 0; t < kLoadBatch; ++t) {
+                const int kk = k0 + t < W ? k0 + t : W - 1;
+                c[t] = a.col[base + (int64_t)kk * 64];
+                v[t] = val[base + (int64_t)kk * 64];
             }
 #pragma unroll
-        for (int t = 0; t < kLoadBatch; ++t)
-            if (k0 + t < len) g[t] = first ? r[c[t]] : fma_b<T>(beta, dold[c[t]], r[c[t]]);
+            for (int t = 0; t < kLoadBatch; ++t) g[t] = first ? r[c[t]] : fma_b<T>(beta, dold[c[t]], r[c[t]]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < kLoadBatch; ++t)
+                if (k0 + t < len) {
+                    c[t] = a.col[base + (int64_t)(k0 + t) * 64];
+                    v[t] = val[base + (int64_t)(k0 + t) * 64];
+                }
+#pragma unroll
+            for (int t = 0; t < kLoadBatch; ++t)
+                if (k0 + t < len) g[t] = first ? r[c[t]] : fma_b<T>(beta, dold[c[t]], r[c[t]]);
+        }
 #pragma unroll
         for (int t = 0; t < kLoadBatch; ++t)
             if (k0 + t < len) acc = fma_b<T>(v[t], g[t], acc);

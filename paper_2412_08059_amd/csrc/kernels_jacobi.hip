@@ -94,22 +94,39 @@ __global__ void __launch_bounds__(kBlock) k_jac_sell(JacArgs<T> a)
         const int W = (int)((a.off[sl + 1] - base) >> 6);
         const IDX *cp = scol + base + lane;
         const T *vp = a.sval + base + lane;
+        const int safe = has ? row : a.n - 1;
         T acc = T(0);
         for (int k0 = 0; k0 < W; k0 += B) {
             int c[B];
             T v[B], g[B];
+            if (sizeof(T) == 4) {
+                // FP32: every lane loads the whole batch (an entry past the
+                // row's length is the slice's padding, past W its last column,
+                // both inside the slice; it gathers the row itself), so the
+                // batch's loads and gathers are issued together
 #pragma unroll
-            for (int j = 0; j < B; ++j) {
-                c[j] = row;
-                if (k0 + j < len) {
-                    const IDX ci = cp[(int64_t)(k0 + j) * 64];
-                    c[j] = (sizeof(IDX) == 2) ? row + (int)ci : (int)ci;
-                    v[j] = vp[(int64_t)(k0 + j) * 64];
+                for (int j = 0; j < B; ++j) {
+                    const int kk = k0 + j < W ? k0 + j : W - 1;
+                    const IDX ci = cp[(int64_t)kk * 64];
+                    v[j] = vp[(int64_t)kk * 64];
+                    const int cc = (sizeof(IDX) == 2) ? row + (int)ci : (int)ci;
+                    c[j] = k0 + j < len ? cc : row;
+                    g[j] = x[k0 + j < len ? cc : safe];
                 }
-            }
+            } else {
 #pragma unroll
-            for (int j = 0; j < B; ++j)
-                if (k0 + j < len && c[j] != row) g[j] = x[c[j]];
+                for (int j = 0; j < B; ++j) {
+                    c[j] = row;
+                    if (k0 + j < len) {
+                        const IDX ci = cp[(int64_t)(k0 + j) * 64];
+                        c[j] = (sizeof(IDX) == 2) ? row + (int)ci : (int)ci;
+                        v[j] = vp[(int64_t)(k0 + j) * 64];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < B; ++j)
+                    if (k0 + j < len && c[j] != row) g[j] = x[c[j]];
+            }
 #pragma unroll
             for (int j = 0; j < B; ++j)
                 if (k0 + j < len && c[j] != row) acc = fma_t<T>(v[j], g[j], acc);
