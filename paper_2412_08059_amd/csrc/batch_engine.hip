@@ -7,6 +7,13 @@
 // runs, so the GPU never waits for the host.  Everything the thread decides
 // from a copy is enqueued behind the running group; a slot's later copies are
 // ignored until they reflect that action (the slot's `guard`).
+//
+// The 2BFS of the systems that choose eps1 runs on a second stream, beside
+// the steps and at its own pace: whenever that stream is idle the thread
+// reads its last state copy (BFS fields only), enqueues the transitions it
+// calls for (sweep start, next sweep, finish, cancel) and a few BFS rounds,
+// then another copy.  A system holds after its k0 FP32 iterations until its
+// features are in, so its arithmetic does not depend on that pace.
 
 #include "batch_internal.hpp"
 #include "knn.hpp"
@@ -29,6 +36,7 @@ namespace batch {
 namespace {
 
 constexpr int kGroupSteps = 8;
+constexpr int kBfsRoundsPerPump = 4;   // BFS rounds enqueued per pass of the BFS stream
 constexpr double kEpsClass[8] = {0, 0, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7};
 
 double now_ms()
@@ -91,7 +99,10 @@ struct Slot {
     int64_t entry0 = -1, padded = 0;
     int adm = 0;            // 1: rows and scan enqueued, 2: live
     bool autoe = false;
-    int feat = 0;           // 0 not started, 1 sweep 1, 2 sweep 2, 3 finishing, 4 done (or none)
+    int feat = 0;           // 0 not started, 1 sweep 1, 2 sweep 2, 3 finishing, 4 done (or none), 5 cancelling
+    bool want_start = false;   // admitted: start the 2BFS on the BFS stream
+    bool want_bfs_cancel = false;
+    bool bfs_ready = false;    // pdiam, t, u, ncomp are in f
     int64_t guard = 0;      // ignore state copies of groups before this one
     bool retiring = false;
     int64_t retire_group = 0;
@@ -115,6 +126,12 @@ struct Engine {
     int64_t mirror_group[2] = {-1, -1};
     BSys *stage = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
+    // BFS stream: its own state copy (read for the BFS fields only)
+    hipStream_t sb = nullptr;
+    hipEvent_t evb = nullptr;
+    BSys *bmirror = nullptr;
+    int32_t bmirror_n = 0;
+    bool b_inflight = false;
     std::vector<Slot> slots;
     std::vector<BSys> finals;           // state copy of a slot at completion
     RangeAlloc slices, entries;
@@ -141,6 +158,8 @@ struct Engine {
     void recompute_hi();
     void admit();
     void process(const BSys *m, int32_t cnt, int64_t gi);
+    bool bfs_pump();
+    bool process_bfs(const BSys *m, int32_t cnt);
     void fail_all(int status);
 };
 
@@ -323,41 +342,17 @@ void Engine::process(const BSys *m, int32_t cnt, int64_t gi)
         if (sl.cancel) {
             launch_cancel(s, a, i);
             sl.cancel = false;
-            sl.feat = 4;
+            if (sl.autoe && sl.feat >= 1 && sl.feat <= 3) sl.want_bfs_cancel = true;   // feat 5, then 4
+            else if (sl.feat != 5) sl.feat = 4;   // 5: a BFS cancel is already under way
+            sl.want_start = false;
             sl.guard = group + 1;
             continue;
         }
         if (sl.autoe && sl.feat < 4) {
-            if (M.err & kErrGuard) {
-                launch_cancel(s, a, i);
-                sl.feat = 4;
-                sl.guard = group + 1;
-                continue;
-            }
-            if (sl.feat == 0) {
-                if (M.err || M.mode == kDone) {
-                    sl.feat = 4;   // malformed input or nothing to solve: no features
-                } else {
-                    launch_bfs_start(s, a, i);
-                    sl.feat = 1;
-                    sl.guard = group + 1;
-                    continue;
-                }
-            } else if (sl.feat == 1 && M.bfs_mode == kBfsSwept) {
-                launch_bfs_next_sweep(s, a, i);
-                sl.feat = 2;
-                sl.guard = group + 1;
-                continue;
-            } else if (sl.feat == 2 && M.bfs_mode == kBfsSwept) {
-                launch_bfs_finish(s, a, i);
-                sl.feat = 3;
-                sl.guard = group + 1;
-                continue;
-            } else if (sl.feat == 3 && M.bfs_mode == kBfsDone && !(M.mode == kCg32 && M.k0_used == 0)) {
-                sl.f.pdiam = M.pdiam;
-                sl.f.bfs_t = M.bfs_t;
-                sl.f.bfs_u = M.bfs_u;
-                sl.f.n_components = M.ncomp;
+            if (sl.feat == 0 && !sl.want_start) {
+                if (M.err || M.mode == kDone) sl.feat = 4;   // malformed input or nothing to solve: no features
+                else sl.want_start = true;
+            } else if (sl.feat == 3 && sl.bfs_ready && !(M.mode == kCg32 && M.k0_used == 0)) {
                 sl.f.k0_used = M.k0_used;
                 double sum = 0.0;
                 for (int j = 0; j < M.k0_used && j < kK0Max; ++j) sum = sum + M.ratios[j];
@@ -393,6 +388,89 @@ void Engine::process(const BSys *m, int32_t cnt, int64_t gi)
     }
 }
 
+// BFS transitions from the BFS stream's state copy (that stream is idle).
+bool Engine::process_bfs(const BSys *m, int32_t cnt)
+{
+    bool enq = false;
+    for (int32_t i = 0; i < (int32_t)slots.size() && i < cnt; ++i) {
+        Slot &sl = slots[i];
+        if (!sl.used || !sl.autoe) continue;
+        const BSys &M = m[i];
+        if (sl.feat == 5) {   // the BFS cancel ran before this copy
+            sl.feat = 4;
+            continue;
+        }
+        if (sl.feat < 1 || sl.feat > 3) continue;
+        if (M.bfs_err & kErrGuard) {   // a bounded loop ran out: no features, the solve is cancelled
+            launch_cancel(s, a, i);
+            sl.guard = group + 1;
+            launch_bfs_cancel(sb, a, i);
+            sl.feat = 5;
+            enq = true;
+            continue;
+        }
+        if (sl.feat == 1 && M.bfs_mode == kBfsSwept) {
+            launch_bfs_next_sweep(sb, a, i, (int32_t)sl.f.n);
+            sl.feat = 2;
+            enq = true;
+        } else if (sl.feat == 2 && M.bfs_mode == kBfsSwept) {
+            launch_bfs_finish(sb, a, i, (int32_t)sl.f.n);
+            sl.feat = 3;
+            enq = true;
+        } else if (sl.feat == 3 && M.bfs_mode == kBfsDone && !sl.bfs_ready) {
+            sl.f.pdiam = M.pdiam;
+            sl.f.bfs_t = M.bfs_t;
+            sl.f.bfs_u = M.bfs_u;
+            sl.f.n_components = M.ncomp;
+            sl.bfs_ready = true;
+        }
+    }
+    return enq;
+}
+
+// One pass of the BFS stream, if it is idle: its last copy is processed,
+// then transitions, rounds and the next copy are enqueued.  Never blocks.
+bool Engine::bfs_pump()
+{
+    if (b_inflight) {
+        const hipError_t q = hipEventQuery(evb);
+        if (q == hipErrorNotReady) return true;
+        if (q != hipSuccess) return false;
+        b_inflight = false;
+    }
+    // transitions enqueued from the copy need a copy behind them
+    bool enq = !b_inflight && bmirror_n > 0 ? process_bfs(bmirror, bmirror_n) : false;
+    bool run = false;
+    for (int32_t i = 0; i < (int32_t)slots.size(); ++i) {
+        Slot &sl = slots[i];
+        if (!sl.used || !sl.autoe) continue;
+        if (sl.want_bfs_cancel) {
+            launch_bfs_cancel(sb, a, i);
+            sl.want_bfs_cancel = false;
+            sl.feat = 5;
+            enq = true;
+        }
+        if (sl.want_start) {
+            launch_bfs_start(sb, a, i, (int32_t)sl.f.n);
+            sl.want_start = false;
+            sl.feat = 1;
+            enq = true;
+        }
+        if (sl.feat == 1 || sl.feat == 2) run = true;
+        if ((sl.feat == 3 && !sl.bfs_ready) || sl.feat == 5) enq = true;   // waiting for a copy that shows the result
+    }
+    if (run)
+        for (int r = 0; r < kBfsRoundsPerPump; ++r) launch_bfs_round(sb, a, hi_sys, small_levels);
+    if (hipGetLastError() != hipSuccess) return false;
+    if (!(enq || run) || hi_sys <= 0) return true;
+    bmirror_n = hi_sys;
+    if (hipMemcpyAsync(bmirror, a.sys, sizeof(BSys) * (size_t)hi_sys, hipMemcpyDeviceToHost, sb) != hipSuccess ||
+        hipEventRecord(evb, sb) != hipSuccess)
+        return false;
+    b_inflight = true;
+    return true;
+}
+
 bool Engine::step_once()
 {
     // new submissions and cancellations
@@ -422,17 +500,17 @@ bool Engine::step_once()
     }
     admit();
     if (failed) return false;
-    bool any_used = false, any_live = false, any_bfs = false;
+    bool any_used = false, any_live = false;
     for (auto &sl : slots) {
         if (!sl.used) continue;
         any_used = true;
         if (sl.adm == 2 && !sl.retiring) any_live = true;
-        if (sl.autoe && (sl.feat == 1 || sl.feat == 2)) any_bfs = true;   // sweeps armed, not finished
     }
     if (!any_used) return true;
+    if (!bfs_pump()) return false;
     const int k = (int)(group & 1);
     if (any_live)
-        for (int g = 0; g < kGroupSteps; ++g) launch_step(s, a, hi_slice, hi_sys, any_bfs, small_levels);
+        for (int g = 0; g < kGroupSteps; ++g) launch_step(s, a, hi_slice, hi_sys);
     if (hipGetLastError() != hipSuccess) return false;
     mirror_n[k] = hi_sys;
     mirror_group[k] = group;
@@ -442,7 +520,14 @@ bool Engine::step_once()
     if (hipEventRecord(ev[k], s) != hipSuccess) return false;
     const int kp = k ^ 1;
     if (mirror_group[kp] >= 0 && mirror_group[kp] == group - 1) {
-        if (hipEventSynchronize(ev[kp]) != hipSuccess) return false;
+        // wait for the previous group's copy, keeping the BFS stream fed meanwhile
+        for (;;) {
+            const hipError_t q = hipEventQuery(ev[kp]);
+            if (q == hipSuccess) break;
+            if (q != hipErrorNotReady) return false;
+            if (!bfs_pump()) return false;
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+        }
         process(mirror[kp], mirror_n[kp], group - 1);
         if (failed) return false;
     }
@@ -471,6 +556,7 @@ void Engine::run()
         }
         if (!step_once()) {
             (void)hipStreamSynchronize(s);
+            (void)hipStreamSynchronize(sb);
             fail_all(MPCG_EDEVICE);
             std::unique_lock<std::mutex> lk(mu);
             while (!stop) cv.wait_for(lk, std::chrono::milliseconds(20));
@@ -478,6 +564,7 @@ void Engine::run()
         }
     }
     (void)hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(sb);
 }
 
 // ------------------------------------------------------------ interface --
@@ -513,7 +600,11 @@ Engine *engine_create(int device, const mpcg_options &opt, const KnnModel *model
     e->finals.resize(max_sys);
     e->slices.init(max_slices);
     e->entries.init(max_entries);
-    bool ok = hipStreamCreateWithFlags(&e->s, hipStreamNonBlocking) == hipSuccess;
+    bool ok = hipStreamCreateWithFlags(&e->s, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&e->sb, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&e->evb, hipEventDisableTiming) == hipSuccess &&
+              hipHostMalloc((void **)&e->bmirror, sizeof(BSys) * (size_t)max_sys, hipHostMallocDefault) ==
+                  hipSuccess;
     for (int k = 0; k < 2 && ok; ++k) {
         ok = hipHostMalloc((void **)&e->mirror[k], sizeof(BSys) * (size_t)max_sys, hipHostMallocDefault) ==
                  hipSuccess &&
@@ -548,6 +639,12 @@ void engine_destroy(Engine *e)
         (void)hipStreamSynchronize(e->s);
         (void)hipStreamDestroy(e->s);
     }
+    if (e->sb) {
+        (void)hipStreamSynchronize(e->sb);
+        (void)hipStreamDestroy(e->sb);
+    }
+    if (e->evb) (void)hipEventDestroy(e->evb);
+    if (e->bmirror) (void)hipHostFree(e->bmirror);
     for (auto &v : e->ev) if (v) (void)hipEventDestroy(v);
     for (auto &m : e->mirror) if (m) (void)hipHostFree(m);
     if (e->stage) (void)hipHostFree(e->stage);

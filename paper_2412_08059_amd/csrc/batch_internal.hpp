@@ -14,7 +14,8 @@
 //                 restart and final-check decisions
 //   k_b_update    per slice: r -= alpha q, x += alpha d, partial of r.r
 //   k_b_scalar2   one block per system: gamma, stop tests, beta, v ratios
-//   k_b_bfs_*     2BFS levels of the systems whose features are pending
+//   k_b_bfs_*     2BFS levels of the systems whose features are pending, on a
+//                 stream of their own beside the steps
 //
 // Per-system sums are taken over that system's slice partials in a fixed
 // order, so a system's arithmetic does not depend on which other systems
@@ -69,7 +70,7 @@ struct alignas(256) BSys {
     // 2BFS
     int32_t bfs_mode, bfs_sweep, bfs_level, bfs_cnt;
     int32_t bfs_nxt, ncomp, pdiam, bfs_t;
-    int32_t bfs_u, small, pad0, pad1;
+    int32_t bfs_u, small, bfs_err, pad1;   // bfs_err: kErrGuard from the BFS kernels
     int64_t padded;                        // SELL-64 entries of the system (admission scan)
     unsigned long long comp_best;
     int64_t item0;                         // first BFS work item of this system in the current level
@@ -114,21 +115,27 @@ void launch_admit_entries(hipStream_t s, const BArena &a, int32_t sys, int32_t n
 // start mode from the options, then the slices become visible to the step
 void launch_admit_finish(hipStream_t s, const BArena &a, int32_t sys, int32_t nslices, double eps1);
 void launch_release(hipStream_t s, const BArena &a, int32_t sys, int32_t slice0, int32_t nslices);
-void launch_cancel(hipStream_t s, const BArena &a, int32_t sys);
+void launch_cancel(hipStream_t s, const BArena &a, int32_t sys);       // the solve (step stream)
+void launch_bfs_cancel(hipStream_t s, const BArena &a, int32_t sys);   // its 2BFS (BFS stream)
 // Algorithm II: eps1 chosen by the host
 void launch_set_eps(hipStream_t s, const BArena &a, int32_t sys, double eps1);
 void launch_fill_slices(hipStream_t s, const BArena &a);   // every slice unowned
 
 // ---- one step over all systems ----
-// bfs: also advance the 2BFS of the systems whose sweeps are running (the host
-// passes false when no system is between its BFS start and finish)
-// small_levels: most levels the one-block-per-system kernel expands per step
-void launch_step(hipStream_t s, const BArena &a, int32_t hi_slice, int32_t hi_sys, bool bfs, int small_levels);
+void launch_step(hipStream_t s, const BArena &a, int32_t hi_slice, int32_t hi_sys);
 
-// ---- 2BFS of one system (host-driven transitions) ----
-void launch_bfs_start(hipStream_t s, const BArena &a, int32_t sys);          // CC + sweep-1 seeds
-void launch_bfs_next_sweep(hipStream_t s, const BArena &a, int32_t sys);     // argmax + sweep-2 seeds
-void launch_bfs_finish(hipStream_t s, const BArena &a, int32_t sys);         // argmax + per-system result
+// ---- 2BFS (BFS stream) ----
+// Kernels on the BFS stream write only the BFS fields of a system's state
+// (bfs_*, ncomp, pdiam, small, comp_best, item0) and the BFS arrays; the step
+// kernels write the other fields.  Each side's host copy is read only for its
+// own fields.
+// One round: every system whose sweep is running expands one large level or
+// up to small_levels small ones.
+void launch_bfs_round(hipStream_t s, const BArena &a, int32_t hi_sys, int small_levels);
+// host-driven transitions of one system of n rows
+void launch_bfs_start(hipStream_t s, const BArena &a, int32_t sys, int32_t n);        // CC + sweep-1 seeds
+void launch_bfs_next_sweep(hipStream_t s, const BArena &a, int32_t sys, int32_t n);   // argmax + sweep-2 seeds
+void launch_bfs_finish(hipStream_t s, const BArena &a, int32_t sys, int32_t n);       // argmax + per-system result
 
 // ---- host engine (batch_engine.hip) ----
 struct Engine;

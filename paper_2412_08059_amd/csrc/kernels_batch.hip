@@ -329,6 +329,14 @@ __global__ void k_cancel(BArena a, int32_t sys)
         S.mode = kDone;
         S.status = MPCG_ECANCELED;
         S.upd = 0;
+    }
+}
+
+// Stops the system's 2BFS: the next rounds skip it.
+__global__ void k_bfs_cancel(BArena a, int32_t sys)
+{
+    if (threadIdx.x == 0) {
+        BSys &S = a.sys[sys];
         if (S.bfs_mode == kBfsRun || S.bfs_mode == kBfsSwept) S.bfs_mode = kBfsNone;
     }
 }
@@ -785,7 +793,7 @@ __global__ void __launch_bounds__(kBlock) k_bfs_small_batch(BArena a, int32_t ma
     }
 }
 
-void launch_step(hipStream_t s, const BArena &a, int32_t hi_slice, int32_t hi_sys, bool bfs, int small_levels)
+void launch_step(hipStream_t s, const BArena &a, int32_t hi_slice, int32_t hi_sys)
 {
     if (hi_slice <= 0 || hi_sys <= 0) return;
     const int gsl = (hi_slice + kSlicesPerBlock - 1) / kSlicesPerBlock;
@@ -793,7 +801,11 @@ void launch_step(hipStream_t s, const BArena &a, int32_t hi_slice, int32_t hi_sy
     hipLaunchKernelGGL(k_b_scalar1, dim3(hi_sys), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_b_update, dim3(gsl), dim3(kBlock), 0, s, a, hi_slice);
     hipLaunchKernelGGL(k_b_scalar2, dim3(hi_sys), dim3(kBlock), 0, s, a);
-    if (!bfs) return;
+}
+
+void launch_bfs_round(hipStream_t s, const BArena &a, int32_t hi_sys, int small_levels)
+{
+    if (hi_sys <= 0) return;
     hipLaunchKernelGGL(k_bfs_plan, dim3(1), dim3(1024), 0, s, a, hi_sys);
     hipLaunchKernelGGL(k_bfs_level_batch, dim3(256), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_bfs_small_batch, dim3(hi_sys), dim3(kBlock), 0, s, a, small_levels);
@@ -848,7 +860,7 @@ __global__ void __launch_bounds__(kBlock) k_b_cc_hook(BArena a, int32_t sys)
             }
         }
     }
-    if (guard) atomicOr(&a.sys[sys].err, kErrGuard);
+    if (guard) atomicOr(&a.sys[sys].bfs_err, kErrGuard);
 }
 
 // Labels compressed; roots seed the first sweep at distance 0.
@@ -867,7 +879,7 @@ __global__ void __launch_bounds__(kBlock) k_b_cc_seed(BArena a, int32_t sys)
             a.q0[S.row0 + pos] = v;
         }
     }
-    if (guard) atomicOr(&S.err, kErrGuard);
+    if (guard) atomicOr(&S.bfs_err, kErrGuard);
 }
 
 __global__ void k_b_bfs_arm(BArena a, int32_t sys, int32_t sweep)
@@ -966,7 +978,7 @@ __global__ void k_b_feat_final(BArena a, int32_t sys)
     const unsigned long long key = S.comp_best;
     const int comp = (int)(0xffffffffu - (unsigned)(key & 0xffffffffull));
     if (key == 0ull || comp < S.row0 || comp >= S.row0 + S.n) {
-        S.err |= kErrGuard;
+        S.bfs_err |= kErrGuard;
         S.bfs_mode = kBfsDone;
         return;
     }
@@ -983,10 +995,10 @@ static int rows_grid(int n)
     return g < 1 ? 1 : g;
 }
 
-void launch_bfs_start(hipStream_t s, const BArena &a, int32_t sys)
+// the kernels walk the system's rows grid-stride: the grid follows its size
+void launch_bfs_start(hipStream_t s, const BArena &a, int32_t sys, int32_t n)
 {
-    // the system's n is read on the device; the grid covers the largest admissible system
-    const int g = 4096;
+    const int g = rows_grid(n);
     hipLaunchKernelGGL(k_b_zero_nxt, dim3(1), dim3(64), 0, s, a, sys);
     hipLaunchKernelGGL(k_b_cc_init, dim3(g), dim3(kBlock), 0, s, a, sys);
     hipLaunchKernelGGL(k_b_cc_hook, dim3(g), dim3(kBlock), 0, s, a, sys);
@@ -994,9 +1006,9 @@ void launch_bfs_start(hipStream_t s, const BArena &a, int32_t sys)
     hipLaunchKernelGGL(k_b_bfs_arm, dim3(1), dim3(64), 0, s, a, sys, 1);
 }
 
-void launch_bfs_next_sweep(hipStream_t s, const BArena &a, int32_t sys)
+void launch_bfs_next_sweep(hipStream_t s, const BArena &a, int32_t sys, int32_t n)
 {
-    const int g = 4096;
+    const int g = rows_grid(n);
     hipLaunchKernelGGL(k_b_argmax, dim3(g), dim3(kBlock), 0, s, a, sys);
     hipLaunchKernelGGL(k_b_fill_dist, dim3(g), dim3(kBlock), 0, s, a, sys);
     hipLaunchKernelGGL(k_b_zero_nxt, dim3(1), dim3(64), 0, s, a, sys);
@@ -1004,9 +1016,9 @@ void launch_bfs_next_sweep(hipStream_t s, const BArena &a, int32_t sys)
     hipLaunchKernelGGL(k_b_bfs_arm, dim3(1), dim3(64), 0, s, a, sys, 2);
 }
 
-void launch_bfs_finish(hipStream_t s, const BArena &a, int32_t sys)
+void launch_bfs_finish(hipStream_t s, const BArena &a, int32_t sys, int32_t n)
 {
-    const int g = 4096;
+    const int g = rows_grid(n);
     hipLaunchKernelGGL(k_b_argmax, dim3(g), dim3(kBlock), 0, s, a, sys);
     hipLaunchKernelGGL(k_b_comp_best, dim3(g), dim3(kBlock), 0, s, a, sys);
     hipLaunchKernelGGL(k_b_feat_final, dim3(1), dim3(64), 0, s, a, sys);
@@ -1049,6 +1061,11 @@ void launch_release(hipStream_t s, const BArena &a, int32_t sys, int32_t slice0,
 void launch_cancel(hipStream_t s, const BArena &a, int32_t sys)
 {
     hipLaunchKernelGGL(k_cancel, dim3(1), dim3(64), 0, s, a, sys);
+}
+
+void launch_bfs_cancel(hipStream_t s, const BArena &a, int32_t sys)
+{
+    hipLaunchKernelGGL(k_bfs_cancel, dim3(1), dim3(64), 0, s, a, sys);
 }
 
 void launch_set_eps(hipStream_t s, const BArena &a, int32_t sys, double eps1)
