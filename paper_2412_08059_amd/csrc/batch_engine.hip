@@ -12,8 +12,10 @@
 // the steps and at its own pace: whenever that stream is idle the thread
 // reads its last state copy (BFS fields only), enqueues the transitions it
 // calls for (sweep start, next sweep, finish, cancel) and a few BFS rounds,
-// then another copy.  A system holds after its k0 FP32 iterations until its
-// features are in, so its arithmetic does not depend on that pace.
+// then another copy.  After its k0 FP32 iterations a system runs ahead,
+// copying x~ at the first crossing of each candidate eps1, until its features
+// are in; the state it then restarts from is the one the sequential method
+// stops in, so its arithmetic does not depend on that pace.
 
 #include "batch_internal.hpp"
 #include "knn.hpp"
@@ -362,7 +364,7 @@ void Engine::process(const BSys *m, int32_t cnt, int64_t gi)
                 const int cls = knn_select(*model, chi, opt.knn_k, &sl.exact);
                 sl.cls = (cls >= 2 && cls <= 7) ? cls : 4;
                 sl.eps1 = kEpsClass[sl.cls];
-                launch_set_eps(s, a, i, sl.eps1);
+                launch_set_eps(s, a, i, sl.eps1, sl.cls - 2);
                 sl.t_feat = now_ms();
                 sl.feat = 4;
                 sl.guard = group + 1;

@@ -39,7 +39,10 @@ enum Mode : int32_t {
     kDone = 6,
 };
 
-enum RestartSrc : int32_t { kSrcX32 = 0, kSrcX64 = 1, kSrcZero = 2 };
+enum RestartSrc : int32_t { kSrcX32 = 0, kSrcX64 = 1, kSrcZero = 2, kSrcSnap = 3 };
+
+// Why a system's FP32 run-ahead stopped before its eps1 was known.
+enum RunAheadStop : int32_t { kRaNone = 0, kRaBreakdown = 1, kRaMaxit = 2, kRaAllCrossed = 3 };
 
 enum BfsMode : int32_t {
     kBfsNone = 0,
@@ -67,6 +70,13 @@ struct alignas(256) BSys {
     double gamma, gamma_prev, delta, alpha, beta, bb, thr1, thr2;
     double relres_sp, relres_restart, relres_final;
     double ratios[kK0Max];
+    // Algorithm II run-ahead: after the k0 prefix, until eps1 is set, the FP32
+    // recurrence continues and x~ is copied at the first crossing of each
+    // candidate eps1 (copy taken by the next product, snap_mask: classes due)
+    double spec_thr[kNumEps];
+    double cross_gamma[kNumEps];
+    int32_t cross_iter[kNumEps];
+    int32_t snap_mask, snap_ci, ra_stop, ra_pad;
     // 2BFS
     int32_t bfs_mode, bfs_sweep, bfs_level, bfs_cnt;
     int32_t bfs_nxt, ncomp, pdiam, bfs_t;
@@ -89,6 +99,7 @@ struct BArena {
     int32_t *rowlen;
     double *b64, *x64, *r64, *q64, *dA64, *dB64;
     float *x32, *r32, *q32, *dA32, *dB32;
+    float *snap32;                         // kNumEps copies of x~, copy t at t * max_slices * 64
     int32_t *dist, *q0, *q1, *label, *tarr;
     unsigned long long *best;
     // per entry
@@ -117,8 +128,8 @@ void launch_admit_finish(hipStream_t s, const BArena &a, int32_t sys, int32_t ns
 void launch_release(hipStream_t s, const BArena &a, int32_t sys, int32_t slice0, int32_t nslices);
 void launch_cancel(hipStream_t s, const BArena &a, int32_t sys);       // the solve (step stream)
 void launch_bfs_cancel(hipStream_t s, const BArena &a, int32_t sys);   // its 2BFS (BFS stream)
-// Algorithm II: eps1 chosen by the host
-void launch_set_eps(hipStream_t s, const BArena &a, int32_t sys, double eps1);
+// Algorithm II: eps1 chosen by the host, of candidate class ci (0: 1e-2 ... 5: 1e-7)
+void launch_set_eps(hipStream_t s, const BArena &a, int32_t sys, double eps1, int32_t ci);
 void launch_fill_slices(hipStream_t s, const BArena &a);   // every slice unowned
 
 // ---- one step over all systems ----

@@ -79,6 +79,7 @@ size_t arena_bytes(int32_t max_sys, int32_t max_slices, int64_t max_entries)
     t += up256(4 * sl) * 2 + up256(8 * sl) + up256(16 * sl);          // slice_w, sys_of_slice, slice_off, pslice
     t += up256(4 * rows);                                             // rowlen
     t += up256(8 * rows) * 6 + up256(4 * rows) * 5;                   // FP64 and FP32 vectors
+    t += up256(4 * rows * kNumEps);                                   // run-ahead copies of x~
     t += up256(4 * rows) * 5 + up256(8 * rows);                       // BFS
     t += up256(4 * e) + up256(8 * e) + up256(4 * e);                  // col, v64, v32
     t += up256(4 * (size_t)max_sys) * 2 + up256(8 * (size_t)max_sys) + 256 + 256;
@@ -111,6 +112,7 @@ BArena carve(void *base, int32_t max_sys, int32_t max_slices, int64_t max_entrie
     a.q32 = reinterpret_cast<float *>(take(4 * rows));
     a.dA32 = reinterpret_cast<float *>(take(4 * rows));
     a.dB32 = reinterpret_cast<float *>(take(4 * rows));
+    a.snap32 = reinterpret_cast<float *>(take(4 * rows * kNumEps));
     a.dist = reinterpret_cast<int32_t *>(take(4 * rows));
     a.q0 = reinterpret_cast<int32_t *>(take(4 * rows));
     a.q1 = reinterpret_cast<int32_t *>(take(4 * rows));
@@ -279,6 +281,14 @@ __global__ void __launch_bounds__(kBlock) k_admit_finish(BArena a, int32_t sys, 
         S.upd = 0;
         const double sb = sqrt(bb);
         S.thr2 = S.tol_abs ? S.eps2 : S.eps2 * sb;
+        double e = 1e-2;
+        for (int t = 0; t < kNumEps; ++t, e *= 0.1) {
+            S.spec_thr[t] = S.tol_abs ? e : e * sb;
+            S.cross_iter[t] = -1;
+            S.cross_gamma[t] = 0.0;
+        }
+        S.snap_mask = 0;
+        S.ra_stop = kRaNone;
         if (S.err) {
             S.status = (S.err & (kErrNonFiniteA | kErrNonFiniteB)) ? MPCG_ENONFINITE : MPCG_EINVAL;
             S.mode = kDone;
@@ -341,29 +351,44 @@ __global__ void k_bfs_cancel(BArena a, int32_t sys)
     }
 }
 
-// Algorithm II: eps1 from the kNN choice.  A system holding after its k0
-// prefix continues with the eps1 test (Remark 3); one still in the prefix
-// picks the test up when the prefix ends.
-__global__ void k_set_eps(BArena a, int32_t sys, double eps1)
+// Algorithm II: eps1 (candidate class ci) from the kNN choice.  A system
+// still in its k0 prefix picks the eps1 test up when the prefix ends.  One
+// past it has been running ahead: if it crossed eps1 on the way, the FP64
+// restart starts from the copy of x~ at that first crossing (or from x~
+// itself while that copy is still due: x~ has not moved since); if the run
+// stopped (breakdown, maxit1) before reaching eps1, from x~ at the stop;
+// otherwise the FP32 phase continues with the eps1 test (Remark 3).  Each
+// case is the state the sequential method stops in.
+__global__ void k_set_eps(BArena a, int32_t sys, double eps1, int32_t ci)
 {
     if (threadIdx.x != 0) return;
     BSys &S = a.sys[sys];
-    S.thr1 = S.tol_abs ? eps1 : eps1 * sqrt(S.bb);
+    const double sb = sqrt(S.bb);
+    S.thr1 = S.tol_abs ? eps1 : eps1 * sb;
     S.eps_set = 1;
-    if (S.mode != kHold) return;
-    if (sqrt(S.gamma) <= S.thr1) {
-        S.relres_sp = sqrt(S.gamma) / sqrt(S.bb);
+    if (S.mode == kHold && S.k0_used == 0) {   // gamma_0 = 0 at admission: nothing to iterate
+        S.relres_sp = sqrt(S.gamma) / sb;
         S.src = kSrcX32;
         S.ph_it = 0;
         S.mode = kRestart;
-    } else if (S.n1 >= S.maxit1) {
-        S.flags |= MPCG_FLAG_FP32_MAXIT;
-        S.relres_sp = sqrt(S.gamma) / sqrt(S.bb);
+        return;
+    }
+    if (S.k0_used == 0 || (S.mode != kHold && S.mode != kCg32)) return;
+    if (ci >= 0 && ci < kNumEps && S.cross_iter[ci] >= 0) {
+        S.n1 = S.cross_iter[ci];
+        S.gamma = S.cross_gamma[ci];
+        S.relres_sp = sqrt(S.gamma) / sb;
+        S.src = ((S.snap_mask >> ci) & 1) ? kSrcX32 : kSrcSnap;
+        S.snap_ci = ci;
+        S.upd = 0;
+        S.ph_it = 0;
+        S.mode = kRestart;
+    } else if (S.mode == kHold) {
+        S.flags |= S.ra_stop == kRaBreakdown ? MPCG_FLAG_FP32_BREAKDOWN : MPCG_FLAG_FP32_MAXIT;
+        S.relres_sp = sqrt(S.gamma) / sb;
         S.src = kSrcX32;
         S.ph_it = 0;
         S.mode = kRestart;
-    } else {
-        S.mode = kCg32;
     }
 }
 
@@ -424,6 +449,7 @@ __device__ inline double cg_product(const BArena &a, const BSys &S, const T *val
 __device__ inline double residual(const BArena &a, const BSys &S, bool restart, int64_t base, int row, int len)
 {
     const int src = restart ? S.src : kSrcX64;
+    const float *xs = a.snap32 + (size_t)S.snap_ci * ((size_t)a.max_slices * 64);   // src == kSrcSnap
     double acc = 0.0;
     const int W = wave_max_i32(len);
     for (int k0 = 0; k0 < W; k0 += kLoadBatch) {
@@ -438,7 +464,10 @@ __device__ inline double residual(const BArena &a, const BSys &S, bool restart, 
 #pragma unroll
         for (int t = 0; t < kLoadBatch; ++t)
             if (k0 + t < len)
-                g[t] = src == kSrcX32 ? (double)a.x32[c[t]] : (src == kSrcX64 ? a.x64[c[t]] : 0.0);
+                g[t] = src == kSrcX32   ? (double)a.x32[c[t]]
+                       : src == kSrcSnap ? (double)xs[c[t]]
+                       : src == kSrcX64  ? a.x64[c[t]]
+                                         : 0.0;
 #pragma unroll
         for (int t = 0; t < kLoadBatch; ++t)
             if (k0 + t < len) acc = fma(v[t], g[t], acc);
@@ -446,6 +475,7 @@ __device__ inline double residual(const BArena &a, const BSys &S, bool restart, 
     const double res = a.b64[row] - acc;
     if (restart) {
         if (src == kSrcX32) a.x64[row] = (double)a.x32[row];
+        else if (src == kSrcSnap) a.x64[row] = (double)xs[row];
         else if (src == kSrcZero) a.x64[row] = 0.0;
         a.r64[row] = res;
     }
@@ -459,10 +489,15 @@ __global__ void __launch_bounds__(kBlock) k_b_product(BArena a, int32_t hi_slice
     const int s = a.sys_of_slice[sl];
     if (s < 0) return;
     const BSys &S = a.sys[s];
-    const int mode = S.mode;
-    if (mode != kCg32 && mode != kCg64 && mode != kRestart && mode != kResid) return;
     const int lane = threadIdx.x & 63;
     const int row = sl * 64 + lane;
+    const int due = S.snap_mask;
+    if (due) {   // run-ahead: x~ of the last iteration, first below these candidates
+        for (int t = 0; t < kNumEps; ++t)
+            if ((due >> t) & 1) a.snap32[(size_t)t * ((size_t)a.max_slices * 64) + row] = a.x32[row];
+    }
+    const int mode = S.mode;
+    if (mode != kCg32 && mode != kCg64 && mode != kRestart && mode != kResid) return;
     const int len = a.rowlen[row];
     const int64_t base = S.entry0 + a.slice_off[sl] + lane;
     double p;
@@ -479,6 +514,7 @@ __global__ void __launch_bounds__(kBlock) k_b_scalar1(BArena a)
     __shared__ double sm[kBlock / 64 + 1];
     BSys &S = a.sys[blockIdx.x];
     const int mode = S.mode;
+    if (threadIdx.x == 0 && S.snap_mask) S.snap_mask = 0;   // the product of this step took the copies
     if (mode != kCg32 && mode != kCg64 && mode != kRestart && mode != kResid) return;
     const double v = sys_sum(a, S, 0, sm);
     if (threadIdx.x != 0) return;
@@ -487,6 +523,12 @@ __global__ void __launch_bounds__(kBlock) k_b_scalar1(BArena a)
         const double delta = v;
         S.delta = delta;
         if (!isfinite(delta) || !(delta > 0.0)) {
+            if (mode == kCg32 && S.auto_eps && !S.eps_set && S.k0_used != 0) {
+                // run-ahead: where the FP32 phase stops depends on eps1
+                S.ra_stop = kRaBreakdown;
+                S.mode = kHold;
+                return;
+            }
             if (mode == kCg32) {
                 S.flags |= MPCG_FLAG_FP32_BREAKDOWN;
                 if (S.auto_eps && !S.eps_set && S.k0_used == 0) S.k0_used = S.n1 < S.k0 ? S.n1 : S.k0;
@@ -584,7 +626,28 @@ __global__ void __launch_bounds__(kBlock) k_b_scalar2(BArena a)
         if (prefix && (S.n1 >= S.k0 || g == 0.0)) S.k0_used = S.n1;
         if (prefix && S.n1 < S.k0 && g != 0.0) return;   // Algorithm II: k0 iterations first
         if (S.auto_eps && !S.eps_set) {
-            S.mode = kHold;
+            // run-ahead until eps1 is known: record the first crossing of
+            // each candidate (x~ is copied by the next product)
+            const double rg = sqrt(g);
+            int due = 0, left = 0;
+            for (int t = 0; t < kNumEps; ++t) {
+                if (S.cross_iter[t] >= 0) continue;
+                if (rg <= S.spec_thr[t]) {
+                    S.cross_iter[t] = S.n1;
+                    S.cross_gamma[t] = g;
+                    due |= 1 << t;
+                } else {
+                    ++left;
+                }
+            }
+            S.snap_mask = due;
+            if (left == 0) {
+                S.ra_stop = kRaAllCrossed;
+                S.mode = kHold;
+            } else if (S.n1 >= S.maxit1) {
+                S.ra_stop = kRaMaxit;
+                S.mode = kHold;
+            }
             return;
         }
         if (sqrt(g) <= S.thr1 || S.n1 >= S.maxit1) {
@@ -1068,9 +1131,9 @@ void launch_bfs_cancel(hipStream_t s, const BArena &a, int32_t sys)
     hipLaunchKernelGGL(k_bfs_cancel, dim3(1), dim3(64), 0, s, a, sys);
 }
 
-void launch_set_eps(hipStream_t s, const BArena &a, int32_t sys, double eps1)
+void launch_set_eps(hipStream_t s, const BArena &a, int32_t sys, double eps1, int32_t ci)
 {
-    hipLaunchKernelGGL(k_set_eps, dim3(1), dim3(64), 0, s, a, sys, eps1);
+    hipLaunchKernelGGL(k_set_eps, dim3(1), dim3(64), 0, s, a, sys, eps1, ci);
 }
 
 }  // namespace batch

@@ -110,6 +110,25 @@ def test_batch_mix_matches_oracle(engine, torch_mod):
         _check_against_oracle(a, b, e, st, x, model)
 
 
+def test_batch_run_ahead_restarts_from_the_crossing(engine, torch_mod):
+    """Features that arrive long after the FP32 run-ahead has passed every
+    candidate eps1: a path-like band (tridiagonal, mu = 1.1, n = 50000) has a
+    2BFS of 2 x 49999 levels while its CG crosses 1e-7 within a few dozen
+    iterations.  The FP64 restart must start from the copy of x~ taken at the
+    chosen class's first crossing -- the state the sequential Algorithm II
+    stops in -- so the result matches the oracle's Algorithm II."""
+    from workloads import paper_family as PF
+    model = oracle.load_model(TEST_MODEL)
+    a, b, req = _make(torch_mod, "band_path_auto", lambda: PF.random_banded(50_000, 3, 1.0, 1.1, seed=3), 0.0,
+                      seed=17)
+    (rid,) = engine.submit([req])
+    st, x = engine.wait_all([rid], timeout_s=120)[rid]
+    print(f"  band_path_auto: status={st.status} n1={st.n1} n2={st.n2} cls={st.eps1_class} "
+          f"pdiam={st.feat.pdiam} t_feat={st.t_feat_ms:.1f} ms", flush=True)
+    assert st.feat.pdiam == 49_999
+    _check_against_oracle(a, b, 0.0, st, x, model)
+
+
 def test_batch_alone_equals_in_mix_bitwise(engine, torch_mod):
     """A system's result does not depend on the other systems in the batch."""
     probe = [("varcoef3d_18_auto", lambda: W.varcoef3d(18, seed=3), 0.0),
