@@ -87,8 +87,8 @@ __device__ inline void bfs_finish(DevState *st, int L)
 // widened by the largest |i - j| of the matrix, is no longer inside it and
 // that widened range is at most a quarter of the window; it is placed ahead
 // of the frontier in the direction the frontier moves.
-constexpr int kWinRows = 1024;
-constexpr int kWinEntries = 5632;
+constexpr int kWinRows = 2048;
+constexpr int kWinEntries = 16384;
 
 __device__ inline void astore_i32(int32_t *p, int v)
 {
@@ -149,7 +149,7 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
     // modulo 3: a slot is cleared two levels before it is used again, after
     // a barrier that every thread passed once it had read the slot
     __shared__ int32_t s_cnt[3], s_min[3], s_max[3];
-    __shared__ int32_t s_cur, s_level, s_go, s_curmin, s_fit, s_a;
+    __shared__ int32_t s_cur, s_level, s_go, s_curmin, s_fit;
     __shared__ long long s_vis;
     const int tid = threadIdx.x;
     const int lsh = __ffs(lanes) - 1;   // lanes is a power of two
@@ -257,34 +257,39 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
             // write the old window back, then fill the new one
             for (int i = tid; i < nw; i += kBfsSmallThreads)
                 if (w_dist[i] >= 0) astore_i32(&dist[w0 + i], w_dist[i]);
-            if (tid == 0) {
-                s_fit = 0;
-                s_a = wp.rows;
-            }
+            if (tid == 0) s_fit = 0;
             const int mode = wp.mode, nb0 = wp.base, rows = wp.rows;
             __syncthreads();
             for (int i = tid; i <= rows; i += kBfsSmallThreads) w_rp[i] = rp[nb0 + i];
             __syncthreads();
             // w_rp is non-decreasing: the fitting rows are a prefix (mode 1)
-            // or a suffix (mode 2) of the rows read
-            if (mode == 1) {
+            // or a suffix (mode 2) of the rows read, so their count gives both
+            // the window's size and its first row (one atomic per wave)
+            {
+                int cntl = 0;
                 for (int i = tid; i <= rows; i += kBfsSmallThreads)
-                    if (w_rp[i] - w_rp[0] <= kWinEntries) atomicMax(&s_fit, i);
-            } else {
-                for (int i = tid; i <= rows; i += kBfsSmallThreads)
-                    if (w_rp[rows] - w_rp[i] <= kWinEntries) atomicMin(&s_a, i);
+                    cntl += (mode == 1 ? w_rp[i] - w_rp[0] : w_rp[rows] - w_rp[i]) <= kWinEntries ? 1 : 0;
+                for (int o = 32; o > 0; o >>= 1) cntl += __shfl_xor(cntl, o, 64);
+                if ((tid & 63) == 0 && cntl) atomicAdd(&s_fit, cntl);
             }
             __syncthreads();
-            const int a = mode == 1 ? 0 : s_a;
-            const int fit = mode == 1 ? s_fit : rows - a;
+            const int cnt = s_fit;   // >= 1: the first (mode 1) or last (mode 2) row always fits
+            const int fit = cnt - 1;
+            const int a = mode == 1 ? 0 : rows + 1 - cnt;
             if (a > 0) {   // move the kept row pointers to the front
-                int t0 = 0, t1 = 0;
-                const int i1 = tid + kBfsSmallThreads;
-                if (tid <= fit) t0 = w_rp[a + tid];
-                if (i1 <= fit) t1 = w_rp[a + i1];
+                constexpr int kMv = (kWinRows + kBfsSmallThreads) / kBfsSmallThreads;   // >= (kWinRows + 1) / threads
+                int tv[kMv];
+#pragma unroll
+                for (int r = 0; r < kMv; ++r) {
+                    const int i = tid + r * kBfsSmallThreads;
+                    tv[r] = i <= fit ? w_rp[a + i] : 0;
+                }
                 __syncthreads();
-                if (tid <= fit) w_rp[tid] = t0;
-                if (i1 <= fit) w_rp[i1] = t1;
+#pragma unroll
+                for (int r = 0; r < kMv; ++r) {
+                    const int i = tid + r * kBfsSmallThreads;
+                    if (i <= fit) w_rp[i] = tv[r];
+                }
                 __syncthreads();
             }
             w0 = nb0 + a;
