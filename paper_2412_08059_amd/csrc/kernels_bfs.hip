@@ -209,7 +209,7 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
             bool got;
             QEnt nv;
             if ((unsigned)wv < (unsigned)nw) {
-                if (w_dist[wv] >= 0) return;   // a self-loop is visited already
+                // in LDS the claim itself is the test (no separate read first)
                 nv = QEnt{w_rp[wv], w_rp[wv + 1]};
                 got = atomicCAS(&w_dist[wv], -1, level + 1) == -1;
             } else {
