@@ -138,6 +138,29 @@ __device__ inline WinPlan plan_window(int fmin, int fmax, int pmax, int band, in
     return p;
 }
 
+// Bit-parallel levels.  When the matrix's largest |i - j| (band) is at most
+// kBitBand and the frontier with that margin lies inside the window, the
+// first wave runs levels alone on bitsets of the window's rows, one 64-bit
+// word per lane: the next frontier is the union over the offsets d of the
+// frontier shifted by +-d and masked by the rows that have an entry at -+d
+// (the pattern is symmetric, so a row's entries also say who reaches it),
+// minus the visited set.  A level is two lane shuffles and a few word
+// operations per offset, with no barrier and no per-vertex atomics.  Each
+// level's new words go to an LDS ring that the wave turns into distances
+// every kBitRing levels.  The wave hands back to the block when the BFS ends
+// or a new frontier vertex comes within band rows of a window edge (the
+// window then moves); the block rebuilds its queue from the frontier bits.
+constexpr int kBitBand = 8;
+constexpr int kBitWords = kWinRows / 64;
+constexpr int kBitRing = 64;
+constexpr int kBitDone = 0, kBitMove = 1;
+
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 __global__ void __launch_bounds__(kBfsSmallThreads)
 k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int32_t *dist,
             QEnt *q0, QEnt *q1, int32_t n, int32_t lanes, int32_t small_max, int32_t band, int32_t k,
@@ -151,6 +174,12 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
     __shared__ int32_t s_cnt[3], s_min[3], s_max[3];
     __shared__ int32_t s_cur, s_level, s_go, s_curmin, s_fit;
     __shared__ long long s_vis;
+    // bit-parallel levels: per-offset row masks (bit i of word w: row 64w + i
+    // has an entry at -d (b_mp) / +d (b_mm)), frontier and visited words, ring
+    __shared__ unsigned long long b_mp[kBitBand + 1][kBitWords], b_mm[kBitBand + 1][kBitWords];
+    __shared__ unsigned long long b_f[kBitWords], b_v[kBitWords], b_ring[kBitRing][kBitWords];
+    __shared__ int32_t b_code, b_level, b_fmin, b_fmax, b_pmax, b_cnt, b_app;
+    __shared__ long long b_vis;
     const int tid = threadIdx.x;
     const int lsh = __ffs(lanes) - 1;   // lanes is a power of two
     if (tid == 0) {
@@ -191,8 +220,234 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
     int pmax = -1;
     bool finished = false;
     __syncthreads();
-    // every iteration expands one level; at most n levels exist
+
+    // moves the window (all threads): the old one is written back, then rows
+    // [base, base + rows) are read and the part whose entries fit is kept
+    auto slide = [&](const WinPlan wp) {
+        for (int i = tid; i < nw; i += kBfsSmallThreads)
+            if (w_dist[i] >= 0) astore_i32(&dist[w0 + i], w_dist[i]);
+        if (tid == 0) s_fit = 0;
+        const int mode = wp.mode, nb0 = wp.base, rows = wp.rows;
+        __syncthreads();
+        for (int i = tid; i <= rows; i += kBfsSmallThreads) w_rp[i] = rp[nb0 + i];
+        __syncthreads();
+        // w_rp is non-decreasing: the fitting rows are a prefix (mode 1)
+        // or a suffix (mode 2) of the rows read, so their count gives both
+        // the window's size and its first row (one atomic per wave)
+        {
+            int cntl = 0;
+            for (int i = tid; i <= rows; i += kBfsSmallThreads)
+                cntl += (mode == 1 ? w_rp[i] - w_rp[0] : w_rp[rows] - w_rp[i]) <= kWinEntries ? 1 : 0;
+            for (int o = 32; o > 0; o >>= 1) cntl += __shfl_xor(cntl, o, 64);
+            if ((tid & 63) == 0 && cntl) atomicAdd(&s_fit, cntl);
+        }
+        __syncthreads();
+        const int cnt = s_fit;   // >= 1: the first (mode 1) or last (mode 2) row always fits
+        const int fit = cnt - 1;
+        const int a = mode == 1 ? 0 : rows + 1 - cnt;
+        if (a > 0) {   // move the kept row pointers to the front
+            constexpr int kMv = (kWinRows + kBfsSmallThreads) / kBfsSmallThreads;   // >= (kWinRows + 1) / threads
+            int tv[kMv];
+#pragma unroll
+            for (int r = 0; r < kMv; ++r) {
+                const int i = tid + r * kBfsSmallThreads;
+                tv[r] = i <= fit ? w_rp[a + i] : 0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < kMv; ++r) {
+                const int i = tid + r * kBfsSmallThreads;
+                if (i <= fit) w_rp[i] = tv[r];
+            }
+            __syncthreads();
+        }
+        w0 = nb0 + a;
+        nw = fit;
+        e0 = w_rp[0];
+        e1 = w_rp[fit];
+        for (int i = tid; i < e1 - e0; i += kBfsSmallThreads) w_col[i] = col[e0 + i];
+        for (int i = tid; i < fit; i += kBfsSmallThreads) w_dist[i] = atomic_load_i32(&dist[w0 + i]);
+        __syncthreads();
+    };
+
+    // bit-parallel levels from the current frontier (level `level`, all of it
+    // and its neighbours inside the window); block-wide, returns kBitDone or
+    // kBitMove with the state of the last frontier in b_*
+    auto bit_levels = [&]() -> int {
+        const int wv = tid >> 6, ln = tid & 63;
+        // row masks and the frontier / visited words, one wave per word
+        for (int wd = wv; wd < kBitWords; wd += kBfsSmallThreads / 64) {
+            const int r = wd * 64 + ln;
+            unsigned lo = 0u, hi = 0u;   // bit d: an entry at offset -d / +d
+            bool f = false, v = false;
+            if (r < nw) {
+                const int row = w0 + r;
+                const int j1 = w_rp[r + 1] - e0;
+                for (int j = w_rp[r] - e0; j < j1; ++j) {
+                    const int o = w_col[j] - row;
+                    if (o < 0 && o >= -kBitBand) lo |= 1u << (-o);
+                    else if (o > 0 && o <= kBitBand) hi |= 1u << o;
+                }
+                const int dd = w_dist[r];
+                f = dd == level;
+                v = dd >= 0;
+            }
+            for (int d = 1; d <= kBitBand; ++d) {
+                const unsigned long long ml = __ballot((lo >> d) & 1u), mh = __ballot((hi >> d) & 1u);
+                if (ln == 0) {
+                    b_mp[d][wd] = ml;
+                    b_mm[d][wd] = mh;
+                }
+            }
+            const unsigned long long mf = __ballot(f), mv = __ballot(v);
+            if (ln == 0) {
+                b_f[wd] = mf;
+                b_v[wd] = mv;
+            }
+        }
+        if (tid == 0) b_app = 0;
+        __syncthreads();
+        if (wv == 0) {
+            const int lane = ln;
+            const bool mine = lane < kBitWords;
+            unsigned long long mp[kBitBand + 1], mm[kBitBand + 1];
+#pragma unroll
+            for (int d = 1; d <= kBitBand; ++d) {
+                mp[d] = mine ? b_mp[d][lane] : 0ull;
+                mm[d] = mine ? b_mm[d][lane] : 0ull;
+            }
+            unsigned long long F = mine ? b_f[lane] : 0ull, V = mine ? b_v[lane] : 0ull, Fp = 0ull;
+            const unsigned long long pf0 = wave_sum_u64((unsigned long long)__popcll(F));
+            const unsigned long long pv0 = wave_sum_u64((unsigned long long)__popcll(V));
+            // rows within band of an edge of the window that is not an edge of the graph
+            unsigned long long zone = 0ull;
+            {
+                const int r0 = lane * 64;
+                const int lo_end = w0 > 0 ? band : 0;                 // rows [0, lo_end)
+                const int hi_beg = w0 + nw < n ? nw - band : nw;      // rows [hi_beg, nw)
+                for (int i = 0; i < 64; ++i) {
+                    const int r = r0 + i;
+                    if (r < nw && (r < lo_end || r >= hi_beg)) zone |= 1ull << i;
+                }
+            }
+            const int lev0 = level;
+            int lev = level, used = 0, code;
+            // ring -> distances: lane t takes slot t (levels lev0 + t + 1 of this batch)
+            auto flush = [&](int count, int base_level) {
+                if (lane < count) {
+                    for (int wd = 0; wd < kBitWords; ++wd) {
+                        unsigned long long x = b_ring[lane][wd];
+                        while (x) {
+                            const int b = __ffsll((long long)x) - 1;
+                            x &= x - 1ull;
+                            w_dist[wd * 64 + b] = base_level + lane + 1;
+                        }
+                    }
+                }
+            };
+            int ring_level = lev0;   // level of the frontier before ring slot 0
+            for (;;) {
+                unsigned long long fl = __shfl_up(F, 1, 64), fr = __shfl_down(F, 1, 64);
+                if (lane == 0) fl = 0ull;
+                if (lane == 63) fr = 0ull;
+                unsigned long long N = 0ull;
+#pragma unroll
+                for (int d = 1; d <= kBitBand; ++d) {
+                    if (d <= band) {
+                        const unsigned long long up = (F << d) | (fl >> (64 - d));
+                        const unsigned long long dn = (F >> d) | (fr << (64 - d));
+                        N |= (up & mp[d]) | (dn & mm[d]);
+                    }
+                }
+                const unsigned long long nb = N & ~V;
+                if (!__any(nb != 0ull)) {
+                    code = kBitDone;
+                    break;
+                }
+                V |= nb;
+                Fp = F;
+                F = nb;
+                ++lev;
+                if (mine) b_ring[used][lane] = nb;
+                ++used;
+                if (__any((nb & zone) != 0ull)) {
+                    code = kBitMove;
+                    break;
+                }
+                if (used == kBitRing) {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    flush(used, ring_level);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    ring_level += used;
+                    used = 0;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            flush(used, ring_level);
+            const unsigned long long pf = wave_sum_u64((unsigned long long)__popcll(F));
+            const unsigned long long pv = wave_sum_u64((unsigned long long)__popcll(V));
+            const int fmin = wave_min_i(F ? lane * 64 + __ffsll((long long)F) - 1 : kIntMax);
+            const int fmax = wave_max_i(F ? lane * 64 + 63 - __clzll((long long)F) : -1);
+            const int pmx = wave_max_i(Fp ? lane * 64 + 63 - __clzll((long long)Fp) : -1);
+            if (mine) b_f[lane] = F;
+            if (lane == 0) {
+                b_code = code;
+                b_level = lev;
+                b_fmin = fmin;
+                b_fmax = fmax;
+                b_pmax = pmx;
+                b_cnt = (int)pf;
+                // frontiers expanded here: the first one and every later one but
+                // an unexpanded last (visited grows by the new vertices)
+                b_vis = (long long)(pv - pv0) + (long long)pf0 - (code == kBitDone ? 0ll : (long long)pf);
+            }
+        }
+        __syncthreads();
+        const int code = b_code;
+        level = b_level;
+        vis += b_vis;
+        curmin = w0 + b_fmin;
+        if (code == kBitDone) return code;
+        // the new frontier into the queue (any order: distances are unique)
+        cur = b_cnt;
+        for (int r = tid; r < nw; r += kBfsSmallThreads) {
+            if ((b_f[r >> 6] >> (r & 63)) & 1ull) {
+                const int pos = atomicAdd(&b_app, 1);
+                sq[c ^ 1][pos] = QEnt{w_rp[r], w_rp[r + 1]};
+            }
+        }
+        c ^= 1;
+        __syncthreads();
+        return code;
+    };
+
+    // every iteration expands one level, or a run of bit-parallel levels; at
+    // most n levels exist
     for (;;) {
+        if (band <= kBitBand && nw > 0 && pmax >= 0 && (w0 == 0 || curmin - band >= w0) &&
+            (w0 + nw == n || (long long)pmax + band < (long long)w0 + nw)) {
+            const int code = bit_levels();
+            if (code == kBitDone) {
+                finished = true;
+                break;
+            }
+            if (cur > small_max) {   // hand over: the multi-block kernel reads the global queue
+                QEnt *qc = (level & 1) ? q1 : q0;
+                for (int i = tid; i < cur && i < kBfsSmallCap; i += kBfsSmallThreads) qc[i] = sq[c][i];
+                break;
+            }
+            const int fmax = w0 + b_fmax, prev = b_pmax >= 0 ? w0 + b_pmax : -1;
+            const WinPlan wp = plan_window(curmin, fmax, prev, band, n, w0, nw);
+            pmax = fmax;
+            if (wp.mode) slide(wp);
+            continue;
+        }
         const int pn = p == 2 ? 0 : p + 1;
         if (tid == 0) {   // the slot of the next level, last read two levels ago
             s_cnt[pn] = 0;
@@ -253,53 +508,7 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
         }
         const WinPlan wp = plan_window(mn, mx, pmax, band, n, w0, nw);
         pmax = mx;
-        if (wp.mode) {
-            // write the old window back, then fill the new one
-            for (int i = tid; i < nw; i += kBfsSmallThreads)
-                if (w_dist[i] >= 0) astore_i32(&dist[w0 + i], w_dist[i]);
-            if (tid == 0) s_fit = 0;
-            const int mode = wp.mode, nb0 = wp.base, rows = wp.rows;
-            __syncthreads();
-            for (int i = tid; i <= rows; i += kBfsSmallThreads) w_rp[i] = rp[nb0 + i];
-            __syncthreads();
-            // w_rp is non-decreasing: the fitting rows are a prefix (mode 1)
-            // or a suffix (mode 2) of the rows read, so their count gives both
-            // the window's size and its first row (one atomic per wave)
-            {
-                int cntl = 0;
-                for (int i = tid; i <= rows; i += kBfsSmallThreads)
-                    cntl += (mode == 1 ? w_rp[i] - w_rp[0] : w_rp[rows] - w_rp[i]) <= kWinEntries ? 1 : 0;
-                for (int o = 32; o > 0; o >>= 1) cntl += __shfl_xor(cntl, o, 64);
-                if ((tid & 63) == 0 && cntl) atomicAdd(&s_fit, cntl);
-            }
-            __syncthreads();
-            const int cnt = s_fit;   // >= 1: the first (mode 1) or last (mode 2) row always fits
-            const int fit = cnt - 1;
-            const int a = mode == 1 ? 0 : rows + 1 - cnt;
-            if (a > 0) {   // move the kept row pointers to the front
-                constexpr int kMv = (kWinRows + kBfsSmallThreads) / kBfsSmallThreads;   // >= (kWinRows + 1) / threads
-                int tv[kMv];
-#pragma unroll
-                for (int r = 0; r < kMv; ++r) {
-                    const int i = tid + r * kBfsSmallThreads;
-                    tv[r] = i <= fit ? w_rp[a + i] : 0;
-                }
-                __syncthreads();
-#pragma unroll
-                for (int r = 0; r < kMv; ++r) {
-                    const int i = tid + r * kBfsSmallThreads;
-                    if (i <= fit) w_rp[i] = tv[r];
-                }
-                __syncthreads();
-            }
-            w0 = nb0 + a;
-            nw = fit;
-            e0 = w_rp[0];
-            e1 = w_rp[fit];
-            for (int i = tid; i < e1 - e0; i += kBfsSmallThreads) w_col[i] = col[e0 + i];
-            for (int i = tid; i < fit; i += kBfsSmallThreads) w_dist[i] = atomic_load_i32(&dist[w0 + i]);
-            __syncthreads();
-        }
+        if (wp.mode) slide(wp);
     }
     // the window's distances go back to global memory before anyone reads them
     for (int i = tid; i < nw; i += kBfsSmallThreads)
