@@ -140,22 +140,25 @@ __device__ inline WinPlan plan_window(int fmin, int fmax, int pmax, int band, in
 
 // Bit-parallel levels.  When the matrix's largest |i - j| (band) is at most
 // kBitBand and the frontier with that margin lies inside the window, the
-// first wave runs levels alone on bitsets of the window's rows, one 64-bit
+// first wave runs levels alone on bitsets of the window's rows, one 32-bit
 // word per lane: the next frontier is the union over the offsets d of the
 // frontier shifted by +-d and masked by the rows that have an entry at -+d
 // (the pattern is symmetric, so a row's entries also say who reaches it),
-// minus the visited set.  A level is two lane shuffles and a few word
-// operations per offset, with no barrier and no per-vertex atomics.  Each
-// level's new words go to an LDS ring that the wave turns into distances
-// every kBitRing levels.  The wave hands back to the block when the BFS ends
-// or a new frontier vertex comes within band rows of a window edge (the
-// window then moves); the block rebuilds its queue from the frontier bits.
+// minus the visited set.  A level is two lane shuffles and, per offset, two
+// funnel shifts (alignbit) and two and-or operations, with no barrier and
+// no per-vertex atomics.  Each level's new words go to an LDS ring; when it
+// is full, and when the wave stops, the whole block turns the ring into
+// distances (a thread per newly visited row finds the slot holding its bit)
+// and the wave goes on.  The wave stops when the BFS ends or a new frontier
+// vertex comes within band rows of a window edge (the window then moves);
+// the block then rebuilds its queue from the frontier bits.
 constexpr int kBitBand = 8;
-constexpr int kBitWords = kWinRows / 64;
-constexpr int kBitRing = 64;
-constexpr int kBitDone = 0, kBitMove = 1;
+constexpr int kBitWords = kWinRows / 32;   // one word per lane
+static_assert(kBitWords == 64, "one 32-bit word of window rows per lane of a wave");
+constexpr int kBitRing = 128;
+constexpr int kBitDone = 0, kBitMove = 1, kBitFlush = 2;
 
-__device__ inline unsigned long long wave_sum_u64(unsigned long long v)
+__device__ inline int wave_sum_i(int v)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
@@ -174,11 +177,11 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
     __shared__ int32_t s_cnt[3], s_min[3], s_max[3];
     __shared__ int32_t s_cur, s_level, s_go, s_curmin, s_fit;
     __shared__ long long s_vis;
-    // bit-parallel levels: per-offset row masks (bit i of word w: row 64w + i
+    // bit-parallel levels: per-offset row masks (bit i of word w: row 32w + i
     // has an entry at -d (b_mp) / +d (b_mm)), frontier and visited words, ring
-    __shared__ unsigned long long b_mp[kBitBand + 1][kBitWords], b_mm[kBitBand + 1][kBitWords];
-    __shared__ unsigned long long b_f[kBitWords], b_v[kBitWords], b_ring[kBitRing][kBitWords];
-    __shared__ int32_t b_code, b_level, b_fmin, b_fmax, b_pmax, b_cnt, b_app;
+    __shared__ uint32_t b_mp[kBitBand + 1][kBitWords], b_mm[kBitBand + 1][kBitWords];
+    __shared__ uint32_t b_f[kBitWords], b_v[kBitWords], b_vs[kBitWords], b_ring[kBitRing][kBitWords];
+    __shared__ int32_t b_code, b_level, b_fmin, b_fmax, b_pmax, b_cnt, b_app, b_used, b_base;
     __shared__ long long b_vis;
     const int tid = threadIdx.x;
     const int lsh = __ffs(lanes) - 1;   // lanes is a power of two
@@ -275,9 +278,10 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
     // kBitMove with the state of the last frontier in b_*
     auto bit_levels = [&]() -> int {
         const int wv = tid >> 6, ln = tid & 63;
-        // row masks and the frontier / visited words, one wave per word
-        for (int wd = wv; wd < kBitWords; wd += kBfsSmallThreads / 64) {
-            const int r = wd * 64 + ln;
+        // row masks and the frontier / visited words: one wave per 64 rows
+        // (two words)
+        for (int g = wv; g < kBitWords / 2; g += kBfsSmallThreads / 64) {
+            const int r = g * 64 + ln;
             unsigned lo = 0u, hi = 0u;   // bit d: an entry at offset -d / +d
             bool f = false, v = false;
             if (r < nw) {
@@ -295,121 +299,144 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
             for (int d = 1; d <= kBitBand; ++d) {
                 const unsigned long long ml = __ballot((lo >> d) & 1u), mh = __ballot((hi >> d) & 1u);
                 if (ln == 0) {
-                    b_mp[d][wd] = ml;
-                    b_mm[d][wd] = mh;
+                    b_mp[d][2 * g] = (uint32_t)ml;
+                    b_mp[d][2 * g + 1] = (uint32_t)(ml >> 32);
+                    b_mm[d][2 * g] = (uint32_t)mh;
+                    b_mm[d][2 * g + 1] = (uint32_t)(mh >> 32);
                 }
             }
             const unsigned long long mf = __ballot(f), mv = __ballot(v);
             if (ln == 0) {
-                b_f[wd] = mf;
-                b_v[wd] = mv;
+                b_f[2 * g] = (uint32_t)mf;
+                b_f[2 * g + 1] = (uint32_t)(mf >> 32);
+                b_v[2 * g] = (uint32_t)mv;
+                b_v[2 * g + 1] = (uint32_t)(mv >> 32);
             }
         }
         if (tid == 0) b_app = 0;
         __syncthreads();
+        // wave 0's state survives the flush rounds
+        uint32_t mp[kBitBand + 1], mm[kBitBand + 1];
+        uint32_t F = 0u, V = 0u, Fp = 0u, zone = 0u;
+        int lev = level, pf0 = 0, pv0 = 0;
         if (wv == 0) {
             const int lane = ln;
-            const bool mine = lane < kBitWords;
-            unsigned long long mp[kBitBand + 1], mm[kBitBand + 1];
 #pragma unroll
             for (int d = 1; d <= kBitBand; ++d) {
-                mp[d] = mine ? b_mp[d][lane] : 0ull;
-                mm[d] = mine ? b_mm[d][lane] : 0ull;
+                mp[d] = b_mp[d][lane];
+                mm[d] = b_mm[d][lane];
             }
-            unsigned long long F = mine ? b_f[lane] : 0ull, V = mine ? b_v[lane] : 0ull, Fp = 0ull;
-            const unsigned long long pf0 = wave_sum_u64((unsigned long long)__popcll(F));
-            const unsigned long long pv0 = wave_sum_u64((unsigned long long)__popcll(V));
+            F = b_f[lane];
+            V = b_v[lane];
+            pf0 = wave_sum_i(__popc(F));
+            pv0 = wave_sum_i(__popc(V));
             // rows within band of an edge of the window that is not an edge of the graph
-            unsigned long long zone = 0ull;
-            {
-                const int r0 = lane * 64;
-                const int lo_end = w0 > 0 ? band : 0;                 // rows [0, lo_end)
-                const int hi_beg = w0 + nw < n ? nw - band : nw;      // rows [hi_beg, nw)
-                for (int i = 0; i < 64; ++i) {
-                    const int r = r0 + i;
-                    if (r < nw && (r < lo_end || r >= hi_beg)) zone |= 1ull << i;
+            const int lo_end = w0 > 0 ? band : 0;                 // rows [0, lo_end)
+            const int hi_beg = w0 + nw < n ? nw - band : nw;      // rows [hi_beg, nw)
+            for (int i = 0; i < 32; ++i) {
+                const int r = lane * 32 + i;
+                if (r < nw && (r < lo_end || r >= hi_beg)) zone |= 1u << i;
+            }
+        }
+        int code;
+        for (;;) {   // flush rounds
+            if (wv == 0) {
+                const int lane = ln;
+                b_vs[lane] = V;   // visited before this round
+                const int base = lev;
+                int used = 0;
+                for (;;) {
+                    uint32_t fl = __shfl_up(F, 1, 64), fr = __shfl_down(F, 1, 64);
+                    if (lane == 0) fl = 0u;
+                    if (lane == 63) fr = 0u;
+                    // every offset up to kBitBand: the masks of offsets the
+                    // matrix does not use are zero (no branch per offset).  up:
+                    // bit u from bit u - d (the words F:fl shifted), dn: bit u
+                    // from bit u + d.
+                    uint32_t N = 0u;
+#pragma unroll
+                    for (int d = 1; d <= kBitBand; ++d) {
+                        const uint32_t up = __builtin_amdgcn_alignbit(F, fl, 32 - d);
+                        const uint32_t dn = __builtin_amdgcn_alignbit(fr, F, d);
+                        N = (up & mp[d]) | N;
+                        N = (dn & mm[d]) | N;
+                    }
+                    const uint32_t nb = N & ~V;
+                    if (!__any(nb != 0u)) {
+                        code = kBitDone;
+                        break;
+                    }
+                    V |= nb;
+                    Fp = F;
+                    F = nb;
+                    ++lev;
+                    b_ring[used][lane] = nb;
+                    ++used;
+                    if (__any((nb & zone) != 0u)) {
+                        code = kBitMove;
+                        break;
+                    }
+                    if (used == kBitRing) {
+                        code = kBitFlush;
+                        break;
+                    }
+                }
+                b_v[lane] = V;
+                if (lane == 0) {
+                    b_code = code;
+                    b_used = used;
+                    b_base = base;
                 }
             }
-            const int lev0 = level;
-            int lev = level, used = 0, code;
-            // ring -> distances: lane t takes slot t (levels lev0 + t + 1 of this batch)
-            auto flush = [&](int count, int base_level) {
-                if (lane < count) {
-                    for (int wd = 0; wd < kBitWords; ++wd) {
-                        unsigned long long x = b_ring[lane][wd];
-                        while (x) {
-                            const int b = __ffsll((long long)x) - 1;
-                            x &= x - 1ull;
-                            w_dist[wd * 64 + b] = base_level + lane + 1;
+            __syncthreads();
+            // ring -> distances: a thread per newly visited row
+            {
+                const int used = b_used, base = b_base;
+                for (int r = tid; r < nw; r += kBfsSmallThreads) {
+                    const int w = r >> 5;
+                    const uint32_t bit = 1u << (r & 31);
+                    if (!(b_v[w] & bit) || (b_vs[w] & bit)) continue;
+                    for (int t = 0; t < used; t += 8) {
+                        uint32_t x[8];
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) x[i] = t + i < used ? b_ring[t + i][w] : 0u;
+                        int hit = -1;
+#pragma unroll
+                        for (int i = 7; i >= 0; --i)
+                            if (x[i] & bit) hit = i;
+                        if (hit >= 0) {
+                            w_dist[r] = base + t + hit + 1;
+                            break;
                         }
                     }
                 }
-            };
-            int ring_level = lev0;   // level of the frontier before ring slot 0
-            for (;;) {
-                unsigned long long fl = __shfl_up(F, 1, 64), fr = __shfl_down(F, 1, 64);
-                if (lane == 0) fl = 0ull;
-                if (lane == 63) fr = 0ull;
-                unsigned long long N = 0ull;
-#pragma unroll
-                for (int d = 1; d <= kBitBand; ++d) {
-                    if (d <= band) {
-                        const unsigned long long up = (F << d) | (fl >> (64 - d));
-                        const unsigned long long dn = (F >> d) | (fr << (64 - d));
-                        N |= (up & mp[d]) | (dn & mm[d]);
-                    }
-                }
-                const unsigned long long nb = N & ~V;
-                if (!__any(nb != 0ull)) {
-                    code = kBitDone;
-                    break;
-                }
-                V |= nb;
-                Fp = F;
-                F = nb;
-                ++lev;
-                if (mine) b_ring[used][lane] = nb;
-                ++used;
-                if (__any((nb & zone) != 0ull)) {
-                    code = kBitMove;
-                    break;
-                }
-                if (used == kBitRing) {
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    flush(used, ring_level);
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    ring_level += used;
-                    used = 0;
-                }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            flush(used, ring_level);
-            const unsigned long long pf = wave_sum_u64((unsigned long long)__popcll(F));
-            const unsigned long long pv = wave_sum_u64((unsigned long long)__popcll(V));
-            const int fmin = wave_min_i(F ? lane * 64 + __ffsll((long long)F) - 1 : kIntMax);
-            const int fmax = wave_max_i(F ? lane * 64 + 63 - __clzll((long long)F) : -1);
-            const int pmx = wave_max_i(Fp ? lane * 64 + 63 - __clzll((long long)Fp) : -1);
-            if (mine) b_f[lane] = F;
+            const int c_ = b_code;
+            __syncthreads();   // the ring is read before the wave writes it again
+            if (c_ != kBitFlush) break;
+        }
+        if (wv == 0) {
+            const int lane = ln;
+            code = b_code;
+            const int pf = wave_sum_i(__popc(F));
+            const int pv = wave_sum_i(__popc(V));
+            const int fmin = wave_min_i(F ? lane * 32 + __ffs((int)F) - 1 : kIntMax);
+            const int fmax = wave_max_i(F ? lane * 32 + 31 - __clz((int)F) : -1);
+            const int pmx = wave_max_i(Fp ? lane * 32 + 31 - __clz((int)Fp) : -1);
+            b_f[lane] = F;
             if (lane == 0) {
-                b_code = code;
                 b_level = lev;
                 b_fmin = fmin;
                 b_fmax = fmax;
                 b_pmax = pmx;
-                b_cnt = (int)pf;
+                b_cnt = pf;
                 // frontiers expanded here: the first one and every later one but
                 // an unexpanded last (visited grows by the new vertices)
-                b_vis = (long long)(pv - pv0) + (long long)pf0 - (code == kBitDone ? 0ll : (long long)pf);
+                b_vis = (long long)(pv - pv0) + pf0 - (code == kBitDone ? 0 : pf);
             }
         }
         __syncthreads();
-        const int code = b_code;
+        code = b_code;
         level = b_level;
         vis += b_vis;
         curmin = w0 + b_fmin;
@@ -417,7 +444,7 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
         // the new frontier into the queue (any order: distances are unique)
         cur = b_cnt;
         for (int r = tid; r < nw; r += kBfsSmallThreads) {
-            if ((b_f[r >> 6] >> (r & 63)) & 1ull) {
+            if ((b_f[r >> 5] >> (r & 31)) & 1u) {
                 const int pos = atomicAdd(&b_app, 1);
                 sq[c ^ 1][pos] = QEnt{w_rp[r], w_rp[r + 1]};
             }
