@@ -754,12 +754,21 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
     DevState s;
     bool feat_timed = false;
     double bnorm = 0.0;
+    bool spec_final = false;      // the FP64 phase is the speculative one (its restart residual below)
+    double spec_rr_final = 0.0;
 
     if (!dponly) {
         float *x32 = p.at<float>(p.L.x32), *r32 = p.at<float>(p.L.r32), *q32 = p.at<float>(p.L.q32);
         float *dA32 = p.at<float>(p.L.dA32), *dB32 = p.at<float>(p.L.dB32);
         const float *x32_src = x32;   // x~ handed to the FP64 restart
         bool broke = false;
+        // speculative FP64 phase (below): started from the tightest candidate's
+        // state when the run-ahead has crossed every candidate before the
+        // features are in; kept if the kNN chooses that candidate
+        bool spec64 = false, spec_keep = false;
+        DevState s64{};
+        int it64_next = 0;
+        double spec_rr = 0.0;
         if (autoe) {
             // Algorithm II.  The 2BFS runs on the side stream from a host
             // thread.  Meanwhile the main stream does the k0-iteration prefix
@@ -789,6 +798,25 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
             if (rc == MPCG_OK && sp0.bnorm2 > 0.0 && !broke) {
                 launch_set_spec(c->stream, p.st, abs_tol ? 1.0 : std::sqrt(sp0.bnorm2), sp0.iter, maxit1);
                 rc = cg_loop<float>(c, ps, x32, r32, q32, dA32, dB32, sp0.iter, 0, &s, &bfs_done, &it_next);
+                if (rc == MPCG_OK && !s.live && s.reason == kConverged && s.cross_iter[kNumEps - 1] >= 0 &&
+                    !bfs_done.load()) {
+                    // every candidate crossed and the features still pending: x~ is
+                    // the state Algorithm II restarts from if the kNN picks the
+                    // tightest candidate, so that FP64 phase starts now (beside
+                    // the BFS); another choice discards it and restarts from its copy
+                    HIPCHK(hipEventRecord(c->tm[3], c->stream));
+                    run_restart(c->stream, ps, x32, x, b, r64, dA64, dB64, 0, eps2, abs_tol, maxit2);
+                    HIPCHK(hipGetLastError());
+                    rc = read_state(c, p, &s64);
+                    if (rc == MPCG_OK) {
+                        spec64 = true;
+                        spec_rr = s64.bnorm2 > 0.0 ? std::sqrt(s64.gamma) / std::sqrt(s64.bnorm2) : 0.0;
+                        it64_next = s64.iter;
+                        if (s64.live)
+                            rc = cg_loop<double>(c, ps, x, r64, q64, dA64, dB64, s64.iter, 0, &s64, &bfs_done,
+                                                 &it64_next);
+                    }
+                }
             }
             bfs_thread.join();
             if (rc == MPCG_OK) rc = rc_bfs;
@@ -806,6 +834,7 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
             S.eps1_class = cls;
             S.eps1_used = e1;
             if (exact) S.flags |= MPCG_FLAG_KNN_EXACT;
+            spec_keep = spec64 && cls - 2 == kNumEps - 1;
             if (!broke) {
                 const int ci = cls - 2;
                 if (s.cross_iter[ci] >= 0) {
@@ -840,10 +869,20 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
         S.n1 = s.iter;
         bnorm = std::sqrt(s.bnorm2);
         S.relres_sp = std::sqrt(s.gamma) / bnorm;
-        HIPCHK(hipEventRecord(c->tm[3], c->stream));
-        // restart in FP64 from float64(x~) with a freshly computed residual
-        run_restart(c->stream, p, x32_src, x, b, r64, dA64, dB64, 0, eps2, abs_tol, maxit2);
-        HIPCHK(hipGetLastError());
+        spec_final = spec_keep;
+        spec_rr_final = spec_rr;
+        if (spec_keep) {
+            // the speculative FP64 phase is the chosen one: it continues
+            if (s64.live) {
+                rc = cg_loop<double>(c, p, x, r64, q64, dA64, dB64, it64_next, 0, &s64);
+                if (rc != MPCG_OK) return rc;
+            }
+        } else {
+            HIPCHK(hipEventRecord(c->tm[3], c->stream));
+            // restart in FP64 from float64(x~) with a freshly computed residual
+            run_restart(c->stream, p, x32_src, x, b, r64, dA64, dB64, 0, eps2, abs_tol, maxit2);
+            HIPCHK(hipGetLastError());
+        }
     } else {
         // FP64-only CG from x0 = 0 through the restart kernel: r = b - A*0 = b
         // exactly, with the same reductions as the mixed path's restart.
@@ -857,6 +896,7 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
     if (s.bnorm2 == 0.0) goto zero_rhs;
     bnorm = std::sqrt(s.bnorm2);
     S.relres_restart_true = std::sqrt(s.gamma) / bnorm;
+    if (spec_final) S.relres_restart_true = spec_rr_final;
     {
         const double thr2 = abs_tol ? eps2 : eps2 * bnorm;
         for (;;) {

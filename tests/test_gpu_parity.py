@@ -436,6 +436,38 @@ def test_algorithm2_runahead_equals_algorithm1_bitwise(torch_mod, tmp_path, name
         assert s2.n1 == 20   # the prefix already passed eps1; Algorithm II stops after it
 
 
+@pytest.mark.parametrize("t", [7, 4])
+def test_algorithm2_speculative_fp64_equals_algorithm1_bitwise(torch_mod, tmp_path, t):
+    """A 2BFS far slower than the CG (tridiagonal band, mu = 1.1, n = 200000:
+    2 x 199999 levels, while the FP32 recurrence passes 1e-7 within a few
+    dozen iterations): the run-ahead crosses every candidate before the
+    features are in, so the FP64 phase starts from the tightest candidate's
+    state beside the BFS.  With the class forced to 7 that phase is kept, with
+    4 it is discarded and the restart comes from the class-4 copy; both must
+    equal Algorithm I with eps1 = 10^-t (N1, N2 and x bit for bit)."""
+    from paper_2412_08059_amd import Solver
+    from workloads import paper_family as PF
+    a = PF.random_banded(200_000, 3, 1.0, 1.1, seed=4)
+    _, b = W.rhs(a, seed=12)
+    mpath = tmp_path / f"one_class_{t}.txt"
+    oracle.save_model(oracle.KnnModel.from_samples(np.array([[1.0, 1, 1, 1], [2.0, 2, 2, 2]]), [t, t], k=1),
+                      str(mpath))
+    s = Solver(a.n, a.nnz, model=str(mpath))
+    A, B = dev(a), t64(torch_mod, b)
+    st2, x2, s2 = s.solve(A, B, 0.0, 1e-10)
+    x2 = x2.cpu().numpy()
+    st1, x1, s1 = s.solve(A, B, 10.0 ** -t, 1e-10)
+    s.close()
+    print(f"class {t}: auto n1={s2.n1} n2={s2.n2} t_feat={s2.t_feat_ms:.1f} t_sp={s2.t_sp_ms:.1f} "
+          f"t_dp={s2.t_dp_ms:.1f} ms; eps1 n1={s1.n1} n2={s1.n2}", flush=True)
+    assert st1 == st2 == 0 and s2.eps1_class == t and s2.feat.pdiam == 199_999
+    assert (s2.n1, s2.n2) == (s1.n1, s1.n2)
+    assert np.array_equal(x2, x1.cpu().numpy())
+    assert s2.relres_restart_true == s1.relres_restart_true
+    if t == 7:   # the FP64 phase began before the features were in
+        assert s2.t_sp_ms < s2.t_feat_ms
+
+
 # ----------------------------------------------- Jacobi-preconditioned CG --
 
 @pytest.fixture(scope="module")
