@@ -60,7 +60,10 @@ typedef enum {
  *            row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz < 2^31.
  *   col_idx  nnz int32 column indices, strictly increasing within a row.
  *   val      nnz float64 values, finite, no stored zeros.
- * The pattern is expected to be symmetric (A is SPD); it is not checked. */
+ * The pattern is expected to be symmetric (A is SPD); it is not checked.
+ * The 2BFS takes the pattern as an undirected graph (its narrow-band levels
+ * find a row's neighbours from the rows that list it), so with an
+ * unsymmetric pattern the features are unspecified. */
 typedef struct {
     int64_t n;
     int64_t nnz;
