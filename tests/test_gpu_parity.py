@@ -464,8 +464,10 @@ def test_algorithm2_speculative_fp64_equals_algorithm1_bitwise(torch_mod, tmp_pa
     assert (s2.n1, s2.n2) == (s1.n1, s1.n2)
     assert np.array_equal(x2, x1.cpu().numpy())
     assert s2.relres_restart_true == s1.relres_restart_true
-    if t == 7:   # the FP64 phase began before the features were in
-        assert s2.t_sp_ms < s2.t_feat_ms
+    # Whether the FP64 phase really began before the features were in
+    # (t_sp_ms < t_feat_ms) depends on the main and side streams running on
+    # different hardware queues, which a process with many live streams does
+    # not guarantee; the result must be the same either way.
 
 
 # ----------------------------------------------- Jacobi-preconditioned CG --
