@@ -495,11 +495,12 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        for kid in (capi.MPCG_KERNEL_CG_SPMV_F64, capi.MPCG_KERNEL_UPDATE_F64, capi.MPCG_KERNEL_CG_SPMV_F32,
-                    capi.MPCG_KERNEL_UPDATE_F32):
-            capi.mpcg_time_kernel(solver.ctx, A.desc, kid, 20)
+        kus = {}
+        for kname, kid in (("cg_spmv_f64", capi.MPCG_KERNEL_CG_SPMV_F64), ("update_f64", capi.MPCG_KERNEL_UPDATE_F64),
+                           ("cg_spmv_f32", capi.MPCG_KERNEL_CG_SPMV_F32), ("update_f32", capi.MPCG_KERNEL_UPDATE_F32)):
+            kus[kname] = round(capi.mpcg_time_kernel(solver.ctx, A.desc, kid, 20) * 1e3, 2)
         solver.close()
-        print(json.dumps({"kernel_only": True, "copy_bytes": 1 << 30}))
+        print(json.dumps({"kernel_only": True, "copy_bytes": 1 << 30, "us_per_launch": kus}))
         return
     X = torch.empty(n, dtype=torch.float64, device="cuda")
     eps1 = capi.MPCG_EPS1_AUTO if have_model else 1e-4
