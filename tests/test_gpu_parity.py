@@ -146,6 +146,11 @@ BFS_CASES = [
     ("er_50k", lambda: W.er_laplacian(50_000, 16, seed=1), [0, 123]),
     ("xstar", lambda: W.extended_star(40, 25, extra_edges=30, seed=4), [0, 5]),
     ("path_3000", lambda: W.path(3000), [0, 1500]),
+    # narrow bands (|i - j| <= 8): the one-workgroup kernel's bit-parallel levels
+    ("band_holes_30001", lambda: __import__("workloads").paper_family.random_banded(30_001, 9, 0.4, 1.1, seed=3),
+     [0, 15_000, 30_000]),
+    ("path_1000", lambda: W.path(1000), [500]),
+    ("banded_100003", lambda: W.banded(100_003, 8, seed=2), [100_002, 777]),
 ]
 
 
@@ -179,6 +184,7 @@ PD_CASES = {
     "er_50k": lambda: W.er_laplacian(50_000, 16, seed=5),
     "xstar": lambda: W.extended_star(10, 30, extra_edges=20, seed=1),
     "union_components": _union_graph,
+    "band_holes_30001": lambda: __import__("workloads").paper_family.random_banded(30_001, 9, 0.4, 1.1, seed=3),
     "diagonal_100": lambda: W.CSR.from_scipy(sp.identity(100, format="csr") * 2.0),
 }
 
