@@ -43,6 +43,7 @@ struct mpcg_ctx {
     bool force_csr = false;   // MPCG_FORCE_CSR=1: always use the CSR-stream kernels
     int sell_batch = 4;       // MPCG_SELL_BATCH=4|8: loads in flight per row in the SELL kernels
     int sell_bf = 1;          // MPCG_SELL_BF=0..3: whole-batch loads (bit 0: FP32 kernels, bit 1: FP64)
+    int sell_split = -1;      // MPCG_SELL_SPLIT=0|1: two-launch CG product (-1: for 32-bit columns)
     int cg_grid = kMaxGrid;   // MPCG_CG_GRID: most blocks of a CG product launch
     int up_grid = kUpdateGrid;   // MPCG_UP_GRID: most blocks of a CG update launch
     mpcg::batch::Engine *eng = nullptr;   // batched engine (own thread and stream), if started
@@ -233,6 +234,8 @@ mpcg_status ingest(mpcg_ctx *c, const mpcg_csr *A, const double *b, bool need_va
         m.idx16 = s.max_band < 32768 ? 1 : 0;
         m.batch = c->sell_batch;
         m.bf_mask = c->sell_bf;
+        // scattered gathers (columns beyond 16-bit offsets): one gathered vector, not two
+        m.split = c->sell_split >= 0 ? c->sell_split : (m.idx16 ? 0 : 1);
         int64_t g = ((int64_t)nsl + kBlock / 64 - 1) / (kBlock / 64);
         if (g > c->cg_grid) g = c->cg_grid;
         m.grid = (int32_t)(g < 1 ? 1 : g);
@@ -607,6 +610,8 @@ mpcg_status mpcg_create(mpcg_ctx **out, const mpcg_options *opt, void *hip_strea
         if (bt && bt[0] == '8') c->sell_batch = 8;
         const int sbf = env_int("MPCG_SELL_BF", 1);
         c->sell_bf = sbf >= 0 && sbf <= 3 ? sbf : 1;
+        const int ssp = env_int("MPCG_SELL_SPLIT", -1);
+        c->sell_split = ssp == 0 || ssp == 1 ? ssp : -1;
         const int cgg = env_int("MPCG_CG_GRID", kMaxGrid);
         c->cg_grid = cgg >= 64 && cgg <= kMaxGrid ? cgg : kMaxGrid;
         const int bg = env_int("MPCG_BFS_GRID", kBfsLevelBlocks);

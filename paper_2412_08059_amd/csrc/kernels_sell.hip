@@ -224,7 +224,12 @@ void launch_ingest_sell(hipStream_t s, const void *rp_in, int rp_is_i64, const i
 
 // -------------------------------------------------------------- kernels --
 
-enum SellMode { kSellCg = 0, kSellRestart = 1, kSellResid = 2, kSellPlain = 3 };
+// kSellDir + kSellCgD: the CG product split in two launches for matrices
+// whose gathers are scattered (32-bit columns): the first takes the prologue
+// of kSellCg and forms d = r + beta d_old (and the deferred x update) row by
+// row, the second gathers only d.  The arithmetic is that of kSellCg; a
+// scattered gather of one vector instead of two is what it saves.
+enum SellMode { kSellCg = 0, kSellRestart = 1, kSellResid = 2, kSellPlain = 3, kSellDir = 4, kSellCgD = 5 };
 
 template <typename T>
 struct SellArgs {
@@ -273,7 +278,14 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
     bool x_pending = false;   // x += alpha_{it-1} d_{it-1} still to apply in the main loop
     const T *dold = nullptr;
     T *dnew = nullptr;
-    if (MODE == kSellCg) {
+    if (MODE == kSellCgD) {   // the direction is formed: skip only after a stop
+        __shared__ int s_skip2;
+        if (tid == 0) s_skip2 = st->stop_it <= a.it;
+        __syncthreads();
+        if (s_skip2) return;
+        dold = (a.it & 1) ? a.dA : a.dB;   // the d formed by kSellDir of this iteration
+    }
+    if (MODE == kSellCg || MODE == kSellDir) {
         const int it = a.it;
         __shared__ int s_skip, s_xdone;
         if (tid == 0) {
@@ -332,6 +344,16 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
             beta = (T)(rho / rhop);
         }
     }
+    if (MODE == kSellDir) {   // d = r + beta d_old and the deferred x update, row by row
+        for (SliceWalk w = slice_walk(a.nslices); w.g < w.g_end; w.g += w.step) {
+            const int i = w.g * kBlock + tid;
+            if (i >= a.n) continue;
+            const T dof = dold[i];
+            if (x_pending) a.x[i] = fma_t<T>(alpha_prev, dof, a.x[i]);
+            dnew[i] = fma_t<T>(beta, dof, a.r[i]);
+        }
+        return;
+    }
 
     const IDX *scol = static_cast<const IDX *>(a.scol);
     const int lb = blockIdx.x;   // partial slot (fixed per block, so sums keep one order)
@@ -365,6 +387,7 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
 #pragma unroll
                 for (int j = 0; j < B; ++j) {
                     if (MODE == kSellCg) g[j] = fma_t<T>(beta, dold[c[j]], a.r[c[j]]);
+                    else if (MODE == kSellCgD) g[j] = dold[c[j]];
                     else if (MODE == kSellPlain) g[j] = a.xin[c[j]];
                     else g[j] = a.x32 ? (T)a.x32[c[j]] : (T)a.x64in[c[j]];
                 }
@@ -381,6 +404,7 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
                 for (int j = 0; j < B; ++j) {
                     if (k0 + j < len) {
                         if (MODE == kSellCg) g[j] = fma_t<T>(beta, dold[c[j]], a.r[c[j]]);
+                        else if (MODE == kSellCgD) g[j] = dold[c[j]];
                         else if (MODE == kSellPlain) g[j] = a.xin[c[j]];
                         else g[j] = a.x32 ? (T)a.x32[c[j]] : (T)a.x64in[c[j]];
                     }
@@ -393,6 +417,10 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
         if (has) {
             if (MODE == kSellPlain) {
                 a.yout[row] = acc;
+            } else if (MODE == kSellCgD) {
+                const T dn = dold[row];
+                a.q[row] = acc;
+                s[0] = fma((double)dn, (double)acc, s[0]);
             } else if (MODE == kSellCg) {
                 const T dof = dold[row];
                 if (x_pending) a.x[row] = fma_t<T>(alpha_prev, dof, a.x[row]);
@@ -471,7 +499,12 @@ void launch_sell_cg_spmv(hipStream_t s, const SellMat &m, const T *r, T *dA, T *
     a.it = it; a.it0 = it0; a.r = r; a.dA = dA; a.dB = dB; a.q = q; a.up = up; a.nup = nup;
     a.x = x; a.snap = snap; a.pc = pc;
     a.part = part; a.st = st;
-    sell_launch<kSellCg, T>(s, m, a);
+    if (m.split) {
+        sell_launch<kSellDir, T>(s, m, a);
+        sell_launch<kSellCgD, T>(s, m, a);
+    } else {
+        sell_launch<kSellCg, T>(s, m, a);
+    }
 }
 
 void launch_sell_restart(hipStream_t s, const SellMat &m, const float *x32, double *x64,

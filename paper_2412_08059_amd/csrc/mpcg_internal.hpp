@@ -121,6 +121,7 @@ struct SellMat {
     int32_t n, nslices, grid, idx16;
     int32_t batch;   // row entries whose loads are issued together: 4 or 8
     int32_t bf_mask; // whole-batch loads without a guard per entry: bit 0 FP32 kernels, bit 1 FP64
+    int32_t split;   // CG product in two launches (direction, then a one-vector gather)
 };
 
 Layout plan_layout(int64_t n, int64_t nnz);

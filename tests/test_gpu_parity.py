@@ -210,6 +210,8 @@ SOLVE_CASES = {
     "varcoef3d_24": (lambda: W.varcoef3d(24, seed=0), [1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7]),
     "banded_30k": (lambda: W.banded(30_000, 8, seed=0), [1e-3, 1e-6]),
     "er_30k": (lambda: W.er_laplacian(30_000, 16, seed=0), [1e-3, 1e-5]),
+    # offsets beyond 16 bits: 32-bit columns, the CG product in two launches
+    "er_100k_wide": (lambda: W.er_laplacian(100_000, 16, seed=3), [1e-4, 1e-7]),
     "star_1001_absolute": (lambda: W.star(1001, mu=1.1), [1e-2, 1e-5]),
 }
 
@@ -235,6 +237,31 @@ def test_solve_parity(any_solver, torch_mod, name):
         res = np.linalg.norm(b - oracle.spmv64(a, xg)) / np.linalg.norm(b)
         assert res <= 1e-10 * (1 + 1e-6)
         assert np.linalg.norm(xg - r.x) / np.linalg.norm(r.x) <= 1e-8
+
+
+@pytest.mark.parametrize("eps1", [-1.0, 1e-5, 0.0])
+def test_split_product_equals_fused_bitwise(torch_mod, eps1):
+    """On a matrix with 32-bit columns the CG product runs as two launches
+    (direction, then a one-vector gather); the arithmetic is the fused
+    product's, so N1, N2, the eps1 class and x are the same bit for bit."""
+    from paper_2412_08059_amd import Solver
+    a = W.er_laplacian(100_000, 16, seed=3)
+    _, b = W.rhs(a, seed=5)
+    A, B = dev(a), t64(torch_mod, b)
+    got = {}
+    for split in ("1", "0"):
+        os.environ["MPCG_SELL_SPLIT"] = split
+        try:
+            s = Solver(a.n, a.nnz, model=TEST_MODEL)
+        finally:
+            del os.environ["MPCG_SELL_SPLIT"]
+        st, x, S = s.solve(A, B, eps1, 1e-10)
+        s.close()
+        assert st == 0
+        got[split] = (S.n1, S.n2, S.eps1_class, x.cpu().numpy().copy())
+    print(f"eps1={eps1}: split n1/n2={got['1'][:2]} fused={got['0'][:2]}", flush=True)
+    assert got["1"][:3] == got["0"][:3]
+    assert np.array_equal(got["1"][3].view(np.uint64), got["0"][3].view(np.uint64))
 
 
 def test_eps1_above_one_is_fp64_only_bitwise(solver, torch_mod):
