@@ -243,7 +243,9 @@ mpcg_status mpcg_diameter_multi(mpcg_ctx *ctx, const mpcg_csr *A, const int32_t 
 mpcg_status mpcg_last_kernel_ms(const mpcg_ctx *ctx, double *ms);
 
 /* Kernels that mpcg_time_kernel can time (the ones a solve launches). */
-#define MPCG_KERNEL_CG_SPMV_F64 0   /* previous x += alpha d, direction update, q = A d, d.q; FP64 */
+#define MPCG_KERNEL_CG_SPMV_F64 0   /* previous x += alpha d, direction update, q = A d, d.q; FP64
+                                       (two launches, direction then product, for a matrix whose
+                                       column offsets exceed 16 bits; timed together) */
 #define MPCG_KERNEL_CG_SPMV_F32 1   /* the same on float32(A), FP32 vectors */
 #define MPCG_KERNEL_UPDATE_F64 2    /* alpha, r -= alpha q, r.r; FP64 */
 #define MPCG_KERNEL_UPDATE_F32 3
