@@ -573,6 +573,16 @@ k_bfs_small(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
 // the level after next.
 constexpr int kBfsItems = 4;
 
+// A level whose frontier holds at least 1/kBottomUp of the vertices is
+// expanded bottom-up: every unvisited vertex scans its row for a neighbour at
+// the current level and stops at the first.  On a low-diameter graph (the
+// Erdos-Renyi one) the middle levels reach most vertices, and there this
+// reads a few entries per unvisited vertex where top-down would try every
+// edge of the frontier with an atomic.  The decision uses only the level's
+// size, which is final when the launch starts, so every block takes it alike.
+// Distances are unique, so the result does not depend on the direction.
+constexpr int kBottomUp = 8;
+
 __global__ void __launch_bounds__(kBlock)
 k_bfs_level(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int32_t *dist,
             QEnt *q0, QEnt *q1, int32_t n, int32_t lanes, int32_t k, int32_t precheck, DevState *st)
@@ -613,6 +623,52 @@ k_bfs_level(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
     int *cnt_next = &st->bfs_cnt[(L + 1) & 3];
     const unsigned long long lt = (1ull << lane) - 1ull;
     int wmin = kIntMax;
+    if ((int64_t)cur * kBottomUp >= n) {
+        if (threadIdx.x == 0) s_min = kIntMax;
+        // the vertex loop is uniform over the block (its waves meet at barriers)
+        for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += stride) {
+            const int64_t vv = base + threadIdx.x;
+            bool found = false;
+            QEnt nv{0, 0};
+            if (vv < n && dist[vv] < 0) {
+                const int b = rp[vv], e = rp[vv + 1];
+                for (int j = b; j < e; ++j) {
+                    const int u = col[j];
+                    if ((unsigned)u < (unsigned)n && dist[u] == L) {
+                        found = true;
+                        break;
+                    }
+                }
+                if (found) {
+                    dist[vv] = L + 1;   // only this thread writes vv; readers here compare with L
+                    nv = QEnt{b, e};
+                }
+            }
+            const unsigned long long m = __ballot(found);
+            if (lane == 0) s_cnt[wv] = __popcll(m);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int sum = 0;
+                for (int w = 0; w < kBlock / 64; ++w) {
+                    const int c = s_cnt[w];
+                    s_cnt[w] = sum;
+                    sum += c;
+                }
+                s_base = sum > 0 ? atomicAdd(cnt_next, sum) : 0;
+            }
+            __syncthreads();
+            if (found) {
+                qn[s_base + s_cnt[wv] + __popcll(m & lt)] = nv;
+                wmin = wmin < (int)vv ? wmin : (int)vv;
+            }
+            __syncthreads();   // s_cnt and s_base are reused by the next step
+        }
+        wmin = wave_min_i(wmin);
+        if (lane == 0 && wmin != kIntMax) atomicMin(&s_min, wmin);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_min != kIntMax) atomicMin(&st->bfs_min[(L + 1) & 3], s_min);
+        return;
+    }
     const int64_t items = (int64_t)cur * lanes;
     if (threadIdx.x == 0) s_min = kIntMax;
     // the batch loop is uniform over the block (its waves meet at barriers)
