@@ -54,6 +54,7 @@ enum BfsMode : int32_t {
 constexpr int kSlicesPerBlock = kBlock / 64;
 constexpr int32_t kErrGuard = 64;     // a bounded device loop ran out (union-find)
 constexpr int kSmallBfsCap = 2048;   // frontier kept in LDS by the one-block-per-system kernel
+constexpr int kVisBits = 1 << 20;     // rows up to which that kernel keeps the visited set in LDS (128 KB)
 constexpr int kSmallBfsLevels = 64;  // default of the levels one launch may expand for one system
 
 struct alignas(256) BSys {
@@ -80,7 +81,8 @@ struct alignas(256) BSys {
     // 2BFS
     int32_t bfs_mode, bfs_sweep, bfs_level, bfs_cnt;
     int32_t bfs_nxt, ncomp, pdiam, bfs_t;
-    int32_t bfs_u, small, bfs_err, pad1;   // bfs_err: kErrGuard from the BFS kernels
+    int32_t bfs_u, small, bfs_err;         // bfs_err: kErrGuard from the BFS kernels
+    int32_t vis_lvl;                       // BArena::vis of the system matches dist after this level
     int64_t padded;                        // SELL-64 entries of the system (admission scan)
     unsigned long long comp_best;
     int64_t item0;                         // first BFS work item of this system in the current level
@@ -101,6 +103,7 @@ struct BArena {
     float *x32, *r32, *q32, *dA32, *dB32;
     float *snap32;                         // kNumEps copies of x~, copy t at t * max_slices * 64
     int32_t *dist, *q0, *q1, *label, *tarr;
+    uint32_t *vis;                         // visited bits of the small-level BFS, one per row
     unsigned long long *best;
     // per entry
     int32_t *col;

@@ -80,7 +80,7 @@ size_t arena_bytes(int32_t max_sys, int32_t max_slices, int64_t max_entries)
     t += up256(4 * rows);                                             // rowlen
     t += up256(8 * rows) * 6 + up256(4 * rows) * 5;                   // FP64 and FP32 vectors
     t += up256(4 * rows * kNumEps);                                   // run-ahead copies of x~
-    t += up256(4 * rows) * 5 + up256(8 * rows);                       // BFS
+    t += up256(4 * rows) * 5 + up256(8 * rows) + up256(rows / 8);     // BFS
     t += up256(4 * e) + up256(8 * e) + up256(4 * e);                  // col, v64, v32
     t += up256(4 * (size_t)max_sys) * 2 + up256(8 * (size_t)max_sys) + 256 + 256;
     return t;
@@ -119,6 +119,7 @@ BArena carve(void *base, int32_t max_sys, int32_t max_slices, int64_t max_entrie
     a.label = reinterpret_cast<int32_t *>(take(4 * rows));
     a.tarr = reinterpret_cast<int32_t *>(take(4 * rows));
     a.best = reinterpret_cast<unsigned long long *>(take(8 * rows));
+    a.vis = reinterpret_cast<uint32_t *>(take(rows / 8));
     a.col = reinterpret_cast<int32_t *>(take(4 * e));
     a.v64 = reinterpret_cast<double *>(take(8 * e));
     a.v32 = reinterpret_cast<float *>(take(4 * e));
@@ -805,21 +806,72 @@ __global__ void __launch_bounds__(kBlock) k_bfs_level_batch(BArena a)
 // the frontier in LDS, each level's result also written to the global queue.
 // Leaves the system as the plan expects: bfs_level = last level expanded,
 // bfs_nxt = the size of the next frontier (queue (bfs_level + 1) & 1).
+// A system of at most kVisBits rows also keeps its visited set in LDS, one
+// bit per row: a level then claims a vertex with an LDS atomic and stores
+// its distance without waiting, where the other systems claim it with a
+// compare-and-swap on dist in HBM.  Either way every vertex is claimed once,
+// at its BFS level.  The bits come from the system's copy in HBM when the
+// previous launch on it was this kernel (vis_lvl = the level before this
+// one), otherwise from dist; the words that changed go back to HBM at exit.
 __global__ void __launch_bounds__(kBlock) k_bfs_small_batch(BArena a, int32_t max_levels)
 {
     __shared__ int32_t sq[2][kSmallBfsCap];
-    __shared__ int32_t s_cnt;
+    __shared__ __align__(16) uint32_t vis[kVisBits / 32];
+    __shared__ int32_t s_cnt, s_lo, s_hi;
     if ((int)blockIdx.x >= a.counts[1]) return;
     const int s = a.small_sys[blockIdx.x];
     BSys &S = a.sys[s];
     const int lanes = S.lanes, row0 = S.row0;
     const int lsh = __ffs(lanes) - 1;   // lanes is a power of two
+    const bool lds_vis = S.n <= kVisBits;
     int level = S.bfs_level;
     int cur = S.bfs_cnt;
     {
         const int32_t *qc = (level & 1) ? a.q1 : a.q0;
         for (int i = threadIdx.x; i < cur; i += kBlock) sq[0][i] = qc[row0 + i];
     }
+    // words of the system's bits: two per 64-row slice, nw <= kVisBits / 32;
+    // rows row0 .. row0 + 32 * nw - 1 are the system's own (padded) rows
+    const int nw = ((S.n + 63) >> 6) * 2;
+    const bool reuse = lds_vis && S.vis_lvl == level - 1;
+    if (lds_vis && reuse) {
+        const uint2 *vg = reinterpret_cast<const uint2 *>(a.vis + (row0 >> 5));   // row0 % 64 == 0
+        uint2 *vl = reinterpret_cast<uint2 *>(vis);
+        for (int p0 = 0; p0 < nw / 2; p0 += 8 * kBlock) {
+            uint2 t[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int p = p0 + k * kBlock + (int)threadIdx.x;
+                if (p < nw / 2) t[k] = vg[p];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int p = p0 + k * kBlock + (int)threadIdx.x;
+                if (p < nw / 2) vl[p] = t[k];
+            }
+        }
+    } else if (lds_vis) {
+        // one word per thread from 32 consecutive distances (eight 16-byte loads)
+        const int4 *dg = reinterpret_cast<const int4 *>(a.dist + row0);
+        for (int w = threadIdx.x; w < nw; w += kBlock) {
+            int4 t[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) t[k] = dg[w * 8 + k];
+            uint32_t bits = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                bits |= (uint32_t)(t[k].x >= 0) << (4 * k) | (uint32_t)(t[k].y >= 0) << (4 * k + 1) |
+                        (uint32_t)(t[k].z >= 0) << (4 * k + 2) | (uint32_t)(t[k].w >= 0) << (4 * k + 3);
+            const int r = S.n - w * 32;   // rows of this word inside the system (padding is not visited)
+            if (r < 32) bits &= r <= 0 ? 0u : ((1u << r) - 1u);
+            vis[w] = bits;
+        }
+    }
+    if (threadIdx.x == 0) {
+        s_lo = reuse ? nw : 0;   // empty range [nw, -1] (no overflow in s_lo + tid); a rebuilt set goes back whole
+        s_hi = reuse ? -1 : nw - 1;
+    }
+    int lo = INT32_MAX, hi = -1;
     int c = 0, nxt = 0;
     for (int rep = 0; rep < max_levels; ++rep) {
         if (threadIdx.x == 0) s_cnt = 0;
@@ -833,8 +885,22 @@ __global__ void __launch_bounds__(kBlock) k_bfs_small_batch(BArena a, int32_t ma
             const int e = a.rowlen[u];
             for (int j = l; j < e; j += lanes) {
                 const int v = a.col[base + (int64_t)j * 64];
-                if (v == u || a.dist[v] >= 0) continue;
-                if (atomicCAS(&a.dist[v], -1, level + 1) == -1) {
+                if (v == u) continue;
+                bool won;
+                if (lds_vis) {
+                    // admission keeps every column inside [row0, row0 + n)
+                    const int lv = v - row0;
+                    const uint32_t bit = 1u << (lv & 31);
+                    won = !(vis[lv >> 5] & bit) && !(atomicOr(&vis[lv >> 5], bit) & bit);
+                    if (won) {
+                        a.dist[v] = level + 1;
+                        lo = min(lo, lv >> 5);
+                        hi = max(hi, lv >> 5);
+                    }
+                } else {
+                    won = a.dist[v] < 0 && atomicCAS(&a.dist[v], -1, level + 1) == -1;
+                }
+                if (won) {
                     const int pos = atomicAdd(&s_cnt, 1);
                     if (pos < kSmallBfsCap) sq[c ^ 1][pos] = v;
                     qn[row0 + pos] = v;
@@ -849,10 +915,20 @@ __global__ void __launch_bounds__(kBlock) k_bfs_small_batch(BArena a, int32_t ma
         cur = nxt;
         c ^= 1;
     }
+    if (lds_vis) {
+        if (hi >= 0) {
+            atomicMin(&s_lo, lo);
+            atomicMax(&s_hi, hi);
+        }
+        __syncthreads();
+        // 0 <= s_lo, s_hi < nw: the system's own words
+        for (int w = s_lo + (int)threadIdx.x; w <= s_hi; w += kBlock) a.vis[(row0 >> 5) + w] = vis[w];
+    }
     if (threadIdx.x == 0) {
         S.bfs_level = level;
         S.bfs_cnt = cur;
         S.bfs_nxt = nxt;
+        if (lds_vis) S.vis_lvl = level;
     }
 }
 
@@ -951,6 +1027,7 @@ __global__ void k_b_bfs_arm(BArena a, int32_t sys, int32_t sweep)
         BSys &S = a.sys[sys];
         S.bfs_level = -1;
         S.bfs_sweep = sweep;
+        S.vis_lvl = INT32_MIN;   // the stored visited bits belong to an earlier sweep
         S.bfs_mode = kBfsRun;
         S.comp_best = 0ull;
     }
