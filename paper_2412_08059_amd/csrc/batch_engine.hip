@@ -140,6 +140,8 @@ struct Engine {
     int32_t hi_sys = 0, hi_slice = 0;
     int64_t group = 0;
     int small_levels = kSmallBfsLevels;   // MPCG_BATCH_SMALL_LEVELS
+    int small_cap = kSmallBfsCapDefault;  // MPCG_BATCH_SMALL_CAP
+    int64_t small_work = INT64_MAX;       // MPCG_BATCH_SMALL_WORK
 
     std::mutex mu;
     std::condition_variable cv;
@@ -462,7 +464,7 @@ bool Engine::bfs_pump()
         if ((sl.feat == 3 && !sl.bfs_ready) || sl.feat == 5) enq = true;   // waiting for a copy that shows the result
     }
     if (run)
-        for (int r = 0; r < kBfsRoundsPerPump; ++r) launch_bfs_round(sb, a, hi_sys, small_levels);
+        for (int r = 0; r < kBfsRoundsPerPump; ++r) launch_bfs_round(sb, a, hi_sys, small_levels, small_cap, small_work);
     if (hipGetLastError() != hipSuccess) return false;
     if (!(enq || run) || hi_sys <= 0) return true;
     bmirror_n = hi_sys;
@@ -595,6 +597,12 @@ Engine *engine_create(int device, const mpcg_options &opt, const KnnModel *model
         const char *r = std::getenv("MPCG_BATCH_SMALL_LEVELS");
         const int v = (r && r[0]) ? std::atoi(r) : 0;
         if (v >= 1 && v <= 4096) e->small_levels = v;
+        const char *c = std::getenv("MPCG_BATCH_SMALL_CAP");
+        const int vc = (c && c[0]) ? std::atoi(c) : 0;
+        if (vc >= 1 && vc <= kSmallBfsCap) e->small_cap = vc;
+        const char *w = std::getenv("MPCG_BATCH_SMALL_WORK");
+        const long long vw = (w && w[0]) ? std::atoll(w) : 0;
+        if (vw >= 1) e->small_work = vw;
     }
     e->model = model;
     e->a = carve(arena, max_sys, (int32_t)max_slices, max_entries);

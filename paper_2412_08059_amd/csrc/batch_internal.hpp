@@ -54,6 +54,7 @@ enum BfsMode : int32_t {
 constexpr int kSlicesPerBlock = kBlock / 64;
 constexpr int32_t kErrGuard = 64;     // a bounded device loop ran out (union-find)
 constexpr int kSmallBfsCap = 2048;   // frontier kept in LDS by the one-block-per-system kernel
+constexpr int kSmallBfsCapDefault = 512;   // default of the largest frontier that kernel takes (<= kSmallBfsCap)
 constexpr int kVisBits = 1 << 20;     // rows up to which that kernel keeps the visited set in LDS (128 KB)
 constexpr int kSmallBfsLevels = 64;  // default of the levels one launch may expand for one system
 
@@ -145,7 +146,11 @@ void launch_step(hipStream_t s, const BArena &a, int32_t hi_slice, int32_t hi_sy
 // own fields.
 // One round: every system whose sweep is running expands one large level or
 // up to small_levels small ones.
-void launch_bfs_round(hipStream_t s, const BArena &a, int32_t hi_sys, int small_levels);
+// small_cap (<= kSmallBfsCap): largest frontier the one-block kernel takes;
+// small_work: edge slots (frontier x lanes, summed over levels) after which
+// one of its blocks stops, so that wide frontiers do not set the round time.
+void launch_bfs_round(hipStream_t s, const BArena &a, int32_t hi_sys, int small_levels, int small_cap,
+                      int64_t small_work);
 // host-driven transitions of one system of n rows
 void launch_bfs_start(hipStream_t s, const BArena &a, int32_t sys, int32_t n);        // CC + sweep-1 seeds
 void launch_bfs_next_sweep(hipStream_t s, const BArena &a, int32_t sys, int32_t n);   // argmax + sweep-2 seeds

@@ -677,7 +677,7 @@ __global__ void __launch_bounds__(kBlock) k_b_scalar2(BArena a)
 // systems with a frontier that fits in LDS go to the one-block-per-system
 // kernel, the others share the multi-block level kernel through an item
 // prefix.
-__global__ void __launch_bounds__(1024) k_bfs_plan(BArena a, int32_t hi_sys)
+__global__ void __launch_bounds__(1024) k_bfs_plan(BArena a, int32_t hi_sys, int32_t small_cap)
 {
     __shared__ int64_t sitems[1024];
     __shared__ int32_t sbig[1024], ssmall[1024];
@@ -704,7 +704,7 @@ __global__ void __launch_bounds__(1024) k_bfs_plan(BArena a, int32_t hi_sys)
                     S.bfs_nxt = 0;
                     S.bfs_level += 1;
                     S.bfs_cnt = c;
-                    if (c <= kSmallBfsCap) {
+                    if (c <= small_cap) {
                         small = 1;
                     } else {
                         big = 1;
@@ -813,7 +813,8 @@ __global__ void __launch_bounds__(kBlock) k_bfs_level_batch(BArena a)
 // at its BFS level.  The bits come from the system's copy in HBM when the
 // previous launch on it was this kernel (vis_lvl = the level before this
 // one), otherwise from dist; the words that changed go back to HBM at exit.
-__global__ void __launch_bounds__(kBlock) k_bfs_small_batch(BArena a, int32_t max_levels)
+__global__ void __launch_bounds__(kBlock) k_bfs_small_batch(BArena a, int32_t max_levels, int32_t small_cap,
+                                                            int64_t max_work)
 {
     __shared__ int32_t sq[2][kSmallBfsCap];
     __shared__ __align__(16) uint32_t vis[kVisBits / 32];
@@ -873,6 +874,7 @@ __global__ void __launch_bounds__(kBlock) k_bfs_small_batch(BArena a, int32_t ma
     }
     int lo = INT32_MAX, hi = -1;
     int c = 0, nxt = 0;
+    int64_t work_done = 0;
     for (int rep = 0; rep < max_levels; ++rep) {
         if (threadIdx.x == 0) s_cnt = 0;
         __syncthreads();
@@ -910,7 +912,8 @@ __global__ void __launch_bounds__(kBlock) k_bfs_small_batch(BArena a, int32_t ma
         __syncthreads();
         nxt = s_cnt;
         __syncthreads();
-        if (nxt == 0 || nxt > kSmallBfsCap || rep + 1 == max_levels) break;
+        work_done += work;
+        if (nxt == 0 || nxt > small_cap || rep + 1 == max_levels || work_done >= max_work) break;
         level += 1;
         cur = nxt;
         c ^= 1;
@@ -942,12 +945,13 @@ void launch_step(hipStream_t s, const BArena &a, int32_t hi_slice, int32_t hi_sy
     hipLaunchKernelGGL(k_b_scalar2, dim3(hi_sys), dim3(kBlock), 0, s, a);
 }
 
-void launch_bfs_round(hipStream_t s, const BArena &a, int32_t hi_sys, int small_levels)
+void launch_bfs_round(hipStream_t s, const BArena &a, int32_t hi_sys, int small_levels, int small_cap,
+                      int64_t small_work)
 {
     if (hi_sys <= 0) return;
-    hipLaunchKernelGGL(k_bfs_plan, dim3(1), dim3(1024), 0, s, a, hi_sys);
+    hipLaunchKernelGGL(k_bfs_plan, dim3(1), dim3(1024), 0, s, a, hi_sys, small_cap);
     hipLaunchKernelGGL(k_bfs_level_batch, dim3(256), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_bfs_small_batch, dim3(hi_sys), dim3(kBlock), 0, s, a, small_levels);
+    hipLaunchKernelGGL(k_bfs_small_batch, dim3(hi_sys), dim3(kBlock), 0, s, a, small_levels, small_cap, small_work);
 }
 
 // ------------------------------------------------- 2BFS per system (host) --
