@@ -233,3 +233,54 @@ def test_batch_many_small_systems_continuous(engine, torch_mod):
             _check_against_oracle(a, b, e, st, x, model)
         else:
             assert st.status == 0 and st.relres_final_true <= EPS2
+
+
+def test_batch_bfs_schedule_does_not_change_results(torch_mod, monkeypatch):
+    """The batched 2BFS gives the same features, and the solves the same bits,
+    however its levels are scheduled: the largest frontier the one-block kernel
+    takes (8 / 512 / 2,048) and the levels one of its launches may expand
+    (1 / 64 / 4,096) change which kernel expands which level, how often a
+    system's visited bits are rebuilt from dist and when the features arrive.
+    An ER graph of more than 2^20 rows takes the path that claims vertices in
+    HBM (smaller systems keep their visited set in LDS); every system's
+    features are checked against the oracle's 2BFS."""
+    from paper_2412_08059_amd import BatchSolver
+    from workloads import paper_family as PF
+    gens = [("banded_30000", lambda: W.banded(30_000, 8, seed=11)),
+            ("poisson2d_64", lambda: W.poisson2d(64)),
+            ("er_5000", lambda: W.er_laplacian(5000, 16, seed=6)),
+            ("disconnected", _disconnected),
+            ("band_path_8000", lambda: PF.random_banded(8000, 3, 1.0, 1.1, seed=4)),
+            ("er_1100000", lambda: W.er_laplacian(1_100_000, 16, seed=13))]
+    mats = [(nm, g()) for nm, g in gens]
+    print("schedules x " + ", ".join(f"{nm} (n={a.n})" for nm, a in mats), flush=True)
+    schedules = [{}, {"MPCG_BATCH_SMALL_CAP": "2048", "MPCG_BATCH_SMALL_LEVELS": "4096"},
+                 {"MPCG_BATCH_SMALL_CAP": "8", "MPCG_BATCH_SMALL_LEVELS": "1"}]
+    runs = []
+    for env in schedules:
+        for k in ("MPCG_BATCH_SMALL_CAP", "MPCG_BATCH_SMALL_LEVELS", "MPCG_BATCH_SMALL_WORK"):
+            if k in env:
+                monkeypatch.setenv(k, env[k])
+            else:
+                monkeypatch.delenv(k, raising=False)
+        eng = BatchSolver(1_300_000, 40_000_000, 16, model=TEST_MODEL)
+        try:
+            reqs = [_make(torch_mod, nm, lambda a=a: a, 0.0, seed=30 + i)[2] for i, (nm, a) in enumerate(mats)]
+            ids = eng.submit(reqs)
+            got = eng.wait_all(ids, timeout_s=120)
+        finally:
+            eng.close()
+        out = {}
+        for rid, (nm, _) in zip(ids, mats):
+            st, x = got[rid]
+            f = st.feat
+            assert st.status == 0 and st.relres_final_true <= EPS2, (env, nm, st.status)
+            out[nm] = ((f.pdiam, f.bfs_t, f.bfs_u, f.n_components), st.n1, st.n2, st.eps1_class,
+                       x.cpu().numpy().view(np.uint64).copy())
+        print(f"  {env or 'default'}: " + ", ".join(f"{nm} pdiam={v[0][0]}" for nm, v in out.items()), flush=True)
+        runs.append(out)
+    for nm, a in mats:
+        assert runs[0][nm][0] == oracle.pseudo_diameter(a), nm
+        for r in runs[1:]:
+            assert r[nm][:4] == runs[0][nm][:4], nm
+            assert np.array_equal(r[nm][4], runs[0][nm][4]), nm
