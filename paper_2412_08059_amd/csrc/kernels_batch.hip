@@ -679,10 +679,12 @@ __global__ void __launch_bounds__(kBlock) k_b_scalar2(BArena a)
 // prefix.
 __global__ void __launch_bounds__(1024) k_bfs_plan(BArena a, int32_t hi_sys, int32_t small_cap)
 {
-    __shared__ int64_t sitems[1024];
-    __shared__ int32_t sbig[1024], ssmall[1024];
+    constexpr int kWaves = 1024 / 64;
+    __shared__ int64_t w_items[kWaves];
+    __shared__ int32_t w_big[kWaves], w_small[kWaves];
     __shared__ int64_t base_items;
     __shared__ int32_t base_big, base_small;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (threadIdx.x == 0) {
         base_items = 0;
         base_big = 0;
@@ -714,35 +716,52 @@ __global__ void __launch_bounds__(1024) k_bfs_plan(BArena a, int32_t hi_sys, int
                 S.small = small;
             }
         }
-        sitems[threadIdx.x] = items;
-        sbig[threadIdx.x] = big;
-        ssmall[threadIdx.x] = small;
+        // exclusive scans of (items, big, small) in system order: inclusive
+        // within each wave by shuffles, then the wave totals in order
+        int64_t si = items;
+        int32_t sb = big, ss = small;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t ti = __shfl_up(si, o, 64);
+            const int32_t tb = __shfl_up(sb, o, 64), ts = __shfl_up(ss, o, 64);
+            if (lane >= o) {
+                si += ti;
+                sb += tb;
+                ss += ts;
+            }
+        }
+        if (lane == 63) {
+            w_items[wid] = si;
+            w_big[wid] = sb;
+            w_small[wid] = ss;
+        }
         __syncthreads();
-        if (threadIdx.x == 0) {   // sequential exclusive scans over this chunk (<= 1024 systems)
+        if (threadIdx.x == 0) {
             int64_t ri = base_items;
             int32_t rb = base_big, rs = base_small;
-            for (int t = 0; t < 1024; ++t) {
-                const int64_t it = sitems[t];
-                const int32_t b = sbig[t], sm_ = ssmall[t];
-                sitems[t] = ri;
-                sbig[t] = rb;
-                ssmall[t] = rs;
-                ri += it;
-                rb += b;
-                rs += sm_;
+            for (int w = 0; w < kWaves; ++w) {
+                const int64_t ti = w_items[w];
+                const int32_t tb = w_big[w], ts = w_small[w];
+                w_items[w] = ri;
+                w_big[w] = rb;
+                w_small[w] = rs;
+                ri += ti;
+                rb += tb;
+                rs += ts;
             }
             base_items = ri;
             base_big = rb;
             base_small = rs;
         }
         __syncthreads();
+        const int64_t ex_items = w_items[wid] + si - items;
+        const int32_t ex_big = w_big[wid] + sb - big, ex_small = w_small[wid] + ss - small;
         if (big) {
-            a.act_sys[sbig[threadIdx.x]] = s;
-            a.act_pre[sbig[threadIdx.x]] = sitems[threadIdx.x];
-            a.sys[s].item0 = sitems[threadIdx.x];
+            a.act_sys[ex_big] = s;
+            a.act_pre[ex_big] = ex_items;
+            a.sys[s].item0 = ex_items;
         }
-        if (small) a.small_sys[ssmall[threadIdx.x]] = s;
-        __syncthreads();
+        if (small) a.small_sys[ex_small] = s;
+        __syncthreads();   // the wave slots are rewritten by the next chunk
     }
     if (threadIdx.x == 0) {
         a.counts[0] = base_big;
