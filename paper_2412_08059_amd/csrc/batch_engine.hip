@@ -142,6 +142,7 @@ struct Engine {
     int small_levels = kSmallBfsLevels;   // MPCG_BATCH_SMALL_LEVELS
     int small_cap = kSmallBfsCapDefault;  // MPCG_BATCH_SMALL_CAP
     int64_t small_work = INT64_MAX;       // MPCG_BATCH_SMALL_WORK
+    int bfs_rounds = kBfsRoundsPerPump;   // MPCG_BATCH_BFS_ROUNDS
 
     std::mutex mu;
     std::condition_variable cv;
@@ -464,7 +465,7 @@ bool Engine::bfs_pump()
         if ((sl.feat == 3 && !sl.bfs_ready) || sl.feat == 5) enq = true;   // waiting for a copy that shows the result
     }
     if (run)
-        for (int r = 0; r < kBfsRoundsPerPump; ++r) launch_bfs_round(sb, a, hi_sys, small_levels, small_cap, small_work);
+        for (int r = 0; r < bfs_rounds; ++r) launch_bfs_round(sb, a, hi_sys, small_levels, small_cap, small_work);
     if (hipGetLastError() != hipSuccess) return false;
     if (!(enq || run) || hi_sys <= 0) return true;
     bmirror_n = hi_sys;
@@ -603,6 +604,9 @@ Engine *engine_create(int device, const mpcg_options &opt, const KnnModel *model
         const char *w = std::getenv("MPCG_BATCH_SMALL_WORK");
         const long long vw = (w && w[0]) ? std::atoll(w) : 0;
         if (vw >= 1) e->small_work = vw;
+        const char *br = std::getenv("MPCG_BATCH_BFS_ROUNDS");
+        const int vr = (br && br[0]) ? std::atoi(br) : 0;
+        if (vr >= 1 && vr <= 64) e->bfs_rounds = vr;
     }
     e->model = model;
     e->a = carve(arena, max_sys, (int32_t)max_slices, max_entries);
