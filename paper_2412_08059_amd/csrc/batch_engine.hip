@@ -143,6 +143,7 @@ struct Engine {
     int small_cap = kSmallBfsCapDefault;  // MPCG_BATCH_SMALL_CAP
     int64_t small_work = INT64_MAX;       // MPCG_BATCH_SMALL_WORK
     int bfs_rounds = kBfsRoundsPerPump;   // MPCG_BATCH_BFS_ROUNDS
+    int level_grid = 1024;                // MPCG_BATCH_LEVEL_GRID
 
     std::mutex mu;
     std::condition_variable cv;
@@ -465,7 +466,7 @@ bool Engine::bfs_pump()
         if ((sl.feat == 3 && !sl.bfs_ready) || sl.feat == 5) enq = true;   // waiting for a copy that shows the result
     }
     if (run)
-        for (int r = 0; r < bfs_rounds; ++r) launch_bfs_round(sb, a, hi_sys, small_levels, small_cap, small_work);
+        for (int r = 0; r < bfs_rounds; ++r) launch_bfs_round(sb, a, hi_sys, small_levels, small_cap, small_work, level_grid);
     if (hipGetLastError() != hipSuccess) return false;
     if (!(enq || run) || hi_sys <= 0) return true;
     bmirror_n = hi_sys;
@@ -607,6 +608,9 @@ Engine *engine_create(int device, const mpcg_options &opt, const KnnModel *model
         const char *br = std::getenv("MPCG_BATCH_BFS_ROUNDS");
         const int vr = (br && br[0]) ? std::atoi(br) : 0;
         if (vr >= 1 && vr <= 64) e->bfs_rounds = vr;
+        const char *lg = std::getenv("MPCG_BATCH_LEVEL_GRID");
+        const int vl = (lg && lg[0]) ? std::atoi(lg) : 0;
+        if (vl >= 1 && vl <= 65536) e->level_grid = vl;
     }
     e->model = model;
     e->a = carve(arena, max_sys, (int32_t)max_slices, max_entries);

@@ -146,11 +146,12 @@ void launch_step(hipStream_t s, const BArena &a, int32_t hi_slice, int32_t hi_sy
 // own fields.
 // One round: every system whose sweep is running expands one large level or
 // up to small_levels small ones.
+// level_grid: blocks of the multi-block level kernel (grid-stride over items);
 // small_cap (<= kSmallBfsCap): largest frontier the one-block kernel takes;
 // small_work: edge slots (frontier x lanes, summed over levels) after which
 // one of its blocks stops, so that wide frontiers do not set the round time.
 void launch_bfs_round(hipStream_t s, const BArena &a, int32_t hi_sys, int small_levels, int small_cap,
-                      int64_t small_work);
+                      int64_t small_work, int level_grid);
 // host-driven transitions of one system of n rows
 void launch_bfs_start(hipStream_t s, const BArena &a, int32_t sys, int32_t n);        // CC + sweep-1 seeds
 void launch_bfs_next_sweep(hipStream_t s, const BArena &a, int32_t sys, int32_t n);   // argmax + sweep-2 seeds

@@ -807,15 +807,33 @@ __global__ void __launch_bounds__(kBlock) k_bfs_level_batch(BArena a)
         }
         int steps = j < e ? (e - j + lanes - 1) >> (__ffs(lanes) - 1) : 0;
         steps = wave_max_i32(steps);
-        for (int t = 0; t < steps; ++t, j += lanes) {
+        for (int t = 0; t < steps; ++t, j += lanes) {   // wave-uniform trip count
+            int v = -1;
+            bool won = false;
             if (j < e) {
-                const int v = a.col[base + (int64_t)j * 64];
-                if (v != u && a.dist[v] < 0 && atomicCAS(&a.dist[v], -1, level + 1) == -1) {
-                    BSys &S = a.sys[s];
-                    const int pos = atomicAdd(&S.bfs_nxt, 1);
+                v = a.col[base + (int64_t)j * 64];
+                won = v != u && a.dist[v] < 0 && atomicCAS(&a.dist[v], -1, level + 1) == -1;
+            }
+            const unsigned long long m = __ballot(won);
+            if (m == 0ull) continue;
+            // the wave's new vertices of one system take one append: the first
+            // winner reserves them all, each winner writes at its rank
+            const int l0 = __ffsll(m) - 1;
+            const int s0 = __shfl(s, l0, 64);
+            if (__all(!won || s == s0)) {
+                int pos0 = 0;
+                if (lane == l0) pos0 = atomicAdd(&a.sys[s0].bfs_nxt, (int)__popcll(m));
+                pos0 = __shfl(pos0, l0, 64);
+                if (won) {
+                    const int rank = (int)__popcll(m & ((1ull << lane) - 1ull));
                     int32_t *qn = (level & 1) ? a.q0 : a.q1;
-                    qn[S.row0 + pos] = v;
+                    qn[a.sys[s].row0 + pos0 + rank] = v;
                 }
+            } else if (won) {   // the wave straddles systems
+                BSys &S = a.sys[s];
+                const int pos = atomicAdd(&S.bfs_nxt, 1);
+                int32_t *qn = (level & 1) ? a.q0 : a.q1;
+                qn[S.row0 + pos] = v;
             }
         }
     }
@@ -965,11 +983,11 @@ void launch_step(hipStream_t s, const BArena &a, int32_t hi_slice, int32_t hi_sy
 }
 
 void launch_bfs_round(hipStream_t s, const BArena &a, int32_t hi_sys, int small_levels, int small_cap,
-                      int64_t small_work)
+                      int64_t small_work, int level_grid)
 {
     if (hi_sys <= 0) return;
     hipLaunchKernelGGL(k_bfs_plan, dim3(1), dim3(1024), 0, s, a, hi_sys, small_cap);
-    hipLaunchKernelGGL(k_bfs_level_batch, dim3(256), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_bfs_level_batch, dim3(level_grid), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_bfs_small_batch, dim3(hi_sys), dim3(kBlock), 0, s, a, small_levels, small_cap, small_work);
 }
 
