@@ -672,14 +672,18 @@ __global__ void __launch_bounds__(kBlock) k_b_scalar2(BArena a)
 
 // ----------------------------------------------------------------- 2BFS --
 
+// One block of four waves (a larger block waits longer for room on a CU
+// beside the steps).
+constexpr int kPlanThreads = 256;
+
 // Single block: retire the level each running system expanded last step
 // (appends -> frontier), detect ended sweeps, and list this step's work:
 // systems with a frontier that fits in LDS go to the one-block-per-system
 // kernel, the others share the multi-block level kernel through an item
 // prefix.
-__global__ void __launch_bounds__(1024) k_bfs_plan(BArena a, int32_t hi_sys, int32_t small_cap)
+__global__ void __launch_bounds__(kPlanThreads) k_bfs_plan(BArena a, int32_t hi_sys, int32_t small_cap)
 {
-    constexpr int kWaves = 1024 / 64;
+    constexpr int kWaves = kPlanThreads / 64;
     __shared__ int64_t w_items[kWaves];
     __shared__ int32_t w_big[kWaves], w_small[kWaves];
     __shared__ int64_t base_items;
@@ -691,26 +695,27 @@ __global__ void __launch_bounds__(1024) k_bfs_plan(BArena a, int32_t hi_sys, int
         base_small = 0;
     }
     __syncthreads();
-    for (int c0 = 0; c0 < hi_sys; c0 += 1024) {
+    for (int c0 = 0; c0 < hi_sys; c0 += kPlanThreads) {
         const int s = c0 + threadIdx.x;
         int64_t items = 0;
         int big = 0, small = 0;
         if (s < hi_sys) {
             BSys &S = a.sys[s];
-            if (S.bfs_mode == kBfsRun) {
-                const int c = S.bfs_nxt;
-                if (S.bfs_level < 0 && S.bfs_sweep == 1) S.ncomp = c;
+            // the fields read, loaded together (one memory latency, not a chain)
+            const int mode = S.bfs_mode, c = S.bfs_nxt, lvl = S.bfs_level, sweep = S.bfs_sweep, lanes = S.lanes;
+            if (mode == kBfsRun) {
+                if (lvl < 0 && sweep == 1) S.ncomp = c;
                 if (c == 0) {
                     S.bfs_mode = kBfsSwept;
                 } else {
                     S.bfs_nxt = 0;
-                    S.bfs_level += 1;
+                    S.bfs_level = lvl + 1;
                     S.bfs_cnt = c;
                     if (c <= small_cap) {
                         small = 1;
                     } else {
                         big = 1;
-                        items = (int64_t)c * S.lanes;
+                        items = (int64_t)c * lanes;
                     }
                 }
                 S.small = small;
@@ -986,7 +991,7 @@ void launch_bfs_round(hipStream_t s, const BArena &a, int32_t hi_sys, int small_
                       int64_t small_work, int level_grid)
 {
     if (hi_sys <= 0) return;
-    hipLaunchKernelGGL(k_bfs_plan, dim3(1), dim3(1024), 0, s, a, hi_sys, small_cap);
+    hipLaunchKernelGGL(k_bfs_plan, dim3(1), dim3(kPlanThreads), 0, s, a, hi_sys, small_cap);
     hipLaunchKernelGGL(k_bfs_level_batch, dim3(level_grid), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_bfs_small_batch, dim3(hi_sys), dim3(kBlock), 0, s, a, small_levels, small_cap, small_work);
 }
