@@ -144,6 +144,7 @@ struct Engine {
     int64_t small_work = INT64_MAX;       // MPCG_BATCH_SMALL_WORK
     int bfs_rounds = kBfsRoundsPerPump;   // MPCG_BATCH_BFS_ROUNDS
     int level_grid = 1024;                // MPCG_BATCH_LEVEL_GRID
+    int group_steps = kGroupSteps;        // MPCG_BATCH_GROUP_STEPS
 
     std::mutex mu;
     std::condition_variable cv;
@@ -516,7 +517,7 @@ bool Engine::step_once()
     if (!bfs_pump()) return false;
     const int k = (int)(group & 1);
     if (any_live)
-        for (int g = 0; g < kGroupSteps; ++g) launch_step(s, a, hi_slice, hi_sys);
+        for (int g = 0; g < group_steps; ++g) launch_step(s, a, hi_slice, hi_sys);
     if (hipGetLastError() != hipSuccess) return false;
     mirror_n[k] = hi_sys;
     mirror_group[k] = group;
@@ -611,6 +612,9 @@ Engine *engine_create(int device, const mpcg_options &opt, const KnnModel *model
         const char *lg = std::getenv("MPCG_BATCH_LEVEL_GRID");
         const int vl = (lg && lg[0]) ? std::atoi(lg) : 0;
         if (vl >= 1 && vl <= 65536) e->level_grid = vl;
+        const char *gs = std::getenv("MPCG_BATCH_GROUP_STEPS");
+        const int vs = (gs && gs[0]) ? std::atoi(gs) : 0;
+        if (vs >= 1 && vs <= 64) e->group_steps = vs;
     }
     e->model = model;
     e->a = carve(arena, max_sys, (int32_t)max_slices, max_entries);
