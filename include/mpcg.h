@@ -279,6 +279,17 @@ const char *mpcg_strerror(mpcg_status s);
  * slots, slices and entries free up (first fit), and their work joins the
  * next step.  A host thread owned by the context drives the steps on a
  * stream of its own; mpcg_batch_poll returns finished solves without blocking.
+ *
+ * Scheduling knobs, read from the environment when the engine starts
+ * (mpcg_batch_set_workspace); none changes any result, only when work runs:
+ *   MPCG_BATCH_GROUP_STEPS  steps enqueued per group (1..64, default 8)
+ *   MPCG_BATCH_BFS_ROUNDS   2BFS rounds per pass of the BFS stream (1..64, 4)
+ *   MPCG_BATCH_SMALL_CAP    largest frontier expanded by one block per system
+ *                           (1..2048, 512); larger ones by the multi-block kernel
+ *   MPCG_BATCH_SMALL_LEVELS levels one such launch may expand (1..4096, 64)
+ *   MPCG_BATCH_SMALL_WORK   frontier x lane slots after which it stops (unbounded)
+ *   MPCG_BATCH_LEVEL_GRID   blocks of the multi-block level kernel (1..65536, 1024)
+ * Values outside the ranges are ignored.
  * -------------------------------------------------------------------------*/
 
 /* One solve.  A, b and x are DEVICE memory owned by the caller and borrowed
