@@ -942,7 +942,9 @@ __global__ void __launch_bounds__(kBlock) k_bfs_small_batch(BArena a, int32_t ma
                         hi = max(hi, lv >> 5);
                     }
                 } else {
-                    won = a.dist[v] < 0 && atomicCAS(&a.dist[v], -1, level + 1) == -1;
+                    // the compare-and-swap returns the old distance: no read before it
+                    // (one dependent memory round trip less per level on a narrow frontier)
+                    won = atomicCAS(&a.dist[v], -1, level + 1) == -1;
                 }
                 if (won) {
                     const int pos = atomicAdd(&s_cnt, 1);
