@@ -16,6 +16,10 @@ Functions and the passages they follow:
                       and FP64-only CG (eps1 = NONE).
   cg64_directions     search directions of FP64 CG (A-orthogonality pin).
   cg_true_residuals   true residual history of plain SP or DP CG (Fig. 2).
+  lanczos_kappa       condition-number estimate from the CG-Lanczos
+                      tridiagonal of an FP64 CG run (gates the x-parity bar).
+  set_threads         host threads for the row loops (products and
+                      element-wise updates; same bits as one thread).
 """
 
 from __future__ import annotations
@@ -46,7 +50,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
-                               "-o", tmp, _SRC, "-lm"])
+                               "-fopenmp", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -54,7 +58,7 @@ def build(force: bool = False) -> str:
 class _Opts(ctypes.Structure):
     _fields_ = [("k0", ctypes.c_int32), ("tol_mode", ctypes.c_int32),
                 ("max_restarts", ctypes.c_int32), ("knn_k", ctypes.c_int32),
-                ("precond", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("dot_acc", ctypes.c_int32),
                 ("maxit1", ctypes.c_int64), ("maxit2", ctypes.c_int64)]
 
 
@@ -98,12 +102,16 @@ def _L():
         lib.or_diameter_multi.restype = ctypes.c_int
         lib.or_knn_select.argtypes = [ctypes.POINTER(_Model), P, ctypes.c_int32, P, P]
         lib.or_knn_select.restype = ctypes.c_int
-        lib.or_solve.argtypes = [I64, P, P, P, P, P, ctypes.c_double, ctypes.c_double,
+        lib.or_solve.argtypes = [I64, P, P, P, P, P, P, ctypes.c_double, ctypes.c_double,
                                  ctypes.POINTER(_Opts), ctypes.POINTER(_Model), ctypes.POINTER(_Stats)]
         lib.or_solve.restype = ctypes.c_int
         lib.or_cg64_directions.argtypes = [I64, P, P, P, P, I64, P]
         lib.or_cg64_directions.restype = I64
         lib.or_cg_true_residuals.argtypes = [ctypes.c_int32, I64, P, P, P, P, I64, P]
+        lib.or_cg_lanczos.argtypes = [I64, P, P, P, P, ctypes.c_double, I64, P, P]
+        lib.or_cg_lanczos.restype = I64
+        lib.or_set_threads.argtypes = [ctypes.c_int32]
+        lib.or_get_threads.restype = ctypes.c_int32
         _lib = lib
     return _lib
 
@@ -236,20 +244,25 @@ class OracleResult:
 
 def solve(a, b, eps1: float, eps2: float = 1e-10, *, k0: int = 20, tol_mode: int = 0,
           max_restarts: int = 5, maxit1: int = 0, maxit2: int = 0, knn_k: int = 0,
-          model: KnnModel | None = None, precond: int = 0) -> OracleResult:
-    """precond = 1: every CG stage preconditioned with M = diag(A) (Jacobi)."""
+          model: KnnModel | None = None, precond: int = 0, dot_acc: int = 0,
+          x0=None) -> OracleResult:
+    """precond = 1: every CG stage preconditioned with M = diag(A) (Jacobi).
+    dot_acc = 1: FP32-phase dot products accumulate in FP32 (else FP64).
+    x0: initial guess of the first stage (float32(x0) for the FP32 stage,
+    x0 for FP64-only CG); None is zero."""
     rp, col, val = _csr_arrays(a)
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.zeros(a.n, dtype=np.float64)
-    opts = _Opts(k0, tol_mode, max_restarts, knn_k, precond, 0, maxit1, maxit2)
+    x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
+    opts = _Opts(k0, tol_mode, max_restarts, knn_k, precond, dot_acc, maxit1, maxit2)
     st = _Stats()
     keep = None
     mp = None
     if model is not None:
         ms, keep = _model_struct(model)
         mp = ctypes.byref(ms)
-    status = _L().or_solve(a.n, _p(rp), _p(col), _p(val), _p(b), _p(x), float(eps1), float(eps2),
-                           ctypes.byref(opts), mp, ctypes.byref(st))
+    status = _L().or_solve(a.n, _p(rp), _p(col), _p(val), _p(b), None if x0a is None else _p(x0a), _p(x),
+                           float(eps1), float(eps2), ctypes.byref(opts), mp, ctypes.byref(st))
     del keep
     return OracleResult(status=status, x=x, n1=st.n1, n2=st.n2, restarts=st.restarts, flags=st.flags,
                         k0_used=st.k0_used, eps1_class=st.eps1_class, eps1_used=st.eps1_used, v=st.v,
@@ -273,3 +286,34 @@ def cg_true_residuals(a, b, prec: int, iters: int) -> np.ndarray:
     out = np.zeros(iters + 1, dtype=np.float64)
     _L().or_cg_true_residuals(int(prec), a.n, _p(rp), _p(col), _p(val), _p(b), iters, _p(out))
     return out
+
+
+def set_threads(t: int) -> None:
+    """Host threads for the oracle's row loops (1 = sequential)."""
+    _L().or_set_threads(int(t))
+
+
+def get_threads() -> int:
+    return int(_L().or_get_threads())
+
+
+def lanczos_kappa(a, b, eps: float = 1e-10, maxit: int = 0):
+    """kappa-hat = lambda_max / lambda_min of the CG-Lanczos tridiagonal T_k
+    of plain FP64 CG on (A, b) from 0, run to ||r|| <= eps ||b|| (maxit <= 0:
+    10 n).  Returns (kappa_hat, lambda_min, lambda_max, k).  The extreme
+    eigenvalues of T_k come from scipy's symmetric tridiagonal solver."""
+    rp, col, val = _csr_arrays(a)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    m = int(maxit) if maxit > 0 else 10 * a.n
+    al = np.zeros(m, dtype=np.float64)
+    be = np.zeros(m, dtype=np.float64)
+    k = int(_L().or_cg_lanczos(a.n, _p(rp), _p(col), _p(val), _p(b), float(eps), m, _p(al), _p(be)))
+    if k == 0:
+        return float("nan"), float("nan"), float("nan"), 0
+    al, be = al[:k], be[:k]
+    diag = 1.0 / al
+    diag[1:] += be[:-1] / al[:-1]
+    off = np.sqrt(be[:-1]) / al[:-1]
+    from scipy.linalg import eigvalsh_tridiagonal
+    lam = eigvalsh_tridiagonal(diag, off)
+    return float(lam[-1] / lam[0]), float(lam[0]), float(lam[-1]), k

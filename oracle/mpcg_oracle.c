@@ -61,6 +61,16 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Row loops (the products and the element-wise vector updates) may run on
+ * several host threads: each iteration writes only its own element, so the
+ * result is the same bits as one thread.  Dot products and the BFS stay
+ * sequential.  or_set_threads(1) (the default) runs everything on one thread. */
+static int g_threads = 1;
+#define OR_ROWS _Pragma("omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1)")
+
+void or_set_threads(int32_t t) { g_threads = t > 1 ? t : 1; }
+int32_t or_get_threads(void) { return g_threads; }
+
 #define OR_OK 0
 #define OR_EINVAL (-1)
 #define OR_ENOTSPD (-2)
@@ -80,7 +90,7 @@ typedef struct {
     int32_t max_restarts; /* extra FP64 restarts after a failed final check */
     int32_t knn_k;        /* 0: take k from the model */
     int32_t precond;      /* 0: none, 1: Jacobi (M = diag(A)) */
-    int32_t pad;
+    int32_t dot_acc;      /* FP32-phase dot products: 0 accumulate in FP64, 1 in FP32 */
     int64_t maxit1;       /* FP32 iteration cap, <=0: n */
     int64_t maxit2;       /* FP64 iteration cap, <=0: max(10n, 1000) */
 } or_opts;
@@ -106,6 +116,7 @@ typedef struct {
 void or_spmv64(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
                const double *x, double *y)
 {
+    OR_ROWS
     for (int64_t i = 0; i < n; ++i) {
         double acc = 0.0;
         for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
@@ -117,6 +128,7 @@ void or_spmv64(int64_t n, const int64_t *rp, const int32_t *col, const double *v
 void or_spmv32(int64_t n, const int64_t *rp, const int32_t *col, const float *val,
                const float *x, float *y)
 {
+    OR_ROWS
     for (int64_t i = 0; i < n; ++i) {
         float acc = 0.0f;
         for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
@@ -467,9 +479,16 @@ static double dot64(int64_t n, const double *a, const double *b)
     return s;
 }
 
-/* FP64 accumulation of FP32 products; each product is exact in FP64. */
-static double dot32(int64_t n, const float *a, const float *b)
+/* Dot product of two FP32 vectors.  acc32 = 0: the products are summed in
+ * FP64 (each FP32 x FP32 product is exact in FP64); acc32 = 1: the whole sum
+ * is an FP32 fma chain, returned widened. */
+static double dot32(int64_t n, const float *a, const float *b, int acc32)
 {
+    if (acc32) {
+        float s = 0.0f;
+        for (int64_t i = 0; i < n; ++i) s = fmaf(a[i], b[i], s);
+        return (double)s;
+    }
     double s = 0.0;
     for (int64_t i = 0; i < n; ++i) s = fma((double)a[i], (double)b[i], s);
     return s;
@@ -480,6 +499,7 @@ static double true_residual(int64_t n, const int64_t *rp, const int32_t *col, co
                             const double *b, const double *x, double *r)
 {
     or_spmv64(n, rp, col, val, x, r);
+    OR_ROWS
     for (int64_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
     return dot64(n, r, r);
 }
@@ -498,6 +518,7 @@ typedef struct {
     const float *val;
     const float *dg;      /* diagonal of A~ (Jacobi), or NULL: no preconditioner */
     float *x, *r, *d, *q, *z;
+    int acc32;            /* dot products accumulated in FP32 (dot_acc = 1) */
     double gamma;         /* r.r (stop test, v ratios) */
     double rho;           /* r.M^-1 r (alpha, beta); equals gamma without a preconditioner */
 } cg32_state;
@@ -506,8 +527,11 @@ typedef struct {
 static void precond32(cg32_state *s)
 {
     if (s->dg) {
-        for (int64_t i = 0; i < s->n; ++i) s->z[i] = s->r[i] / s->dg[i];
-        s->rho = dot32(s->n, s->r, s->z);
+        float *z = s->z;
+        const float *r = s->r, *dg = s->dg;
+        OR_ROWS
+        for (int64_t i = 0; i < s->n; ++i) z[i] = r[i] / dg[i];
+        s->rho = dot32(s->n, s->r, s->z, s->acc32);
     } else {
         s->rho = s->gamma;
     }
@@ -518,20 +542,24 @@ static void precond32(cg32_state *s)
 static int cg32_step(cg32_state *s)
 {
     int64_t n = s->n;
+    float *x = s->x, *r = s->r, *d = s->d;
+    const float *q = s->q;
     or_spmv32(n, s->rp, s->col, s->val, s->d, s->q);
-    double delta = dot32(n, s->d, s->q);
+    double delta = dot32(n, s->d, s->q, s->acc32);
     if (!isfinite(delta) || !(delta > 0.0)) return 1;
     float alpha = (float)(s->rho / delta);
+    OR_ROWS
     for (int64_t i = 0; i < n; ++i) {
-        s->x[i] = fmaf(alpha, s->d[i], s->x[i]);
-        s->r[i] = fmaf(-alpha, s->q[i], s->r[i]);
+        x[i] = fmaf(alpha, d[i], x[i]);
+        r[i] = fmaf(-alpha, q[i], r[i]);
     }
     double rho_old = s->rho;
-    s->gamma = dot32(n, s->r, s->r);
+    s->gamma = dot32(n, s->r, s->r, s->acc32);
     precond32(s);
     float beta = (float)(s->rho / rho_old);
     const float *src = s->dg ? s->z : s->r;   /* M^-1 r' */
-    for (int64_t i = 0; i < n; ++i) s->d[i] = fmaf(beta, s->d[i], src[i]);
+    OR_ROWS
+    for (int64_t i = 0; i < n; ++i) d[i] = fmaf(beta, d[i], src[i]);
     return 0;
 }
 
@@ -545,8 +573,30 @@ static void diagonal(int64_t n, const int64_t *rp, const int32_t *col, const dou
     }
 }
 
+/* FP64 CG state of the second stage: residual r = b - A x, direction d and
+ * (Jacobi) z = M^-1 r; gamma = r.r, rho = r.z (= gamma without a
+ * preconditioner). */
+static void start64(int64_t n, const int64_t *rp, const int32_t *col, const double *val, const double *dg64,
+                    const double *b, const double *x, double *r, double *d, double *z, double *gamma,
+                    double *rho)
+{
+    *gamma = true_residual(n, rp, col, val, b, x, r);
+    *rho = *gamma;
+    if (dg64) {
+        OR_ROWS
+        for (int64_t i = 0; i < n; ++i) z[i] = r[i] / dg64[i];
+        *rho = dot64(n, r, z);
+    }
+    const double *src = dg64 ? z : r;
+    OR_ROWS
+    for (int64_t i = 0; i < n; ++i) d[i] = src[i];
+}
+
+/* Algorithm I / II and FP64-only CG.  x0 (may be NULL: zero) is the initial
+ * guess of the first stage that runs: float32(x0) for the FP32 stage, x0
+ * itself for FP64-only CG. */
 int or_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
-             const double *b, double *x, double eps1, double eps2,
+             const double *b, const double *x0, double *x, double eps1, double eps2,
              const or_opts *opt_in, const or_model *model, or_stats *st)
 {
     or_opts opt = {20, 0, 5, 0, 0, 0, 0, 0};
@@ -571,7 +621,7 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val
         }
     }
     if (status != OR_OK) { if (st) { S.status = status; *st = S; } return status; }
-    if (!all_finite(nnz, val) || !all_finite(n, b)) {
+    if (!all_finite(nnz, val) || !all_finite(n, b) || (x0 && !all_finite(n, x0))) {
         if (st) { S.status = OR_ENONFINITE; *st = S; }
         return OR_ENONFINITE;
     }
@@ -579,7 +629,7 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val
         if (st) { S.status = OR_ENOMODEL; *st = S; }
         return OR_ENOMODEL;
     }
-    if (opt.precond < 0 || opt.precond > 1) {
+    if (opt.precond < 0 || opt.precond > 1 || opt.dot_acc < 0 || opt.dot_acc > 1) {
         if (st) { S.status = OR_EINVAL; *st = S; }
         return OR_EINVAL;
     }
@@ -614,11 +664,12 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val
     double *z = (double *)malloc(sizeof(double) * (size_t)n);
 
     if (eps1 != -1.0) {
-        /* ---- first stage: FP32 copy of A and b, x~ = 0 ---- */
+        /* ---- first stage: FP32 copy of A and b, x~ = float32(x0) ---- */
         float *val32 = (float *)malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
         cg32_state s;
         float *dg32 = NULL;
         s.n = n; s.rp = rp; s.col = col; s.val = val32;
+        s.acc32 = opt.dot_acc;
         s.x = (float *)malloc(sizeof(float) * (size_t)n);
         s.r = (float *)malloc(sizeof(float) * (size_t)n);
         s.d = (float *)malloc(sizeof(float) * (size_t)n);
@@ -630,11 +681,18 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val
             for (int64_t i = 0; i < n; ++i) dg32[i] = (float)dg64[i];
         }
         s.dg = dg32;
-        for (int64_t i = 0; i < n; ++i) {
-            s.x[i] = 0.0f;
-            s.r[i] = (float)b[i];      /* r~ = b~ - A~ * 0 */
+        if (x0) {
+            /* r~ = b~ - A~ x~0, the product in FP32 */
+            for (int64_t i = 0; i < n; ++i) s.x[i] = (float)x0[i];
+            or_spmv32(n, rp, col, val32, s.x, s.q);
+            for (int64_t i = 0; i < n; ++i) s.r[i] = (float)b[i] - s.q[i];
+        } else {
+            for (int64_t i = 0; i < n; ++i) {
+                s.x[i] = 0.0f;
+                s.r[i] = (float)b[i];      /* r~ = b~ - A~ * 0 */
+            }
         }
-        s.gamma = dot32(n, s.r, s.r);
+        s.gamma = dot32(n, s.r, s.r, s.acc32);
         precond32(&s);
         for (int64_t i = 0; i < n; ++i) s.d[i] = dg32 ? s.z[i] : s.r[i];   /* d_0 = M^-1 r_0 */
         int64_t n1 = 0;
@@ -686,20 +744,14 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val
         free(val32); free(s.x); free(s.r); free(s.d); free(s.q); free(s.z); free(dg32);
     } else {
         S.eps1_used = -1.0;
-        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        for (int64_t i = 0; i < n; ++i) x[i] = x0 ? x0[i] : 0.0;
     }
 
     /* ---- second stage: FP64 CG from x0 = float64(x~) with a true residual ---- */
     {
         double thr = eps2 * scale;
-        double gamma = true_residual(n, rp, col, val, b, x, r);
-        /* z = M^-1 r, rho = r.z (rho = gamma without a preconditioner), d = z */
-        double rho = gamma;
-        if (dg64) {
-            for (int64_t i = 0; i < n; ++i) z[i] = r[i] / dg64[i];
-            rho = dot64(n, r, z);
-        }
-        for (int64_t i = 0; i < n; ++i) d[i] = dg64 ? z[i] : r[i];
+        double gamma, rho;
+        start64(n, rp, col, val, dg64, b, x, r, d, z, &gamma, &rho);
         S.relres_restart_true = sqrt(gamma) / beta_b;
         int64_t n2 = 0;
         int32_t restarts = 0;
@@ -711,6 +763,7 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val
                 if (!isfinite(delta)) { status = OR_ENONFINITE; goto final; }
                 if (!(delta > 0.0)) { status = OR_ENOTSPD; goto final; }
                 double alpha = rho / delta;
+                OR_ROWS
                 for (int64_t i = 0; i < n; ++i) {
                     x[i] = fma(alpha, d[i], x[i]);
                     r[i] = fma(-alpha, q[i], r[i]);
@@ -718,36 +771,33 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *val
                 gamma = dot64(n, r, r);
                 double rho_new = gamma;
                 if (dg64) {
+                    OR_ROWS
                     for (int64_t i = 0; i < n; ++i) z[i] = r[i] / dg64[i];
                     rho_new = dot64(n, r, z);
                 }
                 double beta = rho_new / rho;
-                for (int64_t i = 0; i < n; ++i) d[i] = fma(beta, d[i], dg64 ? z[i] : r[i]);
+                const double *src = dg64 ? z : r;
+                OR_ROWS
+                for (int64_t i = 0; i < n; ++i) d[i] = fma(beta, d[i], src[i]);
                 rho = rho_new;
                 ++n2;
             }
-            {
-                double rho = sqrt(true_residual(n, rp, col, val, b, x, q));
-                S.relres_final_true = rho / beta_b;
-                if (rho <= thr) break;
-                if (restarts >= opt.max_restarts) { status = OR_ENOCONV; break; }
-                ++restarts;
-                S.flags |= OR_FLAG_FINAL_RESTARTED;
-                gamma = true_residual(n, rp, col, val, b, x, r);
-                rho = gamma;
-                if (dg64) {
-                    for (int64_t i = 0; i < n; ++i) z[i] = r[i] / dg64[i];
-                    rho = dot64(n, r, z);
-                }
-                for (int64_t i = 0; i < n; ++i) d[i] = dg64 ? z[i] : r[i];
-            }
+            /* final check on the true residual; if it fails, CG starts again
+             * from x with r = b - A x (gamma and rho of that residual) */
+            double res_true = sqrt(true_residual(n, rp, col, val, b, x, q));
+            S.relres_final_true = res_true / beta_b;
+            if (res_true <= thr) break;
+            if (restarts >= opt.max_restarts) { status = OR_ENOCONV; break; }
+            ++restarts;
+            S.flags |= OR_FLAG_FINAL_RESTARTED;
+            start64(n, rp, col, val, dg64, b, x, r, d, z, &gamma, &rho);
         }
     final:
         S.n2 = (int32_t)n2;
         S.restarts = restarts;
         if (status != OR_OK && S.relres_final_true == 0.0) {
-            double rho = sqrt(true_residual(n, rp, col, val, b, x, q));
-            S.relres_final_true = rho / beta_b;
+            double res_true = sqrt(true_residual(n, rp, col, val, b, x, q));
+            S.relres_final_true = res_true / beta_b;
         }
     }
 done:
@@ -805,13 +855,14 @@ void or_cg_true_residuals(int32_t prec, int64_t n, const int64_t *rp, const int3
         s.n = n; s.rp = rp; s.col = col; s.val = val32;
         s.dg = NULL;
         s.z = NULL;
+        s.acc32 = 0;
         s.x = (float *)calloc((size_t)n, sizeof(float));
         s.r = (float *)malloc(sizeof(float) * (size_t)n);
         s.d = (float *)malloc(sizeof(float) * (size_t)n);
         s.q = (float *)malloc(sizeof(float) * (size_t)n);
         for (int64_t k = 0; k < nnz; ++k) val32[k] = (float)val[k];
         for (int64_t i = 0; i < n; ++i) { s.r[i] = (float)b[i]; s.d[i] = s.r[i]; }
-        s.gamma = dot32(n, s.r, s.r);
+        s.gamma = dot32(n, s.r, s.r, 0);
         s.rho = s.gamma;
         for (int64_t it = 0; it <= iters; ++it) {
             for (int64_t i = 0; i < n; ++i) xd[i] = (double)s.x[i];
@@ -851,4 +902,46 @@ void or_cg_true_residuals(int32_t prec, int64_t n, const int64_t *rp, const int3
         free(r); free(d); free(q);
     }
     free(xd); free(tmp);
+}
+
+/* Coefficients of plain FP64 CG from x0 = 0 (no preconditioner), for the
+ * CG-Lanczos estimate of the extreme eigenvalues of A: CG's step lengths
+ * alpha_j and ratios beta_j = gamma_{j+1} / gamma_j define the tridiagonal
+ * Lanczos matrix T_k with diagonal 1/alpha_j + beta_{j-1}/alpha_{j-1} and
+ * off-diagonal sqrt(beta_j)/alpha_j (Saad, "Iterative Methods for Sparse
+ * Linear Systems", the CG-Lanczos connection), whose extreme eigenvalues
+ * approach those of A.  Runs until ||r|| <= eps ||b|| or maxit iterations;
+ * returns the number k of (alpha, beta) pairs written. */
+int64_t or_cg_lanczos(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
+                      const double *b, double eps, int64_t maxit, double *alpha_out, double *beta_out)
+{
+    double *x = (double *)calloc((size_t)n, sizeof(double));
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    double *d = (double *)malloc(sizeof(double) * (size_t)n);
+    double *q = (double *)malloc(sizeof(double) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) { r[i] = b[i]; d[i] = b[i]; }
+    double gamma = dot64(n, r, r);
+    const double thr = eps * sqrt(gamma);
+    int64_t k = 0;
+    while (k < maxit && gamma > 0.0 && !(sqrt(gamma) <= thr)) {
+        or_spmv64(n, rp, col, val, d, q);
+        double delta = dot64(n, d, q);
+        if (!(delta > 0.0)) break;
+        double alpha = gamma / delta;
+        OR_ROWS
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] = fma(alpha, d[i], x[i]);
+            r[i] = fma(-alpha, q[i], r[i]);
+        }
+        double gnew = dot64(n, r, r);
+        double beta = gnew / gamma;
+        OR_ROWS
+        for (int64_t i = 0; i < n; ++i) d[i] = fma(beta, d[i], r[i]);
+        alpha_out[k] = alpha;
+        beta_out[k] = beta;
+        gamma = gnew;
+        ++k;
+    }
+    free(x); free(r); free(d); free(q);
+    return k;
 }

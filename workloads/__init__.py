@@ -18,6 +18,7 @@ from .generators import (  # noqa: F401
     extended_star,
     random_spd_dense,
     rhs,
+    smooth_rhs,
     family_matrix,
     FAMILIES,
 )

@@ -253,6 +253,16 @@ def rhs(a: CSR, seed: int = 0, low: float = -1.0, high: float = 1.0):
 FAMILIES = ("lap2d", "lap3d", "banded", "er")
 
 
+def smooth_rhs(a: CSR):
+    """x*_i = sin(pi (i + 1) / (n + 1)) (the lowest mode of a 1D chain) and
+    b = A x* in FP64.  On a weakly shifted band this makes ||b|| far smaller
+    than ||A|| ||x*||, so the recursive CG residual drifts measurably from
+    the true one before it reaches a tight tolerance."""
+    i = np.arange(a.n, dtype=np.float64)
+    x = np.sin(np.pi * (i + 1.0) / (a.n + 1.0))
+    return x, a.to_scipy() @ x
+
+
 def family_matrix(family: str, n_target: int, seed: int) -> CSR:
     """One matrix of a family at roughly n_target unknowns (grids round to N^2 / N^3)."""
     if family == "lap2d":
