@@ -125,6 +125,19 @@ typedef struct {
                              not available to the batch engine */
     int64_t maxit1;       /* FP32 cap; <= 0: n */
     int64_t maxit2;       /* FP64 cap; <= 0: max(10 n, 1000) */
+    int32_t dot_acc;      /* FP32-phase dot products (d.q, r.r, r.z): 0 accumulate in FP64
+                             (default; each FP32 x FP32 product is exact there), 1 accumulate in
+                             FP32 -- the paper leaves the accumulation precision of the FP32 phase
+                             open (Remark 3 only fixes the FP64 norms of v) */
+    int32_t spmv_variant; /* sparse product: 0 auto (the loaded tuning table, else SELL-64 when
+                             its padding fits, split in two launches for 32-bit columns);
+                             1 SELL-64 fused; 2 SELL-64 split (direction, then a one-vector
+                             gather); 3 CSR stream.  Every variant runs each row's fma chain in
+                             CSR order, so the products are the same bits */
+    int32_t bfs_mode;     /* 2BFS large levels: 0 auto (tuning table, else one launch per
+                             level); 1 one launch per level; 2 one persistent launch with a grid
+                             barrier (falls back to 1 if its blocks cannot all be resident) */
+    int32_t pad_;
 } mpcg_options;
 
 typedef struct mpcg_ctx mpcg_ctx;

@@ -49,12 +49,16 @@ class Solver:
 
     def __init__(self, n_max: int, nnz_max: int, *, k0: int = 20, knn_k: int = 0, tol_mode: int = 0,
                  max_restarts: int = 5, graph_iters: int = 0, maxit1: int = 0, maxit2: int = 0,
-                 model: str | None = None, precond: int = 0, device="cuda"):
-        """precond = 1: Jacobi-preconditioned stages (M = diag(A))."""
+                 model: str | None = None, precond: int = 0, dot_acc: int = 0, spmv_variant: int = 0,
+                 bfs_mode: int = 0, device="cuda"):
+        """precond = 1: Jacobi-preconditioned stages (M = diag(A)); dot_acc = 1:
+        FP32-accumulated FP32-phase dot products; spmv_variant / bfs_mode: see
+        mpcg_options in include/mpcg.h."""
         import torch
         self.device = torch.device(device)
         self.stream = torch.cuda.current_stream(self.device)
-        opt = mpcg_options(k0, knn_k, tol_mode, max_restarts, graph_iters, precond, maxit1, maxit2)
+        opt = mpcg_options(k0, knn_k, tol_mode, max_restarts, graph_iters, precond, maxit1, maxit2, dot_acc,
+                           spmv_variant, bfs_mode, 0)
         self.ctx = capi.mpcg_create(opt, self.stream.cuda_stream)
         nbytes = capi.mpcg_workspace_size(self.ctx, max(1, n_max), max(0, nnz_max))
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -123,10 +127,10 @@ class BatchSolver:
 
     def __init__(self, max_rows: int, max_entries: int, max_systems: int, *, k0: int = 20, knn_k: int = 0,
                  tol_mode: int = 0, max_restarts: int = 5, maxit1: int = 0, maxit2: int = 0,
-                 model: str | None = DEFAULT_MODEL, device="cuda"):
+                 model: str | None = DEFAULT_MODEL, dot_acc: int = 0, device="cuda"):
         import torch
         self.device = torch.device(device)
-        opt = mpcg_options(k0, knn_k, tol_mode, max_restarts, 0, 0, maxit1, maxit2)
+        opt = mpcg_options(k0, knn_k, tol_mode, max_restarts, 0, 0, maxit1, maxit2, dot_acc)
         self.ctx = capi.mpcg_create(opt, torch.cuda.current_stream(self.device).cuda_stream)
         if model:
             st = capi.mpcg_load_model(self.ctx, model)

@@ -46,17 +46,20 @@ def build(verbose: bool = False) -> str:
     hipcc = _hipcc()
     common = ["-O3", "-fPIC", "-std=c++17", "-pthread", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall"]
     dev = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-    objs = []
+    cmds, objs = [], []
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD_DIR, src + ".o")
-        _run([hipcc, *common, *dev, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj])
+        cmds.append([hipcc, *common, *dev, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD_DIR, src + ".o")
-        _run(["g++", "-O2", "-fPIC", "-std=c++17", "-ffp-contract=off", f"-I{INCLUDE}", f"-I{CSRC}",
-              "-Wall", "-c",
-              os.path.join(CSRC, src), "-o", obj])
+        cmds.append(["g++", "-O2", "-fPIC", "-std=c++17", "-ffp-contract=off", f"-I{INCLUDE}", f"-I{CSRC}",
+                     "-Wall", "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    # one compiler process per source, a few at a time
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=max(1, min(8, os.cpu_count() or 1))) as ex:
+        list(ex.map(_run, cmds))
     tmp = LIB + ".tmp"
     _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs])
     os.replace(tmp, LIB)

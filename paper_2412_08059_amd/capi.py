@@ -85,7 +85,9 @@ class mpcg_stats(ctypes.Structure):
 class mpcg_options(ctypes.Structure):
     _fields_ = [("k0", ctypes.c_int32), ("knn_k", ctypes.c_int32), ("tol_mode", ctypes.c_int32),
                 ("max_restarts", ctypes.c_int32), ("graph_iters", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("maxit1", ctypes.c_int64), ("maxit2", ctypes.c_int64)]
+                ("maxit1", ctypes.c_int64), ("maxit2", ctypes.c_int64),
+                ("dot_acc", ctypes.c_int32), ("spmv_variant", ctypes.c_int32), ("bfs_mode", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 class mpcg_request(ctypes.Structure):

@@ -618,6 +618,7 @@ Engine *engine_create(int device, const mpcg_options &opt, const KnnModel *model
     }
     e->model = model;
     e->a = carve(arena, max_sys, (int32_t)max_slices, max_entries);
+    e->a.acc32 = opt.dot_acc;
     e->slots.resize(max_sys);
     e->finals.resize(max_sys);
     e->slices.init(max_slices);

@@ -116,6 +116,8 @@ struct BArena {
     int32_t *small_sys;                    // systems expanding small levels this step
     int32_t *counts;                       // [0] = #act, [1] = #small, [2] = admission error (unused)
     int64_t *items;                        // total items of the large level
+    int32_t acc32;                         // dot_acc = 1: FP32-phase dot products accumulate in FP32
+    int32_t pad_;
 };
 
 size_t arena_bytes(int32_t max_sys, int32_t max_slices, int64_t max_entries);

@@ -40,16 +40,16 @@ struct mpcg_ctx {
     KnnModel model;
     bool has_model = false;
     float last_kernel_ms = 0.0f;
-    bool force_csr = false;   // MPCG_FORCE_CSR=1: always use the CSR-stream kernels
+    bool force_csr = false;   // spmv_variant 3: always use the CSR-stream kernels
     int sell_batch = 4;       // MPCG_SELL_BATCH=4|8: loads in flight per row in the SELL kernels
     int sell_bf = 1;          // MPCG_SELL_BF=0..3: whole-batch loads (bit 0: FP32 kernels, bit 1: FP64)
-    int sell_split = -1;      // MPCG_SELL_SPLIT=0|1: two-launch CG product (-1: for 32-bit columns)
+    int sell_split = -1;      // spmv_variant 1|2: fused|two-launch CG product (-1: two launches for 32-bit columns)
     int cg_grid = kMaxGrid;   // MPCG_CG_GRID: most blocks of a CG product launch
     int up_grid = kUpdateGrid;   // MPCG_UP_GRID: most blocks of a CG update launch
     mpcg::batch::Engine *eng = nullptr;   // batched engine (own thread and stream), if started
     int bfs_grid = kBfsLevelBlocks;   // MPCG_BFS_GRID: blocks of the BFS level kernel
     int bfs_precheck = 0;             // MPCG_BFS_PRECHECK=1: read the distance before claiming a vertex
-    int bfs_persist = 0;              // MPCG_BFS_PERSIST=1: large levels in one persistent launch
+    int bfs_persist = 0;              // bfs_mode 2: large levels in one persistent launch
     // Algorithm II runs the 2BFS beside the FP32 iterations.  A SELL product
     // grid of 8 blocks per CU fills every wave slot, so each resident BFS
     // block would push one product block to the end of the launch (the slice
@@ -539,7 +539,8 @@ mpcg_status fp32_prefix(mpcg_ctx *c, const Plan &p, const double *b, int32_t k0,
     float *x = p.at<float>(p.L.x32), *r = p.at<float>(p.L.r32), *q = p.at<float>(p.L.q32);
     float *dA = p.at<float>(p.L.dA32), *dB = p.at<float>(p.L.dB32);
     // thr = 0: only gamma' = 0 or a breakdown ends the prefix before k0
-    launch_init32(c->stream, b, x, r, dA, p.n, 0.0, 1, k0, k0, p.pc ? p.dg32 : nullptr, p.z32, p.sp, p.st);
+    launch_init32(c->stream, b, x, r, dA, p.n, 0.0, 1, k0, k0, p.pc ? p.dg32 : nullptr, p.z32, p.sp, p.st,
+                  c->opt.dot_acc);
     HIPCHK(hipGetLastError());
     mpcg_status rc = read_state(c, p, s);
     if (rc != MPCG_OK) return rc;
@@ -597,27 +598,26 @@ mpcg_status mpcg_create(mpcg_ctx **out, const mpcg_options *opt, void *hip_strea
         if (o.max_restarts < 0) return MPCG_EINVAL;
     }
     if (o.k0 > kK0Max || o.tol_mode < 0 || o.tol_mode > 1 || o.knn_k < 0 || o.graph_iters < 0 ||
-        o.precond < 0 || o.precond > 1)
+        o.precond < 0 || o.precond > 1 || o.dot_acc < 0 || o.dot_acc > 1 || o.spmv_variant < 0 ||
+        o.spmv_variant > 3 || o.bfs_mode < 0 || o.bfs_mode > 2)
         return MPCG_EINVAL;
     mpcg_ctx *c = new (std::nothrow) mpcg_ctx();
     if (!c) return MPCG_EDEVICE;
     c->opt = o;
     c->stream = static_cast<hipStream_t>(hip_stream);
     {
-        const char *e = std::getenv("MPCG_FORCE_CSR");
-        c->force_csr = e && e[0] == '1';
+        c->force_csr = o.spmv_variant == 3;
         const char *bt = std::getenv("MPCG_SELL_BATCH");
         if (bt && bt[0] == '8') c->sell_batch = 8;
         const int sbf = env_int("MPCG_SELL_BF", 1);
         c->sell_bf = sbf >= 0 && sbf <= 3 ? sbf : 1;
-        const int ssp = env_int("MPCG_SELL_SPLIT", -1);
-        c->sell_split = ssp == 0 || ssp == 1 ? ssp : -1;
+        c->sell_split = o.spmv_variant == 1 ? 0 : (o.spmv_variant == 2 ? 1 : -1);
         const int cgg = env_int("MPCG_CG_GRID", kMaxGrid);
         c->cg_grid = cgg >= 64 && cgg <= kMaxGrid ? cgg : kMaxGrid;
         const int bg = env_int("MPCG_BFS_GRID", kBfsLevelBlocks);
         c->bfs_grid = bg > 0 && bg <= 4096 ? bg : kBfsLevelBlocks;
         c->bfs_precheck = env_int("MPCG_BFS_PRECHECK", 0) ? 1 : 0;
-        c->bfs_persist = env_int("MPCG_BFS_PERSIST", 0) ? 1 : 0;
+        c->bfs_persist = o.bfs_mode == 2 ? 1 : 0;
         const int cgs = env_int("MPCG_CG_GRID_SHARED", 0);
         c->cg_grid_shared = cgs >= 64 && cgs <= kMaxGrid ? cgs : 0;
         const int bgs = env_int("MPCG_BFS_GRID_SHARED", 64);
@@ -861,7 +861,7 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
             }
         } else {
             launch_init32(c->stream, b, x32, r32, dA32, p.n, eps1, abs_tol, maxit1, 0, p.pc ? p.dg32 : nullptr,
-                          p.z32, p.sp, p.st);
+                          p.z32, p.sp, p.st, c->opt.dot_acc);
             HIPCHK(hipGetLastError());
             rc = read_state(c, p, &s);
             if (rc != MPCG_OK) return rc;

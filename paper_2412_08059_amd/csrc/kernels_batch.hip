@@ -60,6 +60,35 @@ __device__ inline double sys_sum(const BArena &a, const BSys &S, int j, double *
     return block_sum_d(acc, sm);
 }
 
+// dot_acc = 1: the FP32 phase's sums in float (partials stored widened, exact).
+__device__ inline float wave_sum_f(float v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline double sys_sum_f(const BArena &a, const BSys &S, int j, double *sm)
+{
+    float acc = 0.0f;
+    for (int i = threadIdx.x; i < S.nslices; i += kBlock) acc += (float)a.pslice[2 * (size_t)(S.slice0 + i) + j];
+    acc = wave_sum_f(acc);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sm[w] = (double)acc;
+    __syncthreads();
+    float s = 0.0f;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kBlock / 64; ++i) s += (float)sm[i];
+    __syncthreads();
+    return (double)s;
+}
+
+// A partial of an FP32-phase dot product in the precision dot_acc asks for:
+// the lane's term (exact in FP64, one rounding in FP32) summed over the wave.
+__device__ inline double wave_dot32(bool f32, float x, float y)
+{
+    return f32 ? (double)wave_sum_f(x * y) : wave_sum_d((double)x * (double)y);
+}
+
 __device__ inline int64_t rp_at(const void *rp, int i64, int64_t i)
 {
     return i64 ? static_cast<const int64_t *>(rp)[i] : (int64_t) static_cast<const int32_t *>(rp)[i];
@@ -187,7 +216,7 @@ k_admit_rows(BArena a, int32_t sys, const void *rp, int rp_i64, const double *b,
     a.dB32[g] = 0.0f;
     const int sl = slice0 + (int)(i >> 6);
     if (len > 0) atomicMax(&a.slice_w[sl], len);
-    const double pr = wave_sum_d((double)rv * (double)rv);
+    const double pr = wave_dot32(a.acc32, rv, rv);
     const double pb = wave_sum_d(bv * bv);
     for (int o = 32; o > 0; o >>= 1) err |= __shfl_xor(err, o, 64);
     if ((threadIdx.x & 63) == 0) {
@@ -271,7 +300,7 @@ __global__ void __launch_bounds__(kBlock) k_admit_finish(BArena a, int32_t sys, 
 {
     __shared__ double sm[kBlock / 64 + 1];
     BSys &S = a.sys[sys];
-    const double g0 = sys_sum(a, S, 0, sm);
+    const double g0 = a.acc32 ? sys_sum_f(a, S, 0, sm) : sys_sum(a, S, 0, sm);
     const double bb = sys_sum(a, S, 1, sm);
     if (threadIdx.x == 0) {
         S.bb = bb;
@@ -442,7 +471,8 @@ __device__ inline double cg_product(const BArena &a, const BSys &S, const T *val
     const T dn = first ? r[row] : fma_b<T>(beta, dold[row], r[row]);
     dnew[row] = dn;
     q[row] = acc;
-    return (double)dn * (double)acc;
+    if (sizeof(T) == 4 && a.acc32) return (double)wave_sum_f((float)dn * (float)acc);   // already summed
+    return wave_sum_d((double)dn * (double)acc);
 }
 
 // Restart: r = b - A x with x = float64(x~), x, or 0; x takes that value.
@@ -504,8 +534,7 @@ __global__ void __launch_bounds__(kBlock) k_b_product(BArena a, int32_t hi_slice
     double p;
     if (mode == kCg32) p = cg_product<float>(a, S, a.v32, a.r32, a.dA32, a.dB32, a.q32, base, row, len);
     else if (mode == kCg64) p = cg_product<double>(a, S, a.v64, a.r64, a.dA64, a.dB64, a.q64, base, row, len);
-    else p = residual(a, S, mode == kRestart, base, row, len);
-    p = wave_sum_d(p);
+    else p = wave_sum_d(residual(a, S, mode == kRestart, base, row, len));
     if (lane == 0) a.pslice[2 * (size_t)sl] = p;
 }
 
@@ -517,7 +546,7 @@ __global__ void __launch_bounds__(kBlock) k_b_scalar1(BArena a)
     const int mode = S.mode;
     if (threadIdx.x == 0 && S.snap_mask) S.snap_mask = 0;   // the product of this step took the copies
     if (mode != kCg32 && mode != kCg64 && mode != kRestart && mode != kResid) return;
-    const double v = sys_sum(a, S, 0, sm);
+    const double v = (mode == kCg32 && a.acc32) ? sys_sum_f(a, S, 0, sm) : sys_sum(a, S, 0, sm);
     if (threadIdx.x != 0) return;
     const double sb = sqrt(S.bb);
     if (mode == kCg32 || mode == kCg64) {
@@ -579,14 +608,16 @@ __global__ void __launch_bounds__(kBlock) k_b_scalar1(BArena a)
 }
 
 template <typename T>
-__device__ inline double cg_update(const BSys &S, T *x, T *r, const T *q, const T *dA, const T *dB, int row)
+__device__ inline double cg_update(const BArena &a, const BSys &S, T *x, T *r, const T *q, const T *dA, const T *dB,
+                                   int row)
 {
     const T alpha = (T)S.alpha;
     const T *d = (S.ph_it & 1) ? dB : dA;
     x[row] = fma_b<T>(alpha, d[row], x[row]);
     const T rv = fma_b<T>(-alpha, q[row], r[row]);
     r[row] = rv;
-    return (double)rv * (double)rv;
+    if (sizeof(T) == 4 && a.acc32) return (double)wave_sum_f((float)rv * (float)rv);
+    return wave_sum_d((double)rv * (double)rv);
 }
 
 __global__ void __launch_bounds__(kBlock) k_b_update(BArena a, int32_t hi_slice)
@@ -599,9 +630,8 @@ __global__ void __launch_bounds__(kBlock) k_b_update(BArena a, int32_t hi_slice)
     if (!S.upd) return;
     const int lane = threadIdx.x & 63;
     const int row = sl * 64 + lane;
-    double p = S.mode == kCg32 ? cg_update<float>(S, a.x32, a.r32, a.q32, a.dA32, a.dB32, row)
-                               : cg_update<double>(S, a.x64, a.r64, a.q64, a.dA64, a.dB64, row);
-    p = wave_sum_d(p);
+    const double p = S.mode == kCg32 ? cg_update<float>(a, S, a.x32, a.r32, a.q32, a.dA32, a.dB32, row)
+                                     : cg_update<double>(a, S, a.x64, a.r64, a.q64, a.dA64, a.dB64, row);
     if (lane == 0) a.pslice[2 * (size_t)sl] = p;
 }
 
@@ -611,7 +641,7 @@ __global__ void __launch_bounds__(kBlock) k_b_scalar2(BArena a)
     __shared__ double sm[kBlock / 64 + 1];
     BSys &S = a.sys[blockIdx.x];
     if (!S.upd) return;
-    const double g = sys_sum(a, S, 0, sm);
+    const double g = (S.mode == kCg32 && a.acc32) ? sys_sum_f(a, S, 0, sm) : sys_sum(a, S, 0, sm);
     if (threadIdx.x != 0) return;
     S.upd = 0;
     const double gp = S.gamma;

@@ -764,10 +764,9 @@ k_bfs_level(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int
 // Expands every level whose frontier is larger than small_max in ONE launch:
 // the blocks meet at a grid barrier between levels instead of ending the
 // kernel.  Data other blocks produce within the launch (queue entries, level
-// counters, the barrier count) is written and read only with agent-scope
-// atomics -- coherent across the XCDs' L2 caches without cache write-back or
-// invalidation -- and each wave waits for its memory operations to complete
-// before its block arrives at the barrier.  The read-only CSR pattern and the
+// counters, the barrier count) is written and read with agent-scope atomics,
+// and the barrier orders them with agent-scope release and acquire fences
+// (the HIP memory model's guarantee, not a property of one chip).  The read-only CSR pattern and the
 // distance pre-check use plain loads (a stale distance only costs a failing
 // compare-and-swap).  Every wait is bounded; if one runs out the kernel
 // raises st->guard and the host repeats the BFS with one launch per level.
@@ -902,12 +901,16 @@ k_bfs_persist(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, i
         if (lane == 0 && wmin != kIntMax) atomicMin(&s_min, wmin);
         __syncthreads();
         if (threadIdx.x == 0 && s_min != kIntMax) atomicMin(&st->bfs_min[(L + 1) & 3], s_min);
-        // this wave's queue stores, claims and counters are complete before its block arrives
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        // Grid barrier.  Every thread's stores and claims of this level are
+        // released at agent scope before its block arrives; the arrival is a
+        // release read-modify-write, the wait ends with an acquire fence, and
+        // every thread acquires at agent scope after it, so the next level
+        // reads what all blocks wrote in this one.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
         if (threadIdx.x == 0) {
             s_ok = 1;
-            __hip_atomic_fetch_add(&st->bfs_bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&st->bfs_bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t target = round * gridDim.x;
             uint32_t spins = 0;
             while (__hip_atomic_load(&st->bfs_bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -917,8 +920,10 @@ k_bfs_persist(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, i
                     break;
                 }
             }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // pairs with the arrivals' release
         }
         __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (!s_ok) {
             if (threadIdx.x == 0) atomicOr(&st->guard, 1);
             return;

@@ -82,6 +82,46 @@ __device__ inline double reduce_partials(const double *p, int cnt, int stride, i
     return block_sum_all(acc, sm);
 }
 
+// FP32 accumulation (dot_acc = 1): the same tree in float.  Partials are
+// stored widened to double (exact) and narrowed back (exact) when reduced.
+__device__ inline float wave_sum_f(float v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline float block_sum_f(float v, double *sm)
+{
+    v = wave_sum_f(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sm[w] = (double)v;
+    __syncthreads();
+    float s = 0.0f;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < kBlock / 64; ++i) s += (float)sm[i];
+    }
+    __syncthreads();
+    return s;
+}
+
+__device__ inline double reduce_partials_f(const double *p, int cnt, int stride, int j, double *sm)
+{
+    float acc = 0.0f;
+    for (int i = threadIdx.x; i < cnt; i += kBlock) acc += (float)p[(size_t)i * stride + j];
+    float s = block_sum_f(acc, sm);
+    if (threadIdx.x == 0) sm[kBlock / 64] = (double)s;
+    __syncthreads();
+    const double r = sm[kBlock / 64];
+    __syncthreads();
+    return r;
+}
+
+// FP32-phase reduction in the precision dot_acc asks for.
+__device__ inline double reduce_partials_acc(bool f32, const double *p, int cnt, int stride, int j, double *sm)
+{
+    return f32 ? reduce_partials_f(p, cnt, stride, j, sm) : reduce_partials(p, cnt, stride, j, sm);
+}
+
 // Blocks are dispatched round-robin over the XCDs; map them so that each XCD
 // walks a contiguous range of rows and its own L2 sees the x-gather reuse.
 __device__ inline int xcd_remap(int b, int nb)
@@ -193,10 +233,12 @@ __device__ inline void resume_phase(DevState *st)
 // in FP64 for k_fin_init32.
 __global__ void __launch_bounds__(kBlock)
 k_init32(const double *__restrict__ b, float *__restrict__ x, float *__restrict__ r,
-         float *__restrict__ dA, int32_t n, const float *__restrict__ dg, float *__restrict__ z, double *part)
+         float *__restrict__ dA, int32_t n, const float *__restrict__ dg, float *__restrict__ z, double *part,
+         int acc32)
 {
     __shared__ double sm[kBlock / 64 + 1];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    float f0 = 0.0f, f2 = 0.0f;
     const int64_t nchunk = ((int64_t)n + kVecTile - 1) / kVecTile;
     for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
 #pragma unroll
@@ -208,19 +250,21 @@ k_init32(const double *__restrict__ b, float *__restrict__ x, float *__restrict_
                 r[i] = rv;
                 x[i] = 0.0f;
                 dA[i] = 0.0f;
-                s0 = fma((double)rv, (double)rv, s0);
+                if (acc32) f0 = fmaf(rv, rv, f0);
+                else s0 = fma((double)rv, (double)rv, s0);
                 s1 = fma(bv, bv, s1);
                 if (dg) {
                     const float zv = rv / dg[i];
                     z[i] = zv;
-                    s2 = fma((double)rv, (double)zv, s2);
+                    if (acc32) f2 = fmaf(rv, zv, f2);
+                    else s2 = fma((double)rv, (double)zv, s2);
                 }
             }
         }
     }
-    s0 = block_sum(s0, sm);
+    s0 = acc32 ? (double)block_sum_f(f0, sm) : block_sum(s0, sm);
     s1 = block_sum(s1, sm);
-    s2 = dg ? block_sum(s2, sm) : s0;
+    s2 = dg ? (acc32 ? (double)block_sum_f(f2, sm) : block_sum(s2, sm)) : s0;
     if (threadIdx.x == 0) {
         part[3 * blockIdx.x] = s0;
         part[3 * blockIdx.x + 1] = s1;
@@ -230,27 +274,28 @@ k_init32(const double *__restrict__ b, float *__restrict__ x, float *__restrict_
 
 __global__ void __launch_bounds__(kBlock)
 k_fin_init32(const double *part, int cnt, double eps, int abs_tol, int32_t maxit, int32_t k0rec,
-             DevState *st)
+             DevState *st, int acc32)
 {
     __shared__ double sm[kBlock / 64 + 1];
-    const double g = reduce_partials(part, cnt, 3, 0, sm);
+    const double g = reduce_partials_acc(acc32, part, cnt, 3, 0, sm);
     const double bb = reduce_partials(part, cnt, 3, 1, sm);
-    const double rho = reduce_partials(part, cnt, 3, 2, sm);
+    const double rho = reduce_partials_acc(acc32, part, cnt, 3, 2, sm);
     if (threadIdx.x == 0) {
         st->bnorm2 = bb;
         st->k0rec = k0rec;
+        st->acc32 = acc32;
         start_phase(st, g, rho, 0, eps, abs_tol, maxit);
     }
 }
 
 void launch_init32(hipStream_t s, const double *b, float *x, float *r, float *dA, int32_t n,
                    double eps, int abs_tol, int32_t maxit, int32_t k0rec, const float *dg, float *z,
-                   double *part, DevState *st)
+                   double *part, DevState *st, int acc32)
 {
     const int grid = vec_grid(n);
-    hipLaunchKernelGGL(k_init32, dim3(grid), dim3(kBlock), 0, s, b, x, r, dA, n, dg, z, part);
+    hipLaunchKernelGGL(k_init32, dim3(grid), dim3(kBlock), 0, s, b, x, r, dA, n, dg, z, part, acc32);
     hipLaunchKernelGGL(k_fin_init32, dim3(1), dim3(kBlock), 0, s, part, grid, eps, abs_tol, maxit, k0rec,
-                       st);
+                       st, acc32);
 }
 
 // Continue a phase with a new stop test (Algorithm II after the k0 prefix);
@@ -378,6 +423,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv(SpmvArgs<T> a)
     bool x_pending = false;   // x += alpha_{it-1} d_{it-1} still to apply in the main loop
     const T *dold = nullptr;
     T *dnew = nullptr;
+    const bool f32acc = MODE == kModeCg && sizeof(T) == 4 && st->acc32;   // dot_acc = 1
     if (MODE == kModeCg) {
         const int it = a.it;
         __shared__ int s_skip, s_xdone;
@@ -392,8 +438,8 @@ __global__ void __launch_bounds__(kBlock) k_spmv(SpmvArgs<T> a)
         if (it != a.it0) {
             const bool xdone = s_xdone;
             // rho_it (alpha, beta) and gamma_it = r.r (stop test, v); equal without a preconditioner
-            const double rho = reduce_partials(a.up, a.nup, 1, 0, sm);
-            const double g = a.pc ? reduce_partials(a.up + a.nup, a.nup, 1, 0, sm) : rho;
+            const double rho = reduce_partials_acc(f32acc, a.up, a.nup, 1, 0, sm);
+            const double g = a.pc ? reduce_partials_acc(f32acc, a.up + a.nup, a.nup, 1, 0, sm) : rho;
             const double gp = st->gr[(it - 1) & 1];
             const double rhop = st->gam[(it - 1) & 1];
             alpha_prev = (T)st->alph[(it - 1) & 1];
@@ -444,6 +490,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv(SpmvArgs<T> a)
     const int t1 = (int)((int64_t)(lb + 1) * a.ntiles / gridDim.x);
     double s[NV];
     for (int j = 0; j < NV; ++j) s[j] = 0.0;
+    float sf = 0.0f;   // d.q in FP32 (dot_acc = 1)
 
     for (int t = t0; t < t1; ++t) {
         const int row0 = t * a.R;
@@ -490,7 +537,8 @@ __global__ void __launch_bounds__(kBlock) k_spmv(SpmvArgs<T> a)
                 const T dn = fmaT<T>(beta, dof, a.r[my_row]);
                 dnew[my_row] = dn;
                 a.q[my_row] = acc;
-                s[0] = fma((double)dn, (double)acc, s[0]);
+                if (f32acc) sf = fmaf((float)dn, (float)acc, sf);
+                else s[0] = fma((double)dn, (double)acc, s[0]);
             } else {
                 const double bv = a.b[my_row];
                 const double res = bv - (double)acc;
@@ -512,6 +560,11 @@ __global__ void __launch_bounds__(kBlock) k_spmv(SpmvArgs<T> a)
         }
     }
     if (MODE == kModePlain) return;
+    if (f32acc) {
+        const float bs = block_sum_f(sf, sm);
+        if (tid == 0) a.part[lb] = (double)bs;
+        return;
+    }
     for (int j = 0; j < NV; ++j) {
         const double bs = block_sum(s[j], sm);
         if (tid == 0) a.part[(size_t)lb * NV + j] = bs;
@@ -643,9 +696,13 @@ k_cg_update(int32_t n, T *__restrict__ r, const T *__restrict__ q, const double 
     }
     if (threadIdx.x == 0) s_skip = st->stop_it <= it;
     const double g = st->gam[it & 1];
+    const bool f32acc = sizeof(T) == 4 && st->acc32;   // dot_acc = 1
     // delta: the product's partials in a fixed order (the same bits in every block)
     double acc = 0.0;
-    {
+    float accf = 0.0f;
+    if (f32acc) {
+        for (int i = threadIdx.x; i < nsp; i += kBlock) accf += (float)sp[i];
+    } else {
         int i = threadIdx.x;
         for (; i + 3 * kBlock < nsp; i += 4 * kBlock) {
             const double p0 = sp[i], p1 = sp[i + kBlock], p2 = sp[i + 2 * kBlock], p3 = sp[i + 3 * kBlock];
@@ -658,7 +715,16 @@ k_cg_update(int32_t n, T *__restrict__ r, const T *__restrict__ q, const double 
     }
     __syncthreads();
     if (s_skip) return;
-    const double delta = block_sum_all(acc, sm);
+    double delta;
+    if (f32acc) {
+        const float df = block_sum_f(accf, sm);
+        if (threadIdx.x == 0) sm[kBlock / 64] = (double)df;
+        __syncthreads();
+        delta = sm[kBlock / 64];
+        __syncthreads();
+    } else {
+        delta = block_sum_all(acc, sm);
+    }
     if (!isfinite(delta) || !(delta > 0.0)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             st->delta = delta;
@@ -677,14 +743,17 @@ k_cg_update(int32_t n, T *__restrict__ r, const T *__restrict__ q, const double 
         st->alph[it & 1] = (double)alpha;
     }
     double s = 0.0, s2 = 0.0;
+    float sf = 0.0f, s2f = 0.0f;
     auto elem = [&](int64_t i, T r0, T q0, T d0) {
         const T rn = fmaT<T>(-alpha, q0, r0);
         r[i] = rn;
-        s2 = fma((double)rn, (double)rn, s2);
+        if (f32acc) s2f = fmaf((float)rn, (float)rn, s2f);
+        else s2 = fma((double)rn, (double)rn, s2);
         if (PC) {
             const T zv = rn / d0;
             z[i] = zv;
-            s = fma((double)rn, (double)zv, s);
+            if (f32acc) sf = fmaf((float)rn, (float)zv, sf);
+            else s = fma((double)rn, (double)zv, s);
         }
     };
 #pragma unroll
@@ -703,14 +772,14 @@ k_cg_update(int32_t n, T *__restrict__ r, const T *__restrict__ q, const double 
         }
     }
     if (PC) {
-        s = block_sum(s, sm);
-        s2 = block_sum(s2, sm);
+        s = f32acc ? (double)block_sum_f(sf, sm) : block_sum(s, sm);
+        s2 = f32acc ? (double)block_sum_f(s2f, sm) : block_sum(s2, sm);
         if (threadIdx.x == 0) {
             up[blockIdx.x] = s;
             up[gridDim.x + blockIdx.x] = s2;
         }
     } else {
-        s2 = block_sum(s2, sm);
+        s2 = f32acc ? (double)block_sum_f(s2f, sm) : block_sum(s2, sm);
         if (threadIdx.x == 0) up[blockIdx.x] = s2;
     }
 }

@@ -278,6 +278,8 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
     bool x_pending = false;   // x += alpha_{it-1} d_{it-1} still to apply in the main loop
     const T *dold = nullptr;
     T *dnew = nullptr;
+    // dot_acc = 1: the FP32 phase's dot products accumulate in FP32
+    const bool f32acc = (MODE == kSellCg || MODE == kSellDir || MODE == kSellCgD) && sizeof(T) == 4 && st->acc32;
     if (MODE == kSellCgD) {   // the direction is formed: skip only after a stop
         __shared__ int s_skip2;
         if (tid == 0) s_skip2 = st->stop_it <= a.it;
@@ -299,8 +301,10 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
         if (it != a.it0) {
             const bool xdone = s_xdone;
             // rho_it (alpha, beta) and gamma_it = r.r (stop test, v); equal without a preconditioner
-            const double rho = sell_reduce_partials(a.up, a.nup, sm);
-            const double g = a.pc ? sell_reduce_partials(a.up + a.nup, a.nup, sm) : rho;
+            const double rho = f32acc ? sell_reduce_partials_f(a.up, a.nup, sm) : sell_reduce_partials(a.up, a.nup, sm);
+            const double g = !a.pc ? rho
+                             : f32acc ? sell_reduce_partials_f(a.up + a.nup, a.nup, sm)
+                                      : sell_reduce_partials(a.up + a.nup, a.nup, sm);
             const double gp = st->gr[(it - 1) & 1];
             const double rhop = st->gam[(it - 1) & 1];
             alpha_prev = (T)st->alph[(it - 1) & 1];
@@ -359,6 +363,7 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
     const int lb = blockIdx.x;   // partial slot (fixed per block, so sums keep one order)
     double s[NV];
     for (int j = 0; j < NV; ++j) s[j] = 0.0;
+    float sf = 0.0f;   // d.q in FP32 (dot_acc = 1)
 
     for (SliceWalk w = slice_walk(a.nslices); w.g < w.g_end; w.g += w.step) {
         const int sl = w.g * (kBlock / 64) + wv;
@@ -420,14 +425,16 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
             } else if (MODE == kSellCgD) {
                 const T dn = dold[row];
                 a.q[row] = acc;
-                s[0] = fma((double)dn, (double)acc, s[0]);
+                if (f32acc) sf = fmaf((float)dn, (float)acc, sf);
+                else s[0] = fma((double)dn, (double)acc, s[0]);
             } else if (MODE == kSellCg) {
                 const T dof = dold[row];
                 if (x_pending) a.x[row] = fma_t<T>(alpha_prev, dof, a.x[row]);
                 const T dn = fma_t<T>(beta, dof, a.r[row]);
                 dnew[row] = dn;
                 a.q[row] = acc;
-                s[0] = fma((double)dn, (double)acc, s[0]);
+                if (f32acc) sf = fmaf((float)dn, (float)acc, sf);
+                else s[0] = fma((double)dn, (double)acc, s[0]);
             } else {
                 const double bv = a.b[row];
                 const double res = bv - (double)acc;
@@ -449,6 +456,11 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
         }
     }
     if (MODE == kSellPlain) return;
+    if (f32acc) {
+        const float bs = sell_block_sum_f(sf, sm);
+        if (tid == 0) a.part[lb] = (double)bs;
+        return;
+    }
     for (int j = 0; j < NV; ++j) {
         const double bs = sell_block_sum(s[j], sm);
         if (tid == 0) a.part[(size_t)lb * NV + j] = bs;

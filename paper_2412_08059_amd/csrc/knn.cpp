@@ -9,10 +9,12 @@
 // Tie rules: the neighbour set starts as the first k samples and a later
 // sample replaces the current farthest member only if it is strictly closer
 // (the farthest member is the one with the largest distance, the largest
-// sample index on equal distances); if any neighbour is at distance zero only
-// the zero-distance neighbours vote, one vote each; equal class scores go to
-// the smaller t (the larger eps1).
+// sample index on equal distances) -- which leaves the k smallest samples in
+// the order (distance, index), the set this file selects directly; if any
+// neighbour is at distance zero only the zero-distance neighbours vote, one
+// vote each; equal class scores go to the smaller t (the larger eps1).
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -111,58 +113,47 @@ int knn_select(const KnnModel &m, const double chi[4], int32_t k_override, int32
     int64_t k = k_override > 0 ? k_override : m.k;
     if (k <= 0) return MPCG_EINVAL;
     if (k > m.ns) k = m.ns;
-    double q[4];
-    for (int j = 0; j < 4; ++j) q[j] = norm01(chi[j], m.fmin[j], m.fmax[j]);
-    std::vector<double> d2((size_t)m.ns);
+    // squared distance of every training sample to the query in the
+    // normalised space, features in index order, one rounding per operation
+    auto scaled = [&](double x, int j) { return norm01(x, m.fmin[j], m.fmax[j]); };
+    std::vector<std::pair<double, int64_t>> cand((size_t)m.ns);
     for (int64_t i = 0; i < m.ns; ++i) {
-        double acc = 0.0;
+        double d2 = 0.0;
         for (int j = 0; j < 4; ++j) {
-            if (!(m.mask & (1 << j))) continue;
-            const double s = norm01(m.feat[4 * i + j], m.fmin[j], m.fmax[j]);
-            const double diff = q[j] - s;
-            const double sq = diff * diff;
-            acc = acc + sq;
+            if ((m.mask >> j) & 1) {
+                const double e = scaled(chi[j], j) - scaled(m.feat[4 * i + j], j);
+                const double e2 = e * e;
+                d2 = d2 + e2;
+            }
         }
-        d2[(size_t)i] = acc;
+        cand[(size_t)i] = {d2, i};
     }
-    // neighbour set as sample indices; the farthest member is found by scan
-    std::vector<int64_t> set((size_t)k);
-    for (int64_t a = 0; a < k; ++a) set[(size_t)a] = a;
-    for (int64_t i = k; i < m.ns; ++i) {
-        int64_t far = 0;
-        for (int64_t a = 1; a < k; ++a) {
-            const int64_t ca = set[(size_t)a], cf = set[(size_t)far];
-            if (d2[(size_t)ca] > d2[(size_t)cf] || (d2[(size_t)ca] == d2[(size_t)cf] && ca > cf)) far = a;
-        }
-        if (d2[(size_t)i] < d2[(size_t)set[(size_t)far]]) set[(size_t)far] = i;
-    }
-    // weights are summed in ascending sample order
-    for (int64_t a = 1; a < k; ++a) {
-        const int64_t key = set[(size_t)a];
-        int64_t b = a - 1;
-        while (b >= 0 && set[(size_t)b] > key) {
-            set[(size_t)b + 1] = set[(size_t)b];
-            --b;
-        }
-        set[(size_t)(b + 1)] = key;
-    }
-    bool zero = false;
-    for (int64_t a = 0; a < k; ++a)
-        if (d2[(size_t)set[(size_t)a]] == 0.0) zero = true;
-    double score[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t a = 0; a < k; ++a) {
-        const int64_t i = set[(size_t)a];
-        const int t = m.label[i];
-        if (zero) {
-            if (d2[(size_t)i] == 0.0) score[t - 2] = score[t - 2] + 1.0;
+    // The tie rules (start from the first k samples; a later one replaces the
+    // farthest member -- largest distance, then largest index -- only when
+    // strictly closer) keep exactly the k smallest samples under the total
+    // order (distance, index): select those.
+    std::partial_sort(cand.begin(), cand.begin() + k, cand.end());
+    cand.resize((size_t)k);
+    // votes are added in ascending sample index
+    std::sort(cand.begin(), cand.end(),
+              [](const std::pair<double, int64_t> &x, const std::pair<double, int64_t> &y) { return x.second < y.second; });
+    const bool at_zero = std::any_of(cand.begin(), cand.end(), [](const std::pair<double, int64_t> &c) {
+        return c.first == 0.0;
+    });
+    double vote[6] = {0, 0, 0, 0, 0, 0};
+    for (const auto &c : cand) {
+        const int cls = m.label[c.second];
+        if (at_zero) {
+            if (c.first == 0.0) vote[cls - 2] = vote[cls - 2] + 1.0;   // exact matches vote by count
         } else {
-            score[t - 2] = score[t - 2] + 1.0 / std::sqrt(d2[(size_t)i]);
+            vote[cls - 2] = vote[cls - 2] + 1.0 / std::sqrt(c.first);   // eq. 23: weight 1/rho
         }
     }
+    // the largest score wins; on equal scores the smaller t (larger eps1)
     int best = 2;
-    for (int t = 3; t <= 7; ++t)
-        if (score[t - 2] > score[best - 2]) best = t;
-    if (exact) *exact = zero ? 1 : 0;
+    for (int cls = 3; cls <= 7; ++cls)
+        if (vote[cls - 2] > vote[best - 2]) best = cls;
+    if (exact) *exact = at_zero ? 1 : 0;
     return best;
 }
 

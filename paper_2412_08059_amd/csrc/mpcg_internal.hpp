@@ -62,7 +62,7 @@ struct alignas(256) DevState {
     int32_t ing_err;  // IngestError bits
     int32_t max_row;  // longest row seen by the ingest kernel
     int32_t max_band; // largest |i - j| over the stored entries
-    int32_t pad_band;
+    int32_t acc32;    // FP32 phase: dot products accumulated in FP32 (dot_acc = 1), else in FP64
     double ratios[kK0Max];
     // BFS.  Launch k of a run expands level bfs_lv[k & 1] (the frontier of
     // level L is queue L & 1, bfs_cnt[L & 3] vertices, smallest bfs_min[L & 3])
@@ -174,9 +174,13 @@ void launch_fill_f32(hipStream_t s, float *p, int64_t n, float v);
 void launch_fill_i32(hipStream_t s, int32_t *p, int64_t n, int32_t v);
 // FP32 phase start.  Jacobi (dg != nullptr): z = r / dg as well, and the
 // phase's rho is r.z; otherwise rho = r.r.
+// acc32 = 1: the FP32 phase's dot products (here r~.r~ and r~.z, later d.q,
+// r.r, r.z) accumulate in FP32 -- per thread, in the wave and block sums and
+// over the block partials -- instead of FP64; recorded in st->acc32 for the
+// phase's kernels.
 void launch_init32(hipStream_t s, const double *b, float *x, float *r, float *dA, int32_t n,
                    double eps, int abs_tol, int32_t maxit, int32_t k0rec, const float *dg, float *z,
-                   double *part, DevState *st);
+                   double *part, DevState *st, int acc32);
 // Jacobi: dg64 = diag(A), dg32 = float32(dg64); a row without a positive,
 // finite diagonal entry sets kErrDiag.
 void launch_diag(hipStream_t s, const int32_t *rp, const int32_t *col, const double *val, int32_t n,

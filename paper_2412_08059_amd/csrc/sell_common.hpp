@@ -55,6 +55,39 @@ __device__ inline double sell_reduce_partials(const double *p, int cnt, double *
     return s;
 }
 
+// FP32 accumulation (dot_acc = 1): the same trees in float; partials are
+// stored widened to double and narrowed back, both exact.
+__device__ inline float sell_wave_sum_f(float v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline float sell_block_sum_f(float v, double *sm)
+{
+    v = sell_wave_sum_f(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sm[w] = (double)v;
+    __syncthreads();
+    float s = 0.0f;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kBlock / 64; ++i) s += (float)sm[i];
+    __syncthreads();
+    return s;
+}
+
+__device__ inline double sell_reduce_partials_f(const double *p, int cnt, double *sm)
+{
+    float acc = 0.0f;
+    for (int i = threadIdx.x; i < cnt; i += kBlock) acc += (float)p[i];
+    float s = sell_block_sum_f(acc, sm);
+    if (threadIdx.x == 0) sm[kBlock / 64] = (double)s;
+    __syncthreads();
+    const double r = sm[kBlock / 64];
+    __syncthreads();
+    return r;
+}
+
 // Slice groups (kBlock / 64 slices, one per wave) of an XCD's contiguous
 // range are dealt round-robin to that XCD's blocks: at any moment the blocks
 // of one XCD work on a narrow window of consecutive rows, so the rows that a

@@ -46,11 +46,7 @@ def solver_csr(torch_mod):
     """A context that always takes the CSR-stream kernels (the fallback used
     when the SELL-64 copy would need too much padding)."""
     from paper_2412_08059_amd import Solver
-    os.environ["MPCG_FORCE_CSR"] = "1"
-    try:
-        s = Solver(200_000, 4_000_000, model=TEST_MODEL)
-    finally:
-        del os.environ["MPCG_FORCE_CSR"]
+    s = Solver(200_000, 4_000_000, model=TEST_MODEL, spmv_variant=3)
     yield s
     s.close()
 
@@ -65,11 +61,7 @@ def solver_persist(torch_mod):
     """A context whose 2BFS expands large levels in one persistent launch
     (grid barrier between levels) instead of one launch per level."""
     from paper_2412_08059_amd import Solver
-    os.environ["MPCG_BFS_PERSIST"] = "1"
-    try:
-        s = Solver(2_200_000, 17_500_000, model=TEST_MODEL)
-    finally:
-        del os.environ["MPCG_BFS_PERSIST"]
+    s = Solver(2_200_000, 17_500_000, model=TEST_MODEL, bfs_mode=2)
     yield s
     s.close()
 
@@ -250,11 +242,7 @@ def test_split_product_equals_fused_bitwise(torch_mod, eps1):
     A, B = dev(a), t64(torch_mod, b)
     got = {}
     for split in ("1", "0"):
-        os.environ["MPCG_SELL_SPLIT"] = split
-        try:
-            s = Solver(a.n, a.nnz, model=TEST_MODEL)
-        finally:
-            del os.environ["MPCG_SELL_SPLIT"]
+        s = Solver(a.n, a.nnz, model=TEST_MODEL, spmv_variant=2 if split == "1" else 1)
         st, x, S = s.solve(A, B, eps1, 1e-10)
         s.close()
         assert st == 0
