@@ -185,6 +185,21 @@ mpcg_status mpcg_select_eps1(const mpcg_ctx *ctx, const mpcg_features_t *f, doub
 mpcg_status mpcg_solve(mpcg_ctx *ctx, const mpcg_csr *A, const double *b, double *x, double eps1,
                        double eps2, mpcg_stats *stats);
 
+/* mpcg_solve for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same solve, with
+ * the workspace taken from a device array built into the library (160 MiB on
+ * every GPU the library runs on, held until the process ends) instead of the
+ * context's arena, so it needs no mpcg_set_workspace and calls no hipMalloc,
+ * hipFree or other allocating routine.  Algorithm II (eps1 = MPCG_EPS1_AUTO)
+ * still starts one host thread for its 2BFS, as mpcg_solve does.
+ * Arguments, results and errors are those of mpcg_solve, plus ENOMEM when the
+ * system's workspace (mpcg_workspace_size for its n and nnz) exceeds the
+ * array -- about 4e5 rows of a 7-point stencil fit.  Every call on a GPU
+ * uses that GPU's one array: calls that overlap on one GPU (other contexts,
+ * other threads) race and must be serialised by the caller. */
+mpcg_status mpcg_solve_noalloc(mpcg_ctx *ctx, const mpcg_csr *A, const double *b, double *x, double eps1,
+                               double eps2, mpcg_stats *stats);
+
 /* y = A x with the solver's SpMV kernel (one fma chain per row in CSR order).
  * precision 64: x, y float64; precision 32: x, y float32 and A rounded to
  * float32 (round to nearest even).  For parity tests and bandwidth timing. */

@@ -37,7 +37,8 @@ MPCG_FLAG_KNN_EXACT = 8
 
 EXPORTED = (
     "mpcg_create", "mpcg_destroy", "mpcg_workspace_size", "mpcg_set_workspace", "mpcg_load_model",
-    "mpcg_features", "mpcg_select_eps1", "mpcg_solve", "mpcg_solve_jacobi", "mpcg_spmv", "mpcg_bfs",
+    "mpcg_features", "mpcg_select_eps1", "mpcg_solve", "mpcg_solve_noalloc", "mpcg_solve_jacobi", "mpcg_spmv",
+    "mpcg_bfs",
     "mpcg_diameter_multi",
     "mpcg_last_kernel_ms", "mpcg_time_kernel", "mpcg_strerror",
     "mpcg_batch_workspace_size", "mpcg_batch_set_workspace", "mpcg_batch_submit", "mpcg_batch_poll",
@@ -115,6 +116,7 @@ def _load():
         "mpcg_select_eps1": ([P, ctypes.POINTER(mpcg_features_t), ctypes.POINTER(D),
                               ctypes.POINTER(I32)], I32),
         "mpcg_solve": ([P, ctypes.POINTER(mpcg_csr), P, P, D, D, ctypes.POINTER(mpcg_stats)], I32),
+        "mpcg_solve_noalloc": ([P, ctypes.POINTER(mpcg_csr), P, P, D, D, ctypes.POINTER(mpcg_stats)], I32),
         "mpcg_solve_jacobi": ([P, ctypes.POINTER(mpcg_csr), P, P, D, D, ctypes.POINTER(mpcg_stats)], I32),
         "mpcg_spmv": ([P, ctypes.POINTER(mpcg_csr), I32, P, P], I32),
         "mpcg_bfs": ([P, ctypes.POINTER(mpcg_csr), I64, P, ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
@@ -202,6 +204,13 @@ def mpcg_solve(ctx: int, A: mpcg_csr, b_ptr: int, x_ptr: int, eps1: float, eps2:
     s = mpcg_stats()
     st = lib.mpcg_solve(ctypes.c_void_p(ctx), ctypes.byref(A), ctypes.c_void_p(b_ptr),
                         ctypes.c_void_p(x_ptr), float(eps1), float(eps2), ctypes.byref(s))
+    return st, s
+
+
+def mpcg_solve_noalloc(ctx: int, A: mpcg_csr, b_ptr: int, x_ptr: int, eps1: float, eps2: float):
+    s = mpcg_stats()
+    st = lib.mpcg_solve_noalloc(ctypes.c_void_p(ctx), ctypes.byref(A), ctypes.c_void_p(b_ptr),
+                                ctypes.c_void_p(x_ptr), float(eps1), float(eps2), ctypes.byref(s))
     return st, s
 
 

@@ -10,11 +10,43 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <vector>
 
 using namespace mpcg;
+
+// ---- workspace of mpcg_solve_noalloc: one array per GPU, in the code object.
+// In host code `scratch` only names the symbol; its device address on each GPU
+// comes from hipGetSymbolAddress at context creation (with that device
+// current) and is the only form host code passes on.
+constexpr size_t kNoAllocBytes = (size_t)160 << 20;   // 160 MiB per GPU
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Called by mpcg_create with the context's device current; once per device.
+hipError_t scratch_init(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && ptr) g_scratch_ptr[dev] = ptr;
+    return e == hipSuccess && !ptr ? hipErrorInvalidSymbol : e;
+}
+
+void *scratch_of(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return dev >= 0 && dev < kMaxDevices ? g_scratch_ptr[dev] : nullptr;
+}
+}  // namespace
 
 // A stream plus the pinned snapshots and events used to poll the device state
 // from it.
@@ -625,7 +657,7 @@ mpcg_status mpcg_create(mpcg_ctx **out, const mpcg_options *opt, void *hip_strea
         const int upg = env_int("MPCG_UP_GRID", kUpdateGrid);
         c->up_grid = upg >= 64 && upg <= kMaxGrid ? upg : kUpdateGrid;
     }
-    if (hipGetDevice(&c->device) != hipSuccess ||
+    if (hipGetDevice(&c->device) != hipSuccess || scratch_init(c->device) != hipSuccess ||
         hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
         hipHostMalloc((void **)&c->hst, 6 * sizeof(DevState), hipHostMallocDefault) != hipSuccess ||
         hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking) != hipSuccess) {
@@ -959,6 +991,25 @@ zero_rhs:
     S.status = MPCG_OK;
     if (stats) *stats = S;
     return MPCG_OK;
+}
+
+mpcg_status mpcg_solve_noalloc(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *x, double eps1,
+                               double eps2, mpcg_stats *stats)
+{
+    if (!c || !A || A->n <= 0 || A->n >= 0x7fffffff || A->nnz < 0 || A->nnz >= 0x7fffffff) return MPCG_EINVAL;
+    if (plan_layout(A->n, A->nnz).total > kNoAllocBytes) return MPCG_ENOMEM;
+    void *ptr = scratch_of(c->device);
+    if (!ptr) return MPCG_EDEVICE;
+    // the solve runs on the device array instead of the context's arena; every
+    // region the solve reads before writing is cleared by the solve itself
+    char *const ws = c->ws;
+    const size_t ws_bytes = c->ws_bytes;
+    c->ws = static_cast<char *>(ptr);
+    c->ws_bytes = kNoAllocBytes;
+    const mpcg_status rc = mpcg_solve(c, A, b, x, eps1, eps2, stats);
+    c->ws = ws;
+    c->ws_bytes = ws_bytes;
+    return rc;
 }
 
 mpcg_status mpcg_spmv(mpcg_ctx *c, const mpcg_csr *A, int32_t precision, const void *x, void *y)
