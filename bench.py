@@ -66,10 +66,70 @@ def measured_traffic(kernel: str, workload: str):
         return None
 
 
-def cpu_baseline(a, b, n1, n2, n_dp):
-    """The oracle (scalar C, one thread) on a bounded sample of the same
-    workload, extrapolated to a time-to-1e-10 with the GPU's iteration counts."""
+def sell_format_bytes(kind: str, a) -> float:
+    """HBM bytes the library's SELL-64 copy makes a launch move: every padded
+    entry's value and stored column (16-bit offsets when the band allows,
+    else 32-bit), the row pointers the slices read their lengths from, the
+    slice offsets, and the vectors as in kernel_bytes (perfect gather reuse).
+    Padded entries: 64 x the longest row of each 64-row slice."""
+    import numpy as np
+    s = 8 if kind.endswith("64") else 4
+    n = a.n
+    lens = np.diff(a.row_ptr)
+    pad = np.zeros(((n + 63) // 64) * 64, dtype=np.int64)
+    pad[:n] = lens
+    padded = int(pad.reshape(-1, 64).max(axis=1).sum()) * 64
+    rows = np.repeat(np.arange(n, dtype=np.int64), lens)
+    band = int(np.abs(a.col.astype(np.int64) - rows).max()) if a.nnz else 0
+    cw = 2 if band < 32768 else 4
+    mat = (s + cw) * padded + 4 * (n + 1) + 8 * (n // 64 + 1)
+    if kind.startswith("cg_spmv"):
+        return mat + 6 * s * n
+    if kind.startswith("update"):
+        return 3 * s * n
+    return mat + 2 * s * n
+
+
+def _host_info():
+    info = {"nproc": len(os.sched_getaffinity(0)), "cpu_model": None}
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True,
+                             timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+    except (OSError, ValueError):
+        pass
+    return info
+
+
+def cpu_baseline(a, b, model_path, x_mixed, x_dp, n1, n2, n_dp):
+    """The oracle on the host's cores, two legs:
+    - all cores (its row loops on every thread; the same bits as one thread):
+      Algorithm II with the packaged model (2BFS, v, kNN, FP32 then FP64 CG),
+      timed in full, and FP64-only CG, whose CG-Lanczos coefficients give
+      kappa-hat; their solutions are the reference for the GPU's errors;
+    - one thread on a bounded sample (the 2BFS plus 20- and 40-iteration runs
+      in each precision), extrapolated with the GPU's iteration counts."""
+    import numpy as np
     import oracle
+    host = _host_info()
+    threads = max(1, min(16, host["nproc"]))
+    oracle.set_threads(threads)
+    try:
+        model = oracle.load_model(model_path)
+        t0 = time.perf_counter()
+        r = oracle.solve(a, b, oracle.EPS1_AUTO, 1e-10, model=model)
+        t_mixed = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        kap, lmin, lmax, k_dp, x_or_dp = oracle.lanczos_kappa(a, b, 1e-10, want_x=True)
+        t_dp = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(1)
+    rel = lambda x, y: float(np.linalg.norm(x - y) / np.linalg.norm(y))
+
     t0 = time.perf_counter()
     oracle.pseudo_diameter(a)
     t_feat = time.perf_counter() - t0
@@ -86,18 +146,26 @@ def cpu_baseline(a, b, n1, n2, n_dp):
     t64b = timed(eps1=-1.0, eps2=1e-300, maxit2=2 * k, max_restarts=0)
     it32 = (t32b - t32a) / k
     it64 = (t64b - t64a) / k
-    mixed_ms = (t_feat + n1 * it32 + n2 * it64) * 1e3
+    one_ms = (t_feat + n1 * it32 + n2 * it64) * 1e3
     return {
-        "value": round(mixed_ms, 1),
+        "value": round(t_mixed * 1e3, 1),
         "unit": "ms",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": (f"scalar C oracle, 1 thread: 2BFS on the full matrix ({t_feat * 1e3:.0f} ms) and "
-                   f"{k}/{2 * k}-iteration FP32 and FP64 CG runs on it (per-iteration {it32 * 1e3:.1f} / "
-                   f"{it64 * 1e3:.1f} ms), extrapolated with the GPU run's N1={n1}, N2={n2}; "
-                   f"FP64-only estimate {n_dp * it64 * 1e3:.0f} ms for N_dp={n_dp}"),
-        "fp64_only_ms": round(n_dp * it64 * 1e3, 1),
-        "omega_cpu": round(it32 / it64, 3),
+        "sample": (f"the whole workload: the oracle's Algorithm II solve (class {r.eps1_class}, N1={r.n1}, "
+                   f"N2={r.n2}) with its row loops on {threads} threads; FP64-only CG (N_dp={k_dp}) "
+                   f"{t_dp * 1e3:.0f} ms; one-thread leg: 2BFS ({t_feat * 1e3:.0f} ms) and {k}/{2 * k}-iteration "
+                   f"runs ({it32 * 1e3:.1f} / {it64 * 1e3:.1f} ms per FP32 / FP64 iteration) extrapolated with "
+                   f"the GPU's N1={n1}, N2={n2}"),
+        "fp64_only_ms": round(t_dp * 1e3, 1),
+        "one_thread_ms": round(one_ms, 1),
+        "one_thread_fp64_only_ms": round(n_dp * it64 * 1e3, 1),
+        "omega_cpu_one_thread": round(it32 / it64, 3),
+        "nproc": host["nproc"],
+        "cpu_model": host["cpu_model"],
+        "oracle_counts": {"eps1_class": r.eps1_class, "n1": r.n1, "n2": r.n2, "n_dp": k_dp},
+        "kappa_hat": round(kap, 1),
+        "err_vs_oracle": {"mixed": rel(x_mixed, r.x), "fp64_only": rel(x_dp, x_or_dp)},
     }
 
 
@@ -122,6 +190,66 @@ def _iter_bytes(n, m, n1, n2):
     it = lambda s: kernel_bytes("cg_spmv" + ("64" if s == 8 else "32"), n, m) + kernel_bytes(
         "update" + ("64" if s == 8 else "32"), n, m)
     return n1 * it(4) + n2 * it(8)
+
+
+def bench_c1(args):
+    """The paper's own regime: 2D Poisson 64^2 (n = 4,096), eps1 = 1e-4 and
+    Algorithm II against FP64-only CG on the GPU (mean of repeated solves).
+    At this size a CG iteration is launch- and latency-bound in both
+    precisions."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2412_08059_amd import DEFAULT_MODEL, DeviceCSR, Solver
+    a = W.poisson2d(64)
+    xs, b = W.rhs(a, seed=args.seed)
+    sv = Solver(a.n, a.nnz, model=DEFAULT_MODEL)
+    A, B = DeviceCSR.from_host(a), torch.from_numpy(b).cuda()
+    X = torch.empty(a.n, dtype=torch.float64, device="cuda")
+    out = {}
+    for label, e1 in (("eps1_1e-4", 1e-4), ("auto", 0.0), ("fp64_only", -1.0)):
+        for _ in range(3):
+            sv.solve(A, B, e1, 1e-10, x=X)
+        torch.cuda.synchronize()
+        reps = 20
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st, _, S = sv.solve(A, B, e1, 1e-10, x=X)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        out[label] = {"ms": round(ms, 3), "n1": S.n1, "n2": S.n2, "status": st, "eps1": S.eps1_used,
+                      "err_vs_xstar": float(np.linalg.norm(X.cpu().numpy() - xs) / np.linalg.norm(xs))}
+    sv.close()
+    out["speedup_eps1_1e-4_vs_fp64_only"] = round(out["fp64_only"]["ms"] / out["eps1_1e-4"]["ms"], 3)
+    out["speedup_auto_vs_fp64_only"] = round(out["fp64_only"]["ms"] / out["auto"]["ms"], 3)
+    return out
+
+
+def bench_large_band(args):
+    """Bandwidth outside the 256 MB Infinity Cache: the CG kernels on a band of
+    n = 4e6 rows (half-width 8, the C3a recipe), whose FP64 CG product moves
+    about 1 GB per launch.  HIP events over back-to-back launches on the
+    library stream (mpcg_time_kernel)."""
+    import workloads as W
+    from paper_2412_08059_amd import DeviceCSR, Solver, capi
+    t = time.perf_counter()
+    a = W.banded(args.large_n, 8, seed=args.seed)
+    print(f"# large band n={a.n} nnz={a.nnz} (generated in {time.perf_counter() - t:.1f}s)", file=sys.stderr,
+          flush=True)
+    sv = Solver(a.n, a.nnz)
+    A = DeviceCSR.from_host(a)
+    out = {"n": a.n, "m": a.nnz}
+    for k, kid in (("cg_spmv_f64", capi.MPCG_KERNEL_CG_SPMV_F64), ("cg_spmv_f32", capi.MPCG_KERNEL_CG_SPMV_F32),
+                   ("update_f64", capi.MPCG_KERNEL_UPDATE_F64), ("update_f32", capi.MPCG_KERNEL_UPDATE_F32),
+                   ("spmv_f64", capi.MPCG_KERNEL_SPMV_F64)):
+        ms = capi.mpcg_time_kernel(sv.ctx, A.desc, kid, 20)
+        byt = kernel_bytes(k, a.n, a.nnz)
+        fbyt = sell_format_bytes(k, a)
+        out[k] = {"us": round(ms * 1e3, 2), "bytes": int(byt), "GBs": round(byt / (ms * 1e-3) / 1e9, 1),
+                  "frac": round(byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3), "format_bytes": int(fbyt),
+                  "frac_format": round(fbyt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}
+    sv.close()
+    return out
 
 
 def bench_batch(args):
@@ -450,6 +578,9 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-nmin", type=float, default=1e3)
     ap.add_argument("--batch-nmax", type=float, default=2e5)
+    ap.add_argument("--large-n", type=int, default=4_000_000, help="rows of the >1 GB band case")
+    ap.add_argument("--no-large", action="store_true", help="skip the >1 GB band kernel timings")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 2D Poisson 64^2 (C1) solves")
     ap.add_argument("--serve-count", type=int, default=64)
     ap.add_argument("--serve-nmin", type=float, default=1e4)
     ap.add_argument("--serve-nmax", type=float, default=4e6)
@@ -480,7 +611,7 @@ def main():
     have_model = os.path.exists(model)
     t_gen = time.perf_counter()
     a = W.varcoef3d(args.grid, seed=args.seed)
-    _, b = W.rhs(a, seed=args.seed)
+    xstar, b = W.rhs(a, seed=args.seed)
     t_gen = time.perf_counter() - t_gen
     n, m = a.n, a.nnz
     print(f"# workload varcoef3d {args.grid}^3 n={n} m={m} (generated in {t_gen:.1f}s); "
@@ -503,6 +634,7 @@ def main():
         print(json.dumps({"kernel_only": True, "copy_bytes": 1 << 30, "us_per_launch": kus}))
         return
     X = torch.empty(n, dtype=torch.float64, device="cuda")
+    XD = torch.empty(n, dtype=torch.float64, device="cuda")
     eps1 = capi.MPCG_EPS1_AUTO if have_model else 1e-4
     torch.cuda.synchronize()
 
@@ -510,7 +642,7 @@ def main():
         t0 = time.perf_counter()
         st1, _, sm = solver.solve(A, B, eps1, 1e-10, x=X)
         t1 = time.perf_counter()
-        st2, _, sd = solver.solve(A, B, capi.MPCG_EPS1_NONE, 1e-10, x=X)
+        st2, _, sd = solver.solve(A, B, capi.MPCG_EPS1_NONE, 1e-10, x=XD)
         t2 = time.perf_counter()
         if st1 != 0 or st2 != 0:
             raise RuntimeError(f"solve failed: mixed {st1}, fp64-only {st2}")
@@ -534,6 +666,10 @@ def main():
     ms_per_step = (T1 - T0) * 1e3 / args.steps
     mixed_ms = float(np.mean(mixed))
     dp_ms = float(np.mean(dp))
+    x_mixed = X.cpu().numpy().copy()
+    x_dp = XD.cpu().numpy().copy()
+    rel = lambda x, y: float(np.linalg.norm(x - y) / np.linalg.norm(y))
+    err_xstar = {"mixed": rel(x_mixed, xstar), "fp64_only": rel(x_dp, xstar)}
 
     # per-kernel launch times, HIP events on the library stream
     reps = 30
@@ -546,8 +682,10 @@ def main():
     kernels = {}
     for k, ms in kt.items():
         byt = kernel_bytes(k, n, m)
+        fbyt = sell_format_bytes(k, a)
         kernels[k] = {"us": round(ms * 1e3, 2), "GBs": round(byt / (ms * 1e-3) / 1e9, 1),
-                      "bytes": int(byt)}
+                      "bytes": int(byt), "format_bytes": int(fbyt),
+                      "frac_format": round(fbyt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}
     # dominant kernel of the mixed step = largest launch count x duration
     share = {"cg_spmv_f32": sm.n1 * kt["cg_spmv_f32"], "update_f32": sm.n1 * kt["update_f32"],
              "cg_spmv_f64": sm.n2 * kt["cg_spmv_f64"], "update_f64": sm.n2 * kt["update_f64"]}
@@ -557,7 +695,10 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dom_gbs / HBM_PEAK_GBS, 3),
                 "traffic": None if traffic is None else int(traffic),
-                "bytes_per_launch": kernels[dom]["bytes"], "us_per_launch": kernels[dom]["us"]}
+                "bytes_per_launch": kernels[dom]["bytes"], "us_per_launch": kernels[dom]["us"],
+                "format_bytes_per_launch": kernels[dom]["format_bytes"],
+                "frac_format": kernels[dom]["frac_format"],
+                "working_set_under_256MB_infinity_cache": kernels[dom]["format_bytes"] < 256e6}
 
     sweep = None
     if not args.no_sweep:
@@ -591,9 +732,17 @@ def main():
                "speedup_vs_fp64_only": round(jr["fp64_only"]["ms"] / jr["mixed"]["ms"], 3), "runs": jr}
         print(f"# jacobi: {jac}", file=sys.stderr, flush=True)
 
+    c1 = None if args.no_c1 else bench_c1(args)
+    if c1 is not None:
+        print(f"# C1 Poisson 64^2: {json.dumps(c1)}", file=sys.stderr, flush=True)
+    large = None if args.no_large else bench_large_band(args)
+    if large is not None:
+        print(f"# large band: {json.dumps(large)}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(a, b, sm.n1, sm.n2, sd.n2)
+        cpu = cpu_baseline(a, b, model, x_mixed, x_dp, sm.n1, sm.n2, sd.n2)
+        print(f"# cpu baseline: {json.dumps(cpu)}", file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC,
@@ -621,8 +770,14 @@ def main():
         "equiv_fp64_iters_per_s": round(sd.n2 / (mixed_ms * 1e-3), 1),
         "relres_final_true": sm.relres_final_true,
         "spmv_f64_GBs": kernels["spmv_f64"]["GBs"],
-        "spmv_frac_hbm": round(kernels["cg_spmv_f64"]["GBs"] / HBM_PEAK_GBS, 3),
+        "spmv_frac_hbm": round(kernels["spmv_f64"]["GBs"] / HBM_PEAK_GBS, 3),
+        "cg_spmv_f64_frac_hbm": round(kernels["cg_spmv_f64"]["GBs"] / HBM_PEAK_GBS, 3),
+        "err_vs_xstar": err_xstar,
+        "err_vs_oracle": None if cpu is None else cpu["err_vs_oracle"],
+        "kappa_hat": None if cpu is None else cpu["kappa_hat"],
         "kernels": kernels,
+        "c1_poisson2d_64": c1,
+        "large_band": large,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "eps1_sweep": sweep,

@@ -108,7 +108,7 @@ def _L():
         lib.or_cg64_directions.argtypes = [I64, P, P, P, P, I64, P]
         lib.or_cg64_directions.restype = I64
         lib.or_cg_true_residuals.argtypes = [ctypes.c_int32, I64, P, P, P, P, I64, P]
-        lib.or_cg_lanczos.argtypes = [I64, P, P, P, P, ctypes.c_double, I64, P, P]
+        lib.or_cg_lanczos.argtypes = [I64, P, P, P, P, ctypes.c_double, I64, P, P, P]
         lib.or_cg_lanczos.restype = I64
         lib.or_set_threads.argtypes = [ctypes.c_int32]
         lib.or_get_threads.restype = ctypes.c_int32
@@ -297,23 +297,28 @@ def get_threads() -> int:
     return int(_L().or_get_threads())
 
 
-def lanczos_kappa(a, b, eps: float = 1e-10, maxit: int = 0):
+def lanczos_kappa(a, b, eps: float = 1e-10, maxit: int = 0, want_x: bool = False):
     """kappa-hat = lambda_max / lambda_min of the CG-Lanczos tridiagonal T_k
     of plain FP64 CG on (A, b) from 0, run to ||r|| <= eps ||b|| (maxit <= 0:
-    10 n).  Returns (kappa_hat, lambda_min, lambda_max, k).  The extreme
-    eigenvalues of T_k come from scipy's symmetric tridiagonal solver."""
+    10 n).  Returns (kappa_hat, lambda_min, lambda_max, k), and the CG iterate
+    as a fifth item when want_x.  The extreme eigenvalues of T_k come from
+    scipy's symmetric tridiagonal solver."""
     rp, col, val = _csr_arrays(a)
     b = np.ascontiguousarray(b, dtype=np.float64)
     m = int(maxit) if maxit > 0 else 10 * a.n
     al = np.zeros(m, dtype=np.float64)
     be = np.zeros(m, dtype=np.float64)
-    k = int(_L().or_cg_lanczos(a.n, _p(rp), _p(col), _p(val), _p(b), float(eps), m, _p(al), _p(be)))
+    x = np.zeros(a.n, dtype=np.float64) if want_x else None
+    k = int(_L().or_cg_lanczos(a.n, _p(rp), _p(col), _p(val), _p(b), float(eps), m, _p(al), _p(be),
+                               None if x is None else _p(x)))
     if k == 0:
-        return float("nan"), float("nan"), float("nan"), 0
+        out = (float("nan"), float("nan"), float("nan"), 0)
+        return out + (x,) if want_x else out
     al, be = al[:k], be[:k]
     diag = 1.0 / al
     diag[1:] += be[:-1] / al[:-1]
     off = np.sqrt(be[:-1]) / al[:-1]
     from scipy.linalg import eigvalsh_tridiagonal
     lam = eigvalsh_tridiagonal(diag, off)
-    return float(lam[-1] / lam[0]), float(lam[0]), float(lam[-1]), k
+    out = (float(lam[-1] / lam[0]), float(lam[0]), float(lam[-1]), k)
+    return out + (x,) if want_x else out

@@ -911,9 +911,12 @@ void or_cg_true_residuals(int32_t prec, int64_t n, const int64_t *rp, const int3
  * off-diagonal sqrt(beta_j)/alpha_j (Saad, "Iterative Methods for Sparse
  * Linear Systems", the CG-Lanczos connection), whose extreme eigenvalues
  * approach those of A.  Runs until ||r|| <= eps ||b|| or maxit iterations;
- * returns the number k of (alpha, beta) pairs written. */
+ * returns the number k of (alpha, beta) pairs written.  x_out (may be NULL)
+ * gets the final iterate: the arithmetic is that of FP64-only CG in or_solve
+ * up to its stop, before any final check. */
 int64_t or_cg_lanczos(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
-                      const double *b, double eps, int64_t maxit, double *alpha_out, double *beta_out)
+                      const double *b, double eps, int64_t maxit, double *alpha_out, double *beta_out,
+                      double *x_out)
 {
     double *x = (double *)calloc((size_t)n, sizeof(double));
     double *r = (double *)malloc(sizeof(double) * (size_t)n);
@@ -942,6 +945,7 @@ int64_t or_cg_lanczos(int64_t n, const int64_t *rp, const int32_t *col, const do
         gamma = gnew;
         ++k;
     }
+    if (x_out) memcpy(x_out, x, sizeof(double) * (size_t)n);
     free(x); free(r); free(d); free(q);
     return k;
 }

@@ -173,3 +173,15 @@ def test_threaded_row_loops_give_the_same_bits(eps1):
         oracle.set_threads(1)
     assert (r1.n1, r1.n2, r1.relres_final_true) == (r4.n1, r4.n2, r4.relres_final_true)
     assert np.array_equal(r1.x, r4.x)
+
+
+def test_lanczos_iterate_is_the_fp64_only_cg_iterate():
+    """The CG run behind kappa-hat is FP64-only CG from 0: its iterate is the
+    oracle solve's, bit for bit, when the final check passes at once."""
+    a = W.varcoef3d(16, seed=2)
+    _, b = W.rhs(a, seed=2)
+    kap, lmin, lmax, k, x = oracle.lanczos_kappa(a, b, 1e-10, want_x=True)
+    r = oracle.solve(a, b, oracle.EPS1_NONE, 1e-10)
+    assert r.status == oracle.OK and r.restarts == 0 and r.n2 == k
+    assert np.array_equal(r.x, x)
+    assert lmin > 0 and kap == lmax / lmin
