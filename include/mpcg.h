@@ -266,6 +266,49 @@ typedef struct {
 mpcg_status mpcg_diameter_multi(mpcg_ctx *ctx, const mpcg_csr *A, const int32_t *starts, int32_t count,
                                 double q, mpcg_diam_t *out);
 
+/* Scheduling parameters of the products and the 2BFS (the autotuner's
+ * knobs).  None changes a result: each picks how a product issues its loads
+ * or how many blocks expand a 2BFS level, never what is summed in which
+ * order (the block partitions that fix the reduction order are constants of
+ * the library).  Sources, in order: mpcg_set_tuning's values for every
+ * matrix; else the entry of the table loaded with mpcg_load_tuning for the
+ * matrix's class (GPU architecture and compute units, 16- or 32-bit SELL
+ * column offsets, round(log2(nnz / n)), nearest floor(log2(n))); else the
+ * built-in defaults.  mpcg_options.spmv_variant 1-3 and bfs_mode 1-2 override
+ * sell_split, the SELL/CSR choice and bfs_persist. */
+typedef struct {
+    int32_t sell_batch;          /* SELL-64 entries of a row whose loads are issued together: 4 or 8 */
+    int32_t sell_whole_batch;    /* bit 0 FP32, bit 1 FP64 products: every lane loads its whole batch
+                                    (slice padding included) instead of guarding each entry */
+    int32_t sell_split;          /* CG product in two launches: 0 no, 1 yes, -1 for 32-bit columns */
+    int32_t bfs_grid;            /* blocks of the 2BFS level kernel, 1..4096 */
+    int32_t bfs_grid_shared;     /* the same beside Algorithm II's FP32 phase, 1..4096 */
+    int32_t bfs_persist;         /* 1: large 2BFS levels in one persistent launch */
+    int32_t batch_group_steps;   /* batch engine: steps enqueued per group, 1..64 */
+    int32_t batch_bfs_rounds;    /* 2BFS rounds per pass of its BFS stream, 1..64 */
+    int32_t batch_small_cap;     /* largest frontier one block per system expands, 1..2048 */
+    int32_t batch_small_levels;  /* levels one such launch may expand, 1..4096 */
+    int32_t batch_level_grid;    /* blocks of the multi-block level kernel, 1..65536 */
+    int32_t pad_;
+} mpcg_tuning;
+
+/* Use *t for every matrix from now on (NULL: back to the table and the
+ * defaults).  EINVAL for a value out of range.  The batch engine takes its
+ * fields when mpcg_batch_set_workspace starts it. */
+mpcg_status mpcg_set_tuning(mpcg_ctx *ctx, const mpcg_tuning *t);
+
+/* Load a tuning table (host path; text, header "mpcg-tune 1", then lines
+ * "solve <arch> <cu> <idx16> <lenlog> <nlog> <sell_batch> <sell_whole_batch>
+ * <sell_split> <bfs_grid> <bfs_grid_shared> <bfs_persist>" and at most one
+ * "batch <arch> <cu> <group_steps> <bfs_rounds> <small_cap> <small_levels>
+ * <level_grid>").  EINVAL for a missing or malformed file (the previous
+ * table is kept). */
+mpcg_status mpcg_load_tuning(mpcg_ctx *ctx, const char *path);
+
+/* The parameters a solve would use for a matrix of n rows, nnz entries and
+ * largest |i - j| = band (HOST output). */
+mpcg_status mpcg_get_tuning(const mpcg_ctx *ctx, int64_t n, int64_t nnz, int64_t band, mpcg_tuning *out);
+
 /* Time of the most recent mpcg_spmv kernel launch in milliseconds (HIP events
  * on the context stream), 0 if none. */
 mpcg_status mpcg_last_kernel_ms(const mpcg_ctx *ctx, double *ms);
@@ -308,16 +351,10 @@ const char *mpcg_strerror(mpcg_status s);
  * next step.  A host thread owned by the context drives the steps on a
  * stream of its own; mpcg_batch_poll returns finished solves without blocking.
  *
- * Scheduling knobs, read from the environment when the engine starts
- * (mpcg_batch_set_workspace); none changes any result, only when work runs:
- *   MPCG_BATCH_GROUP_STEPS  steps enqueued per group (1..64, default 8)
- *   MPCG_BATCH_BFS_ROUNDS   2BFS rounds per pass of the BFS stream (1..64, 4)
- *   MPCG_BATCH_SMALL_CAP    largest frontier expanded by one block per system
- *                           (1..2048, 512); larger ones by the multi-block kernel
- *   MPCG_BATCH_SMALL_LEVELS levels one such launch may expand (1..4096, 64)
- *   MPCG_BATCH_SMALL_WORK   frontier x lane slots after which it stops (unbounded)
- *   MPCG_BATCH_LEVEL_GRID   blocks of the multi-block level kernel (1..65536, 1024)
- * Values outside the ranges are ignored.
+ * Its scheduling knobs (steps per group, 2BFS rounds, the one-block 2BFS
+ * kernel's frontier and level caps, the level kernel's grid) are the batch_*
+ * fields of mpcg_tuning, taken when the engine starts; none changes any
+ * result, only when work runs.
  * -------------------------------------------------------------------------*/
 
 /* One solve.  A, b and x are DEVICE memory owned by the caller and borrowed

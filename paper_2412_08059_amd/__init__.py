@@ -21,6 +21,16 @@ from .capi import (  # noqa: F401
 )
 
 DEFAULT_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "knn_model.txt")
+# the autotuner's frozen table (paper_2412_08059_amd/autotune.py writes it)
+DEFAULT_TUNING = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.txt")
+
+
+def _load_tuning(ctx, tuning):
+    path = DEFAULT_TUNING if tuning == "default" else tuning
+    if path and os.path.exists(path):
+        st = capi.mpcg_load_tuning(ctx, path)
+        if st != MPCG_OK:
+            raise MpcgError(st, f"mpcg_load_tuning({path})")
 
 
 class DeviceCSR:
@@ -50,16 +60,19 @@ class Solver:
     def __init__(self, n_max: int, nnz_max: int, *, k0: int = 20, knn_k: int = 0, tol_mode: int = 0,
                  max_restarts: int = 5, graph_iters: int = 0, maxit1: int = 0, maxit2: int = 0,
                  model: str | None = None, precond: int = 0, dot_acc: int = 0, spmv_variant: int = 0,
-                 bfs_mode: int = 0, device="cuda"):
+                 bfs_mode: int = 0, tuning: str | dict | None = "default", device="cuda"):
         """precond = 1: Jacobi-preconditioned stages (M = diag(A)); dot_acc = 1:
         FP32-accumulated FP32-phase dot products; spmv_variant / bfs_mode: see
-        mpcg_options in include/mpcg.h."""
+        mpcg_options in include/mpcg.h.  tuning: "default" (the packaged
+        table, if present), a table path, a dict of mpcg_tuning fields used
+        for every matrix, or None (built-in defaults)."""
         import torch
         self.device = torch.device(device)
         self.stream = torch.cuda.current_stream(self.device)
         opt = mpcg_options(k0, knn_k, tol_mode, max_restarts, graph_iters, precond, maxit1, maxit2, dot_acc,
                            spmv_variant, bfs_mode, 0)
         self.ctx = capi.mpcg_create(opt, self.stream.cuda_stream)
+        self.set_tuning(tuning)
         nbytes = capi.mpcg_workspace_size(self.ctx, max(1, n_max), max(0, nnz_max))
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         st = capi.mpcg_set_workspace(self.ctx, self.workspace.data_ptr(), nbytes)
@@ -69,6 +82,23 @@ class Solver:
             st = capi.mpcg_load_model(self.ctx, model)
             if st != MPCG_OK:
                 raise MpcgError(st, f"mpcg_load_model({model})")
+
+    def set_tuning(self, tuning):
+        """A table path ("default": the packaged one), a dict of mpcg_tuning
+        fields for every matrix, or None (clears explicit values)."""
+        if isinstance(tuning, dict):
+            st = capi.mpcg_set_tuning(self.ctx, tuning)
+            if st != MPCG_OK:
+                raise MpcgError(st, "mpcg_set_tuning")
+        else:
+            capi.mpcg_set_tuning(self.ctx, None)
+            _load_tuning(self.ctx, tuning)
+
+    def tuning_for(self, n: int, nnz: int, band: int) -> dict:
+        st, t = capi.mpcg_get_tuning(self.ctx, n, nnz, band)
+        if st != MPCG_OK:
+            raise MpcgError(st, "mpcg_get_tuning")
+        return t.as_dict()
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -127,11 +157,19 @@ class BatchSolver:
 
     def __init__(self, max_rows: int, max_entries: int, max_systems: int, *, k0: int = 20, knn_k: int = 0,
                  tol_mode: int = 0, max_restarts: int = 5, maxit1: int = 0, maxit2: int = 0,
-                 model: str | None = DEFAULT_MODEL, dot_acc: int = 0, device="cuda"):
+                 model: str | None = DEFAULT_MODEL, dot_acc: int = 0, tuning: str | dict | None = "default",
+                 device="cuda"):
+        """tuning: as for Solver; its batch_* fields set the engine's schedule."""
         import torch
         self.device = torch.device(device)
         opt = mpcg_options(k0, knn_k, tol_mode, max_restarts, 0, 0, maxit1, maxit2, dot_acc)
         self.ctx = capi.mpcg_create(opt, torch.cuda.current_stream(self.device).cuda_stream)
+        if isinstance(tuning, dict):
+            st = capi.mpcg_set_tuning(self.ctx, tuning)
+            if st != MPCG_OK:
+                raise MpcgError(st, "mpcg_set_tuning")
+        else:
+            _load_tuning(self.ctx, tuning)
         if model:
             st = capi.mpcg_load_model(self.ctx, model)
             if st != MPCG_OK:

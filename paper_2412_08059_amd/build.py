@@ -24,7 +24,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 
 HIP_SOURCES = ["kernels_cg.hip", "kernels_sell.hip", "kernels_bfs.hip", "kernels_jacobi.hip", "kernels_batch.hip",
                "batch_engine.hip", "capi.hip"]
-HOST_SOURCES = ["knn.cpp"]
+HOST_SOURCES = ["knn.cpp", "tune.cpp"]
 
 
 def _hipcc() -> str:

@@ -40,6 +40,7 @@ EXPORTED = (
     "mpcg_features", "mpcg_select_eps1", "mpcg_solve", "mpcg_solve_noalloc", "mpcg_solve_jacobi", "mpcg_spmv",
     "mpcg_bfs",
     "mpcg_diameter_multi",
+    "mpcg_set_tuning", "mpcg_load_tuning", "mpcg_get_tuning",
     "mpcg_last_kernel_ms", "mpcg_time_kernel", "mpcg_strerror",
     "mpcg_batch_workspace_size", "mpcg_batch_set_workspace", "mpcg_batch_submit", "mpcg_batch_poll",
     "mpcg_batch_cancel", "mpcg_batch_load",
@@ -91,6 +92,18 @@ class mpcg_options(ctypes.Structure):
                 ("pad_", ctypes.c_int32)]
 
 
+class mpcg_tuning(ctypes.Structure):
+    _fields_ = [("sell_batch", ctypes.c_int32), ("sell_whole_batch", ctypes.c_int32),
+                ("sell_split", ctypes.c_int32), ("bfs_grid", ctypes.c_int32), ("bfs_grid_shared", ctypes.c_int32),
+                ("bfs_persist", ctypes.c_int32), ("batch_group_steps", ctypes.c_int32),
+                ("batch_bfs_rounds", ctypes.c_int32), ("batch_small_cap", ctypes.c_int32),
+                ("batch_small_levels", ctypes.c_int32), ("batch_level_grid", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
+
+
 class mpcg_request(ctypes.Structure):
     _fields_ = [("A", mpcg_csr), ("b", ctypes.c_void_p), ("x", ctypes.c_void_p), ("eps1", ctypes.c_double),
                 ("eps2", ctypes.c_double), ("user", ctypes.c_void_p)]
@@ -122,6 +135,9 @@ def _load():
         "mpcg_bfs": ([P, ctypes.POINTER(mpcg_csr), I64, P, ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
         "mpcg_diameter_multi": ([P, ctypes.POINTER(mpcg_csr), ctypes.POINTER(I32), I32, D,
                                  ctypes.POINTER(mpcg_diam_t)], I32),
+        "mpcg_set_tuning": ([P, ctypes.POINTER(mpcg_tuning)], I32),
+        "mpcg_load_tuning": ([P, ctypes.c_char_p], I32),
+        "mpcg_get_tuning": ([P, I64, I64, I64, ctypes.POINTER(mpcg_tuning)], I32),
         "mpcg_last_kernel_ms": ([P, ctypes.POINTER(D)], I32),
         "mpcg_time_kernel": ([P, ctypes.POINTER(mpcg_csr), I32, I32, ctypes.POINTER(D)], I32),
         "mpcg_strerror": ([I32], ctypes.c_char_p),
@@ -212,6 +228,29 @@ def mpcg_solve_noalloc(ctx: int, A: mpcg_csr, b_ptr: int, x_ptr: int, eps1: floa
     st = lib.mpcg_solve_noalloc(ctypes.c_void_p(ctx), ctypes.byref(A), ctypes.c_void_p(b_ptr),
                                 ctypes.c_void_p(x_ptr), float(eps1), float(eps2), ctypes.byref(s))
     return st, s
+
+
+def mpcg_set_tuning(ctx: int, t) -> int:
+    """t: an mpcg_tuning, a dict of its fields (the rest from the defaults
+    mpcg_get_tuning reports for an empty context), or None to clear."""
+    if t is None:
+        return lib.mpcg_set_tuning(ctypes.c_void_p(ctx), None)
+    if isinstance(t, dict):
+        st, base = mpcg_get_tuning(ctx, 1, 1, 0)
+        for k, v in t.items():
+            setattr(base, k, int(v))
+        t = base
+    return lib.mpcg_set_tuning(ctypes.c_void_p(ctx), ctypes.byref(t))
+
+
+def mpcg_load_tuning(ctx: int, path: str) -> int:
+    return lib.mpcg_load_tuning(ctypes.c_void_p(ctx), path.encode())
+
+
+def mpcg_get_tuning(ctx: int, n: int, nnz: int, band: int):
+    t = mpcg_tuning()
+    st = lib.mpcg_get_tuning(ctypes.c_void_p(ctx), int(n), int(nnz), int(band), ctypes.byref(t))
+    return st, t
 
 
 def mpcg_spmv(ctx: int, A: mpcg_csr, precision: int, x_ptr: int, y_ptr: int) -> int:

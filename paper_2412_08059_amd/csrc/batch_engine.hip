@@ -139,12 +139,13 @@ struct Engine {
     RangeAlloc slices, entries;
     int32_t hi_sys = 0, hi_slice = 0;
     int64_t group = 0;
-    int small_levels = kSmallBfsLevels;   // MPCG_BATCH_SMALL_LEVELS
-    int small_cap = kSmallBfsCapDefault;  // MPCG_BATCH_SMALL_CAP
-    int64_t small_work = INT64_MAX;       // MPCG_BATCH_SMALL_WORK
-    int bfs_rounds = kBfsRoundsPerPump;   // MPCG_BATCH_BFS_ROUNDS
-    int level_grid = 1024;                // MPCG_BATCH_LEVEL_GRID
-    int group_steps = kGroupSteps;        // MPCG_BATCH_GROUP_STEPS
+    // scheduling knobs: mpcg_tuning's batch_* fields
+    int small_levels = kSmallBfsLevels;
+    int small_cap = kSmallBfsCapDefault;
+    int64_t small_work = INT64_MAX;   // frontier x lane slots after which a one-block launch stops: no limit
+    int bfs_rounds = kBfsRoundsPerPump;
+    int level_grid = 1024;
+    int group_steps = kGroupSteps;
 
     std::mutex mu;
     std::condition_variable cv;
@@ -576,7 +577,8 @@ void Engine::run()
 
 // ------------------------------------------------------------ interface --
 
-Engine *engine_create(int device, const mpcg_options &opt, const KnnModel *model, void *arena, size_t bytes,
+Engine *engine_create(int device, const mpcg_options &opt, const mpcg_tuning &tune, const KnnModel *model,
+                      void *arena, size_t bytes,
                       int64_t max_rows, int64_t max_entries, int32_t max_sys, int *status)
 {
     const int64_t max_slices = (max_rows + 63) / 64;
@@ -596,26 +598,11 @@ Engine *engine_create(int device, const mpcg_options &opt, const KnnModel *model
     }
     e->device = device;
     e->opt = opt;
-    {
-        const char *r = std::getenv("MPCG_BATCH_SMALL_LEVELS");
-        const int v = (r && r[0]) ? std::atoi(r) : 0;
-        if (v >= 1 && v <= 4096) e->small_levels = v;
-        const char *c = std::getenv("MPCG_BATCH_SMALL_CAP");
-        const int vc = (c && c[0]) ? std::atoi(c) : 0;
-        if (vc >= 1 && vc <= kSmallBfsCap) e->small_cap = vc;
-        const char *w = std::getenv("MPCG_BATCH_SMALL_WORK");
-        const long long vw = (w && w[0]) ? std::atoll(w) : 0;
-        if (vw >= 1) e->small_work = vw;
-        const char *br = std::getenv("MPCG_BATCH_BFS_ROUNDS");
-        const int vr = (br && br[0]) ? std::atoi(br) : 0;
-        if (vr >= 1 && vr <= 64) e->bfs_rounds = vr;
-        const char *lg = std::getenv("MPCG_BATCH_LEVEL_GRID");
-        const int vl = (lg && lg[0]) ? std::atoi(lg) : 0;
-        if (vl >= 1 && vl <= 65536) e->level_grid = vl;
-        const char *gs = std::getenv("MPCG_BATCH_GROUP_STEPS");
-        const int vs = (gs && gs[0]) ? std::atoi(gs) : 0;
-        if (vs >= 1 && vs <= 64) e->group_steps = vs;
-    }
+    e->small_levels = tune.batch_small_levels;
+    e->small_cap = tune.batch_small_cap;
+    e->bfs_rounds = tune.batch_bfs_rounds;
+    e->level_grid = tune.batch_level_grid;
+    e->group_steps = tune.batch_group_steps;
     e->model = model;
     e->a = carve(arena, max_sys, (int32_t)max_slices, max_entries);
     e->a.acc32 = opt.dot_acc;

@@ -161,7 +161,8 @@ void launch_bfs_finish(hipStream_t s, const BArena &a, int32_t sys, int32_t n); 
 
 // ---- host engine (batch_engine.hip) ----
 struct Engine;
-Engine *engine_create(int device, const mpcg_options &opt, const KnnModel *model, void *arena, size_t bytes,
+Engine *engine_create(int device, const mpcg_options &opt, const mpcg_tuning &tune, const KnnModel *model,
+                      void *arena, size_t bytes,
                       int64_t max_rows, int64_t max_entries, int32_t max_sys, int *status);
 void engine_destroy(Engine *e);
 int engine_submit(Engine *e, const mpcg_request *reqs, int32_t count, uint64_t *ids);

@@ -5,6 +5,7 @@
 
 #include "batch_internal.hpp"
 #include "mpcg_internal.hpp"
+#include "tune.hpp"
 
 #include <atomic>
 #include <cmath>
@@ -12,6 +13,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -73,22 +75,11 @@ struct mpcg_ctx {
     bool has_model = false;
     float last_kernel_ms = 0.0f;
     bool force_csr = false;   // spmv_variant 3: always use the CSR-stream kernels
-    int sell_batch = 4;       // MPCG_SELL_BATCH=4|8: loads in flight per row in the SELL kernels
-    int sell_bf = 1;          // MPCG_SELL_BF=0..3: whole-batch loads (bit 0: FP32 kernels, bit 1: FP64)
-    int sell_split = -1;      // spmv_variant 1|2: fused|two-launch CG product (-1: two launches for 32-bit columns)
-    int cg_grid = kMaxGrid;   // MPCG_CG_GRID: most blocks of a CG product launch
-    int up_grid = kUpdateGrid;   // MPCG_UP_GRID: most blocks of a CG update launch
     mpcg::batch::Engine *eng = nullptr;   // batched engine (own thread and stream), if started
-    int bfs_grid = kBfsLevelBlocks;   // MPCG_BFS_GRID: blocks of the BFS level kernel
-    int bfs_precheck = 0;             // MPCG_BFS_PRECHECK=1: read the distance before claiming a vertex
-    int bfs_persist = 0;              // bfs_mode 2: large levels in one persistent launch
-    // Algorithm II runs the 2BFS beside the FP32 iterations.  A SELL product
-    // grid of 8 blocks per CU fills every wave slot, so each resident BFS
-    // block would push one product block to the end of the launch (the slice
-    // partition is static): while the BFS runs, the FP32 product takes one
-    // block per CU fewer and the BFS a small grid that fits the freed slots.
-    int cg_grid_shared = 0;           // MPCG_CG_GRID_SHARED: 0 = 7 blocks per CU
-    int bfs_grid_shared = 64;         // MPCG_BFS_GRID_SHARED
+    std::string arch;         // GPU architecture name (e.g. gfx950), the tuning table's key
+    mpcg::TuneTable table;    // mpcg_load_tuning
+    bool has_explicit = false;
+    mpcg_tuning explicit_t{}; // mpcg_set_tuning
 };
 
 #define HIPCHK(x)                                        \
@@ -192,9 +183,23 @@ struct Plan {
     SellMat sell{};
     bool use_sell = false;
     int nup = 1;
+    mpcg_tuning tune{};   // scheduling parameters resolved for this matrix
     char *ws = nullptr;
     template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
 };
+
+// Scheduling parameters for a matrix: mpcg_set_tuning's, else the table's
+// entry for its class, else the defaults; the options' explicit product and
+// 2BFS variants override them.
+mpcg_tuning resolve_tuning(const mpcg_ctx *c, int64_t n, int64_t nnz, int64_t band)
+{
+    mpcg_tuning t = c->has_explicit ? c->explicit_t : tune_lookup(c->table, c->arch, c->num_cu, n, nnz, band);
+    if (c->opt.spmv_variant == 1) t.sell_split = 0;
+    if (c->opt.spmv_variant == 2) t.sell_split = 1;
+    if (c->opt.bfs_mode == 1) t.bfs_persist = 0;
+    if (c->opt.bfs_mode == 2) t.bfs_persist = 1;
+    return t;
+}
 
 mpcg_status read_state(const Chan &ch, const Plan &p, DevState *out)
 {
@@ -256,7 +261,8 @@ mpcg_status ingest(mpcg_ctx *c, const mpcg_csr *A, const double *b, bool need_va
     p->sh64 = spmv_shape(A->n, A->nnz, 8, c->num_cu);
     p->sh32 = spmv_shape(A->n, A->nnz, 4, c->num_cu);
     p->nup = vec_grid(A->n);
-    if (p->nup > c->up_grid) p->nup = c->up_grid;
+    if (p->nup > kUpdateGrid) p->nup = kUpdateGrid;
+    p->tune = resolve_tuning(c, A->n, A->nnz, s.max_band);
     if (p->use_sell) {
         SellMat &m = p->sell;
         m.rp = p->rp;
@@ -264,12 +270,12 @@ mpcg_status ingest(mpcg_ctx *c, const mpcg_csr *A, const double *b, bool need_va
         m.n = p->n;
         m.nslices = nsl;
         m.idx16 = s.max_band < 32768 ? 1 : 0;
-        m.batch = c->sell_batch;
-        m.bf_mask = c->sell_bf;
+        m.batch = p->tune.sell_batch;
+        m.bf_mask = p->tune.sell_whole_batch;
         // scattered gathers (columns beyond 16-bit offsets): one gathered vector, not two
-        m.split = c->sell_split >= 0 ? c->sell_split : (m.idx16 ? 0 : 1);
+        m.split = p->tune.sell_split >= 0 ? p->tune.sell_split : (m.idx16 ? 0 : 1);
         int64_t g = ((int64_t)nsl + kBlock / 64 - 1) / (kBlock / 64);
-        if (g > c->cg_grid) g = c->cg_grid;
+        if (g > kMaxGrid) g = kMaxGrid;
         m.grid = (int32_t)(g < 1 ? 1 : g);
         m.scol = p->ws + p->L.sell_col;
         m.v64 = p->at<double>(p->L.sell_v64);
@@ -430,18 +436,13 @@ mpcg_status jacobi_stage(mpcg_ctx *c, const Plan &p, const T *b, const T *dg, T 
     return read_state(ch, p, out);
 }
 
-int env_int(const char *name, int def)
-{
-    const char *e = std::getenv(name);
-    return (e && e[0]) ? std::atoi(e) : def;
-}
 
-BfsBufs bfs_bufs(const mpcg_ctx *c, const Plan &p, bool shared = false)
+BfsBufs bfs_bufs(const Plan &p, bool shared = false)
 {
     BfsBufs b{};
-    b.persist = c->bfs_persist;
-    b.grid = shared ? c->bfs_grid_shared : c->bfs_grid;
-    b.precheck = c->bfs_precheck;
+    b.persist = p.tune.bfs_persist;
+    b.grid = shared ? p.tune.bfs_grid_shared : p.tune.bfs_grid;
+    b.precheck = 0;
     b.rp = p.rp;
     b.col = p.col;
     b.n = p.n;
@@ -539,7 +540,7 @@ mpcg_status pseudo_diameter_with(const Chan &ch, const Plan &p, const BfsBufs &b
 mpcg_status pseudo_diameter(const mpcg_ctx *c, const Chan &ch, const Plan &p, mpcg_features_t *f,
                             bool shared = false)
 {
-    BfsBufs bb = bfs_bufs(c, p, shared);
+    BfsBufs bb = bfs_bufs(p, shared);
     mpcg_status rc = pseudo_diameter_with(ch, p, bb, f);
     if (rc == MPCG_EDEVICE && bb.persist) {
         HIPCHK(hipStreamSynchronize(ch.s));
@@ -559,7 +560,7 @@ Plan shared_plan(const mpcg_ctx *c, const Plan &p)
 {
     Plan q = p;
     if (p.use_sell && p.sell.grid >= 8 * c->num_cu) {
-        const int g = c->cg_grid_shared > 0 ? c->cg_grid_shared : 7 * c->num_cu;
+        const int g = 7 * c->num_cu;
         if (g < q.sell.grid) q.sell.grid = g;
     }
     return q;
@@ -637,32 +638,19 @@ mpcg_status mpcg_create(mpcg_ctx **out, const mpcg_options *opt, void *hip_strea
     if (!c) return MPCG_EDEVICE;
     c->opt = o;
     c->stream = static_cast<hipStream_t>(hip_stream);
-    {
-        c->force_csr = o.spmv_variant == 3;
-        const char *bt = std::getenv("MPCG_SELL_BATCH");
-        if (bt && bt[0] == '8') c->sell_batch = 8;
-        const int sbf = env_int("MPCG_SELL_BF", 1);
-        c->sell_bf = sbf >= 0 && sbf <= 3 ? sbf : 1;
-        c->sell_split = o.spmv_variant == 1 ? 0 : (o.spmv_variant == 2 ? 1 : -1);
-        const int cgg = env_int("MPCG_CG_GRID", kMaxGrid);
-        c->cg_grid = cgg >= 64 && cgg <= kMaxGrid ? cgg : kMaxGrid;
-        const int bg = env_int("MPCG_BFS_GRID", kBfsLevelBlocks);
-        c->bfs_grid = bg > 0 && bg <= 4096 ? bg : kBfsLevelBlocks;
-        c->bfs_precheck = env_int("MPCG_BFS_PRECHECK", 0) ? 1 : 0;
-        c->bfs_persist = o.bfs_mode == 2 ? 1 : 0;
-        const int cgs = env_int("MPCG_CG_GRID_SHARED", 0);
-        c->cg_grid_shared = cgs >= 64 && cgs <= kMaxGrid ? cgs : 0;
-        const int bgs = env_int("MPCG_BFS_GRID_SHARED", 64);
-        c->bfs_grid_shared = bgs > 0 && bgs <= 4096 ? bgs : 64;
-        const int upg = env_int("MPCG_UP_GRID", kUpdateGrid);
-        c->up_grid = upg >= 64 && upg <= kMaxGrid ? upg : kUpdateGrid;
-    }
+    c->force_csr = o.spmv_variant == 3;
+    hipDeviceProp_t prop{};
     if (hipGetDevice(&c->device) != hipSuccess || scratch_init(c->device) != hipSuccess ||
+        hipGetDeviceProperties(&prop, c->device) != hipSuccess ||
         hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
         hipHostMalloc((void **)&c->hst, 6 * sizeof(DevState), hipHostMallocDefault) != hipSuccess ||
         hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking) != hipSuccess) {
         mpcg_destroy(c);
         return MPCG_EDEVICE;
+    }
+    {
+        const std::string name(prop.gcnArchName);
+        c->arch = name.substr(0, name.find(':'));   // "gfx950:sramecc+:xnack-" -> "gfx950"
     }
     for (auto &e : c->ev)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) { mpcg_destroy(c); return MPCG_EDEVICE; }
@@ -699,6 +687,35 @@ mpcg_status mpcg_destroy(mpcg_ctx *c)
     if (c->hst) (void)hipHostFree(c->hst);
     knn_free(&c->model);
     delete c;
+    return MPCG_OK;
+}
+
+mpcg_status mpcg_set_tuning(mpcg_ctx *c, const mpcg_tuning *t)
+{
+    if (!c) return MPCG_EINVAL;
+    if (!t) {
+        c->has_explicit = false;
+        return MPCG_OK;
+    }
+    if (!tune_valid(*t)) return MPCG_EINVAL;
+    c->explicit_t = *t;
+    c->has_explicit = true;
+    return MPCG_OK;
+}
+
+mpcg_status mpcg_load_tuning(mpcg_ctx *c, const char *path)
+{
+    if (!c || !path) return MPCG_EINVAL;
+    TuneTable tb;
+    if (tune_load(path, &tb) != 0) return MPCG_EINVAL;
+    c->table = tb;
+    return MPCG_OK;
+}
+
+mpcg_status mpcg_get_tuning(const mpcg_ctx *c, int64_t n, int64_t nnz, int64_t band, mpcg_tuning *out)
+{
+    if (!c || !out || n <= 0 || nnz < 0 || band < 0) return MPCG_EINVAL;
+    *out = resolve_tuning(c, n, nnz, band);
     return MPCG_OK;
 }
 
@@ -1037,7 +1054,7 @@ mpcg_status mpcg_bfs(mpcg_ctx *c, const mpcg_csr *A, int64_t src, int32_t *dist,
     Plan p;
     mpcg_status rc = ingest(c, A, nullptr, false, &p);
     if (rc != MPCG_OK) return rc;
-    BfsBufs bb = bfs_bufs(c, p);
+    BfsBufs bb = bfs_bufs(p);
     launch_bfs_seed_single(c->stream, bb, (int32_t)src);
     DevState s;
     rc = bfs_run(c->main, p, bb, &s);
@@ -1134,7 +1151,7 @@ mpcg_status mpcg_diameter_multi(mpcg_ctx *c, const mpcg_csr *A, const int32_t *s
     d.pdiam = f.pdiam;
     d.pdiam_multi = f.pdiam;
     d.best_start = -1;
-    BfsBufs bb = bfs_bufs(c, p);
+    BfsBufs bb = bfs_bufs(p);
     bb.persist = 0;   // one launch per level: needs no co-residency
     // the per-component key array is not used by single-source sweeps
     unsigned long long *hist = bb.best;
@@ -1275,7 +1292,8 @@ mpcg_status mpcg_batch_set_workspace(mpcg_ctx *c, void *arena, size_t bytes, int
     if (c->opt.precond != 0) return MPCG_EINVAL;   // the batched engine runs unpreconditioned stages
     if (c->eng) return MPCG_EBUSY;
     int st = MPCG_OK;
-    c->eng = mpcg::batch::engine_create(c->device, c->opt, &c->model, arena, bytes, max_rows, max_entries,
+    const mpcg_tuning bt = c->has_explicit ? c->explicit_t : tune_batch(c->table, c->arch, c->num_cu);
+    c->eng = mpcg::batch::engine_create(c->device, c->opt, bt, &c->model, arena, bytes, max_rows, max_entries,
                                         max_systems, &st);
     return (mpcg_status)st;
 }

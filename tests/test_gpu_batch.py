@@ -254,16 +254,12 @@ def test_batch_bfs_schedule_does_not_change_results(torch_mod, monkeypatch):
             ("er_1100000", lambda: W.er_laplacian(1_100_000, 16, seed=13))]
     mats = [(nm, g()) for nm, g in gens]
     print("schedules x " + ", ".join(f"{nm} (n={a.n})" for nm, a in mats), flush=True)
-    schedules = [{}, {"MPCG_BATCH_SMALL_CAP": "2048", "MPCG_BATCH_SMALL_LEVELS": "4096"},
-                 {"MPCG_BATCH_SMALL_CAP": "8", "MPCG_BATCH_SMALL_LEVELS": "1"}]
+    schedules = [{}, {"batch_small_cap": 2048, "batch_small_levels": 4096},
+                 {"batch_small_cap": 8, "batch_small_levels": 1, "batch_group_steps": 3, "batch_bfs_rounds": 2,
+                  "batch_level_grid": 96}]
     runs = []
     for env in schedules:
-        for k in ("MPCG_BATCH_SMALL_CAP", "MPCG_BATCH_SMALL_LEVELS", "MPCG_BATCH_SMALL_WORK"):
-            if k in env:
-                monkeypatch.setenv(k, env[k])
-            else:
-                monkeypatch.delenv(k, raising=False)
-        eng = BatchSolver(1_300_000, 40_000_000, 16, model=TEST_MODEL)
+        eng = BatchSolver(1_300_000, 40_000_000, 16, model=TEST_MODEL, tuning=env or None)
         try:
             reqs = [_make(torch_mod, nm, lambda a=a: a, 0.0, seed=30 + i)[2] for i, (nm, a) in enumerate(mats)]
             ids = eng.submit(reqs)
