@@ -139,6 +139,13 @@ struct Engine {
     RangeAlloc slices, entries;
     int32_t hi_sys = 0, hi_slice = 0;
     int64_t group = 0;
+    // the step's work list: the admitted systems that are not retiring
+    bool list_dirty = true;
+    int32_t list_slices = 0, list_sys = 0;
+    // step groups captured as graphs, by (product grid, per-system grid)
+    hipStream_t cap = nullptr;
+    std::map<std::pair<int32_t, int32_t>, hipGraphExec_t> graphs;
+    bool graphs_ok = true;
     // scheduling knobs: mpcg_tuning's batch_* fields
     int small_levels = kSmallBfsLevels;
     int small_cap = kSmallBfsCapDefault;
@@ -162,6 +169,9 @@ struct Engine {
 
     void run();
     bool step_once();
+    bool rebuild_list();
+    bool launch_group();
+    void drop_graphs();
     void finish(Slot &sl, const BSys *M, int status_override);
     void recompute_hi();
     void admit();
@@ -334,6 +344,7 @@ void Engine::process(const BSys *m, int32_t cnt, int64_t gi)
             launch_admit_finish(s, a, i, sl.nslices, sl.req.eps1);
             sl.adm = 2;
             sl.guard = group + 1;
+            list_dirty = true;
             continue;
         }
         if (sl.retiring) {
@@ -392,6 +403,7 @@ void Engine::process(const BSys *m, int32_t cnt, int64_t gi)
             sl.retiring = true;
             sl.retire_group = group + 1;
             sl.guard = group + 1;
+            list_dirty = true;
         }
     }
 }
@@ -479,6 +491,94 @@ bool Engine::bfs_pump()
     return true;
 }
 
+// Grid sizes of the step's launches, rounded up to m * 2^e with 8 <= m < 16
+// (at most one block in eight past the listed work) so that few distinct
+// sizes -- and captured graphs -- occur.
+static int32_t coarse_grid(int64_t x)
+{
+    if (x <= 16) return (int32_t)(x > 0 ? x : 1);
+    int e = 0;
+    while ((x >> e) >= 16) ++e;
+    int64_t m = x >> e;
+    if ((m << e) < x) ++m;
+    return (int32_t)(m << e);
+}
+
+// The work list: systems whose rows and entries are in place and that have
+// not been seen to finish, in slot order.
+bool Engine::rebuild_list()
+{
+    ListChunk c{};
+    int32_t total = 0, nsys = 0;
+    std::vector<int32_t> ids;
+    for (int32_t i = 0; i < (int32_t)slots.size(); ++i)
+        if (slots[i].used && slots[i].adm == 2 && !slots[i].retiring) ids.push_back(i);
+    for (int32_t i : ids) total += slots[i].nslices;
+    nsys = (int32_t)ids.size();
+    int32_t pre = 0;
+    size_t k = 0;
+    do {
+        c.first = (int32_t)k;
+        c.n = 0;
+        for (; k < ids.size() && c.n < kListChunk; ++k, ++c.n) {
+            const Slot &sl = slots[ids[k]];
+            c.slot[c.n] = ids[k];
+            c.slice0[c.n] = sl.slice0;
+            c.nslices[c.n] = sl.nslices;
+            c.pre[c.n] = pre;
+            pre += sl.nslices;
+        }
+        c.last = k == ids.size() ? 1 : 0;
+        c.total_slices = total;
+        c.total_sys = nsys;
+        launch_worklist(s, a, c);
+    } while (k < ids.size());
+    if (hipGetLastError() != hipSuccess) return false;
+    list_slices = total;
+    list_sys = nsys;
+    list_dirty = false;
+    return true;
+}
+
+void Engine::drop_graphs()
+{
+    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+}
+
+// One group of steps: a graph replay when the group is captured (once per
+// pair of grid sizes), else plain launches.
+bool Engine::launch_group()
+{
+    const int32_t gsl = coarse_grid((list_slices + kSlicesPerBlock - 1) / kSlicesPerBlock);
+    const int32_t gsys = coarse_grid(list_sys);
+    if (graphs_ok) {
+        const auto key = std::make_pair(gsl, gsys);
+        auto it = graphs.find(key);
+        if (it == graphs.end()) {
+            if (graphs.size() >= 64) drop_graphs();
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ex = nullptr;
+            bool ok = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                for (int j = 0; j < group_steps; ++j) launch_step(cap, a, gsl, gsys);
+                ok = hipStreamEndCapture(cap, &g) == hipSuccess && g != nullptr;
+            }
+            ok = ok && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            if (!ok) {
+                graphs_ok = false;   // plain launches from now on
+            } else {
+                it = graphs.emplace(key, ex).first;
+            }
+        }
+        if (graphs_ok) return hipGraphLaunch(it->second, s) == hipSuccess;
+    }
+    for (int j = 0; j < group_steps; ++j) launch_step(s, a, gsl, gsys);
+    return hipGetLastError() == hipSuccess;
+}
+
 bool Engine::step_once()
 {
     // new submissions and cancellations
@@ -517,8 +617,8 @@ bool Engine::step_once()
     if (!any_used) return true;
     if (!bfs_pump()) return false;
     const int k = (int)(group & 1);
-    if (any_live)
-        for (int g = 0; g < group_steps; ++g) launch_step(s, a, hi_slice, hi_sys);
+    if (list_dirty && !rebuild_list()) return false;
+    if (any_live && list_sys > 0 && !launch_group()) return false;
     if (hipGetLastError() != hipSuccess) return false;
     mirror_n[k] = hi_sys;
     mirror_group[k] = group;
@@ -612,6 +712,7 @@ Engine *engine_create(int device, const mpcg_options &opt, const mpcg_tuning &tu
     e->entries.init(max_entries);
     bool ok = hipStreamCreateWithFlags(&e->s, hipStreamNonBlocking) == hipSuccess &&
               hipStreamCreateWithFlags(&e->sb, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&e->evb, hipEventDisableTiming) == hipSuccess &&
               hipHostMalloc((void **)&e->bmirror, sizeof(BSys) * (size_t)max_sys, hipHostMallocDefault) ==
                   hipSuccess;
@@ -653,6 +754,8 @@ void engine_destroy(Engine *e)
         (void)hipStreamSynchronize(e->sb);
         (void)hipStreamDestroy(e->sb);
     }
+    e->drop_graphs();
+    if (e->cap) (void)hipStreamDestroy(e->cap);
     if (e->evb) (void)hipEventDestroy(e->evb);
     if (e->bmirror) (void)hipHostFree(e->bmirror);
     for (auto &v : e->ev) if (v) (void)hipEventDestroy(v);

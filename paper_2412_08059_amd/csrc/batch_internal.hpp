@@ -78,7 +78,8 @@ struct alignas(256) BSys {
     double spec_thr[kNumEps];
     double cross_gamma[kNumEps];
     int32_t cross_iter[kNumEps];
-    int32_t snap_mask, snap_ci, ra_stop, ra_pad;
+    int32_t snap_mask, snap_ci, ra_stop;
+    int32_t spec;                          // the FP64 phase runs speculatively from the tightest candidate
     // 2BFS
     int32_t bfs_mode, bfs_sweep, bfs_level, bfs_cnt;
     int32_t bfs_nxt, ncomp, pdiam, bfs_t;
@@ -116,8 +117,21 @@ struct BArena {
     int32_t *small_sys;                    // systems expanding small levels this step
     int32_t *counts;                       // [0] = #act, [1] = #small, [2] = admission error (unused)
     int64_t *items;                        // total items of the large level
+    // the step's work list, rebuilt when a system joins or leaves it
+    int32_t *step_map;                     // [k] = slice of the k-th listed slice (systems in list order)
+    int32_t *step_sys;                     // [k] = slot of the k-th listed system
+    int32_t *step_cnt;                     // [0] = listed slices, [1] = listed systems
     int32_t acc32;                         // dot_acc = 1: FP32-phase dot products accumulate in FP32
     int32_t pad_;
+};
+
+// One launch's share of a work-list rebuild: entries first .. first + n - 1
+// of the list (slot, its first slice and slice count, and the list position
+// of its first slice); the last share also writes the totals.
+constexpr int kListChunk = 200;   // keeps the launch argument under 4 KB
+struct ListChunk {
+    int32_t first, n, last, total_slices, total_sys, pad_;
+    int32_t slot[kListChunk], slice0[kListChunk], nslices[kListChunk], pre[kListChunk];
 };
 
 size_t arena_bytes(int32_t max_sys, int32_t max_slices, int64_t max_entries);
@@ -138,8 +152,12 @@ void launch_bfs_cancel(hipStream_t s, const BArena &a, int32_t sys);   // its 2B
 void launch_set_eps(hipStream_t s, const BArena &a, int32_t sys, double eps1, int32_t ci);
 void launch_fill_slices(hipStream_t s, const BArena &a);   // every slice unowned
 
-// ---- one step over all systems ----
-void launch_step(hipStream_t s, const BArena &a, int32_t hi_slice, int32_t hi_sys);
+// ---- one step over the systems of the work list ----
+// A rebuild of the work list (chunks in order); then steps launch grid_slices
+// blocks of four slices and grid_sys blocks of one system, at least the
+// listed counts (blocks past them return at once).
+void launch_worklist(hipStream_t s, const BArena &a, const ListChunk &c);
+void launch_step(hipStream_t s, const BArena &a, int32_t grid_slices, int32_t grid_sys);
 
 // ---- 2BFS (BFS stream) ----
 // Kernels on the BFS stream write only the BFS fields of a system's state

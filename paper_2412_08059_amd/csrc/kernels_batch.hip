@@ -112,6 +112,7 @@ size_t arena_bytes(int32_t max_sys, int32_t max_slices, int64_t max_entries)
     t += up256(4 * rows) * 5 + up256(8 * rows) + up256(rows / 8);     // BFS
     t += up256(4 * e) + up256(8 * e) + up256(4 * e);                  // col, v64, v32
     t += up256(4 * (size_t)max_sys) * 2 + up256(8 * (size_t)max_sys) + 256 + 256;
+    t += up256(4 * sl) + up256(4 * (size_t)max_sys) + 256;            // step work list
     return t;
 }
 
@@ -157,6 +158,9 @@ BArena carve(void *base, int32_t max_sys, int32_t max_slices, int64_t max_entrie
     a.act_pre = reinterpret_cast<int64_t *>(take(8 * (size_t)max_sys));
     a.counts = reinterpret_cast<int32_t *>(take(256));
     a.items = reinterpret_cast<int64_t *>(take(256));
+    a.step_map = reinterpret_cast<int32_t *>(take(4 * sl));
+    a.step_sys = reinterpret_cast<int32_t *>(take(4 * (size_t)max_sys));
+    a.step_cnt = reinterpret_cast<int32_t *>(take(256));
     return a;
 }
 
@@ -403,6 +407,25 @@ __global__ void k_set_eps(BArena a, int32_t sys, double eps1, int32_t ci)
         S.mode = kRestart;
         return;
     }
+    if (S.spec) {   // the speculative FP64 phase (see k_b_scalar2)
+        S.spec = 0;
+        if (ci >= 0 && ci < kNumEps && S.cross_iter[ci] == S.cross_iter[kNumEps - 1]) return;   // same state: kept
+        // discarded: the FP64 stage starts again from the chosen candidate's copy
+        S.n2 = 0;
+        S.restarts = 0;
+        S.flags &= ~MPCG_FLAG_FINAL_RESTARTED;
+        S.pend = 0;
+        S.status = MPCG_OK;
+        S.n1 = S.cross_iter[ci];
+        S.gamma = S.cross_gamma[ci];
+        S.relres_sp = sqrt(S.gamma) / sb;
+        S.src = ((S.snap_mask >> ci) & 1) ? kSrcX32 : kSrcSnap;
+        S.snap_ci = ci;
+        S.upd = 0;
+        S.ph_it = 0;
+        S.mode = kRestart;
+        return;
+    }
     if (S.k0_used == 0 || (S.mode != kHold && S.mode != kCg32)) return;
     if (ci >= 0 && ci < kNumEps && S.cross_iter[ci] >= 0) {
         S.n1 = S.cross_iter[ci];
@@ -513,10 +536,11 @@ __device__ inline double residual(const BArena &a, const BSys &S, bool restart, 
     return res * res;
 }
 
-__global__ void __launch_bounds__(kBlock) k_b_product(BArena a, int32_t hi_slice)
+__global__ void __launch_bounds__(kBlock) k_b_product(BArena a)
 {
-    const int sl = blockIdx.x * kSlicesPerBlock + (threadIdx.x >> 6);
-    if (sl >= hi_slice) return;
+    const int k = blockIdx.x * kSlicesPerBlock + (threadIdx.x >> 6);
+    if (k >= a.step_cnt[0]) return;
+    const int sl = a.step_map[k];
     const int s = a.sys_of_slice[sl];
     if (s < 0) return;
     const BSys &S = a.sys[s];
@@ -542,7 +566,8 @@ __global__ void __launch_bounds__(kBlock) k_b_product(BArena a, int32_t hi_slice
 __global__ void __launch_bounds__(kBlock) k_b_scalar1(BArena a)
 {
     __shared__ double sm[kBlock / 64 + 1];
-    BSys &S = a.sys[blockIdx.x];
+    if ((int)blockIdx.x >= a.step_cnt[1]) return;
+    BSys &S = a.sys[a.step_sys[blockIdx.x]];
     const int mode = S.mode;
     if (threadIdx.x == 0 && S.snap_mask) S.snap_mask = 0;   // the product of this step took the copies
     if (mode != kCg32 && mode != kCg64 && mode != kRestart && mode != kResid) return;
@@ -620,10 +645,11 @@ __device__ inline double cg_update(const BArena &a, const BSys &S, T *x, T *r, c
     return wave_sum_d((double)rv * (double)rv);
 }
 
-__global__ void __launch_bounds__(kBlock) k_b_update(BArena a, int32_t hi_slice)
+__global__ void __launch_bounds__(kBlock) k_b_update(BArena a)
 {
-    const int sl = blockIdx.x * kSlicesPerBlock + (threadIdx.x >> 6);
-    if (sl >= hi_slice) return;
+    const int k = blockIdx.x * kSlicesPerBlock + (threadIdx.x >> 6);
+    if (k >= a.step_cnt[0]) return;
+    const int sl = a.step_map[k];
     const int s = a.sys_of_slice[sl];
     if (s < 0) return;
     const BSys &S = a.sys[s];
@@ -639,7 +665,8 @@ __global__ void __launch_bounds__(kBlock) k_b_update(BArena a, int32_t hi_slice)
 __global__ void __launch_bounds__(kBlock) k_b_scalar2(BArena a)
 {
     __shared__ double sm[kBlock / 64 + 1];
-    BSys &S = a.sys[blockIdx.x];
+    if ((int)blockIdx.x >= a.step_cnt[1]) return;
+    BSys &S = a.sys[a.step_sys[blockIdx.x]];
     if (!S.upd) return;
     const double g = (S.mode == kCg32 && a.acc32) ? sys_sum_f(a, S, 0, sm) : sys_sum(a, S, 0, sm);
     if (threadIdx.x != 0) return;
@@ -673,8 +700,18 @@ __global__ void __launch_bounds__(kBlock) k_b_scalar2(BArena a)
             }
             S.snap_mask = due;
             if (left == 0) {
+                // every candidate crossed before eps1 is known: the FP64 phase
+                // starts now from the tightest candidate's state (x~ of this
+                // iteration); k_set_eps keeps it when the chosen candidate
+                // crossed at this same iteration, else restarts the FP64 phase
+                // from the chosen candidate's copy -- the sequential method's
+                // state either way
                 S.ra_stop = kRaAllCrossed;
-                S.mode = kHold;
+                S.spec = 1;
+                S.relres_sp = sqrt(g) / sb;
+                S.src = kSrcX32;
+                S.ph_it = 0;
+                S.mode = kRestart;
             } else if (S.n1 >= S.maxit1) {
                 S.ra_stop = kRaMaxit;
                 S.mode = kHold;
@@ -1009,14 +1046,33 @@ __global__ void __launch_bounds__(kBlock) k_bfs_small_batch(BArena a, int32_t ma
     }
 }
 
-void launch_step(hipStream_t s, const BArena &a, int32_t hi_slice, int32_t hi_sys)
+// Block j writes the list entries of the chunk's system j: its slot, and the
+// slices of its range at their list positions.
+__global__ void __launch_bounds__(kBlock) k_worklist(BArena a, ListChunk c)
 {
-    if (hi_slice <= 0 || hi_sys <= 0) return;
-    const int gsl = (hi_slice + kSlicesPerBlock - 1) / kSlicesPerBlock;
-    hipLaunchKernelGGL(k_b_product, dim3(gsl), dim3(kBlock), 0, s, a, hi_slice);
-    hipLaunchKernelGGL(k_b_scalar1, dim3(hi_sys), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_b_update, dim3(gsl), dim3(kBlock), 0, s, a, hi_slice);
-    hipLaunchKernelGGL(k_b_scalar2, dim3(hi_sys), dim3(kBlock), 0, s, a);
+    const int j = blockIdx.x;
+    if (c.last && j == 0 && threadIdx.x == 0) {
+        a.step_cnt[0] = c.total_slices;
+        a.step_cnt[1] = c.total_sys;
+    }
+    if (j >= c.n) return;
+    const int32_t s0 = c.slice0[j], pre = c.pre[j];
+    for (int i = threadIdx.x; i < c.nslices[j]; i += kBlock) a.step_map[pre + i] = s0 + i;
+    if (threadIdx.x == 0) a.step_sys[c.first + j] = c.slot[j];
+}
+
+void launch_worklist(hipStream_t s, const BArena &a, const ListChunk &c)
+{
+    hipLaunchKernelGGL(k_worklist, dim3(c.n > 0 ? c.n : 1), dim3(kBlock), 0, s, a, c);
+}
+
+void launch_step(hipStream_t s, const BArena &a, int32_t grid_slices, int32_t grid_sys)
+{
+    if (grid_slices <= 0 || grid_sys <= 0) return;
+    hipLaunchKernelGGL(k_b_product, dim3(grid_slices), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_b_scalar1, dim3(grid_sys), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_b_update, dim3(grid_slices), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_b_scalar2, dim3(grid_sys), dim3(kBlock), 0, s, a);
 }
 
 void launch_bfs_round(hipStream_t s, const BArena &a, int32_t hi_sys, int small_levels, int small_cap,
