@@ -310,8 +310,8 @@ def bench_family(args):
     from workloads import paper_family as PF
     n = args.family_n
     sizes = {"star": n + 1, "random": n, "banded": n}
-    eng = BatchSolver(256 * (n + 128), 256 * 200_000, 256, model=DEFAULT_MODEL)
-    solver = None if args.family_no_omega else Solver(n + 8, 200_000)
+    eng = BatchSolver(256 * (n + 128), 256 * 200_000, 256, model=DEFAULT_MODEL, dot_acc=args.dot_acc)
+    solver = None if args.family_no_omega else Solver(n + 8, 200_000, dot_acc=args.dot_acc)
     fams = {}
     for fam in ("star", "random", "banded"):
         specs = PF.sample_specs(fam, sizes[fam], scale=args.family_scale, seed=args.seed)
@@ -339,7 +339,8 @@ def bench_family(args):
                                   f"n={n}; Algorithm III values; mu in {{1.1, 3, 10}}; x~U(1,2), b=Ax; eps2=1e-10; "
                                   f"sample scale {args.family_scale} of the appendix sizes; "
                                   f"{args.family_reps} training/test splits",
-                      "features": "(m, pseudo-diameter, v)"},
+                      "features": "(m, pseudo-diameter, v)",
+                      "fp32_dot_accumulation": "fp32" if args.dot_acc else "fp64"},
            "paper_context": {"Acc_pct_n1000": [70, 71, 74], "E_third_pct_n1000": [22, 22, 17.7],
                              "E_meas_pct_n1000": [31.0, 30.8, 25.3], "note": "sequential CPU, Colab"},
            "families": fams}
@@ -589,6 +590,8 @@ def main():
     ap.add_argument("--kernel-only", action="store_true",
                     help="for PMC runs: a 1 GiB device copy (counter calibration) and 20 launches of "
                          "each CG kernel on the workload, nothing else")
+    ap.add_argument("--kernel-band", action="store_true",
+                    help="with --kernel-only: the 4e6-row band (--large-n) instead of the 3D grid")
     ap.add_argument("--workload", choices=("solve", "batch", "serve", "family", "jacobi_iter", "diameter"),
                     default="solve",
                     help="solve: the 128^3 single-system benchmark (default); batch: many systems in one "
@@ -601,6 +604,8 @@ def main():
     ap.add_argument("--family-scale", type=float, default=0.25, help="fraction of the appendix sample sizes")
     ap.add_argument("--family-reps", type=int, default=20)
     ap.add_argument("--family-no-omega", action="store_true", help="skip the per-matrix omega measurement")
+    ap.add_argument("--dot-acc", type=int, default=0, choices=(0, 1),
+                    help="family workload: FP32-phase dot products accumulated in FP64 (0) or FP32 (1)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-nmin", type=float, default=1e3)
     ap.add_argument("--batch-nmax", type=float, default=2e5)
@@ -637,7 +642,10 @@ def main():
     model = args.model or DEFAULT_MODEL
     have_model = os.path.exists(model)
     t_gen = time.perf_counter()
-    a = W.varcoef3d(args.grid, seed=args.seed)
+    if args.kernel_only and args.kernel_band:
+        a = W.banded(args.large_n, 8, seed=args.seed)   # the >1 GB band, for counter runs
+    else:
+        a = W.varcoef3d(args.grid, seed=args.seed)
     xstar, b = W.rhs(a, seed=args.seed)
     t_gen = time.perf_counter() - t_gen
     n, m = a.n, a.nnz
