@@ -285,6 +285,11 @@ def bench_batch(args):
                       "cg_GBs": round(byt / wall / 1e9, 1),
                       "latency_ms_p50": round(float(np.percentile([s.t_total_ms for s in st], 50)), 1),
                       "latency_ms_max": round(float(np.max([s.t_total_ms for s in st])), 1)}
+        if e1 == 0.0:
+            tf = [s.t_feat_ms for s in st]
+            res[label]["features_ms_p50"] = round(float(np.percentile(tf, 50)), 1)
+            res[label]["features_ms_p90"] = round(float(np.percentile(tf, 90)), 1)
+            res[label]["eps1_classes"] = {str(t): int(sum(1 for s in st if s.eps1_class == t)) for t in range(2, 8)}
         print(f"# batch {label}: {res[label]}", file=sys.stderr, flush=True)
     eng.close()
     fams = {f: sum(1 for g, _, _ in systems if g == f) for f in ("lap2d", "lap3d", "banded", "er")}

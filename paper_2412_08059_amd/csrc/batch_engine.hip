@@ -103,6 +103,7 @@ struct Slot {
     bool autoe = false;
     int feat = 0;           // 0 not started, 1 sweep 1, 2 sweep 2, 3 finishing, 4 done (or none), 5 cancelling
     bool want_start = false;   // admitted: start the 2BFS on the BFS stream
+    bool fast = false;         // the first sweep runs from vertex 0 without components
     bool want_bfs_cancel = false;
     bool bfs_ready = false;    // pdiam, t, u, ncomp are in f
     int64_t guard = 0;      // ignore state copies of groups before this one
@@ -434,8 +435,15 @@ bool Engine::process_bfs(const BSys *m, int32_t cnt)
             sl.feat = 2;
             enq = true;
         } else if (sl.feat == 2 && M.bfs_mode == kBfsSwept) {
-            launch_bfs_finish(sb, a, i, (int32_t)sl.f.n);
-            sl.feat = 3;
+            if (sl.fast && M.reached < (int32_t)sl.f.n) {
+                // not connected: start over with the connected components
+                launch_bfs_start(sb, a, i, (int32_t)sl.f.n);
+                sl.fast = false;
+                sl.feat = 1;
+            } else {
+                launch_bfs_finish(sb, a, i, (int32_t)sl.f.n);
+                sl.feat = 3;
+            }
             enq = true;
         } else if (sl.feat == 3 && M.bfs_mode == kBfsDone && !sl.bfs_ready) {
             sl.f.pdiam = M.pdiam;
@@ -471,7 +479,8 @@ bool Engine::bfs_pump()
             enq = true;
         }
         if (sl.want_start) {
-            launch_bfs_start(sb, a, i, (int32_t)sl.f.n);
+            launch_bfs_fast_start(sb, a, i, (int32_t)sl.f.n);
+            sl.fast = true;
             sl.want_start = false;
             sl.feat = 1;
             enq = true;

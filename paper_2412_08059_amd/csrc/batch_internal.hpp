@@ -85,6 +85,8 @@ struct alignas(256) BSys {
     int32_t bfs_nxt, ncomp, pdiam, bfs_t;
     int32_t bfs_u, small, bfs_err;         // bfs_err: kErrGuard from the BFS kernels
     int32_t vis_lvl;                       // BArena::vis of the system matches dist after this level
+    int32_t reached;                       // vertices the first sweep reached (counted at its end)
+    int32_t reached_pad;
     int64_t padded;                        // SELL-64 entries of the system (admission scan)
     unsigned long long comp_best;
     int64_t item0;                         // first BFS work item of this system in the current level
@@ -118,7 +120,7 @@ struct BArena {
     int32_t *counts;                       // [0] = #act, [1] = #small, [2] = admission error (unused)
     int64_t *items;                        // total items of the large level
     // the step's work list, rebuilt when a system joins or leaves it
-    int32_t *step_map;                     // [k] = slice of the k-th listed slice (systems in list order)
+    int2 *step_map;                        // [k] = (slice, slot) of the k-th listed slice (systems in list order)
     int32_t *step_sys;                     // [k] = slot of the k-th listed system
     int32_t *step_cnt;                     // [0] = listed slices, [1] = listed systems
     int32_t acc32;                         // dot_acc = 1: FP32-phase dot products accumulate in FP32
@@ -174,6 +176,10 @@ void launch_bfs_round(hipStream_t s, const BArena &a, int32_t hi_sys, int small_
                       int64_t small_work, int level_grid);
 // host-driven transitions of one system of n rows
 void launch_bfs_start(hipStream_t s, const BArena &a, int32_t sys, int32_t n);        // CC + sweep-1 seeds
+// first sweep from vertex 0 alone, every vertex labelled with it (no
+// components): right when the graph is connected, which its end shows
+// (reached == n); otherwise the host starts over with launch_bfs_start
+void launch_bfs_fast_start(hipStream_t s, const BArena &a, int32_t sys, int32_t n);
 void launch_bfs_next_sweep(hipStream_t s, const BArena &a, int32_t sys, int32_t n);   // argmax + sweep-2 seeds
 void launch_bfs_finish(hipStream_t s, const BArena &a, int32_t sys, int32_t n);       // argmax + per-system result
 

@@ -55,8 +55,21 @@ __device__ inline double block_sum_d(double v, double *sm)
 // Sum of component j of the slice partials of system S, fixed order.
 __device__ inline double sys_sum(const BArena &a, const BSys &S, int j, double *sm)
 {
+    // four loads in flight per thread, added in index order (the same bits
+    // as one at a time)
+    const double *p = a.pslice + 2 * (size_t)S.slice0 + j;
+    const int cnt = S.nslices;
     double acc = 0.0;
-    for (int i = threadIdx.x; i < S.nslices; i += kBlock) acc += a.pslice[2 * (size_t)(S.slice0 + i) + j];
+    int i = threadIdx.x;
+    for (; i + 3 * kBlock < cnt; i += 4 * kBlock) {
+        const double p0 = p[2 * (size_t)i], p1 = p[2 * (size_t)(i + kBlock)];
+        const double p2 = p[2 * (size_t)(i + 2 * kBlock)], p3 = p[2 * (size_t)(i + 3 * kBlock)];
+        acc += p0;
+        acc += p1;
+        acc += p2;
+        acc += p3;
+    }
+    for (; i < cnt; i += kBlock) acc += p[2 * (size_t)i];
     return block_sum_d(acc, sm);
 }
 
@@ -69,8 +82,19 @@ __device__ inline float wave_sum_f(float v)
 
 __device__ inline double sys_sum_f(const BArena &a, const BSys &S, int j, double *sm)
 {
+    const double *p = a.pslice + 2 * (size_t)S.slice0 + j;
+    const int cnt = S.nslices;
     float acc = 0.0f;
-    for (int i = threadIdx.x; i < S.nslices; i += kBlock) acc += (float)a.pslice[2 * (size_t)(S.slice0 + i) + j];
+    int i = threadIdx.x;
+    for (; i + 3 * kBlock < cnt; i += 4 * kBlock) {
+        const double p0 = p[2 * (size_t)i], p1 = p[2 * (size_t)(i + kBlock)];
+        const double p2 = p[2 * (size_t)(i + 2 * kBlock)], p3 = p[2 * (size_t)(i + 3 * kBlock)];
+        acc += (float)p0;
+        acc += (float)p1;
+        acc += (float)p2;
+        acc += (float)p3;
+    }
+    for (; i < cnt; i += kBlock) acc += (float)p[2 * (size_t)i];
     acc = wave_sum_f(acc);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0) sm[w] = (double)acc;
@@ -112,7 +136,7 @@ size_t arena_bytes(int32_t max_sys, int32_t max_slices, int64_t max_entries)
     t += up256(4 * rows) * 5 + up256(8 * rows) + up256(rows / 8);     // BFS
     t += up256(4 * e) + up256(8 * e) + up256(4 * e);                  // col, v64, v32
     t += up256(4 * (size_t)max_sys) * 2 + up256(8 * (size_t)max_sys) + 256 + 256;
-    t += up256(4 * sl) + up256(4 * (size_t)max_sys) + 256;            // step work list
+    t += up256(8 * sl) + up256(4 * (size_t)max_sys) + 256;            // step work list
     return t;
 }
 
@@ -158,7 +182,7 @@ BArena carve(void *base, int32_t max_sys, int32_t max_slices, int64_t max_entrie
     a.act_pre = reinterpret_cast<int64_t *>(take(8 * (size_t)max_sys));
     a.counts = reinterpret_cast<int32_t *>(take(256));
     a.items = reinterpret_cast<int64_t *>(take(256));
-    a.step_map = reinterpret_cast<int32_t *>(take(4 * sl));
+    a.step_map = reinterpret_cast<int2 *>(take(8 * sl));
     a.step_sys = reinterpret_cast<int32_t *>(take(4 * (size_t)max_sys));
     a.step_cnt = reinterpret_cast<int32_t *>(take(256));
     return a;
@@ -540,8 +564,8 @@ __global__ void __launch_bounds__(kBlock) k_b_product(BArena a)
 {
     const int k = blockIdx.x * kSlicesPerBlock + (threadIdx.x >> 6);
     if (k >= a.step_cnt[0]) return;
-    const int sl = a.step_map[k];
-    const int s = a.sys_of_slice[sl];
+    const int2 e = a.step_map[k];   // slice and its system: no dependent lookup of the owner
+    const int sl = e.x, s = e.y;
     if (s < 0) return;
     const BSys &S = a.sys[s];
     const int lane = threadIdx.x & 63;
@@ -649,8 +673,8 @@ __global__ void __launch_bounds__(kBlock) k_b_update(BArena a)
 {
     const int k = blockIdx.x * kSlicesPerBlock + (threadIdx.x >> 6);
     if (k >= a.step_cnt[0]) return;
-    const int sl = a.step_map[k];
-    const int s = a.sys_of_slice[sl];
+    const int2 e = a.step_map[k];   // slice and its system: no dependent lookup of the owner
+    const int sl = e.x, s = e.y;
     if (s < 0) return;
     const BSys &S = a.sys[s];
     if (!S.upd) return;
@@ -1057,7 +1081,7 @@ __global__ void __launch_bounds__(kBlock) k_worklist(BArena a, ListChunk c)
     }
     if (j >= c.n) return;
     const int32_t s0 = c.slice0[j], pre = c.pre[j];
-    for (int i = threadIdx.x; i < c.nslices[j]; i += kBlock) a.step_map[pre + i] = s0 + i;
+    for (int i = threadIdx.x; i < c.nslices[j]; i += kBlock) a.step_map[pre + i] = make_int2(s0 + i, c.slot[j]);
     if (threadIdx.x == 0) a.step_sys[c.first + j] = c.slot[j];
 }
 
@@ -1155,6 +1179,28 @@ __global__ void __launch_bounds__(kBlock) k_b_cc_seed(BArena a, int32_t sys)
     if (guard) atomicOr(&S.bfs_err, kErrGuard);
 }
 
+// First sweep without components: every vertex labelled with vertex 0, which
+// seeds the sweep alone (k_b_seed_root, after this kernel).
+__global__ void __launch_bounds__(kBlock) k_b_fast_init(BArena a, int32_t sys)
+{
+    const BSys &S = a.sys[sys];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < S.n; i += gridDim.x * kBlock) {
+        a.label[S.row0 + i] = S.row0;
+        a.dist[S.row0 + i] = -1;
+    }
+}
+
+__global__ void k_b_seed_root(BArena a, int32_t sys)
+{
+    if (threadIdx.x != 0) return;
+    BSys &S = a.sys[sys];
+    a.dist[S.row0] = 0;
+    a.best[S.row0] = 0ull;
+    a.q0[S.row0] = S.row0;
+    S.bfs_nxt = 1;
+    S.reached = 0;
+}
+
 __global__ void k_b_bfs_arm(BArena a, int32_t sys, int32_t sweep)
 {
     if (threadIdx.x == 0) {
@@ -1176,9 +1222,9 @@ __global__ void k_b_zero_nxt(BArena a, int32_t sys)
 // connected system sends every vertex to the same key slot, and same-address
 // atomics serialise: a wave whose reached vertices share one component takes
 // the maximum over its lanes first and issues one atomic.
-__global__ void __launch_bounds__(kBlock) k_b_argmax(BArena a, int32_t sys)
+__global__ void __launch_bounds__(kBlock) k_b_argmax(BArena a, int32_t sys, int32_t count)
 {
-    const BSys &S = a.sys[sys];
+    BSys &S = a.sys[sys];
     const int lane = threadIdx.x & 63;
     // wave-uniform loop: every lane of a wave walks the same bases
     for (int base = blockIdx.x * kBlock + (threadIdx.x & ~63); base < S.n; base += gridDim.x * kBlock) {
@@ -1195,6 +1241,7 @@ __global__ void __launch_bounds__(kBlock) k_b_argmax(BArena a, int32_t sys)
         }
         const unsigned long long m = __ballot(lab >= 0);
         if (m == 0ull) continue;
+        if (count && lane == 0) atomicAdd(&S.reached, (int)__popcll(m));   // the first sweep's reach
         const int l0 = __ffsll((unsigned long long)m) - 1;
         const int L = __shfl(lab, l0, 64);
         if (__all(lab < 0 || lab == L)) {
@@ -1280,10 +1327,18 @@ void launch_bfs_start(hipStream_t s, const BArena &a, int32_t sys, int32_t n)
     hipLaunchKernelGGL(k_b_bfs_arm, dim3(1), dim3(64), 0, s, a, sys, 1);
 }
 
+void launch_bfs_fast_start(hipStream_t s, const BArena &a, int32_t sys, int32_t n)
+{
+    const int g = rows_grid(n);
+    hipLaunchKernelGGL(k_b_fast_init, dim3(g), dim3(kBlock), 0, s, a, sys);
+    hipLaunchKernelGGL(k_b_seed_root, dim3(1), dim3(64), 0, s, a, sys);
+    hipLaunchKernelGGL(k_b_bfs_arm, dim3(1), dim3(64), 0, s, a, sys, 1);
+}
+
 void launch_bfs_next_sweep(hipStream_t s, const BArena &a, int32_t sys, int32_t n)
 {
     const int g = rows_grid(n);
-    hipLaunchKernelGGL(k_b_argmax, dim3(g), dim3(kBlock), 0, s, a, sys);
+    hipLaunchKernelGGL(k_b_argmax, dim3(g), dim3(kBlock), 0, s, a, sys, 1);
     hipLaunchKernelGGL(k_b_fill_dist, dim3(g), dim3(kBlock), 0, s, a, sys);
     hipLaunchKernelGGL(k_b_zero_nxt, dim3(1), dim3(64), 0, s, a, sys);
     hipLaunchKernelGGL(k_b_seed_far, dim3(g), dim3(kBlock), 0, s, a, sys);
@@ -1293,7 +1348,7 @@ void launch_bfs_next_sweep(hipStream_t s, const BArena &a, int32_t sys, int32_t 
 void launch_bfs_finish(hipStream_t s, const BArena &a, int32_t sys, int32_t n)
 {
     const int g = rows_grid(n);
-    hipLaunchKernelGGL(k_b_argmax, dim3(g), dim3(kBlock), 0, s, a, sys);
+    hipLaunchKernelGGL(k_b_argmax, dim3(g), dim3(kBlock), 0, s, a, sys, 0);
     hipLaunchKernelGGL(k_b_comp_best, dim3(g), dim3(kBlock), 0, s, a, sys);
     hipLaunchKernelGGL(k_b_feat_final, dim3(1), dim3(64), 0, s, a, sys);
 }
