@@ -26,7 +26,9 @@
  *     HOST memory.
  *   - The caller owns every buffer.  The library allocates no device memory:
  *     all scratch lives in the arena handed over by mpcg_set_workspace.  It
- *     allocates a few KB of pinned host memory per context for the readbacks.
+ *     allocates a few KB of pinned host memory per context for the readbacks,
+ *     and captures HIP graphs (whose memory the HIP runtime owns) for the
+ *     batched engine's steps and the rounds of the bit-parallel 2BFS.
  *   - All work is enqueued on the context's stream; a call returns after its
  *     results are complete (it synchronises that stream).  One context per
  *     host thread and stream; calls on one context must not overlap.
@@ -90,6 +92,8 @@ typedef struct {
 #define MPCG_FLAG_FP32_MAXIT 2       /* FP32 phase hit maxit1: switched to FP64 */
 #define MPCG_FLAG_FINAL_RESTARTED 4  /* final true residual above eps2: FP64 restarted from b - Ax */
 #define MPCG_FLAG_KNN_EXACT 8        /* a training sample had zero distance to chi */
+#define MPCG_FLAG_BFS_DIA 16         /* the 2BFS ran as bit-parallel levels over the diagonals
+                                        (mpcg_tuning.bfs_dia); the features are the same integers */
 
 typedef struct {
     int32_t n1;           /* FP32 iterations (the k0 prefix included) */
@@ -190,8 +194,9 @@ mpcg_status mpcg_solve(mpcg_ctx *ctx, const mpcg_csr *A, const double *b, double
  * the workspace taken from a device array built into the library (160 MiB on
  * every GPU the library runs on, held until the process ends) instead of the
  * context's arena, so it needs no mpcg_set_workspace and calls no hipMalloc,
- * hipFree or other allocating routine.  Algorithm II (eps1 = MPCG_EPS1_AUTO)
- * still starts one host thread for its 2BFS, as mpcg_solve does.
+ * hipFree or other allocating routine, and captures no graphs (its 2BFS rounds
+ * are plain launches).  Algorithm II (eps1 = MPCG_EPS1_AUTO) still starts one
+ * host thread for its 2BFS, as mpcg_solve does.
  * Arguments, results and errors are those of mpcg_solve, plus ENOMEM when the
  * system's workspace (mpcg_workspace_size for its n and nnz) exceeds the
  * array -- about 4e5 rows of a 7-point stencil fit.  Every call on a GPU
@@ -289,7 +294,13 @@ typedef struct {
     int32_t batch_small_cap;     /* largest frontier one block per system expands, 1..2048 */
     int32_t batch_small_levels;  /* levels one such launch may expand, 1..4096 */
     int32_t batch_level_grid;    /* blocks of the multi-block level kernel, 1..65536 */
-    int32_t pad_;
+    int32_t bfs_dia;             /* 2BFS sweeps as bit-parallel levels over the diagonals when the
+                                    pattern lies on at most 16 of them: 0 never, 1 when the pattern is
+                                    wider than |i - j| <= 8 and has at least 2^16 rows, 2 whenever it
+                                    qualifies */
+    int32_t bfs_dia_tiles;       /* with bfs_dia: 1 = several levels per launch (a block forms them on
+                                    its own words plus a halo that the levels consume), 0 = one launch
+                                    per level */
 } mpcg_tuning;
 
 /* Use *t for every matrix from now on (NULL: back to the table and the
@@ -299,7 +310,7 @@ mpcg_status mpcg_set_tuning(mpcg_ctx *ctx, const mpcg_tuning *t);
 
 /* Load a tuning table (host path; text, header "mpcg-tune 1", then lines
  * "solve <arch> <cu> <idx16> <lenlog> <nlog> <sell_batch> <sell_whole_batch>
- * <sell_split> <bfs_grid> <bfs_grid_shared> <bfs_persist>" and at most one
+ * <sell_split> <bfs_grid> <bfs_grid_shared> <bfs_persist> [<bfs_dia> [<bfs_dia_tiles>]]" and at most one
  * "batch <arch> <cu> <group_steps> <bfs_rounds> <small_cap> <small_levels>
  * <level_grid>").  EINVAL for a missing or malformed file (the previous
  * table is kept). */

@@ -30,7 +30,8 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "tuning.txt")
 
-SOLVE_FIELDS = ("sell_batch", "sell_whole_batch", "sell_split", "bfs_grid", "bfs_grid_shared", "bfs_persist")
+SOLVE_FIELDS = ("sell_batch", "sell_whole_batch", "sell_split", "bfs_grid", "bfs_grid_shared", "bfs_persist",
+                "bfs_dia", "bfs_dia_tiles")
 BATCH_FIELDS = ("batch_group_steps", "batch_bfs_rounds", "batch_small_cap", "batch_small_levels",
                 "batch_level_grid")
 
@@ -84,7 +85,7 @@ def format_table(solve_rows: dict, batch_row, comment: str = "") -> str:
     if comment:
         out += ["# " + ln for ln in comment.splitlines()]
     out.append("# solve arch cu idx16 lenlog nlog sell_batch sell_whole_batch sell_split bfs_grid "
-               "bfs_grid_shared bfs_persist")
+               "bfs_grid_shared bfs_persist bfs_dia bfs_dia_tiles")
     for key in sorted(solve_rows):
         v = solve_rows[key]
         arch, cu, idx16, ll, nl = key
@@ -104,9 +105,10 @@ def parse_table(text: str):
         raise ValueError("not an mpcg-tune 1 table")
     for ln in lines[1:]:
         f = ln.split()
-        if f[0] == "solve" and len(f) == 12:
+        if f[0] == "solve" and len(f) in (12, 13, 14):
             key = (f[1], int(f[2]), int(f[3]), int(f[4]), int(f[5]))
-            solve_rows[key] = dict(zip(SOLVE_FIELDS, (int(v) for v in f[6:])))
+            vals = [int(v) for v in f[6:]] + [1] * (14 - len(f))   # the bfs_dia fields default to 1
+            solve_rows[key] = dict(zip(SOLVE_FIELDS, vals))
         elif f[0] == "batch" and len(f) == 8:
             batch_row = (f[1], int(f[2]), dict(zip(BATCH_FIELDS, (int(v) for v in f[3:]))))
         else:

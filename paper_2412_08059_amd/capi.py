@@ -34,6 +34,7 @@ MPCG_FLAG_FP32_BREAKDOWN = 1
 MPCG_FLAG_FP32_MAXIT = 2
 MPCG_FLAG_FINAL_RESTARTED = 4
 MPCG_FLAG_KNN_EXACT = 8
+MPCG_FLAG_BFS_DIA = 16
 
 EXPORTED = (
     "mpcg_create", "mpcg_destroy", "mpcg_workspace_size", "mpcg_set_workspace", "mpcg_load_model",
@@ -98,10 +99,10 @@ class mpcg_tuning(ctypes.Structure):
                 ("bfs_persist", ctypes.c_int32), ("batch_group_steps", ctypes.c_int32),
                 ("batch_bfs_rounds", ctypes.c_int32), ("batch_small_cap", ctypes.c_int32),
                 ("batch_small_levels", ctypes.c_int32), ("batch_level_grid", ctypes.c_int32),
-                ("pad_", ctypes.c_int32)]
+                ("bfs_dia", ctypes.c_int32), ("bfs_dia_tiles", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class mpcg_request(ctypes.Structure):

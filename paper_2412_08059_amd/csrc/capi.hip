@@ -52,12 +52,71 @@ void *scratch_of(int dev)
 
 // A stream plus the pinned snapshots and events used to poll the device state
 // from it.
+// A round of bit-parallel level launches captured as a graph, replayed while
+// its arguments stay the same.
+struct DiaGraph {
+    hipStream_t cap = nullptr;   // capture stream (owned)
+    hipGraphExec_t exec = nullptr;
+    BfsBufs key{};               // the arguments it was captured with
+    bool failed = false;         // capture unavailable: plain launches
+    bool suspended = false;      // plain launches (mpcg_solve_noalloc: the graph runtime allocates)
+};
+
 struct Chan {
     hipStream_t s = nullptr;
     DevState *poll[2] = {nullptr, nullptr};
     DevState *sync = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
+    DiaGraph *dia = nullptr;     // owned
 };
+
+bool same_dia_args(const BfsBufs &a, const BfsBufs &b)
+{
+    return a.df0 == b.df0 && a.df1 == b.df1 && a.dv == b.dv && a.dm == b.dm && a.dist == b.dist && a.st == b.st &&
+           a.part_cnt == b.part_cnt && a.part_min == b.part_min &&
+           a.nwords == b.nwords && a.dia_grid == b.dia_grid && std::memcmp(&a.doff, &b.doff, sizeof(DiaOffs)) == 0;
+}
+
+// One round: a replay of the captured graph (captured again when the
+// arguments change), else plain launches.
+void dia_round(const Chan &ch, const BfsBufs &bb)
+{
+    DiaGraph *g = ch.dia;
+    if (g && !g->failed && !g->suspended) {
+        if (!g->exec || !same_dia_args(g->key, bb)) {
+            if (g->exec) (void)hipGraphExecDestroy(g->exec);
+            g->exec = nullptr;
+            hipGraph_t gr = nullptr;
+            bool ok = (g->cap || hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking) == hipSuccess) &&
+                      hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                launch_dia_round(g->cap, bb);
+                ok = hipStreamEndCapture(g->cap, &gr) == hipSuccess && gr != nullptr;
+            }
+            ok = ok && hipGraphInstantiate(&g->exec, gr, nullptr, nullptr, 0) == hipSuccess;
+            if (gr) (void)hipGraphDestroy(gr);
+            (void)hipGetLastError();
+            if (!ok) {
+                g->exec = nullptr;
+                g->failed = true;
+            } else {
+                g->key = bb;
+            }
+        }
+        if (g->exec && hipGraphLaunch(g->exec, ch.s) == hipSuccess) return;
+        (void)hipGetLastError();
+    }
+    launch_dia_round(ch.s, bb);
+}
+
+void dia_graph_free(Chan &ch)
+{
+    if (!ch.dia) return;
+    if (ch.dia->exec) (void)hipGraphExecDestroy(ch.dia->exec);
+    if (ch.dia->cap) (void)hipStreamDestroy(ch.dia->cap);
+    delete ch.dia;
+    ch.dia = nullptr;
+}
 
 struct mpcg_ctx {
     int device = 0;
@@ -136,6 +195,7 @@ Layout plan_layout(int64_t n, int64_t nnz)
     L.z64 = take(sizeof(double) * N);
     L.dg32 = take(sizeof(float) * N);
     L.dg64 = take(sizeof(double) * N);
+    L.dia_bits = take(sizeof(uint32_t) * (((N + 31) / 32 + 2) * (3 + 2 * kDiaMax) + 2 * kDiaRing + 4 * kDiaPartMax));
     L.total = off;
     return L;
 }
@@ -454,6 +514,25 @@ BfsBufs bfs_bufs(const Plan &p, bool shared = false)
     b.small_max = kBfsSmallWork / lanes;
     if (b.small_max < 64) b.small_max = 64;
     if (b.small_max > kBfsSmallCap) b.small_max = kBfsSmallCap;
+    b.dia = 0;   // set by dia_prepare when the pattern qualifies
+    b.nwords = (p.n + 31) / 32;
+    b.dia_grid = 2048;
+    b.doff = DiaOffs{};
+    {
+        const size_t nw = (size_t)b.nwords + 2;
+        uint32_t *bits = p.at<uint32_t>(p.L.dia_bits);
+        b.df0 = bits;
+        b.df1 = bits + nw;
+        b.dv = bits + 2 * nw;
+        b.dm = bits + 3 * nw;   // kDiaMax masks, b.nwords words apart
+        b.draw = bits + 3 * nw + (size_t)kDiaMax * b.nwords;   // and their unaligned row masks
+        int32_t *ring = reinterpret_cast<int32_t *>(b.draw + (size_t)kDiaMax * b.nwords);
+        b.ring_cnt = ring;
+        b.ring_min = ring + kDiaRing;
+        b.part_cnt = ring + 2 * kDiaRing;
+        b.part_min = ring + 2 * kDiaRing + 2 * kDiaPartMax;
+    }
+    b.dia_h = 0;
     b.dist = p.at<int32_t>(p.L.dist);
     b.q0 = p.at<QEnt>(p.L.q0);
     b.q1 = p.at<QEnt>(p.L.q1);
@@ -464,12 +543,84 @@ BfsBufs bfs_bufs(const Plan &p, bool shared = false)
     return b;
 }
 
+// The bit-parallel levels over diagonals replace the queue kernels for a
+// sweep when the tuning asks for them (bfs_dia: 1 on patterns wider than the
+// one-workgroup kernel's narrow-band window, above 2^16 rows; 2 whenever it
+// qualifies) and the pattern lies on at most kDiaMax diagonals.  Returns
+// MPCG_OK whether or not it qualifies (bb->dia says which).
+mpcg_status dia_prepare(const Chan &ch, const Plan &p, BfsBufs *bb)
+{
+    bb->dia = 0;
+    const int mode = p.tune.bfs_dia;
+    // launch k expands level k: at most n levels, kept below the launch index wrap
+    if (mode == 0 || p.n >= (1 << 30) - 64 || (mode == 1 && (p.band <= 8 || p.n < (1 << 16)))) return MPCG_OK;
+    launch_dia_detect(ch.s, *bb);
+    HIPCHK(hipGetLastError());
+    DevState s;
+    mpcg_status rc = read_state(ch, p, &s);
+    if (rc != MPCG_OK) return rc;
+    if (s.dia_over || s.dia_off[0] == 0) return MPCG_OK;
+    bb->doff.nd = 0;
+    for (int t = 0; t < kDiaMax && s.dia_off[t] != 0; ++t) bb->doff.d[bb->doff.nd++] = s.dia_off[t];
+    for (int t = 0; t < kDiaMax; ++t) {
+        if (t >= bb->doff.nd) bb->doff.d[t] = 0;
+        const int64_t m = -(int64_t)bb->doff.d[t];
+        bb->doff.q[t] = (int32_t)(m >= 0 ? m / 32 : -((-m + 31) / 32));   // floor(-d / 32)
+        bb->doff.r[t] = (int32_t)(m - 32 * (int64_t)bb->doff.q[t]);
+    }
+    launch_dia_masks(ch.s, *bb);
+    HIPCHK(hipGetLastError());
+    bb->dia = 1;
+    // temporal tiles: a tile's loaded range (kDiaTileWords) holds its own
+    // words and a halo of h R words on each side; h as large as keeps the
+    // own words at least half the range
+    int R = 1;
+    for (int t = 0; t < bb->doff.nd; ++t) {
+        const int d = bb->doff.d[t] < 0 ? -bb->doff.d[t] : bb->doff.d[t];
+        if (d / 32 + 1 > R) R = d / 32 + 1;
+    }
+    bb->dia_R = R;
+    bb->dia_h = 0;
+    // Tiles pay when a launch forms many levels over several tiles: a tile's
+    // level runs on one CU, the per-level kernel's on the whole grid.
+    if (p.tune.bfs_dia_tiles && bb->doff.nd <= kDiaTileDiags && R <= kDiaPad && bb->nwords > kDiaTileWords) {
+        int h = kDiaTileWords / (4 * R);
+        if (h > kDiaMaxLevels) h = kDiaMaxLevels;
+        if (h >= kDiaTileMinLevels) {
+            bb->dia_h = h;
+            bb->dia_T = kDiaTileWords - 2 * h * R;
+        }
+    }
+    return MPCG_OK;
+}
+
 mpcg_status bfs_run(const Chan &ch, const Plan &p, const BfsBufs &bb, DevState *out)
 {
+    if (bb.dia && bb.dia_h > 0) {   // temporal tiles: dia_h levels per launch
+        const int launches = 64 / bb.dia_h > 1 ? 64 / bb.dia_h : 1;
+        int k = 0;
+        for (int64_t round = 0;; ++round) {
+            k = launch_dia_multi_round(ch.s, bb, launches, k);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(ch.poll[round & 1], p.st, sizeof(DevState), hipMemcpyDeviceToHost, ch.s));
+            HIPCHK(hipEventRecord(ch.ev[round & 1], ch.s));
+            if (round > 0) {
+                HIPCHK(hipEventSynchronize(ch.ev[(round - 1) & 1]));
+                if (ch.poll[(round - 1) & 1]->bfs_done) break;
+                if (ch.poll[(round - 1) & 1]->guard) {
+                    (void)hipStreamSynchronize(ch.s);
+                    return MPCG_EDEVICE;
+                }
+            }
+            if (round > (int64_t)p.n + 4) return MPCG_EDEVICE;
+        }
+        return read_state(ch, p, out);
+    }
     const int levels = 16;
     int k = 0;
     for (int64_t round = 0;; ++round) {
-        k = launch_bfs_round(ch.s, bb, levels, k);
+        if (bb.dia) dia_round(ch, bb);
+        else k = launch_bfs_round(ch.s, bb, levels, k);
         if (k > 0x3fffffff) k &= 1;   // k only selects a parity slot: keep its parity
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(ch.poll[round & 1], p.st, sizeof(DevState), hipMemcpyDeviceToHost, ch.s));
@@ -488,24 +639,37 @@ mpcg_status bfs_run(const Chan &ch, const Plan &p, const BfsBufs &bb, DevState *
 }
 
 // 2BFS per component; fills pdiam, bfs_t, bfs_u, n_components.
-mpcg_status pseudo_diameter_with(const Chan &ch, const Plan &p, const BfsBufs &bb, mpcg_features_t *f)
+mpcg_status pseudo_diameter_with(const Chan &ch, const Plan &p, BfsBufs bb, mpcg_features_t *f, int *dia_used)
 {
     DevState s;
-    launch_bfs_seed_single(ch.s, bb, 0);
-    mpcg_status rc = bfs_run(ch, p, bb, &s);
+    *dia_used = 0;
+    mpcg_status rc = dia_prepare(ch, p, &bb);
+    if (rc != MPCG_OK) return rc;
+    auto seed = [&](int32_t v) {
+        if (bb.dia) {
+            launch_dia_seed(ch.s, bb, v);
+            launch_dia_ring_seed(ch.s, bb, v);
+        } else {
+            launch_bfs_seed_single(ch.s, bb, v);
+        }
+    };
+    seed(0);
+    rc = bfs_run(ch, p, bb, &s);
     if (rc != MPCG_OK) return rc;
     if (s.guard) return MPCG_EDEVICE;
     if (s.bfs_visited == p.n) {
         const int32_t t = s.bfs_far;
-        launch_bfs_seed_single(ch.s, bb, t);
+        seed(t);
         rc = bfs_run(ch, p, bb, &s);
         if (rc != MPCG_OK) return rc;
         f->pdiam = s.bfs_ecc;
         f->bfs_t = t;
         f->bfs_u = s.bfs_far;
         f->n_components = 1;
+        *dia_used = bb.dia;
         return MPCG_OK;
     }
+    bb.dia = 0;   // not connected: components and multi-source sweeps on the queue kernels
     launch_cc(ch.s, bb);
     launch_bfs_seed_roots(ch.s, bb);
     rc = bfs_run(ch, p, bb, &s);
@@ -537,17 +701,20 @@ mpcg_status pseudo_diameter_with(const Chan &ch, const Plan &p, const BfsBufs &b
 // The persistent level kernel bounds its barrier waits; if one ran out (its
 // blocks could not all be resident), the BFS is repeated with one launch per
 // level, which needs no co-residency.
+// *dia_used (if given): both sweeps ran as bit-parallel levels over diagonals.
 mpcg_status pseudo_diameter(const mpcg_ctx *c, const Chan &ch, const Plan &p, mpcg_features_t *f,
-                            bool shared = false)
+                            bool shared = false, int *dia_used = nullptr)
 {
     BfsBufs bb = bfs_bufs(p, shared);
-    mpcg_status rc = pseudo_diameter_with(ch, p, bb, f);
+    int dia = 0;
+    mpcg_status rc = pseudo_diameter_with(ch, p, bb, f, &dia);
     if (rc == MPCG_EDEVICE && bb.persist) {
         HIPCHK(hipStreamSynchronize(ch.s));
         HIPCHK(hipMemsetAsync(&p.st->guard, 0, sizeof(int32_t), ch.s));
         bb.persist = 0;
-        rc = pseudo_diameter_with(ch, p, bb, f);
+        rc = pseudo_diameter_with(ch, p, bb, f, &dia);
     }
+    if (dia_used) *dia_used = dia;
     return rc;
 }
 
@@ -662,6 +829,8 @@ mpcg_status mpcg_create(mpcg_ctx **out, const mpcg_options *opt, void *hip_strea
     c->main.sync = &c->hst[2];
     c->main.ev[0] = c->ev[0];
     c->main.ev[1] = c->ev[1];
+    c->main.dia = new (std::nothrow) DiaGraph();   // null: plain launches
+    c->side.dia = new (std::nothrow) DiaGraph();
     c->side.s = c->side_stream;
     c->side.poll[0] = &c->hst[3];
     c->side.poll[1] = &c->hst[4];
@@ -681,6 +850,8 @@ mpcg_status mpcg_destroy(mpcg_ctx *c)
         (void)hipStreamSynchronize(c->side_stream);
         (void)hipStreamDestroy(c->side_stream);
     }
+    dia_graph_free(c->main);
+    dia_graph_free(c->side);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
     for (auto &e : c->side.ev) if (e) (void)hipEventDestroy(e);
     for (auto &e : c->tm) if (e) (void)hipEventDestroy(e);
@@ -834,11 +1005,12 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
             f.n = n;
             f.m = A->nnz;
             mpcg_status rc_bfs = MPCG_OK;
+            int bfs_dia = 0;
             std::atomic<int> bfs_done{0};
             std::thread bfs_thread([&]() {
                 (void)hipSetDevice(c->device);
                 (void)hipEventRecord(c->tm[1], c->side.s);
-                rc_bfs = pseudo_diameter(c, c->side, p, &f, true);
+                rc_bfs = pseudo_diameter(c, c->side, p, &f, true, &bfs_dia);
                 (void)hipEventRecord(c->tm[2], c->side.s);
                 (void)hipEventSynchronize(c->tm[2]);
                 bfs_done.store(1);
@@ -888,6 +1060,7 @@ mpcg_status mpcg_solve(mpcg_ctx *c, const mpcg_csr *A, const double *b, double *
             S.eps1_class = cls;
             S.eps1_used = e1;
             if (exact) S.flags |= MPCG_FLAG_KNN_EXACT;
+            if (bfs_dia) S.flags |= MPCG_FLAG_BFS_DIA;
             spec_keep = spec64 && cls - 2 == kNumEps - 1;
             if (!broke) {
                 const int ci = cls - 2;
@@ -1023,7 +1196,11 @@ mpcg_status mpcg_solve_noalloc(mpcg_ctx *c, const mpcg_csr *A, const double *b, 
     const size_t ws_bytes = c->ws_bytes;
     c->ws = static_cast<char *>(ptr);
     c->ws_bytes = kNoAllocBytes;
+    if (c->main.dia) c->main.dia->suspended = true;
+    if (c->side.dia) c->side.dia->suspended = true;
     const mpcg_status rc = mpcg_solve(c, A, b, x, eps1, eps2, stats);
+    if (c->main.dia) c->main.dia->suspended = false;
+    if (c->side.dia) c->side.dia->suspended = false;
     c->ws = ws;
     c->ws_bytes = ws_bytes;
     return rc;
@@ -1055,14 +1232,24 @@ mpcg_status mpcg_bfs(mpcg_ctx *c, const mpcg_csr *A, int64_t src, int32_t *dist,
     mpcg_status rc = ingest(c, A, nullptr, false, &p);
     if (rc != MPCG_OK) return rc;
     BfsBufs bb = bfs_bufs(p);
-    launch_bfs_seed_single(c->stream, bb, (int32_t)src);
+    rc = dia_prepare(c->main, p, &bb);
+    if (rc != MPCG_OK) return rc;
+    auto seed = [&]() {
+        if (bb.dia) {
+            launch_dia_seed(c->stream, bb, (int32_t)src);
+            launch_dia_ring_seed(c->stream, bb, (int32_t)src);
+        } else {
+            launch_bfs_seed_single(c->stream, bb, (int32_t)src);
+        }
+    };
+    seed();
     DevState s;
     rc = bfs_run(c->main, p, bb, &s);
     if (rc == MPCG_EDEVICE && bb.persist) {   // see pseudo_diameter
         HIPCHK(hipStreamSynchronize(c->stream));
         HIPCHK(hipMemsetAsync(&p.st->guard, 0, sizeof(int32_t), c->stream));
         bb.persist = 0;
-        launch_bfs_seed_single(c->stream, bb, (int32_t)src);
+        seed();
         rc = bfs_run(c->main, p, bb, &s);
     }
     if (rc != MPCG_OK) return rc;

@@ -1196,4 +1196,519 @@ void launch_comp_final(hipStream_t s, const BfsBufs &b)
     hipLaunchKernelGGL(k_comp_final, dim3(grid), dim3(kBlock), 0, s, b.label, b.best, b.n, b.st);
 }
 
+
+// ------------------------------------- bit-parallel levels over diagonals --
+//
+// When the stored pattern lies on at most kDiaMax diagonals (offsets j - i),
+// as grids and bands do, a level can be formed on bit vectors of all n rows
+// instead of a queue: v is at the next level iff it is unvisited and, for
+// some offset d, u = v - d is in the frontier and row u stores column v.  The
+// masks are kept aligned to v (bit v of mask t: row v - d_t stores column v),
+// so each thread forms one 32-bit word of the next frontier from one mask
+// word and one 32-bit window of the frontier per diagonal (a funnel shift of
+// two words, one word when d_t is a multiple of 32), removes the visited
+// bits, writes the new vertices' distances, and its block adds the count of
+// new vertices and their smallest index to the level state.  Launch k expands
+// level k (a sweep runs one level per launch from k = 0), so the buffers are
+// chosen without reading the state; block 0 keeps the level-state protocol of
+// the queue kernels (retire level k, or finish when it is empty), so the
+// stop, the eccentricity, the farthest vertex (smallest index of the last
+// level) and the distances are the queue kernels' integers.  Once a level is
+// empty every later launch reads an empty frontier and writes nothing but
+// zero words.
+
+// Distinct nonzero offsets of the stored entries into st->dia_off (slots
+// filled from 0; 0 marks an empty slot), or st->dia_over when there are more
+// than kDiaMax.  One row per thread, its entries loaded together.
+__global__ void __launch_bounds__(kBlock)
+k_dia_offsets(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int32_t n, DevState *st)
+{
+    __shared__ int32_t tab[kDiaMax];
+    __shared__ int over;
+    if (threadIdx.x < kDiaMax) tab[threadIdx.x] = 0;
+    if (threadIdx.x == 0) over = 0;
+    __syncthreads();
+    constexpr int kRow = 16;   // entries loaded at once
+    for (int64_t i0 = (int64_t)blockIdx.x * kBlock; i0 < n && !*(volatile int *)&over;
+         i0 += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = i0 + threadIdx.x;
+        if (i >= n) continue;
+        const int b = rp[i], e = rp[i + 1];
+        for (int k0 = b; k0 < e; k0 += kRow) {
+            int c[kRow];
+#pragma unroll
+            for (int j = 0; j < kRow; ++j) c[j] = k0 + j < e ? col[k0 + j] : (int)i;
+#pragma unroll
+            for (int j = 0; j < kRow; ++j) {
+                if ((unsigned)c[j] >= (unsigned)n) continue;   // ignored, as by the queue kernels
+                const int d = c[j] - (int)i;
+                if (d == 0) continue;
+                int t = 0;
+                while (t < kDiaMax) {   // plain reads first: the offset is almost always known
+                    const int v = tab[t];
+                    if (v == d || v == 0) break;
+                    ++t;
+                }
+                if (t < kDiaMax && tab[t] == d) continue;
+                bool put = false;
+                for (t = 0; t < kDiaMax && !put; ++t) {
+                    const int old = atomicCAS(&tab[t], 0, d);
+                    put = old == 0 || old == d;
+                }
+                if (!put) over = 1;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && over) atomicOr(&st->dia_over, 1);
+    if (threadIdx.x < kDiaMax && !over) {
+        const int d = tab[threadIdx.x];
+        if (d != 0) {
+            // most blocks find every offset already there: read the table
+            // first (coherent loads) so that only new offsets take a CAS
+            bool put = false;
+            for (int t = 0; t < kDiaMax && !put; ++t) {
+                const int v = __hip_atomic_load(&st->dia_off[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (v == d) put = true;
+                if (v == 0) break;
+            }
+            for (int t = 0; t < kDiaMax && !put; ++t) {
+                const int old = atomicCAS(&st->dia_off[t], 0, d);
+                put = old == 0 || old == d;
+            }
+            if (!put) atomicOr(&st->dia_over, 1);
+        }
+    }
+}
+
+__global__ void k_dia_reset(DevState *st)
+{
+    if (threadIdx.x < kDiaMax) st->dia_off[threadIdx.x] = 0;
+    if (threadIdx.x == 0) st->dia_over = 0;
+}
+
+void launch_dia_detect(hipStream_t s, const BfsBufs &b)
+{
+    int g = (b.n + kBlock - 1) / kBlock;
+    if (g > 2048) g = 2048;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_dia_reset, dim3(1), dim3(64), 0, s, b.st);
+    hipLaunchKernelGGL(k_dia_offsets, dim3(g), dim3(kBlock), 0, s, b.rp, b.col, b.n, b.st);
+}
+
+// Row masks: bit u of raw[t] is set iff row u stores column u + d_t.  A wave
+// covers 64 rows = two words of each mask and writes them alone.
+__global__ void __launch_bounds__(kBlock)
+k_dia_rowmasks(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int32_t n, int32_t nw,
+               uint32_t *raw, DiaOffs o)
+{
+    const int lane = threadIdx.x & 63;
+    constexpr int kRow = 16;
+    // wave-uniform loop: a wave's lanes share the base row
+    for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < n;
+         base += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = base + lane;
+        uint32_t has = 0u;
+        if (i < n) {
+            const int b = rp[i], e = rp[i + 1];
+            for (int k0 = b; k0 < e; k0 += kRow) {
+                int c[kRow];
+#pragma unroll
+                for (int j = 0; j < kRow; ++j) c[j] = k0 + j < e ? col[k0 + j] : (int)i;
+#pragma unroll
+                for (int j = 0; j < kRow; ++j) {
+                    if ((unsigned)c[j] >= (unsigned)n) continue;   // so every neighbour u + d is a row
+                    const int d = c[j] - (int)i;
+                    for (int t = 0; t < o.nd; ++t)
+                        if (o.d[t] == d) has |= 1u << t;
+                }
+            }
+        }
+        const int w0 = (int)(base >> 5);
+        for (int t = 0; t < o.nd; ++t) {
+            const unsigned long long m = __ballot((has >> t) & 1u);
+            if (lane == 0) {
+                raw[(size_t)t * nw + w0] = (uint32_t)(m & 0xffffffffull);
+                if (w0 + 1 < nw) raw[(size_t)t * nw + w0 + 1] = (uint32_t)(m >> 32);
+            }
+        }
+    }
+}
+
+// 32 bits of bit vector B starting at bit position p (bits outside [0, 32 nw) read as 0).
+__device__ inline uint32_t dia_window(const uint32_t *B, int64_t p, int32_t nw)
+{
+    const int64_t q = p >> 5;   // floor, also for p < 0
+    const int r = (int)(p & 31);
+    const uint32_t lo = (q >= 0 && q < nw) ? B[q] : 0u;
+    if (r == 0) return lo;
+    const uint32_t hi = (q + 1 >= 0 && q + 1 < nw) ? B[q + 1] : 0u;
+    return (lo >> r) | (hi << (32 - r));
+}
+
+// The window of diagonal t at word w starts at bit 32 w - d_t = 32 (w + q_t) + r_t.
+// F holds the words [lo, hi) of the bit vector (words outside [0, nw) read
+// as 0; callers keep the words a window needs inside [lo, hi)).  Both words
+// are loaded unconditionally from clamped indices, so a word's windows issue
+// their loads together.
+__device__ inline uint32_t dia_win(const uint32_t *F, int lo, int hi, int w, int qt, int rt, int32_t nw)
+{
+    const int q = w + qt;
+    const int i0 = q < lo ? lo : (q >= hi ? hi - 1 : q);
+    const int i1 = q + 1 < lo ? lo : (q + 1 >= hi ? hi - 1 : q + 1);
+    uint32_t w0 = F[i0 - lo], w1 = F[i1 - lo];
+    w0 = (q >= 0 && q < nw) ? w0 : 0u;
+    w1 = (q + 1 >= 0 && q + 1 < nw) ? w1 : 0u;
+    return __builtin_amdgcn_alignbit(w1, w0, rt);
+}
+
+// Aligned masks: word w of dm[t] = bits v in [32 w, 32 w + 32) of "row v - d_t
+// stores column v" = the 32-bit window of raw[t] at 32 w - d_t.
+__global__ void __launch_bounds__(kBlock)
+k_dia_align(const uint32_t *__restrict__ raw, uint32_t *dm, int32_t nw, DiaOffs o)
+{
+    for (int w = blockIdx.x * kBlock + threadIdx.x; w < nw; w += gridDim.x * kBlock)
+        for (int t = 0; t < o.nd; ++t)
+            dm[(size_t)t * nw + w] = dia_window(raw + (size_t)t * nw, 32 * (int64_t)w - o.d[t], nw);
+}
+
+void launch_dia_masks(hipStream_t s, const BfsBufs &b)
+{
+    uint32_t *raw = b.draw;
+    int g = (b.n + kBlock - 1) / kBlock;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_dia_rowmasks, dim3(g), dim3(kBlock), 0, s, b.rp, b.col, b.n, b.nwords, raw, b.doff);
+    int ga = (b.nwords + kBlock - 1) / kBlock;
+    if (ga > 4096) ga = 4096;
+    hipLaunchKernelGGL(k_dia_align, dim3(ga), dim3(kBlock), 0, s, raw, b.dm, b.nwords, b.doff);
+}
+
+// Both frontier buffers and the visited bits start empty.  The per-level
+// kernel then writes only the words that gain vertices, so a buffer can keep
+// bits of the frontier two (four, ...) levels back; those vertices are
+// visited, and so are all their neighbours (a BFS neighbour is at most one
+// level further), so the extra bits add only visited vertices, which the
+// level removes -- the levels are exact, and a level dirties only the words
+// of its own frontier.
+__global__ void k_dia_clear(uint32_t *f0, uint32_t *f1, uint32_t *v, int32_t nw)
+{
+    for (int w = blockIdx.x * kBlock + threadIdx.x; w < nw; w += gridDim.x * kBlock) {
+        f0[w] = 0u;
+        f1[w] = 0u;
+        v[w] = 0u;
+    }
+}
+
+__global__ void k_dia_seed(uint32_t *f0, uint32_t *v, int32_t *dist, int32_t src, int32_t *pcnt, int32_t *pmin,
+                           DevState *st)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        f0[src >> 5] = 1u << (src & 31);
+        v[src >> 5] = 1u << (src & 31);
+        dist[src] = 0;
+        bfs_start(st, 1, src);
+        st->dia_base = 0;
+    }
+    // level 0's per-block partials: the source alone
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kDiaPartMax; i += gridDim.x * blockDim.x) {
+        pcnt[i] = i == 0 ? 1 : 0;
+        pmin[i] = i == 0 ? src : kIntMax;
+    }
+}
+
+void launch_dia_seed(hipStream_t s, const BfsBufs &b, int32_t src)
+{
+    int g = (b.nwords + kBlock - 1) / kBlock;
+    if (g > 1024) g = 1024;
+    launch_fill_i32(s, b.dist, b.n, -1);
+    hipLaunchKernelGGL(k_dia_clear, dim3(g), dim3(kBlock), 0, s, b.df0, b.df1, b.dv, b.nwords);
+    hipLaunchKernelGGL(k_dia_seed, dim3(1), dim3(kBlock), 0, s, b.df0, b.dv, b.dist, src, b.part_cnt, b.part_min,
+                       b.st);
+}
+
+// Launch j of a round expands level L = st->dia_base + j; rounds are
+// kDiaRound launches, and k_dia_round_end (the round's last launch) moves
+// the base on, so every launch of a round has fixed arguments (the round can
+// be replayed as a captured graph) and its frontier parity is j & 1.  Each
+// block stores its count of new vertices and their smallest index in slot
+// blockIdx.x of the partials of parity (L + 1) & 1 -- plain stores, no
+// same-address atomics across the grid; wave 0 of block 0 in the next launch
+// sums them (all loads at once) and retires the level: the level-state
+// protocol of the queue kernels, with the sums in place of the counters.
+template <int ND>
+__global__ void __launch_bounds__(kBlock)
+k_dia_level(const uint32_t *__restrict__ fc, uint32_t *__restrict__ fn, uint32_t *dv, const uint32_t *__restrict__ dm,
+            int32_t *dist, int32_t nw, int32_t j, DiaOffs o, const int32_t *__restrict__ pc_cur,
+            const int32_t *__restrict__ pm_cur, int32_t *pc_next, int32_t *pm_next, DevState *st)
+{
+    __shared__ int s_cnt[kBlock / 64], s_min[kBlock / 64];
+    const int L = st->dia_base + j;   // needed only for the distances and the retirement
+    if (blockIdx.x == 0 && threadIdx.x < 64) {
+        // level L's size and smallest vertex from the previous launch's
+        // partials (the seed's for level 0), then its retirement
+        const int lane = threadIdx.x;
+        const int done = st->bfs_done;
+        int c = 0, m = kIntMax;
+        for (int i = lane; i < (int)gridDim.x; i += 64) {
+            c += pc_cur[i];
+            m = m < pm_cur[i] ? m : pm_cur[i];
+        }
+        c = wave_sum_i(c);
+        m = wave_min_i(m);
+        if (lane == 0 && !done) {
+            if (c == 0) {
+                st->bfs_done = 1;   // level L is empty: L - 1 was the last
+                st->bfs_ecc = L - 1;
+                st->bfs_far = st->bfs_min[(L - 1) & 3];
+            } else {
+                st->bfs_visited += c;
+                st->bfs_min[L & 3] = m;
+                st->bfs_lv[(L + 1) & 1] = L + 1;
+            }
+        }
+    }
+    int cnt = 0, mn = kIntMax;
+    for (int w = blockIdx.x * kBlock + threadIdx.x; w < nw; w += gridDim.x * kBlock) {
+        const uint32_t vis = dv[w];
+        uint32_t nb = 0u;
+#pragma unroll
+        for (int t = 0; t < ND; ++t) nb |= dia_win(fc, 0, nw, w, o.q[t], o.r[t], nw) & dm[(size_t)t * nw + w];
+        nb &= ~vis;
+        if (nb) {   // words without new vertices keep older frontiers' bits: see k_dia_clear
+            fn[w] = nb;
+            dv[w] = vis | nb;
+            cnt += __popc(nb);
+            const int v0 = 32 * w + __ffs(nb) - 1;
+            mn = mn < v0 ? mn : v0;
+            for (uint32_t bb = nb; bb; bb &= bb - 1u) dist[32 * w + __ffs(bb) - 1] = L + 1;
+        }
+    }
+    cnt = wave_sum_i(cnt);
+    mn = wave_min_i(mn);
+    if ((threadIdx.x & 63) == 0) {
+        s_cnt[threadIdx.x >> 6] = cnt;
+        s_min[threadIdx.x >> 6] = mn;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int c = 0, m = kIntMax;
+        for (int i = 0; i < kBlock / 64; ++i) {
+            c += s_cnt[i];
+            m = m < s_min[i] ? m : s_min[i];
+        }
+        pc_next[blockIdx.x] = c;
+        pm_next[blockIdx.x] = m;
+    }
+}
+
+__global__ void k_dia_round_end(DevState *st)
+{
+    if (threadIdx.x == 0) st->dia_base += kDiaRound;
+}
+
+#define MPCG_DIA_CASES(X)                                                                                           \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
+void launch_dia_round(hipStream_t s, const BfsBufs &b)
+{
+    int g = (b.nwords + kBlock - 1) / kBlock;   // one word per thread
+    if (g > b.dia_grid) g = b.dia_grid;
+    if (g > kDiaPartMax) g = kDiaPartMax;
+    if (g < 1) g = 1;
+    for (int j = 0; j < kDiaRound; ++j) {
+        const uint32_t *fc = (j & 1) ? b.df1 : b.df0;
+        uint32_t *fn = (j & 1) ? b.df0 : b.df1;
+        const int32_t *pcc = b.part_cnt + (j & 1) * kDiaPartMax, *pmc = b.part_min + (j & 1) * kDiaPartMax;
+        int32_t *pcn = b.part_cnt + ((j + 1) & 1) * kDiaPartMax, *pmn = b.part_min + ((j + 1) & 1) * kDiaPartMax;
+        switch (b.doff.nd) {
+#define X(N)                                                                                                        \
+    case N:                                                                                                         \
+        hipLaunchKernelGGL(k_dia_level<N>, dim3(g), dim3(kBlock), 0, s, fc, fn, b.dv, b.dm, b.dist, b.nwords, j,    \
+                           b.doff, pcc, pmc, pcn, pmn, b.st);                                                       \
+        break;
+            MPCG_DIA_CASES(X)
+#undef X
+        default: break;
+        }
+    }
+    hipLaunchKernelGGL(k_dia_round_end, dim3(1), dim3(64), 0, s, b.st);
+}
+
+// ------------------------------- several levels per launch: temporal tiles --
+//
+// A block owns the words [a, e) of a tile and loads the frontier of level L0
+// over [a - hR, e + hR) (R: the most words a diagonal's window reaches, so a
+// level's words need the previous level's within R of them).  It then forms
+// h levels in LDS, each over a range R words narrower on both sides than the
+// last, so after h levels its own words are exact; the halo work is redone by
+// the neighbouring blocks.  Frontier and visited bits of the range live in
+// LDS, the masks of a thread's words in registers (patterns with at most
+// kDiaTileDiags diagonals).  Each level's count and smallest new vertex (own words only) go
+// to a ring of kDiaRing slots indexed by level; block 0 retires the previous
+// launch's levels at the start (first empty level: finish) and clears the
+// slots of the next launch's levels.  The distances, the stop, the
+// eccentricity and the farthest vertex are the per-level kernels' integers.
+
+
+template <int ND>
+__global__ void __launch_bounds__(kDiaTileThreads)
+k_dia_multi(const uint32_t *__restrict__ fin, uint32_t *__restrict__ fout, uint32_t *dv,
+            const uint32_t *__restrict__ dm, int32_t *dist, int32_t nw, int32_t L0, int32_t h, int32_t T, int32_t R,
+            DiaOffs o, int32_t *ring_cnt, int32_t *ring_min, DevState *st)
+{
+    // F: frontier bits of the loaded range at LDS index kDiaPad + (w - lo),
+    // zero outside it, so that a window needs no bounds test (words outside
+    // [0, nw) fall in the zero parts; R <= kDiaPad)
+    constexpr int kF = kDiaTileWords + 2 * kDiaPad;
+    __shared__ uint32_t F[2][kF];
+    __shared__ uint32_t V[kDiaTileWords];
+    __shared__ int s_cnt[kDiaMaxLevels], s_min[kDiaMaxLevels];
+    const int tid = threadIdx.x;
+    if (blockIdx.x == 0 && tid < 64) {
+        // Wave 0 of block 0 retires the previous launch's levels (level 0 at
+        // the first launch), lane l taking level first + l, all loads at once.
+        const int done = st->bfs_done;
+        const int first = L0 - h + 1 < 0 ? 0 : L0 - h + 1;
+        const int nl = L0 - first + 1;
+        const int lam = first + tid;
+        int c = 1, mprev = kIntMax;
+        if (tid < nl) {
+            c = ring_cnt[lam % kDiaRing];
+            if (lam > 0) mprev = ring_min[(lam - 1) % kDiaRing];
+        }
+        const unsigned long long zero = __ballot(tid < nl && c == 0);
+        const int z = zero ? __ffsll((long long)zero) - 1 : nl;   // first empty level's lane
+        const int vis = wave_sum_i(tid < z ? c : 0);
+        if (!done) {
+            if (tid == 0) st->bfs_visited += vis;
+            if (zero && tid == z) {
+                st->bfs_ecc = lam - 1;
+                st->bfs_far = mprev;
+                st->bfs_done = 1;
+            }
+            if (tid < h) {   // the slots of the next launch's levels
+                ring_cnt[(L0 + h + 1 + tid) % kDiaRing] = 0;
+                ring_min[(L0 + h + 1 + tid) % kDiaRing] = kIntMax;
+            }
+        }
+    }
+    if (tid < kDiaMaxLevels) {
+        s_cnt[tid] = 0;
+        s_min[tid] = kIntMax;
+    }
+    const int a = blockIdx.x * T;
+    const int e = a + T < nw ? a + T : nw;
+    const int lo = a - h * R > 0 ? a - h * R : 0;
+    const int hi = e + h * R < nw ? e + h * R : nw;
+    for (int i = tid; i < kF; i += kDiaTileThreads) {
+        if (i < kDiaPad || i >= kDiaPad + (hi - lo)) F[0][i] = 0u;
+        F[1][i] = 0u;
+    }
+    // thread-owned words w = lo + tid + j kDiaTileThreads; their masks stay in
+    // registers for the launch (all loads issued together)
+    uint32_t mr[kDiaPerThread][ND];
+#pragma unroll
+    for (int j = 0; j < kDiaPerThread; ++j) {
+        const int w = lo + tid + j * kDiaTileThreads;
+        const int wc = w < hi ? w : hi - 1;
+#pragma unroll
+        for (int t = 0; t < ND; ++t) mr[j][t] = dm[(size_t)t * nw + wc];
+        if (w < hi) {
+            F[0][kDiaPad + w - lo] = fin[w];
+            V[w - lo] = dv[w];
+        }
+    }
+    __syncthreads();
+    for (int l = 0; l < h; ++l) {
+        const uint32_t *cur = F[l & 1];
+        uint32_t *nxt = F[(l + 1) & 1];
+        const int shrink = (h - l - 1) * R;
+        const int vl = a - shrink > lo ? a - shrink : lo;
+        const int vh = e + shrink < hi ? e + shrink : hi;
+        int cnt = 0, mn = kIntMax;
+#pragma unroll
+        for (int j = 0; j < kDiaPerThread; ++j) {
+            int w = lo + tid + j * kDiaTileThreads;
+            // opaque per level: the window indices derived from w are formed
+            // here, not hoisted out of the level loop (96 live registers)
+            asm volatile("" : "+v"(w));
+            if (w >= vl && w < vh) {
+                const int iw = kDiaPad + w - lo;
+                uint32_t nb = 0u;
+#pragma unroll
+                for (int t = 0; t < ND; ++t) {
+                    const int i0 = iw + o.q[t];
+                    uint32_t win = cur[i0];
+                    if (o.r[t]) win = __builtin_amdgcn_alignbit(cur[i0 + 1], win, o.r[t]);
+                    nb |= win & mr[j][t];
+                }
+                const uint32_t vis = V[w - lo];
+                nb &= ~vis;
+                nxt[iw] = nb;
+                if (nb) {
+                    V[w - lo] = vis | nb;
+                    if (w >= a && w < e) {
+                        cnt += __popc(nb);
+                        const int v0 = 32 * w + __ffs(nb) - 1;
+                        mn = mn < v0 ? mn : v0;
+                        for (uint32_t bb = nb; bb; bb &= bb - 1u) dist[32 * w + __ffs(bb) - 1] = L0 + l + 1;
+                    }
+                }
+            }
+        }
+        cnt = wave_sum_i(cnt);
+        mn = wave_min_i(mn);
+        if ((tid & 63) == 0 && cnt) {
+            atomicAdd(&s_cnt[l], cnt);
+            atomicMin(&s_min[l], mn);
+        }
+        __syncthreads();
+    }
+    const uint32_t *fl = F[h & 1];
+    for (int w = a + tid; w < e; w += kDiaTileThreads) {   // changed words only: see k_dia_clear
+        const uint32_t fw = fl[kDiaPad + w - lo], vw = V[w - lo];
+        if (fw) fout[w] = fw;
+        if (vw != dv[w]) dv[w] = vw;   // only this block writes its own words
+    }
+    if (tid < h && s_cnt[tid]) {
+        atomicAdd(&ring_cnt[(L0 + tid + 1) % kDiaRing], s_cnt[tid]);
+        atomicMin(&ring_min[(L0 + tid + 1) % kDiaRing], s_min[tid]);
+    }
+}
+
+__global__ void k_dia_ring_seed(int32_t *ring_cnt, int32_t *ring_min, int32_t src)
+{
+    const int t = threadIdx.x;
+    if (t < kDiaRing) {
+        ring_cnt[t] = t == 0 ? 1 : 0;
+        ring_min[t] = t == 0 ? src : kIntMax;
+    }
+}
+
+void launch_dia_ring_seed(hipStream_t s, const BfsBufs &b, int32_t src)
+{
+    hipLaunchKernelGGL(k_dia_ring_seed, dim3(1), dim3(kDiaRing), 0, s, b.ring_cnt, b.ring_min, src);
+}
+
+int launch_dia_multi_round(hipStream_t s, const BfsBufs &b, int launches, int k)
+{
+    const int g = (b.nwords + b.dia_T - 1) / b.dia_T;
+    for (int l = 0; l < launches; ++l, ++k) {
+        const uint32_t *fin = (k & 1) ? b.df1 : b.df0;
+        uint32_t *fout = (k & 1) ? b.df0 : b.df1;
+        switch (b.doff.nd) {
+#define X(N)                                                                                                        \
+    case N:                                                                                                         \
+        hipLaunchKernelGGL(k_dia_multi<N>, dim3(g), dim3(kDiaTileThreads), 0, s, fin, fout, b.dv, b.dm, b.dist,     \
+                           b.nwords, k * b.dia_h, b.dia_h, b.dia_T, b.dia_R, b.doff, b.ring_cnt, b.ring_min, b.st); \
+        break;
+            X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
+#undef X
+        default: break;
+        }
+    }
+    return k;
+}
+
 }  // namespace mpcg

@@ -21,6 +21,17 @@ constexpr int kBfsSmallCap = 2048;    // frontier size handled by the one-workgr
 constexpr int kBfsSmallThreads = 1024;
 constexpr int kBfsSmallWork = 2048;   // (vertex, lane) items per level in the one-workgroup kernel
 constexpr int kBfsLevelBlocks = 128;  // level-kernel blocks (measured best on the 128^3 grid)
+constexpr int kDiaMax = 16;           // largest number of diagonals the bit-parallel 2BFS handles
+constexpr int kDiaRound = 16;         // level launches per round (a multiple of 4: the level rings)
+constexpr int kDiaPartMax = 2048;     // largest grid of the per-level kernel (per-block partials)
+constexpr int kDiaTileThreads = 1024; // threads of a temporal-tile block
+constexpr int kDiaPerThread = 8;      // words of a tile's loaded range per thread
+constexpr int kDiaTileWords = kDiaTileThreads * kDiaPerThread;   // loaded range (LDS: 2 padded copies + visited)
+constexpr int kDiaTileDiags = 8;      // most diagonals of a temporal-tile pattern (masks in registers)
+constexpr int kDiaPad = 1024;         // zero words beside a tile's LDS range: largest halo per level R
+constexpr int kDiaMaxLevels = 16;     // levels per temporal-tile launch
+constexpr int kDiaTileMinLevels = 8;  // fewer levels per launch: the per-level kernel is faster
+constexpr int kDiaRing = 64;          // level-count ring (>= 3 launches of levels)
 constexpr int kNumXcd = 8;            // MI355X: blocks are dispatched round-robin over 8 XCDs
 constexpr int kMaxGrid = 2048;        // largest grid of a kernel that writes reduction partials
 constexpr int kUpdateGrid = 1024;     // blocks of a CG update launch: fewer partials for the next product
@@ -86,6 +97,12 @@ struct alignas(256) DevState {
     double spec_thr[6];
     double cross_gamma[6];
     int64_t spare_i64;    // host-side scratch in the pinned mirror
+    // Diagonal structure of the pattern (k_dia_offsets): the distinct nonzero
+    // offsets j - i of the stored entries, if there are at most kDiaMax
+    // (slots filled from 0, 0 = empty; dia_over: more than kDiaMax).
+    int32_t dia_base;     // first level of the current round of bit-parallel level launches
+    int32_t dia_over;
+    int32_t dia_off[16];
 };
 
 // Byte offsets of every region inside the caller's arena.
@@ -97,6 +114,7 @@ struct Layout {
     size_t sell_wid, sell_off, sell_col, sell_v64, sell_v32, ingest_blk;
     size_t snap32;      // kNumEps copies of x~ taken at the candidate thresholds
     size_t z32, z64, dg32, dg64;   // Jacobi: M^-1 r and diag(A) in both precisions
+    size_t dia_bits;    // bit-parallel 2BFS: frontiers F0, F1, visited V, kDiaMax aligned and kDiaMax row masks
     int64_t sell_cap;   // padded entries the SELL arrays can hold
     size_t total;
     int64_t n, nnz;
@@ -244,6 +262,13 @@ struct QEnt {
     int32_t b, e;
 };
 
+// The diagonals of a pattern (offsets j - i, nd of them), passed by value.
+struct DiaOffs {
+    int32_t d[kDiaMax];
+    int32_t q[kDiaMax], r[kDiaMax];   // -d = 32 q + r, 0 <= r < 32 (window word and shift)
+    int32_t nd;
+};
+
 struct BfsBufs {
     const int32_t *rp, *col;
     int32_t n;
@@ -257,7 +282,36 @@ struct BfsBufs {
     int32_t grid;       // blocks of the level kernel
     int32_t precheck;   // read the distance before claiming a vertex
     int32_t persist;    // large levels in one persistent launch (grid barrier) instead of one launch each
+    // bit-parallel levels over the diagonals (when the pattern has at most
+    // kDiaMax of them): frontier bits of even / odd levels, visited bits, and
+    // per diagonal t the rows v that row v - d_t reaches (aligned masks)
+    int32_t dia;        // 1: the sweeps run as bit-parallel levels
+    int32_t nwords;     // 32-bit words per bit vector
+    int32_t dia_grid;   // largest grid of the level kernel
+    DiaOffs doff;       // the diagonals (host copy of st->dia_off)
+    uint32_t *df0, *df1, *dv, *dm, *draw;   // dm, draw: kDiaMax masks of nwords words each
+    // temporal tiles: dia_h levels per launch, dia_T words per block, halo
+    // dia_R words per level (dia_h = 0: one level per launch)
+    int32_t dia_h, dia_T, dia_R;
+    int32_t *ring_cnt, *ring_min;   // kDiaRing slots each
+    int32_t *part_cnt, *part_min;   // per-level kernel: 2 x kDiaPartMax per-block partials each
 };
+// Diagonal structure: st->dia_over / dia_off from the CSR pattern (cleared
+// first); then, with b.doff filled from them, the masks.  Columns outside
+// [0, n) are ignored.
+void launch_dia_detect(hipStream_t s, const BfsBufs &b);
+void launch_dia_masks(hipStream_t s, const BfsBufs &b);
+// Single-source sweep with bit-parallel levels: seed, then rounds of
+// kDiaRound level launches and one that moves the round's base level on;
+// every launch of a round has fixed arguments (the queue kernels'
+// level-state protocol).
+void launch_dia_seed(hipStream_t s, const BfsBufs &b, int32_t src);
+void launch_dia_round(hipStream_t s, const BfsBufs &b);
+// Temporal tiles: the ring's seed (after launch_dia_seed), then rounds of
+// `launches` launches of dia_h levels each; launch k expands levels
+// k dia_h .. (k + 1) dia_h - 1.
+void launch_dia_ring_seed(hipStream_t s, const BfsBufs &b, int32_t src);
+int launch_dia_multi_round(hipStream_t s, const BfsBufs &b, int launches, int k);
 void launch_bfs_seed_single(hipStream_t s, const BfsBufs &b, int32_t src);
 // Enqueues one round (the one-workgroup kernel, then `levels` level kernels)
 // with launch indices k, k + 1, ...; returns the next launch index.

@@ -3,7 +3,7 @@
 // File format (text, '#' starts a comment line):
 //   mpcg-tune 1
 //   solve <arch> <cu> <idx16> <lenlog> <nlog> <sell_batch> <sell_whole_batch> <sell_split> <bfs_grid>
-//         <bfs_grid_shared> <bfs_persist>
+//         <bfs_grid_shared> <bfs_persist> [<bfs_dia> [<bfs_dia_tiles>]]
 //   batch <arch> <cu> <group_steps> <bfs_rounds> <small_cap> <small_levels> <level_grid>
 
 #include "tune.hpp"
@@ -29,6 +29,8 @@ mpcg_tuning tune_defaults()
     t.batch_small_cap = 512;
     t.batch_small_levels = 64;
     t.batch_level_grid = 1024;
+    t.bfs_dia = 1;
+    t.bfs_dia_tiles = 1;
     return t;
 }
 
@@ -40,7 +42,8 @@ bool tune_valid(const mpcg_tuning &t)
            t.batch_group_steps >= 1 && t.batch_group_steps <= 64 && t.batch_bfs_rounds >= 1 &&
            t.batch_bfs_rounds <= 64 && t.batch_small_cap >= 1 && t.batch_small_cap <= 2048 &&
            t.batch_small_levels >= 1 && t.batch_small_levels <= 4096 && t.batch_level_grid >= 1 &&
-           t.batch_level_grid <= 65536;
+           t.batch_level_grid <= 65536 && t.bfs_dia >= 0 && t.bfs_dia <= 2 &&
+           (t.bfs_dia_tiles == 0 || t.bfs_dia_tiles == 1);
 }
 
 int32_t tune_lenlog(int64_t n, int64_t nnz)
@@ -80,11 +83,12 @@ int tune_load(const char *path, TuneTable *out)
         if (!std::strcmp(kind, "solve")) {
             TuneEntry e;
             e.t = tune_defaults();
-            const int got = std::sscanf(p, "%*s %*s %d %d %d %d %d %d %d %d %d %d", &e.key.cu, &e.key.idx16,
+            const int got = std::sscanf(p, "%*s %*s %d %d %d %d %d %d %d %d %d %d %d %d", &e.key.cu, &e.key.idx16,
                                         &e.key.lenlog, &e.key.nlog, &e.t.sell_batch, &e.t.sell_whole_batch,
-                                        &e.t.sell_split, &e.t.bfs_grid, &e.t.bfs_grid_shared, &e.t.bfs_persist);
+                                        &e.t.sell_split, &e.t.bfs_grid, &e.t.bfs_grid_shared, &e.t.bfs_persist,
+                                        &e.t.bfs_dia, &e.t.bfs_dia_tiles);
             e.key.arch = arch;
-            ok = got == 10 && tune_valid(e.t);
+            ok = got >= 10 && got <= 12 && tune_valid(e.t);   // the bfs_dia fields may be absent (defaults)
             if (ok) tb.solve.push_back(e);
         } else if (!std::strcmp(kind, "batch")) {
             mpcg_tuning t = tune_defaults();
@@ -132,6 +136,8 @@ mpcg_tuning tune_lookup(const TuneTable &tb, const std::string &arch, int32_t cu
         t.bfs_grid = best->t.bfs_grid;
         t.bfs_grid_shared = best->t.bfs_grid_shared;
         t.bfs_persist = best->t.bfs_persist;
+        t.bfs_dia = best->t.bfs_dia;
+        t.bfs_dia_tiles = best->t.bfs_dia_tiles;
     }
     return t;
 }

@@ -66,9 +66,19 @@ def solver_persist(torch_mod):
     s.close()
 
 
-@pytest.fixture(params=["level", "persist"])
-def bfs_solver(request, solver, solver_persist):
-    return solver if request.param == "level" else solver_persist
+@pytest.fixture(scope="module")
+def solver_dia(torch_mod):
+    """A context whose 2BFS sweeps run as bit-parallel levels over the
+    diagonals whenever the pattern lies on at most 16 of them."""
+    from paper_2412_08059_amd import Solver
+    s = Solver(2_200_000, 17_500_000, model=TEST_MODEL, tuning={"bfs_dia": 2})
+    yield s
+    s.close()
+
+
+@pytest.fixture(params=["level", "persist", "dia"])
+def bfs_solver(request, solver, solver_persist, solver_dia):
+    return {"level": solver, "persist": solver_persist, "dia": solver_dia}[request.param]
 
 
 def dev(a, **kw):
