@@ -180,6 +180,19 @@ def tune_solve(quick: bool = False, log=print):
                 bfs[(grid, persist)] = statistics.median(ts)
         g, persist = choose_min(bfs)
         base.update(bfs_grid=g, bfs_persist=persist)
+        dia = {}   # the 2BFS on diagonals (where the pattern has at most 16), one launch or tiles per level
+        for cand in ((0, 1), (1, 0), (1, 1)):
+            capi.mpcg_set_tuning(sv.ctx, dict(base, bfs_dia=cand[0], bfs_dia_tiles=cand[1]))
+            ts = []
+            for _ in range(2 if quick else 3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sv.bfs(A, 0)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            dia[cand] = statistics.median(ts)
+        d, dt = choose_min(dia)
+        base.update(bfs_dia=d, bfs_dia_tiles=dt)
         shared = {}
         for gs in (32, 64, 128):
             capi.mpcg_set_tuning(sv.ctx, dict(base, bfs_grid_shared=gs))

@@ -516,7 +516,7 @@ BfsBufs bfs_bufs(const Plan &p, bool shared = false)
     if (b.small_max > kBfsSmallCap) b.small_max = kBfsSmallCap;
     b.dia = 0;   // set by dia_prepare when the pattern qualifies
     b.nwords = (p.n + 31) / 32;
-    b.dia_grid = 2048;
+    b.dia_grid = kDiaPartMax;   // one word per thread: the level is latency-bound per word
     b.doff = DiaOffs{};
     {
         const size_t nw = (size_t)b.nwords + 2;

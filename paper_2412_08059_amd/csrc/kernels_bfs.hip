@@ -1468,8 +1468,14 @@ k_dia_level(const uint32_t *__restrict__ fc, uint32_t *__restrict__ fn, uint32_t
             }
         }
     }
+    // XCD-aware placement: the blocks of one XCD (blockIdx.x mod kNumXcd)
+    // take consecutive 256-word chunks, so the frontier words a window reads
+    // a few chunks away were mostly written on the same XCD
+    const int G = gridDim.x, b = blockIdx.x;
+    const int nx = G < kNumXcd ? G : kNumXcd, xq = G / nx, xr = G % nx, x = b % nx;
+    const int chunk = x * xq + (x < xr ? x : xr) + b / nx;
     int cnt = 0, mn = kIntMax;
-    for (int w = blockIdx.x * kBlock + threadIdx.x; w < nw; w += gridDim.x * kBlock) {
+    for (int w = chunk * kBlock + threadIdx.x; w < nw; w += G * kBlock) {
         const uint32_t vis = dv[w];
         uint32_t nb = 0u;
 #pragma unroll
