@@ -168,3 +168,28 @@ def test_localization_brute_force():
         nn = sorted(range(40), key=lambda i: (d[i], i))[:k]
         tot += sum(ltr[i] == lq for i in nn) / k
     assert abs(got - tot / 15 * 100) < 1e-9
+
+
+def test_family_eval_formulas_agree_with_the_oracle_cost_model():
+    """family_eval (the package's experiment driver) keeps its own copies of
+    eq. 4, the class rule, eq. 27 and eq. 26; the oracle's cost module is the
+    pinned one.  Both must give the same numbers on random sweeps."""
+    from oracle import cost as C
+    rng = np.random.default_rng(17)
+    n1 = rng.integers(1, 2000, size=(50, 6)).astype(np.float64)
+    n2 = rng.integers(1, 2000, size=(50, 6)).astype(np.float64)
+    n1[3] = n1[3, 0]; n2[3] = n2[3, 0]            # all six classes tied: the larger eps1 wins
+    ndp = rng.integers(500, 3000, size=50).astype(np.float64)
+    omega = rng.uniform(0.2, 1.0, size=50)
+    for w in (1 / 3, omega):
+        I = FE.costs(n1, n2, w)
+        wr = np.broadcast_to(np.asarray(w, dtype=np.float64), (50,))
+        for i in range(50):
+            for t in range(6):
+                assert I[i, t] == C.cost_I(n1[i, t], n2[i, t], wr[i])
+            assert FE.optimal_class(I)[i] == C.label_from_sweep(n1[i], n2[i], wr[i])
+        sel = FE.optimal_class(I) - 2
+        Isel = I[np.arange(50), sel]
+        assert abs(FE.efficiency(Isel, ndp) - C.overall_efficiency(list(Isel), list(ndp))) <= 1e-12
+    for n, k_cg, k in ((1000, 300.0, 5), (12345, 77.5, 20)):
+        assert abs(FE.training_size(n, k_cg, k, c=0.1) - C.ns_bound(n, 0.1 * n, k_cg, k)) <= 1e-9 * n * k_cg
