@@ -82,6 +82,9 @@ CASES = {
     "poisson2d_700": lambda: W.poisson2d(700),
     "grid3d_40x40x200": lambda: _diagonals(320_000, [1, 40, 1600], seed=4),
     "holes_600001": lambda: _diagonals(600_001, [1, 3, 130, 4000], keep=0.7, seed=5),
+    # halo of 256 words per level (8 levels per launch) and of 257 (one launch per level)
+    "reach_256_400000": lambda: _diagonals(400_000, [1, 8160], seed=6),
+    "reach_257_400000": lambda: _diagonals(400_000, [1, 8192], seed=7),
     "diagonal_only_97": lambda: W.CSR.from_scipy(sp.identity(97, format="csr") * 3.0),
 }
 

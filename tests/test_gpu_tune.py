@@ -72,10 +72,12 @@ def test_every_bfs_candidate_gives_the_same_features(torch_mod, name):
     try:
         for grid in (1, 64, 256):
             for persist in (0, 1):
-                s.set_tuning(dict(bfs_grid=grid, bfs_grid_shared=grid, bfs_persist=persist))
-                st, f = s.features(A, B, 20)
-                assert st == 0
-                got.add((f.pdiam, f.bfs_t, f.bfs_u, f.n_components, f.k0_used, f.v))
+                for dia, tiles in ((0, 0), (2, 0), (2, 1)):   # queue kernels, diagonal levels, tiles
+                    s.set_tuning(dict(bfs_grid=grid, bfs_grid_shared=grid, bfs_persist=persist, bfs_dia=dia,
+                                      bfs_dia_tiles=tiles))
+                    st, f = s.features(A, B, 20)
+                    assert st == 0
+                    got.add((f.pdiam, f.bfs_t, f.bfs_u, f.n_components, f.k0_used, f.v))
     finally:
         s.close()
     assert len(got) == 1, got
@@ -87,9 +89,9 @@ def test_table_lookup_and_overrides(torch_mod, tmp_path):
     from paper_2412_08059_amd import autotune as at
     props = torch.cuda.get_device_properties(0)
     arch, cu = props.gcnArchName.split(":")[0], props.multi_processor_count
-    mk = lambda bt, w, sp, g: dict(sell_batch=bt, sell_whole_batch=w, sell_split=sp, bfs_grid=g,
-                                    bfs_grid_shared=32, bfs_persist=0)
-    rows = {(arch, cu, 1, 3, 12): mk(8, 0, -1, 64), (arch, cu, 1, 3, 20): mk(4, 3, -1, 256),
+    mk = lambda bt, w, sp, g, dia=1: dict(sell_batch=bt, sell_whole_batch=w, sell_split=sp, bfs_grid=g,
+                                           bfs_grid_shared=32, bfs_persist=0, bfs_dia=dia, bfs_dia_tiles=1)
+    rows = {(arch, cu, 1, 3, 12): mk(8, 0, -1, 64), (arch, cu, 1, 3, 20): mk(4, 3, -1, 256, dia=0),
             (arch, cu, 0, 4, 20): mk(8, 2, 1, 128), ("gfx000", cu, 1, 3, 16): mk(8, 3, 0, 1)}
     batch = (arch, cu, dict(batch_group_steps=3, batch_bfs_rounds=5, batch_small_cap=100, batch_small_levels=7,
                             batch_level_grid=99))
@@ -101,10 +103,12 @@ def test_table_lookup_and_overrides(torch_mod, tmp_path):
         assert s.tuning_for(2 ** 13, 7 * 2 ** 13, 64)["sell_batch"] == 8          # nlog 13 -> entry 12
         assert s.tuning_for(2 ** 16, 7 * 2 ** 16, 64)["bfs_grid"] == 64            # nlog 16: 12 and 20 tie -> 12
         assert s.tuning_for(2 ** 21, 7 * 2 ** 21, 64)["sell_whole_batch"] == 3     # nlog 21 -> entry 20
+        assert s.tuning_for(2 ** 21, 7 * 2 ** 21, 64)["bfs_dia"] == 0
         assert s.tuning_for(2 ** 20, 16 * 2 ** 20, 40000)["sell_split"] == 1       # 32-bit, lenlog 4
         # no entry for this class (lenlog 1): the defaults
         d = s.tuning_for(1000, 2000, 1)
         assert (d["sell_batch"], d["sell_whole_batch"], d["sell_split"], d["bfs_grid"]) == (4, 1, -1, 128)
+        assert (d["bfs_dia"], d["bfs_dia_tiles"]) == (1, 1)
         # a malformed table is refused and the loaded one stays
         bad = tmp_path / "bad.txt"
         bad.write_text("mpcg-tune 1\nsolve gfx950 256 1 3\n")
@@ -114,6 +118,8 @@ def test_table_lookup_and_overrides(torch_mod, tmp_path):
         s.set_tuning({"sell_batch": 4, "bfs_grid": 17})
         assert s.tuning_for(2 ** 13, 7 * 2 ** 13, 64)["bfs_grid"] == 17
         assert capi.mpcg_set_tuning(s.ctx, {"sell_batch": 5}) == capi.MPCG_EINVAL
+        assert capi.mpcg_set_tuning(s.ctx, {"bfs_dia": 3}) == capi.MPCG_EINVAL
+        assert capi.mpcg_set_tuning(s.ctx, {"bfs_dia_tiles": 2}) == capi.MPCG_EINVAL
     finally:
         s.close()
     # the options' explicit product variant overrides the table's split
