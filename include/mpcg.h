@@ -299,7 +299,8 @@ typedef struct {
                                     wider than |i - j| <= 8 and has at least 2^16 rows, 2 whenever it
                                     qualifies */
     int32_t bfs_dia_tiles;       /* with bfs_dia: 1 = several levels per launch (a block forms them on
-                                    its own words plus a halo that the levels consume), 0 = one launch
+                                    its own words plus a halo that the levels consume: up to 16 levels
+                                    per tile where 8 or more fit, else 2 per launch), 0 = one launch
                                     per level */
 } mpcg_tuning;
 

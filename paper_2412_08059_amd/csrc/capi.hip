@@ -73,7 +73,7 @@ struct Chan {
 bool same_dia_args(const BfsBufs &a, const BfsBufs &b)
 {
     return a.df0 == b.df0 && a.df1 == b.df1 && a.dv == b.dv && a.dm == b.dm && a.dist == b.dist && a.st == b.st &&
-           a.part_cnt == b.part_cnt && a.part_min == b.part_min &&
+           a.part_cnt == b.part_cnt && a.part_min == b.part_min && a.dia_two == b.dia_two &&
            a.nwords == b.nwords && a.dia_grid == b.dia_grid && std::memcmp(&a.doff, &b.doff, sizeof(DiaOffs)) == 0;
 }
 
@@ -195,7 +195,7 @@ Layout plan_layout(int64_t n, int64_t nnz)
     L.z64 = take(sizeof(double) * N);
     L.dg32 = take(sizeof(float) * N);
     L.dg64 = take(sizeof(double) * N);
-    L.dia_bits = take(sizeof(uint32_t) * (((N + 31) / 32 + 2) * (3 + 2 * kDiaMax) + 2 * kDiaRing + 4 * kDiaPartMax));
+    L.dia_bits = take(sizeof(uint32_t) * (((N + 31) / 32 + 2) * (3 + 2 * kDiaMax) + 2 * kDiaRing + 8 * kDiaPartMax));
     L.total = off;
     return L;
 }
@@ -530,9 +530,10 @@ BfsBufs bfs_bufs(const Plan &p, bool shared = false)
         b.ring_cnt = ring;
         b.ring_min = ring + kDiaRing;
         b.part_cnt = ring + 2 * kDiaRing;
-        b.part_min = ring + 2 * kDiaRing + 2 * kDiaPartMax;
+        b.part_min = ring + 2 * kDiaRing + 4 * kDiaPartMax;
     }
     b.dia_h = 0;
+    b.dia_two = 0;
     b.dist = p.at<int32_t>(p.L.dist);
     b.q0 = p.at<QEnt>(p.L.q0);
     b.q1 = p.at<QEnt>(p.L.q1);
@@ -591,6 +592,8 @@ mpcg_status dia_prepare(const Chan &ch, const Plan &p, BfsBufs *bb)
             bb->dia_T = kDiaTileWords - 2 * h * R;
         }
     }
+    // otherwise two levels per launch (chunks with a 2R-word halo in LDS)
+    bb->dia_two = p.tune.bfs_dia_tiles && bb->dia_h == 0 && bb->doff.nd <= kDiaTileDiags && R <= kDia2MaxReach;
     return MPCG_OK;
 }
 

@@ -1410,7 +1410,7 @@ __global__ void k_dia_seed(uint32_t *f0, uint32_t *v, int32_t *dist, int32_t src
         bfs_start(st, 1, src);
         st->dia_base = 0;
     }
-    // level 0's per-block partials: the source alone
+    // level 0's per-block partials (one-level kernel): the source alone
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kDiaPartMax; i += gridDim.x * blockDim.x) {
         pcnt[i] = i == 0 ? 1 : 0;
         pmin[i] = i == 0 ? src : kIntMax;
@@ -1508,9 +1508,147 @@ k_dia_level(const uint32_t *__restrict__ fc, uint32_t *__restrict__ fn, uint32_t
     }
 }
 
-__global__ void k_dia_round_end(DevState *st)
+__global__ void k_dia_round_end(DevState *st, int32_t levels)
 {
-    if (threadIdx.x == 0) st->dia_base += kDiaRound;
+    if (threadIdx.x == 0) st->dia_base += levels;
+}
+
+// Two levels per launch.  A block takes a chunk of kBlock words (one per
+// thread) and loads into LDS the level-L frontier over the chunk widened by
+// 2R words on each side (R: the most words a diagonal's window reaches).  It
+// forms the neighbours of that frontier at every word of the chunk widened
+// by R -- the words the chunk's level-(L + 1) windows read -- and from those
+// level L + 2 at its own words.  The neighbours are not stripped of visited
+// vertices (other blocks update those words in this launch): besides level
+// L + 1 they hold only vertices of levels L - 1 and L, whose neighbours are at
+// most at level L + 1 and are removed at the thread's own word together with
+// its visited bits and its exact level L + 1.  Launch j of a round expands
+// levels L0 + 1 and L0 + 2, L0 = dia_base + 2 j, and writes per-block partials
+// of both; wave 0 of block 0 of the next launch retires them (at L0 = 0 it
+// counts the source).  Only words that gain vertices are written (see
+// k_dia_clear).  LDS: (2 kBlock + 6 R) words.  (Staging the halo words'
+// masks in LDS as well, or loading six words' masks at once into registers,
+// measured slower at 128^3.)
+template <int ND>
+__global__ void __launch_bounds__(kBlock)
+k_dia_level2(const uint32_t *__restrict__ fc, uint32_t *__restrict__ fn, uint32_t *dv, const uint32_t *__restrict__ dm,
+             int32_t *dist, int32_t nw, int32_t j, int32_t R, DiaOffs o, const int32_t *__restrict__ pc_cur,
+             const int32_t *__restrict__ pm_cur, int32_t *pc_next, int32_t *pm_next, DevState *st)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ int s_cnt[2][kBlock / 64], s_min[2][kBlock / 64];
+    const int L0 = st->dia_base + 2 * j;
+    if (blockIdx.x == 0 && threadIdx.x < 64) {
+        // retire levels L0 - 1 and L0 (the previous launch's partials)
+        const int lane = threadIdx.x;
+        const int done = st->bfs_done;
+        int ca = 0, ma = kIntMax, cb = 0, mb = kIntMax;
+        if (L0 > 0)
+            for (int i = lane; i < (int)gridDim.x; i += 64) {
+                ca += pc_cur[i];
+                ma = ma < pm_cur[i] ? ma : pm_cur[i];
+                cb += pc_cur[kDiaPartMax + i];
+                mb = mb < pm_cur[kDiaPartMax + i] ? mb : pm_cur[kDiaPartMax + i];
+            }
+        ca = wave_sum_i(ca);
+        ma = wave_min_i(ma);
+        cb = wave_sum_i(cb);
+        mb = wave_min_i(mb);
+        if (lane == 0 && !done) {
+            if (L0 == 0) {
+                st->bfs_visited += 1;   // the source (bfs_far already holds it)
+            } else if (ca == 0) {       // level L0 - 1 empty: L0 - 2 was the last
+                st->bfs_done = 1;
+                st->bfs_ecc = L0 - 2;
+            } else if (cb == 0) {       // level L0 empty: L0 - 1 was the last
+                st->bfs_visited += ca;
+                st->bfs_done = 1;
+                st->bfs_ecc = L0 - 1;
+                st->bfs_far = ma;
+            } else {
+                st->bfs_visited += ca + cb;
+                st->bfs_far = mb;
+                st->bfs_lv[0] = L0;
+            }
+        }
+    }
+    const int G = gridDim.x, b = blockIdx.x;
+    const int nx = G < kNumXcd ? G : kNumXcd, xq = G / nx, xr = G % nx, x = b % nx;
+    const int nchunks = (nw + kBlock - 1) / kBlock;
+    const int NF = kBlock + 4 * R, NN = kBlock + 2 * R;
+    uint32_t *LF = lds, *LN = lds + NF;   // level-L frontier from c0 - 2R, neighbours from c0 - R
+    int c1 = 0, m1 = kIntMax, c2 = 0, m2 = kIntMax;
+    for (int chunk = x * xq + (x < xr ? x : xr) + b / nx; chunk < nchunks; chunk += G) {
+        const int c0 = chunk * kBlock;
+        for (int i = threadIdx.x; i < NF; i += kBlock) {
+            const int w = c0 - 2 * R + i;
+            LF[i] = (w >= 0 && w < nw) ? fc[w] : 0u;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < NN; i += kBlock) {
+            const int u = c0 - R + i;
+            uint32_t nb = 0u;
+            if (u >= 0 && u < nw) {
+                const int iu = i + R;   // u's index in LF
+#pragma unroll
+                for (int t = 0; t < ND; ++t) {
+                    const int k = iu + o.q[t];
+                    nb |= __builtin_amdgcn_alignbit(LF[k + 1], LF[k], o.r[t]) & dm[(size_t)t * nw + u];
+                }
+            }
+            LN[i] = nb;
+        }
+        __syncthreads();
+        const int w = c0 + threadIdx.x;
+        if (w < nw) {
+            const uint32_t vis = dv[w];
+            const int iw = threadIdx.x + R;   // w's index in LN
+            const uint32_t own1 = LN[iw] & ~vis;
+            uint32_t nb2 = 0u;
+#pragma unroll
+            for (int t = 0; t < ND; ++t) {
+                const int k = iw + o.q[t];
+                nb2 |= __builtin_amdgcn_alignbit(LN[k + 1], LN[k], o.r[t]) & dm[(size_t)t * nw + w];
+            }
+            nb2 &= ~(vis | own1);
+            if (nb2) fn[w] = nb2;
+            if (own1 | nb2) dv[w] = vis | own1 | nb2;
+            if (own1) {
+                c1 += __popc(own1);
+                const int v0 = 32 * w + __ffs(own1) - 1;
+                m1 = m1 < v0 ? m1 : v0;
+                for (uint32_t bb = own1; bb; bb &= bb - 1u) dist[32 * w + __ffs(bb) - 1] = L0 + 1;
+            }
+            if (nb2) {
+                c2 += __popc(nb2);
+                const int v0 = 32 * w + __ffs(nb2) - 1;
+                m2 = m2 < v0 ? m2 : v0;
+                for (uint32_t bb = nb2; bb; bb &= bb - 1u) dist[32 * w + __ffs(bb) - 1] = L0 + 2;
+            }
+        }
+        __syncthreads();   // LDS reused by the next chunk
+    }
+    c1 = wave_sum_i(c1);
+    m1 = wave_min_i(m1);
+    c2 = wave_sum_i(c2);
+    m2 = wave_min_i(m2);
+    if ((threadIdx.x & 63) == 0) {
+        s_cnt[0][threadIdx.x >> 6] = c1;
+        s_min[0][threadIdx.x >> 6] = m1;
+        s_cnt[1][threadIdx.x >> 6] = c2;
+        s_min[1][threadIdx.x >> 6] = m2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        const int l = threadIdx.x;
+        int c = 0, m = kIntMax;
+        for (int i = 0; i < kBlock / 64; ++i) {
+            c += s_cnt[l][i];
+            m = m < s_min[l][i] ? m : s_min[l][i];
+        }
+        pc_next[l * kDiaPartMax + blockIdx.x] = c;
+        pm_next[l * kDiaPartMax + blockIdx.x] = m;
+    }
 }
 
 #define MPCG_DIA_CASES(X)                                                                                           \
@@ -1522,11 +1660,28 @@ void launch_dia_round(hipStream_t s, const BfsBufs &b)
     if (g > b.dia_grid) g = b.dia_grid;
     if (g > kDiaPartMax) g = kDiaPartMax;
     if (g < 1) g = 1;
+    const int two = b.dia_two;   // two levels per launch
+    const size_t lds2 = sizeof(uint32_t) * (2 * kBlock + 6 * (size_t)b.dia_R);
     for (int j = 0; j < kDiaRound; ++j) {
         const uint32_t *fc = (j & 1) ? b.df1 : b.df0;
         uint32_t *fn = (j & 1) ? b.df0 : b.df1;
-        const int32_t *pcc = b.part_cnt + (j & 1) * kDiaPartMax, *pmc = b.part_min + (j & 1) * kDiaPartMax;
-        int32_t *pcn = b.part_cnt + ((j + 1) & 1) * kDiaPartMax, *pmn = b.part_min + ((j + 1) & 1) * kDiaPartMax;
+        // per-block partials by launch parity (two levels each for the two-level kernel)
+        const int32_t *pcc = b.part_cnt + (j & 1) * 2 * kDiaPartMax, *pmc = b.part_min + (j & 1) * 2 * kDiaPartMax;
+        int32_t *pcn = b.part_cnt + ((j + 1) & 1) * 2 * kDiaPartMax;
+        int32_t *pmn = b.part_min + ((j + 1) & 1) * 2 * kDiaPartMax;
+        if (two) {
+            switch (b.doff.nd) {
+#define X(N)                                                                                                        \
+    case N:                                                                                                         \
+        hipLaunchKernelGGL(k_dia_level2<N>, dim3(g), dim3(kBlock), lds2, s, fc, fn, b.dv, b.dm, b.dist, b.nwords, \
+                           j, b.dia_R, b.doff, pcc, pmc, pcn, pmn, b.st);                                           \
+        break;
+                X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
+#undef X
+            default: break;
+            }
+            continue;
+        }
         switch (b.doff.nd) {
 #define X(N)                                                                                                        \
     case N:                                                                                                         \
@@ -1538,7 +1693,7 @@ void launch_dia_round(hipStream_t s, const BfsBufs &b)
         default: break;
         }
     }
-    hipLaunchKernelGGL(k_dia_round_end, dim3(1), dim3(64), 0, s, b.st);
+    hipLaunchKernelGGL(k_dia_round_end, dim3(1), dim3(64), 0, s, b.st, (two ? 2 : 1) * kDiaRound);
 }
 
 // ------------------------------- several levels per launch: temporal tiles --

@@ -23,12 +23,13 @@ constexpr int kBfsSmallWork = 2048;   // (vertex, lane) items per level in the o
 constexpr int kBfsLevelBlocks = 128;  // level-kernel blocks (measured best on the 128^3 grid)
 constexpr int kDiaMax = 16;           // largest number of diagonals the bit-parallel 2BFS handles
 constexpr int kDiaRound = 16;         // level launches per round (a multiple of 4: the level rings)
-constexpr int kDiaPartMax = 2048;     // largest grid of the per-level kernel (per-block partials)
+constexpr int kDiaPartMax = 2048;     // largest grid of the level kernels (per-block partials)
 constexpr int kDiaTileThreads = 1024; // threads of a temporal-tile block
 constexpr int kDiaPerThread = 8;      // words of a tile's loaded range per thread
 constexpr int kDiaTileWords = kDiaTileThreads * kDiaPerThread;   // loaded range (LDS: 2 padded copies + visited)
 constexpr int kDiaTileDiags = 8;      // most diagonals of a temporal-tile pattern (masks in registers)
 constexpr int kDiaPad = 1024;         // zero words beside a tile's LDS range: largest halo per level R
+constexpr int kDia2MaxReach = 2048;   // largest R of the two-level kernel (LDS: 2 kBlock + 6 R words)
 constexpr int kDiaMaxLevels = 16;     // levels per temporal-tile launch
 constexpr int kDiaTileMinLevels = 8;  // fewer levels per launch: the per-level kernel is faster
 constexpr int kDiaRing = 64;          // level-count ring (>= 3 launches of levels)
@@ -294,7 +295,8 @@ struct BfsBufs {
     // dia_R words per level (dia_h = 0: one level per launch)
     int32_t dia_h, dia_T, dia_R;
     int32_t *ring_cnt, *ring_min;   // kDiaRing slots each
-    int32_t *part_cnt, *part_min;   // per-level kernel: 2 x kDiaPartMax per-block partials each
+    int32_t *part_cnt, *part_min;   // level kernels: 2 parities x 2 levels x kDiaPartMax per-block partials each
+    int32_t dia_two;                // two levels per launch (k_dia_level2)
 };
 // Diagonal structure: st->dia_over / dia_off from the CSR pattern (cleared
 // first); then, with b.doff filled from them, the masks.  Columns outside

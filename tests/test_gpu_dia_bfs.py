@@ -35,9 +35,10 @@ DIA_TUNINGS = {"tiles": {"bfs_dia": 2, "bfs_dia_tiles": 1, "bfs_persist": 0},
 
 @pytest.fixture(scope="module", params=list(DIA_TUNINGS))
 def dia_solver(request, torch_mod):
-    """Several levels per launch (temporal tiles), or one launch per level;
-    with bfs_persist the sweeps that the diagonals cannot take (a pattern
-    that is not connected) run on the persistent queue kernel."""
+    """Several levels per launch (temporal tiles where a tile holds 8 or more
+    levels, else two levels per launch), or one launch per level; with
+    bfs_persist the sweeps that the diagonals cannot take (a pattern that is
+    not connected) run on the persistent queue kernel."""
     from paper_2412_08059_amd import Solver
     s = Solver(2_200_000, 20_000_000, tuning=DIA_TUNINGS[request.param])
     s.dia_tuning = DIA_TUNINGS[request.param]
