@@ -302,6 +302,9 @@ typedef struct {
                                     its own words plus a halo that the levels consume: up to 16 levels
                                     per tile where 8 or more fit, else 2 per launch), 0 = one launch
                                     per level */
+    int32_t sell_stream;         /* the SELL products read the matrix with nontemporal loads: -1 where
+                                    that precision's copy exceeds the 256 MB Infinity Cache, 0 never,
+                                    1 always */
 } mpcg_tuning;
 
 /* Use *t for every matrix from now on (NULL: back to the table and the
@@ -311,7 +314,7 @@ mpcg_status mpcg_set_tuning(mpcg_ctx *ctx, const mpcg_tuning *t);
 
 /* Load a tuning table (host path; text, header "mpcg-tune 1", then lines
  * "solve <arch> <cu> <idx16> <lenlog> <nlog> <sell_batch> <sell_whole_batch>
- * <sell_split> <bfs_grid> <bfs_grid_shared> <bfs_persist> [<bfs_dia> [<bfs_dia_tiles>]]" and at most one
+ * <sell_split> <bfs_grid> <bfs_grid_shared> <bfs_persist> [<bfs_dia> [<bfs_dia_tiles> [<sell_stream>]]]" and at most one
  * "batch <arch> <cu> <group_steps> <bfs_rounds> <small_cap> <small_levels>
  * <level_grid>").  EINVAL for a missing or malformed file (the previous
  * table is kept). */

@@ -31,7 +31,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "tuning.txt")
 
 SOLVE_FIELDS = ("sell_batch", "sell_whole_batch", "sell_split", "bfs_grid", "bfs_grid_shared", "bfs_persist",
-                "bfs_dia", "bfs_dia_tiles")
+                "bfs_dia", "bfs_dia_tiles", "sell_stream")
+# the fields a table row may leave out, with their defaults (the C library's)
+OPTIONAL_DEFAULTS = {"bfs_dia": 1, "bfs_dia_tiles": 1, "sell_stream": -1}
 BATCH_FIELDS = ("batch_group_steps", "batch_bfs_rounds", "batch_small_cap", "batch_small_levels",
                 "batch_level_grid")
 
@@ -85,7 +87,7 @@ def format_table(solve_rows: dict, batch_row, comment: str = "") -> str:
     if comment:
         out += ["# " + ln for ln in comment.splitlines()]
     out.append("# solve arch cu idx16 lenlog nlog sell_batch sell_whole_batch sell_split bfs_grid "
-               "bfs_grid_shared bfs_persist bfs_dia bfs_dia_tiles")
+               "bfs_grid_shared bfs_persist bfs_dia bfs_dia_tiles sell_stream")
     for key in sorted(solve_rows):
         v = solve_rows[key]
         arch, cu, idx16, ll, nl = key
@@ -105,10 +107,11 @@ def parse_table(text: str):
         raise ValueError("not an mpcg-tune 1 table")
     for ln in lines[1:]:
         f = ln.split()
-        if f[0] == "solve" and len(f) in (12, 13, 14):
+        if f[0] == "solve" and 12 <= len(f) <= 6 + len(SOLVE_FIELDS):
             key = (f[1], int(f[2]), int(f[3]), int(f[4]), int(f[5]))
-            vals = [int(v) for v in f[6:]] + [1] * (14 - len(f))   # the bfs_dia fields default to 1
-            solve_rows[key] = dict(zip(SOLVE_FIELDS, vals))
+            row = dict(OPTIONAL_DEFAULTS)
+            row.update(zip(SOLVE_FIELDS, (int(v) for v in f[6:])))
+            solve_rows[key] = row
         elif f[0] == "batch" and len(f) == 8:
             batch_row = (f[1], int(f[2]), dict(zip(BATCH_FIELDS, (int(v) for v in f[3:]))))
         else:

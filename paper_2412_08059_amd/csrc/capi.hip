@@ -332,6 +332,12 @@ mpcg_status ingest(mpcg_ctx *c, const mpcg_csr *A, const double *b, bool need_va
         m.idx16 = s.max_band < 32768 ? 1 : 0;
         m.batch = p->tune.sell_batch;
         m.bf_mask = p->tune.sell_whole_batch;
+        // nontemporal matrix loads: where that precision's copy (values and
+        // column offsets) exceeds the Infinity Cache, unless the tuning says
+        const int64_t ib = m.idx16 ? 2 : 4;
+        const int nt_auto = (padded * (8 + ib) > kInfinityCacheBytes ? 2 : 0) |
+                            (padded * (4 + ib) > kInfinityCacheBytes ? 1 : 0);
+        m.nt_mask = p->tune.sell_stream < 0 ? nt_auto : (p->tune.sell_stream ? 3 : 0);
         // scattered gathers (columns beyond 16-bit offsets): one gathered vector, not two
         m.split = p->tune.sell_split >= 0 ? p->tune.sell_split : (m.idx16 ? 0 : 1);
         int64_t g = ((int64_t)nsl + kBlock / 64 - 1) / (kBlock / 64);

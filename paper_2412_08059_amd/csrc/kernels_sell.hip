@@ -260,13 +260,23 @@ struct SellArgs {
     DevState *st;
 };
 
+// NT: the matrix (values, column offsets) is read with nontemporal loads.
+// Streamed once per product, it then does not evict the gathered vectors from
+// the caches; worth it when the copy exceeds the 256 MB Infinity Cache (a
+// copy that fits is re-read from it by the next product).
+template <bool NT, typename P> __device__ inline P sell_ld(const P *p)
+{
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+
 // B = entries of a row whose loads are issued together (4 or 8)
 // BF: every lane loads all B entries of a batch (no guard per entry), so the
 // batch's index and value loads are issued together and its gathers too; an
 // entry past the row's length is the slice's padding (past W, its last
 // column; both inside the slice), its gather reads the row itself and its
 // product is skipped.  Without BF each entry's loads sit behind its own guard.
-template <int MODE, typename T, typename IDX, int B, bool BF>
+template <int MODE, typename T, typename IDX, int B, bool BF, bool NT>
 __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
 {
     constexpr int NV = (MODE == kSellRestart) ? 3 : 1;
@@ -384,8 +394,8 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
 #pragma unroll
                 for (int j = 0; j < B; ++j) {
                     const int kk = k0 + j < W ? k0 + j : W - 1;
-                    const IDX ci = cp[(int64_t)kk * 64];
-                    v[j] = vp[(int64_t)kk * 64];
+                    const IDX ci = sell_ld<NT>(cp + (int64_t)kk * 64);
+                    v[j] = sell_ld<NT>(vp + (int64_t)kk * 64);
                     const int cc = (sizeof(IDX) == 2) ? row + (int)ci : (int)ci;
                     c[j] = k0 + j < len ? cc : safe;
                 }
@@ -400,9 +410,9 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
 #pragma unroll
                 for (int j = 0; j < B; ++j) {
                     if (k0 + j < len) {
-                        const IDX ci = cp[(int64_t)(k0 + j) * 64];
+                        const IDX ci = sell_ld<NT>(cp + (int64_t)(k0 + j) * 64);
                         c[j] = (sizeof(IDX) == 2) ? row + (int)ci : (int)ci;
-                        v[j] = vp[(int64_t)(k0 + j) * 64];
+                        v[j] = sell_ld<NT>(vp + (int64_t)(k0 + j) * 64);
                     }
                 }
 #pragma unroll
@@ -467,27 +477,34 @@ __global__ void __launch_bounds__(kBlock) k_sell(SellArgs<T> a)
     }
 }
 
-template <int MODE, typename T, bool BF>
+template <int MODE, typename T, bool BF, bool NT>
 static void sell_launch_bf(hipStream_t s, const SellMat &m, const SellArgs<T> &a)
 {
     if (m.batch == 8) {
         if (m.idx16)
-            hipLaunchKernelGGL((k_sell<MODE, T, int16_t, 8, BF>), dim3(m.grid), dim3(kBlock), 0, s, a);
+            hipLaunchKernelGGL((k_sell<MODE, T, int16_t, 8, BF, NT>), dim3(m.grid), dim3(kBlock), 0, s, a);
         else
-            hipLaunchKernelGGL((k_sell<MODE, T, int32_t, 8, BF>), dim3(m.grid), dim3(kBlock), 0, s, a);
+            hipLaunchKernelGGL((k_sell<MODE, T, int32_t, 8, BF, NT>), dim3(m.grid), dim3(kBlock), 0, s, a);
     } else {
         if (m.idx16)
-            hipLaunchKernelGGL((k_sell<MODE, T, int16_t, 4, BF>), dim3(m.grid), dim3(kBlock), 0, s, a);
+            hipLaunchKernelGGL((k_sell<MODE, T, int16_t, 4, BF, NT>), dim3(m.grid), dim3(kBlock), 0, s, a);
         else
-            hipLaunchKernelGGL((k_sell<MODE, T, int32_t, 4, BF>), dim3(m.grid), dim3(kBlock), 0, s, a);
+            hipLaunchKernelGGL((k_sell<MODE, T, int32_t, 4, BF, NT>), dim3(m.grid), dim3(kBlock), 0, s, a);
     }
 }
 
 template <int MODE, typename T>
 static void sell_launch(hipStream_t s, const SellMat &m, const SellArgs<T> &a)
 {
-    if ((m.bf_mask >> (sizeof(T) == 8 ? 1 : 0)) & 1) sell_launch_bf<MODE, T, true>(s, m, a);
-    else sell_launch_bf<MODE, T, false>(s, m, a);
+    const int bit = sizeof(T) == 8 ? 1 : 0;
+    const bool bf = (m.bf_mask >> bit) & 1, nt = MODE != kSellDir && ((m.nt_mask >> bit) & 1);
+    if (bf) {
+        if (nt) sell_launch_bf<MODE, T, true, true>(s, m, a);
+        else sell_launch_bf<MODE, T, true, false>(s, m, a);
+    } else {
+        if (nt) sell_launch_bf<MODE, T, false, true>(s, m, a);
+        else sell_launch_bf<MODE, T, false, false>(s, m, a);
+    }
 }
 
 template <typename T>

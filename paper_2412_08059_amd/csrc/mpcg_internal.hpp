@@ -33,6 +33,7 @@ constexpr int kDia2MaxReach = 2048;   // largest R of the two-level kernel (LDS:
 constexpr int kDiaMaxLevels = 16;     // levels per temporal-tile launch
 constexpr int kDiaTileMinLevels = 8;  // fewer levels per launch: the per-level kernel is faster
 constexpr int kDiaRing = 64;          // level-count ring (>= 3 launches of levels)
+constexpr int64_t kInfinityCacheBytes = 256ll << 20;   // MI355X last-level (Infinity) cache
 constexpr int kNumXcd = 8;            // MI355X: blocks are dispatched round-robin over 8 XCDs
 constexpr int kMaxGrid = 2048;        // largest grid of a kernel that writes reduction partials
 constexpr int kUpdateGrid = 1024;     // blocks of a CG update launch: fewer partials for the next product
@@ -140,6 +141,7 @@ struct SellMat {
     int32_t n, nslices, grid, idx16;
     int32_t batch;   // row entries whose loads are issued together: 4 or 8
     int32_t bf_mask; // whole-batch loads without a guard per entry: bit 0 FP32 kernels, bit 1 FP64
+    int32_t nt_mask; // nontemporal loads of the matrix stream: bit 0 FP32 kernels, bit 1 FP64
     int32_t split;   // CG product in two launches (direction, then a one-vector gather)
 };
 

@@ -3,7 +3,7 @@
 // File format (text, '#' starts a comment line):
 //   mpcg-tune 1
 //   solve <arch> <cu> <idx16> <lenlog> <nlog> <sell_batch> <sell_whole_batch> <sell_split> <bfs_grid>
-//         <bfs_grid_shared> <bfs_persist> [<bfs_dia> [<bfs_dia_tiles>]]
+//         <bfs_grid_shared> <bfs_persist> [<bfs_dia> [<bfs_dia_tiles> [<sell_stream>]]]
 //   batch <arch> <cu> <group_steps> <bfs_rounds> <small_cap> <small_levels> <level_grid>
 
 #include "tune.hpp"
@@ -31,6 +31,7 @@ mpcg_tuning tune_defaults()
     t.batch_level_grid = 1024;
     t.bfs_dia = 1;
     t.bfs_dia_tiles = 1;
+    t.sell_stream = -1;
     return t;
 }
 
@@ -43,7 +44,7 @@ bool tune_valid(const mpcg_tuning &t)
            t.batch_bfs_rounds <= 64 && t.batch_small_cap >= 1 && t.batch_small_cap <= 2048 &&
            t.batch_small_levels >= 1 && t.batch_small_levels <= 4096 && t.batch_level_grid >= 1 &&
            t.batch_level_grid <= 65536 && t.bfs_dia >= 0 && t.bfs_dia <= 2 &&
-           (t.bfs_dia_tiles == 0 || t.bfs_dia_tiles == 1);
+           (t.bfs_dia_tiles == 0 || t.bfs_dia_tiles == 1) && t.sell_stream >= -1 && t.sell_stream <= 1;
 }
 
 int32_t tune_lenlog(int64_t n, int64_t nnz)
@@ -83,12 +84,12 @@ int tune_load(const char *path, TuneTable *out)
         if (!std::strcmp(kind, "solve")) {
             TuneEntry e;
             e.t = tune_defaults();
-            const int got = std::sscanf(p, "%*s %*s %d %d %d %d %d %d %d %d %d %d %d %d", &e.key.cu, &e.key.idx16,
-                                        &e.key.lenlog, &e.key.nlog, &e.t.sell_batch, &e.t.sell_whole_batch,
-                                        &e.t.sell_split, &e.t.bfs_grid, &e.t.bfs_grid_shared, &e.t.bfs_persist,
-                                        &e.t.bfs_dia, &e.t.bfs_dia_tiles);
+            const int got = std::sscanf(p, "%*s %*s %d %d %d %d %d %d %d %d %d %d %d %d %d", &e.key.cu,
+                                        &e.key.idx16, &e.key.lenlog, &e.key.nlog, &e.t.sell_batch,
+                                        &e.t.sell_whole_batch, &e.t.sell_split, &e.t.bfs_grid, &e.t.bfs_grid_shared,
+                                        &e.t.bfs_persist, &e.t.bfs_dia, &e.t.bfs_dia_tiles, &e.t.sell_stream);
             e.key.arch = arch;
-            ok = got >= 10 && got <= 12 && tune_valid(e.t);   // the bfs_dia fields may be absent (defaults)
+            ok = got >= 10 && got <= 13 && tune_valid(e.t);   // the last three fields may be absent (defaults)
             if (ok) tb.solve.push_back(e);
         } else if (!std::strcmp(kind, "batch")) {
             mpcg_tuning t = tune_defaults();
@@ -138,6 +139,7 @@ mpcg_tuning tune_lookup(const TuneTable &tb, const std::string &arch, int32_t cu
         t.bfs_persist = best->t.bfs_persist;
         t.bfs_dia = best->t.bfs_dia;
         t.bfs_dia_tiles = best->t.bfs_dia_tiles;
+        t.sell_stream = best->t.sell_stream;
     }
     return t;
 }

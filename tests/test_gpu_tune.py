@@ -46,17 +46,18 @@ def test_every_sell_candidate_gives_the_same_bits(torch_mod, name):
     idx16 = 1 if at.band_of(a) < 32768 else 0
     try:
         for cand in at.sell_candidates(idx16):
-            s.set_tuning(dict(zip(("sell_batch", "sell_whole_batch", "sell_split"), cand)))
-            out = []
-            for e1 in (1e-5, 0.0):
-                st, x, S = s.solve(A, B, e1, 1e-10)
-                assert st == 0
-                out.append((S.n1, S.n2, S.eps1_class, x.cpu().numpy().view(np.uint64).copy()))
-            print(f"{name} {cand}: n1/n2 {[o[:2] for o in out]}", flush=True)
-            if ref is None:
-                ref = out
-            for o, r in zip(out, ref):
-                assert o[:3] == r[:3] and np.array_equal(o[3], r[3]), cand
+            for stream in (0, 1):   # cached or nontemporal matrix loads
+                s.set_tuning(dict(zip(("sell_batch", "sell_whole_batch", "sell_split"), cand), sell_stream=stream))
+                out = []
+                for e1 in (1e-5, 0.0):
+                    st, x, S = s.solve(A, B, e1, 1e-10)
+                    assert st == 0
+                    out.append((S.n1, S.n2, S.eps1_class, x.cpu().numpy().view(np.uint64).copy()))
+                print(f"{name} {cand} stream {stream}: n1/n2 {[o[:2] for o in out]}", flush=True)
+                if ref is None:
+                    ref = out
+                for o, r in zip(out, ref):
+                    assert o[:3] == r[:3] and np.array_equal(o[3], r[3]), (cand, stream)
     finally:
         s.close()
 
@@ -90,7 +91,8 @@ def test_table_lookup_and_overrides(torch_mod, tmp_path):
     props = torch.cuda.get_device_properties(0)
     arch, cu = props.gcnArchName.split(":")[0], props.multi_processor_count
     mk = lambda bt, w, sp, g, dia=1: dict(sell_batch=bt, sell_whole_batch=w, sell_split=sp, bfs_grid=g,
-                                           bfs_grid_shared=32, bfs_persist=0, bfs_dia=dia, bfs_dia_tiles=1)
+                                           bfs_grid_shared=32, bfs_persist=0, bfs_dia=dia, bfs_dia_tiles=1,
+                                           sell_stream=-1)
     rows = {(arch, cu, 1, 3, 12): mk(8, 0, -1, 64), (arch, cu, 1, 3, 20): mk(4, 3, -1, 256, dia=0),
             (arch, cu, 0, 4, 20): mk(8, 2, 1, 128), ("gfx000", cu, 1, 3, 16): mk(8, 3, 0, 1)}
     batch = (arch, cu, dict(batch_group_steps=3, batch_bfs_rounds=5, batch_small_cap=100, batch_small_levels=7,
@@ -108,7 +110,7 @@ def test_table_lookup_and_overrides(torch_mod, tmp_path):
         # no entry for this class (lenlog 1): the defaults
         d = s.tuning_for(1000, 2000, 1)
         assert (d["sell_batch"], d["sell_whole_batch"], d["sell_split"], d["bfs_grid"]) == (4, 1, -1, 128)
-        assert (d["bfs_dia"], d["bfs_dia_tiles"]) == (1, 1)
+        assert (d["bfs_dia"], d["bfs_dia_tiles"], d["sell_stream"]) == (1, 1, -1)
         # a malformed table is refused and the loaded one stays
         bad = tmp_path / "bad.txt"
         bad.write_text("mpcg-tune 1\nsolve gfx950 256 1 3\n")
@@ -120,6 +122,7 @@ def test_table_lookup_and_overrides(torch_mod, tmp_path):
         assert capi.mpcg_set_tuning(s.ctx, {"sell_batch": 5}) == capi.MPCG_EINVAL
         assert capi.mpcg_set_tuning(s.ctx, {"bfs_dia": 3}) == capi.MPCG_EINVAL
         assert capi.mpcg_set_tuning(s.ctx, {"bfs_dia_tiles": 2}) == capi.MPCG_EINVAL
+        assert capi.mpcg_set_tuning(s.ctx, {"sell_stream": 2}) == capi.MPCG_EINVAL
     finally:
         s.close()
     # the options' explicit product variant overrides the table's split

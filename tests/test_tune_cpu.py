@@ -33,18 +33,21 @@ def test_candidates_and_choice():
 
 def test_table_roundtrip():
     rows = {("gfx950", 256, 1, 3, 21): dict(sell_batch=4, sell_whole_batch=1, sell_split=-1, bfs_grid=128,
-                                            bfs_grid_shared=64, bfs_persist=0, bfs_dia=1, bfs_dia_tiles=1),
+                                            bfs_grid_shared=64, bfs_persist=0, bfs_dia=1, bfs_dia_tiles=1,
+                                            sell_stream=-1),
             ("gfx950", 256, 0, 4, 20): dict(sell_batch=8, sell_whole_batch=3, sell_split=1, bfs_grid=256,
-                                            bfs_grid_shared=32, bfs_persist=1, bfs_dia=2, bfs_dia_tiles=0)}
+                                            bfs_grid_shared=32, bfs_persist=1, bfs_dia=2, bfs_dia_tiles=0,
+                                            sell_stream=1)}
     batch = ("gfx950", 256, dict(batch_group_steps=4, batch_bfs_rounds=4, batch_small_cap=256,
                                  batch_small_levels=64, batch_level_grid=512))
     text = at.format_table(rows, batch, comment="test")
     assert text.startswith("mpcg-tune 1\n")
     r2, b2 = at.parse_table(text)
     assert r2 == rows and b2 == batch
-    # rows written before the 2BFS-on-diagonals fields take their defaults (1, 1)
+    # rows written before the last three fields take their defaults (1, 1, -1)
     old_row = "mpcg-tune 1\nsolve gfx950 256 1 3 21 4 1 -1 128 64 0\n"
     r3, _ = at.parse_table(old_row)
     assert r3[("gfx950", 256, 1, 3, 21)]["bfs_dia"] == 1 and r3[("gfx950", 256, 1, 3, 21)]["bfs_dia_tiles"] == 1
+    assert r3[("gfx950", 256, 1, 3, 21)]["sell_stream"] == -1
     with pytest.raises(ValueError):
         at.parse_table("mpcg-tune 2\n")
