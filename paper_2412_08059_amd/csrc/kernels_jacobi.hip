@@ -74,7 +74,14 @@ __device__ inline bool jac_prologue(const JacArgs<T> &a, double *sm)
     return true;
 }
 
-template <typename T, typename IDX, int B>
+// NT: nontemporal loads of the matrix stream (see the SELL products)
+template <bool NT, typename P> __device__ inline P jac_ld(const P *p)
+{
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+
+template <typename T, typename IDX, int B, bool NT>
 __global__ void __launch_bounds__(kBlock) k_jac_sell(JacArgs<T> a)
 {
     __shared__ double sm[kBlock / 64 + 1];
@@ -107,8 +114,8 @@ __global__ void __launch_bounds__(kBlock) k_jac_sell(JacArgs<T> a)
 #pragma unroll
                 for (int j = 0; j < B; ++j) {
                     const int kk = k0 + j < W ? k0 + j : W - 1;
-                    const IDX ci = cp[(int64_t)kk * 64];
-                    v[j] = vp[(int64_t)kk * 64];
+                    const IDX ci = jac_ld<NT>(cp + (int64_t)kk * 64);
+                    v[j] = jac_ld<NT>(vp + (int64_t)kk * 64);
                     const int cc = (sizeof(IDX) == 2) ? row + (int)ci : (int)ci;
                     c[j] = k0 + j < len ? cc : row;
                     g[j] = x[k0 + j < len ? cc : safe];
@@ -118,9 +125,9 @@ __global__ void __launch_bounds__(kBlock) k_jac_sell(JacArgs<T> a)
                 for (int j = 0; j < B; ++j) {
                     c[j] = row;
                     if (k0 + j < len) {
-                        const IDX ci = cp[(int64_t)(k0 + j) * 64];
+                        const IDX ci = jac_ld<NT>(cp + (int64_t)(k0 + j) * 64);
                         c[j] = (sizeof(IDX) == 2) ? row + (int)ci : (int)ci;
-                        v[j] = vp[(int64_t)(k0 + j) * 64];
+                        v[j] = jac_ld<NT>(vp + (int64_t)(k0 + j) * 64);
                     }
                 }
 #pragma unroll
@@ -233,10 +240,14 @@ void launch_jacobi_iter(hipStream_t s, const JacMat &m, const T *val_csr, const 
         a.sval = sizeof(T) == 8 ? reinterpret_cast<const T *>(m.sell.v64) : reinterpret_cast<const T *>(m.sell.v32);
         a.off = m.sell.off;
         a.nslices = m.sell.nslices;
-        if (m.sell.idx16)
-            hipLaunchKernelGGL((k_jac_sell<T, int16_t, 4>), dim3(a.np), dim3(kBlock), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_jac_sell<T, int32_t, 4>), dim3(a.np), dim3(kBlock), 0, s, a);
+        const bool nt = (m.sell.nt_mask >> (sizeof(T) == 8 ? 1 : 0)) & 1;
+        if (m.sell.idx16) {
+            if (nt) hipLaunchKernelGGL((k_jac_sell<T, int16_t, 4, true>), dim3(a.np), dim3(kBlock), 0, s, a);
+            else hipLaunchKernelGGL((k_jac_sell<T, int16_t, 4, false>), dim3(a.np), dim3(kBlock), 0, s, a);
+        } else {
+            if (nt) hipLaunchKernelGGL((k_jac_sell<T, int32_t, 4, true>), dim3(a.np), dim3(kBlock), 0, s, a);
+            else hipLaunchKernelGGL((k_jac_sell<T, int32_t, 4, false>), dim3(a.np), dim3(kBlock), 0, s, a);
+        }
     } else {
         a.col = m.col;
         a.val = val_csr;
