@@ -715,6 +715,9 @@ Engine *engine_create(int device, const mpcg_options &opt, const mpcg_tuning &tu
     e->model = model;
     e->a = carve(arena, max_sys, (int32_t)max_slices, max_entries);
     e->a.acc32 = opt.dot_acc;
+    // nontemporal matrix loads where the arena's FP64 matrices (8-byte values,
+    // 4-byte columns) can exceed the Infinity Cache, unless the tuning says
+    e->a.nt = tune.sell_stream < 0 ? (max_entries * 12 > kInfinityCacheBytes ? 1 : 0) : tune.sell_stream;
     e->slots.resize(max_sys);
     e->finals.resize(max_sys);
     e->slices.init(max_slices);

@@ -124,7 +124,7 @@ struct BArena {
     int32_t *step_sys;                     // [k] = slot of the k-th listed system
     int32_t *step_cnt;                     // [0] = listed slices, [1] = listed systems
     int32_t acc32;                         // dot_acc = 1: FP32-phase dot products accumulate in FP32
-    int32_t pad_;
+    int32_t nt;                            // the step product reads the matrices with nontemporal loads
 };
 
 // One launch's share of a work-list rebuild: entries first .. first + n - 1

@@ -471,9 +471,17 @@ __global__ void k_set_eps(BArena a, int32_t sys, double eps1, int32_t ci)
 
 // ----------------------------------------------------------------- step --
 
+// NT: nontemporal loads of the matrix stream (an arena beyond the Infinity
+// Cache: streamed once per step, the matrices then do not evict the vectors)
+template <bool NT, typename P> __device__ inline P b_ld(const P *p)
+{
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+
 // Wave per slice.  CG product of iteration j of the phase:
 // d_j = r_j + beta_j d_{j-1} (d_0 = r_0), q = A d_j, partial of d_j.q (FP64).
-template <typename T>
+template <typename T, bool NT>
 __device__ inline double cg_product(const BArena &a, const BSys &S, const T *val, const T *r, T *dA, T *dB,
                                     T *q, int64_t base, int row, int len)
 {
@@ -495,8 +503,8 @@ __device__ inline double cg_product(const BArena &a, const BSys &S, const T *val
 #pragma unroll
             for (int t = 0; t < kLoadBatch; ++t) {
                 const int kk = k0 + t < W ? k0 + t : W - 1;
-                c[t] = a.col[base + (int64_t)kk * 64];
-                v[t] = val[base + (int64_t)kk * 64];
+                c[t] = b_ld<NT>(a.col + base + (int64_t)kk * 64);
+                v[t] = b_ld<NT>(val + base + (int64_t)kk * 64);
             }
 #pragma unroll
             for (int t = 0; t < kLoadBatch; ++t) g[t] = first ? r[c[t]] : fma_b<T>(beta, dold[c[t]], r[c[t]]);
@@ -504,8 +512,8 @@ __device__ inline double cg_product(const BArena &a, const BSys &S, const T *val
 #pragma unroll
             for (int t = 0; t < kLoadBatch; ++t)
                 if (k0 + t < len) {
-                    c[t] = a.col[base + (int64_t)(k0 + t) * 64];
-                    v[t] = val[base + (int64_t)(k0 + t) * 64];
+                    c[t] = b_ld<NT>(a.col + base + (int64_t)(k0 + t) * 64);
+                    v[t] = b_ld<NT>(val + base + (int64_t)(k0 + t) * 64);
                 }
 #pragma unroll
             for (int t = 0; t < kLoadBatch; ++t)
@@ -524,6 +532,7 @@ __device__ inline double cg_product(const BArena &a, const BSys &S, const T *val
 
 // Restart: r = b - A x with x = float64(x~), x, or 0; x takes that value.
 // Final check: partial of ||b - A x||^2.
+template <bool NT>
 __device__ inline double residual(const BArena &a, const BSys &S, bool restart, int64_t base, int row, int len)
 {
     const int src = restart ? S.src : kSrcX64;
@@ -536,8 +545,8 @@ __device__ inline double residual(const BArena &a, const BSys &S, bool restart, 
 #pragma unroll
         for (int t = 0; t < kLoadBatch; ++t)
             if (k0 + t < len) {
-                c[t] = a.col[base + (int64_t)(k0 + t) * 64];
-                v[t] = a.v64[base + (int64_t)(k0 + t) * 64];
+                c[t] = b_ld<NT>(a.col + base + (int64_t)(k0 + t) * 64);
+                v[t] = b_ld<NT>(a.v64 + base + (int64_t)(k0 + t) * 64);
             }
 #pragma unroll
         for (int t = 0; t < kLoadBatch; ++t)
@@ -560,6 +569,7 @@ __device__ inline double residual(const BArena &a, const BSys &S, bool restart, 
     return res * res;
 }
 
+template <bool NT>
 __global__ void __launch_bounds__(kBlock) k_b_product(BArena a)
 {
     const int k = blockIdx.x * kSlicesPerBlock + (threadIdx.x >> 6);
@@ -580,9 +590,9 @@ __global__ void __launch_bounds__(kBlock) k_b_product(BArena a)
     const int len = a.rowlen[row];
     const int64_t base = S.entry0 + a.slice_off[sl] + lane;
     double p;
-    if (mode == kCg32) p = cg_product<float>(a, S, a.v32, a.r32, a.dA32, a.dB32, a.q32, base, row, len);
-    else if (mode == kCg64) p = cg_product<double>(a, S, a.v64, a.r64, a.dA64, a.dB64, a.q64, base, row, len);
-    else p = wave_sum_d(residual(a, S, mode == kRestart, base, row, len));
+    if (mode == kCg32) p = cg_product<float, NT>(a, S, a.v32, a.r32, a.dA32, a.dB32, a.q32, base, row, len);
+    else if (mode == kCg64) p = cg_product<double, NT>(a, S, a.v64, a.r64, a.dA64, a.dB64, a.q64, base, row, len);
+    else p = wave_sum_d(residual<NT>(a, S, mode == kRestart, base, row, len));
     if (lane == 0) a.pslice[2 * (size_t)sl] = p;
 }
 
@@ -1093,7 +1103,8 @@ void launch_worklist(hipStream_t s, const BArena &a, const ListChunk &c)
 void launch_step(hipStream_t s, const BArena &a, int32_t grid_slices, int32_t grid_sys)
 {
     if (grid_slices <= 0 || grid_sys <= 0) return;
-    hipLaunchKernelGGL(k_b_product, dim3(grid_slices), dim3(kBlock), 0, s, a);
+    if (a.nt) hipLaunchKernelGGL(k_b_product<true>, dim3(grid_slices), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_b_product<false>, dim3(grid_slices), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_b_scalar1, dim3(grid_sys), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_b_update, dim3(grid_slices), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_b_scalar2, dim3(grid_sys), dim3(kBlock), 0, s, a);
