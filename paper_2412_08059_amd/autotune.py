@@ -168,7 +168,9 @@ def tune_solve(quick: bool = False, log=print):
             t32, t64 = _time_kernels(capi, sv.ctx, A.desc, reps)
             sell[cand] = t32 + t64
         best_sell = choose_min(sell)
-        base = dict(zip(("sell_batch", "sell_whole_batch", "sell_split"), best_sell))
+        # nontemporal matrix loads stay with the size rule (-1): a class spans
+        # sizes on both sides of the Infinity Cache
+        base = dict(zip(("sell_batch", "sell_whole_batch", "sell_split"), best_sell), sell_stream=-1)
         bfs = {}
         for persist in (0, 1):
             for grid in (64, 128, 256):
