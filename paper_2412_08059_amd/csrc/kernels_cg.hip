@@ -697,21 +697,23 @@ k_cg_update(int32_t n, T *__restrict__ r, const T *__restrict__ q, const double 
     if (threadIdx.x == 0) s_skip = st->stop_it <= it;
     const double g = st->gam[it & 1];
     const bool f32acc = sizeof(T) == 4 && st->acc32;   // dot_acc = 1
-    // delta: the product's partials in a fixed order (the same bits in every block)
+    // delta: the product's partials in a fixed order (the same bits in every
+    // block).  nsp <= kMaxGrid, so every thread's share is issued at once;
+    // a share past nsp adds +0.0, which leaves the sum's bits unchanged (the
+    // running sum starts at +0.0 and so is never -0.0).
     double acc = 0.0;
     float accf = 0.0f;
     if (f32acc) {
         for (int i = threadIdx.x; i < nsp; i += kBlock) accf += (float)sp[i];
     } else {
-        int i = threadIdx.x;
-        for (; i + 3 * kBlock < nsp; i += 4 * kBlock) {
-            const double p0 = sp[i], p1 = sp[i + kBlock], p2 = sp[i + 2 * kBlock], p3 = sp[i + 3 * kBlock];
-            acc += p0;
-            acc += p1;
-            acc += p2;
-            acc += p3;
+        double pv[kMaxGrid / kBlock];
+#pragma unroll
+        for (int k = 0; k < kMaxGrid / kBlock; ++k) {
+            const int i = threadIdx.x + k * kBlock;
+            pv[k] = i < nsp ? sp[i] : 0.0;
         }
-        for (; i < nsp; i += kBlock) acc += sp[i];
+#pragma unroll
+        for (int k = 0; k < kMaxGrid / kBlock; ++k) acc += pv[k];
     }
     __syncthreads();
     if (s_skip) return;
@@ -723,7 +725,14 @@ k_cg_update(int32_t n, T *__restrict__ r, const T *__restrict__ q, const double 
         delta = sm[kBlock / 64];
         __syncthreads();
     } else {
-        delta = block_sum_all(acc, sm);
+        // butterfly in each wave, then waves 0..3 in order by every thread:
+        // block_sum's bits with one barrier (sm_d is written once)
+        __shared__ double sm_d[kBlock / 64];
+        const double v = wave_sum(acc);
+        if ((threadIdx.x & 63) == 0) sm_d[threadIdx.x >> 6] = v;
+        __syncthreads();
+        delta = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) delta += sm_d[w];
     }
     if (!isfinite(delta) || !(delta > 0.0)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
