@@ -305,6 +305,13 @@ typedef struct {
     int32_t sell_stream;         /* the SELL products read the matrix with nontemporal loads: -1 where
                                     that precision's copy exceeds the 256 MB Infinity Cache, 0 never,
                                     1 always */
+    int32_t batch_runahead;      /* batch engine, Algorithm II: 0 = a system whose features are still
+                                    being computed holds after its k0 prefix (it takes no bandwidth
+                                    from the others meanwhile), 1 = it runs ahead in FP32 with copies
+                                    of x~ at each candidate's crossing and a speculative FP64 phase */
+    int32_t batch_bfs_band;      /* batch engine: 1 = a connected system whose pattern lies within
+                                    |i - j| <= 31 takes its 2BFS as bit-parallel levels of one wave
+                                    per system, 0 = the level kernels of every other system */
 } mpcg_tuning;
 
 /* Use *t for every matrix from now on (NULL: back to the table and the
@@ -316,8 +323,8 @@ mpcg_status mpcg_set_tuning(mpcg_ctx *ctx, const mpcg_tuning *t);
  * "solve <arch> <cu> <idx16> <lenlog> <nlog> <sell_batch> <sell_whole_batch>
  * <sell_split> <bfs_grid> <bfs_grid_shared> <bfs_persist> [<bfs_dia> [<bfs_dia_tiles> [<sell_stream>]]]" and at most one
  * "batch <arch> <cu> <group_steps> <bfs_rounds> <small_cap> <small_levels>
- * <level_grid>").  EINVAL for a missing or malformed file (the previous
- * table is kept). */
+ * <level_grid> [<runahead> [<bfs_band>]]").  EINVAL for a missing or
+ * malformed file (the previous table is kept). */
 mpcg_status mpcg_load_tuning(mpcg_ctx *ctx, const char *path);
 
 /* The parameters a solve would use for a matrix of n rows, nnz entries and

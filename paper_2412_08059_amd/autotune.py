@@ -35,7 +35,8 @@ SOLVE_FIELDS = ("sell_batch", "sell_whole_batch", "sell_split", "bfs_grid", "bfs
 # the fields a table row may leave out, with their defaults (the C library's)
 OPTIONAL_DEFAULTS = {"bfs_dia": 1, "bfs_dia_tiles": 1, "sell_stream": -1}
 BATCH_FIELDS = ("batch_group_steps", "batch_bfs_rounds", "batch_small_cap", "batch_small_levels",
-                "batch_level_grid")
+                "batch_level_grid", "batch_runahead", "batch_bfs_band")
+BATCH_OPTIONAL_DEFAULTS = {"batch_runahead": 0, "batch_bfs_band": 1}
 
 
 # ----------------------------------------------------------- class keys --
@@ -94,7 +95,8 @@ def format_table(solve_rows: dict, batch_row, comment: str = "") -> str:
         out.append(f"solve {arch} {cu} {idx16} {ll} {nl} " + " ".join(str(int(v[f])) for f in SOLVE_FIELDS))
     if batch_row is not None:
         arch, cu, v = batch_row
-        out.append("# batch arch cu group_steps bfs_rounds small_cap small_levels level_grid")
+        out.append("# batch arch cu group_steps bfs_rounds small_cap small_levels level_grid runahead bfs_band")
+        v = {**BATCH_OPTIONAL_DEFAULTS, **v}
         out.append(f"batch {arch} {cu} " + " ".join(str(int(v[f])) for f in BATCH_FIELDS))
     return "\n".join(out) + "\n"
 
@@ -112,8 +114,10 @@ def parse_table(text: str):
             row = dict(OPTIONAL_DEFAULTS)
             row.update(zip(SOLVE_FIELDS, (int(v) for v in f[6:])))
             solve_rows[key] = row
-        elif f[0] == "batch" and len(f) == 8:
-            batch_row = (f[1], int(f[2]), dict(zip(BATCH_FIELDS, (int(v) for v in f[3:]))))
+        elif f[0] == "batch" and 8 <= len(f) <= 3 + len(BATCH_FIELDS):
+            row = dict(BATCH_OPTIONAL_DEFAULTS)
+            row.update(zip(BATCH_FIELDS, (int(v) for v in f[3:])))
+            batch_row = (f[1], int(f[2]), row)
         else:
             raise ValueError(f"bad line: {ln}")
     return solve_rows, batch_row
@@ -256,7 +260,7 @@ def tune_batch(arch: str, cu: int, quick: bool = False, log=print):
         log(f"# tune batch {c}: {tot * 1e3:.1f} ms (auto + FP64-only)")
     best = dict(choose_min(res))
     out = {"batch_group_steps": 8, "batch_bfs_rounds": 4, "batch_small_cap": 512, "batch_small_levels": 64,
-           "batch_level_grid": 1024}
+           "batch_level_grid": 1024, **BATCH_OPTIONAL_DEFAULTS}
     out.update(best)
     return arch, cu, out
 

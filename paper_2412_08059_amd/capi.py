@@ -99,7 +99,8 @@ class mpcg_tuning(ctypes.Structure):
                 ("bfs_persist", ctypes.c_int32), ("batch_group_steps", ctypes.c_int32),
                 ("batch_bfs_rounds", ctypes.c_int32), ("batch_small_cap", ctypes.c_int32),
                 ("batch_small_levels", ctypes.c_int32), ("batch_level_grid", ctypes.c_int32),
-                ("bfs_dia", ctypes.c_int32), ("bfs_dia_tiles", ctypes.c_int32), ("sell_stream", ctypes.c_int32)]
+                ("bfs_dia", ctypes.c_int32), ("bfs_dia_tiles", ctypes.c_int32), ("sell_stream", ctypes.c_int32),
+                ("batch_runahead", ctypes.c_int32), ("batch_bfs_band", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -20,6 +20,7 @@
 #include "batch_internal.hpp"
 #include "knn.hpp"
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -28,6 +29,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -38,6 +40,10 @@ namespace batch {
 namespace {
 
 constexpr int kGroupSteps = 8;
+// While a system is being admitted or waits for its features, a group lasts
+// about this long (the host sees each group's state copy one group later):
+// at least two steps, at most the tuned length, a power of two.
+constexpr double kGroupLatencyMs = 4.0;
 constexpr int kBfsRoundsPerPump = 4;   // BFS rounds enqueued per pass of the BFS stream
 constexpr double kEpsClass[8] = {0, 0, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7};
 
@@ -101,8 +107,11 @@ struct Slot {
     int64_t entry0 = -1, padded = 0;
     int adm = 0;            // 1: rows and scan enqueued, 2: live
     bool autoe = false;
-    int feat = 0;           // 0 not started, 1 sweep 1, 2 sweep 2, 3 finishing, 4 done (or none), 5 cancelling
+    int feat = 0;           // 0 not started, 1 sweep 1, 2 sweep 2, 3 finishing, 4 done (or none), 5 cancelling,
+                            // 6 band 2BFS launched
     bool want_start = false;   // admitted: start the 2BFS on the BFS stream
+    bool band = false;         // the 2BFS runs as the one-wave band sweeps (entries within |i - j| <= 31)
+    int32_t nh = 0;            // the most offsets of one sign in the band's pattern
     bool fast = false;         // the first sweep runs from vertex 0 without components
     bool want_bfs_cancel = false;
     bool bfs_ready = false;    // pdiam, t, u, ncomp are in f
@@ -145,7 +154,10 @@ struct Engine {
     int32_t list_slices = 0, list_sys = 0;
     // step groups captured as graphs, by (product grid, per-system grid)
     hipStream_t cap = nullptr;
-    std::map<std::pair<int32_t, int32_t>, hipGraphExec_t> graphs;
+    std::map<std::tuple<int32_t, int32_t, int32_t>, hipGraphExec_t> graphs;   // (grids, steps)
+    double step_ms = 0.0;         // recent wall time per step (from the copies' arrival)
+    double t_last_copy = 0.0;     // when the previous group's copy was processed
+    int len_k[2] = {0, 0};        // steps of the group of each copy slot
     bool graphs_ok = true;
     // scheduling knobs: mpcg_tuning's batch_* fields
     int small_levels = kSmallBfsLevels;
@@ -154,6 +166,7 @@ struct Engine {
     int bfs_rounds = kBfsRoundsPerPump;
     int level_grid = 1024;
     int group_steps = kGroupSteps;
+    bool band_on = true;   // batch_bfs_band
 
     std::mutex mu;
     std::condition_variable cv;
@@ -171,7 +184,8 @@ struct Engine {
     void run();
     bool step_once();
     bool rebuild_list();
-    bool launch_group();
+    bool launch_group(int len);
+    int group_len() const;
     void drop_graphs();
     void finish(Slot &sl, const BSys *M, int status_override);
     void recompute_hi();
@@ -362,7 +376,8 @@ void Engine::process(const BSys *m, int32_t cnt, int64_t gi)
         if (sl.cancel) {
             launch_cancel(s, a, i);
             sl.cancel = false;
-            if (sl.autoe && sl.feat >= 1 && sl.feat <= 3) sl.want_bfs_cancel = true;   // feat 5, then 4
+            if (sl.autoe && ((sl.feat >= 1 && sl.feat <= 3) || sl.feat == 6))
+                sl.want_bfs_cancel = true;   // feat 5, then 4
             else if (sl.feat != 5) sl.feat = 4;   // 5: a BFS cancel is already under way
             sl.want_start = false;
             sl.guard = group + 1;
@@ -370,8 +385,13 @@ void Engine::process(const BSys *m, int32_t cnt, int64_t gi)
         }
         if (sl.autoe && sl.feat < 4) {
             if (sl.feat == 0 && !sl.want_start) {
-                if (M.err || M.mode == kDone) sl.feat = 4;   // malformed input or nothing to solve: no features
-                else sl.want_start = true;
+                if (M.err || M.mode == kDone) {
+                    sl.feat = 4;   // malformed input or nothing to solve: no features
+                } else {
+                    sl.want_start = true;
+                    sl.band = band_on && M.bw <= kBandMaxBw && (sl.f.n + 31) / 32 <= kBandMaxWords;
+                    sl.nh = std::max(__builtin_popcountll(M.doffs & 0xffffffffull), __builtin_popcountll(M.doffs >> 33));
+                }
             } else if (sl.feat == 3 && sl.bfs_ready && !(M.mode == kCg32 && M.k0_used == 0)) {
                 sl.f.k0_used = M.k0_used;
                 double sum = 0.0;
@@ -419,6 +439,27 @@ bool Engine::process_bfs(const BSys *m, int32_t cnt)
         const BSys &M = m[i];
         if (sl.feat == 5) {   // the BFS cancel ran before this copy
             sl.feat = 4;
+            continue;
+        }
+        if (sl.feat == 6) {   // the band sweeps ran before this copy
+            if (M.bfs_mode == kBfsDone) {
+                sl.f.pdiam = M.pdiam;
+                sl.f.bfs_t = M.bfs_t;
+                sl.f.bfs_u = M.bfs_u;
+                sl.f.n_components = M.ncomp;
+                sl.bfs_ready = true;
+                sl.feat = 3;
+            } else if (M.band_fail == 2) {   // not connected: the components, then the level kernels
+                launch_bfs_start(sb, a, i, (int32_t)sl.f.n);
+                sl.fast = false;
+                sl.feat = 1;
+                enq = true;
+            } else {   // frontier too wide for the window: the level kernels
+                launch_bfs_fast_start(sb, a, i, (int32_t)sl.f.n);
+                sl.fast = true;
+                sl.feat = 1;
+                enq = true;
+            }
             continue;
         }
         if (sl.feat < 1 || sl.feat > 3) continue;
@@ -469,6 +510,7 @@ bool Engine::bfs_pump()
     // transitions enqueued from the copy need a copy behind them
     bool enq = !b_inflight && bmirror_n > 0 ? process_bfs(bmirror, bmirror_n) : false;
     bool run = false;
+    BandList bl[4] = {};
     for (int32_t i = 0; i < (int32_t)slots.size(); ++i) {
         Slot &sl = slots[i];
         if (!sl.used || !sl.autoe) continue;
@@ -479,15 +521,33 @@ bool Engine::bfs_pump()
             enq = true;
         }
         if (sl.want_start) {
-            launch_bfs_fast_start(sb, a, i, (int32_t)sl.f.n);
-            sl.fast = true;
+            if (sl.band) {
+                // one launch per class of offset counts: a launch unrolls its
+                // level for the most offsets its systems have
+                launch_band_masks(sb, a, i, sl.nslices);
+                const int c = sl.nh <= 4 ? 0 : sl.nh <= 8 ? 1 : sl.nh <= 16 ? 2 : 3;
+                BandList &l = bl[c];
+                l.slot[l.cnt++] = i;
+                l.nh_max = std::max(l.nh_max, sl.nh);
+                l.nw_max = std::max(l.nw_max, (int32_t)((sl.f.n + 31) / 32));
+                if (l.cnt == kBandList) {
+                    launch_bfs_band(sb, a, l);
+                    l = BandList{};
+                }
+                sl.feat = 6;
+            } else {
+                launch_bfs_fast_start(sb, a, i, (int32_t)sl.f.n);
+                sl.fast = true;
+                sl.feat = 1;
+            }
             sl.want_start = false;
-            sl.feat = 1;
             enq = true;
         }
         if (sl.feat == 1 || sl.feat == 2) run = true;
-        if ((sl.feat == 3 && !sl.bfs_ready) || sl.feat == 5) enq = true;   // waiting for a copy that shows the result
+        if ((sl.feat == 3 && !sl.bfs_ready) || sl.feat == 5 || sl.feat == 6)
+            enq = true;   // waiting for a copy that shows the result
     }
+    for (const BandList &l : bl) launch_bfs_band(sb, a, l);   // nothing for an empty list
     if (run)
         for (int r = 0; r < bfs_rounds; ++r) launch_bfs_round(sb, a, hi_sys, small_levels, small_cap, small_work, level_grid);
     if (hipGetLastError() != hipSuccess) return false;
@@ -557,12 +617,12 @@ void Engine::drop_graphs()
 
 // One group of steps: a graph replay when the group is captured (once per
 // pair of grid sizes), else plain launches.
-bool Engine::launch_group()
+bool Engine::launch_group(int len)
 {
     const int32_t gsl = coarse_grid((list_slices + kSlicesPerBlock - 1) / kSlicesPerBlock);
     const int32_t gsys = coarse_grid(list_sys);
     if (graphs_ok) {
-        const auto key = std::make_pair(gsl, gsys);
+        const auto key = std::make_tuple(gsl, gsys, (int32_t)len);
         auto it = graphs.find(key);
         if (it == graphs.end()) {
             if (graphs.size() >= 64) drop_graphs();
@@ -570,7 +630,7 @@ bool Engine::launch_group()
             hipGraphExec_t ex = nullptr;
             bool ok = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
             if (ok) {
-                for (int j = 0; j < group_steps; ++j) launch_step(cap, a, gsl, gsys);
+                for (int j = 0; j < len; ++j) launch_step(cap, a, gsl, gsys);
                 ok = hipStreamEndCapture(cap, &g) == hipSuccess && g != nullptr;
             }
             ok = ok && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
@@ -584,8 +644,23 @@ bool Engine::launch_group()
         }
         if (graphs_ok) return hipGraphLaunch(it->second, s) == hipSuccess;
     }
-    for (int j = 0; j < group_steps; ++j) launch_step(s, a, gsl, gsys);
+    for (int j = 0; j < len; ++j) launch_step(s, a, gsl, gsys);
     return hipGetLastError() == hipSuccess;
+}
+
+// Steps of the next group: the tuned length, or shorter while a system is
+// being admitted or waits for its features (their latency is counted in
+// groups).
+int Engine::group_len() const
+{
+    bool waiting = false;
+    for (const auto &sl : slots)
+        if (sl.used && !sl.retiring && (sl.adm == 1 || (sl.autoe && sl.feat < 4))) waiting = true;
+    if (!waiting || step_ms <= 0.0) return group_steps;
+    int want = (int)(kGroupLatencyMs / step_ms);
+    int len = 2;
+    while (len * 2 <= want && len * 2 <= group_steps) len *= 2;
+    return len < group_steps ? len : group_steps;
 }
 
 bool Engine::step_once()
@@ -627,7 +702,9 @@ bool Engine::step_once()
     if (!bfs_pump()) return false;
     const int k = (int)(group & 1);
     if (list_dirty && !rebuild_list()) return false;
-    if (any_live && list_sys > 0 && !launch_group()) return false;
+    const int len = group_len();
+    len_k[k] = any_live && list_sys > 0 ? len : 0;
+    if (any_live && list_sys > 0 && !launch_group(len)) return false;
     if (hipGetLastError() != hipSuccess) return false;
     mirror_n[k] = hi_sys;
     mirror_group[k] = group;
@@ -645,6 +722,10 @@ bool Engine::step_once()
             if (!bfs_pump()) return false;
             std::this_thread::sleep_for(std::chrono::microseconds(20));
         }
+        // the previous group ran since the copy before it was processed
+        const double t = now_ms();
+        if (t_last_copy > 0.0 && len_k[kp] > 0) step_ms = (t - t_last_copy) / len_k[kp];
+        t_last_copy = t;
         process(mirror[kp], mirror_n[kp], group - 1);
         if (failed) return false;
     }
@@ -718,6 +799,8 @@ Engine *engine_create(int device, const mpcg_options &opt, const mpcg_tuning &tu
     // nontemporal matrix loads where the arena's FP64 matrices (8-byte values,
     // 4-byte columns) can exceed the Infinity Cache, unless the tuning says
     e->a.nt = tune.sell_stream < 0 ? (max_entries * 12 > kInfinityCacheBytes ? 1 : 0) : tune.sell_stream;
+    e->a.hold = tune.batch_runahead == 0 ? 1 : 0;
+    e->band_on = tune.batch_bfs_band != 0;
     e->slots.resize(max_sys);
     e->finals.resize(max_sys);
     e->slices.init(max_slices);

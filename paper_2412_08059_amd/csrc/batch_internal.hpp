@@ -41,8 +41,9 @@ enum Mode : int32_t {
 
 enum RestartSrc : int32_t { kSrcX32 = 0, kSrcX64 = 1, kSrcZero = 2, kSrcSnap = 3 };
 
-// Why a system's FP32 run-ahead stopped before its eps1 was known.
-enum RunAheadStop : int32_t { kRaNone = 0, kRaBreakdown = 1, kRaMaxit = 2, kRaAllCrossed = 3 };
+// Why a system's FP32 run-ahead stopped before its eps1 was known (kRaWait:
+// the engine holds systems after their k0 prefix until eps1 is known).
+enum RunAheadStop : int32_t { kRaNone = 0, kRaBreakdown = 1, kRaMaxit = 2, kRaAllCrossed = 3, kRaWait = 4 };
 
 enum BfsMode : int32_t {
     kBfsNone = 0,
@@ -86,7 +87,10 @@ struct alignas(256) BSys {
     int32_t bfs_u, small, bfs_err;         // bfs_err: kErrGuard from the BFS kernels
     int32_t vis_lvl;                       // BArena::vis of the system matches dist after this level
     int32_t reached;                       // vertices the first sweep reached (counted at its end)
-    int32_t reached_pad;
+    int32_t bw;                            // max |i - j| over the entries (admission)
+    unsigned long long doffs;              // bit d + 32: some entry at j - i = d, 0 < |d| <= 31 (admission)
+    int32_t band_fail;                     // band 2BFS: 1 frontier too wide for its window, 2 not connected
+    int32_t band_pad;
     int64_t padded;                        // SELL-64 entries of the system (admission scan)
     unsigned long long comp_best;
     int64_t item0;                         // first BFS work item of this system in the current level
@@ -108,6 +112,9 @@ struct BArena {
     float *snap32;                         // kNumEps copies of x~, copy t at t * max_slices * 64
     int32_t *dist, *q0, *q1, *label, *tarr;
     uint32_t *vis;                         // visited bits of the small-level BFS, one per row
+    uint32_t *dm;                          // band 2BFS: per 32-row word w of the row space, 64 words
+                                           // dm[w * 64 + d + 32], bit b: row 32 w + b is reached from
+                                           // row 32 w + b - d (an entry at offset d of that row)
     unsigned long long *best;
     // per entry
     int32_t *col;
@@ -125,6 +132,7 @@ struct BArena {
     int32_t *step_cnt;                     // [0] = listed slices, [1] = listed systems
     int32_t acc32;                         // dot_acc = 1: FP32-phase dot products accumulate in FP32
     int32_t nt;                            // the step product reads the matrices with nontemporal loads
+    int32_t hold;                          // Algorithm II: hold after the k0 prefix until eps1 is set
 };
 
 // One launch's share of a work-list rebuild: entries first .. first + n - 1
@@ -174,6 +182,20 @@ void launch_step(hipStream_t s, const BArena &a, int32_t grid_slices, int32_t gr
 // one of its blocks stops, so that wide frontiers do not set the round time.
 void launch_bfs_round(hipStream_t s, const BArena &a, int32_t hi_sys, int small_levels, int small_cap,
                       int64_t small_work, int level_grid);
+// Band 2BFS of the systems whose entries all lie within |i - j| <= 31 (one
+// wave per system, both sweeps in one launch; bit-parallel levels over a
+// window of 64 words that follows the frontier).  The system's words of dm
+// are formed first (launch_band_masks, one system); the sweeps leave
+// bfs_mode = kBfsDone with pdiam, t, u, ncomp = 1, or band_fail set.
+constexpr int kBandList = 200;          // systems per launch (keeps the argument under 4 KB)
+constexpr int kBandMaxWords = 28672;    // rows / 32 of the largest system (its visited bits in LDS)
+constexpr int kBandMaxBw = 31;   // offsets d + 32 fit bits 1..63 of a 64-bit mask
+struct BandList {
+    int32_t cnt, nh_max, nw_max, pad_;   // nh_max: the most offsets of one sign; nw_max: the most 32-row words
+    int32_t slot[kBandList];
+};
+void launch_band_masks(hipStream_t s, const BArena &a, int32_t sys, int32_t nslices);
+void launch_bfs_band(hipStream_t s, const BArena &a, const BandList &l);
 // host-driven transitions of one system of n rows
 void launch_bfs_start(hipStream_t s, const BArena &a, int32_t sys, int32_t n);        // CC + sweep-1 seeds
 // first sweep from vertex 0 alone, every vertex labelled with it (no

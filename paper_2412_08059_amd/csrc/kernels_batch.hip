@@ -134,6 +134,7 @@ size_t arena_bytes(int32_t max_sys, int32_t max_slices, int64_t max_entries)
     t += up256(8 * rows) * 6 + up256(4 * rows) * 5;                   // FP64 and FP32 vectors
     t += up256(4 * rows * kNumEps);                                   // run-ahead copies of x~
     t += up256(4 * rows) * 5 + up256(8 * rows) + up256(rows / 8);     // BFS
+    t += up256(8 * rows);                                             // band 2BFS masks
     t += up256(4 * e) + up256(8 * e) + up256(4 * e);                  // col, v64, v32
     t += up256(4 * (size_t)max_sys) * 2 + up256(8 * (size_t)max_sys) + 256 + 256;
     t += up256(8 * sl) + up256(4 * (size_t)max_sys) + 256;            // step work list
@@ -174,6 +175,7 @@ BArena carve(void *base, int32_t max_sys, int32_t max_slices, int64_t max_entrie
     a.tarr = reinterpret_cast<int32_t *>(take(4 * rows));
     a.best = reinterpret_cast<unsigned long long *>(take(8 * rows));
     a.vis = reinterpret_cast<uint32_t *>(take(rows / 8));
+    a.dm = reinterpret_cast<uint32_t *>(take(8 * rows));
     a.col = reinterpret_cast<int32_t *>(take(4 * e));
     a.v64 = reinterpret_cast<double *>(take(8 * e));
     a.v32 = reinterpret_cast<float *>(take(4 * e));
@@ -302,7 +304,8 @@ k_admit_entries(BArena a, int32_t sys, const void *rp, int rp_i64, const int32_t
     const int64_t base = S.entry0 + a.slice_off[sl] + lane;
     const int len = a.rowlen[g];
     const int64_t lo = i < S.n ? rp_at(rp, rp_i64, i) : 0;
-    int err = 0, prev = -1;
+    int err = 0, prev = -1, bw = 0;
+    unsigned long long offs = 0ull;   // the band 2BFS's offsets
     for (int k = 0; k < W; ++k) {
         int cg = (int)g;
         double v = 0.0;
@@ -314,13 +317,26 @@ k_admit_entries(BArena a, int32_t sys, const void *rp, int rp_i64, const int32_t
             if (!isfinite(v)) err |= kErrNonFiniteA;
             prev = c;
             cg = S.row0 + (c >= 0 && c < S.n ? c : 0);
+            const int d = cg - (int)g;
+            const int ad = d < 0 ? -d : d;
+            bw = ad > bw ? ad : bw;
+            if (d != 0 && ad <= kBandMaxBw) offs |= 1ull << (d + 32);
         }
         a.col[base + (int64_t)k * 64] = cg;
         a.v64[base + (int64_t)k * 64] = v;
         a.v32[base + (int64_t)k * 64] = (float)v;
     }
-    for (int o = 32; o > 0; o >>= 1) err |= __shfl_xor(err, o, 64);
-    if (lane == 0 && err) atomicOr(&a.sys[sys].err, err);
+    for (int o = 32; o > 0; o >>= 1) {
+        err |= __shfl_xor(err, o, 64);
+        const int b2 = __shfl_xor(bw, o, 64);
+        bw = b2 > bw ? b2 : bw;
+        offs |= __shfl_xor(offs, o, 64);
+    }
+    if (lane == 0) {
+        if (err) atomicOr(&a.sys[sys].err, err);
+        if (bw) atomicMax(&a.sys[sys].bw, bw);
+        if (offs) atomicOr(&a.sys[sys].doffs, offs);
+    }
 }
 
 // Start state.  Host-filled fields (options, ranges) are already in place.
@@ -460,6 +476,11 @@ __global__ void k_set_eps(BArena a, int32_t sys, double eps1, int32_t ci)
         S.upd = 0;
         S.ph_it = 0;
         S.mode = kRestart;
+    } else if (S.mode == kHold && S.ra_stop == kRaWait) {
+        // held right after the k0 prefix, eps1 not yet crossed: the FP32
+        // phase continues with the eps1 test
+        S.ra_stop = kRaNone;
+        S.mode = kCg32;
     } else if (S.mode == kHold) {
         S.flags |= S.ra_stop == kRaBreakdown ? MPCG_FLAG_FP32_BREAKDOWN : MPCG_FLAG_FP32_MAXIT;
         S.relres_sp = sqrt(S.gamma) / sb;
@@ -718,8 +739,9 @@ __global__ void __launch_bounds__(kBlock) k_b_scalar2(BArena a)
         if (prefix && (S.n1 >= S.k0 || g == 0.0)) S.k0_used = S.n1;
         if (prefix && S.n1 < S.k0 && g != 0.0) return;   // Algorithm II: k0 iterations first
         if (S.auto_eps && !S.eps_set) {
-            // run-ahead until eps1 is known: record the first crossing of
-            // each candidate (x~ is copied by the next product)
+            // until eps1 is known: record the first crossing of each
+            // candidate (x~ is copied by the next product); then either hold
+            // (a.hold) or run ahead
             const double rg = sqrt(g);
             int due = 0, left = 0;
             for (int t = 0; t < kNumEps; ++t) {
@@ -733,7 +755,22 @@ __global__ void __launch_bounds__(kBlock) k_b_scalar2(BArena a)
                 }
             }
             S.snap_mask = due;
-            if (left == 0) {
+            if (a.hold) {
+                // Until the loosest candidate is crossed every choice of eps1
+                // needs these iterations; from the first crossing on they may
+                // be wasted, so the system waits there for eps1 without taking
+                // bandwidth from the others (no iteration past the chosen
+                // eps1, no speculative FP64 phase that the choice may
+                // discard).  k_set_eps resumes it from the state the
+                // sequential method stops in, as after a run-ahead.
+                if (due) {
+                    S.ra_stop = left == 0 ? kRaAllCrossed : kRaWait;
+                    S.mode = kHold;
+                } else if (S.n1 >= S.maxit1) {
+                    S.ra_stop = kRaMaxit;
+                    S.mode = kHold;
+                }
+            } else if (left == 0) {
                 // every candidate crossed before eps1 is known: the FP64 phase
                 // starts now from the tightest candidate's state (x~ of this
                 // iteration); k_set_eps keeps it when the chosen candidate
@@ -1362,6 +1399,222 @@ void launch_bfs_finish(hipStream_t s, const BArena &a, int32_t sys, int32_t n)
     hipLaunchKernelGGL(k_b_argmax, dim3(g), dim3(kBlock), 0, s, a, sys, 0);
     hipLaunchKernelGGL(k_b_comp_best, dim3(g), dim3(kBlock), 0, s, a, sys);
     hipLaunchKernelGGL(k_b_feat_final, dim3(1), dim3(64), 0, s, a, sys);
+}
+
+// ------------------------------------------------------------ band 2BFS --
+//
+// A system whose entries all lie within |i - j| <= 31 has, for every offset
+// d = j - i present, a bit vector over its rows: bit v of word d says that
+// row v - d has an entry at offset d, i.e. the edge (v - d) -> v.  One level
+// of a sweep is then, for every 32-row word of the window, the OR over the
+// offsets of (that vector AND the frontier shifted by d), minus the visited
+// rows: each row of the next level is found from the rows that list it,
+// exactly the vertices a level that expands the frontier's rows finds.  A
+// wave keeps 64 words (2,048 rows) of the frontier in registers, one per
+// lane, and the words of the offsets' vectors for the same rows in LDS; the
+// window moves with the frontier.  The frontier of a band moves by at most
+// one word per level, so a level touches only the window; a frontier wider
+// than 62 words (it cannot occur on a band swept from one end) ends the
+// attempt and the system takes the level kernels.
+
+// The system's words of dm are ORed into below: zero them first.
+__global__ void __launch_bounds__(kBlock) k_band_clear(BArena a, int32_t sys)
+{
+    const BSys &S = a.sys[sys];
+    const int64_t words = (int64_t)((S.n + 31) >> 5) * 64;
+    uint32_t *dw = a.dm + (size_t)(S.row0 >> 5) * 64;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < words; i += (int64_t)gridDim.x * kBlock)
+        dw[i] = 0u;
+}
+
+// Wave per slice: for each offset d present, the slice's rows that have an
+// entry at d (a ballot) mark rows u + d of dm's word d, i.e. 64 bits placed
+// at row 64 j + d, across up to three words.
+__global__ void __launch_bounds__(kBlock) k_band_masks(BArena a, int32_t sys)
+{
+    const BSys &S = a.sys[sys];
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * kSlicesPerBlock + (threadIdx.x >> 6);
+    if (j >= S.nslices) return;
+    const int sl = S.slice0 + j;
+    const int g = S.row0 + j * 64 + lane;
+    const int len = a.rowlen[g];
+    const int64_t base = S.entry0 + a.slice_off[sl] + lane;
+    unsigned long long om = 0ull;
+    for (int k = 0; k < len; ++k) {
+        const int d = a.col[base + (int64_t)k * 64] - g;
+        if (d != 0 && d >= -kBandMaxBw && d <= kBandMaxBw) om |= 1ull << (d + 32);
+    }
+    const int nw = (S.n + 31) >> 5;
+    uint32_t *dw = a.dm + (size_t)(S.row0 >> 5) * 64;
+    unsigned long long pres = S.doffs;   // the same in every lane: a wave-uniform loop
+    while (pres) {
+        const int k = __ffsll(pres) - 1;
+        pres &= pres - 1ull;
+        const unsigned long long b = __ballot((om >> k) & 1ull);
+        if (b == 0ull) continue;
+        const int d = k - 32;
+        const int first = 64 * j + d;                   // local row of bit 0 (may be negative)
+        const int w0 = first >= 0 ? first >> 5 : -((31 - first) >> 5);   // floor(first / 32)
+        const int sh = first - 32 * w0;                 // 0..31
+        const unsigned long long lo = b << sh;
+        if (lane < 3) {
+            const uint32_t part = lane == 0 ? (uint32_t)lo
+                                  : lane == 1 ? (uint32_t)(lo >> 32)
+                                              : (sh ? (uint32_t)(b >> (64 - sh)) : 0u);
+            const int w = w0 + lane;
+            if (part && w >= 0 && w < nw) atomicOr(&dw[(size_t)w * 64 + k], part);
+        }
+    }
+}
+
+// The offsets' words of one window position, in registers: lane l holds
+// word W0 + l of every listed offset (zero outside the system).  Offsets
+// d < 0 first (slots 1..31 of the offset mask), then d > 0 (slots 33..63).
+template <int NH>
+struct BandOffs {
+    int nneg, npos;
+    int sneg[NH], spos[NH];           // dm slots
+    uint32_t mneg[NH], mpos[NH];      // the window's words
+};
+
+template <int NH>
+__device__ inline void band_load(const uint32_t *dw, int W0, int nw, BandOffs<NH> &o)
+{
+    const int w = W0 + (int)threadIdx.x;
+    const bool in = w >= 0 && w < nw;
+    const uint32_t *p = dw + (size_t)(in ? w : 0) * 64;
+#pragma unroll
+    for (int k = 0; k < NH; ++k) {
+        o.mneg[k] = (in && k < o.nneg) ? p[o.sneg[k]] : 0u;
+        o.mpos[k] = (in && k < o.npos) ? p[o.spos[k]] : 0u;
+    }
+}
+
+// One sweep from local row src.  Returns false when the frontier outgrows
+// the window; else ecc (the last level), far (its smallest row) and reached.
+// V (LDS) holds the system's visited bits; the window's words of it live in
+// a register per lane between slides.
+template <int NH>
+__device__ inline bool band_sweep(const uint32_t *dw, int n, int nw, BandOffs<NH> &o, uint32_t *V, int src,
+                                  int &ecc, int &far, int &reached)
+{
+    const int lane = threadIdx.x;
+    for (int w = lane; w < nw; w += 64) V[w] = 0u;
+    __syncthreads();
+    int W0 = (src >> 5) - 31;
+    band_load<NH>(dw, W0, nw, o);
+    uint32_t F = lane == 31 ? (1u << (src & 31)) : 0u;
+    int w = W0 + lane;
+    uint32_t Vr = (w >= 0 && w < nw) ? F : 0xffffffffu;   // rows outside the system count as visited
+    ecc = 0;
+    far = src;
+    int cnt = lane == 31 ? 1 : 0;
+    bool ok = true;
+    for (int lev = 0; lev < n; ++lev) {   // every level reaches a new row: at most n - 1 of them
+        const uint32_t up = __shfl_up(F, 1, 64), dn = __shfl_down(F, 1, 64);
+        const uint32_t fp = lane == 0 ? 0u : up, fn = lane == 63 ? 0u : dn;
+        // bit b of a term: frontier row 32 (W0 + lane) + b - d, for the rows listed under d
+        // (the words of unlisted k are zero: no branch per offset)
+        uint32_t acc = 0u;
+#pragma unroll
+        for (int k = 0; k < NH; ++k) {
+            acc |= __builtin_amdgcn_alignbit(fn, F, 32 - o.sneg[k]) & o.mneg[k];   // -d = 32 - slot
+            acc |= __builtin_amdgcn_alignbit(F, fp, 64 - o.spos[k]) & o.mpos[k];   // 32 - d
+        }
+        const uint32_t nv = acc & ~Vr;
+        const unsigned long long any = __ballot(nv != 0u);
+        if (any == 0ull) break;
+        Vr |= nv;
+        F = nv;
+        ++ecc;
+        cnt += __popc(nv);
+        const int lo = __ffsll(any) - 1, hi = 63 - __clzll(any);
+        const uint32_t nlo = __builtin_amdgcn_readlane(nv, lo);
+        far = (W0 + lo) * 32 + __ffs(nlo) - 1;
+        if (lo == 0 || hi == 63) {
+            if (hi - lo > 61) {
+                ok = false;
+                break;
+            }
+            if (w >= 0 && w < nw) V[w] = Vr;
+            // moving up: the frontier's first word to lane 1; down: its last to lane 62
+            const int W0n = hi == 63 ? W0 + lo - 1 : W0 + hi - 62;
+            const int from = lane + (W0n - W0);
+            const uint32_t Fs = __shfl(F, from & 63, 64);
+            F = (from >= 0 && from < 64) ? Fs : 0u;
+            W0 = W0n;
+            w = W0 + lane;
+            __syncthreads();
+            Vr = (w >= 0 && w < nw) ? V[w] : 0xffffffffu;
+            band_load<NH>(dw, W0, nw, o);
+        }
+    }
+    for (int o2 = 32; o2 > 0; o2 >>= 1) cnt += __shfl_xor(cnt, o2, 64);
+    reached = cnt;
+    return ok;
+}
+
+// One wave per listed system: both sweeps (from row 0, then from the first
+// sweep's far row), the result in the system's BFS fields.  NH: the most
+// offsets of one sign the launch's systems have.
+template <int NH>
+__global__ void __launch_bounds__(64) k_bfs_band(BArena a, BandList L)
+{
+    extern __shared__ uint32_t band_vis[];
+    if ((int)blockIdx.x >= L.cnt) return;
+    BSys &S = a.sys[L.slot[blockIdx.x]];
+    const int lane = threadIdx.x;
+    const int n = S.n, nw = (n + 31) >> 5;
+    const unsigned long long pres = S.doffs;
+    BandOffs<NH> o;
+    {
+        unsigned long long mn = pres & 0xffffffffull, mp = pres >> 33;   // slots 1..31; 33..63 (d = 1..31)
+        o.nneg = __popcll(mn);
+        o.npos = __popcll(mp);
+#pragma unroll
+        for (int k = 0; k < NH; ++k) {
+            o.sneg[k] = mn ? __ffsll(mn) - 1 : 0;
+            mn &= mn - 1ull;
+            o.spos[k] = mp ? __ffsll(mp) + 32 : 0;
+            mp &= mp - 1ull;
+        }
+    }
+    const uint32_t *dw = a.dm + (size_t)(S.row0 >> 5) * 64;
+    int ecc1 = 0, t = 0, reached = 0, ecc2 = 0, u = 0, r2 = 0;
+    int fail = 0;
+    if (o.nneg > NH || o.npos > NH || nw > L.nw_max) fail = 1;   // the launch does not fit it (host error)
+    else if (!band_sweep<NH>(dw, n, nw, o, band_vis, 0, ecc1, t, reached)) fail = 1;
+    else if (reached != n) fail = 2;
+    else if (!band_sweep<NH>(dw, n, nw, o, band_vis, t, ecc2, u, r2)) fail = 1;
+    if (lane == 0) {
+        S.band_fail = fail;
+        S.reached = reached;
+        if (!fail) {
+            S.pdiam = ecc2;
+            S.bfs_t = t;
+            S.bfs_u = u;
+            S.ncomp = 1;
+            S.bfs_mode = kBfsDone;
+        }
+    }
+}
+
+void launch_band_masks(hipStream_t s, const BArena &a, int32_t sys, int32_t nslices)
+{
+    hipLaunchKernelGGL(k_band_clear, dim3(rows_grid(nslices * 64)), dim3(kBlock), 0, s, a, sys);
+    hipLaunchKernelGGL(k_band_masks, dim3((nslices + kSlicesPerBlock - 1) / kSlicesPerBlock), dim3(kBlock), 0, s,
+                       a, sys);
+}
+
+void launch_bfs_band(hipStream_t s, const BArena &a, const BandList &l)
+{
+    if (l.cnt <= 0) return;
+    const size_t lds = sizeof(uint32_t) * (size_t)l.nw_max;
+    if (l.nh_max <= 4) hipLaunchKernelGGL(k_bfs_band<4>, dim3(l.cnt), dim3(64), lds, s, a, l);
+    else if (l.nh_max <= 8) hipLaunchKernelGGL(k_bfs_band<8>, dim3(l.cnt), dim3(64), lds, s, a, l);
+    else if (l.nh_max <= 16) hipLaunchKernelGGL(k_bfs_band<16>, dim3(l.cnt), dim3(64), lds, s, a, l);
+    else hipLaunchKernelGGL(k_bfs_band<31>, dim3(l.cnt), dim3(64), lds, s, a, l);
 }
 
 // ------------------------------------------------------- admission (host) --

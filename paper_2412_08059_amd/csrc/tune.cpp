@@ -5,6 +5,7 @@
 //   solve <arch> <cu> <idx16> <lenlog> <nlog> <sell_batch> <sell_whole_batch> <sell_split> <bfs_grid>
 //         <bfs_grid_shared> <bfs_persist> [<bfs_dia> [<bfs_dia_tiles> [<sell_stream>]]]
 //   batch <arch> <cu> <group_steps> <bfs_rounds> <small_cap> <small_levels> <level_grid>
+//         [<runahead> [<bfs_band>]]
 
 #include "tune.hpp"
 
@@ -32,6 +33,8 @@ mpcg_tuning tune_defaults()
     t.bfs_dia = 1;
     t.bfs_dia_tiles = 1;
     t.sell_stream = -1;
+    t.batch_runahead = 0;
+    t.batch_bfs_band = 1;
     return t;
 }
 
@@ -44,7 +47,8 @@ bool tune_valid(const mpcg_tuning &t)
            t.batch_bfs_rounds <= 64 && t.batch_small_cap >= 1 && t.batch_small_cap <= 2048 &&
            t.batch_small_levels >= 1 && t.batch_small_levels <= 4096 && t.batch_level_grid >= 1 &&
            t.batch_level_grid <= 65536 && t.bfs_dia >= 0 && t.bfs_dia <= 2 &&
-           (t.bfs_dia_tiles == 0 || t.bfs_dia_tiles == 1) && t.sell_stream >= -1 && t.sell_stream <= 1;
+           (t.bfs_dia_tiles == 0 || t.bfs_dia_tiles == 1) && t.sell_stream >= -1 && t.sell_stream <= 1 &&
+           (t.batch_runahead == 0 || t.batch_runahead == 1) && (t.batch_bfs_band == 0 || t.batch_bfs_band == 1);
 }
 
 int32_t tune_lenlog(int64_t n, int64_t nnz)
@@ -94,10 +98,10 @@ int tune_load(const char *path, TuneTable *out)
         } else if (!std::strcmp(kind, "batch")) {
             mpcg_tuning t = tune_defaults();
             int cu = 0;
-            const int got = std::sscanf(p, "%*s %*s %d %d %d %d %d %d", &cu, &t.batch_group_steps,
+            const int got = std::sscanf(p, "%*s %*s %d %d %d %d %d %d %d %d", &cu, &t.batch_group_steps,
                                         &t.batch_bfs_rounds, &t.batch_small_cap, &t.batch_small_levels,
-                                        &t.batch_level_grid);
-            ok = got == 6 && tune_valid(t);
+                                        &t.batch_level_grid, &t.batch_runahead, &t.batch_bfs_band);
+            ok = got >= 6 && got <= 8 && tune_valid(t);   // the last two fields may be absent (defaults)
             if (ok) {
                 tb.has_batch = true;
                 tb.batch_arch = arch;

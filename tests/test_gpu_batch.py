@@ -110,21 +110,30 @@ def test_batch_mix_matches_oracle(engine, torch_mod):
         _check_against_oracle(a, b, e, st, x, model)
 
 
-def test_batch_run_ahead_restarts_from_the_crossing(engine, torch_mod):
-    """Features that arrive long after the FP32 run-ahead has passed every
+@pytest.mark.parametrize("runahead,band", [(1, 0), (0, 0), (0, 1)])
+def test_batch_run_ahead_restarts_from_the_crossing(torch_mod, runahead, band):
+    """Features that arrive long after the FP32 phase has passed every
     candidate eps1: a path-like band (tridiagonal, mu = 1.1, n = 50000) has a
     2BFS of 2 x 49999 levels while its CG crosses 1e-7 within a few dozen
-    iterations.  The FP64 restart must start from the copy of x~ taken at the
-    chosen class's first crossing -- the state the sequential Algorithm II
-    stops in -- so the result matches the oracle's Algorithm II."""
+    iterations (with the level kernels; the band sweeps take a few ms).
+    Whether the system runs ahead (copies of x~ at each crossing, a
+    speculative FP64 phase) or holds after its k0 prefix, the FP64 restart
+    must start from the state the sequential Algorithm II stops in, so the
+    result matches the oracle's Algorithm II."""
+    from paper_2412_08059_amd import BatchSolver
     from workloads import paper_family as PF
     model = oracle.load_model(TEST_MODEL)
     a, b, req = _make(torch_mod, "band_path_auto", lambda: PF.random_banded(50_000, 3, 1.0, 1.1, seed=3), 0.0,
                       seed=17)
-    (rid,) = engine.submit([req])
-    st, x = engine.wait_all([rid], timeout_s=120)[rid]
-    print(f"  band_path_auto: status={st.status} n1={st.n1} n2={st.n2} cls={st.eps1_class} "
-          f"pdiam={st.feat.pdiam} t_feat={st.t_feat_ms:.1f} ms", flush=True)
+    eng = BatchSolver(100_000, 1_000_000, 4, model=TEST_MODEL,
+                      tuning={"batch_runahead": runahead, "batch_bfs_band": band})
+    try:
+        (rid,) = eng.submit([req])
+        st, x = eng.wait_all([rid], timeout_s=120)[rid]
+    finally:
+        eng.close()
+    print(f"  band_path_auto runahead={runahead} band={band}: status={st.status} n1={st.n1} n2={st.n2} "
+          f"cls={st.eps1_class} pdiam={st.feat.pdiam} t_feat={st.t_feat_ms:.1f} ms", flush=True)
     assert st.feat.pdiam == 49_999
     _check_against_oracle(a, b, 0.0, st, x, model)
 
@@ -240,7 +249,9 @@ def test_batch_bfs_schedule_does_not_change_results(torch_mod, monkeypatch):
     however its levels are scheduled: the largest frontier the one-block kernel
     takes (8 / 512 / 2,048) and the levels one of its launches may expand
     (1 / 64 / 4,096) change which kernel expands which level, how often a
-    system's visited bits are rebuilt from dist and when the features arrive.
+    system's visited bits are rebuilt from dist and when the features arrive;
+    the bands take the one-wave band sweeps or the level kernels, and the
+    systems hold after their k0 prefix or run ahead.
     An ER graph of more than 2^20 rows takes the path that claims vertices in
     HBM (smaller systems keep their visited set in LDS); every system's
     features are checked against the oracle's 2BFS."""
@@ -254,9 +265,10 @@ def test_batch_bfs_schedule_does_not_change_results(torch_mod, monkeypatch):
             ("er_1100000", lambda: W.er_laplacian(1_100_000, 16, seed=13))]
     mats = [(nm, g()) for nm, g in gens]
     print("schedules x " + ", ".join(f"{nm} (n={a.n})" for nm, a in mats), flush=True)
-    schedules = [{}, {"batch_small_cap": 2048, "batch_small_levels": 4096},
+    schedules = [{}, {"batch_small_cap": 2048, "batch_small_levels": 4096, "batch_bfs_band": 0},
                  {"batch_small_cap": 8, "batch_small_levels": 1, "batch_group_steps": 3, "batch_bfs_rounds": 2,
-                  "batch_level_grid": 96}]
+                  "batch_level_grid": 96, "batch_runahead": 1, "batch_bfs_band": 0},
+                 {"batch_runahead": 1}]
     runs = []
     for env in schedules:
         eng = BatchSolver(1_300_000, 40_000_000, 16, model=TEST_MODEL, tuning=env or None)
@@ -280,3 +292,57 @@ def test_batch_bfs_schedule_does_not_change_results(torch_mod, monkeypatch):
         for r in runs[1:]:
             assert r[nm][:4] == runs[0][nm][:4], nm
             assert np.array_equal(r[nm][4], runs[0][nm][4]), nm
+
+
+def _fork(M, L):
+    """A tree of bandwidth 2 whose first sweep ends inside the row range: a
+    path up the even rows 0 .. 2M, from 2M one branch back down the odd rows
+    to row 1 and one up rows 2M + 1 .. 2M + L (M > L).  The far row of the
+    sweep from row 0 is row 1, and the sweep from there splits at row 2M into
+    two frontiers that move apart: wider than the band sweeps' window."""
+    n = 2 * M + 1 + L
+    edges = [(2 * i, 2 * i + 2) for i in range(M)] + [(2 * M, 2 * M - 1)]
+    edges += [(2 * i + 1, 2 * i - 1) for i in range(M - 1, 0, -1)]
+    edges += [(2 * M, 2 * M + 1)] + [(2 * M + k, 2 * M + k + 1) for k in range(1, L)]
+    r = np.array([e[0] for e in edges] + [e[1] for e in edges])
+    c = np.array([e[1] for e in edges] + [e[0] for e in edges])
+    adj = sp.csr_matrix((np.ones(len(r)), (r, c)), shape=(n, n))
+    lap = sp.diags(np.asarray(adj.sum(axis=1)).ravel() + 1.0) - adj
+    return W.CSR.from_scipy(lap.tocsr())
+
+
+def test_batch_band_2bfs_matches_oracle(torch_mod):
+    """The one-wave band sweeps: features equal to the oracle's 2BFS on bands
+    of half-width 1 to 31 (full and sparse), a band of 800,000 rows (its
+    visited bits take 100 KB of LDS), a system of fewer rows than one word,
+    and the two fallbacks -- a band that is not connected (components, then
+    the level kernels) and a fork whose second sweep outgrows the window --
+    each also with the band sweeps off."""
+    from paper_2412_08059_amd import BatchSolver
+    from workloads import paper_family as PF
+    band_blocks = lambda: W.CSR.from_scipy(sp.block_diag([W.banded(3000, 4, seed=1).to_scipy(),
+                                                           W.banded(2000, 6, seed=2).to_scipy()]).tocsr())
+    gens = [("band_w1", lambda: PF.random_banded(20_000, 3, 1.0, 1.1, seed=5)),
+            ("band_w8", lambda: W.banded(40_000, 8, seed=3)),
+            ("band_w31", lambda: W.banded(9_000, 31, seed=4)),
+            ("band_sparse17", lambda: PF.random_banded(30_000, 35, 0.3, 3.0, seed=6)),
+            ("band_800k", lambda: W.banded(800_000, 8, seed=7)),
+            ("band_tiny", lambda: W.banded(20, 3, seed=8)),
+            ("band_disconnected", band_blocks),
+            ("fork", lambda: _fork(3000, 2000))]
+    mats = [(nm, g()) for nm, g in gens]
+    for band in (1, 0):
+        eng = BatchSolver(1_000_000, 30_000_000, len(mats), model=TEST_MODEL, tuning={"batch_bfs_band": band})
+        try:
+            reqs = [_make(torch_mod, nm, lambda a=a: a, 0.0, seed=50 + i)[2] for i, (nm, a) in enumerate(mats)]
+            print(f"band sweeps {band}: " + ", ".join(f"{nm} (n={a.n})" for nm, a in mats), flush=True)
+            ids = eng.submit(reqs)
+            got = eng.wait_all(ids, timeout_s=300)
+        finally:
+            eng.close()
+        for rid, (nm, a) in zip(ids, mats):
+            st, _ = got[rid]
+            f = st.feat
+            print(f"  {nm}: status={st.status} pdiam={f.pdiam} t_feat={st.t_feat_ms:.1f} ms", flush=True)
+            assert st.status == 0 and st.relres_final_true <= EPS2, (nm, st.status)
+            assert (f.pdiam, f.bfs_t, f.bfs_u, f.n_components) == oracle.pseudo_diameter(a), nm

@@ -39,7 +39,8 @@ def test_table_roundtrip():
                                             bfs_grid_shared=32, bfs_persist=1, bfs_dia=2, bfs_dia_tiles=0,
                                             sell_stream=1)}
     batch = ("gfx950", 256, dict(batch_group_steps=4, batch_bfs_rounds=4, batch_small_cap=256,
-                                 batch_small_levels=64, batch_level_grid=512))
+                                 batch_small_levels=64, batch_level_grid=512, batch_runahead=1,
+                                 batch_bfs_band=0))
     text = at.format_table(rows, batch, comment="test")
     assert text.startswith("mpcg-tune 1\n")
     r2, b2 = at.parse_table(text)
@@ -47,6 +48,9 @@ def test_table_roundtrip():
     # rows written before the last three fields take their defaults (1, 1, -1)
     old_row = "mpcg-tune 1\nsolve gfx950 256 1 3 21 4 1 -1 128 64 0\n"
     r3, _ = at.parse_table(old_row)
+    # a batch row written before the last two fields takes their defaults (hold, band 2BFS on)
+    _, b4 = at.parse_table("mpcg-tune 1\nbatch gfx950 256 8 4 512 64 1024\n")
+    assert b4[2]["batch_runahead"] == 0 and b4[2]["batch_bfs_band"] == 1
     assert r3[("gfx950", 256, 1, 3, 21)]["bfs_dia"] == 1 and r3[("gfx950", 256, 1, 3, 21)]["bfs_dia_tiles"] == 1
     assert r3[("gfx950", 256, 1, 3, 21)]["sell_stream"] == -1
     with pytest.raises(ValueError):
