@@ -108,7 +108,9 @@ struct Slot {
     int adm = 0;            // 1: rows and scan enqueued, 2: live
     bool autoe = false;
     int feat = 0;           // 0 not started, 1 sweep 1, 2 sweep 2, 3 finishing, 4 done (or none), 5 cancelling,
-                            // 6 band 2BFS launched
+                            // 6 band sweeps running (band stream), 7 they gave up: the level kernels next
+    bool band_cancel = false;  // cancelled while its band sweeps run: no features once they end
+    bool fall_cc = false;      // feat 7: not connected, start with the components
     bool want_start = false;   // admitted: start the 2BFS on the BFS stream
     bool band = false;         // the 2BFS runs as the one-wave band sweeps (entries within |i - j| <= 31)
     int32_t nh = 0;            // the most offsets of one sign in the band's pattern
@@ -143,6 +145,12 @@ struct Engine {
     hipEvent_t evb = nullptr;
     BSys *bmirror = nullptr;
     int32_t bmirror_n = 0;
+    // band stream (the one-wave band sweeps) and its state copy
+    hipStream_t sband = nullptr;
+    hipEvent_t evband = nullptr;
+    BSys *bandmirror = nullptr;
+    int32_t bandmirror_n = 0;
+    bool band_inflight = false;
     bool b_inflight = false;
     std::vector<Slot> slots;
     std::vector<BSys> finals;           // state copy of a slot at completion
@@ -185,6 +193,8 @@ struct Engine {
     bool step_once();
     bool rebuild_list();
     bool launch_group(int len);
+    bool band_pump();
+    void process_band(const BSys *m, int32_t cnt);
     int group_len() const;
     void drop_graphs();
     void finish(Slot &sl, const BSys *M, int status_override);
@@ -376,8 +386,8 @@ void Engine::process(const BSys *m, int32_t cnt, int64_t gi)
         if (sl.cancel) {
             launch_cancel(s, a, i);
             sl.cancel = false;
-            if (sl.autoe && ((sl.feat >= 1 && sl.feat <= 3) || sl.feat == 6))
-                sl.want_bfs_cancel = true;   // feat 5, then 4
+            if (sl.autoe && sl.feat == 6) sl.band_cancel = true;   // feat 4 once the band sweeps have ended
+            else if (sl.autoe && sl.feat >= 1 && sl.feat <= 3) sl.want_bfs_cancel = true;   // feat 5, then 4
             else if (sl.feat != 5) sl.feat = 4;   // 5: a BFS cancel is already under way
             sl.want_start = false;
             sl.guard = group + 1;
@@ -389,7 +399,7 @@ void Engine::process(const BSys *m, int32_t cnt, int64_t gi)
                     sl.feat = 4;   // malformed input or nothing to solve: no features
                 } else {
                     sl.want_start = true;
-                    sl.band = band_on && M.bw <= kBandMaxBw && (sl.f.n + 31) / 32 <= kBandMaxWords;
+                    sl.band = band_on && M.bw <= kBandMaxBw;
                     sl.nh = std::max(__builtin_popcountll(M.doffs & 0xffffffffull), __builtin_popcountll(M.doffs >> 33));
                 }
             } else if (sl.feat == 3 && sl.bfs_ready && !(M.mode == kCg32 && M.k0_used == 0)) {
@@ -441,27 +451,6 @@ bool Engine::process_bfs(const BSys *m, int32_t cnt)
             sl.feat = 4;
             continue;
         }
-        if (sl.feat == 6) {   // the band sweeps ran before this copy
-            if (M.bfs_mode == kBfsDone) {
-                sl.f.pdiam = M.pdiam;
-                sl.f.bfs_t = M.bfs_t;
-                sl.f.bfs_u = M.bfs_u;
-                sl.f.n_components = M.ncomp;
-                sl.bfs_ready = true;
-                sl.feat = 3;
-            } else if (M.band_fail == 2) {   // not connected: the components, then the level kernels
-                launch_bfs_start(sb, a, i, (int32_t)sl.f.n);
-                sl.fast = false;
-                sl.feat = 1;
-                enq = true;
-            } else {   // frontier too wide for the window: the level kernels
-                launch_bfs_fast_start(sb, a, i, (int32_t)sl.f.n);
-                sl.fast = true;
-                sl.feat = 1;
-                enq = true;
-            }
-            continue;
-        }
         if (sl.feat < 1 || sl.feat > 3) continue;
         if (M.bfs_err & kErrGuard) {   // a bounded loop ran out: no features, the solve is cancelled
             launch_cancel(s, a, i);
@@ -497,10 +486,78 @@ bool Engine::process_bfs(const BSys *m, int32_t cnt)
     return enq;
 }
 
+// Results of the band stream's last launch (its own state copy, read for the
+// band systems' BFS fields only).
+void Engine::process_band(const BSys *m, int32_t cnt)
+{
+    for (int32_t i = 0; i < (int32_t)slots.size() && i < cnt; ++i) {
+        Slot &sl = slots[i];
+        if (!sl.used || sl.feat != 6) continue;
+        const BSys &M = m[i];
+        if (sl.band_cancel) {
+            sl.feat = 4;
+        } else if (M.bfs_mode == kBfsDone) {
+            sl.f.pdiam = M.pdiam;
+            sl.f.bfs_t = M.bfs_t;
+            sl.f.bfs_u = M.bfs_u;
+            sl.f.n_components = M.ncomp;
+            sl.bfs_ready = true;
+            sl.feat = 3;
+        } else {   // not connected (the components first), or a frontier too wide for the window
+            sl.fall_cc = M.band_fail == 2;
+            sl.feat = 7;
+        }
+    }
+}
+
+// The band stream, when idle: the systems waiting for band sweeps, grouped
+// by offset count (a launch unrolls its level for the most offsets its
+// systems have), then a state copy.  Runs beside the BFS stream, so a long
+// band does not hold up the level kernels' rounds.
+bool Engine::band_pump()
+{
+    if (band_inflight) {
+        const hipError_t q = hipEventQuery(evband);
+        if (q == hipErrorNotReady) return true;
+        if (q != hipSuccess) return false;
+        band_inflight = false;
+        process_band(bandmirror, bandmirror_n);
+    }
+    BandList bl[4] = {};
+    bool any = false;
+    for (int32_t i = 0; i < (int32_t)slots.size(); ++i) {
+        Slot &sl = slots[i];
+        if (!sl.used || !sl.autoe || !sl.want_start || !sl.band) continue;
+        launch_band_masks(sband, a, i, sl.nslices);
+        const int c = sl.nh <= 4 ? 0 : sl.nh <= 8 ? 1 : sl.nh <= 16 ? 2 : 3;
+        BandList &l = bl[c];
+        l.slot[l.cnt++] = i;
+        l.nh_max = std::max(l.nh_max, sl.nh);
+        if (l.cnt == kBandList) {
+            launch_bfs_band(sband, a, l);
+            l = BandList{};
+        }
+        sl.want_start = false;
+        sl.feat = 6;
+        any = true;
+    }
+    if (!any) return true;
+    for (const BandList &l : bl) launch_bfs_band(sband, a, l);   // nothing for an empty list
+    if (hipGetLastError() != hipSuccess) return false;
+    bandmirror_n = hi_sys;
+    if (hipMemcpyAsync(bandmirror, a.sys, sizeof(BSys) * (size_t)hi_sys, hipMemcpyDeviceToHost, sband) !=
+            hipSuccess ||
+        hipEventRecord(evband, sband) != hipSuccess)
+        return false;
+    band_inflight = true;
+    return true;
+}
+
 // One pass of the BFS stream, if it is idle: its last copy is processed,
 // then transitions, rounds and the next copy are enqueued.  Never blocks.
 bool Engine::bfs_pump()
 {
+    if (!band_pump()) return false;
     if (b_inflight) {
         const hipError_t q = hipEventQuery(evb);
         if (q == hipErrorNotReady) return true;
@@ -510,7 +567,6 @@ bool Engine::bfs_pump()
     // transitions enqueued from the copy need a copy behind them
     bool enq = !b_inflight && bmirror_n > 0 ? process_bfs(bmirror, bmirror_n) : false;
     bool run = false;
-    BandList bl[4] = {};
     for (int32_t i = 0; i < (int32_t)slots.size(); ++i) {
         Slot &sl = slots[i];
         if (!sl.used || !sl.autoe) continue;
@@ -520,34 +576,23 @@ bool Engine::bfs_pump()
             sl.feat = 5;
             enq = true;
         }
-        if (sl.want_start) {
-            if (sl.band) {
-                // one launch per class of offset counts: a launch unrolls its
-                // level for the most offsets its systems have
-                launch_band_masks(sb, a, i, sl.nslices);
-                const int c = sl.nh <= 4 ? 0 : sl.nh <= 8 ? 1 : sl.nh <= 16 ? 2 : 3;
-                BandList &l = bl[c];
-                l.slot[l.cnt++] = i;
-                l.nh_max = std::max(l.nh_max, sl.nh);
-                l.nw_max = std::max(l.nw_max, (int32_t)((sl.f.n + 31) / 32));
-                if (l.cnt == kBandList) {
-                    launch_bfs_band(sb, a, l);
-                    l = BandList{};
-                }
-                sl.feat = 6;
-            } else {
-                launch_bfs_fast_start(sb, a, i, (int32_t)sl.f.n);
-                sl.fast = true;
-                sl.feat = 1;
-            }
+        if (sl.want_start && !sl.band) {
+            launch_bfs_fast_start(sb, a, i, (int32_t)sl.f.n);
+            sl.fast = true;
             sl.want_start = false;
+            sl.feat = 1;
+            enq = true;
+        }
+        if (sl.feat == 7) {   // the band sweeps gave up: the level kernels
+            if (sl.fall_cc) launch_bfs_start(sb, a, i, (int32_t)sl.f.n);
+            else launch_bfs_fast_start(sb, a, i, (int32_t)sl.f.n);
+            sl.fast = !sl.fall_cc;
+            sl.feat = 1;
             enq = true;
         }
         if (sl.feat == 1 || sl.feat == 2) run = true;
-        if ((sl.feat == 3 && !sl.bfs_ready) || sl.feat == 5 || sl.feat == 6)
-            enq = true;   // waiting for a copy that shows the result
+        if ((sl.feat == 3 && !sl.bfs_ready) || sl.feat == 5) enq = true;   // waiting for a copy that shows the result
     }
-    for (const BandList &l : bl) launch_bfs_band(sb, a, l);   // nothing for an empty list
     if (run)
         for (int r = 0; r < bfs_rounds; ++r) launch_bfs_round(sb, a, hi_sys, small_levels, small_cap, small_work, level_grid);
     if (hipGetLastError() != hipSuccess) return false;
@@ -755,6 +800,7 @@ void Engine::run()
         if (!step_once()) {
             (void)hipStreamSynchronize(s);
             (void)hipStreamSynchronize(sb);
+            (void)hipStreamSynchronize(sband);
             fail_all(MPCG_EDEVICE);
             std::unique_lock<std::mutex> lk(mu);
             while (!stop) cv.wait_for(lk, std::chrono::milliseconds(20));
@@ -763,6 +809,7 @@ void Engine::run()
     }
     (void)hipStreamSynchronize(s);
     (void)hipStreamSynchronize(sb);
+    (void)hipStreamSynchronize(sband);
 }
 
 // ------------------------------------------------------------ interface --
@@ -807,6 +854,10 @@ Engine *engine_create(int device, const mpcg_options &opt, const mpcg_tuning &tu
     e->entries.init(max_entries);
     bool ok = hipStreamCreateWithFlags(&e->s, hipStreamNonBlocking) == hipSuccess &&
               hipStreamCreateWithFlags(&e->sb, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&e->sband, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&e->evband, hipEventDisableTiming) == hipSuccess &&
+              hipHostMalloc((void **)&e->bandmirror, sizeof(BSys) * (size_t)max_sys, hipHostMallocDefault) ==
+                  hipSuccess &&
               hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&e->evb, hipEventDisableTiming) == hipSuccess &&
               hipHostMalloc((void **)&e->bmirror, sizeof(BSys) * (size_t)max_sys, hipHostMallocDefault) ==
@@ -849,6 +900,12 @@ void engine_destroy(Engine *e)
         (void)hipStreamSynchronize(e->sb);
         (void)hipStreamDestroy(e->sb);
     }
+    if (e->sband) {
+        (void)hipStreamSynchronize(e->sband);
+        (void)hipStreamDestroy(e->sband);
+    }
+    if (e->evband) (void)hipEventDestroy(e->evband);
+    if (e->bandmirror) (void)hipHostFree(e->bandmirror);
     e->drop_graphs();
     if (e->cap) (void)hipStreamDestroy(e->cap);
     if (e->evb) (void)hipEventDestroy(e->evb);

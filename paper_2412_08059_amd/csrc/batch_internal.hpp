@@ -111,7 +111,7 @@ struct BArena {
     float *x32, *r32, *q32, *dA32, *dB32;
     float *snap32;                         // kNumEps copies of x~, copy t at t * max_slices * 64
     int32_t *dist, *q0, *q1, *label, *tarr;
-    uint32_t *vis;                         // visited bits of the small-level BFS, one per row
+    uint32_t *vis;                         // visited bits of the small-level BFS and of the band sweeps, one per row
     uint32_t *dm;                          // band 2BFS: per 32-row word w of the row space, 64 words
                                            // dm[w * 64 + d + 32], bit b: row 32 w + b is reached from
                                            // row 32 w + b - d (an entry at offset d of that row)
@@ -188,10 +188,9 @@ void launch_bfs_round(hipStream_t s, const BArena &a, int32_t hi_sys, int small_
 // are formed first (launch_band_masks, one system); the sweeps leave
 // bfs_mode = kBfsDone with pdiam, t, u, ncomp = 1, or band_fail set.
 constexpr int kBandList = 200;          // systems per launch (keeps the argument under 4 KB)
-constexpr int kBandMaxWords = 28672;    // rows / 32 of the largest system (its visited bits in LDS)
-constexpr int kBandMaxBw = 31;   // offsets d + 32 fit bits 1..63 of a 64-bit mask
+constexpr int kBandMaxBw = 31;          // offsets d + 32 fit bits 1..63 of a 64-bit mask
 struct BandList {
-    int32_t cnt, nh_max, nw_max, pad_;   // nh_max: the most offsets of one sign; nw_max: the most 32-row words
+    int32_t cnt, nh_max;                // nh_max: the most offsets of one sign among the listed systems
     int32_t slot[kBandList];
 };
 void launch_band_masks(hipStream_t s, const BArena &a, int32_t sys, int32_t nslices);

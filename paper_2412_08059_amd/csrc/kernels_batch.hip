@@ -1491,17 +1491,28 @@ __device__ inline void band_load(const uint32_t *dw, int W0, int nw, BandOffs<NH
     }
 }
 
+// V: the system's visited bits in HBM, touched only when the window moves
+// (the window's words live in a register per lane).  Another lane may have
+// written a word earlier: agent-scope accesses (no stale L1 line) after a
+// wait for this wave's stores.
+__device__ inline uint32_t band_vload(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void band_vstore(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // One sweep from local row src.  Returns false when the frontier outgrows
 // the window; else ecc (the last level), far (its smallest row) and reached.
-// V (LDS) holds the system's visited bits; the window's words of it live in
-// a register per lane between slides.
 template <int NH>
 __device__ inline bool band_sweep(const uint32_t *dw, int n, int nw, BandOffs<NH> &o, uint32_t *V, int src,
                                   int &ecc, int &far, int &reached)
 {
     const int lane = threadIdx.x;
-    for (int w = lane; w < nw; w += 64) V[w] = 0u;
-    __syncthreads();
+    for (int w = lane; w < nw; w += 64) band_vstore(&V[w], 0u);
+    __threadfence_block();
     int W0 = (src >> 5) - 31;
     band_load<NH>(dw, W0, nw, o);
     uint32_t F = lane == 31 ? (1u << (src & 31)) : 0u;
@@ -1537,7 +1548,7 @@ __device__ inline bool band_sweep(const uint32_t *dw, int n, int nw, BandOffs<NH
                 ok = false;
                 break;
             }
-            if (w >= 0 && w < nw) V[w] = Vr;
+            if (w >= 0 && w < nw) band_vstore(&V[w], Vr);
             // moving up: the frontier's first word to lane 1; down: its last to lane 62
             const int W0n = hi == 63 ? W0 + lo - 1 : W0 + hi - 62;
             const int from = lane + (W0n - W0);
@@ -1545,8 +1556,8 @@ __device__ inline bool band_sweep(const uint32_t *dw, int n, int nw, BandOffs<NH
             F = (from >= 0 && from < 64) ? Fs : 0u;
             W0 = W0n;
             w = W0 + lane;
-            __syncthreads();
-            Vr = (w >= 0 && w < nw) ? V[w] : 0xffffffffu;
+            __threadfence_block();
+            Vr = (w >= 0 && w < nw) ? band_vload(&V[w]) : 0xffffffffu;
             band_load<NH>(dw, W0, nw, o);
         }
     }
@@ -1561,7 +1572,6 @@ __device__ inline bool band_sweep(const uint32_t *dw, int n, int nw, BandOffs<NH
 template <int NH>
 __global__ void __launch_bounds__(64) k_bfs_band(BArena a, BandList L)
 {
-    extern __shared__ uint32_t band_vis[];
     if ((int)blockIdx.x >= L.cnt) return;
     BSys &S = a.sys[L.slot[blockIdx.x]];
     const int lane = threadIdx.x;
@@ -1581,12 +1591,13 @@ __global__ void __launch_bounds__(64) k_bfs_band(BArena a, BandList L)
         }
     }
     const uint32_t *dw = a.dm + (size_t)(S.row0 >> 5) * 64;
+    uint32_t *V = a.vis + (S.row0 >> 5);
     int ecc1 = 0, t = 0, reached = 0, ecc2 = 0, u = 0, r2 = 0;
     int fail = 0;
-    if (o.nneg > NH || o.npos > NH || nw > L.nw_max) fail = 1;   // the launch does not fit it (host error)
-    else if (!band_sweep<NH>(dw, n, nw, o, band_vis, 0, ecc1, t, reached)) fail = 1;
+    if (o.nneg > NH || o.npos > NH) fail = 1;   // the launch's unrolling does not cover it (host error)
+    else if (!band_sweep<NH>(dw, n, nw, o, V, 0, ecc1, t, reached)) fail = 1;
     else if (reached != n) fail = 2;
-    else if (!band_sweep<NH>(dw, n, nw, o, band_vis, t, ecc2, u, r2)) fail = 1;
+    else if (!band_sweep<NH>(dw, n, nw, o, V, t, ecc2, u, r2)) fail = 1;
     if (lane == 0) {
         S.band_fail = fail;
         S.reached = reached;
@@ -1610,11 +1621,10 @@ void launch_band_masks(hipStream_t s, const BArena &a, int32_t sys, int32_t nsli
 void launch_bfs_band(hipStream_t s, const BArena &a, const BandList &l)
 {
     if (l.cnt <= 0) return;
-    const size_t lds = sizeof(uint32_t) * (size_t)l.nw_max;
-    if (l.nh_max <= 4) hipLaunchKernelGGL(k_bfs_band<4>, dim3(l.cnt), dim3(64), lds, s, a, l);
-    else if (l.nh_max <= 8) hipLaunchKernelGGL(k_bfs_band<8>, dim3(l.cnt), dim3(64), lds, s, a, l);
-    else if (l.nh_max <= 16) hipLaunchKernelGGL(k_bfs_band<16>, dim3(l.cnt), dim3(64), lds, s, a, l);
-    else hipLaunchKernelGGL(k_bfs_band<31>, dim3(l.cnt), dim3(64), lds, s, a, l);
+    if (l.nh_max <= 4) hipLaunchKernelGGL(k_bfs_band<4>, dim3(l.cnt), dim3(64), 0, s, a, l);
+    else if (l.nh_max <= 8) hipLaunchKernelGGL(k_bfs_band<8>, dim3(l.cnt), dim3(64), 0, s, a, l);
+    else if (l.nh_max <= 16) hipLaunchKernelGGL(k_bfs_band<16>, dim3(l.cnt), dim3(64), 0, s, a, l);
+    else hipLaunchKernelGGL(k_bfs_band<31>, dim3(l.cnt), dim3(64), 0, s, a, l);
 }
 
 // ------------------------------------------------------- admission (host) --

@@ -346,3 +346,25 @@ def test_batch_band_2bfs_matches_oracle(torch_mod):
             print(f"  {nm}: status={st.status} pdiam={f.pdiam} t_feat={st.t_feat_ms:.1f} ms", flush=True)
             assert st.status == 0 and st.relres_final_true <= EPS2, (nm, st.status)
             assert (f.pdiam, f.bfs_t, f.bfs_u, f.n_components) == oracle.pseudo_diameter(a), nm
+
+
+def test_batch_cancel_during_band_sweeps(torch_mod):
+    """A system cancelled while its band sweeps run (a band of 2,000,000 rows:
+    two sweeps of 250,000 levels) is reported cancelled -- or solved, if the
+    cancel came too late -- and its slot serves the next request."""
+    from paper_2412_08059_amd import BatchSolver, capi
+    eng = BatchSolver(2_100_000, 40_000_000, 2, model=TEST_MODEL)
+    try:
+        big = _make(torch_mod, "band_2m", lambda: W.banded(2_000_000, 8, seed=9), 0.0, seed=7)
+        (rid,) = eng.submit([big[2]])
+        time.sleep(0.05)
+        assert eng.cancel(rid) in (0, capi.MPCG_EINVAL)   # EINVAL: already reported
+        st, _ = eng.wait_all([rid], timeout_s=120)[rid]
+        print(f"  band_2m: status={st.status} t_feat={st.t_feat_ms:.1f} ms", flush=True)
+        assert st.status in (0, capi.MPCG_ECANCELED)
+        a, b, req = _make(torch_mod, "after", lambda: W.banded(5000, 8, seed=10), 0.0, seed=8)
+        (rid2,) = eng.submit([req])
+        st2, x2 = eng.wait_all([rid2], timeout_s=60)[rid2]
+        _check_against_oracle(a, b, 0.0, st2, x2, oracle.load_model(TEST_MODEL))
+    finally:
+        eng.close()
