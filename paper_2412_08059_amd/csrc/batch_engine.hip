@@ -12,10 +12,15 @@
 // the steps and at its own pace: whenever that stream is idle the thread
 // reads its last state copy (BFS fields only), enqueues the transitions it
 // calls for (sweep start, next sweep, finish, cancel) and a few BFS rounds,
-// then another copy.  After its k0 FP32 iterations a system runs ahead,
-// copying x~ at the first crossing of each candidate eps1, until its features
-// are in; the state it then restarts from is the one the sequential method
-// stops in, so its arithmetic does not depend on that pace.
+// then another copy.  Systems whose entries lie within |i - j| <= 31 take
+// both sweeps in one launch of one-wave bit-parallel levels on a third
+// stream with its own copy, so a long band holds up no one else's rounds.
+// After its k0 FP32 iterations a system continues in FP32 until it crosses
+// the loosest candidate eps1 and then waits there for its features (or, with
+// batch_runahead, runs ahead copying x~ at each candidate's first crossing);
+// the state it then restarts from is the one the sequential method stops in,
+// so its arithmetic does not depend on that pace.  While any system is being
+// admitted or waits for features, groups are shortened to a few ms.
 
 #include "batch_internal.hpp"
 #include "knn.hpp"
