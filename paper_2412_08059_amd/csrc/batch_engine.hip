@@ -115,6 +115,7 @@ struct Slot {
     int feat = 0;           // 0 not started, 1 sweep 1, 2 sweep 2, 3 finishing, 4 done (or none), 5 cancelling,
                             // 6 band sweeps running (band stream), 7 they gave up: the level kernels next
     bool band_cancel = false;  // cancelled while its band sweeps run: no features once they end
+    int split = -1;            // its CG product in two launches: 1 / 0, -1 until a copy shows admission
     bool fall_cc = false;      // feat 7: not connected, start with the components
     bool want_start = false;   // admitted: start the 2BFS on the BFS stream
     bool band = false;         // the 2BFS runs as the one-wave band sweeps (entries within |i - j| <= 31)
@@ -167,7 +168,7 @@ struct Engine {
     int32_t list_slices = 0, list_sys = 0;
     // step groups captured as graphs, by (product grid, per-system grid)
     hipStream_t cap = nullptr;
-    std::map<std::tuple<int32_t, int32_t, int32_t>, hipGraphExec_t> graphs;   // (grids, steps)
+    std::map<std::tuple<int32_t, int32_t, int32_t, int32_t>, hipGraphExec_t> graphs;   // (grids, steps, dir)
     double step_ms = 0.0;         // recent wall time per step (from the copies' arrival)
     double t_last_copy = 0.0;     // when the previous group's copy was processed
     int len_k[2] = {0, 0};        // steps of the group of each copy slot
@@ -198,6 +199,7 @@ struct Engine {
     bool step_once();
     bool rebuild_list();
     bool launch_group(int len);
+    bool dir_needed() const;
     bool band_pump();
     void process_band(const BSys *m, int32_t cnt);
     int group_len() const;
@@ -377,6 +379,7 @@ void Engine::process(const BSys *m, int32_t cnt, int64_t gi)
             list_dirty = true;
             continue;
         }
+        if (sl.split < 0) sl.split = M.split;   // this copy follows the admission (guard)
         if (sl.retiring) {
             if (gi >= sl.retire_group) {
                 finish(sl, &finals[i], 0);
@@ -672,7 +675,8 @@ bool Engine::launch_group(int len)
     const int32_t gsl = coarse_grid((list_slices + kSlicesPerBlock - 1) / kSlicesPerBlock);
     const int32_t gsys = coarse_grid(list_sys);
     if (graphs_ok) {
-        const auto key = std::make_tuple(gsl, gsys, (int32_t)len);
+        const bool dir = dir_needed();
+        const auto key = std::make_tuple(gsl, gsys, (int32_t)len, (int32_t)dir);
         auto it = graphs.find(key);
         if (it == graphs.end()) {
             if (graphs.size() >= 64) drop_graphs();
@@ -680,7 +684,7 @@ bool Engine::launch_group(int len)
             hipGraphExec_t ex = nullptr;
             bool ok = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
             if (ok) {
-                for (int j = 0; j < len; ++j) launch_step(cap, a, gsl, gsys);
+                for (int j = 0; j < len; ++j) launch_step(cap, a, gsl, gsys, dir);
                 ok = hipStreamEndCapture(cap, &g) == hipSuccess && g != nullptr;
             }
             ok = ok && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
@@ -694,8 +698,19 @@ bool Engine::launch_group(int len)
         }
         if (graphs_ok) return hipGraphLaunch(it->second, s) == hipSuccess;
     }
-    for (int j = 0; j < len; ++j) launch_step(s, a, gsl, gsys);
+    const bool dir = dir_needed();
+    for (int j = 0; j < len; ++j) launch_step(s, a, gsl, gsys, dir);
     return hipGetLastError() == hipSuccess;
+}
+
+// Some listed system may gather a stored direction: its split flag is set on
+// the device at admission and reaches the host one copy later, so a system
+// not yet seen counts as split.
+bool Engine::dir_needed() const
+{
+    for (const auto &sl : slots)
+        if (sl.used && !sl.retiring && sl.adm == 2 && sl.split != 0) return true;
+    return false;
 }
 
 // Steps of the next group: the tuned length, or shorter while a system is

@@ -90,7 +90,7 @@ struct alignas(256) BSys {
     int32_t bw;                            // max |i - j| over the entries (admission)
     unsigned long long doffs;              // bit d + 32: some entry at j - i = d, 0 < |d| <= 31 (admission)
     int32_t band_fail;                     // band 2BFS: 1 frontier too wide for its window, 2 not connected
-    int32_t band_pad;
+    int32_t split;                         // CG product in two launches (scattered columns, set at admission)
     int64_t padded;                        // SELL-64 entries of the system (admission scan)
     unsigned long long comp_best;
     int64_t item0;                         // first BFS work item of this system in the current level
@@ -167,7 +167,8 @@ void launch_fill_slices(hipStream_t s, const BArena &a);   // every slice unowne
 // blocks of four slices and grid_sys blocks of one system, at least the
 // listed counts (blocks past them return at once).
 void launch_worklist(hipStream_t s, const BArena &a, const ListChunk &c);
-void launch_step(hipStream_t s, const BArena &a, int32_t grid_slices, int32_t grid_sys);
+// dir: some listed system gathers a stored direction (k_b_dir first)
+void launch_step(hipStream_t s, const BArena &a, int32_t grid_slices, int32_t grid_sys, bool dir);
 
 // ---- 2BFS (BFS stream) ----
 // Kernels on the BFS stream write only the BFS fields of a system's state
@@ -189,6 +190,10 @@ void launch_bfs_round(hipStream_t s, const BArena &a, int32_t hi_sys, int small_
 // bfs_mode = kBfsDone with pdiam, t, u, ncomp = 1, or band_fail set.
 constexpr int kBandList = 200;          // systems per launch (keeps the argument under 4 KB)
 constexpr int kBandMaxBw = 31;          // offsets d + 32 fit bits 1..63 of a 64-bit mask
+// Systems whose entries reach farther than this from the diagonal gather
+// scattered columns: their CG product runs in two launches (k_b_dir forms
+// d, the product gathers it alone instead of r and d_old).
+constexpr int kSplitBw = 4096;
 struct BandList {
     int32_t cnt, nh_max;                // nh_max: the most offsets of one sign among the listed systems
     int32_t slot[kBandList];

@@ -347,6 +347,7 @@ __global__ void __launch_bounds__(kBlock) k_admit_finish(BArena a, int32_t sys, 
     const double g0 = a.acc32 ? sys_sum_f(a, S, 0, sm) : sys_sum(a, S, 0, sm);
     const double bb = sys_sum(a, S, 1, sm);
     if (threadIdx.x == 0) {
+        S.split = S.bw > kSplitBw ? 1 : 0;   // k_admit_entries has recorded the bandwidth
         S.bb = bb;
         S.gamma = g0;
         S.ph_it = 0;
@@ -511,6 +512,30 @@ __device__ inline double cg_product(const BArena &a, const BSys &S, const T *val
     const T beta = (T)S.beta;
     T *dnew = (j & 1) ? dB : dA;
     const T *dold = (j & 1) ? dA : dB;
+    if (S.split) {   // d_j was formed by k_b_dir: gather it alone
+        T acc = T(0);
+        const int W = wave_max_i32(len);
+        for (int k0 = 0; k0 < W; k0 += kLoadBatch) {
+            int c[kLoadBatch];
+            T v[kLoadBatch], g[kLoadBatch];
+#pragma unroll
+            for (int t = 0; t < kLoadBatch; ++t)
+                if (k0 + t < len) {
+                    c[t] = b_ld<NT>(a.col + base + (int64_t)(k0 + t) * 64);
+                    v[t] = b_ld<NT>(val + base + (int64_t)(k0 + t) * 64);
+                }
+#pragma unroll
+            for (int t = 0; t < kLoadBatch; ++t)
+                if (k0 + t < len) g[t] = dnew[c[t]];
+#pragma unroll
+            for (int t = 0; t < kLoadBatch; ++t)
+                if (k0 + t < len) acc = fma_b<T>(v[t], g[t], acc);
+        }
+        const T dn = dnew[row];
+        q[row] = acc;
+        if (sizeof(T) == 4 && a.acc32) return (double)wave_sum_f((float)dn * (float)acc);
+        return wave_sum_d((double)dn * (double)acc);
+    }
     T acc = T(0);
     const int W = wave_max_i32(len);
     for (int k0 = 0; k0 < W; k0 += kLoadBatch) {
@@ -1137,9 +1162,37 @@ void launch_worklist(hipStream_t s, const BArena &a, const ListChunk &c)
     hipLaunchKernelGGL(k_worklist, dim3(c.n > 0 ? c.n : 1), dim3(kBlock), 0, s, a, c);
 }
 
-void launch_step(hipStream_t s, const BArena &a, int32_t grid_slices, int32_t grid_sys)
+// Wave per slice of a split system in a CG phase: d_j = r_j + beta_j d_{j-1}
+// (d_0 = r_0), the value the fused product forms per gathered entry, stored
+// once for the product to gather (the same fma, so the same bits).
+template <typename T>
+__device__ inline void dir_rows(const BSys &S, const T *r, T *dA, T *dB, int row)
+{
+    const int j = S.ph_it;
+    T *dnew = (j & 1) ? dB : dA;
+    const T *dold = (j & 1) ? dA : dB;
+    dnew[row] = j == 0 ? r[row] : fma_b<T>((T)S.beta, dold[row], r[row]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_b_dir(BArena a)
+{
+    const int k = blockIdx.x * kSlicesPerBlock + (threadIdx.x >> 6);
+    if (k >= a.step_cnt[0]) return;
+    const int2 e = a.step_map[k];
+    const int sl = e.x, s = e.y;
+    if (s < 0) return;
+    const BSys &S = a.sys[s];
+    if (!S.split) return;
+    const int mode = S.mode;
+    const int row = sl * 64 + (threadIdx.x & 63);
+    if (mode == kCg32) dir_rows<float>(S, a.r32, a.dA32, a.dB32, row);
+    else if (mode == kCg64) dir_rows<double>(S, a.r64, a.dA64, a.dB64, row);
+}
+
+void launch_step(hipStream_t s, const BArena &a, int32_t grid_slices, int32_t grid_sys, bool dir)
 {
     if (grid_slices <= 0 || grid_sys <= 0) return;
+    if (dir) hipLaunchKernelGGL(k_b_dir, dim3(grid_slices), dim3(kBlock), 0, s, a);
     if (a.nt) hipLaunchKernelGGL(k_b_product<true>, dim3(grid_slices), dim3(kBlock), 0, s, a);
     else hipLaunchKernelGGL(k_b_product<false>, dim3(grid_slices), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_b_scalar1, dim3(grid_sys), dim3(kBlock), 0, s, a);
