@@ -208,6 +208,7 @@ struct Engine {
     void recompute_hi();
     void admit();
     void process(const BSys *m, int32_t cnt, int64_t gi);
+    void process_slots(const BSys *m, int32_t cnt, int64_t gi, AdmitList &l2);
     bool bfs_pump();
     bool process_bfs(const BSys *m, int32_t cnt);
     void fail_all(int status);
@@ -278,17 +279,32 @@ void Engine::fail_all(int status)
 // scan are enqueued (stage 2 runs once a state copy shows the scan's total).
 void Engine::admit()
 {
-    while (!local.empty()) {
+    // the systems admitted now share one launch per kernel of stage 1, and
+    // consecutive slots' staged states one copy
+    AdmitList l{};
+    int32_t run0 = 0, runn = 0;
+    auto flush_copy = [&]() {
+        if (runn > 0 && hipMemcpyAsync(&a.sys[run0], &stage[run0], sizeof(BSys) * (size_t)runn,
+                                       hipMemcpyHostToDevice, s) != hipSuccess)
+            failed = true;
+        runn = 0;
+    };
+    auto flush = [&]() {
+        flush_copy();
+        if (!failed) launch_admit_stage1(s, a, l);
+        l = AdmitList{};
+    };
+    while (!local.empty() && !failed) {
         int32_t slot = -1;
         for (int32_t i = 0; i < (int32_t)slots.size(); ++i)
             if (!slots[i].used) { slot = i; break; }
-        if (slot < 0) return;
+        if (slot < 0) break;
         Pending p = local.front();
         const mpcg_request &r = p.req;
         const int32_t n = (int32_t)r.A.n;
         const int32_t nsl = (n + 63) / 64;
         const int64_t s0 = slices.alloc(nsl);
-        if (s0 < 0) return;   // wait for space
+        if (s0 < 0) break;   // wait for space
         local.pop_front();
         Slot &sl = slots[slot];
         sl = Slot{};
@@ -325,12 +341,20 @@ void Engine::admit()
         S.lanes = lanes;
         S.eps2 = r.eps2;
         S.mode = kFree;
-        if (hipMemcpyAsync(&a.sys[slot], &S, sizeof(BSys), hipMemcpyHostToDevice, s) != hipSuccess) {
-            failed = true;
-            return;
+        if (runn > 0 && slot == run0 + runn) {
+            ++runn;
+        } else {
+            flush_copy();
+            run0 = slot;
+            runn = 1;
         }
-        launch_admit_rows(s, a, slot, r.A.row_ptr, r.A.row_ptr_is_i64, r.A.nnz, r.b, S.row0, n, S.slice0, nsl);
-        launch_admit_scan(s, a, slot);
+        const int k = l.cnt++;
+        l.sys[k] = slot;
+        l.nsl[k] = nsl;
+        l.rp[k] = r.A.row_ptr;
+        l.rp_i64[k] = r.A.row_ptr_is_i64;
+        l.b[k] = r.b;
+        if (l.cnt == kAdmitList) flush();
         {
             std::lock_guard<std::mutex> lk(mu);
             n_queued -= 1;
@@ -338,9 +362,17 @@ void Engine::admit()
         }
         recompute_hi();
     }
+    if (l.cnt > 0 || runn > 0) flush();
 }
 
 void Engine::process(const BSys *m, int32_t cnt, int64_t gi)
+{
+    AdmitList l2{};   // stage 2 of the systems whose scan this copy shows: one launch per kernel
+    process_slots(m, cnt, gi, l2);
+    if (!failed) launch_admit_stage2(s, a, l2);
+}
+
+void Engine::process_slots(const BSys *m, int32_t cnt, int64_t gi, AdmitList &l2)
 {
     for (int32_t i = 0; i < (int32_t)slots.size() && i < cnt; ++i) {
         Slot &sl = slots[i];
@@ -366,14 +398,19 @@ void Engine::process(const BSys *m, int32_t cnt, int64_t gi)
             }
             sl.entry0 = e0;
             stage[i].entry0 = e0;
-            if (hipMemcpyAsync(&a.sys[i].entry0, &stage[i].entry0, sizeof(int64_t), hipMemcpyHostToDevice, s) !=
-                hipSuccess) {
-                failed = true;
-                return;
+            const int k = l2.cnt++;
+            l2.sys[k] = i;
+            l2.nsl[k] = sl.nslices;
+            l2.rp[k] = sl.req.A.row_ptr;
+            l2.rp_i64[k] = sl.req.A.row_ptr_is_i64;
+            l2.col[k] = sl.req.A.col_idx;
+            l2.val[k] = sl.req.A.val;
+            l2.eps1[k] = sl.req.eps1;
+            l2.entry0[k] = e0;
+            if (l2.cnt == kAdmitList) {
+                launch_admit_stage2(s, a, l2);
+                l2 = AdmitList{};
             }
-            launch_admit_entries(s, a, i, sl.nslices, sl.req.A.row_ptr, sl.req.A.row_ptr_is_i64, sl.req.A.col_idx,
-                                 sl.req.A.val);
-            launch_admit_finish(s, a, i, sl.nslices, sl.req.eps1);
             sl.adm = 2;
             sl.guard = group + 1;
             list_dirty = true;

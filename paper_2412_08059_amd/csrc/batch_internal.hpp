@@ -147,14 +147,23 @@ struct ListChunk {
 size_t arena_bytes(int32_t max_sys, int32_t max_slices, int64_t max_entries);
 BArena carve(void *base, int32_t max_sys, int32_t max_slices, int64_t max_entries);
 
-// ---- admission (one system) ----
-void launch_admit_rows(hipStream_t s, const BArena &a, int32_t sys, const void *rp, int rp_i64, int64_t nnz,
-                       const double *b, int32_t row0, int32_t n, int32_t slice0, int32_t nslices);
-void launch_admit_scan(hipStream_t s, const BArena &a, int32_t sys);
-void launch_admit_entries(hipStream_t s, const BArena &a, int32_t sys, int32_t nslices, const void *rp,
-                          int rp_i64, const int32_t *col, const double *val);
-// start mode from the options, then the slices become visible to the step
-void launch_admit_finish(hipStream_t s, const BArena &a, int32_t sys, int32_t nslices, double eps1);
+// ---- admission, a list of systems per launch ----
+// Stage 1 (rows, padded-size scan) needs each system's staged BSys on the
+// device; stage 2 (entries, start state, publication) its entry range,
+// written into the BSys by the start-state kernel.
+constexpr int kAdmitList = 48;   // keeps the argument under 4 KB
+struct AdmitList {
+    int32_t cnt, pad_;
+    int32_t sys[kAdmitList], nsl[kAdmitList], rp_i64[kAdmitList];
+    const void *rp[kAdmitList];
+    const double *b[kAdmitList];
+    const int32_t *col[kAdmitList];
+    const double *val[kAdmitList];
+    double eps1[kAdmitList];
+    int64_t entry0[kAdmitList];
+};
+void launch_admit_stage1(hipStream_t s, const BArena &a, const AdmitList &l);
+void launch_admit_stage2(hipStream_t s, const BArena &a, const AdmitList &l);
 void launch_release(hipStream_t s, const BArena &a, int32_t sys, int32_t slice0, int32_t nslices);
 void launch_cancel(hipStream_t s, const BArena &a, int32_t sys);       // the solve (step stream)
 void launch_bfs_cancel(hipStream_t s, const BArena &a, int32_t sys);   // its 2BFS (BFS stream)

@@ -192,9 +192,9 @@ BArena carve(void *base, int32_t max_sys, int32_t max_slices, int64_t max_entrie
 
 // ------------------------------------------------------------ admission --
 
-__global__ void k_fill_slice_w(BArena a, int32_t slice0, int32_t nslices)
+__device__ inline void adm_fill(const BArena &a, int32_t slice0, int32_t nslices, int blk)
 {
-    const int j = blockIdx.x * kBlock + threadIdx.x;
+    const int j = blk * kBlock + threadIdx.x;
     if (j < nslices) a.slice_w[slice0 + j] = 0;
 }
 
@@ -213,11 +213,10 @@ void launch_fill_slices(hipStream_t s, const BArena &a)
 
 // Thread per (padded) row of the system: row length, slice width, b, the FP32
 // start r~ = float32(b), x = 0, and per-slice partials of r~.r~ and b.b.
-__global__ void __launch_bounds__(kBlock)
-k_admit_rows(BArena a, int32_t sys, const void *rp, int rp_i64, const double *b, int32_t row0, int32_t n,
-             int64_t nnz, int32_t slice0, int32_t nslices)
+__device__ inline void adm_rows(const BArena &a, int32_t sys, const void *rp, int rp_i64, const double *b,
+                                int32_t row0, int32_t n, int64_t nnz, int32_t slice0, int32_t nslices, int blk)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;   // local row
+    const int64_t i = (int64_t)blk * kBlock + threadIdx.x;   // local row
     if (i >= (int64_t)nslices * 64) return;
     const int64_t g = row0 + i;
     int err = 0, len = 0;
@@ -258,9 +257,8 @@ k_admit_rows(BArena a, int32_t sys, const void *rp, int rp_i64, const double *b,
 }
 
 // Padded entry offsets of the system's slices (local to its entry range).
-__global__ void __launch_bounds__(1024) k_admit_scan(BArena a, int32_t sys)
+__device__ inline void adm_scan(const BArena &a, int32_t sys, int64_t *part)
 {
-    __shared__ int64_t part[1024];
     BSys &S = a.sys[sys];
     const int ns = S.nslices, s0 = S.slice0;
     const int per = (ns + 1023) / 1024;
@@ -290,18 +288,18 @@ __global__ void __launch_bounds__(1024) k_admit_scan(BArena a, int32_t sys)
 // values checked; entries written column-major inside the slice with global
 // column indices.  Lanes past a row's length get a zero entry on their own
 // row, which the products never read (they stop at the row length).
-__global__ void __launch_bounds__(kBlock)
-k_admit_entries(BArena a, int32_t sys, const void *rp, int rp_i64, const int32_t *col, const double *val)
+__device__ inline void adm_entries(const BArena &a, int32_t sys, const void *rp, int rp_i64, const int32_t *col,
+                                   const double *val, int64_t entry0, int blk)
 {
     const BSys &S = a.sys[sys];
     const int lane = threadIdx.x & 63;
-    const int j = blockIdx.x * kSlicesPerBlock + (threadIdx.x >> 6);
+    const int j = blk * kSlicesPerBlock + (threadIdx.x >> 6);
     if (j >= S.nslices) return;
     const int sl = S.slice0 + j;
     const int64_t i = (int64_t)j * 64 + lane;
     const int64_t g = S.row0 + i;
     const int W = a.slice_w[sl];
-    const int64_t base = S.entry0 + a.slice_off[sl] + lane;
+    const int64_t base = entry0 + a.slice_off[sl] + lane;
     const int len = a.rowlen[g];
     const int64_t lo = i < S.n ? rp_at(rp, rp_i64, i) : 0;
     int err = 0, prev = -1, bw = 0;
@@ -340,14 +338,14 @@ k_admit_entries(BArena a, int32_t sys, const void *rp, int rp_i64, const int32_t
 }
 
 // Start state.  Host-filled fields (options, ranges) are already in place.
-__global__ void __launch_bounds__(kBlock) k_admit_finish(BArena a, int32_t sys, double eps1)
+__device__ inline void adm_finish(const BArena &a, int32_t sys, double eps1, int64_t entry0, double *sm)
 {
-    __shared__ double sm[kBlock / 64 + 1];
     BSys &S = a.sys[sys];
     const double g0 = a.acc32 ? sys_sum_f(a, S, 0, sm) : sys_sum(a, S, 0, sm);
     const double bb = sys_sum(a, S, 1, sm);
     if (threadIdx.x == 0) {
-        S.split = S.bw > kSplitBw ? 1 : 0;   // k_admit_entries has recorded the bandwidth
+        S.entry0 = entry0;
+        S.split = S.bw > kSplitBw ? 1 : 0;   // the entries' pass has recorded the bandwidth
         S.bb = bb;
         S.gamma = g0;
         S.ph_it = 0;
@@ -390,11 +388,77 @@ __global__ void __launch_bounds__(kBlock) k_admit_finish(BArena a, int32_t sys, 
 }
 
 // Marks the system's slices as live (after every admission kernel).
-__global__ void k_admit_publish(BArena a, int32_t sys)
+__device__ inline void adm_publish(const BArena &a, int32_t sys, int blk)
 {
     const BSys &S = a.sys[sys];
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < S.nslices; j += gridDim.x * blockDim.x)
-        a.sys_of_slice[S.slice0 + j] = sys;
+    const int j = blk * kBlock + threadIdx.x;
+    if (j < S.nslices) a.sys_of_slice[S.slice0 + j] = sys;
+}
+
+// ---- admission of a list of systems: one launch per stage ----
+//
+// The blocks of a launch are dealt to the listed systems in order, each
+// system taking as many as its slices need (spb slices per block); a block
+// finds its system by walking the list (at most kAdmitList entries).
+__device__ inline bool adm_block(const AdmitList &L, int spb, int &j, int &blk)
+{
+    int b = (int)blockIdx.x;
+    for (j = 0; j < L.cnt; ++j) {
+        const int nb = (L.nsl[j] + spb - 1) / spb;
+        if (b < nb) {
+            blk = b;
+            return true;
+        }
+        b -= nb;
+    }
+    return false;
+}
+
+// stage 1: slice widths zeroed (a launch of its own: the rows' pass takes
+// their maximum), then the rows' pass, then the padded-size scan
+__global__ void __launch_bounds__(kBlock) k_admit_fill_l(BArena a, AdmitList L)
+{
+    int j, blk;
+    if (!adm_block(L, kBlock, j, blk)) return;
+    const BSys &S = a.sys[L.sys[j]];
+    adm_fill(a, S.slice0, S.nslices, blk);
+}
+
+__global__ void __launch_bounds__(kBlock) k_admit_rows_l(BArena a, AdmitList L)
+{
+    int j, blk;
+    if (!adm_block(L, kSlicesPerBlock, j, blk)) return;
+    const BSys &S = a.sys[L.sys[j]];
+    adm_rows(a, L.sys[j], L.rp[j], L.rp_i64[j], L.b[j], S.row0, S.n, S.nnz, S.slice0, S.nslices, blk);
+}
+
+__global__ void __launch_bounds__(1024) k_admit_scan_l(BArena a, AdmitList L)
+{
+    __shared__ int64_t part[1024];
+    if ((int)blockIdx.x >= L.cnt) return;
+    adm_scan(a, L.sys[blockIdx.x], part);
+}
+
+// stage 2: entries, start state (block per system), publication
+__global__ void __launch_bounds__(kBlock) k_admit_entries_l(BArena a, AdmitList L)
+{
+    int j, blk;
+    if (!adm_block(L, kSlicesPerBlock, j, blk)) return;
+    adm_entries(a, L.sys[j], L.rp[j], L.rp_i64[j], L.col[j], L.val[j], L.entry0[j], blk);
+}
+
+__global__ void __launch_bounds__(kBlock) k_admit_finish_l(BArena a, AdmitList L)
+{
+    __shared__ double sm[kBlock / 64 + 1];
+    if ((int)blockIdx.x >= L.cnt) return;
+    adm_finish(a, L.sys[blockIdx.x], L.eps1[blockIdx.x], L.entry0[blockIdx.x], sm);
+}
+
+__global__ void __launch_bounds__(kBlock) k_admit_publish_l(BArena a, AdmitList L)
+{
+    int j, blk;
+    if (!adm_block(L, kBlock, j, blk)) return;
+    adm_publish(a, L.sys[j], blk);
 }
 
 __global__ void k_release(BArena a, int32_t sys, int32_t slice0, int32_t nslices)
@@ -1682,31 +1746,27 @@ void launch_bfs_band(hipStream_t s, const BArena &a, const BandList &l)
 
 // ------------------------------------------------------- admission (host) --
 
-void launch_admit_rows(hipStream_t s, const BArena &a, int32_t sys, const void *rp, int rp_i64, int64_t nnz,
-                       const double *b, int32_t row0, int32_t n, int32_t slice0, int32_t nslices)
+static int adm_grid(const AdmitList &l, int spb)
 {
-    hipLaunchKernelGGL(k_fill_slice_w, dim3((nslices + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a, slice0,
-                       nslices);
-    hipLaunchKernelGGL(k_admit_rows, dim3((nslices * 64 + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a, sys, rp,
-                       rp_i64, b, row0, n, nnz, slice0, nslices);
+    int g = 0;
+    for (int j = 0; j < l.cnt; ++j) g += (l.nsl[j] + spb - 1) / spb;
+    return g;
 }
 
-void launch_admit_scan(hipStream_t s, const BArena &a, int32_t sys)
+void launch_admit_stage1(hipStream_t s, const BArena &a, const AdmitList &l)
 {
-    hipLaunchKernelGGL(k_admit_scan, dim3(1), dim3(1024), 0, s, a, sys);
+    if (l.cnt <= 0) return;
+    hipLaunchKernelGGL(k_admit_fill_l, dim3(adm_grid(l, kBlock)), dim3(kBlock), 0, s, a, l);
+    hipLaunchKernelGGL(k_admit_rows_l, dim3(adm_grid(l, kSlicesPerBlock)), dim3(kBlock), 0, s, a, l);
+    hipLaunchKernelGGL(k_admit_scan_l, dim3(l.cnt), dim3(1024), 0, s, a, l);
 }
 
-void launch_admit_entries(hipStream_t s, const BArena &a, int32_t sys, int32_t nslices, const void *rp,
-                          int rp_i64, const int32_t *col, const double *val)
+void launch_admit_stage2(hipStream_t s, const BArena &a, const AdmitList &l)
 {
-    hipLaunchKernelGGL(k_admit_entries, dim3((nslices + kSlicesPerBlock - 1) / kSlicesPerBlock), dim3(kBlock), 0,
-                       s, a, sys, rp, rp_i64, col, val);
-}
-
-void launch_admit_finish(hipStream_t s, const BArena &a, int32_t sys, int32_t nslices, double eps1)
-{
-    hipLaunchKernelGGL(k_admit_finish, dim3(1), dim3(kBlock), 0, s, a, sys, eps1);
-    hipLaunchKernelGGL(k_admit_publish, dim3(rows_grid(nslices)), dim3(kBlock), 0, s, a, sys);
+    if (l.cnt <= 0) return;
+    hipLaunchKernelGGL(k_admit_entries_l, dim3(adm_grid(l, kSlicesPerBlock)), dim3(kBlock), 0, s, a, l);
+    hipLaunchKernelGGL(k_admit_finish_l, dim3(l.cnt), dim3(kBlock), 0, s, a, l);
+    hipLaunchKernelGGL(k_admit_publish_l, dim3(adm_grid(l, kBlock)), dim3(kBlock), 0, s, a, l);
 }
 
 void launch_release(hipStream_t s, const BArena &a, int32_t sys, int32_t slice0, int32_t nslices)
