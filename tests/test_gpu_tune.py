@@ -111,9 +111,12 @@ def test_table_lookup_and_overrides(torch_mod, tmp_path):
         d = s.tuning_for(1000, 2000, 1)
         assert (d["sell_batch"], d["sell_whole_batch"], d["sell_split"], d["bfs_grid"]) == (4, 1, -1, 128)
         assert (d["bfs_dia"], d["bfs_dia_tiles"], d["sell_stream"]) == (1, 1, -1)
+        assert (d["batch_runahead"], d["batch_bfs_band"]) == (0, 1)
         # a malformed table is refused and the loaded one stays
         bad = tmp_path / "bad.txt"
         bad.write_text("mpcg-tune 1\nsolve gfx950 256 1 3\n")
+        assert capi.mpcg_load_tuning(s.ctx, str(bad)) == capi.MPCG_EINVAL
+        bad.write_text("mpcg-tune 1\nbatch gfx950 256 8 4 512 64 1024 3 1\n")   # runahead out of range
         assert capi.mpcg_load_tuning(s.ctx, str(bad)) == capi.MPCG_EINVAL
         assert s.tuning_for(2 ** 13, 7 * 2 ** 13, 64)["sell_batch"] == 8
         # explicit values win over the table; None goes back to it
@@ -123,6 +126,8 @@ def test_table_lookup_and_overrides(torch_mod, tmp_path):
         assert capi.mpcg_set_tuning(s.ctx, {"bfs_dia": 3}) == capi.MPCG_EINVAL
         assert capi.mpcg_set_tuning(s.ctx, {"bfs_dia_tiles": 2}) == capi.MPCG_EINVAL
         assert capi.mpcg_set_tuning(s.ctx, {"sell_stream": 2}) == capi.MPCG_EINVAL
+        assert capi.mpcg_set_tuning(s.ctx, {"batch_runahead": 2}) == capi.MPCG_EINVAL
+        assert capi.mpcg_set_tuning(s.ctx, {"batch_bfs_band": -1}) == capi.MPCG_EINVAL
     finally:
         s.close()
     # the options' explicit product variant overrides the table's split
