@@ -305,10 +305,12 @@ typedef struct {
     int32_t sell_stream;         /* the SELL products read the matrix with nontemporal loads: -1 where
                                     that precision's copy exceeds the 256 MB Infinity Cache, 0 never,
                                     1 always */
-    int32_t batch_runahead;      /* batch engine, Algorithm II: 0 = a system whose features are still
-                                    being computed holds after its k0 prefix (it takes no bandwidth
-                                    from the others meanwhile), 1 = it runs ahead in FP32 with copies
-                                    of x~ at each candidate's crossing and a speculative FP64 phase */
+    int32_t batch_runahead;      /* batch engine, Algorithm II, a system whose features are still
+                                    being computed: 1 = it runs ahead in FP32 with copies of x~ at
+                                    each candidate's crossing and a speculative FP64 phase; 2 = it
+                                    waits at its first crossing of a candidate, taking no bandwidth
+                                    from the others; 0 = it waits while more than 8 systems share
+                                    the steps, else runs ahead */
     int32_t batch_bfs_band;      /* batch engine: 1 = a connected system whose pattern lies within
                                     |i - j| <= 31 takes its 2BFS as bit-parallel levels of one wave
                                     per system, 0 = the level kernels of every other system */

@@ -903,7 +903,9 @@ Engine *engine_create(int device, const mpcg_options &opt, const mpcg_tuning &tu
     // nontemporal matrix loads where the arena's FP64 matrices (8-byte values,
     // 4-byte columns) can exceed the Infinity Cache, unless the tuning says
     e->a.nt = tune.sell_stream < 0 ? (max_entries * 12 > kInfinityCacheBytes ? 1 : 0) : tune.sell_stream;
-    e->a.hold = tune.batch_runahead == 0 ? 1 : 0;
+    // 0: wait when more than kHoldAboveSystems systems are listed; 1: always
+    // run ahead; 2: always wait
+    e->a.hold_above = tune.batch_runahead == 1 ? INT32_MAX : tune.batch_runahead == 2 ? -1 : kHoldAboveSystems;
     e->band_on = tune.batch_bfs_band != 0;
     e->slots.resize(max_sys);
     e->finals.resize(max_sys);

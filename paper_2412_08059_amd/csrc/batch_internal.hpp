@@ -132,7 +132,8 @@ struct BArena {
     int32_t *step_cnt;                     // [0] = listed slices, [1] = listed systems
     int32_t acc32;                         // dot_acc = 1: FP32-phase dot products accumulate in FP32
     int32_t nt;                            // the step product reads the matrices with nontemporal loads
-    int32_t hold;                          // Algorithm II: hold after the k0 prefix until eps1 is set
+    int32_t hold_above;                    // Algorithm II: a system waits for eps1 at its first crossing when
+                                           // more systems than this are listed (else it runs ahead)
 };
 
 // One launch's share of a work-list rebuild: entries first .. first + n - 1
@@ -203,6 +204,10 @@ constexpr int kBandMaxBw = 31;          // offsets d + 32 fit bits 1..63 of a 64
 // scattered columns: their CG product runs in two launches (k_b_dir forms
 // d, the product gathers it alone instead of r and d_old).
 constexpr int kSplitBw = 4096;
+// batch_runahead = 0: systems wait for their features (at their first
+// crossing) only while more than this many systems share the steps; with
+// fewer, the run-ahead takes bandwidth that would otherwise go unused.
+constexpr int kHoldAboveSystems = 8;
 struct BandList {
     int32_t cnt, nh_max;                // nh_max: the most offsets of one sign among the listed systems
     int32_t slot[kBandList];

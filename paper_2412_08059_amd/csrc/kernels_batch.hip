@@ -830,7 +830,7 @@ __global__ void __launch_bounds__(kBlock) k_b_scalar2(BArena a)
         if (S.auto_eps && !S.eps_set) {
             // until eps1 is known: record the first crossing of each
             // candidate (x~ is copied by the next product); then either hold
-            // (a.hold) or run ahead
+            // (many systems listed: a.hold_above) or run ahead
             const double rg = sqrt(g);
             int due = 0, left = 0;
             for (int t = 0; t < kNumEps; ++t) {
@@ -844,7 +844,7 @@ __global__ void __launch_bounds__(kBlock) k_b_scalar2(BArena a)
                 }
             }
             S.snap_mask = due;
-            if (a.hold) {
+            if (a.step_cnt[1] > a.hold_above) {
                 // Until the loosest candidate is crossed every choice of eps1
                 // needs these iterations; from the first crossing on they may
                 // be wasted, so the system waits there for eps1 without taking

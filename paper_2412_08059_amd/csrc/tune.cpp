@@ -48,7 +48,7 @@ bool tune_valid(const mpcg_tuning &t)
            t.batch_small_levels >= 1 && t.batch_small_levels <= 4096 && t.batch_level_grid >= 1 &&
            t.batch_level_grid <= 65536 && t.bfs_dia >= 0 && t.bfs_dia <= 2 &&
            (t.bfs_dia_tiles == 0 || t.bfs_dia_tiles == 1) && t.sell_stream >= -1 && t.sell_stream <= 1 &&
-           (t.batch_runahead == 0 || t.batch_runahead == 1) && (t.batch_bfs_band == 0 || t.batch_bfs_band == 1);
+           (t.batch_runahead >= 0 && t.batch_runahead <= 2) && (t.batch_bfs_band == 0 || t.batch_bfs_band == 1);
 }
 
 int32_t tune_lenlog(int64_t n, int64_t nnz)

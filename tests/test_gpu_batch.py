@@ -110,14 +110,15 @@ def test_batch_mix_matches_oracle(engine, torch_mod):
         _check_against_oracle(a, b, e, st, x, model)
 
 
-@pytest.mark.parametrize("runahead,band", [(1, 0), (0, 0), (0, 1)])
+@pytest.mark.parametrize("runahead,band", [(1, 0), (2, 0), (2, 1), (0, 1)])
 def test_batch_run_ahead_restarts_from_the_crossing(torch_mod, runahead, band):
     """Features that arrive long after the FP32 phase has passed every
     candidate eps1: a path-like band (tridiagonal, mu = 1.1, n = 50000) has a
     2BFS of 2 x 49999 levels while its CG crosses 1e-7 within a few dozen
     iterations (with the level kernels; the band sweeps take a few ms).
     Whether the system runs ahead (copies of x~ at each crossing, a
-    speculative FP64 phase) or holds after its k0 prefix, the FP64 restart
+    speculative FP64 phase: runahead 1, or 0 with few systems listed) or
+    waits at its first crossing (runahead 2), the FP64 restart
     must start from the state the sequential Algorithm II stops in, so the
     result matches the oracle's Algorithm II."""
     from paper_2412_08059_amd import BatchSolver
@@ -251,7 +252,7 @@ def test_batch_bfs_schedule_does_not_change_results(torch_mod, monkeypatch):
     (1 / 64 / 4,096) change which kernel expands which level, how often a
     system's visited bits are rebuilt from dist and when the features arrive;
     the bands take the one-wave band sweeps or the level kernels, and the
-    systems hold after their k0 prefix or run ahead.
+    systems wait at their first crossing or run ahead.
     An ER graph of more than 2^20 rows takes the path that claims vertices in
     HBM (smaller systems keep their visited set in LDS); every system's
     features are checked against the oracle's 2BFS."""
@@ -268,7 +269,7 @@ def test_batch_bfs_schedule_does_not_change_results(torch_mod, monkeypatch):
     schedules = [{}, {"batch_small_cap": 2048, "batch_small_levels": 4096, "batch_bfs_band": 0},
                  {"batch_small_cap": 8, "batch_small_levels": 1, "batch_group_steps": 3, "batch_bfs_rounds": 2,
                   "batch_level_grid": 96, "batch_runahead": 1, "batch_bfs_band": 0},
-                 {"batch_runahead": 1}]
+                 {"batch_runahead": 2}]
     runs = []
     for env in schedules:
         eng = BatchSolver(1_300_000, 40_000_000, 16, model=TEST_MODEL, tuning=env or None)

@@ -126,7 +126,7 @@ def test_table_lookup_and_overrides(torch_mod, tmp_path):
         assert capi.mpcg_set_tuning(s.ctx, {"bfs_dia": 3}) == capi.MPCG_EINVAL
         assert capi.mpcg_set_tuning(s.ctx, {"bfs_dia_tiles": 2}) == capi.MPCG_EINVAL
         assert capi.mpcg_set_tuning(s.ctx, {"sell_stream": 2}) == capi.MPCG_EINVAL
-        assert capi.mpcg_set_tuning(s.ctx, {"batch_runahead": 2}) == capi.MPCG_EINVAL
+        assert capi.mpcg_set_tuning(s.ctx, {"batch_runahead": 3}) == capi.MPCG_EINVAL
         assert capi.mpcg_set_tuning(s.ctx, {"batch_bfs_band": -1}) == capi.MPCG_EINVAL
     finally:
         s.close()
