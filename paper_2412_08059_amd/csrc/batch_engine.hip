@@ -16,8 +16,9 @@
 // both sweeps in one launch of one-wave bit-parallel levels on a third
 // stream with its own copy, so a long band holds up no one else's rounds.
 // After its k0 FP32 iterations a system continues in FP32 until it crosses
-// the loosest candidate eps1 and then waits there for its features (or, with
-// batch_runahead, runs ahead copying x~ at each candidate's first crossing);
+// the loosest candidate eps1; there it waits for its features while many
+// systems share the steps, or runs ahead copying x~ at each candidate's first
+// crossing (batch_runahead: 0 decides by the number of listed systems);
 // the state it then restarts from is the one the sequential method stops in,
 // so its arithmetic does not depend on that pace.  While any system is being
 // admitted or waits for features, groups are shortened to a few ms.
